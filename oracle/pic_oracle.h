@@ -1,0 +1,121 @@
+/*
+ * pic_oracle.h -- plain FP64 CPU oracle of the electrostatic 1D3V PIC Monte Carlo step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This code is the slow, obviously-correct reference that the
+ * GPU library is checked against.  Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load it; the product path never does.  It shares no code, header,
+ * table or constant generator with the GPU library.
+ *
+ * What it computes follows the PIC cycle the paper names in its Background section
+ * (particle load, mover, deposition to the grid, electrostatic field solve, force
+ * interpolation, Monte Carlo collisions) for the 1D3V electrostatic code described there.
+ * The paper gives no equations for these steps, so each one is the textbook method it
+ * names implicitly (Birdsall-Langdon cloud-in-cell, a three-point Poisson stencil solved
+ * by the Thomas algorithm, the Boris rotation, the Vahedi-Surendra null-collision method),
+ * with every unstated choice fixed by a written reading (the R-tags in the comments).
+ *
+ * Units are normalised: eps0 = e = m_e = n0 = T_e = 1, so omega_pe = v_th,e = lambda_D = 1.
+ */
+#ifndef PIC_ORACLE_H
+#define PIC_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One charged species. */
+typedef struct {
+    double q, m, w;      /* charge, mass, macro-particle weight (real particles per area)   */
+    double T;            /* temperature of the initial Maxwellian                            */
+    int64_t ppc;         /* initial particles per cell                                       */
+    int64_t capacity;    /* maximum particles held                                           */
+} orc_species;
+
+typedef struct {
+    int64_t ncells;      /* N cells; N+1 nodes when bounded, N nodes when periodic            */
+    int32_t periodic;    /* 0 = absorbing grounded walls, 1 = periodic                        */
+    int32_t nspecies;    /* 1 (electrons on a fixed neutralising background) or 2 (e, ion)    */
+    int32_t collisions;  /* 0 = collisionless                                                 */
+    int32_t init_mode;   /* 0 = random cell load + Maxwellian, 1 = cold quiet start + sine    */
+    double dx, dt, eps0;
+    double B[3];         /* uniform magnetic field                                            */
+    double E_ext;        /* uniform external field along x                                    */
+    uint32_t seed;       /* Philox key word 0                                                 */
+    int32_t sort_every;  /* K; 0 = never                                                      */
+    orc_species sp[2];   /* 0 = electrons, 1 = ions                                           */
+    double ngs_el, ngs_iz, ngs_cx;  /* n_g * sigma for e-elastic, e-ionisation, ion CX       */
+    double eps_iz;       /* ionisation energy                                                 */
+    double T_n, m_n;     /* neutral temperature and mass                                      */
+    double perturb_amp;  /* quiet start: displacement amplitude A (density ~ 1 - A cos kx)    */
+    int32_t perturb_mode;
+} orc_config;
+
+/* Cumulative diagnostics (reset only by orc_create / orc_init). */
+typedef struct {
+    int64_t count[2];            /* particles alive per species                              */
+    double charge;               /* sum_s q_s w_s n_s                                        */
+    double ke[2];                /* 1/2 m_s w_s sum |v|^2                                    */
+    double field_energy;         /* 1/2 eps0 sum_j E_j^2 V_j of the self-consistent field    */
+    int64_t wall_count[2][2];    /* [wall 0=left,1=right][species] absorbed particles        */
+    double wall_charge[2][2];    /* absorbed q w                                             */
+    double wall_ke[2][2];        /* absorbed 1/2 m w |v|^2                                   */
+    int64_t coll[3];             /* e-elastic, e-ionisation, ion charge exchange             */
+    int64_t created[2];          /* particles created per species                            */
+    int64_t pushes;              /* sum over steps of the particles pushed                   */
+    int64_t step;
+} orc_diag;
+
+typedef struct orc_state orc_state;
+
+orc_state *orc_create(const orc_config *cfg);
+void orc_free(orc_state *st);
+/* Non-zero after a capacity overflow (1, 3) or a particle outside the grid (2). */
+int orc_error(const orc_state *st);
+
+/* Particle load (R17 init / R19 quiet start), then deposit of Q^0 and the speed bound. */
+void orc_init(orc_state *st);
+
+/* Inject / read back a species' particles: absolute x, velocity, id. */
+int orc_set_particles(orc_state *st, int s, int64_t n, const double *x, const double *vx,
+                      const double *vy, const double *vz, const uint32_t *id, uint32_t next_id);
+int64_t orc_get_particles(const orc_state *st, int s, double *x, double *vx, double *vy,
+                          double *vz, uint32_t *id);
+uint32_t orc_next_id(const orc_state *st, int s);
+
+/* The stages of one step, callable one by one. */
+void orc_deposit(orc_state *st);                 /* particles -> Q_s (FP64 CIC shares)    */
+void orc_solve(orc_state *st);                   /* Q -> rho -> phi -> E (Thomas)         */
+void orc_set_fields(orc_state *st, const double *E);  /* replace E (self part)           */
+void orc_push(orc_state *st);                    /* gather + Boris + position update      */
+void orc_walls(orc_state *st);                   /* absorb (bounded) or wrap (periodic)   */
+void orc_collide(orc_state *st);                 /* null-collision MC + creation          */
+void orc_sort(orc_state *st);                    /* stable counting sort by cell          */
+void orc_step(orc_state *st, int64_t nsteps);    /* full steps, including the step count  */
+
+/* Read-outs. */
+int64_t orc_nnodes(const orc_state *st);
+void orc_get_grid(const orc_state *st, double *Q0, double *Q1, double *rho, double *phi,
+                  double *E);
+void orc_get_diag(orc_state *st, orc_diag *out);
+/* Collision bookkeeping of the last orc_collide call: per alive particle (post-wall order)
+ * the channel taken (-1 none, 0 elastic, 1 ionisation, 2 CX), and nu_max per species. */
+int64_t orc_last_channels(const orc_state *st, int s, int32_t *chan, uint32_t *ids);
+void orc_last_numax(const orc_state *st, double *numax, double *pnull);
+void orc_set_step(orc_state *st, int64_t step);
+
+/* Philox4x32-10 block and the derived variates, exposed for pinning. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* n independent blocks: ctr[4n], key[2n] -> out[4n]. */
+void orc_philox_batch(int64_t n, const uint32_t *ctr, const uint32_t *key, uint32_t *out);
+double orc_uniform(uint32_t r);
+void orc_boxmuller(double u1, double u2, double *z0, double *z1);
+
+/* Tridiagonal (Thomas) solve of a_i x_{i-1} + b_i x_i + c_i x_{i+1} = d_i, exposed for pinning. */
+void orc_thomas(int64_t n, const double *a, const double *b, const double *c, const double *d,
+                double *x);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,525 @@
+"""Pins of the CPU oracle against what mathematics and independent routines fix.
+
+Every check here compares the oracle with something other than itself: a library routine
+(PyTorch's Philox header, scipy's banded solver, numpy's FFT and stable argsort), a closed
+form (Boris gyration angle, constant-force leapfrog, the exact nodal solution of the
+three-point Poisson stencil, the discrete Langmuir frequency, free-streaming exits), an
+invariant (CIC moments, Gauss's law, total-momentum conservation, energy balance of
+ionisation) or a statistical law (collision counts, isotropy, Maxwellian samples).
+"""
+import math
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.stats
+
+import oracle
+import synth
+
+TORCH_INC = None
+try:
+    import torch  # noqa: F401  (only for the location of its headers)
+
+    TORCH_INC = os.path.join(os.path.dirname(torch.__file__), "include")
+except Exception:  # pragma: no cover
+    pass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# ---------------------------------------------------------------------------------------
+# Philox4x32-10 and the derived variates
+# ---------------------------------------------------------------------------------------
+@pytest.mark.skipif(TORCH_INC is None, reason="torch headers not found")
+def test_philox_matches_pytorch_header(tmp_path):
+    exe = tmp_path / "philox_ref"
+    subprocess.run(["g++", "-O2", "-std=c++17", f"-I{TORCH_INC}", "-o", str(exe),
+                    os.path.join(HERE, "philox_torch_ref.cpp")], check=True)
+    out = tmp_path / "ref.bin"
+    n = 1_000_000
+    subprocess.run([str(exe), str(n), "20261202", str(out)], check=True)
+    rec = np.fromfile(out, dtype=np.uint32).reshape(-1, 10)
+    got = oracle.philox_batch(rec[:, :4], rec[:, 4:6])
+    assert np.array_equal(got, rec[:, 6:10])
+
+
+def test_uniform_is_exact_open_interval():
+    r = np.array([0, 1, 511, 512, 2**31, 2**32 - 1, 123456789], dtype=np.uint64)
+    for v in r:
+        u = oracle.uniform(int(v))
+        assert 0.0 < u < 1.0
+        assert float(np.float32(u)) == u          # exactly representable in binary32
+        assert (u * 2**24) % 2 == 1.0             # odd multiple of 2^-24
+    assert oracle.uniform(0) == 2.0**-24
+    assert oracle.uniform(2**32 - 1) == 1.0 - 2.0**-24
+
+
+def test_boxmuller_bound_and_law():
+    zmax = math.sqrt(-2.0 * math.log(2.0**-24))
+    z0, z1 = oracle.boxmuller(2.0**-24, 0.0)
+    assert abs(z0 - zmax) < 1e-12 and abs(z1) < 1e-12
+    rng = np.random.default_rng(3)
+    w = rng.integers(0, 2**32, size=(20000, 2), dtype=np.uint64)
+    zs = []
+    for a, b in w:
+        za, zb = oracle.boxmuller(oracle.uniform(int(a)), oracle.uniform(int(b)))
+        zs += [za, zb]
+    zs = np.array(zs)
+    assert np.all(np.abs(zs) <= zmax + 1e-12)
+    assert scipy.stats.kstest(zs, "norm").pvalue > 1e-3
+
+
+# ---------------------------------------------------------------------------------------
+# Deposit (cloud-in-cell)
+# ---------------------------------------------------------------------------------------
+def _one_species(ncells, periodic=False, cap=4096):
+    e = synth.ensemble(ncells, 1, nspecies=1, periodic=periodic, collisions=False)
+    e["species"][0]["capacity"] = cap
+    return e
+
+
+def test_deposit_node_particle_and_moments():
+    e = _one_species(16)
+    o = oracle.Oracle(e, init=False)
+    # a particle exactly on node 5 puts its whole share there
+    o.set_particles(0, [5 * e["dx"]], [0.0], [0.0], [0.0], [0], 1)
+    o.deposit()
+    Q = o.grid()["Q"][0]
+    expect = np.zeros(o.nnodes)
+    expect[5] = 1.0
+    assert np.array_equal(Q, expect)
+    # brute force on 1-4 random particles: zeroth and first moments of CIC are exact,
+    # and each particle touches only the two nodes around it
+    rng = np.random.default_rng(7)
+    for n in (1, 2, 3, 4):
+        x = rng.random(n) * 16 * e["dx"]
+        o.set_particles(0, x, np.zeros(n), np.zeros(n), np.zeros(n), np.arange(n), n)
+        o.deposit()
+        Q = o.grid()["Q"][0]
+        nodes = np.arange(o.nnodes) * e["dx"]
+        assert abs(Q.sum() - n) < 1e-13
+        assert abs((Q * nodes).sum() - x.sum()) < 1e-12
+        support = set()
+        for xi in x:
+            support |= {int(xi // e["dx"]), int(xi // e["dx"]) + 1}
+        assert set(np.nonzero(Q)[0]) <= support
+        assert np.all(Q >= 0)
+
+
+def test_deposit_periodic_wraps_last_cell():
+    e = _one_species(8, periodic=True)
+    o = oracle.Oracle(e, init=False)
+    x = (7 + 0.25) * e["dx"]
+    o.set_particles(0, [x], [0.0], [0.0], [0.0], [0], 1)
+    o.deposit()
+    Q = o.grid()["Q"][0]
+    assert o.nnodes == 8
+    assert Q[7] == 0.75 and Q[0] == 0.25 and Q.sum() == 1.0
+
+
+def test_deposit_charge_invariant_full_init():
+    w = synth.scaled(synth.c1_plain_small(), ncells=64, ppc=50)
+    e = w["ensembles"][0]
+    o = oracle.Oracle(e)
+    o.solve()
+    g = o.grid()
+    V = np.full(o.nnodes, e["dx"])
+    V[0] = V[-1] = e["dx"] / 2
+    total = sum(sp["q"] * sp["w"] * sp["ppc"] * e["ncells"] for sp in e["species"])
+    qsum = (g["rho"] * V).sum()
+    scale = sum(abs(sp["q"] * sp["w"]) * sp["ppc"] * e["ncells"] for sp in e["species"])
+    assert abs(qsum - total) <= 1e-14 * scale * 10
+
+
+# ---------------------------------------------------------------------------------------
+# Poisson solve and node field
+# ---------------------------------------------------------------------------------------
+def test_thomas_matches_scipy_banded():
+    rng = np.random.default_rng(11)
+    n = 500
+    a = rng.standard_normal(n)
+    c = rng.standard_normal(n)
+    b = 4.0 + np.abs(a) + np.abs(c)
+    d = rng.standard_normal(n)
+    x = oracle.thomas(a, b, c, d)
+    ab = np.zeros((3, n))
+    ab[0, 1:] = c[:-1]
+    ab[1] = b
+    ab[2, :-1] = a[1:]
+    ref = scipy.linalg.solve_banded((1, 1), ab, d)
+    assert np.max(np.abs(x - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_poisson_uniform_interior_charge_closed_form():
+    """One unit particle on every interior node: uniform rho inside, grounded walls.
+    The three-point stencil is exact for the quadratic phi = rho x (L - x) / (2 eps0)."""
+    N = 40
+    e = _one_species(N)
+    e["species"][0]["q"] = 1.0
+    o = oracle.Oracle(e, init=False)
+    dx = e["dx"]
+    x = np.arange(1, N) * dx
+    n = len(x)
+    o.set_particles(0, x, np.zeros(n), np.zeros(n), np.zeros(n), np.arange(n), n)
+    o.deposit()
+    o.solve()
+    g = o.grid()
+    rho = e["species"][0]["w"] / dx
+    L = N * dx
+    xs = np.arange(N + 1) * dx
+    phi_ref = rho * xs * (L - xs) / 2.0
+    assert np.max(np.abs(g["phi"] - phi_ref)) <= 1e-12 * np.max(phi_ref)
+    E_ref = rho * (xs - L / 2.0)
+    assert np.max(np.abs(g["E"][1:-1] - E_ref[1:-1])) <= 1e-12 * np.max(np.abs(E_ref))
+    # Gauss over the whole domain: E_N - E_0 = total charge / eps0
+    assert abs((g["E"][-1] - g["E"][0]) - rho * (N - 1) * dx) <= 1e-12 * rho * L
+
+
+def test_poisson_point_charge_green_function():
+    N, j0 = 50, 17
+    e = _one_species(N)
+    e["species"][0]["q"] = 1.0
+    o = oracle.Oracle(e, init=False)
+    dx = e["dx"]
+    o.set_particles(0, [j0 * dx], [0.0], [0.0], [0.0], [0], 1)
+    o.deposit()
+    o.solve()
+    phi = o.grid()["phi"]
+    sig = e["species"][0]["w"]
+    L, x0 = N * dx, j0 * dx
+    xs = np.arange(N + 1) * dx
+    ref = np.where(xs <= x0, sig * xs * (L - x0) / L, sig * x0 * (L - xs) / L)
+    assert np.max(np.abs(phi - ref)) <= 1e-12 * np.max(ref)
+
+
+def _random_two_species(N, seed, periodic=False, nspecies=2, ppc=7):
+    e = synth.ensemble(N, ppc, nspecies=nspecies, periodic=periodic, collisions=False)
+    st = synth.random_state(e, [ppc * N] * nspecies, seed=seed)
+    o = oracle.Oracle(e, init=False)
+    o.set_state(st)
+    return e, o
+
+
+def test_poisson_bounded_matches_scipy_and_gauss():
+    e, o = _random_two_species(97, seed=5)
+    o.deposit()
+    o.solve()
+    g = o.grid()
+    N, dx = e["ncells"], e["dx"]
+    rho = g["rho"]
+    m = N - 1
+    ab = np.zeros((3, m))
+    ab[0, 1:] = 1.0
+    ab[1] = -2.0
+    ab[2, :-1] = 1.0
+    ref = np.concatenate([[0.0], scipy.linalg.solve_banded((1, 1), ab, -rho[1:N] * dx * dx), [0.0]])
+    assert np.max(np.abs(g["phi"] - ref)) <= 1e-12 * np.max(np.abs(ref))
+    V = np.full(N + 1, dx)
+    V[0] = V[-1] = dx / 2
+    gauss = (rho * V).sum() / e["eps0"]
+    assert abs((g["E"][-1] - g["E"][0]) - gauss) <= 1e-11 * max(1.0, np.abs(rho * V).sum())
+
+
+def test_poisson_periodic_matches_fft():
+    e, o = _random_two_species(128, seed=9, periodic=True)
+    o.deposit()
+    o.solve()
+    g = o.grid()
+    N, dx = e["ncells"], e["dx"]
+    rho = g["rho"]
+    assert abs(rho.sum()) <= 1e-12 * np.abs(rho).sum()
+    rk = np.fft.fft(rho)
+    m = np.arange(N)
+    lam = (2.0 - 2.0 * np.cos(2 * np.pi * m / N)) / dx**2   # eigenvalues of -Laplacian
+    phik = np.zeros_like(rk)
+    phik[1:] = rk[1:] / lam[1:] / e["eps0"]
+    phi_ref = np.fft.ifft(phik).real
+    assert np.max(np.abs(g["phi"] - phi_ref)) <= 1e-11 * np.max(np.abs(phi_ref))
+    Eref = (np.roll(phi_ref, 1) - np.roll(phi_ref, -1)) / (2 * dx)
+    assert np.max(np.abs(g["E"] - Eref)) <= 1e-11 * np.max(np.abs(Eref))
+    assert abs(g["E"].sum()) <= 1e-10 * np.abs(g["E"]).sum()
+
+
+# ---------------------------------------------------------------------------------------
+# Boris push
+# ---------------------------------------------------------------------------------------
+def _rodrigues(v, axis, ang):
+    k = axis / np.linalg.norm(axis)
+    return (v * math.cos(ang) + np.cross(k, v) * math.sin(ang)
+            + k * np.dot(k, v) * (1 - math.cos(ang)))
+
+
+@pytest.mark.parametrize("q,m", [(-1.0, 1.0), (1.0, synth.M_ION)])
+def test_boris_gyration_exact_angle(q, m):
+    e = synth.ensemble(64, 1, nspecies=1, periodic=True, collisions=False, B=synth.oblique_B())
+    e["species"][0]["q"], e["species"][0]["m"] = q, m
+    B = np.array(e["B"])
+    Bmag = np.linalg.norm(B)
+    o = oracle.Oracle(e, init=False)
+    o.set_fields(np.zeros(o.nnodes))
+    v0 = np.array([0.3, -0.7, 0.45]) * (1.0 if m == 1.0 else 1e-3)
+    x0 = 10.0
+    o.set_particles(0, [x0], [v0[0]], [v0[1]], [v0[2]], [0], 1)
+    theta = 2.0 * math.atan(abs(q) * Bmag * e["dt"] / (2 * m))
+    x = x0
+    for n in range(1, 201):
+        o.push()
+        p = o.particles(0)
+        v = np.array([p["vx"][0], p["vy"][0], p["vz"][0]])
+        vref = _rodrigues(v0, B, -math.copysign(1.0, q) * n * theta)
+        assert np.max(np.abs(v - vref)) <= 1e-12 * np.linalg.norm(v0)
+        assert abs(np.linalg.norm(v) - np.linalg.norm(v0)) <= 1e-13 * np.linalg.norm(v0)
+        x += e["dt"] * vref[0]
+        assert abs(p["x"][0] - x) <= 1e-11
+
+
+def test_leapfrog_constant_field_exact():
+    e = synth.ensemble(64, 1, nspecies=1, periodic=True, collisions=False)
+    o = oracle.Oracle(e, init=False)
+    E0 = 0.25
+    o.set_fields(np.full(o.nnodes, E0))
+    q, m, dt = -1.0, 1.0, e["dt"]
+    v0, x0 = 0.1, 20.0
+    o.set_particles(0, [x0], [v0], [0.0], [0.0], [0], 1)
+    a = q / m * E0
+    for k in range(1, 51):
+        o.push()
+        p = o.particles(0)
+        assert abs(p["vx"][0] - (v0 + k * a * dt)) <= 1e-13
+        xr = x0 + k * dt * v0 + a * dt * dt * k * (k + 1) / 2
+        assert abs(p["x"][0] - xr) <= 1e-12
+
+
+# ---------------------------------------------------------------------------------------
+# Coupled push + solve: Langmuir oscillation and momentum conservation
+# ---------------------------------------------------------------------------------------
+def _mode_series(ncells, nsteps, ppc=20):
+    w = synth.c4_langmuir(ncells=ncells, ppc=ppc)
+    ens = w["ensembles"][0]
+    o = oracle.Oracle(ens)
+    N, dx = ens["ncells"], ens["dx"]
+    k = 2 * np.pi / (N * dx)
+    xs = np.arange(N) * dx
+    basis = np.exp(-1j * k * xs)
+    amps = []
+    for _ in range(nsteps):
+        o.step(1)
+        amps.append(np.dot(o.grid()["E"], basis))
+    a = np.array(amps)
+    ref = a[np.argmax(np.abs(a))]
+    return np.real(a * np.conj(ref)) / np.abs(ref), o
+
+
+def test_langmuir_frequency_matches_leapfrog_dispersion():
+    b, _ = _mode_series(2048, 300, ppc=20)
+    c = np.dot(b[1:-1], b[2:] + b[:-2]) / (2.0 * np.dot(b[1:-1], b[1:-1]))
+    dt = synth.DT
+    w_num = math.acos(c) / dt
+    w_ref = (2.0 / dt) * math.asin(dt / 2.0)     # omega_pe = 1
+    assert abs(w_num / w_ref - 1.0) < 1e-4
+
+
+def test_total_momentum_conserved_periodic_warm():
+    e = synth.ensemble(128, 30, nspecies=1, periodic=True, collisions=False, T_e=1.0)
+    o = oracle.Oracle(e)
+    p0 = o.particles(0)["vx"].sum()
+    scale = np.abs(o.particles(0)["vx"]).sum()
+    for _ in range(50):
+        o.step(1)
+        p = o.particles(0)["vx"].sum()
+        assert abs(p - p0) <= 1e-12 * scale
+
+
+# ---------------------------------------------------------------------------------------
+# Walls
+# ---------------------------------------------------------------------------------------
+def test_free_streaming_wall_exits_exact():
+    N = 64
+    e = synth.ensemble(N, 100, collisions=False)
+    st = synth.random_state(e, [4000, 4000], seed=21, vscale=[1.0, 0.3])
+    o = oracle.Oracle(e, init=False)
+    o.set_state(st)
+    o.set_fields(np.zeros(o.nnodes))
+    L, dt = N * e["dx"], e["dt"]
+    for n in range(1, 61):
+        o.push()
+        o.walls()
+        d = o.diag()
+        for s in range(2):
+            x = st[s]["x"] + n * dt * st[s]["vx"].astype(np.float64)
+            left = np.count_nonzero(x < 0)
+            right = np.count_nonzero(x >= L)
+            assert d["wall_count"][0][s] == left
+            assert d["wall_count"][1][s] == right
+            assert d["count"][s] == len(x) - left - right
+    # tallied charge is count * q w for each wall and species
+    for s in range(2):
+        sp = e["species"][s]
+        for wall in range(2):
+            assert d["wall_charge"][wall][s] == pytest.approx(d["wall_count"][wall][s] * sp["q"] * sp["w"], rel=1e-12)
+
+
+# ---------------------------------------------------------------------------------------
+# Null-collision Monte Carlo
+# ---------------------------------------------------------------------------------------
+def _collision_setup(n, ngs, seed=31, vscale=(1.5, 3e-3)):
+    e = synth.ensemble(32, 1, collisions=True)
+    e["ngs_el"], e["ngs_iz"], e["ngs_cx"] = ngs
+    for sp in e["species"]:
+        sp["capacity"] = 3 * n
+    st = synth.random_state(e, [n, n], seed=seed, vscale=list(vscale))
+    o = oracle.Oracle(e, init=False)
+    o.set_state(st)
+    o.set_fields(np.zeros(o.nnodes))
+    o.set_step(7)
+    return e, st, o
+
+
+def test_null_collision_counts_match_probabilities():
+    n = 200_000
+    e, st, o = _collision_setup(n, (0.2, 0.3, 40.0))
+    o.collide()
+    nu, pn = o.last_numax()
+    for s in range(2):
+        v = np.stack([st[s]["vx"], st[s]["vy"], st[s]["vz"]]).astype(np.float64)
+        v2 = (v * v).sum(0)
+        spd = np.sqrt(v2)
+        # the bound covers every particle
+        assert nu[s] >= ((e["ngs_el"] + e["ngs_iz"]) if s == 0 else e["ngs_cx"]) * spd.max()
+        assert pn[s] == pytest.approx(1 - math.exp(-nu[s] * e["dt"]), rel=1e-14)
+        chan, ids = o.last_channels(s)
+        if s == 0:
+            rates = [e["ngs_el"] * spd, np.where(0.5 * v2 >= e["eps_iz"], e["ngs_iz"] * spd, 0.0)]
+            kinds = [0, 1]
+        else:
+            rates = [e["ngs_cx"] * spd]
+            kinds = [2]
+        for r, k in zip(rates, kinds):
+            p = pn[s] * r / nu[s]
+            mu, sd = p.sum(), math.sqrt((p * (1 - p)).sum())
+            got = np.count_nonzero(chan == k)
+            assert abs(got - mu) <= 4 * sd + 1, (s, k, got, mu, sd)
+            # for small nu dt the count is close to sum nu_k dt
+            assert abs(mu - (r * e["dt"]).sum()) <= 0.5 * mu
+
+
+def test_collision_kinematics_identities_and_creation():
+    n = 100_000
+    e, st, o = _collision_setup(n, (0.2, 0.3, 40.0), seed=33)
+    before = [{k: st[s][k].astype(np.float64) for k in ("x", "vx", "vy", "vz")} for s in range(2)]
+    ids0 = [st[s]["id"] for s in range(2)]
+    o.collide()
+    me, M = 1.0, e["m_n"]
+    pe = o.particles(0)
+    pi = o.particles(1)
+    ch_e, id_e = o.last_channels(0)
+    ch_i, id_i = o.last_channels(1)
+    # order of survivors is unchanged and first n slots are the old particles
+    assert np.array_equal(pe["id"][:n], ids0[0]) and np.array_equal(id_e, ids0[0])
+    v_old = np.stack([before[0][k] for k in ("vx", "vy", "vz")])
+    v_new = np.stack([pe[k][:n] for k in ("vx", "vy", "vz")])
+    n_old2 = (v_old**2).sum(0)
+    n_new2 = (v_new**2).sum(0)
+    # untouched particles keep their velocity bit for bit
+    nc = ch_e < 0
+    assert np.array_equal(v_new[:, nc], v_old[:, nc])
+    # elastic: energy loss to a heavy target lies in [0, 4 m/M] of the energy; the lab-frame
+    # scattered directions are isotropic
+    el = ch_e == 0
+    ratio = n_new2[el] / n_old2[el]
+    assert np.all(ratio <= 1 + 1e-12) and np.all(ratio >= 1 - 4 * me / M - 1e-12)
+    dirs = v_new[:, el] / np.sqrt(n_new2[el])
+    assert abs(dirs[0].mean()) < 5 / math.sqrt(el.sum())
+    assert abs((dirs[0] ** 2).mean() - 1 / 3) < 5 * math.sqrt(4 / 45) / math.sqrt(el.sum())
+    # ionisation: parent + child energy = parent energy - eps_iz, children at parent x,
+    # new ids next_id + rank of the parent id, paired ions with the same rank
+    iz = np.nonzero(ch_e == 1)[0]
+    assert len(iz) > 100
+    order = np.argsort(ids0[0][iz], kind="stable")
+    parents = iz[order]
+    n_new = len(parents)
+    assert len(pe["id"]) == n + n_new and len(pi["id"]) == n + n_new
+    assert np.array_equal(pe["id"][n:], np.arange(n, n + n_new, dtype=np.uint32))
+    assert np.array_equal(pi["id"][n:], np.arange(n, n + n_new, dtype=np.uint32))
+    e_par = 0.5 * me * n_new2[parents]
+    child_v = np.stack([pe[k][n:] for k in ("vx", "vy", "vz")])
+    e_child = 0.5 * me * (child_v**2).sum(0)
+    e_in = 0.5 * me * n_old2[parents]
+    assert np.max(np.abs(e_par + e_child - (e_in - e["eps_iz"])) / e_in) < 1e-12
+    assert np.all(0.5 * me * n_old2[parents] >= e["eps_iz"])
+    assert np.array_equal(pe["x"][n:], before[0]["x"][parents])
+    assert np.array_equal(pi["x"][n:], before[0]["x"][parents])
+    # new ions and charge-exchanged ions are Maxwellian at T_n
+    vn = math.sqrt(e["T_n"] / e["m_n"])
+    ion_new = np.concatenate([pi[k][n:] for k in ("vx", "vy", "vz")]) / vn
+    assert scipy.stats.kstest(ion_new, "norm").pvalue > 1e-3
+    cx = ch_i == 2
+    assert cx.sum() > 1000
+    ion_cx = np.concatenate([pi[k][:n][cx] for k in ("vx", "vy", "vz")]) / vn
+    assert scipy.stats.kstest(ion_cx, "norm").pvalue > 1e-3
+    d = o.diag()
+    assert d["coll"] == [int(el.sum()), len(iz), int(cx.sum())]
+    assert d["created"] == [n_new, n_new]
+
+
+# ---------------------------------------------------------------------------------------
+# Sort, init and full-step properties
+# ---------------------------------------------------------------------------------------
+def test_sort_matches_numpy_stable_argsort():
+    e, o = _random_two_species(50, seed=41, ppc=20)
+    before = [o.particles(s) for s in range(2)]
+    o.sort()
+    for s in range(2):
+        b = before[s]
+        order = np.argsort(np.floor(b["x"] / e["dx"]).astype(np.int64), kind="stable")
+        a = o.particles(s)
+        for k in ("x", "vx", "vy", "vz", "id"):
+            assert np.array_equal(a[k], b[k][order])
+
+
+def test_init_load_statistics():
+    w = synth.scaled(synth.c2_sheath(), ncells=200, ppc=200)
+    e = w["ensembles"][0]
+    o = oracle.Oracle(e)
+    for s in range(2):
+        p = o.particles(s)
+        ppc = e["species"][s]["ppc"]
+        n = ppc * e["ncells"]
+        assert np.array_equal(p["id"], np.arange(n, dtype=np.uint32))
+        cell = np.floor(p["x"] / e["dx"]).astype(np.int64)
+        assert np.array_equal(cell, np.arange(n) // ppc)
+        off = p["x"] / e["dx"] - cell
+        assert np.all(off.astype(np.float32).astype(np.float64) == off)
+        assert scipy.stats.kstest(off, "uniform").pvalue > 1e-3
+        vth = math.sqrt(e["species"][s]["T"] / e["species"][s]["m"])
+        for k in ("vx", "vy", "vz"):
+            assert scipy.stats.kstest(p[k] / vth, "norm").pvalue > 1e-3
+
+
+def test_sort_does_not_change_physics():
+    """Sorting only permutes particles: with id-keyed random numbers the collision
+    decisions and the trajectories agree with an unsorted run up to the rounding of the
+    order-dependent FP64 deposit sums."""
+    w = synth.scaled(synth.c2_sheath(), ncells=64, ppc=40)
+    e = w["ensembles"][0]
+    e["ngs_el"], e["ngs_iz"] = 0.2, 0.3
+    for sp in e["species"]:
+        sp["capacity"] *= 3
+    e2 = dict(e, sort_every=0)
+    a, b = oracle.Oracle(e), oracle.Oracle(e2)
+    a.step(25)
+    b.step(25)
+    da, db = a.diag(), b.diag()
+    assert da["coll"] == db["coll"] and da["created"] == db["created"]
+    for s in range(2):
+        pa, pb = a.particles(s), b.particles(s)
+        ia, ib = np.argsort(pa["id"]), np.argsort(pb["id"])
+        assert np.array_equal(pa["id"][ia], pb["id"][ib])
+        for k in ("x", "vx", "vy", "vz"):
+            assert np.allclose(pa[k][ia], pb[k][ib], rtol=1e-9, atol=1e-12)
+    assert np.allclose(a.grid()["E"], b.grid()["E"], rtol=1e-9, atol=1e-12)
+    assert a.error == 0
