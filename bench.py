@@ -1,0 +1,183 @@
+"""Benchmark: particle-pushes/s of the full PIC MC step on one MI355X.
+
+Workload: the magnetised sheath slab at 1e5 cells x 200 particles per cell per species
+(4.0e7 particles, electrons + argon-mass ions), oblique B (omega_ce/omega_pe = 2 at 80
+degrees to x), three null-collision channels with ionisation births, absorbing walls, cell
+sort every 20 steps; FP32 cell+offset particles with the FP64 field solve, one fused
+particle pass per step replayed from a HIP graph.  A step is the whole hot path: field
+solve, gather + Boris push, walls, null-collision MC, births, deposit, and the sort on
+every 20th step.  Inputs are synthetic (seeded Philox particle load) and resident in HBM
+before the timed region starts.
+
+Prints ONE JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+B_ALG_PARTICLE = 44.0          # FP32 form: read cell+off+v+id (24 B), write cell+off+v (20 B)
+B_ALG_CELL = 8.0               # gather table (E_j, dE_j) per cell, float2
+B_ALG_NODE = 16.0              # two species' int64 charge sums per node
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("pic_kernels.hip", "pic_device.h"):
+        with open(os.path.join(ROOT, "paper_2606_28534_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(workload_name, pushes_per_launch):
+    """HBM bytes per launch of the fused pass from the committed PMC summary, or None when
+    the summary is missing or was taken on a different kernel source."""
+    p = os.path.join(ROOT, "profiles", f"pmc_fused_pass_{workload_name}.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(seed, steps):
+    """The FP64 oracle as it stands, single-threaded, on the first `steps` steps of the
+    same workload (particle load excluded from the timing)."""
+    import oracle
+    import synth
+
+    oracle.build(force=False)
+    e = synth.c2_sheath(seed=seed)["ensembles"][0]
+    o = oracle.Oracle(e)
+    d0 = o.diag()["pushes"]
+    t0 = time.perf_counter()
+    o.step(steps)
+    t1 = time.perf_counter()
+    pushes = o.diag()["pushes"] - d0
+    return {"value": pushes / (t1 - t0), "unit": "particle-pushes/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {steps} steps of the same 1e5-cell x 200-ppc workload (seed {seed}), "
+                      f"{pushes} pushes in {t1 - t0:.1f} s, FP64, one host thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--ncells", type=int, default=100_000)
+    ap.add_argument("--ppc", type=int, default=200)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs the hot path on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2606_28534_amd as pic
+    import synth
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    work = synth.c2_sheath(seed=args.seed, ncells=args.ncells, ppc=args.ppc)
+    e = work["ensembles"][0]
+    sim = pic.Sim(work, fused=True)
+    stream = sim.stream
+
+    # warm-up (graph capture happens here)
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    d0 = sim.diag()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    d1 = sim.diag()
+    pushes = d1["pushes"] - d0["pushes"]
+    wall = t1 - t0
+    value = pushes / wall
+
+    # dominant kernel: the fused particle pass, timed with HIP events on the library's
+    # launch stream over a run of the same steps without the graph
+    sim.timing(True)
+    dt0 = sim.diag()["pushes"]
+    nt = min(args.steps, 200)
+    sim.step(nt)
+    ms_tot, launches = sim.timing_read()
+    sim.timing(False)
+    dt1 = sim.diag()["pushes"]
+    pass_pushes = (dt1 - dt0) / max(launches, 1)
+    avg_ms = ms_tot / max(launches, 1)
+    bytes_per_launch = (B_ALG_PARTICLE * pass_pushes + B_ALG_CELL * e["ncells"]
+                        + B_ALG_NODE * (e["ncells"] + 1))
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = traffic_from_profiles("sheath_1e5", pass_pushes)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_particles<fp32, push|collide|deposit>",
+                "avg_launch_ms": round(avg_ms, 5), "bytes_alg_per_launch": bytes_per_launch,
+                "launches_timed": launches}
+    step_bytes = (B_ALG_PARTICLE + 48.0 / e["sort_every"]) * (pushes / args.steps)
+    whole_step = {"bytes_alg_per_step": step_bytes,
+                  "frac_of_hbm_peak": round(step_bytes / (wall / args.steps) / 1e9 / HBM_PEAK_GBS, 4)}
+    del sim
+    torch.cuda.empty_cache()
+
+    plain = None
+    if not args.no_plain:
+        psim = pic.Sim(work, fused=False, precision="fp64")
+        psim.step(2)
+        torch.cuda.synchronize()
+        p0 = psim.diag()["pushes"]
+        pn = max(10, args.steps // 20)
+        tp0 = time.perf_counter()
+        psim.step(pn)
+        torch.cuda.synchronize()
+        tp1 = time.perf_counter()
+        pp = psim.diag()["pushes"] - p0
+        plain = {"value": pp / (tp1 - tp0), "ms_per_step": (tp1 - tp0) / pn * 1e3, "steps": pn,
+                 "form": "FP64 x/v particles, one kernel per stage, FP64 atomics deposit, no graph",
+                 "frac_of_hbm_peak_68B": round(68.0 * pp / (tp1 - tp0) / 1e9 / HBM_PEAK_GBS, 4)}
+        del psim
+        torch.cuda.empty_cache()
+
+    cpu = None if args.no_cpu else cpu_baseline(args.seed, args.cpu_steps)
+
+    out = {
+        "metric": "particle-pushes/s per full step at 1 MI355X",
+        "value": value, "unit": "particle-pushes/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"sheath slab {e['ncells']} cells x {e['species'][0]['ppc']} ppc x 2 species, "
+                               f"oblique B, 3 collision channels, sort every {e['sort_every']}",
+                   "particles": 2 * e["species"][0]["ppc"] * e["ncells"], "seed": args.seed,
+                   "form": "FP32 cell+offset, fused pass, HIP graph", "parallelism": "single GPU"},
+        "roofline": roofline,
+        "whole_step": whole_step,
+        "plain": plain,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,196 @@
+/*
+ * pic.h -- C ABI of the MI355X (gfx950) electrostatic 1D3V PIC Monte Carlo hot path.
+ *
+ * The library computes the per-step particle cycle that the paper's Background section
+ * names for its 1D3V electrostatic PIC MC code (particle load, mover, deposition to the
+ * grid, field solve, force interpolation, Monte Carlo collisions) plus the "natural
+ * sorting" of particles by cell the same section describes, for the magnetised
+ * double-bounded plasma layer of the paper's sheath-case table (absorbing walls, uniform
+ * neutral background).  The paper fixes no equations for these steps; the method each
+ * entry point implements is stated at its declaration.
+ *
+ * Conventions for every entry point:
+ *   - Return value: PIC_OK (0) or a negative PIC_E* code; nothing throws across the ABI.
+ *     pic_last_error(ctx) returns a message for the last failing call on that context.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Every call that
+ *     only enqueues GPU work is asynchronous on that stream; calls that return host data
+ *     (pic_diag, pic_get_*) and pic_set_* synchronise it.
+ *   - Device memory: the caller allocates ONE workspace of the size pic_query_workspace
+ *     reports and keeps it alive until pic_free; the library carves every particle, grid
+ *     and scratch array out of it and never allocates or frees device memory itself,
+ *     except the small per-context HIP graph objects.  Host pointers are only read during
+ *     the call.
+ *   - Normalised units: eps0 = e = m_e = n0 = T_e = 1 (omega_pe = v_th,e = lambda_D = 1).
+ *   - Sticky device error flags (capacity overflow, non-finite field) are checked at the
+ *     end of pic_step and in pic_diag; a non-zero flag turns into the matching PIC_E* code.
+ */
+#ifndef PIC_H
+#define PIC_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIC_OK 0
+#define PIC_EINVAL (-1)      /* bad configuration, index or size                          */
+#define PIC_ECAPACITY (-2)   /* particle, birth or id capacity exceeded: state undefined  */
+#define PIC_ENONFINITE (-3)  /* NaN or Inf met in the field solve                          */
+#define PIC_EHIP (-4)        /* HIP runtime error; message in pic_last_error               */
+#define PIC_ESTATE (-5)      /* call not valid in the current state                        */
+
+#define PIC_FP64_PLAIN 0     /* particles as x:f64, v:f64x3, id:u32                        */
+#define PIC_FP32_CELLOFF 1   /* particles as cell:i32, offset:f32 in [0,1), v:f32x3, id:u32 */
+
+#define PIC_ABSORBING 0      /* grounded absorbing walls at x = 0 and x = L               */
+#define PIC_PERIODIC 1
+
+#define PIC_MAX_ENSEMBLES 256
+
+typedef struct pic_ctx pic_ctx;
+
+typedef struct {
+    double q, m, w;      /* charge, mass, macro-particle weight (n0 L / P)                 */
+    double T;            /* temperature of the initial Maxwellian                          */
+    int64_t ppc;         /* initial particles per cell                                     */
+    int64_t capacity;    /* slots reserved for this species (>= ppc * ncells)             */
+} pic_species_desc;
+
+/* One independent plasma (an "ensemble"); a run holds 1 .. PIC_MAX_ENSEMBLES of them. */
+typedef struct {
+    int64_t ncells;      /* N >= 2 cells of width dx; N+1 nodes bounded, N periodic       */
+    double dx, dt, eps0;
+    double B[3];         /* uniform magnetic field                                         */
+    double E_ext;        /* uniform external field along x, added at the gather            */
+    uint32_t seed;       /* Philox key word 0 (word 1 is the species index)                */
+    int32_t init_mode;   /* 0: ppc per cell, Philox offsets + Maxwellian (R17);
+                            1: quiet start with a sine displacement (R19)                  */
+    pic_species_desc sp[2];                    /* 0 = electrons, 1 = ions                 */
+    double ngs_el, ngs_iz, ngs_cx;             /* n_g sigma: e-elastic, e-ionisation, CX  */
+    double eps_iz;                             /* ionisation energy                        */
+    double T_n, m_n;                           /* neutral temperature and mass             */
+    double perturb_amp;                        /* quiet start displacement amplitude A     */
+    int32_t perturb_mode;                      /* quiet start mode number                  */
+} pic_ensemble_desc;
+
+typedef struct {
+    int32_t n_ensembles;
+    int32_t precision;   /* PIC_FP64_PLAIN or PIC_FP32_CELLOFF                              */
+    int32_t boundary;    /* PIC_ABSORBING or PIC_PERIODIC (all ensembles)                   */
+    int32_t nspecies;    /* 1: electrons on a fixed neutralising background; 2: e + ions   */
+    int32_t collisions;  /* 0: collisionless                                               */
+    int32_t sort_every;  /* K: counting sort (which also compacts absorbed slots) when the
+                            step count reaches a multiple of K; 0 = compaction-only sort
+                            every 20 steps, physics unchanged either way                    */
+    int32_t fused;       /* 0: one kernel per stage; 1: fused particle pass + HIP graph    */
+    int32_t block;       /* threads per block for particle kernels; 0 = default            */
+    int32_t grid;        /* persistent blocks for particle kernels; 0 = default            */
+    int32_t window;      /* LDS deposit window in nodes (power of two); 0 = default        */
+    const pic_ensemble_desc *ens;              /* [n_ensembles], copied by pic_init       */
+} pic_config;
+
+/* Scalars of one ensemble.  Counts are exact; sums are FP64. */
+typedef struct {
+    int64_t count[2];            /* alive particles per species                            */
+    double charge;               /* sum_s q_s w_s count_s                                  */
+    double ke[2];                /* 1/2 m_s w_s sum |v|^2 (current velocities)             */
+    double field_energy;         /* 1/2 eps0 sum_j E_j^2 V_j of the last solved field      */
+    int64_t wall_count[2][2];    /* [left, right][species] particles absorbed (cumulative)  */
+    double wall_charge[2][2];    /* absorbed q w                                            */
+    double wall_ke[2][2];        /* absorbed 1/2 m w |v|^2                                  */
+    int64_t coll[3];             /* e-elastic, e-ionisation, ion CX events (cumulative)     */
+    int64_t created[2];          /* particles created per species (cumulative)              */
+    int64_t pushes;              /* particles pushed, summed over steps (cumulative)        */
+    int64_t step;                /* steps taken                                             */
+    double numax[2];             /* null-collision frequency bound of the last collide     */
+    double emax;                 /* max |E| of the last solved / set field                  */
+} pic_diag_out;
+
+/* Host-side particle exchange: absolute position x in [0, L), velocity, id. */
+typedef struct {
+    double *x, *vx, *vy, *vz;
+    uint32_t *id;
+} pic_particles;
+
+/* Bytes of device workspace a configuration needs (256-byte aligned). */
+int pic_query_workspace(const pic_config *cfg, size_t *bytes);
+
+/* Create a context on `workspace` (>= the queried size, device memory) and load the
+ * particles: reading R17 (random load) or R19 (quiet start) per ensemble, then the
+ * cloud-in-cell deposit Q^0.  The step counter starts at 0. */
+int pic_init(const pic_config *cfg, void *workspace, size_t bytes, void *stream, pic_ctx **out);
+
+/* Cloud-in-cell deposit (Birdsall-Langdon linear weighting) of every alive particle into
+ * the per-species node sums Q_s (FP32 form: int64 fixed point, 2^24 per particle; FP64
+ * form: FP64 sums).  Replaces the previous Q. */
+int pic_deposit(pic_ctx *ctx, void *stream);
+
+/* Field solve from Q: rho_j = sum_s q_s w_s Q_{s,j} / V_j, the three-point Poisson stencil
+ * with grounded walls (R3) or a neutralising background and zero-mean phi (R4), solved
+ * exactly by two prefix sums (equivalent to the Thomas solve, R5), node E from the centred
+ * difference with the half-cell Gauss rule at walls (R6).  FP64. */
+int pic_solve(pic_ctx *ctx, void *stream);
+
+/* Gather E at each particle (linear), Boris push in E + E_ext along x and uniform B,
+ * position update, absorbing walls (R8: absorbed slots are marked dead and tallied; the
+ * next sort compacts them) or periodic wrap. */
+int pic_push(pic_ctx *ctx, void *stream);
+
+/* Null-collision Monte Carlo (R9-R14): per-particle Philox decision against the bound
+ * nu_max, channel choice, scattering kinematics, ionisation births appended with ids
+ * next_id + rank of the parent id. */
+int pic_collide(pic_ctx *ctx, void *stream);
+
+/* Counting sort of each species by cell (histogram, exclusive scan, scatter); drops the
+ * absorbed slots, so it is also the stream compaction.  Order inside a cell is unspecified. */
+int pic_sort(pic_ctx *ctx, void *stream);
+
+/* nsteps full steps (R2 order): solve, push + walls, collide, deposit, and a sort when
+ * the new step count is a multiple of K.  With cfg.fused = 1 the particle stages run as
+ * one pass per step and the steps replay a captured HIP graph.  Synchronises the stream
+ * once at the end to read the sticky error flags. */
+int pic_step(pic_ctx *ctx, int32_t nsteps, void *stream);
+
+/* Scalars of ensemble `ens` (synchronises `stream`). */
+int pic_diag(pic_ctx *ctx, int32_t ens, pic_diag_out *out, void *stream);
+
+/* Copy the alive particles of (ens, species) to host arrays of length >= `cap`; `count`
+ * receives the number written.  Order unspecified (compare by id). */
+int pic_get_particles(pic_ctx *ctx, int32_t ens, int32_t species, pic_particles out,
+                      int64_t cap, int64_t *count, void *stream);
+
+/* Replace the particles of (ens, species) with `count` host particles (x in [0, L));
+ * next_id is the id the next created particle of this species receives. */
+int pic_set_particles(pic_ctx *ctx, int32_t ens, int32_t species, pic_particles in,
+                      int64_t count, uint32_t next_id, void *stream);
+
+/* Copy node arrays of ensemble `ens` to host (each may be NULL; length = node count):
+ * Q_s as particle units, rho, phi, E (self-consistent part). */
+int pic_get_grid(pic_ctx *ctx, int32_t ens, double *Q0, double *Q1, double *rho, double *phi,
+                 double *E, void *stream);
+
+/* Replace the self-consistent node field of ensemble `ens` with host values (test hook:
+ * push in a given field, e.g. zero). */
+int pic_set_fields(pic_ctx *ctx, int32_t ens, const double *E, void *stream);
+
+/* Set the step counter (the collision random-number tag of the next collide). */
+int pic_set_step(pic_ctx *ctx, int64_t step);
+
+/* Node count of ensemble `ens` (N+1 bounded, N periodic), or a negative error. */
+int64_t pic_nnodes(const pic_ctx *ctx, int32_t ens);
+
+/* Measurement hook: with `enable` != 0, pic_step runs its steps without the graph and
+ * brackets every particle-pass launch with HIP events recorded on the caller's stream
+ * (up to 65536 launches); pic_timing_read synchronises that stream and returns the summed
+ * kernel time in milliseconds and the number of timed launches.  Enabling again resets. */
+int pic_timing(pic_ctx *ctx, int32_t enable);
+int pic_timing_read(pic_ctx *ctx, double *ms_total, int64_t *launches, void *stream);
+
+void pic_free(pic_ctx *ctx);
+const char *pic_last_error(const pic_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

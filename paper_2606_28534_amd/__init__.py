@@ -1,0 +1,267 @@
+"""MI355X-native electrostatic 1D3V PIC Monte Carlo hot path: Python binding.
+
+A thin ctypes layer over the C ABI of libpic.so (declared in include/pic.h).  It only
+marshals arguments: torch provides the device workspace and the stream, and every stage
+of the step runs in the library's HIP kernels.  If the library is missing, importing the
+binding raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpic.so")
+
+PIC_OK, PIC_EINVAL, PIC_ECAPACITY, PIC_ENONFINITE, PIC_EHIP, PIC_ESTATE = 0, -1, -2, -3, -4, -5
+PIC_FP64_PLAIN, PIC_FP32_CELLOFF = 0, 1
+PIC_ABSORBING, PIC_PERIODIC = 0, 1
+
+EXPORTS = ("pic_query_workspace", "pic_init", "pic_deposit", "pic_solve", "pic_push",
+           "pic_collide", "pic_sort", "pic_step", "pic_diag", "pic_get_particles",
+           "pic_set_particles", "pic_get_grid", "pic_set_fields", "pic_set_step",
+           "pic_nnodes", "pic_timing", "pic_timing_read", "pic_free", "pic_last_error")
+
+
+class PicError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"pic error {code}: {msg}")
+        self.code = code
+
+
+class SpeciesDesc(C.Structure):
+    _fields_ = [("q", C.c_double), ("m", C.c_double), ("w", C.c_double), ("T", C.c_double),
+                ("ppc", C.c_int64), ("capacity", C.c_int64)]
+
+
+class EnsembleDesc(C.Structure):
+    _fields_ = [("ncells", C.c_int64), ("dx", C.c_double), ("dt", C.c_double),
+                ("eps0", C.c_double), ("B", C.c_double * 3), ("E_ext", C.c_double),
+                ("seed", C.c_uint32), ("init_mode", C.c_int32), ("sp", SpeciesDesc * 2),
+                ("ngs_el", C.c_double), ("ngs_iz", C.c_double), ("ngs_cx", C.c_double),
+                ("eps_iz", C.c_double), ("T_n", C.c_double), ("m_n", C.c_double),
+                ("perturb_amp", C.c_double), ("perturb_mode", C.c_int32)]
+
+
+class Config(C.Structure):
+    _fields_ = [("n_ensembles", C.c_int32), ("precision", C.c_int32), ("boundary", C.c_int32),
+                ("nspecies", C.c_int32), ("collisions", C.c_int32), ("sort_every", C.c_int32),
+                ("fused", C.c_int32), ("block", C.c_int32), ("grid", C.c_int32),
+                ("window", C.c_int32), ("ens", C.POINTER(EnsembleDesc))]
+
+
+class DiagOut(C.Structure):
+    _fields_ = [("count", C.c_int64 * 2), ("charge", C.c_double), ("ke", C.c_double * 2),
+                ("field_energy", C.c_double), ("wall_count", (C.c_int64 * 2) * 2),
+                ("wall_charge", (C.c_double * 2) * 2), ("wall_ke", (C.c_double * 2) * 2),
+                ("coll", C.c_int64 * 3), ("created", C.c_int64 * 2), ("pushes", C.c_int64),
+                ("step", C.c_int64), ("numax", C.c_double * 2), ("emax", C.c_double)]
+
+    def as_dict(self):
+        return {
+            "count": list(self.count), "charge": self.charge, "ke": list(self.ke),
+            "field_energy": self.field_energy,
+            "wall_count": [list(r) for r in self.wall_count],
+            "wall_charge": [list(r) for r in self.wall_charge],
+            "wall_ke": [list(r) for r in self.wall_ke],
+            "coll": list(self.coll), "created": list(self.created), "pushes": self.pushes,
+            "step": self.step, "numax": list(self.numax), "emax": self.emax,
+        }
+
+
+class Particles(C.Structure):
+    _fields_ = [("x", C.POINTER(C.c_double)), ("vx", C.POINTER(C.c_double)),
+                ("vy", C.POINTER(C.c_double)), ("vz", C.POINTER(C.c_double)),
+                ("id", C.POINTER(C.c_uint32))]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libpic.so (after torch, so both share one HIP runtime); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (no CPU fallback)")
+    import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+    L = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    L.pic_query_workspace.argtypes = [C.POINTER(Config), C.POINTER(C.c_size_t)]
+    L.pic_init.argtypes = [C.POINTER(Config), P, C.c_size_t, P, C.POINTER(P)]
+    for n in ("pic_deposit", "pic_solve", "pic_push", "pic_collide", "pic_sort"):
+        getattr(L, n).argtypes = [P, P]
+    L.pic_step.argtypes = [P, C.c_int32, P]
+    L.pic_diag.argtypes = [P, C.c_int32, C.POINTER(DiagOut), P]
+    L.pic_get_particles.argtypes = [P, C.c_int32, C.c_int32, Particles, C.c_int64,
+                                    C.POINTER(C.c_int64), P]
+    L.pic_set_particles.argtypes = [P, C.c_int32, C.c_int32, Particles, C.c_int64, C.c_uint32, P]
+    L.pic_get_grid.argtypes = [P, C.c_int32, P, P, P, P, P, P]
+    L.pic_set_fields.argtypes = [P, C.c_int32, P, P]
+    L.pic_set_step.argtypes = [P, C.c_int64]
+    L.pic_nnodes.argtypes = [P, C.c_int32]
+    L.pic_nnodes.restype = C.c_int64
+    L.pic_timing.argtypes = [P, C.c_int32]
+    L.pic_timing_read.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64), P]
+    L.pic_free.argtypes = [P]
+    L.pic_free.restype = None
+    L.pic_last_error.argtypes = [P]
+    L.pic_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def make_config(work, fused=True, precision=None, block=0, grid=0, window=0):
+    """Translate a workload dict ({"ensembles": [...], "precision": "fp32"|"fp64"}) into
+    the C configuration.  Returns (Config, keep-alive array)."""
+    ens = work["ensembles"]
+    arr = (EnsembleDesc * len(ens))()
+    for i, e in enumerate(ens):
+        d = arr[i]
+        d.ncells, d.dx, d.dt, d.eps0 = e["ncells"], e["dx"], e["dt"], e["eps0"]
+        for k in range(3):
+            d.B[k] = e["B"][k]
+        d.E_ext, d.seed, d.init_mode = e["E_ext"], e["seed"], e["init_mode"]
+        for s, sp in enumerate(e["species"]):
+            d.sp[s].q, d.sp[s].m, d.sp[s].w, d.sp[s].T = sp["q"], sp["m"], sp["w"], sp["T"]
+            d.sp[s].ppc, d.sp[s].capacity = sp["ppc"], sp["capacity"]
+        d.ngs_el, d.ngs_iz, d.ngs_cx = e["ngs_el"], e["ngs_iz"], e["ngs_cx"]
+        d.eps_iz, d.T_n, d.m_n = e["eps_iz"], e["T_n"], e["m_n"]
+        d.perturb_amp, d.perturb_mode = e["perturb_amp"], e["perturb_mode"]
+    e0 = ens[0]
+    prec = precision or work.get("precision", "fp32")
+    cfg = Config()
+    cfg.n_ensembles = len(ens)
+    cfg.precision = PIC_FP64_PLAIN if prec == "fp64" else PIC_FP32_CELLOFF
+    cfg.boundary = PIC_PERIODIC if e0["periodic"] else PIC_ABSORBING
+    cfg.nspecies = e0["nspecies"]
+    cfg.collisions = int(e0["collisions"])
+    cfg.sort_every = e0["sort_every"]
+    cfg.fused = int(fused)
+    cfg.block, cfg.grid, cfg.window = block, grid, window
+    cfg.ens = arr
+    return cfg, arr
+
+
+def _ptr(a):
+    return C.c_void_p(a.ctypes.data)
+
+
+class Sim:
+    """One run of the PIC MC hot path on the current GPU (torch provides the memory)."""
+
+    def __init__(self, work, fused=True, precision=None, block=0, grid=0, window=0, stream=None):
+        import torch
+
+        self.L = load_library()
+        self.work = work
+        self.cfg, self._arr = make_config(work, fused, precision, block, grid, window)
+        nbytes = C.c_size_t(0)
+        self._check(self.L.pic_query_workspace(C.byref(self.cfg), C.byref(nbytes)), None)
+        self.ws_bytes = nbytes.value
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.h = C.c_void_p()
+        self._check(self.L.pic_init(C.byref(self.cfg), C.c_void_p(self.ws.data_ptr()),
+                                    self.ws_bytes, self._s(), C.byref(self.h)), None)
+        self.nens = len(work["ensembles"])
+        self.nspecies = work["ensembles"][0]["nspecies"]
+
+    def _s(self):
+        return C.c_void_p(self.stream.cuda_stream)
+
+    def _check(self, rc, h="self"):
+        if rc != PIC_OK:
+            hh = self.h if h == "self" else None
+            msg = self.L.pic_last_error(hh).decode() if hh else "see stderr"
+            raise PicError(rc, msg)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.pic_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- stages -------------------------------------------------------------------------
+    def deposit(self):
+        self._check(self.L.pic_deposit(self.h, self._s()))
+
+    def solve(self):
+        self._check(self.L.pic_solve(self.h, self._s()))
+
+    def push(self):
+        self._check(self.L.pic_push(self.h, self._s()))
+
+    def collide(self):
+        self._check(self.L.pic_collide(self.h, self._s()))
+
+    def sort(self):
+        self._check(self.L.pic_sort(self.h, self._s()))
+
+    def step(self, n=1):
+        self._check(self.L.pic_step(self.h, int(n), self._s()))
+
+    def timing(self, enable=True):
+        self._check(self.L.pic_timing(self.h, int(bool(enable))))
+
+    def timing_read(self):
+        ms, n = C.c_double(0), C.c_int64(0)
+        self._check(self.L.pic_timing_read(self.h, C.byref(ms), C.byref(n), self._s()))
+        return ms.value, n.value
+
+    def set_step(self, n):
+        self._check(self.L.pic_set_step(self.h, int(n)))
+
+    # ---- data exchange ------------------------------------------------------------------
+    def diag(self, ens=0):
+        d = DiagOut()
+        self._check(self.L.pic_diag(self.h, int(ens), C.byref(d), self._s()))
+        return d.as_dict()
+
+    def nnodes(self, ens=0):
+        return int(self.L.pic_nnodes(self.h, int(ens)))
+
+    def particles(self, ens=0, s=0):
+        cap = int(self.work["ensembles"][ens]["species"][s]["capacity"])
+        x, vx, vy, vz = (np.empty(cap) for _ in range(4))
+        ids = np.empty(cap, dtype=np.uint32)
+        p = Particles(x.ctypes.data_as(C.POINTER(C.c_double)), vx.ctypes.data_as(C.POINTER(C.c_double)),
+                      vy.ctypes.data_as(C.POINTER(C.c_double)), vz.ctypes.data_as(C.POINTER(C.c_double)),
+                      ids.ctypes.data_as(C.POINTER(C.c_uint32)))
+        n = C.c_int64(0)
+        self._check(self.L.pic_get_particles(self.h, int(ens), int(s), p, cap, C.byref(n), self._s()))
+        k = n.value
+        return {"x": x[:k].copy(), "vx": vx[:k].copy(), "vy": vy[:k].copy(), "vz": vz[:k].copy(),
+                "id": ids[:k].copy()}
+
+    def set_particles(self, ens, s, x, vx, vy, vz, ids, next_id):
+        x, vx, vy, vz = (np.ascontiguousarray(a, dtype=np.float64) for a in (x, vx, vy, vz))
+        ids = np.ascontiguousarray(ids, dtype=np.uint32)
+        p = Particles(x.ctypes.data_as(C.POINTER(C.c_double)), vx.ctypes.data_as(C.POINTER(C.c_double)),
+                      vy.ctypes.data_as(C.POINTER(C.c_double)), vz.ctypes.data_as(C.POINTER(C.c_double)),
+                      ids.ctypes.data_as(C.POINTER(C.c_uint32)))
+        self._check(self.L.pic_set_particles(self.h, int(ens), int(s), p, len(x), int(next_id), self._s()))
+
+    def set_state(self, state, ens=0):
+        for s, st in enumerate(state):
+            self.set_particles(ens, s, st["x"], st["vx"], st["vy"], st["vz"], st["id"], st["next_id"])
+
+    def grid(self, ens=0):
+        nn = self.nnodes(ens)
+        Q0, Q1, rho, phi, E = (np.zeros(nn) for _ in range(5))
+        self._check(self.L.pic_get_grid(self.h, int(ens), _ptr(Q0), _ptr(Q1), _ptr(rho), _ptr(phi),
+                                        _ptr(E), self._s()))
+        return {"Q": [Q0, Q1][: self.nspecies], "rho": rho, "phi": phi, "E": E}
+
+    def set_fields(self, E, ens=0):
+        E = np.ascontiguousarray(E, dtype=np.float64)
+        assert len(E) == self.nnodes(ens)
+        self._check(self.L.pic_set_fields(self.h, int(ens), _ptr(E), self._s()))

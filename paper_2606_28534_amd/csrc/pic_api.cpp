@@ -1,0 +1,789 @@
+// pic_api.cpp -- C ABI, context and workspace management, step scheduling and HIP graph
+// capture of the gfx950 PIC MC library.  See include/pic.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pic.h"
+#include "pic_device.h"
+#include "pic_kernels.h"
+
+using namespace pic;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kCompactEvery = 20;  // sort cadence used for compaction when K = 0
+constexpr int kDiagGrid = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Sizes derived from a configuration; shared by the query and the carving.
+struct Plan {
+    int nens = 0, nseg = 0, nspecies = 0;
+    bool f64 = false;
+    std::vector<SegC> seg;
+    std::vector<EnsC> ens;
+    int64_t cap_tot = 0, nodes_tot = 0, cells_tot = 0, chunks_tot = 0;
+    int64_t bm_words = 0, l1_tot = 0, birth_stripe_cap = 0;
+    int64_t scanpart = 0;
+    size_t bytes = 0;
+};
+
+int build_plan(const pic_config *cfg, Plan &P, std::string &msg)
+{
+    if (!cfg || !cfg->ens) {
+        msg = "null config";
+        return PIC_EINVAL;
+    }
+    if (cfg->n_ensembles < 1 || cfg->n_ensembles > 256) {
+        msg = "n_ensembles must be in [1, 256]";
+        return PIC_EINVAL;
+    }
+    if (cfg->nspecies < 1 || cfg->nspecies > 2) {
+        msg = "nspecies must be 1 or 2";
+        return PIC_EINVAL;
+    }
+    if (cfg->precision != PIC_FP64_PLAIN && cfg->precision != PIC_FP32_CELLOFF) {
+        msg = "bad precision";
+        return PIC_EINVAL;
+    }
+    if (cfg->boundary != PIC_ABSORBING && cfg->boundary != PIC_PERIODIC) {
+        msg = "bad boundary";
+        return PIC_EINVAL;
+    }
+    P.nens = cfg->n_ensembles;
+    P.nspecies = cfg->nspecies;
+    P.nseg = P.nens * P.nspecies;
+    P.f64 = cfg->precision == PIC_FP64_PLAIN;
+    const bool periodic = cfg->boundary == PIC_PERIODIC;
+    int64_t base = 0, gbase = 0, cbase = 0, chunk0 = 0, bm = 0, l1 = 0, ecap = 0;
+    for (int e = 0; e < P.nens; ++e) {
+        const pic_ensemble_desc &D = cfg->ens[e];
+        if (D.ncells < 2 || D.ncells > (int64_t)1 << 30 || !(D.dx > 0) || !(D.dt > 0) || !(D.eps0 > 0)) {
+            msg = "ensemble " + std::to_string(e) + ": bad ncells/dx/dt/eps0";
+            return PIC_EINVAL;
+        }
+        EnsC E{};
+        E.ncells = D.ncells;
+        E.nnodes = periodic ? D.ncells : D.ncells + 1;
+        E.gbase = gbase;
+        E.chunk0 = chunk0;
+        E.nchunks = (E.nnodes + kChunk - 1) / kChunk;
+        E.dx = D.dx;
+        E.dt = D.dt;
+        E.eps0 = D.eps0;
+        E.E_ext = D.E_ext;
+        E.L = (double)D.ncells * D.dx;
+        E.ngs_el = D.ngs_el;
+        E.ngs_iz = D.ngs_iz;
+        E.ngs_cx = D.ngs_cx;
+        E.eps_iz = D.eps_iz;
+        E.vn = (D.m_n > 0) ? std::sqrt(D.T_n / D.m_n) : 0.0;
+        E.m_e = D.sp[0].m;
+        E.m_n = D.m_n;
+        E.seed = D.seed;
+        E.periodic = periodic ? 1 : 0;
+        E.nspecies = P.nspecies;
+        // birth ranking: ids below 2 x electron capacity (rounded to 1024)
+        int64_t idcap = (2 * D.sp[0].capacity + 2048) / 1024 * 1024;
+        idcap = std::min<int64_t>(idcap, ((int64_t)1 << 32) - 1024);
+        E.idcap = idcap;
+        E.bm_base = bm;
+        E.l1_base = l1;
+        bm += idcap / 32;
+        l1 += idcap / 1024;
+        for (int s = 0; s < P.nspecies; ++s) {
+            const pic_species_desc &sp = D.sp[s];
+            if (sp.capacity < sp.ppc * D.ncells || sp.capacity < 1 || sp.ppc < 0 || !(sp.m > 0)) {
+                msg = "ensemble " + std::to_string(e) + " species " + std::to_string(s) +
+                      ": capacity < ppc * ncells or bad mass";
+                return PIC_EINVAL;
+            }
+            if (sp.capacity > ((int64_t)1 << 32) - 1) {
+                msg = "capacity above 2^32 - 1 per species";
+                return PIC_EINVAL;
+            }
+            E.qw[s] = sp.q * sp.w;
+            SegC S{};
+            S.base = base;
+            S.cap = sp.capacity;
+            S.cbase = cbase;
+            S.gbase = gbase;
+            S.ens = e;
+            S.species = s;
+            S.ncells = (int32_t)D.ncells;
+            S.periodic = E.periodic;
+            S.h = sp.q / sp.m * 0.5 * D.dt;
+            for (int k = 0; k < 3; ++k) S.t[k] = S.h * D.B[k];
+            const double tt = S.t[0] * S.t[0] + S.t[1] * S.t[1] + S.t[2] * S.t[2];
+            for (int k = 0; k < 3; ++k) S.s[k] = 2.0 / (1.0 + tt) * S.t[k];
+            S.dt = D.dt;
+            S.dx = D.dx;
+            S.dtdx = D.dt / D.dx;
+            S.qw = sp.q * sp.w;
+            S.halfmw = 0.5 * sp.m * sp.w;
+            S.m = sp.m;
+            S.ngsT = cfg->collisions ? ((s == 0) ? D.ngs_el + D.ngs_iz : D.ngs_cx) : 0.0;
+            S.qm_abs = std::fabs(sp.q / sp.m);
+            S.seed = D.seed;
+            S.other = (s == 0 && P.nspecies > 1) ? (int32_t)(P.seg.size() + 1) : -1;
+            E.seg[s] = (int32_t)P.seg.size();
+            P.seg.push_back(S);
+            base += sp.capacity;
+            cbase += D.ncells;
+            if (s == 0) ecap += sp.capacity;
+        }
+        if (P.nspecies == 1) E.seg[1] = -1;
+        P.ens.push_back(E);
+        gbase += E.nnodes;
+        chunk0 += E.nchunks;
+    }
+    P.cap_tot = base;
+    P.nodes_tot = gbase;
+    P.cells_tot = cbase;
+    P.chunks_tot = chunk0;
+    P.bm_words = bm;
+    P.l1_tot = l1 + 1;
+    P.birth_stripe_cap = std::max<int64_t>(4096, (int64_t)std::ceil(4e-3 * (double)ecap / kStripes));
+    P.scanpart = std::max(scan_blocks(P.l1_tot), scan_blocks(P.cells_tot)) + 1;
+    return PIC_OK;
+}
+
+struct Carver {
+    char *base;
+    size_t off = 0;
+    template <typename T>
+    T *take(int64_t n)
+    {
+        T *p = base ? (T *)(base + off) : nullptr;
+        off += align_up((size_t)std::max<int64_t>(n, 1) * sizeof(T));
+        return p;
+    }
+};
+
+// Carve the workspace (base == nullptr only measures).
+size_t carve(const Plan &P, char *base, Dev &d)
+{
+    Carver c{base};
+    memset(&d, 0, sizeof(d));
+    d.nseg = P.nseg;
+    d.nens = P.nens;
+    d.nspecies = P.nspecies;
+    d.seg = c.take<SegC>(P.nseg);
+    d.ens = c.take<EnsC>(P.nens);
+    for (int b = 0; b < 2; ++b) {
+        d.id[b] = c.take<uint32_t>(P.cap_tot);
+        if (P.f64) {
+            d.x[b] = c.take<double>(P.cap_tot);
+            d.dvx[b] = c.take<double>(P.cap_tot);
+            d.dvy[b] = c.take<double>(P.cap_tot);
+            d.dvz[b] = c.take<double>(P.cap_tot);
+        } else {
+            d.cell[b] = c.take<int32_t>(P.cap_tot);
+            d.off[b] = c.take<float>(P.cap_tot);
+            d.fvx[b] = c.take<float>(P.cap_tot);
+            d.fvy[b] = c.take<float>(P.cap_tot);
+            d.fvz[b] = c.take<float>(P.cap_tot);
+        }
+    }
+    d.cur = c.take<int32_t>(1);
+    d.n_slots = c.take<int64_t>(P.nseg);
+    d.next_id = c.take<uint32_t>(P.nseg);
+    d.step = c.take<int64_t>(1);
+    d.nodes_tot = P.nodes_tot;
+    d.cells_tot = P.cells_tot;
+    d.Qi = c.take<unsigned long long>(2 * P.nodes_tot);
+    d.Qd = (double *)d.Qi;
+    d.rho = c.take<double>(P.nodes_tot);
+    d.phi = c.take<double>(P.nodes_tot);
+    d.E = c.take<double>(P.nodes_tot);
+    d.Ecell = c.take<float2>(P.nodes_tot);
+    d.agg = c.take<double>(P.chunks_tot * A_NAGG);
+    d.part = c.take<double>(P.chunks_tot * P_NPART);
+    d.emax = c.take<double>(P.nens);
+    d.fe = c.take<double>(P.nens);
+    d.numax = c.take<double>(P.nseg);
+    d.pnull = c.take<double>(P.nseg);
+    d.vmax2 = c.take<unsigned long long>(2 * kStripes * P.nseg);
+    d.vcur = c.take<int32_t>(1);
+    d.cnt = c.take<unsigned long long>((int64_t)kStripes * P.nseg * C_NCNT);
+    d.sums = c.take<double>((int64_t)kStripes * P.nseg * S_NSUM);
+    d.birth_stripe_cap = P.birth_stripe_cap;
+    d.births = c.take<Birth>(kStripes * P.birth_stripe_cap);
+    d.nbirth = c.take<uint32_t>(kStripes);
+    d.bitmap = c.take<uint32_t>(P.bm_words);
+    d.l1cnt = c.take<uint32_t>(P.l1_tot);
+    d.l1pre = c.take<uint32_t>(P.l1_tot);
+    d.l1_tot = P.l1_tot;
+    d.cellcnt = c.take<uint32_t>(P.cells_tot);
+    d.cursor = c.take<uint32_t>(P.cells_tot);
+    d.segstart = c.take<int64_t>(P.nseg);
+    d.scanpart = c.take<uint32_t>(P.scanpart);
+    d.ticket = c.take<uint32_t>(8);
+    d.err = c.take<int32_t>(1);
+    c.take<double>(2 * kDiagGrid);  // diag scratch (last region)
+    return c.off;
+}
+
+}  // namespace
+
+struct pic_ctx {
+    pic_config cfg{};
+    std::vector<pic_ensemble_desc> ens;
+    Plan P;
+    Dev d{};
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    double *diag_scratch = nullptr;
+    Launch L{};
+    int64_t host_step = 0;
+    int sort_every = 0;  // effective cadence (>= 1)
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph = nullptr;
+    std::string msg;
+    // measurement hook
+    bool timing = false;
+    std::vector<hipEvent_t> ev;  // pairs
+    int64_t ev_used = 0;
+};
+
+namespace {
+
+int fail(pic_ctx *c, int code, const std::string &m)
+{
+    if (c) c->msg = m;
+    return code;
+}
+
+int hipfail(pic_ctx *c, hipError_t e, const char *where)
+{
+    return fail(c, PIC_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPC(ctx, expr)                                   \
+    do {                                                  \
+        hipError_t _e = (expr);                           \
+        if (_e != hipSuccess) return hipfail(ctx, _e, #expr); \
+    } while (0)
+
+int check_err(pic_ctx *c, hipStream_t s)
+{
+    int32_t err = 0;
+    HIPC(c, hipMemcpyAsync(&err, c->d.err, sizeof(err), hipMemcpyDeviceToHost, s));
+    HIPC(c, hipStreamSynchronize(s));
+    if (err & (E_CAP_PART | E_CAP_BIRTH | E_CAP_ID))
+        return fail(c, PIC_ECAPACITY, "capacity exceeded (flags " + std::to_string(err) + ")");
+    if (err & E_NONFINITE) return fail(c, PIC_ENONFINITE, "non-finite field");
+    return PIC_OK;
+}
+
+bool is_sort_step(const pic_ctx *c, int64_t step_after) { return step_after % c->sort_every == 0; }
+
+// Enqueue one full step; `sort_now` when the step count after it is a multiple of K.
+hipError_t enqueue_step(pic_ctx *c, hipStream_t s, bool sort_now)
+{
+    const Dev &d = c->d;
+    const bool f64 = c->P.f64;
+    const bool coll = c->cfg.collisions != 0;
+    hipError_t e;
+    const bool tm = c->timing && c->ev_used + 2 <= (int64_t)c->ev.size();
+    if (c->cfg.fused) {
+        if ((e = launch_solve(d, f64, c->P.chunks_tot, true, s)) != hipSuccess) return e;
+        const int stages = coll ? (SB_PUSH | SB_COLLIDE | SB_DEPOSIT) : (SB_PUSH | SB_DEPOSIT);
+        if (tm && (e = hipEventRecord(c->ev[c->ev_used], s)) != hipSuccess) return e;
+        if ((e = launch_particles(d, c->L, s, f64, stages, sort_now ? 1 : 0)) != hipSuccess) return e;
+        if (tm) {
+            if ((e = hipEventRecord(c->ev[c->ev_used + 1], s)) != hipSuccess) return e;
+            c->ev_used += 2;
+        }
+        if (coll) {
+            if ((e = launch_births(d, f64, true, s)) != hipSuccess) return e;
+        } else if ((e = launch_advance(d, s)) != hipSuccess) {
+            return e;
+        }
+        if (sort_now && (e = launch_sort(d, f64, c->L, s)) != hipSuccess) return e;
+        return hipSuccess;
+    }
+    if ((e = launch_solve(d, f64, c->P.chunks_tot, false, s)) != hipSuccess) return e;
+    if (tm && (e = hipEventRecord(c->ev[c->ev_used], s)) != hipSuccess) return e;
+    if ((e = launch_particles(d, c->L, s, f64, SB_PUSH, 0)) != hipSuccess) return e;
+    if (tm) {
+        if ((e = hipEventRecord(c->ev[c->ev_used + 1], s)) != hipSuccess) return e;
+        c->ev_used += 2;
+    }
+    if (coll) {
+        if ((e = launch_particles(d, c->L, s, f64, SB_COLLIDE, 0)) != hipSuccess) return e;
+        if ((e = launch_births(d, f64, false, s)) != hipSuccess) return e;
+    }
+    if ((e = launch_zero_q(d, f64, s)) != hipSuccess) return e;
+    if ((e = launch_particles(d, c->L, s, f64, SB_DEPOSIT, 0)) != hipSuccess) return e;
+    if ((e = launch_advance(d, s)) != hipSuccess) return e;
+    if (sort_now) {
+        if ((e = launch_particles(d, c->L, s, f64, SB_HIST, 0)) != hipSuccess) return e;
+        if ((e = launch_sort(d, f64, c->L, s)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int build_graph(pic_ctx *c)
+{
+    if (c->graph) return PIC_OK;
+    if (!c->cap_stream) HIPC(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    HIPC(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < c->sort_every && e == hipSuccess; ++i)
+        e = enqueue_step(c, c->cap_stream, i == c->sort_every - 1);
+    hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+    if (e != hipSuccess) return hipfail(c, e, "graph capture");
+    if (e2 != hipSuccess) return hipfail(c, e2, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c->graph = nullptr;
+        return hipfail(c, e, "hipGraphInstantiate");
+    }
+    return PIC_OK;
+}
+
+Launch default_launch(const pic_config *cfg, const Plan &P)
+{
+    Launch L;
+    L.block = cfg->block > 0 ? cfg->block : 256;
+    L.ppt = 4;
+    int64_t tiles = 0;
+    for (const SegC &S : P.seg) tiles += (S.cap + (int64_t)L.block * L.ppt - 1) / ((int64_t)L.block * L.ppt);
+    int g = cfg->grid > 0 ? cfg->grid : 2048;
+    g = (int)std::min<int64_t>(g, std::max<int64_t>(8, (tiles + 7) / 8 * 8));
+    L.grid = std::max(8, g / 8 * 8);
+    L.window = cfg->window > 0 ? cfg->window : 256;
+    return L;
+}
+
+}  // namespace
+
+// =======================================================================================
+extern "C" {
+
+int pic_query_workspace(const pic_config *cfg, size_t *bytes)
+{
+    Plan P;
+    std::string m;
+    int rc = build_plan(cfg, P, m);
+    if (rc) return rc;
+    Dev d;
+    *bytes = carve(P, nullptr, d);
+    return PIC_OK;
+}
+
+int pic_init(const pic_config *cfg, void *workspace, size_t bytes, void *stream, pic_ctx **out)
+{
+    if (!out) return PIC_EINVAL;
+    *out = nullptr;
+    pic_ctx *c = new pic_ctx();
+    int rc = build_plan(cfg, c->P, c->msg);
+    if (rc) {
+        fprintf(stderr, "pic_init: %s\n", c->msg.c_str());
+        delete c;
+        return rc;
+    }
+    c->cfg = *cfg;
+    c->ens.assign(cfg->ens, cfg->ens + cfg->n_ensembles);
+    c->cfg.ens = c->ens.data();
+    const size_t need = carve(c->P, nullptr, c->d);
+    if (!workspace || bytes < need) {
+        fprintf(stderr, "pic_init: workspace too small (%zu < %zu)\n", bytes, need);
+        delete c;
+        return PIC_EINVAL;
+    }
+    c->ws = (char *)workspace;
+    c->ws_bytes = bytes;
+    carve(c->P, c->ws, c->d);
+    c->d.periodic = cfg->boundary == PIC_PERIODIC;
+    c->d.collisions = cfg->collisions;
+    c->diag_scratch = (double *)(c->ws + need - align_up(2 * kDiagGrid * sizeof(double)));
+    c->L = default_launch(cfg, c->P);
+    c->sort_every = cfg->sort_every > 0 ? cfg->sort_every : kCompactEvery;
+    hipStream_t s = (hipStream_t)stream;
+    Dev &d = c->d;
+    auto done = [&](int code) {
+        if (code != PIC_OK) {
+            fprintf(stderr, "pic_init: %s\n", c->msg.c_str());
+            delete c;
+            return code;
+        }
+        *out = c;
+        return PIC_OK;
+    };
+    hipError_t e;
+#define IHIP(expr)                                              \
+    if ((e = (expr)) != hipSuccess) return done(hipfail(c, e, #expr));
+    IHIP(hipMemsetAsync(c->ws, 0, need, s));
+    IHIP(hipMemcpyAsync((void *)d.seg, c->P.seg.data(), c->P.seg.size() * sizeof(SegC), hipMemcpyHostToDevice, s));
+    IHIP(hipMemcpyAsync((void *)d.ens, c->P.ens.data(), c->P.ens.size() * sizeof(EnsC), hipMemcpyHostToDevice, s));
+    std::vector<int64_t> nslots(c->P.nseg);
+    std::vector<uint32_t> nid(c->P.nseg);
+    for (int sg = 0; sg < c->P.nseg; ++sg) {
+        const SegC &S = c->P.seg[sg];
+        const pic_ensemble_desc &D = cfg->ens[S.ens];
+        const pic_species_desc &sp = D.sp[S.species];
+        const int64_t n = sp.ppc * D.ncells;
+        nslots[sg] = n;
+        nid[sg] = (uint32_t)n;
+        const double vth = std::sqrt(sp.T / sp.m);
+        IHIP(launch_init(d, c->P.f64, sg, n, sp.ppc, D.init_mode, vth, D.perturb_amp, D.perturb_mode, s));
+    }
+    IHIP(hipMemcpyAsync(d.n_slots, nslots.data(), nslots.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    IHIP(hipMemcpyAsync(d.next_id, nid.data(), nid.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    IHIP(launch_vmax(d, c->P.f64, s));
+    IHIP(launch_zero_q(d, c->P.f64, s));
+    IHIP(launch_particles(d, c->L, s, c->P.f64, SB_DEPOSIT, 0));
+    IHIP(hipStreamSynchronize(s));
+#undef IHIP
+    return done(PIC_OK);
+}
+
+int pic_deposit(pic_ctx *c, void *stream)
+{
+    if (!c) return PIC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    HIPC(c, launch_zero_q(c->d, c->P.f64, s));
+    HIPC(c, launch_particles(c->d, c->L, s, c->P.f64, SB_DEPOSIT, 0));
+    return PIC_OK;
+}
+
+int pic_solve(pic_ctx *c, void *stream)
+{
+    if (!c) return PIC_EINVAL;
+    HIPC(c, launch_solve(c->d, c->P.f64, c->P.chunks_tot, false, (hipStream_t)stream));
+    return PIC_OK;
+}
+
+int pic_push(pic_ctx *c, void *stream)
+{
+    if (!c) return PIC_EINVAL;
+    HIPC(c, launch_particles(c->d, c->L, (hipStream_t)stream, c->P.f64, SB_PUSH, 0));
+    return PIC_OK;
+}
+
+int pic_collide(pic_ctx *c, void *stream)
+{
+    if (!c) return PIC_EINVAL;
+    if (!c->cfg.collisions) return PIC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    HIPC(c, launch_params(c->d, s));
+    HIPC(c, launch_particles(c->d, c->L, s, c->P.f64, SB_COLLIDE, 0));
+    HIPC(c, launch_births(c->d, c->P.f64, false, s));
+    return PIC_OK;
+}
+
+int pic_sort(pic_ctx *c, void *stream)
+{
+    if (!c) return PIC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    HIPC(c, launch_particles(c->d, c->L, s, c->P.f64, SB_HIST, 0));
+    HIPC(c, launch_sort(c->d, c->P.f64, c->L, s));
+    return PIC_OK;
+}
+
+int pic_step(pic_ctx *c, int32_t nsteps, void *stream)
+{
+    if (!c || nsteps < 0) return PIC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const int K = c->sort_every;
+    while (nsteps > 0) {
+        if (c->cfg.fused && !c->timing && c->host_step % K == 0 && nsteps >= K) {
+            int rc = build_graph(c);
+            if (rc) return rc;
+            HIPC(c, hipGraphLaunch(c->graph, s));
+            c->host_step += K;
+            nsteps -= K;
+        } else {
+            HIPC(c, enqueue_step(c, s, is_sort_step(c, c->host_step + 1)));
+            c->host_step += 1;
+            nsteps -= 1;
+        }
+    }
+    return check_err(c, s);
+}
+
+int pic_set_step(pic_ctx *c, int64_t step)
+{
+    if (!c || step < 0) return PIC_EINVAL;
+    HIPC(c, hipMemcpy(c->d.step, &step, sizeof(step), hipMemcpyHostToDevice));
+    c->host_step = step;
+    return PIC_OK;
+}
+
+int64_t pic_nnodes(const pic_ctx *c, int32_t ens)
+{
+    if (!c || ens < 0 || ens >= c->P.nens) return PIC_EINVAL;
+    return c->P.ens[ens].nnodes;
+}
+
+int pic_diag(pic_ctx *c, int32_t ens, pic_diag_out *out, void *stream)
+{
+    if (!c || !out || ens < 0 || ens >= c->P.nens) return PIC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const int nseg = c->P.nseg;
+    std::vector<unsigned long long> cnt((size_t)kStripes * nseg * C_NCNT);
+    std::vector<double> sums((size_t)kStripes * nseg * S_NSUM);
+    HIPC(c, hipMemcpyAsync(cnt.data(), c->d.cnt, cnt.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPC(c, hipMemcpyAsync(sums.data(), c->d.sums, sums.size() * 8, hipMemcpyDeviceToHost, s));
+    double emax = 0, fe = 0;
+    std::vector<double> numax(nseg);
+    int64_t step = 0;
+    HIPC(c, hipMemcpyAsync(&emax, c->d.emax + ens, 8, hipMemcpyDeviceToHost, s));
+    HIPC(c, hipMemcpyAsync(&fe, c->d.fe + ens, 8, hipMemcpyDeviceToHost, s));
+    HIPC(c, hipMemcpyAsync(numax.data(), c->d.numax, nseg * 8, hipMemcpyDeviceToHost, s));
+    HIPC(c, hipMemcpyAsync(&step, c->d.step, 8, hipMemcpyDeviceToHost, s));
+    memset(out, 0, sizeof(*out));
+    const EnsC &E = c->P.ens[ens];
+    std::vector<double> part(2 * kDiagGrid);
+    for (int sp = 0; sp < c->P.nspecies; ++sp) {
+        const int sg = E.seg[sp];
+        HIPC(c, launch_diag(c->d, c->P.f64, sg, c->diag_scratch, kDiagGrid, s));
+        HIPC(c, hipMemcpyAsync(part.data(), c->diag_scratch, part.size() * 8, hipMemcpyDeviceToHost, s));
+        HIPC(c, hipStreamSynchronize(s));
+        double n = 0, v2 = 0;
+        for (int i = 0; i < kDiagGrid; ++i) {
+            n += part[2 * i];
+            v2 += part[2 * i + 1];
+        }
+        const pic_species_desc &D = c->ens[ens].sp[sp];
+        out->count[sp] = (int64_t)n;
+        out->ke[sp] = 0.5 * D.m * D.w * v2;
+        out->charge += D.q * D.w * n;
+        unsigned long long a[C_NCNT] = {0};
+        double kl = 0, kr = 0;
+        for (int st = 0; st < kStripes; ++st) {
+            for (int k = 0; k < C_NCNT; ++k) a[k] += cnt[((size_t)st * nseg + sg) * C_NCNT + k];
+            kl += sums[((size_t)st * nseg + sg) * S_NSUM + S_KE_L];
+            kr += sums[((size_t)st * nseg + sg) * S_NSUM + S_KE_R];
+        }
+        out->wall_count[0][sp] = (int64_t)a[C_WALL_L];
+        out->wall_count[1][sp] = (int64_t)a[C_WALL_R];
+        out->wall_charge[0][sp] = D.q * D.w * (double)a[C_WALL_L];
+        out->wall_charge[1][sp] = D.q * D.w * (double)a[C_WALL_R];
+        out->wall_ke[0][sp] = kl;
+        out->wall_ke[1][sp] = kr;
+        out->created[sp] = (int64_t)a[C_CREATED];
+        out->pushes += (int64_t)a[C_PUSH];
+        if (sp == 0) {
+            out->coll[0] = (int64_t)a[C_EL];
+            out->coll[1] = (int64_t)a[C_IZ];
+        } else {
+            out->coll[2] = (int64_t)a[C_CX];
+        }
+        out->numax[sp] = numax[sg];
+    }
+    out->field_energy = fe;
+    out->emax = emax;
+    out->step = step;
+    return check_err(c, s);
+}
+
+int pic_get_particles(pic_ctx *c, int32_t ens, int32_t species, pic_particles out, int64_t cap,
+                      int64_t *count, void *stream)
+{
+    if (!c || !count || ens < 0 || ens >= c->P.nens || species < 0 || species >= c->P.nspecies)
+        return fail(c, PIC_EINVAL, "bad ensemble/species");
+    hipStream_t s = (hipStream_t)stream;
+    const int sg = c->P.ens[ens].seg[species];
+    const SegC &S = c->P.seg[sg];
+    int64_t n = 0;
+    int32_t b = 0;
+    HIPC(c, hipMemcpyAsync(&n, c->d.n_slots + sg, 8, hipMemcpyDeviceToHost, s));
+    HIPC(c, hipMemcpyAsync(&b, c->d.cur, 4, hipMemcpyDeviceToHost, s));
+    HIPC(c, hipStreamSynchronize(s));
+    std::vector<uint32_t> id(n);
+    HIPC(c, hipMemcpy(id.data(), c->d.id[b] + S.base, n * 4, hipMemcpyDeviceToHost));
+    int64_t k = 0;
+    if (c->P.f64) {
+        std::vector<double> x(n), vx(n), vy(n), vz(n);
+        HIPC(c, hipMemcpy(x.data(), c->d.x[b] + S.base, n * 8, hipMemcpyDeviceToHost));
+        HIPC(c, hipMemcpy(vx.data(), c->d.dvx[b] + S.base, n * 8, hipMemcpyDeviceToHost));
+        HIPC(c, hipMemcpy(vy.data(), c->d.dvy[b] + S.base, n * 8, hipMemcpyDeviceToHost));
+        HIPC(c, hipMemcpy(vz.data(), c->d.dvz[b] + S.base, n * 8, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < n; ++i) {
+            if (!(x[i] >= 0.0)) continue;
+            if (k >= cap) return fail(c, PIC_EINVAL, "output capacity too small");
+            out.x[k] = x[i];
+            out.vx[k] = vx[i];
+            out.vy[k] = vy[i];
+            out.vz[k] = vz[i];
+            out.id[k] = id[i];
+            ++k;
+        }
+    } else {
+        std::vector<int32_t> cell(n);
+        std::vector<float> off(n), vx(n), vy(n), vz(n);
+        HIPC(c, hipMemcpy(cell.data(), c->d.cell[b] + S.base, n * 4, hipMemcpyDeviceToHost));
+        HIPC(c, hipMemcpy(off.data(), c->d.off[b] + S.base, n * 4, hipMemcpyDeviceToHost));
+        HIPC(c, hipMemcpy(vx.data(), c->d.fvx[b] + S.base, n * 4, hipMemcpyDeviceToHost));
+        HIPC(c, hipMemcpy(vy.data(), c->d.fvy[b] + S.base, n * 4, hipMemcpyDeviceToHost));
+        HIPC(c, hipMemcpy(vz.data(), c->d.fvz[b] + S.base, n * 4, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < n; ++i) {
+            if (cell[i] == kDead) continue;
+            if (k >= cap) return fail(c, PIC_EINVAL, "output capacity too small");
+            out.x[k] = ((double)cell[i] + (double)off[i]) * S.dx;
+            out.vx[k] = vx[i];
+            out.vy[k] = vy[i];
+            out.vz[k] = vz[i];
+            out.id[k] = id[i];
+            ++k;
+        }
+    }
+    *count = k;
+    return PIC_OK;
+}
+
+int pic_set_particles(pic_ctx *c, int32_t ens, int32_t species, pic_particles in, int64_t count,
+                      uint32_t next_id, void *stream)
+{
+    if (!c || ens < 0 || ens >= c->P.nens || species < 0 || species >= c->P.nspecies || count < 0)
+        return fail(c, PIC_EINVAL, "bad ensemble/species/count");
+    const int sg = c->P.ens[ens].seg[species];
+    const SegC &S = c->P.seg[sg];
+    if (count > S.cap) return fail(c, PIC_EINVAL, "count above capacity");
+    const double L = c->P.ens[ens].L;
+    const int64_t idcap = c->P.ens[ens].idcap;
+    if ((int64_t)next_id > idcap) return fail(c, PIC_EINVAL, "next_id above the id capacity");
+    for (int64_t i = 0; i < count; ++i) {
+        if (!(in.x[i] >= 0.0 && in.x[i] < L)) return fail(c, PIC_EINVAL, "x outside [0, L)");
+        if ((int64_t)in.id[i] >= idcap) return fail(c, PIC_EINVAL, "id above the id capacity");
+        if (!std::isfinite(in.vx[i]) || !std::isfinite(in.vy[i]) || !std::isfinite(in.vz[i]))
+            return fail(c, PIC_EINVAL, "non-finite velocity");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    int32_t b = 0;
+    HIPC(c, hipMemcpyAsync(&b, c->d.cur, 4, hipMemcpyDeviceToHost, s));
+    HIPC(c, hipStreamSynchronize(s));
+    HIPC(c, hipMemcpy(c->d.id[b] + S.base, in.id, count * 4, hipMemcpyHostToDevice));
+    if (c->P.f64) {
+        HIPC(c, hipMemcpy(c->d.x[b] + S.base, in.x, count * 8, hipMemcpyHostToDevice));
+        HIPC(c, hipMemcpy(c->d.dvx[b] + S.base, in.vx, count * 8, hipMemcpyHostToDevice));
+        HIPC(c, hipMemcpy(c->d.dvy[b] + S.base, in.vy, count * 8, hipMemcpyHostToDevice));
+        HIPC(c, hipMemcpy(c->d.dvz[b] + S.base, in.vz, count * 8, hipMemcpyHostToDevice));
+    } else {
+        std::vector<int32_t> cell(count);
+        std::vector<float> off(count), vx(count), vy(count), vz(count);
+        for (int64_t i = 0; i < count; ++i) {
+            const double g = in.x[i] / S.dx;
+            const double jf = std::floor(g);
+            int cl = (int)jf;
+            float o = (float)(g - jf);
+            if (o >= 1.0f) {
+                o = 0.0f;
+                cl += 1;
+            }
+            if (cl >= S.ncells) return fail(c, PIC_EINVAL, "x rounds to L");
+            cell[i] = cl;
+            off[i] = o;
+            vx[i] = (float)in.vx[i];
+            vy[i] = (float)in.vy[i];
+            vz[i] = (float)in.vz[i];
+        }
+        HIPC(c, hipMemcpy(c->d.cell[b] + S.base, cell.data(), count * 4, hipMemcpyHostToDevice));
+        HIPC(c, hipMemcpy(c->d.off[b] + S.base, off.data(), count * 4, hipMemcpyHostToDevice));
+        HIPC(c, hipMemcpy(c->d.fvx[b] + S.base, vx.data(), count * 4, hipMemcpyHostToDevice));
+        HIPC(c, hipMemcpy(c->d.fvy[b] + S.base, vy.data(), count * 4, hipMemcpyHostToDevice));
+        HIPC(c, hipMemcpy(c->d.fvz[b] + S.base, vz.data(), count * 4, hipMemcpyHostToDevice));
+    }
+    HIPC(c, hipMemcpy(c->d.n_slots + sg, &count, 8, hipMemcpyHostToDevice));
+    HIPC(c, hipMemcpy(c->d.next_id + sg, &next_id, 4, hipMemcpyHostToDevice));
+    // the speed maxima of the current half are recomputed for every segment
+    int32_t vc = 0;
+    HIPC(c, hipMemcpy(&vc, c->d.vcur, 4, hipMemcpyDeviceToHost));
+    HIPC(c, hipMemset(c->d.vmax2 + (size_t)vc * kStripes * c->P.nseg, 0, (size_t)kStripes * c->P.nseg * 8));
+    HIPC(c, launch_vmax(c->d, c->P.f64, s));
+    HIPC(c, hipStreamSynchronize(s));
+    return PIC_OK;
+}
+
+int pic_get_grid(pic_ctx *c, int32_t ens, double *Q0, double *Q1, double *rho, double *phi,
+                 double *E, void *stream)
+{
+    if (!c || ens < 0 || ens >= c->P.nens) return PIC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    HIPC(c, hipStreamSynchronize(s));
+    const EnsC &En = c->P.ens[ens];
+    const int64_t nn = En.nnodes;
+    double *Qs[2] = {Q0, Q1};
+    for (int sp = 0; sp < 2; ++sp) {
+        if (!Qs[sp]) continue;
+        if (sp >= c->P.nspecies) {
+            std::fill(Qs[sp], Qs[sp] + nn, 0.0);
+            continue;
+        }
+        if (c->P.f64) {
+            HIPC(c, hipMemcpy(Qs[sp], c->d.Qd + sp * c->P.nodes_tot + En.gbase, nn * 8, hipMemcpyDeviceToHost));
+        } else {
+            std::vector<long long> q(nn);
+            HIPC(c, hipMemcpy(q.data(), c->d.Qi + sp * c->P.nodes_tot + En.gbase, nn * 8, hipMemcpyDeviceToHost));
+            for (int64_t j = 0; j < nn; ++j) Qs[sp][j] = (double)q[j] / kFix;
+        }
+    }
+    if (rho) HIPC(c, hipMemcpy(rho, c->d.rho + En.gbase, nn * 8, hipMemcpyDeviceToHost));
+    if (phi) HIPC(c, hipMemcpy(phi, c->d.phi + En.gbase, nn * 8, hipMemcpyDeviceToHost));
+    if (E) HIPC(c, hipMemcpy(E, c->d.E + En.gbase, nn * 8, hipMemcpyDeviceToHost));
+    return PIC_OK;
+}
+
+int pic_set_fields(pic_ctx *c, int32_t ens, const double *E, void *stream)
+{
+    if (!c || !E || ens < 0 || ens >= c->P.nens) return PIC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    HIPC(c, hipStreamSynchronize(s));
+    const EnsC &En = c->P.ens[ens];
+    HIPC(c, hipMemcpy(c->d.E + En.gbase, E, En.nnodes * 8, hipMemcpyHostToDevice));
+    HIPC(c, launch_field_stats(c->d, c->P.f64, c->P.chunks_tot, s));
+    HIPC(c, hipStreamSynchronize(s));
+    return PIC_OK;
+}
+
+int pic_timing(pic_ctx *c, int32_t enable)
+{
+    if (!c) return PIC_EINVAL;
+    c->timing = enable != 0;
+    c->ev_used = 0;
+    if (c->timing && c->ev.empty()) {
+        c->ev.resize(2 * 65536);
+        for (auto &e : c->ev) HIPC(c, hipEventCreate(&e));
+    }
+    return PIC_OK;
+}
+
+int pic_timing_read(pic_ctx *c, double *ms_total, int64_t *launches, void *stream)
+{
+    if (!c || !ms_total || !launches) return PIC_EINVAL;
+    HIPC(c, hipStreamSynchronize((hipStream_t)stream));
+    double tot = 0.0;
+    for (int64_t i = 0; i + 1 < c->ev_used; i += 2) {
+        float ms = 0.f;
+        HIPC(c, hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
+        tot += ms;
+    }
+    *ms_total = tot;
+    *launches = c->ev_used / 2;
+    return PIC_OK;
+}
+
+void pic_free(pic_ctx *c)
+{
+    if (!c) return;
+    for (auto &e : c->ev) (void)hipEventDestroy(e);
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    delete c;
+}
+
+const char *pic_last_error(const pic_ctx *c) { return c ? c->msg.c_str() : "null context"; }
+
+}  // extern "C"

@@ -1,0 +1,208 @@
+// pic_device.h -- device-side data layout and helpers of the gfx950 PIC MC library.
+//
+// Layout in HBM (all carved from the caller's workspace):
+//   particles   SoA per precision, two buffers (the sort scatters from one into the other);
+//               segment = (ensemble, species) owns slots [base, base + cap) in every array.
+//               FP32 form: cell:i32 | off:f32 | vx,vy,vz:f32 | id:u32  (24 B per particle)
+//               FP64 form: x:f64 | vx,vy,vz:f64 | id:u32                  (36 B per particle)
+//   grid        per ensemble, nodes [gbase, gbase + nnodes): Q_s (int64 fixed point or f64),
+//               rho, phi, E (f64) and per cell (E_j, E_{j+1} - E_j) as float2 for the gather.
+//   tallies     striped counters [stripe][segment][k] so that at most grid/STRIPES blocks
+//               ever hit one address with an atomic.
+//   births      ionisation births of one step, striped, plus a per-ensemble bitmap over
+//               electron ids and per-1024-id counts used to rank births by parent id.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pic {
+
+constexpr int kStripes = 32;          // striped atomic counters
+constexpr int kWave = 64;             // CDNA wavefront
+constexpr int32_t kDead = INT32_MIN;  // FP32 form: cell of an absorbed slot
+constexpr int kChunk = 2048;          // nodes per block in the field solve
+constexpr int kSolveThreads = 256;
+constexpr int kIdsPerGroup = 1024;    // ids per birth-rank count (32 bitmap words)
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 16;        // elements per thread in the generic scan
+constexpr double kFix = 16777216.0;   // 2^24 fixed-point scale of the deposit
+constexpr double kNuSafety = 1.0 + 1.0 / 65536.0;
+
+// Counter slots per (stripe, segment).
+enum Cnt : int {
+    C_PUSH = 0, C_WALL_L, C_WALL_R, C_EL, C_IZ, C_CX, C_CREATED, C_NCNT
+};
+enum Sum : int { S_KE_L = 0, S_KE_R, S_NSUM };
+// Per-chunk solve aggregates.
+enum Agg : int { A_SUMRHO = 0, A_SUMPRE, A_TOTQ, A_N1, A_D, A_CNT, A_NAGG };
+enum Part : int { P_EMAX = 0, P_FE, P_PHISUM, P_NONFIN, P_NPART };
+// Error flags (bit mask).
+enum Err : int { E_CAP_PART = 1, E_CAP_BIRTH = 2, E_CAP_ID = 4, E_NONFINITE = 8 };
+
+// Constant per segment.
+struct SegC {
+    int64_t base, cap;        // slots
+    int64_t cbase;            // first entry in per-cell arrays (sort counts)
+    int64_t gbase;            // first node of the ensemble grid
+    int32_t ens, species, ncells, periodic;
+    double h, t[3], s[3];     // (q/m) dt/2 and the Boris rotation vectors
+    double dt, dx, dtdx;
+    double qw, halfmw, m;
+    double ngsT, qm_abs;      // n_g sigma_total, |q/m|
+    uint32_t seed;
+    int32_t other;            // ion segment of this ensemble (electron segments), else -1
+};
+
+// Constant per ensemble.
+struct EnsC {
+    int64_t ncells, nnodes, gbase;
+    int64_t chunk0, nchunks;  // solve chunks [chunk0, chunk0 + nchunks)
+    int64_t bm_base, l1_base, idcap;  // birth ranking: bitmap words, group counts, id limit
+    double dx, dt, eps0, E_ext, L;
+    double qw[2];
+    double ngs_el, ngs_iz, ngs_cx, eps_iz, vn, m_e, m_n;
+    int32_t seg[2];
+    uint32_t seed;
+    int32_t periodic, nspecies;
+};
+
+struct Birth {
+    uint32_t pid;
+    int32_t ens;
+    int32_t cell;
+    float off;
+    double x;
+    double ve[3];
+    double vi[3];
+};
+
+// Everything a kernel may touch; passed by value.
+struct Dev {
+    int32_t nseg, nens, nspecies, periodic, collisions;
+    const SegC *seg;
+    const EnsC *ens;
+    // particles (buffer b in {0,1}); FP32 and FP64 forms
+    int32_t *cell[2];
+    float *off[2], *fvx[2], *fvy[2], *fvz[2];
+    double *x[2], *dvx[2], *dvy[2], *dvz[2];
+    uint32_t *id[2];
+    int32_t *cur;             // [1] current particle buffer
+    int64_t *n_slots;         // [nseg] slots in use (alive + absorbed-not-yet-compacted)
+    uint32_t *next_id;        // [nseg]
+    int64_t *step;            // [1]
+    // grid
+    int64_t nodes_tot, cells_tot;
+    unsigned long long *Qi;   // [2][nodes_tot] (int64 fixed point, two's complement)
+    double *Qd;               // [2][nodes_tot]
+    double *rho, *phi, *E;    // [nodes_tot]
+    float2 *Ecell;            // [nodes_tot]
+    double *agg;              // [nchunks_tot][A_NAGG]
+    double *part;             // [nchunks_tot][P_NPART]
+    double *emax, *fe;        // [nens]
+    double *numax, *pnull;    // [nseg]
+    // tallies
+    unsigned long long *vmax2;  // [2][kStripes][nseg] max |v|^2 as double bits
+    int32_t *vcur;            // [1] which vmax2 half holds the current maxima
+    unsigned long long *cnt;  // [kStripes][nseg][C_NCNT]
+    double *sums;             // [kStripes][nseg][S_NSUM]
+    // births
+    Birth *births;            // [kStripes][birth_stripe_cap]
+    uint32_t *nbirth;         // [kStripes]
+    int64_t birth_stripe_cap;
+    uint32_t *bitmap;         // per-ensemble electron-id bitmaps
+    uint32_t *l1cnt, *l1pre;  // per-ensemble counts per 1024 ids and their scan
+    int64_t l1_tot;
+    // sort
+    uint32_t *cellcnt, *cursor;  // [cells_tot] over all segments (SegC::cbase)
+    int64_t *segstart;        // [nseg]
+    // scan scratch, tickets, errors
+    uint32_t *scanpart;       // [<= 1 << 16]
+    uint32_t *ticket;         // [8]
+    int32_t *err;             // [1]
+};
+
+// ---------------------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds; each multiplies counter words 0 and 2
+// by the published constants, xors the high halves with the other counter words and the
+// round key, and bumps the key by the published Weyl increments between rounds.
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// Uniform in (0,1): an odd multiple of 2^-24, exact in both float and double.
+__device__ __forceinline__ double u01d(uint32_t r) { return ((double)(r >> 9) + 0.5) * 0x1p-23; }
+__device__ __forceinline__ float u01f(uint32_t r) { return ((float)(r >> 9) + 0.5f) * 0x1p-23f; }
+
+// Key and counter layout of the random streams: key = (seed, species),
+// counter = (particle id, step tag, block, 0).  Tag 0xFFFFFFFF is the particle load.
+constexpr uint32_t kInitTag = 0xFFFFFFFFu;
+__device__ __forceinline__ uint4 draw(uint32_t seed, int species, uint32_t id, uint32_t tag,
+                                      uint32_t blk)
+{
+    return philox(id, tag, blk, 0u, seed, (uint32_t)species);
+}
+
+// ---------------------------------------------------------------------------------------
+// Wave-level helpers (64 lanes).
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    return v;
+}
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    return v;
+}
+__device__ __forceinline__ double wave_sum_f64(double v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    return v;
+}
+__device__ __forceinline__ double wave_max_f64(double v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m));
+    return v;
+}
+__device__ __forceinline__ int wave_min_i32(int v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = min(v, __shfl_xor(v, m));
+    return v;
+}
+
+// Double bits of a non-negative value order like unsigned integers.
+__device__ __forceinline__ unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
+
+// |v|^2 in FP64 from the stored components, summed left to right with no fused
+// multiply-add, so both precisions and the reference take identical collision decisions.
+__device__ __forceinline__ double speed2_rn(double a, double b, double c)
+{
+    return __dadd_rn(__dadd_rn(__dmul_rn(a, a), __dmul_rn(b, b)), __dmul_rn(c, c));
+}
+
+__device__ __forceinline__ int stripe_of_block() { return (int)(blockIdx.x & (kStripes - 1)); }
+
+}  // namespace pic

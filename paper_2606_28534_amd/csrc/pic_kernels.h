@@ -1,0 +1,34 @@
+// pic_kernels.h -- host-side launchers of the gfx950 kernels (internal to the library).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "pic_device.h"
+
+namespace pic {
+
+// Launch shape of the particle kernels.
+struct Launch {
+    int block;   // threads per block (multiple of 64, <= 256)
+    int ppt;     // particles per thread per tile (1, 2, 4, 8)
+    int grid;    // persistent blocks (multiple of 8 for the XCD-aware mapping)
+    int window;  // LDS deposit / sort window in cells
+};
+
+enum StageBits : int { SB_PUSH = 1, SB_COLLIDE = 2, SB_DEPOSIT = 4, SB_HIST = 8 };
+
+hipError_t launch_particles(const Dev &d, const Launch &L, hipStream_t s, bool f64, int stages, int hist);
+hipError_t launch_init(const Dev &d, bool f64, int sg, int64_t n, int64_t ppc, int init_mode,
+                       double vth, double amp, int mode, hipStream_t s);
+hipError_t launch_vmax(const Dev &d, bool f64, hipStream_t s);
+hipError_t launch_zero_q(const Dev &d, bool f64, hipStream_t s);
+hipError_t launch_solve(const Dev &d, bool f64, int64_t nchunks, bool zero_q, hipStream_t s);
+hipError_t launch_field_stats(const Dev &d, bool f64, int64_t nchunks, hipStream_t s);
+hipError_t launch_params(const Dev &d, hipStream_t s);
+hipError_t launch_scan(uint32_t *in, uint32_t *out, int64_t n, uint32_t *part, bool zero_in, hipStream_t s);
+int64_t scan_blocks(int64_t n);
+hipError_t launch_births(const Dev &d, bool f64, bool advance, hipStream_t s);
+hipError_t launch_advance(const Dev &d, hipStream_t s);
+hipError_t launch_sort(const Dev &d, bool f64, const Launch &L, hipStream_t s);
+hipError_t launch_diag(const Dev &d, bool f64, int sg, double *out, int grid, hipStream_t s);
+
+}  // namespace pic

@@ -1,0 +1,1805 @@
+// pic_kernels.hip -- gfx950 kernels of the electrostatic 1D3V PIC Monte Carlo step.
+//
+// One particle-pass template covers every particle stage: gather + Boris push + walls,
+// null-collision MC, cloud-in-cell deposit and the sort histogram are compile-time stage
+// bits, so the separate-stage verbs and the fused step run the same per-particle code.
+// The pass is HBM-bound (about 44 B of particle traffic per particle and step in the FP32
+// cell+offset form): it streams each segment's slots once, coalesced, with persistent
+// blocks that own contiguous, XCD-local runs of tiles; the deposit goes through a sliding
+// LDS window after a wavefront segmented reduction, so the HBM atomics are per node and
+// per window, not per particle.
+#include <type_traits>
+
+#include "pic_device.h"
+#include "pic_kernels.h"
+
+namespace pic {
+
+// =======================================================================================
+// Tile scheduling: live tiles are enumerated over all segments; block b owns a contiguous
+// run of them.  Blocks are dispatched round-robin over the 8 XCDs, so block b is mapped
+// to run (b % 8) * (G / 8) + b / 8: each XCD gets one contiguous eighth of the particles
+// (and of the cells, once sorted), which keeps its L2 working set to its own part of the
+// grid.
+// =======================================================================================
+constexpr int kMaxSeg = 512;
+
+__device__ __forceinline__ void sched_prefix(const Dev &d, int64_t tile, int64_t *s_tpre)
+{
+    // s_tpre[i] = sum over segments < i of ceil(n_slots / tile); nseg <= kMaxSeg.
+    __shared__ int64_t s_tmp[kMaxSeg];
+    for (int i = threadIdx.x; i < d.nseg; i += blockDim.x) {
+        int64_t n = d.n_slots[i];
+        s_tmp[i] = (n + tile - 1) / tile;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t acc = 0;
+        for (int i = 0; i < d.nseg; ++i) {
+            s_tpre[i] = acc;
+            acc += s_tmp[i];
+        }
+        s_tpre[d.nseg] = acc;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ int seg_of_tile(const int64_t *s_tpre, int nseg, int64_t t)
+{
+    int lo = 0, hi = nseg;  // s_tpre[lo] <= t < s_tpre[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (s_tpre[mid] <= t)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void block_run(int64_t T, int64_t &t0, int64_t &t1)
+{
+    const int64_t G = gridDim.x;
+    int64_t vb = blockIdx.x;
+    if ((G & 7) == 0) vb = (int64_t)(blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+    t0 = vb * T / G;
+    t1 = (vb + 1) * T / G;
+}
+
+// =======================================================================================
+// Block reductions of a few per-thread tallies, flushed to the striped counters.
+// =======================================================================================
+struct Tally {
+    uint32_t push, wl, wr, el, iz, cx;
+    double kel, ker, v2max;
+    __device__ void zero()
+    {
+        push = wl = wr = el = iz = cx = 0;
+        kel = ker = 0.0;
+        v2max = 0.0;
+    }
+};
+
+__device__ void flush_tally(const Dev &d, int seg, Tally &t, bool want_vmax)
+{
+    __shared__ double s_red[16][9];
+    const int lane = lane_id(), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    double v[9] = {(double)t.push, (double)t.wl, (double)t.wr, (double)t.el, (double)t.iz,
+                   (double)t.cx, t.kel, t.ker, t.v2max};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = wave_sum_f64(v[k]);
+    v[8] = wave_max_f64(v[8]);
+    if (lane == 0)
+        for (int k = 0; k < 9; ++k) s_red[w][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a[9];
+        for (int k = 0; k < 9; ++k) a[k] = s_red[0][k];
+        for (int i = 1; i < nw; ++i) {
+            for (int k = 0; k < 8; ++k) a[k] += s_red[i][k];
+            a[8] = fmax(a[8], s_red[i][8]);
+        }
+        const int st = stripe_of_block();
+        unsigned long long *c = d.cnt + ((int64_t)st * d.nseg + seg) * C_NCNT;
+        if (a[0] != 0.0) atomicAdd(c + C_PUSH, (unsigned long long)a[0]);
+        if (a[1] != 0.0) atomicAdd(c + C_WALL_L, (unsigned long long)a[1]);
+        if (a[2] != 0.0) atomicAdd(c + C_WALL_R, (unsigned long long)a[2]);
+        if (a[3] != 0.0) atomicAdd(c + C_EL, (unsigned long long)a[3]);
+        if (a[4] != 0.0) atomicAdd(c + C_IZ, (unsigned long long)a[4]);
+        if (a[5] != 0.0) atomicAdd(c + C_CX, (unsigned long long)a[5]);
+        double *sm = d.sums + ((int64_t)st * d.nseg + seg) * S_NSUM;
+        if (a[6] != 0.0) unsafeAtomicAdd(sm + S_KE_L, a[6]);
+        if (a[7] != 0.0) unsafeAtomicAdd(sm + S_KE_R, a[7]);
+        if (want_vmax && a[8] > 0.0) {
+            const int half = 1 - *d.vcur;
+            atomicMax(d.vmax2 + ((int64_t)half * kStripes + st) * d.nseg + seg, dbits(a[8]));
+        }
+    }
+    __syncthreads();
+    t.zero();
+}
+
+// =======================================================================================
+// Particle state in registers.
+// =======================================================================================
+template <bool F64>
+struct PS;
+template <>
+struct PS<false> {
+    int cell;
+    float off, vx, vy, vz;
+    uint32_t id;
+};
+template <>
+struct PS<true> {
+    double x, vx, vy, vz;
+    uint32_t id;
+};
+
+template <bool F64>
+__device__ __forceinline__ void p_load(const Dev &d, int b, int64_t i, PS<F64> &p, bool need_v,
+                                       bool need_id)
+{
+    if constexpr (!F64) {
+        p.cell = d.cell[b][i];
+        if (p.cell == kDead) return;
+        p.off = d.off[b][i];
+        if (need_v) {
+            p.vx = d.fvx[b][i];
+            p.vy = d.fvy[b][i];
+            p.vz = d.fvz[b][i];
+        }
+    } else {
+        p.x = d.x[b][i];
+        if (!(p.x >= 0.0)) return;
+        if (need_v) {
+            p.vx = d.dvx[b][i];
+            p.vy = d.dvy[b][i];
+            p.vz = d.dvz[b][i];
+        }
+    }
+    if (need_id) p.id = d.id[b][i];
+}
+
+template <bool F64>
+__device__ __forceinline__ bool p_alive(const PS<F64> &p)
+{
+    if constexpr (!F64)
+        return p.cell != kDead;
+    else
+        return p.x >= 0.0;
+}
+
+template <bool F64>
+__device__ __forceinline__ void p_kill(PS<F64> &p)
+{
+    if constexpr (!F64)
+        p.cell = kDead;
+    else
+        p.x = -1.0;
+}
+
+// Cell index and fraction of an absolute position in [0, L): x / dx may round up to N
+// for x just below L, which is folded back into the last cell.
+__device__ __forceinline__ int64_t cell_of_x(const SegC &S, double x, double &f)
+{
+    const double g = x / S.dx;
+    double jf = floor(g);
+    if (jf > (double)(S.ncells - 1)) jf = (double)(S.ncells - 1);
+    if (!(jf >= 0.0)) jf = 0.0;
+    f = g - jf;
+    return (int64_t)jf;
+}
+
+// Cell index and in-cell fraction.
+template <bool F64>
+__device__ __forceinline__ int p_cell(const SegC &S, const PS<F64> &p, double &f)
+{
+    if constexpr (!F64) {
+        f = (double)p.off;
+        return p.cell;
+    } else {
+        return (int)cell_of_x(S, p.x, f);
+    }
+}
+
+// Boris rotation in the given precision: half kick, v' = v- + v- x t, v+ = v- + v' x s,
+// half kick.
+template <typename T>
+__device__ __forceinline__ void boris(T h, const T t[3], const T s[3], T Ep, T &vx, T &vy, T &vz)
+{
+    T ax = vx + h * Ep, ay = vy, az = vz;
+    const T px = ax + (ay * t[2] - az * t[1]);
+    const T py = ay + (az * t[0] - ax * t[2]);
+    const T pz = az + (ax * t[1] - ay * t[0]);
+    ax += py * s[2] - pz * s[1];
+    ay += pz * s[0] - px * s[2];
+    az += px * s[1] - py * s[0];
+    vx = ax + h * Ep;
+    vy = ay;
+    vz = az;
+}
+
+// Gather (linear weighting of node E), Boris push, position update, walls.
+// Returns 0 alive, 1 absorbed at the left wall, 2 at the right wall.
+template <bool F64>
+__device__ __forceinline__ int p_push(const Dev &d, const SegC &S, const EnsC &e, PS<F64> &p)
+{
+    if constexpr (!F64) {
+        const float2 ec = d.Ecell[S.gbase + p.cell];
+        const float Ep = fmaf(p.off, ec.y, ec.x) + (float)e.E_ext;
+        const float h = (float)S.h;
+        const float t[3] = {(float)S.t[0], (float)S.t[1], (float)S.t[2]};
+        const float s[3] = {(float)S.s[0], (float)S.s[1], (float)S.s[2]};
+        boris<float>(h, t, s, Ep, p.vx, p.vy, p.vz);
+        float o = p.off + p.vx * (float)S.dtdx;
+        const float fl = floorf(o);
+        int c = p.cell + (int)fl;
+        o -= fl;
+        if (o >= 1.0f) {
+            o -= 1.0f;
+            c += 1;
+        }
+        p.off = o;
+        if (S.periodic) {
+            if (c < 0)
+                c += S.ncells;
+            else if (c >= S.ncells)
+                c -= S.ncells;
+            p.cell = c;
+            if (c < 0 || c >= S.ncells) {  // moved more than a period: not a valid state
+                atomicOr(d.err, (int)E_NONFINITE);
+                return 3;
+            }
+            return 0;
+        }
+        p.cell = c;
+        if (c < 0) return 1;
+        if (c >= S.ncells) return 2;
+        return 0;
+    } else {
+        double f;
+        const int64_t j = cell_of_x(S, p.x, f);
+        int64_t j1 = j + 1;
+        if (S.periodic && j1 == S.ncells) j1 = 0;
+        const double Ep = (1.0 - f) * d.E[S.gbase + j] + f * d.E[S.gbase + j1] + e.E_ext;
+        boris<double>(S.h, S.t, S.s, Ep, p.vx, p.vy, p.vz);
+        double x = p.x + S.dt * p.vx;
+        const double L = e.L;
+        if (S.periodic) {
+            if (x < 0.0)
+                x += L;
+            else if (x >= L)
+                x -= L;
+            if (x >= L) x -= L;  // x + L rounded up to L
+            p.x = x;
+            if (!(x >= 0.0 && x < L)) {
+                atomicOr(d.err, (int)E_NONFINITE);
+                return 3;
+            }
+            return 0;
+        }
+        p.x = x;
+        if (x >= 0.0 && x < L) return 0;
+        return (x < 0.0) ? 1 : 2;  // NaN counts as the right wall
+    }
+}
+
+__device__ __forceinline__ void sc(float a, float *s, float *c) { sincosf(a, s, c); }
+__device__ __forceinline__ void sc(double a, double *s, double *c) { sincos(a, s, c); }
+__device__ __forceinline__ float msqrt(float a) { return sqrtf(a); }
+__device__ __forceinline__ double msqrt(double a) { return sqrt(a); }
+__device__ __forceinline__ float mlog(float a) { return logf(a); }
+__device__ __forceinline__ double mlog(double a) { return log(a); }
+
+template <typename T>
+__device__ __forceinline__ void iso_dir(T ua, T ub, T d[3])
+{
+    const T c = (T)1 - (T)2 * ua;
+    const T s2 = (T)1 - c * c;
+    const T sn = s2 > (T)0 ? msqrt(s2) : (T)0;
+    T sp, cp;
+    sc((T)6.283185307179586476925286766559 * ub, &sp, &cp);
+    d[0] = c;
+    d[1] = sn * cp;
+    d[2] = sn * sp;
+}
+
+template <typename T>
+__device__ __forceinline__ void three_normals(uint4 w, T z[3])
+{
+    T u1 = (T)u01d(w.x), u2 = (T)u01d(w.y), u3 = (T)u01d(w.z), u4 = (T)u01d(w.w);
+    const T r1 = msqrt((T)-2 * mlog(u1)), r2 = msqrt((T)-2 * mlog(u3));
+    T s1, c1, s2, c2;
+    sc((T)6.283185307179586476925286766559 * u2, &s1, &c1);
+    sc((T)6.283185307179586476925286766559 * u4, &s2, &c2);
+    z[0] = r1 * c1;
+    z[1] = r1 * s1;
+    z[2] = r2 * c2;
+}
+
+// Null-collision decision (FP64, no contraction: identical to the reference for identical
+// inputs) and scattering kinematics (in the particle precision).  Returns the channel
+// (-1 none, 0 elastic, 1 ionisation, 2 CX); on ionisation fills the new pair.
+template <bool F64>
+__device__ __forceinline__ int p_collide(const EnsC &e, const SegC &S, int s, double numax,
+                                         double pnull, uint32_t tag, PS<F64> &p, double ve[3],
+                                         double vi[3])
+{
+    using T = typename std::conditional<F64, double, float>::type;
+    const uint4 w = draw(S.seed, s, p.id, tag, 0u);
+    if (!(u01d(w.x) < pnull)) return -1;
+    const double v2 = speed2_rn((double)p.vx, (double)p.vy, (double)p.vz);
+    const double spd = __dsqrt_rn(v2);
+    const double thr = __dmul_rn(u01d(w.y), numax);
+    int chan = -1;
+    if (s == 0) {
+        const double nu_el = __dmul_rn(e.ngs_el, spd);
+        const double nu_iz =
+            (__dmul_rn(__dmul_rn(0.5, S.m), v2) >= e.eps_iz) ? __dmul_rn(e.ngs_iz, spd) : 0.0;
+        if (thr < nu_el)
+            chan = 0;
+        else if (thr < __dadd_rn(nu_el, nu_iz))
+            chan = 1;
+    } else {
+        if (thr < __dmul_rn(e.ngs_cx, spd)) chan = 2;
+    }
+    if (chan < 0) return -1;
+    if (chan == 0) {
+        T dd[3];
+        iso_dir<T>((T)u01d(w.z), (T)u01d(w.w), dd);
+        const T vs = (T)spd;
+        const T cth = ((T)p.vx * dd[0] + (T)p.vy * dd[1] + (T)p.vz * dd[2]) / vs;
+        const T f2 = (T)1 - (T)(2.0 * S.m / e.m_n) * ((T)1 - cth);
+        const T sp2 = msqrt((T)v2 * f2);
+        p.vx = sp2 * dd[0];
+        p.vy = sp2 * dd[1];
+        p.vz = sp2 * dd[2];
+    } else if (chan == 1) {
+        const uint4 w1 = draw(S.seed, s, p.id, tag, 1u);
+        const uint4 w2 = draw(S.seed, s, p.id, tag, 2u);
+        const T erem = (T)(0.5 * S.m * v2 - e.eps_iz);
+        const T u = (T)u01d(w1.x);
+        const T e1 = u * erem, e2 = ((T)1 - u) * erem;
+        T d1[3], d2[3], z[3];
+        iso_dir<T>((T)u01d(w.z), (T)u01d(w.w), d1);
+        iso_dir<T>((T)u01d(w1.y), (T)u01d(w1.z), d2);
+        const T s1 = msqrt((T)2 * e1 / (T)S.m), s2 = msqrt((T)2 * e2 / (T)S.m);
+        p.vx = s1 * d1[0];
+        p.vy = s1 * d1[1];
+        p.vz = s1 * d1[2];
+        three_normals<T>(w2, z);
+        const T vn = (T)e.vn;
+        for (int k = 0; k < 3; ++k) {
+            ve[k] = (double)(s2 * d2[k]);
+            vi[k] = (double)(vn * z[k]);
+        }
+    } else {
+        const uint4 w2 = draw(S.seed, s, p.id, tag, 2u);
+        T z[3];
+        three_normals<T>(w2, z);
+        const T vn = (T)e.vn;
+        p.vx = vn * z[0];
+        p.vy = vn * z[1];
+        p.vz = vn * z[2];
+    }
+    return chan;
+}
+
+// =======================================================================================
+// Deposit machinery (FP32 form): a wave-level segmented reduction by cell, then one LDS
+// atomic per distinct cell and wave, then one HBM atomic per window node at flush.
+// =======================================================================================
+__device__ __forceinline__ void wave_window_deposit(int key, uint32_t fq, bool depo, bool hist,
+                                                    unsigned long long *sQ, uint32_t *sH)
+{
+    const int lane = lane_id();
+    unsigned long long act = __ballot(key >= 0);
+    int it = 0;
+    while (act != 0ull && it < 8) {
+        const int leader = __ffsll((long long)act) - 1;
+        const int k = __shfl(key, leader);
+        const bool mine = (key == k) && ((act >> lane) & 1ull);
+        const unsigned long long m = __ballot(mine);
+        const uint32_t S = wave_sum_u32(mine ? fq : 0u);
+        if (lane == leader) {
+            const uint32_t c = (uint32_t)__popcll(m);
+            if (depo) {
+                atomicAdd(&sQ[k], (unsigned long long)c * 16777216ull - (unsigned long long)S);
+                atomicAdd(&sQ[k + 1], (unsigned long long)S);
+            }
+            if (hist) atomicAdd(&sH[k], c);
+        }
+        act &= ~m;
+        ++it;
+    }
+    if ((act >> lane) & 1ull) {
+        if (depo) {
+            atomicAdd(&sQ[key], 16777216ull - (unsigned long long)fq);
+            atomicAdd(&sQ[key + 1], (unsigned long long)fq);
+        }
+        if (hist) atomicAdd(&sH[key], 1u);
+    }
+}
+
+__device__ __forceinline__ uint32_t fixed_share(float off)
+{
+    return (uint32_t)__float2uint_rn(off * 16777216.0f);
+}
+
+// Direct HBM deposit of one particle (outside the window, or another segment).
+__device__ __forceinline__ void global_deposit32(const Dev &d, const SegC &S, int s, int cell,
+                                                 float off, bool hist)
+{
+    const uint32_t fq = fixed_share(off);
+    int j1 = cell + 1;
+    if (S.periodic && j1 == S.ncells) j1 = 0;
+    unsigned long long *Q = d.Qi + (int64_t)s * d.nodes_tot + S.gbase;
+    atomicAdd(Q + cell, 16777216ull - fq);
+    atomicAdd(Q + j1, (unsigned long long)fq);
+    if (hist) atomicAdd(d.cellcnt + S.cbase + cell, 1u);
+}
+
+__device__ __forceinline__ void global_deposit64(const Dev &d, const SegC &S, int s, double x,
+                                                 bool hist)
+{
+    double f;
+    const int j = (int)cell_of_x(S, x, f);
+    int j1 = j + 1;
+    if (S.periodic && j1 == S.ncells) j1 = 0;
+    double *Q = d.Qd + (int64_t)s * d.nodes_tot + S.gbase;
+    unsafeAtomicAdd(Q + j, 1.0 - f);
+    unsafeAtomicAdd(Q + j1, f);
+    if (hist) atomicAdd(d.cellcnt + S.cbase + j, 1u);
+}
+
+struct Window {
+    int seg;   // segment the window belongs to (-1 none)
+    int base;  // first cell
+};
+
+__device__ void window_flush(const Dev &d, const Window &w, int W, unsigned long long *sQ,
+                             uint32_t *sH, bool hist)
+{
+    __syncthreads();
+    if (w.seg >= 0) {
+        const SegC &S = d.seg[w.seg];
+        const int s = S.species;
+        const int nn = S.periodic ? S.ncells : S.ncells + 1;
+        unsigned long long *Q = d.Qi + (int64_t)s * d.nodes_tot + S.gbase;
+        for (int i = threadIdx.x; i <= W; i += blockDim.x) {
+            const unsigned long long v = sQ[i];
+            if (v) {
+                int node = w.base + i;
+                if (S.periodic && node >= S.ncells) node -= S.ncells;
+                if (node < nn) atomicAdd(Q + node, v);
+                sQ[i] = 0ull;
+            }
+            if (hist && i < W) {
+                const uint32_t c = sH[i];
+                if (c) {
+                    const int cell = w.base + i;
+                    if (cell < S.ncells) atomicAdd(d.cellcnt + S.cbase + cell, c);
+                    sH[i] = 0u;
+                }
+            }
+        }
+    } else {
+        for (int i = threadIdx.x; i <= W; i += blockDim.x) {
+            sQ[i] = 0ull;
+            if (i < W) sH[i] = 0u;
+        }
+    }
+    __syncthreads();
+}
+
+// =======================================================================================
+// The particle pass.
+// =======================================================================================
+enum Stage : int { ST_PUSH = 1, ST_COLLIDE = 2, ST_DEPOSIT = 4, ST_HIST = 8 };
+
+template <bool F64, int STAGES, int PPT>
+__global__ void __launch_bounds__(256) k_particles(Dev d, int W, int hist_rt)
+{
+    constexpr bool PUSH = STAGES & ST_PUSH;
+    constexpr bool COLL = STAGES & ST_COLLIDE;
+    constexpr bool DEPO = STAGES & ST_DEPOSIT;
+    constexpr bool HISTC = STAGES & ST_HIST;  // histogram-only pass
+    const bool hist = HISTC || (hist_rt != 0);
+    constexpr bool NEED_V = PUSH || COLL;
+    constexpr bool NEED_ID = COLL;
+    constexpr bool WINDOW = !F64 && (DEPO || HISTC);
+
+    extern __shared__ unsigned long long s_dyn[];
+    unsigned long long *sQ = s_dyn;                  // [W + 1]
+    uint32_t *sH = (uint32_t *)(s_dyn + (W + 1));    // [W]
+    __shared__ int64_t s_tpre[kMaxSeg + 1];
+    __shared__ int s_c0;
+
+    const int BLOCK = blockDim.x;
+    const int64_t TILE = (int64_t)BLOCK * PPT;
+    sched_prefix(d, TILE, s_tpre);
+    const int64_t T = s_tpre[d.nseg];
+    int64_t t0, t1;
+    block_run(T, t0, t1);
+    const int b = *d.cur;
+    const int64_t step = *d.step;
+    const uint32_t tag = (uint32_t)step;
+    const int st = stripe_of_block();
+
+    Window win{-1, 0};
+    if constexpr (WINDOW) {
+        for (int i = threadIdx.x; i <= W; i += BLOCK) {
+            sQ[i] = 0ull;
+            if (i < W) sH[i] = 0u;
+        }
+    }
+    Tally tal;
+    tal.zero();
+    int tseg = -1;
+    __syncthreads();
+
+    for (int64_t t = t0; t < t1; ++t) {
+        const int sg = seg_of_tile(s_tpre, d.nseg, t);
+        const SegC &S = d.seg[sg];
+        const EnsC &e = d.ens[S.ens];
+        const int s = S.species;
+        if (sg != tseg) {
+            if (tseg >= 0 && (PUSH || COLL)) flush_tally(d, tseg, tal, COLL);
+            tseg = sg;
+        }
+        const int64_t lt = t - s_tpre[sg];
+        const int64_t first = S.base + lt * TILE;
+        const int64_t last = S.base + min((lt + 1) * TILE, d.n_slots[sg]);
+
+        PS<F64> p[PPT];
+        bool live[PPT];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int64_t i = first + (int64_t)k * BLOCK + threadIdx.x;
+            live[k] = false;
+            if (i < last) {
+                p_load<F64>(d, b, i, p[k], NEED_V, NEED_ID);
+                live[k] = p_alive<F64>(p[k]);
+            }
+        }
+        // The sliding deposit window: decided from the tile's first slot before the push.
+        if constexpr (WINDOW) {
+            if (threadIdx.x == 0) s_c0 = live[0] ? p[0].cell : kDead;
+            __syncthreads();
+            const int c0 = s_c0;
+            const bool reseg = (win.seg != sg);
+            const bool slide = (c0 != kDead) && (c0 < win.base || c0 > win.base + W / 2);
+            if (reseg || slide) {
+                window_flush(d, win, W, sQ, sH, hist);
+                win.seg = sg;
+                win.base = (c0 == kDead) ? 0 : max(c0 - W / 8, 0);
+            }
+        }
+        const double numax = COLL ? d.numax[sg] : 0.0;
+        const double pnull = COLL ? d.pnull[sg] : 0.0;
+
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int64_t i = first + (int64_t)k * BLOCK + threadIdx.x;
+            int key = -1;
+            uint32_t fq = 0;
+            if (live[k]) {
+                if (PUSH) {
+                    ++tal.push;
+                    const int wall = p_push<F64>(d, S, e, p[k]);
+                    if (wall == 3) {
+                        p_kill<F64>(p[k]);
+                        live[k] = false;
+                        if constexpr (!F64)
+                            d.cell[b][i] = kDead;
+                        else
+                            d.x[b][i] = -1.0;
+                    } else if (wall) {
+                        const double v2 = speed2_rn((double)p[k].vx, (double)p[k].vy, (double)p[k].vz);
+                        if (wall == 1) {
+                            ++tal.wl;
+                            tal.kel += S.halfmw * v2;
+                        } else {
+                            ++tal.wr;
+                            tal.ker += S.halfmw * v2;
+                        }
+                        p_kill<F64>(p[k]);
+                        live[k] = false;
+                        if constexpr (!F64)
+                            d.cell[b][i] = kDead;
+                        else
+                            d.x[b][i] = -1.0;
+                    }
+                }
+                if (COLL && live[k]) {
+                    double ve[3], vi[3];
+                    const int ch = p_collide<F64>(e, S, s, numax, pnull, tag, p[k], ve, vi);
+                    if (ch == 0)
+                        ++tal.el;
+                    else if (ch == 2)
+                        ++tal.cx;
+                    else if (ch == 1) {
+                        ++tal.iz;
+                        // birth record: slot in this block's stripe
+                        const uint32_t slot = atomicAdd(d.nbirth + st, 1u);
+                        if ((int64_t)slot < d.birth_stripe_cap) {
+                            Birth &B = d.births[(int64_t)st * d.birth_stripe_cap + slot];
+                            B.pid = p[k].id;
+                            B.ens = S.ens;
+                            if constexpr (!F64) {
+                                B.cell = p[k].cell;
+                                B.off = p[k].off;
+                                B.x = ((double)p[k].cell + (double)p[k].off) * S.dx;
+                            } else {
+                                B.cell = 0;
+                                B.off = 0.f;
+                                B.x = p[k].x;
+                            }
+                            for (int q = 0; q < 3; ++q) {
+                                B.ve[q] = ve[q];
+                                B.vi[q] = vi[q];
+                            }
+                            atomicOr(d.bitmap + e.bm_base + (p[k].id >> 5), 1u << (p[k].id & 31));
+                            atomicAdd(d.l1cnt + e.l1_base + (p[k].id >> 10), 1u);
+                        } else {
+                            atomicOr(d.err, (int)E_CAP_BIRTH);
+                        }
+                        const double ve2 = speed2_rn(ve[0], ve[1], ve[2]);
+                        tal.v2max = fmax(tal.v2max, ve2);
+                        if (S.other >= 0) {
+                            const double vi2 = speed2_rn(vi[0], vi[1], vi[2]);
+                            const int half = 1 - *d.vcur;
+                            atomicMax(d.vmax2 + ((int64_t)half * kStripes + st) * d.nseg + S.other,
+                                      dbits(vi2));
+                        }
+                        if (DEPO) {
+                            // the new pair sits at the parent's position
+                            if constexpr (!F64) {
+                                global_deposit32(d, S, s, p[k].cell, p[k].off, hist);
+                                if (S.other >= 0)
+                                    global_deposit32(d, d.seg[S.other], 1, p[k].cell, p[k].off, hist);
+                            } else {
+                                global_deposit64(d, S, s, p[k].x, hist);
+                                if (S.other >= 0) global_deposit64(d, d.seg[S.other], 1, p[k].x, hist);
+                            }
+                        }
+                    }
+                    tal.v2max = fmax(tal.v2max, speed2_rn((double)p[k].vx, (double)p[k].vy, (double)p[k].vz));
+                }
+                if (live[k] && (PUSH || COLL)) {
+                    if constexpr (!F64) {
+                        if (PUSH) {
+                            d.cell[b][i] = p[k].cell;
+                            d.off[b][i] = p[k].off;
+                        }
+                        d.fvx[b][i] = p[k].vx;
+                        d.fvy[b][i] = p[k].vy;
+                        d.fvz[b][i] = p[k].vz;
+                    } else {
+                        if (PUSH) d.x[b][i] = p[k].x;
+                        d.dvx[b][i] = p[k].vx;
+                        d.dvy[b][i] = p[k].vy;
+                        d.dvz[b][i] = p[k].vz;
+                    }
+                }
+                if (live[k] && (DEPO || HISTC)) {
+                    if constexpr (!F64) {
+                        const int rel = p[k].cell - win.base;
+                        if (rel >= 0 && rel < W) {
+                            key = rel;
+                            fq = DEPO ? fixed_share(p[k].off) : 0u;
+                        } else {
+                            if (DEPO)
+                                global_deposit32(d, S, s, p[k].cell, p[k].off, hist);
+                            else
+                                atomicAdd(d.cellcnt + S.cbase + p[k].cell, 1u);
+                        }
+                    } else {
+                        if (DEPO)
+                            global_deposit64(d, S, s, p[k].x, hist);
+                        else {
+                            double f;
+                            const int j = p_cell<true>(S, p[k], f);
+                            atomicAdd(d.cellcnt + S.cbase + j, 1u);
+                        }
+                    }
+                }
+            }
+            if constexpr (WINDOW) wave_window_deposit(key, fq, DEPO, hist, sQ, sH);
+        }
+        if constexpr (WINDOW) __syncthreads();
+    }
+    if constexpr (WINDOW) window_flush(d, win, W, sQ, sH, hist);
+    if ((PUSH || COLL) && tseg >= 0) flush_tally(d, tseg, tal, COLL);
+}
+
+// =======================================================================================
+// Particle load.
+// =======================================================================================
+template <bool F64>
+__global__ void k_init(Dev d, int sg, int64_t n, int64_t ppc, int init_mode, double vth,
+                       double amp, int mode)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const SegC &S = d.seg[sg];
+    const EnsC &e = d.ens[S.ens];
+    const int s = S.species;
+    const int64_t i = S.base + p;
+    double x;
+    int cell = 0;
+    float off = 0.f;
+    if (init_mode == 0) {
+        cell = (int)(p / ppc);
+        const uint4 w = draw(S.seed, s, (uint32_t)p, kInitTag, 0u);
+        off = u01f(w.x);
+        x = ((double)cell + (double)off) * S.dx;
+    } else {
+        const double L = e.L;
+        const double k = 6.283185307179586476925286766559 * (double)mode / L;
+        const double x0 = ((double)p + 0.5) * L / (double)n;
+        x = x0 + (amp / k) * sin(k * x0);
+        if (x < 0.0) x += L;
+        if (x >= L) x -= L;
+        if (!(x >= 0.0 && x < L)) x = 0.0;
+        const double g = x / S.dx;
+        double jf = floor(g);
+        cell = (int)jf;
+        off = (float)(g - jf);
+        if (off >= 1.0f) {
+            off = 0.0f;
+            cell += 1;
+            if (cell >= S.ncells) cell = 0;
+        }
+    }
+    double z[3];
+    three_normals<double>(draw(S.seed, s, (uint32_t)p, kInitTag, 1u), z);
+    if constexpr (!F64) {
+        d.cell[0][i] = cell;
+        d.off[0][i] = off;
+        d.fvx[0][i] = (float)(vth * z[0]);
+        d.fvy[0][i] = (float)(vth * z[1]);
+        d.fvz[0][i] = (float)(vth * z[2]);
+    } else {
+        d.x[0][i] = x;
+        d.dvx[0][i] = vth * z[0];
+        d.dvy[0][i] = vth * z[1];
+        d.dvz[0][i] = vth * z[2];
+    }
+    d.id[0][i] = (uint32_t)p;
+}
+
+// Max |v|^2 of every segment into the current half of vmax2 (after a load or injection).
+template <bool F64>
+__global__ void k_vmax(Dev d)
+{
+    __shared__ double s_m[16];
+    const int sg = blockIdx.y;
+    const SegC &S = d.seg[sg];
+    const int b = *d.cur;
+    const int64_t n = d.n_slots[sg];
+    double m = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = S.base + p;
+        if constexpr (!F64) {
+            if (d.cell[b][i] == kDead) continue;
+            m = fmax(m, speed2_rn(d.fvx[b][i], d.fvy[b][i], d.fvz[b][i]));
+        } else {
+            if (!(d.x[b][i] >= 0.0)) continue;
+            m = fmax(m, speed2_rn(d.dvx[b][i], d.dvy[b][i], d.dvz[b][i]));
+        }
+    }
+    m = wave_max_f64(m);
+    if (lane_id() == 0) s_m[threadIdx.x / kWave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < (int)(blockDim.x / kWave); ++i) m = fmax(m, s_m[i]);
+        const int half = *d.vcur;
+        if (m > 0.0)
+            atomicMax(d.vmax2 + ((int64_t)half * kStripes + stripe_of_block()) * d.nseg + sg, dbits(m));
+    }
+}
+
+// =======================================================================================
+// Field solve.  With constant coefficients the three-point Poisson system on the interior
+// nodes (phi_0 = phi_N = 0) factors into two prefix sums:
+//   C_m = sum_{i=1..m} rho_i,  E_{m+1/2} = E_{1/2} + (dx/eps0) C_m,
+//   phi_j = -dx (j E_{1/2} + (dx/eps0) sum_{m<j} C_m),
+//   E_{1/2} = -(dx/eps0) sum_{m=0}^{N-1} C_m / N      (from phi_N = 0).
+// This is the exact solution of the same tridiagonal system the Thomas algorithm solves,
+// computed in two passes over the nodes: pass 1 reduces per-chunk aggregates, pass 2 has
+// each chunk scan the aggregates of its ensemble and then its own nodes.  Node E is the
+// centred difference, i.e. the mean of the two face fields, with the half-cell Gauss rule
+// at bounded walls.  Periodic runs add the uniform background that cancels the deposited
+// charge and shift phi to zero mean afterwards.
+// =======================================================================================
+template <bool F64>
+__device__ __forceinline__ double node_charge(const Dev &d, const EnsC &e, int64_t j)
+{
+    double q = 0.0;
+    for (int s = 0; s < e.nspecies; ++s) {
+        double Q;
+        if constexpr (!F64) {
+            const long long qi = (long long)d.Qi[(int64_t)s * d.nodes_tot + e.gbase + j];
+            Q = (double)qi * (1.0 / kFix);
+        } else {
+            Q = d.Qd[(int64_t)s * d.nodes_tot + e.gbase + j];
+        }
+        q += e.qw[s] * Q;
+    }
+    return q;
+}
+
+__device__ __forceinline__ double node_vol(const EnsC &e, int64_t j)
+{
+    if (!e.periodic && (j == 0 || j == e.ncells)) return 0.5 * e.dx;
+    return e.dx;
+}
+
+// Block-wide inclusive scan of one double per thread (256 threads).
+__device__ double block_incl_scan(double v, double *s_buf)
+{
+    const int lane = lane_id(), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const double n = __shfl_up(v, o);
+        if (lane >= o) v += n;
+    }
+    if (lane == kWave - 1) s_buf[w] = v;
+    __syncthreads();
+    double add = 0.0;
+    for (int i = 0; i < w; ++i) add += s_buf[i];
+    __syncthreads();
+    (void)nw;
+    return v + add;
+}
+
+__device__ double block_sum(double v, double *s_buf)
+{
+    v = wave_sum_f64(v);
+    const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    if (lane_id() == 0) s_buf[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    for (int i = 0; i < nw; ++i) r += s_buf[i];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ int chunk_ens(const Dev &d, int64_t k)
+{
+    int lo = 0, hi = d.nens;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (d.ens[mid].chunk0 <= k)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+constexpr int kNodesPerThread = kChunk / kSolveThreads;
+
+template <bool F64>
+__global__ void __launch_bounds__(kSolveThreads) k_solve1(Dev d)
+{
+    __shared__ double s_buf[8];
+    const int64_t k = blockIdx.x;
+    const int ei = chunk_ens(d, k);
+    const EnsC &e = d.ens[ei];
+    const int64_t N = e.ncells, nn = e.nnodes;
+    const int64_t a = (k - e.chunk0) * kChunk;
+    const int64_t j0 = a + (int64_t)threadIdx.x * kNodesPerThread;
+    double loc = 0.0, sumpre = 0.0, totq = 0.0, n1 = 0.0, dd = 0.0, cnt = 0.0;
+    // thread-local prefix of interior rho and its running sum
+    double rho_loc[kNodesPerThread];
+#pragma unroll
+    for (int q = 0; q < kNodesPerThread; ++q) {
+        const int64_t j = j0 + q;
+        double r = 0.0;
+        if (j < nn) {
+            const double V = node_vol(e, j);
+            r = node_charge<F64>(d, e, j) / V;
+            d.rho[e.gbase + j] = r;
+            totq += r * V;
+        }
+        rho_loc[q] = (j >= 1 && j <= N - 1) ? r : 0.0;
+        loc += rho_loc[q];
+    }
+    const double excl = block_incl_scan(loc, s_buf) - loc;
+    // integer counts in this thread's node range: interior nodes and the prefix weights
+    double run = excl, runc = 0.0;
+    int64_t c1_before = 0;  // interior nodes in [a, j0)
+    {
+        const int64_t lo = max(a, (int64_t)1), hi = min(j0, N);  // [lo, hi) interior, i < j0
+        c1_before = hi > lo ? hi - lo : 0;
+    }
+    int64_t c1 = c1_before;
+#pragma unroll
+    for (int q = 0; q < kNodesPerThread; ++q) {
+        const int64_t j = j0 + q;
+        run += rho_loc[q];
+        if (j >= 1 && j <= N - 1) {
+            ++c1;
+            n1 += 1.0;
+        }
+        if (j < N) {  // m in [0, N-1]
+            sumpre += run;
+            dd += (double)c1;
+            cnt += 1.0;
+        }
+        (void)runc;
+    }
+    const double A = block_sum(loc, s_buf);
+    const double B = block_sum(sumpre, s_buf);
+    const double TQ = block_sum(totq, s_buf);
+    const double N1 = block_sum(n1, s_buf);
+    const double D = block_sum(dd, s_buf);
+    const double CN = block_sum(cnt, s_buf);
+    if (threadIdx.x == 0) {
+        double *g = d.agg + k * A_NAGG;
+        g[A_SUMRHO] = A;
+        g[A_SUMPRE] = B;
+        g[A_TOTQ] = TQ;
+        g[A_N1] = N1;
+        g[A_D] = D;
+        g[A_CNT] = CN;
+    }
+}
+
+// Reading R11: per-segment null-collision bound from the current max speed and max field.
+__device__ void compute_params(const Dev &d)
+{
+    for (int sg = threadIdx.x; sg < d.nseg; sg += blockDim.x) {
+        const SegC &S = d.seg[sg];
+        const EnsC &e = d.ens[S.ens];
+        const int half = *d.vcur;
+        unsigned long long m = 0ull;
+        for (int st = 0; st < kStripes; ++st)
+            m = max(m, d.vmax2[((int64_t)half * kStripes + st) * d.nseg + sg]);
+        const double vmax = __dsqrt_rn(__longlong_as_double((long long)m));
+        const double Vb = __dadd_rn(vmax, __dmul_rn(__dmul_rn(S.qm_abs, e.dt),
+                                                    __dadd_rn(d.emax[S.ens], fabs(e.E_ext))));
+        const double numax = __dmul_rn(__dmul_rn(S.ngsT, Vb), kNuSafety);
+        d.numax[sg] = numax;
+        d.pnull[sg] = 1.0 - exp(-__dmul_rn(numax, e.dt));
+    }
+}
+
+__global__ void k_params(Dev d) { compute_params(d); }
+
+template <bool F64>
+__global__ void __launch_bounds__(kSolveThreads) k_solve2(Dev d, int zero_q)
+{
+    __shared__ double s_buf[8];
+    __shared__ double s_C0, s_F0, s_Eh, s_bg, s_Ctot;
+    __shared__ bool s_last;
+    const int64_t k = blockIdx.x;
+    const int ei = chunk_ens(d, k);
+    const EnsC &e = d.ens[ei];
+    const int64_t N = e.ncells, nn = e.nnodes;
+    const int64_t a = (k - e.chunk0) * kChunk;
+    const double dx = e.dx, ce = e.dx / e.eps0;
+    // scan the ensemble's chunk aggregates (serially by one thread: at most a few hundred)
+    if (threadIdx.x == 0) {
+        double bg = 0.0;
+        if (e.periodic) {
+            double tq = 0.0;
+            for (int64_t c = 0; c < e.nchunks; ++c) tq += d.agg[(e.chunk0 + c) * A_NAGG + A_TOTQ];
+            bg = -tq / e.L;
+        }
+        double Cpre = 0.0, Fpre = 0.0, S = 0.0, C0 = 0.0, F0 = 0.0;
+        for (int64_t c = 0; c < e.nchunks; ++c) {
+            const double *g = d.agg + (e.chunk0 + c) * A_NAGG;
+            const double A = g[A_SUMRHO] + bg * g[A_N1];
+            const double B = g[A_SUMPRE] + bg * g[A_D];
+            if (c == k - e.chunk0) {
+                C0 = Cpre;
+                F0 = Fpre;
+            }
+            const double within = g[A_CNT] * Cpre + B;
+            S += within;
+            Fpre += within;
+            Cpre += A;
+        }
+        s_C0 = C0;
+        s_F0 = F0;
+        s_bg = bg;
+        s_Ctot = Cpre;
+        s_Eh = -ce * S / (double)N;
+    }
+    __syncthreads();
+    const double bg = s_bg, Eh = s_Eh;
+    const int64_t j0 = a + (int64_t)threadIdx.x * kNodesPerThread;
+    // local inclusive prefix of interior rho' (with background) -> C_j
+    double rl[kNodesPerThread + 1];
+    double loc = 0.0;
+#pragma unroll
+    for (int q = 0; q < kNodesPerThread; ++q) {
+        const int64_t j = j0 + q;
+        double r = 0.0;
+        if (j >= 1 && j <= N - 1 && j < nn) r = d.rho[e.gbase + j] + bg;
+        rl[q] = r;
+        loc += r;
+    }
+    const double cex = block_incl_scan(loc, s_buf) - loc;
+    double Cj[kNodesPerThread];
+    double c = s_C0 + cex;
+    double csum = 0.0;
+#pragma unroll
+    for (int q = 0; q < kNodesPerThread; ++q) {
+        c += rl[q];
+        Cj[q] = c;
+        csum += (j0 + q < N) ? c : 0.0;
+    }
+    // exclusive prefix of C over m < j (m in [0, N-1])
+    const double fex = block_incl_scan(csum, s_buf) - csum;
+    double F = s_F0 + fex;
+    double emax = 0.0, fe = 0.0, phisum = 0.0;
+    int nonfin = 0;
+    // C_{j-1} for the first node of the thread
+    double Cprev = (j0 == 0) ? 0.0 : (Cj[0] - rl[0]);
+#pragma unroll
+    for (int q = 0; q < kNodesPerThread; ++q) {
+        const int64_t j = j0 + q;
+        if (j >= nn) break;
+        double phi = -dx * ((double)j * Eh + ce * F);
+        if (!e.periodic && j == N) phi = 0.0;
+        if (j == 0) phi = 0.0;
+        d.phi[e.gbase + j] = phi;
+        phisum += phi;
+        // face fields around node j
+        const double Em = Eh + ce * Cprev;  // E_{j-1/2} (j >= 1)
+        const double Ep = Eh + ce * Cj[q];  // E_{j+1/2} (j <= N-1)
+        double Ej;
+        if (e.periodic) {
+            if (j == 0) {
+                const double Elast = Eh + ce * s_Ctot;  // E_{N-1/2}
+                Ej = 0.5 * (Elast + Ep);
+            } else {
+                Ej = 0.5 * (Em + Ep);
+            }
+        } else if (j == 0) {
+            Ej = Eh - d.rho[e.gbase] * node_vol(e, 0) / e.eps0;
+        } else if (j == N) {
+            Ej = Em + d.rho[e.gbase + N] * node_vol(e, N) / e.eps0;
+        } else {
+            Ej = 0.5 * (Em + Ep);
+        }
+        d.E[e.gbase + j] = Ej;
+        if (!isfinite(Ej)) nonfin = 1;
+        emax = fmax(emax, fabs(Ej));
+        fe += Ej * Ej * node_vol(e, j);
+        if (j < N) F += Cj[q];
+        Cprev = Cj[q];
+    }
+    // zero the deposit for the next pass when asked (fused step)
+    if (zero_q) {
+        for (int q = 0; q < kNodesPerThread; ++q) {
+            const int64_t j = j0 + q;
+            if (j >= nn) break;
+            for (int s = 0; s < e.nspecies; ++s) {
+                if constexpr (!F64)
+                    d.Qi[(int64_t)s * d.nodes_tot + e.gbase + j] = 0ull;
+                else
+                    d.Qd[(int64_t)s * d.nodes_tot + e.gbase + j] = 0.0;
+            }
+        }
+    }
+    // chunk partials
+    {
+        double em = wave_max_f64(emax);
+        __shared__ double s_em[8];
+        if (lane_id() == 0) s_em[threadIdx.x / kWave] = em;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int i = 1; i < (int)(blockDim.x / kWave); ++i) em = fmax(em, s_em[i]);
+            s_em[0] = em;
+        }
+        __syncthreads();
+        em = s_em[0];
+        const double fes = block_sum(fe, s_buf);
+        const double ps = block_sum(phisum, s_buf);
+        const double nf = block_sum((double)nonfin, s_buf);
+        if (threadIdx.x == 0) {
+            double *pp = d.part + k * P_NPART;
+            pp[P_EMAX] = em;
+            pp[P_FE] = fes;
+            pp[P_PHISUM] = ps;
+            pp[P_NONFIN] = nf;
+        }
+    }
+    // the last chunk to finish reduces the partials per ensemble and sets the
+    // null-collision parameters of every segment
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = (atomicAdd(d.ticket + 0, 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (s_last) {
+        __threadfence();
+        for (int en = threadIdx.x; en < d.nens; en += blockDim.x) {
+            const EnsC &E = d.ens[en];
+            double em = 0.0, f = 0.0, nf = 0.0;
+            for (int64_t c = 0; c < E.nchunks; ++c) {
+                const double *pp = d.part + (E.chunk0 + c) * P_NPART;
+                em = fmax(em, pp[P_EMAX]);
+                f += pp[P_FE];
+                nf += pp[P_NONFIN];
+            }
+            d.emax[en] = em;
+            d.fe[en] = 0.5 * E.eps0 * f;
+            if (nf > 0.0) atomicOr(d.err, (int)E_NONFINITE);
+        }
+        __syncthreads();
+        __threadfence();
+        compute_params(d);
+        if (threadIdx.x == 0) d.ticket[0] = 0u;
+    }
+}
+
+// Periodic only: subtract the mean of phi and build the gather table.
+__global__ void __launch_bounds__(kSolveThreads) k_phi_shift(Dev d)
+{
+    const int64_t k = blockIdx.x;
+    const int ei = chunk_ens(d, k);
+    const EnsC &e = d.ens[ei];
+    __shared__ double s_mean;
+    if (threadIdx.x == 0) {
+        double ps = 0.0;
+        for (int64_t c = 0; c < e.nchunks; ++c) ps += d.part[(e.chunk0 + c) * P_NPART + P_PHISUM];
+        s_mean = ps / (double)e.ncells;
+    }
+    __syncthreads();
+    const int64_t a = (k - e.chunk0) * kChunk;
+    for (int64_t j = a + threadIdx.x; j < min(a + kChunk, e.nnodes); j += blockDim.x)
+        d.phi[e.gbase + j] -= s_mean;
+}
+
+// Gather table: per cell (E_j, E_{j+1} - E_j) in float.
+__global__ void k_ecell(Dev d)
+{
+    const int64_t k = blockIdx.x;
+    const int ei = chunk_ens(d, k);
+    const EnsC &e = d.ens[ei];
+    const int64_t a = (k - e.chunk0) * kChunk;
+    for (int64_t j = a + threadIdx.x; j < min(a + kChunk, e.ncells); j += blockDim.x) {
+        const int64_t j1 = (e.periodic && j + 1 == e.ncells) ? 0 : j + 1;
+        const double E0 = d.E[e.gbase + j], E1 = d.E[e.gbase + j1];
+        d.Ecell[e.gbase + j] = make_float2((float)E0, (float)(E1 - E0));
+    }
+}
+
+// Max |E| and field energy of a field set from the host (test hook).
+__global__ void __launch_bounds__(kSolveThreads) k_field_stats(Dev d)
+{
+    __shared__ double s_buf[8];
+    for (int en = 0; en < d.nens; ++en) {
+        const EnsC &e = d.ens[en];
+        double em = 0.0, fe = 0.0;
+        for (int64_t j = threadIdx.x; j < e.nnodes; j += blockDim.x) {
+            const double E = d.E[e.gbase + j];
+            em = fmax(em, fabs(E));
+            fe += E * E * node_vol(e, j);
+        }
+        em = wave_max_f64(em);
+        __shared__ double s_em[8];
+        if (lane_id() == 0) s_em[threadIdx.x / kWave] = em;
+        __syncthreads();
+        const double f = block_sum(fe, s_buf);
+        if (threadIdx.x == 0) {
+            for (int i = 1; i < (int)(blockDim.x / kWave); ++i) em = fmax(em, s_em[i]);
+            d.emax[en] = em;
+            d.fe[en] = 0.5 * e.eps0 * f;
+        }
+        __syncthreads();
+    }
+}
+
+template <bool F64>
+__global__ void k_zero_q(Dev d)
+{
+    const int64_t n = 2 * d.nodes_tot;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if constexpr (!F64)
+            d.Qi[i] = 0ull;
+        else
+            d.Qd[i] = 0.0;
+    }
+}
+
+// =======================================================================================
+// Generic exclusive scan of u32 (three kernels: block sums, scan of sums, down-sweep).
+// =======================================================================================
+constexpr int kScanTile = kScanBlock * kScanItems;
+
+__device__ uint32_t block_excl_scan_u32(uint32_t v, uint32_t *s_buf, uint32_t &total)
+{
+    const int lane = lane_id(), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t n = __shfl_up(x, o);
+        if (lane >= o) x += n;
+    }
+    if (lane == kWave - 1) s_buf[w] = x;
+    __syncthreads();
+    uint32_t add = 0, tot = 0;
+    for (int i = 0; i < nw; ++i) {
+        if (i < w) add += s_buf[i];
+        tot += s_buf[i];
+    }
+    __syncthreads();
+    total = tot;
+    return x - v + add;
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_scan_sums(const uint32_t *in, int64_t n, uint32_t *part)
+{
+    __shared__ uint32_t s_buf[16];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    uint32_t s = 0;
+    for (int q = 0; q < kScanItems; ++q) {
+        const int64_t i = base + (int64_t)q * kScanBlock + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    uint32_t tot;
+    block_excl_scan_u32(s, s_buf, tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_part(uint32_t *part, int64_t nb)
+{
+    __shared__ uint32_t s_buf[16];
+    __shared__ uint32_t s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (int64_t c = 0; c < nb; c += blockDim.x) {
+        const int64_t i = c + threadIdx.x;
+        const uint32_t v = i < nb ? part[i] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan_u32(v, s_buf, tot);
+        if (i < nb) part[i] = ex + s_carry;
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry += tot;
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_scan_down(uint32_t *in, uint32_t *out, int64_t n,
+                                                          const uint32_t *part, int zero_in)
+{
+    __shared__ uint32_t s_buf[16];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    // each thread owns kScanItems consecutive elements
+    const int64_t i0 = base + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+        v[q] = (i0 + q < n) ? in[i0 + q] : 0u;
+        s += v[q];
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_scan_u32(s, s_buf, tot) + part[blockIdx.x];
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+        if (i0 + q < n) {
+            out[i0 + q] = ex;
+            if (zero_in) in[i0 + q] = 0u;
+        }
+        ex += v[q];
+    }
+}
+
+// =======================================================================================
+// Births: rank by parent id (bitmap popcounts below the id plus the scanned per-1024-id
+// counts), then write the new electron and ion at slot n_slots + rank with id
+// next_id + rank.  The last block updates the counters.
+// =======================================================================================
+__device__ __forceinline__ void birth_locate(const Dev &d, int64_t k, int &st, uint32_t &idx,
+                                             const uint32_t *s_pre)
+{
+    int lo = 0, hi = kStripes;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((int64_t)s_pre[mid] <= k)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    st = lo;
+    idx = (uint32_t)(k - s_pre[lo]);
+}
+
+template <bool F64>
+__global__ void k_birth_place(Dev d, int advance)
+{
+    __shared__ uint32_t s_pre[kStripes + 1];
+    __shared__ bool s_last;
+    if (threadIdx.x == 0) {
+        uint32_t a = 0;
+        for (int i = 0; i < kStripes; ++i) {
+            s_pre[i] = a;
+            a += min((int64_t)d.nbirth[i], d.birth_stripe_cap);
+        }
+        s_pre[kStripes] = a;
+    }
+    __syncthreads();
+    const int64_t M = s_pre[kStripes];
+    const int b = *d.cur;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < M;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        int st;
+        uint32_t idx;
+        birth_locate(d, k, st, idx, s_pre);
+        const Birth B = d.births[(int64_t)st * d.birth_stripe_cap + idx];
+        const EnsC &e = d.ens[B.ens];
+        const uint32_t pid = B.pid;
+        const int64_t g = (int64_t)(pid >> 10);
+        uint32_t r = d.l1pre[e.l1_base + g] - d.l1pre[e.l1_base];
+        const int64_t w0 = e.bm_base + (g << 5), wp = e.bm_base + (pid >> 5);
+        for (int64_t w = w0; w < wp; ++w) r += __popc(d.bitmap[w]);
+        r += __popc(d.bitmap[wp] & ((1u << (pid & 31)) - 1u));
+        for (int s = 0; s < e.nspecies; ++s) {
+            const int sg = e.seg[s];
+            const SegC &S = d.seg[sg];
+            const int64_t slot = d.n_slots[sg] + r;
+            if (slot >= S.cap) {
+                atomicOr(d.err, (int)E_CAP_PART);
+                continue;
+            }
+            if ((int64_t)d.next_id[sg] + r >= e.idcap) {
+                atomicOr(d.err, (int)E_CAP_ID);
+                continue;
+            }
+            const int64_t i = S.base + slot;
+            const double *v = (s == 0) ? B.ve : B.vi;
+            if constexpr (!F64) {
+                d.cell[b][i] = B.cell;
+                d.off[b][i] = B.off;
+                d.fvx[b][i] = (float)v[0];
+                d.fvy[b][i] = (float)v[1];
+                d.fvz[b][i] = (float)v[2];
+            } else {
+                d.x[b][i] = B.x;
+                d.dvx[b][i] = v[0];
+                d.dvy[b][i] = v[1];
+                d.dvz[b][i] = v[2];
+            }
+            d.id[b][i] = d.next_id[sg] + r;
+        }
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = (atomicAdd(d.ticket + 1, 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    // counts of births per ensemble
+    for (int en = threadIdx.x; en < d.nens; en += blockDim.x) {
+        const EnsC &e = d.ens[en];
+        const uint32_t m = d.l1pre[e.l1_base + (e.idcap >> 10)] - d.l1pre[e.l1_base];
+        for (int s = 0; s < e.nspecies; ++s) {
+            const int sg = e.seg[s];
+            const SegC &S = d.seg[sg];
+            d.n_slots[sg] = min(d.n_slots[sg] + (int64_t)m, S.cap);
+            d.next_id[sg] += m;
+            if (m) atomicAdd(d.cnt + ((int64_t)0 * d.nseg + sg) * C_NCNT + C_CREATED, (unsigned long long)m);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        d.ticket[1] = 0u;
+        // the freshly accumulated maxima become current; clear the other half
+        *d.vcur = 1 - *d.vcur;
+    }
+    __syncthreads();
+    {
+        const int old = 1 - *d.vcur;
+        for (int64_t i = threadIdx.x; i < (int64_t)kStripes * d.nseg; i += blockDim.x)
+            d.vmax2[(int64_t)old * kStripes * d.nseg + i] = 0ull;
+    }
+    (void)advance;
+}
+
+// Clear the bitmap words and group counts the births touched, reset the birth counts,
+// and (optionally) advance the step counter.
+__global__ void k_birth_clear(Dev d, int advance)
+{
+    __shared__ uint32_t s_pre[kStripes + 1];
+    __shared__ bool s_last;
+    if (threadIdx.x == 0) {
+        uint32_t a = 0;
+        for (int i = 0; i < kStripes; ++i) {
+            s_pre[i] = a;
+            a += min((int64_t)d.nbirth[i], d.birth_stripe_cap);
+        }
+        s_pre[kStripes] = a;
+    }
+    __syncthreads();
+    const int64_t M = s_pre[kStripes];
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < M;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        int st;
+        uint32_t idx;
+        birth_locate(d, k, st, idx, s_pre);
+        const Birth &B = d.births[(int64_t)st * d.birth_stripe_cap + idx];
+        const EnsC &e = d.ens[B.ens];
+        d.bitmap[e.bm_base + (B.pid >> 5)] = 0u;
+        d.l1cnt[e.l1_base + (B.pid >> 10)] = 0u;
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = (atomicAdd(d.ticket + 2, 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    for (int i = threadIdx.x; i < kStripes; i += blockDim.x) d.nbirth[i] = 0u;
+    if (threadIdx.x == 0) {
+        d.ticket[2] = 0u;
+        if (advance) *d.step += 1;
+    }
+}
+
+__global__ void k_advance(Dev d)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *d.step += 1;
+}
+
+// =======================================================================================
+// Counting sort by cell: the histogram is in cellcnt, scanned into cursor (global
+// positions over the concatenated segments).  Each tile ranks its particles per cell in
+// LDS (wave-leader reservation), reserves one run per cell with one HBM atomic, and
+// scatters into the other buffer.  Absorbed slots are dropped.
+// =======================================================================================
+template <bool F64, int PPT>
+__global__ void __launch_bounds__(256) k_sort_scatter(Dev d, int W)
+{
+    extern __shared__ unsigned long long s_dyn[];
+    uint32_t *sCnt = (uint32_t *)s_dyn;   // [W] counts, then bases
+    __shared__ int64_t s_tpre[kMaxSeg + 1];
+    __shared__ int s_min;
+    __shared__ bool s_last;
+    const int BLOCK = blockDim.x;
+    const int64_t TILE = (int64_t)BLOCK * PPT;
+    sched_prefix(d, TILE, s_tpre);
+    const int64_t T = s_tpre[d.nseg];
+    int64_t t0, t1;
+    block_run(T, t0, t1);
+    const int b = *d.cur, nb = 1 - b;
+    const int lane = lane_id();
+    for (int i = threadIdx.x; i < W; i += BLOCK) sCnt[i] = 0u;
+    __syncthreads();
+    for (int64_t t = t0; t < t1; ++t) {
+        const int sg = seg_of_tile(s_tpre, d.nseg, t);
+        const SegC &S = d.seg[sg];
+        const int64_t lt = t - s_tpre[sg];
+        const int64_t first = S.base + lt * TILE;
+        const int64_t last = S.base + min((lt + 1) * TILE, d.n_slots[sg]);
+        int cell[PPT];
+        uint32_t rank[PPT];
+        int mn = INT32_MAX;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int64_t i = first + (int64_t)k * BLOCK + threadIdx.x;
+            cell[k] = kDead;
+            if (i < last) {
+                if constexpr (!F64) {
+                    cell[k] = d.cell[b][i];
+                } else {
+                    const double x = d.x[b][i];
+                    double f;
+                    cell[k] = (x >= 0.0) ? (int)cell_of_x(S, x, f) : kDead;
+                }
+            }
+            if (cell[k] != kDead) mn = min(mn, cell[k]);
+        }
+        mn = wave_min_i32(mn);
+        if (threadIdx.x == 0) s_min = INT32_MAX;
+        __syncthreads();
+        if (lane == 0) atomicMin(&s_min, mn);
+        __syncthreads();
+        const int base = s_min;
+        // local ranks
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int rel = (cell[k] != kDead) ? cell[k] - base : -1;
+            const int key = (rel >= 0 && rel < W) ? rel : -1;
+            rank[k] = 0xFFFFFFFFu;
+            unsigned long long act = __ballot(key >= 0);
+            int it = 0;
+            while (act != 0ull && it < 8) {
+                const int leader = __ffsll((long long)act) - 1;
+                const int kk = __shfl(key, leader);
+                const bool mine = (key == kk) && ((act >> lane) & 1ull);
+                const unsigned long long m = __ballot(mine);
+                uint32_t r0 = 0;
+                if (lane == leader) r0 = atomicAdd(&sCnt[kk], (uint32_t)__popcll(m));
+                r0 = __shfl(r0, leader);
+                if (mine) rank[k] = r0 + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+                act &= ~m;
+                ++it;
+            }
+            if ((act >> lane) & 1ull) rank[k] = atomicAdd(&sCnt[key], 1u);
+        }
+        __syncthreads();
+        // reserve runs: counts -> global bases
+        for (int i = threadIdx.x; i < W; i += BLOCK) {
+            const uint32_t c = sCnt[i];
+            if (c) sCnt[i] = atomicAdd(d.cursor + S.cbase + base + i, c);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            if (cell[k] == kDead) continue;
+            const int64_t i = first + (int64_t)k * BLOCK + threadIdx.x;
+            uint32_t pos;
+            if (rank[k] != 0xFFFFFFFFu)
+                pos = sCnt[cell[k] - base] + rank[k];
+            else
+                pos = atomicAdd(d.cursor + S.cbase + cell[k], 1u);
+            const int64_t o = S.base + (int64_t)pos - d.segstart[sg];
+            if (o < S.base || o >= S.base + S.cap) {  // histogram and slots disagree
+                atomicOr(d.err, (int)E_CAP_PART);
+                continue;
+            }
+            if constexpr (!F64) {
+                d.cell[nb][o] = cell[k];
+                d.off[nb][o] = d.off[b][i];
+                d.fvx[nb][o] = d.fvx[b][i];
+                d.fvy[nb][o] = d.fvy[b][i];
+                d.fvz[nb][o] = d.fvz[b][i];
+            } else {
+                d.x[nb][o] = d.x[b][i];
+                d.dvx[nb][o] = d.dvx[b][i];
+                d.dvy[nb][o] = d.dvy[b][i];
+                d.dvz[nb][o] = d.dvz[b][i];
+            }
+            d.id[nb][o] = d.id[b][i];
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < W; i += BLOCK) sCnt[i] = 0u;
+        __syncthreads();
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = (atomicAdd(d.ticket + 3, 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    for (int sg = threadIdx.x; sg < d.nseg; sg += BLOCK) {
+        const SegC &S = d.seg[sg];
+        const int64_t n = (int64_t)d.cursor[S.cbase + S.ncells - 1] - d.segstart[sg];
+        d.n_slots[sg] = min(max(n, (int64_t)0), S.cap);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        *d.cur = nb;
+        d.ticket[3] = 0u;
+    }
+}
+
+// After the scan of cellcnt into cursor: the first global position of each segment.
+__global__ void k_segstart(Dev d)
+{
+    for (int sg = threadIdx.x; sg < d.nseg; sg += blockDim.x) d.segstart[sg] = d.cursor[d.seg[sg].cbase];
+}
+
+// =======================================================================================
+// Diagnostics: alive count and sum |v|^2 per segment (FP64, fixed order per block, then
+// striped into a small array reduced on the host).
+// =======================================================================================
+template <bool F64>
+__global__ void k_diag(Dev d, int sg, double *out /* [grid][2] */)
+{
+    __shared__ double s_buf[8];
+    const SegC &S = d.seg[sg];
+    const int b = *d.cur;
+    const int64_t n = d.n_slots[sg];
+    double c = 0.0, v2 = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = S.base + p;
+        if constexpr (!F64) {
+            if (d.cell[b][i] == kDead) continue;
+            v2 += speed2_rn(d.fvx[b][i], d.fvy[b][i], d.fvz[b][i]);
+        } else {
+            if (!(d.x[b][i] >= 0.0)) continue;
+            v2 += speed2_rn(d.dvx[b][i], d.dvy[b][i], d.dvz[b][i]);
+        }
+        c += 1.0;
+    }
+    c = block_sum(c, s_buf);
+    v2 = block_sum(v2, s_buf);
+    if (threadIdx.x == 0) {
+        out[2 * blockIdx.x] = c;
+        out[2 * blockIdx.x + 1] = v2;
+    }
+}
+
+// =======================================================================================
+// Host launchers.
+// =======================================================================================
+#define LAUNCH_CHECK()                                          \
+    do {                                                        \
+        hipError_t _e = hipGetLastError();                      \
+        if (_e != hipSuccess) return _e;                        \
+    } while (0)
+
+template <bool F64, int STAGES>
+static hipError_t launch_particles_t(const Dev &d, const Launch &L, hipStream_t s, int hist)
+{
+    const size_t lds = (size_t)(L.window + 1) * 8 + (size_t)L.window * 4;
+    switch (L.ppt) {
+    case 1:
+        hipLaunchKernelGGL((k_particles<F64, STAGES, 1>), dim3(L.grid), dim3(L.block), lds, s, d, L.window, hist);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_particles<F64, STAGES, 2>), dim3(L.grid), dim3(L.block), lds, s, d, L.window, hist);
+        break;
+    case 8:
+        hipLaunchKernelGGL((k_particles<F64, STAGES, 8>), dim3(L.grid), dim3(L.block), lds, s, d, L.window, hist);
+        break;
+    default:
+        hipLaunchKernelGGL((k_particles<F64, STAGES, 4>), dim3(L.grid), dim3(L.block), lds, s, d, L.window, hist);
+        break;
+    }
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_particles(const Dev &d, const Launch &L, hipStream_t s, bool f64, int stages, int hist)
+{
+#define PIC_CASE(ST)                                                          \
+    case ST:                                                                  \
+        return f64 ? launch_particles_t<true, ST>(d, L, s, hist)              \
+                   : launch_particles_t<false, ST>(d, L, s, hist);
+    switch (stages) {
+        PIC_CASE(ST_PUSH)
+        PIC_CASE(ST_COLLIDE)
+        PIC_CASE(ST_DEPOSIT)
+        PIC_CASE(ST_HIST)
+        PIC_CASE(ST_PUSH | ST_COLLIDE | ST_DEPOSIT)
+        PIC_CASE(ST_PUSH | ST_DEPOSIT)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef PIC_CASE
+}
+
+hipError_t launch_init(const Dev &d, bool f64, int sg, int64_t n, int64_t ppc, int init_mode,
+                       double vth, double amp, int mode, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int B = 256;
+    const int64_t G = (n + B - 1) / B;
+    if (f64)
+        hipLaunchKernelGGL(k_init<true>, dim3(G), dim3(B), 0, s, d, sg, n, ppc, init_mode, vth, amp, mode);
+    else
+        hipLaunchKernelGGL(k_init<false>, dim3(G), dim3(B), 0, s, d, sg, n, ppc, init_mode, vth, amp, mode);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_vmax(const Dev &d, bool f64, hipStream_t s)
+{
+    dim3 g(256, d.nseg);
+    if (f64)
+        hipLaunchKernelGGL(k_vmax<true>, g, dim3(256), 0, s, d);
+    else
+        hipLaunchKernelGGL(k_vmax<false>, g, dim3(256), 0, s, d);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_zero_q(const Dev &d, bool f64, hipStream_t s)
+{
+    if (f64)
+        hipLaunchKernelGGL(k_zero_q<true>, dim3(512), dim3(256), 0, s, d);
+    else
+        hipLaunchKernelGGL(k_zero_q<false>, dim3(512), dim3(256), 0, s, d);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_solve(const Dev &d, bool f64, int64_t nchunks, bool zero_q, hipStream_t s)
+{
+    if (f64) {
+        hipLaunchKernelGGL(k_solve1<true>, dim3(nchunks), dim3(kSolveThreads), 0, s, d);
+        hipLaunchKernelGGL(k_solve2<true>, dim3(nchunks), dim3(kSolveThreads), 0, s, d, zero_q ? 1 : 0);
+    } else {
+        hipLaunchKernelGGL(k_solve1<false>, dim3(nchunks), dim3(kSolveThreads), 0, s, d);
+        hipLaunchKernelGGL(k_solve2<false>, dim3(nchunks), dim3(kSolveThreads), 0, s, d, zero_q ? 1 : 0);
+    }
+    LAUNCH_CHECK();
+    if (d.periodic) {
+        hipLaunchKernelGGL(k_phi_shift, dim3(nchunks), dim3(kSolveThreads), 0, s, d);
+        LAUNCH_CHECK();
+    }
+    if (!f64) {
+        hipLaunchKernelGGL(k_ecell, dim3(nchunks), dim3(kSolveThreads), 0, s, d);
+        LAUNCH_CHECK();
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_field_stats(const Dev &d, bool f64, int64_t nchunks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_field_stats, dim3(1), dim3(kSolveThreads), 0, s, d);
+    LAUNCH_CHECK();
+    if (!f64) {
+        hipLaunchKernelGGL(k_ecell, dim3(nchunks), dim3(kSolveThreads), 0, s, d);
+        LAUNCH_CHECK();
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_params(const Dev &d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_params, dim3(1), dim3(256), 0, s, d);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_scan(uint32_t *in, uint32_t *out, int64_t n, uint32_t *part, bool zero_in, hipStream_t s)
+{
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(kScanBlock), 0, s, in, n, part);
+    hipLaunchKernelGGL(k_scan_part, dim3(1), dim3(1024), 0, s, part, nb);
+    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kScanBlock), 0, s, in, out, n, part, zero_in ? 1 : 0);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+int64_t scan_blocks(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
+
+hipError_t launch_births(const Dev &d, bool f64, bool advance, hipStream_t s)
+{
+    hipError_t e = launch_scan(d.l1cnt, d.l1pre, d.l1_tot, d.scanpart, false, s);
+    if (e != hipSuccess) return e;
+    if (f64)
+        hipLaunchKernelGGL(k_birth_place<true>, dim3(64), dim3(256), 0, s, d, 0);
+    else
+        hipLaunchKernelGGL(k_birth_place<false>, dim3(64), dim3(256), 0, s, d, 0);
+    hipLaunchKernelGGL(k_birth_clear, dim3(64), dim3(256), 0, s, d, advance ? 1 : 0);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_advance(const Dev &d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, d);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_sort(const Dev &d, bool f64, const Launch &L, hipStream_t s)
+{
+    hipError_t e = launch_scan(d.cellcnt, d.cursor, d.cells_tot, d.scanpart, true, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_segstart, dim3(1), dim3(256), 0, s, d);
+    const size_t lds = (size_t)L.window * 4;
+    if (f64)
+        hipLaunchKernelGGL((k_sort_scatter<true, 4>), dim3(L.grid), dim3(L.block), lds, s, d, L.window);
+    else
+        hipLaunchKernelGGL((k_sort_scatter<false, 4>), dim3(L.grid), dim3(L.block), lds, s, d, L.window);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_diag(const Dev &d, bool f64, int sg, double *out, int grid, hipStream_t s)
+{
+    if (f64)
+        hipLaunchKernelGGL(k_diag<true>, dim3(grid), dim3(256), 0, s, d, sg, out);
+    else
+        hipLaunchKernelGGL(k_diag<false>, dim3(grid), dim3(256), 0, s, d, sg, out);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+}  // namespace pic

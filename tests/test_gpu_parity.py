@@ -1,0 +1,298 @@
+"""GPU parity: each stage of the HIP path against the FP64 oracle on identical inputs.
+
+Both sides take their inputs from the synth module (seeded, synthetic); nothing the GPU
+computes is fed to the oracle.  Sizes span several tiles, chunks and ragged tails.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity_util import (TOL_FIELD, TOL_MOMENT, by_id, cell_counts, compare_particles, rel)
+
+pytestmark = pytest.mark.gpu
+
+PRECISIONS = ["fp32", "fp64"]
+
+
+@pytest.fixture(scope="module")
+def pic():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2606_28534_amd as P
+
+    P.load_library()
+    return P
+
+
+def work_of(e, precision="fp32"):
+    return {"name": "t", "steps": 1, "precision": precision, "ensembles": [e]}
+
+
+def ens_small(ncells=300, ppc=37, collisions=True, B=None, periodic=False, nspecies=2, sort_every=0,
+              seed=3, capacity=None):
+    e = synth.ensemble(ncells, ppc, collisions=collisions, B=B, periodic=periodic,
+                       nspecies=nspecies, sort_every=sort_every, seed=seed)
+    if capacity is not None:
+        for sp in e["species"]:
+            sp["capacity"] = int(capacity)
+    return e
+
+
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_init_matches_oracle(pic, prec):
+    e = ens_small(ncells=517, ppc=41, B=synth.oblique_B())
+    sim = pic.Sim(work_of(e, prec), fused=False)
+    o = oracle.Oracle(e)
+    for s in range(2):
+        g, r = by_id(sim.particles(0, s)), by_id(o.particles(s))
+        assert np.array_equal(g["id"], r["id"])
+        assert np.array_equal(g["x"], r["x"])      # cell and offset bit for bit
+        for k in ("vx", "vy", "vz"):
+            if prec == "fp32":
+                # v computed in FP64 and rounded once to binary32
+                assert np.array_equal(g[k], r[k].astype(np.float32).astype(np.float64)) or \
+                    np.max(np.abs(g[k] - r[k]) / np.maximum(np.abs(r[k]), 1e-30)) <= 2 ** -23
+            else:
+                assert np.max(np.abs(g[k] - r[k])) <= 1e-14 * np.max(np.abs(r[k]))
+    # the deposit of the load
+    gq, oq = sim.grid()["Q"], o.grid()["Q"]
+    n = e["species"][0]["ppc"] * e["ncells"]
+    for s in range(2):
+        if prec == "fp32":
+            assert abs(gq[s].sum() - n) == 0.0       # integer shares: exact total
+            assert np.max(np.abs(gq[s] - oq[s])) <= 2.0 ** -25 * 2 * e["species"][s]["ppc"] + 1e-9
+        else:
+            assert rel(gq[s], oq[s]) <= 1e-13
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+@pytest.mark.parametrize("periodic", [False, True])
+def test_deposit_and_solve_from_injected_state(pic, prec, periodic):
+    N = 4099  # several solve chunks and a ragged tail
+    e = ens_small(ncells=N, ppc=3, periodic=periodic, capacity=40000)
+    st = synth.random_state(e, [30011, 28999], seed=5)
+    sim = pic.Sim(work_of(e, prec), fused=False)
+    sim.set_state(st)
+    o = oracle.Oracle(e, init=False)
+    o.set_state(st)
+    sim.deposit()
+    o.deposit()
+    g, r = sim.grid(), o.grid()
+    for s in range(2):
+        if prec == "fp32":
+            assert g["Q"][s].sum() == len(st[s]["x"])
+            cnt = cell_counts(st[s]["x"], e["dx"], N)
+            bound = np.zeros(len(g["Q"][s]))
+            bound[:N] += cnt
+            if periodic:
+                bound += np.roll(cnt, 1)[: len(bound)]
+            else:
+                bound[1:] += cnt
+            assert np.all(np.abs(g["Q"][s] - r["Q"][s]) <= 2.0 ** -25 * bound + 1e-12)
+        else:
+            assert rel(g["Q"][s], r["Q"][s]) <= 1e-13
+    sim.solve()
+    o.solve()
+    g, r = sim.grid(), o.grid()
+    tol = TOL_FIELD if prec == "fp32" else 1e-10
+    for k in ("rho", "phi", "E"):
+        assert rel(g[k], r[k]) <= tol, (k, rel(g[k], r[k]))
+
+
+def test_scan_solve_equals_thomas_fp64(pic):
+    """The two-prefix-sum solve against the oracle's Thomas solve on the same charge."""
+    for N in (2, 3, 2047, 2048, 2049, 10007):
+        e = ens_small(ncells=N, ppc=2, nspecies=1, collisions=False, capacity=5 * N + 3)
+        st = synth.random_state(e, [5 * N + 3], seed=N)
+        sim = pic.Sim(work_of(e, "fp64"), fused=False)
+        sim.set_state(st)
+        o = oracle.Oracle(e, init=False)
+        o.set_state(st)
+        sim.deposit()
+        o.deposit()
+        sim.solve()
+        o.solve()
+        g, r = sim.grid(), o.grid()
+        assert rel(g["phi"], r["phi"]) <= 1e-10, N
+        assert rel(g["E"], r["E"]) <= 1e-10, N
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+@pytest.mark.parametrize("bfield", [False, True])
+def test_push_walls_from_injected_state(pic, prec, bfield):
+    N = 777
+    e = ens_small(ncells=N, ppc=10, B=synth.oblique_B() if bfield else None, collisions=False,
+                  capacity=40001)
+    st = synth.random_state(e, [40001, 39989], seed=11, vscale=[2.0, 0.05])
+    Ef = synth.random_field(e, seed=2, amp=0.3)
+    sim = pic.Sim(work_of(e, prec), fused=False)
+    sim.set_state(st)
+    sim.set_fields(Ef)
+    o = oracle.Oracle(e, init=False)
+    o.set_state(st)
+    o.set_fields(Ef)
+    for _ in range(3):
+        sim.push()
+        o.push()
+        o.walls()
+    L = N * e["dx"]
+    for s in range(2):
+        gp, op = sim.particles(0, s), o.particles(s)
+        # particles within rounding of a wall may go either way
+        near = op["id"][(np.abs(op["x"]) < 1e-5) | (np.abs(op["x"] - L) < 1e-5)]
+        compare_particles(gp, op, e["dx"], prec == "fp64", exclude=near)
+    gd, od = sim.diag(), o.diag()
+    for w in range(2):
+        for s in range(2):
+            assert abs(gd["wall_count"][w][s] - od["wall_count"][w][s]) <= 0
+    assert gd["pushes"] == od["pushes"]
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_collide_from_injected_state(pic, prec):
+    N = 64
+    e = ens_small(ncells=N, ppc=1)
+    e["ngs_el"], e["ngs_iz"], e["ngs_cx"] = 0.2, 0.3, 40.0
+    n = 60000
+    for sp in e["species"]:
+        sp["capacity"] = 3 * n
+    st = synth.random_state(e, [n, n], seed=23, vscale=[1.5, 3e-3])
+    sim = pic.Sim(work_of(e, prec), fused=False)
+    sim.set_state(st)
+    sim.set_fields(np.zeros(sim.nnodes()))
+    sim.set_step(7)
+    o = oracle.Oracle(e, init=False)
+    o.set_state(st)
+    o.set_fields(np.zeros(o.nnodes))
+    o.set_step(7)
+    sim.collide()
+    o.collide()
+    gd, od = sim.diag(), o.diag()
+    nu_o, _ = o.last_numax()
+    assert np.allclose(gd["numax"], nu_o, rtol=1e-15, atol=0)
+    # decisions are taken in FP64 on identical inputs: identical counts
+    assert gd["coll"] == od["coll"]
+    assert gd["created"] == od["created"]
+    for s in range(2):
+        gp, op = sim.particles(0, s), o.particles(s)
+        compare_particles(gp, op, e["dx"], prec == "fp64",
+                          vtol=(1e-12 if prec == "fp64" else 1e-5))
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_sort_groups_by_cell(pic, prec):
+    N = 1000
+    e = ens_small(ncells=N, ppc=5, capacity=20000)
+    st = synth.random_state(e, [20000, 15000], seed=8)
+    sim = pic.Sim(work_of(e, prec), fused=False)
+    sim.set_state(st)
+    sim.sort()
+    o = oracle.Oracle(e, init=False)
+    o.set_state(st)
+    o.sort()
+    for s in range(2):
+        g, r = sim.particles(0, s), o.particles(s)
+        gc = np.floor(g["x"] / e["dx"]).astype(np.int64)
+        assert np.all(np.diff(gc) >= 0)                      # grouped by cell, ascending
+        rc = np.floor(r["x"] / e["dx"]).astype(np.int64)
+        assert np.array_equal(gc, rc)                        # same histogram
+        for c in np.unique(rc)[:: max(1, len(np.unique(rc)) // 50)]:
+            assert set(g["id"][gc == c]) == set(r["id"][rc == c])
+        compare_particles(g, r, e["dx"], prec == "fp64", vtol=0.0, xtol=0.0)
+
+
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_collisionless_window_20_steps(pic, prec):
+    w = synth.scaled(synth.c2_sheath(), ncells=1500, ppc=40)
+    e = w["ensembles"][0]
+    e["collisions"] = False
+    sim = pic.Sim(work_of(e, prec), fused=(prec == "fp32"))
+    o = oracle.Oracle(e)
+    sim.step(20)
+    o.step(20)
+    gd, od = sim.diag(), o.diag()
+    assert gd["count"] == od["count"]
+    assert gd["wall_count"] == od["wall_count"]
+    assert gd["pushes"] == od["pushes"]
+    for s in range(2):
+        gp, op = sim.particles(0, s), o.particles(s)
+        vt = 1e-9 if prec == "fp64" else 1e-4
+        compare_particles(gp, op, e["dx"], prec == "fp64", vtol=vt, xtol=(1e-8 if prec == "fp64" else 1e-4))
+    g, r = sim.grid(), o.grid()
+    assert rel(g["E"], r["E"]) <= (1e-8 if prec == "fp64" else 1e-4)
+    for k in ("ke",):
+        for s in range(2):
+            assert abs(gd[k][s] - od[k][s]) <= TOL_MOMENT * abs(od[k][s])
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_one_full_step_with_collisions(pic, prec):
+    w = synth.scaled(synth.c2_sheath(), ncells=2000, ppc=50)
+    e = w["ensembles"][0]
+    e["ngs_el"], e["ngs_iz"] = 0.1, 0.2
+    for sp in e["species"]:
+        sp["capacity"] *= 2
+    sim = pic.Sim(work_of(e, prec), fused=(prec == "fp32"))
+    o = oracle.Oracle(e)
+    sim.step(1)
+    o.step(1)
+    gd, od = sim.diag(), o.diag()
+    # FP32 velocities can flip a decision that sits within rounding of a threshold
+    slack = 0 if prec == "fp64" else 3
+    for k in range(3):
+        assert abs(gd["coll"][k] - od["coll"][k]) <= slack
+    assert gd["wall_count"] == od["wall_count"]
+    for s in range(2):
+        assert abs(gd["created"][s] - od["created"][s]) <= slack
+    g, r = sim.grid(), o.grid()
+    assert rel(g["E"], r["E"]) <= TOL_FIELD  # E^0 (solved before the step's push)
+    if prec == "fp64":
+        for s in range(2):
+            compare_particles(sim.particles(0, s), o.particles(s), e["dx"], True, vtol=1e-11, xtol=1e-10)
+
+
+def _state(sim, nspec=2):
+    return [by_id(sim.particles(0, s)) for s in range(nspec)]
+
+
+def test_fused_equals_separate_and_graph_equals_eager(pic):
+    w = synth.scaled(synth.c2_sheath(), ncells=1200, ppc=30)
+    e = w["ensembles"][0]
+    e["ngs_el"], e["ngs_iz"] = 0.1, 0.2
+    for sp in e["species"]:
+        sp["capacity"] *= 2
+    fused_graph = pic.Sim(work_of(e), fused=True)
+    fused_eager = pic.Sim(work_of(e), fused=True)
+    separate = pic.Sim(work_of(e), fused=False)
+    fused_graph.step(25)           # one graph replay (20 steps) + 5 eager steps
+    for _ in range(25):
+        fused_eager.step(1)
+    separate.step(25)
+    a, b, c = _state(fused_graph), _state(fused_eager), _state(separate)
+    for s in range(2):
+        for k in ("id", "x", "vx", "vy", "vz"):
+            assert np.array_equal(a[s][k], b[s][k]), (s, k)
+            assert np.array_equal(a[s][k], c[s][k]), (s, k)
+    da, dc = fused_graph.diag(), separate.diag()
+    assert da["coll"] == dc["coll"] and da["created"] == dc["created"]
+    assert np.array_equal(fused_graph.grid()["Q"][0], separate.grid()["Q"][0])
+
+
+def test_run_is_deterministic(pic):
+    w = synth.scaled(synth.c2_sheath(), ncells=900, ppc=60)
+    e = w["ensembles"][0]
+    a, b = pic.Sim(work_of(e)), pic.Sim(work_of(e))
+    a.step(30)
+    b.step(30)
+    sa, sb = _state(a), _state(b)
+    for s in range(2):
+        for k in ("id", "x", "vx", "vy", "vz"):
+            assert np.array_equal(sa[s][k], sb[s][k])
+    assert np.array_equal(a.grid()["Q"][1], b.grid()["Q"][1])

@@ -1,0 +1,78 @@
+"""CPU checks of the C-ABI library: it loads and exports every symbol include/pic.h
+declares; workspace queries and configuration validation need no GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "pic.h")).read()
+    return sorted(set(re.findall(r"\b(pic_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2606_28534_amd as P
+
+    return P, P.load_library()
+
+
+def test_exports_every_declared_symbol(lib):
+    P, L = lib
+    names = declared_symbols()
+    assert len(names) >= 17
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(P.EXPORTS) <= set(names)
+
+
+def test_workspace_query_sizes(lib):
+    P, L = lib
+    for work, lo, hi in ((synth.c2_sheath(), 1.5e9, 4e9), (synth.c1_plain_small(), 1e6, 2e8)):
+        cfg, keep = P.make_config(work)
+        n = C.c_size_t(0)
+        assert L.pic_query_workspace(C.byref(cfg), C.byref(n)) == 0
+        assert lo < n.value < hi, n.value
+    # the large single-GPU share fits a 288 GB device
+    cfg, keep = P.make_config(synth.c5_large())
+    n = C.c_size_t(0)
+    assert L.pic_query_workspace(C.byref(cfg), C.byref(n)) == 0
+    assert n.value < 100e9
+
+
+def test_bad_configs_rejected(lib):
+    P, L = lib
+    work = synth.c1_plain_small()
+    e = work["ensembles"][0]
+    n = C.c_size_t(0)
+    bad = dict(e, ncells=1)
+    cfg, keep = P.make_config(dict(work, ensembles=[bad]))
+    assert L.pic_query_workspace(C.byref(cfg), C.byref(n)) == P.PIC_EINVAL
+    bad = synth.ensemble(100, 10)
+    bad["species"][0]["capacity"] = 10
+    cfg, keep = P.make_config(dict(work, ensembles=[bad]))
+    assert L.pic_query_workspace(C.byref(cfg), C.byref(n)) == P.PIC_EINVAL
+    cfg, keep = P.make_config(work)
+    cfg.precision = 7
+    assert L.pic_query_workspace(C.byref(cfg), C.byref(n)) == P.PIC_EINVAL
+    cfg, keep = P.make_config(work)
+    cfg.n_ensembles = 0
+    assert L.pic_query_workspace(C.byref(cfg), C.byref(n)) == P.PIC_EINVAL
+    # init refuses a workspace that is too small before touching the GPU
+    cfg, keep = P.make_config(work)
+    h = C.c_void_p()
+    assert L.pic_init(C.byref(cfg), C.c_void_p(0), 16, None, C.byref(h)) == P.PIC_EINVAL
+
+
+def test_null_context_calls_fail_cleanly(lib):
+    P, L = lib
+    for n in ("pic_deposit", "pic_solve", "pic_push", "pic_collide", "pic_sort"):
+        assert getattr(L, n)(None, None) == P.PIC_EINVAL
+    assert L.pic_step(None, 1, None) == P.PIC_EINVAL
+    assert L.pic_last_error(None) == b"null context"
