@@ -160,6 +160,12 @@ int pic_diag(pic_ctx *ctx, int32_t ens, pic_diag_out *out, void *stream);
 int pic_get_particles(pic_ctx *ctx, int32_t ens, int32_t species, pic_particles out,
                       int64_t cap, int64_t *count, void *stream);
 
+/* Raw slots [first, first + count) of (ens, species) in the current buffer, absorbed slots
+ * included (their x is -1), without compaction: a cheap sampled read-back for runs too
+ * large to copy whole.  Slot order is the load order until the first sort. */
+int pic_get_slots(pic_ctx *ctx, int32_t ens, int32_t species, int64_t first, int64_t count,
+                  pic_particles out, void *stream);
+
 /* Replace the particles of (ens, species) with `count` host particles (x in [0, L));
  * next_id is the id the next created particle of this species receives. */
 int pic_set_particles(pic_ctx *ctx, int32_t ens, int32_t species, pic_particles in,

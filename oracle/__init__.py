@@ -98,6 +98,7 @@ def lib():
         L.orc_last_channels.restype = C.c_int64
         L.orc_last_numax.argtypes = [P, P, P]
         L.orc_set_step.argtypes = [P, C.c_int64]
+        L.orc_init_particle.argtypes = [C.POINTER(_Config), C.c_int, C.c_int64, P, P, P, P]
         L.orc_philox4x32_10.argtypes = [P, P, P]
         L.orc_philox_batch.argtypes = [C.c_int64, P, P, P]
         L.orc_uniform.argtypes = [C.c_uint32]
@@ -240,6 +241,21 @@ class Oracle:
         pn = np.zeros(2)
         self.L.orc_last_numax(self.h, _ptr(nu), _ptr(pn))
         return nu, pn
+
+
+def init_particles(e, s, ps):
+    """The load of particles `ps` (indices) of species s of ensemble dict e, one by one."""
+    cfg = make_config(e)
+    ps = np.asarray(ps, dtype=np.int64)
+    out = {k: np.empty(len(ps)) for k in ("x", "vx", "vy", "vz")}
+    L = lib()
+    x, vx, vy, vz = (C.c_double() for _ in range(4))
+    for i, p in enumerate(ps):
+        L.orc_init_particle(C.byref(cfg), int(s), int(p), C.byref(x), C.byref(vx), C.byref(vy),
+                            C.byref(vz))
+        out["x"][i], out["vx"][i], out["vy"][i], out["vz"][i] = x.value, vx.value, vy.value, vz.value
+    out["id"] = ps.astype(np.uint32)
+    return out
 
 
 def philox(ctr, key):

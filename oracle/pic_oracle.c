@@ -213,10 +213,41 @@ int orc_error(const orc_state *st) { return st->err; }
  * Reading R19 (init_mode 1): quiet start x0 = (p + 1/2) L / P displaced by
  *   (A / k) sin(k x0) with k = 2 pi mode / L, which gives density ~ 1 - A cos(k x) to first
  *   order; velocities Maxwellian at T_s (cold when T_s = 0).                              */
+void orc_init_particle(const orc_config *c, int s, int64_t p, double *xo, double *vx, double *vy,
+                       double *vz)
+{
+    int64_t ppc = c->sp[s].ppc;
+    int64_t P = ppc * c->ncells;
+    double L = (double)c->ncells * c->dx;
+    double vth = sqrt(c->sp[s].T / c->sp[s].m);
+    uint32_t w[4];
+    uint32_t key[2] = {c->seed, (uint32_t)s};
+    double z[3];
+    double x;
+    if (c->init_mode == 0) {
+        int64_t cell = p / ppc;
+        uint32_t ctr[4] = {(uint32_t)p, ORC_INIT_TAG, 0u, 0u};
+        orc_philox4x32_10(ctr, key, w);
+        x = ((double)cell + orc_uniform(w[0])) * c->dx;
+    } else {
+        double k = ORC_TWO_PI * (double)c->perturb_mode / L;
+        double x0 = ((double)p + 0.5) * L / (double)P;
+        x = x0 + (c->perturb_amp / k) * sin(k * x0);
+        while (x < 0.0) x += L;
+        while (x >= L) x -= L;
+    }
+    uint32_t ctr1[4] = {(uint32_t)p, ORC_INIT_TAG, 1u, 0u};
+    orc_philox4x32_10(ctr1, key, w);
+    three_normals(w, z);
+    *xo = x;
+    *vx = vth * z[0];
+    *vy = vth * z[1];
+    *vz = vth * z[2];
+}
+
 void orc_init(orc_state *st)
 {
     const orc_config *c = &st->cfg;
-    double L = dlen(st);
     for (int s = 0; s < c->nspecies; s++) {
         int64_t ppc = c->sp[s].ppc;
         int64_t P = ppc * c->ncells;
@@ -224,28 +255,8 @@ void orc_init(orc_state *st)
             st->err = 1;
             P = st->cap[s];
         }
-        double vth = sqrt(c->sp[s].T / c->sp[s].m);
         for (int64_t p = 0; p < P; p++) {
-            uint32_t w[4];
-            double z[3];
-            double x;
-            if (c->init_mode == 0) {
-                int64_t cell = p / ppc;
-                draw_block(st, s, (uint32_t)p, ORC_INIT_TAG, 0u, w);
-                x = ((double)cell + orc_uniform(w[0])) * c->dx;
-            } else {
-                double k = ORC_TWO_PI * (double)c->perturb_mode / L;
-                double x0 = ((double)p + 0.5) * L / (double)P;
-                x = x0 + (c->perturb_amp / k) * sin(k * x0);
-                while (x < 0.0) x += L;
-                while (x >= L) x -= L;
-            }
-            draw_block(st, s, (uint32_t)p, ORC_INIT_TAG, 1u, w);
-            three_normals(w, z);
-            st->x[s][p] = x;
-            st->vx[s][p] = vth * z[0];
-            st->vy[s][p] = vth * z[1];
-            st->vz[s][p] = vth * z[2];
+            orc_init_particle(c, s, p, &st->x[s][p], &st->vx[s][p], &st->vy[s][p], &st->vz[s][p]);
             st->id[s][p] = (uint32_t)p;
         }
         st->n[s] = P;

@@ -76,6 +76,11 @@ int orc_error(const orc_state *st);
 /* Particle load (R17 init / R19 quiet start), then deposit of Q^0 and the speed bound. */
 void orc_init(orc_state *st);
 
+/* The load of one particle p of species s (the same recipe as orc_init), for checking
+ * sampled particles of runs too large to load whole on the CPU. */
+void orc_init_particle(const orc_config *cfg, int s, int64_t p, double *x, double *vx, double *vy,
+                       double *vz);
+
 /* Inject / read back a species' particles: absolute x, velocity, id. */
 int orc_set_particles(orc_state *st, int s, int64_t n, const double *x, const double *vx,
                       const double *vy, const double *vz, const uint32_t *id, uint32_t next_id);

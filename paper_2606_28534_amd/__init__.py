@@ -21,7 +21,7 @@ PIC_ABSORBING, PIC_PERIODIC = 0, 1
 
 EXPORTS = ("pic_query_workspace", "pic_init", "pic_deposit", "pic_solve", "pic_push",
            "pic_collide", "pic_sort", "pic_step", "pic_diag", "pic_get_particles",
-           "pic_set_particles", "pic_get_grid", "pic_set_fields", "pic_set_step",
+           "pic_get_slots", "pic_set_particles", "pic_get_grid", "pic_set_fields", "pic_set_step",
            "pic_nnodes", "pic_timing", "pic_timing_read", "pic_free", "pic_last_error")
 
 
@@ -99,6 +99,7 @@ def load_library():
     L.pic_get_particles.argtypes = [P, C.c_int32, C.c_int32, Particles, C.c_int64,
                                     C.POINTER(C.c_int64), P]
     L.pic_set_particles.argtypes = [P, C.c_int32, C.c_int32, Particles, C.c_int64, C.c_uint32, P]
+    L.pic_get_slots.argtypes = [P, C.c_int32, C.c_int32, C.c_int64, C.c_int64, Particles, P]
     L.pic_get_grid.argtypes = [P, C.c_int32, P, P, P, P, P, P]
     L.pic_set_fields.argtypes = [P, C.c_int32, P, P]
     L.pic_set_step.argtypes = [P, C.c_int64]
@@ -241,6 +242,16 @@ class Sim:
         k = n.value
         return {"x": x[:k].copy(), "vx": vx[:k].copy(), "vy": vy[:k].copy(), "vz": vz[:k].copy(),
                 "id": ids[:k].copy()}
+
+    def slots(self, ens, s, first, count):
+        """Raw slots [first, first + count) (absorbed slots have x = -1)."""
+        x, vx, vy, vz = (np.empty(count) for _ in range(4))
+        ids = np.empty(count, dtype=np.uint32)
+        p = Particles(x.ctypes.data_as(C.POINTER(C.c_double)), vx.ctypes.data_as(C.POINTER(C.c_double)),
+                      vy.ctypes.data_as(C.POINTER(C.c_double)), vz.ctypes.data_as(C.POINTER(C.c_double)),
+                      ids.ctypes.data_as(C.POINTER(C.c_uint32)))
+        self._check(self.L.pic_get_slots(self.h, int(ens), int(s), int(first), int(count), p, self._s()))
+        return {"x": x, "vx": vx, "vy": vy, "vz": vz, "id": ids}
 
     def set_particles(self, ens, s, x, vx, vy, vz, ids, next_id):
         x, vx, vy, vz = (np.ascontiguousarray(a, dtype=np.float64) for a in (x, vx, vy, vz))

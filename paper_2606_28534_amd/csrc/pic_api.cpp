@@ -112,7 +112,7 @@ int build_plan(const pic_config *cfg, Plan &P, std::string &msg)
             E.qw[s] = sp.q * sp.w;
             SegC S{};
             S.base = base;
-            S.cap = sp.capacity;
+            S.cap = (sp.capacity + kSlotAlign - 1) / kSlotAlign * kSlotAlign;
             S.cbase = cbase;
             S.gbase = gbase;
             S.ens = e;
@@ -135,7 +135,7 @@ int build_plan(const pic_config *cfg, Plan &P, std::string &msg)
             S.other = (s == 0 && P.nspecies > 1) ? (int32_t)(P.seg.size() + 1) : -1;
             E.seg[s] = (int32_t)P.seg.size();
             P.seg.push_back(S);
-            base += sp.capacity;
+            base += S.cap;
             cbase += D.ncells;
             if (s == 0) ecap += sp.capacity;
         }
@@ -192,6 +192,7 @@ size_t carve(const Plan &P, char *base, Dev &d)
             d.fvz[b] = c.take<float>(P.cap_tot);
         }
     }
+    d.cap_tot = P.cap_tot;
     d.cur = c.take<int32_t>(1);
     d.n_slots = c.take<int64_t>(P.nseg);
     d.next_id = c.take<uint32_t>(P.nseg);
@@ -356,13 +357,13 @@ Launch default_launch(const pic_config *cfg, const Plan &P)
 {
     Launch L;
     L.block = cfg->block > 0 ? cfg->block : 256;
-    L.ppt = 4;
+    L.ppt = (cfg->precision == PIC_FP32_CELLOFF) ? 8 : 4;
     int64_t tiles = 0;
     for (const SegC &S : P.seg) tiles += (S.cap + (int64_t)L.block * L.ppt - 1) / ((int64_t)L.block * L.ppt);
-    int g = cfg->grid > 0 ? cfg->grid : 2048;
+    int g = cfg->grid > 0 ? cfg->grid : 1024;
     g = (int)std::min<int64_t>(g, std::max<int64_t>(8, (tiles + 7) / 8 * 8));
     L.grid = std::max(8, g / 8 * 8);
-    L.window = cfg->window > 0 ? cfg->window : 256;
+    L.window = cfg->window > 0 ? cfg->window : 512;
     return L;
 }
 
@@ -641,6 +642,46 @@ int pic_get_particles(pic_ctx *c, int32_t ens, int32_t species, pic_particles ou
         }
     }
     *count = k;
+    return PIC_OK;
+}
+
+int pic_get_slots(pic_ctx *c, int32_t ens, int32_t species, int64_t first, int64_t count,
+                  pic_particles out, void *stream)
+{
+    if (!c || ens < 0 || ens >= c->P.nens || species < 0 || species >= c->P.nspecies || first < 0 ||
+        count < 0)
+        return fail(c, PIC_EINVAL, "bad ensemble/species/range");
+    const int sg = c->P.ens[ens].seg[species];
+    const SegC &S = c->P.seg[sg];
+    if (first + count > S.cap) return fail(c, PIC_EINVAL, "slot range beyond capacity");
+    hipStream_t s = (hipStream_t)stream;
+    int32_t b = 0;
+    HIPC(c, hipMemcpyAsync(&b, c->d.cur, 4, hipMemcpyDeviceToHost, s));
+    HIPC(c, hipStreamSynchronize(s));
+    const int64_t i0 = S.base + first;
+    HIPC(c, hipMemcpy(out.id, c->d.id[b] + i0, count * 4, hipMemcpyDeviceToHost));
+    if (c->P.f64) {
+        HIPC(c, hipMemcpy(out.x, c->d.x[b] + i0, count * 8, hipMemcpyDeviceToHost));
+        HIPC(c, hipMemcpy(out.vx, c->d.dvx[b] + i0, count * 8, hipMemcpyDeviceToHost));
+        HIPC(c, hipMemcpy(out.vy, c->d.dvy[b] + i0, count * 8, hipMemcpyDeviceToHost));
+        HIPC(c, hipMemcpy(out.vz, c->d.dvz[b] + i0, count * 8, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < count; ++i)
+            if (!(out.x[i] >= 0.0)) out.x[i] = -1.0;
+    } else {
+        std::vector<int32_t> cell(count);
+        std::vector<float> off(count), vx(count), vy(count), vz(count);
+        HIPC(c, hipMemcpy(cell.data(), c->d.cell[b] + i0, count * 4, hipMemcpyDeviceToHost));
+        HIPC(c, hipMemcpy(off.data(), c->d.off[b] + i0, count * 4, hipMemcpyDeviceToHost));
+        HIPC(c, hipMemcpy(vx.data(), c->d.fvx[b] + i0, count * 4, hipMemcpyDeviceToHost));
+        HIPC(c, hipMemcpy(vy.data(), c->d.fvy[b] + i0, count * 4, hipMemcpyDeviceToHost));
+        HIPC(c, hipMemcpy(vz.data(), c->d.fvz[b] + i0, count * 4, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < count; ++i) {
+            out.x[i] = (cell[i] == kDead) ? -1.0 : ((double)cell[i] + (double)off[i]) * S.dx;
+            out.vx[i] = vx[i];
+            out.vy[i] = vy[i];
+            out.vz[i] = vz[i];
+        }
+    }
     return PIC_OK;
 }
 

@@ -27,6 +27,7 @@ constexpr int kScanBlock = 256;
 constexpr int kScanItems = 16;        // elements per thread in the generic scan
 constexpr double kFix = 16777216.0;   // 2^24 fixed-point scale of the deposit
 constexpr double kNuSafety = 1.0 + 1.0 / 65536.0;
+constexpr int64_t kSlotAlign = 4096;  // segment slot ranges are multiples of the largest tile
 
 // Counter slots per (stripe, segment).
 enum Cnt : int {
@@ -86,6 +87,7 @@ struct Dev {
     float *off[2], *fvx[2], *fvy[2], *fvz[2];
     double *x[2], *dvx[2], *dvy[2], *dvz[2];
     uint32_t *id[2];
+    int64_t cap_tot;          // total slots (a multiple of kSlotAlign)
     int32_t *cur;             // [1] current particle buffer
     int64_t *n_slots;         // [nseg] slots in use (alive + absorbed-not-yet-compacted)
     uint32_t *next_id;        // [nseg]

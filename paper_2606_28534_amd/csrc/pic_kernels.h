@@ -29,6 +29,8 @@ int64_t scan_blocks(int64_t n);
 hipError_t launch_births(const Dev &d, bool f64, bool advance, hipStream_t s);
 hipError_t launch_advance(const Dev &d, hipStream_t s);
 hipError_t launch_sort(const Dev &d, bool f64, const Launch &L, hipStream_t s);
+hipError_t launch_pass32(const Dev &d, int ppt, int W, hipStream_t s, int stages, int hist, int64_t cap_tot);
+hipError_t launch_sort32_scatter(const Dev &d, int ppt, int W, hipStream_t s, int64_t cap_tot);
 hipError_t launch_diag(const Dev &d, bool f64, int sg, double *out, int grid, hipStream_t s);
 
 }  // namespace pic

@@ -1,0 +1,346 @@
+// pic_particle.h -- per-particle device code shared by the particle kernels: register
+// state, gather + Boris push + walls, null-collision decision and kinematics, and the
+// direct (HBM atomic) cloud-in-cell deposit of a single particle.
+#pragma once
+#include <type_traits>
+
+#include "pic_device.h"
+
+namespace pic {
+
+// =======================================================================================
+// Particle state in registers.
+// =======================================================================================
+template <bool F64>
+struct PS;
+template <>
+struct PS<false> {
+    int cell;
+    float off, vx, vy, vz;
+    uint32_t id;
+};
+template <>
+struct PS<true> {
+    double x, vx, vy, vz;
+    uint32_t id;
+};
+
+template <bool F64>
+__device__ __forceinline__ void p_load(const Dev &d, int b, int64_t i, PS<F64> &p, bool need_v,
+                                       bool need_id)
+{
+    if constexpr (!F64) {
+        p.cell = d.cell[b][i];
+        if (p.cell == kDead) return;
+        p.off = d.off[b][i];
+        if (need_v) {
+            p.vx = d.fvx[b][i];
+            p.vy = d.fvy[b][i];
+            p.vz = d.fvz[b][i];
+        }
+    } else {
+        p.x = d.x[b][i];
+        if (!(p.x >= 0.0)) return;
+        if (need_v) {
+            p.vx = d.dvx[b][i];
+            p.vy = d.dvy[b][i];
+            p.vz = d.dvz[b][i];
+        }
+    }
+    if (need_id) p.id = d.id[b][i];
+}
+
+template <bool F64>
+__device__ __forceinline__ bool p_alive(const PS<F64> &p)
+{
+    if constexpr (!F64)
+        return p.cell != kDead;
+    else
+        return p.x >= 0.0;
+}
+
+template <bool F64>
+__device__ __forceinline__ void p_kill(PS<F64> &p)
+{
+    if constexpr (!F64)
+        p.cell = kDead;
+    else
+        p.x = -1.0;
+}
+
+// Cell index and fraction of an absolute position in [0, L): x / dx may round up to N
+// for x just below L, which is folded back into the last cell.
+__device__ __forceinline__ int64_t cell_of_x(const SegC &S, double x, double &f)
+{
+    const double g = x / S.dx;
+    double jf = floor(g);
+    if (jf > (double)(S.ncells - 1)) jf = (double)(S.ncells - 1);
+    if (!(jf >= 0.0)) jf = 0.0;
+    f = g - jf;
+    return (int64_t)jf;
+}
+
+// Cell index and in-cell fraction.
+template <bool F64>
+__device__ __forceinline__ int p_cell(const SegC &S, const PS<F64> &p, double &f)
+{
+    if constexpr (!F64) {
+        f = (double)p.off;
+        return p.cell;
+    } else {
+        return (int)cell_of_x(S, p.x, f);
+    }
+}
+
+// Boris rotation in the given precision: half kick, v' = v- + v- x t, v+ = v- + v' x s,
+// half kick.
+template <typename T>
+__device__ __forceinline__ void boris(T h, const T t[3], const T s[3], T Ep, T &vx, T &vy, T &vz)
+{
+    T ax = vx + h * Ep, ay = vy, az = vz;
+    const T px = ax + (ay * t[2] - az * t[1]);
+    const T py = ay + (az * t[0] - ax * t[2]);
+    const T pz = az + (ax * t[1] - ay * t[0]);
+    ax += py * s[2] - pz * s[1];
+    ay += pz * s[0] - px * s[2];
+    az += px * s[1] - py * s[0];
+    vx = ax + h * Ep;
+    vy = ay;
+    vz = az;
+}
+
+// Gather (linear weighting of node E), Boris push, position update, walls.
+// Returns 0 alive, 1 absorbed at the left wall, 2 at the right wall.
+template <bool F64>
+__device__ __forceinline__ int p_push(const Dev &d, const SegC &S, const EnsC &e, PS<F64> &p)
+{
+    if constexpr (!F64) {
+        const float2 ec = d.Ecell[S.gbase + p.cell];
+        const float Ep = fmaf(p.off, ec.y, ec.x) + (float)e.E_ext;
+        const float h = (float)S.h;
+        const float t[3] = {(float)S.t[0], (float)S.t[1], (float)S.t[2]};
+        const float s[3] = {(float)S.s[0], (float)S.s[1], (float)S.s[2]};
+        boris<float>(h, t, s, Ep, p.vx, p.vy, p.vz);
+        float o = p.off + p.vx * (float)S.dtdx;
+        const float fl = floorf(o);
+        int c = p.cell + (int)fl;
+        o -= fl;
+        if (o >= 1.0f) {
+            o -= 1.0f;
+            c += 1;
+        }
+        p.off = o;
+        if (S.periodic) {
+            if (c < 0)
+                c += S.ncells;
+            else if (c >= S.ncells)
+                c -= S.ncells;
+            p.cell = c;
+            if (c < 0 || c >= S.ncells) {  // moved more than a period: not a valid state
+                atomicOr(d.err, (int)E_NONFINITE);
+                return 3;
+            }
+            return 0;
+        }
+        p.cell = c;
+        if (c < 0) return 1;
+        if (c >= S.ncells) return 2;
+        return 0;
+    } else {
+        double f;
+        const int64_t j = cell_of_x(S, p.x, f);
+        int64_t j1 = j + 1;
+        if (S.periodic && j1 == S.ncells) j1 = 0;
+        const double Ep = (1.0 - f) * d.E[S.gbase + j] + f * d.E[S.gbase + j1] + e.E_ext;
+        boris<double>(S.h, S.t, S.s, Ep, p.vx, p.vy, p.vz);
+        double x = p.x + S.dt * p.vx;
+        const double L = e.L;
+        if (S.periodic) {
+            if (x < 0.0)
+                x += L;
+            else if (x >= L)
+                x -= L;
+            if (x >= L) x -= L;  // x + L rounded up to L
+            p.x = x;
+            if (!(x >= 0.0 && x < L)) {
+                atomicOr(d.err, (int)E_NONFINITE);
+                return 3;
+            }
+            return 0;
+        }
+        p.x = x;
+        if (x >= 0.0 && x < L) return 0;
+        return (x < 0.0) ? 1 : 2;  // NaN counts as the right wall
+    }
+}
+
+__device__ __forceinline__ void sc(float a, float *s, float *c) { sincosf(a, s, c); }
+__device__ __forceinline__ void sc(double a, double *s, double *c) { sincos(a, s, c); }
+__device__ __forceinline__ float msqrt(float a) { return sqrtf(a); }
+__device__ __forceinline__ double msqrt(double a) { return sqrt(a); }
+__device__ __forceinline__ float mlog(float a) { return logf(a); }
+__device__ __forceinline__ double mlog(double a) { return log(a); }
+
+template <typename T>
+__device__ __forceinline__ void iso_dir(T ua, T ub, T d[3])
+{
+    const T c = (T)1 - (T)2 * ua;
+    const T s2 = (T)1 - c * c;
+    const T sn = s2 > (T)0 ? msqrt(s2) : (T)0;
+    T sp, cp;
+    sc((T)6.283185307179586476925286766559 * ub, &sp, &cp);
+    d[0] = c;
+    d[1] = sn * cp;
+    d[2] = sn * sp;
+}
+
+template <typename T>
+__device__ __forceinline__ void three_normals(uint4 w, T z[3])
+{
+    T u1 = (T)u01d(w.x), u2 = (T)u01d(w.y), u3 = (T)u01d(w.z), u4 = (T)u01d(w.w);
+    const T r1 = msqrt((T)-2 * mlog(u1)), r2 = msqrt((T)-2 * mlog(u3));
+    T s1, c1, s2, c2;
+    sc((T)6.283185307179586476925286766559 * u2, &s1, &c1);
+    sc((T)6.283185307179586476925286766559 * u4, &s2, &c2);
+    z[0] = r1 * c1;
+    z[1] = r1 * s1;
+    z[2] = r2 * c2;
+}
+
+// Null-collision decision (FP64, no contraction: identical to the reference for identical
+// inputs) and scattering kinematics (in the particle precision).  Returns the channel
+// (-1 none, 0 elastic, 1 ionisation, 2 CX); on ionisation fills the new pair.
+template <bool F64>
+__device__ __forceinline__ int p_collide(const EnsC &e, const SegC &S, int s, double numax,
+                                         double pnull, uint32_t tag, PS<F64> &p, double ve[3],
+                                         double vi[3])
+{
+    using T = typename std::conditional<F64, double, float>::type;
+    const uint4 w = draw(S.seed, s, p.id, tag, 0u);
+    if (!(u01d(w.x) < pnull)) return -1;
+    const double v2 = speed2_rn((double)p.vx, (double)p.vy, (double)p.vz);
+    const double spd = __dsqrt_rn(v2);
+    const double thr = __dmul_rn(u01d(w.y), numax);
+    int chan = -1;
+    if (s == 0) {
+        const double nu_el = __dmul_rn(e.ngs_el, spd);
+        const double nu_iz =
+            (__dmul_rn(__dmul_rn(0.5, S.m), v2) >= e.eps_iz) ? __dmul_rn(e.ngs_iz, spd) : 0.0;
+        if (thr < nu_el)
+            chan = 0;
+        else if (thr < __dadd_rn(nu_el, nu_iz))
+            chan = 1;
+    } else {
+        if (thr < __dmul_rn(e.ngs_cx, spd)) chan = 2;
+    }
+    if (chan < 0) return -1;
+    if (chan == 0) {
+        T dd[3];
+        iso_dir<T>((T)u01d(w.z), (T)u01d(w.w), dd);
+        const T vs = (T)spd;
+        const T cth = ((T)p.vx * dd[0] + (T)p.vy * dd[1] + (T)p.vz * dd[2]) / vs;
+        const T f2 = (T)1 - (T)(2.0 * S.m / e.m_n) * ((T)1 - cth);
+        const T sp2 = msqrt((T)v2 * f2);
+        p.vx = sp2 * dd[0];
+        p.vy = sp2 * dd[1];
+        p.vz = sp2 * dd[2];
+    } else if (chan == 1) {
+        const uint4 w1 = draw(S.seed, s, p.id, tag, 1u);
+        const uint4 w2 = draw(S.seed, s, p.id, tag, 2u);
+        const T erem = (T)(0.5 * S.m * v2 - e.eps_iz);
+        const T u = (T)u01d(w1.x);
+        const T e1 = u * erem, e2 = ((T)1 - u) * erem;
+        T d1[3], d2[3], z[3];
+        iso_dir<T>((T)u01d(w.z), (T)u01d(w.w), d1);
+        iso_dir<T>((T)u01d(w1.y), (T)u01d(w1.z), d2);
+        const T s1 = msqrt((T)2 * e1 / (T)S.m), s2 = msqrt((T)2 * e2 / (T)S.m);
+        p.vx = s1 * d1[0];
+        p.vy = s1 * d1[1];
+        p.vz = s1 * d1[2];
+        three_normals<T>(w2, z);
+        const T vn = (T)e.vn;
+        for (int k = 0; k < 3; ++k) {
+            ve[k] = (double)(s2 * d2[k]);
+            vi[k] = (double)(vn * z[k]);
+        }
+    } else {
+        const uint4 w2 = draw(S.seed, s, p.id, tag, 2u);
+        T z[3];
+        three_normals<T>(w2, z);
+        const T vn = (T)e.vn;
+        p.vx = vn * z[0];
+        p.vy = vn * z[1];
+        p.vz = vn * z[2];
+    }
+    return chan;
+}
+
+// =======================================================================================
+// Deposit machinery (FP32 form): a wave-level segmented reduction by cell, then one LDS
+// atomic per distinct cell and wave, then one HBM atomic per window node at flush.
+// =======================================================================================
+__device__ __forceinline__ void wave_window_deposit(int key, uint32_t fq, bool depo, bool hist,
+                                                    unsigned long long *sQ, uint32_t *sH)
+{
+    const int lane = lane_id();
+    unsigned long long act = __ballot(key >= 0);
+    int it = 0;
+    while (act != 0ull && it < 8) {
+        const int leader = __ffsll((long long)act) - 1;
+        const int k = __shfl(key, leader);
+        const bool mine = (key == k) && ((act >> lane) & 1ull);
+        const unsigned long long m = __ballot(mine);
+        const uint32_t S = wave_sum_u32(mine ? fq : 0u);
+        if (lane == leader) {
+            const uint32_t c = (uint32_t)__popcll(m);
+            if (depo) {
+                atomicAdd(&sQ[k], (unsigned long long)c * 16777216ull - (unsigned long long)S);
+                atomicAdd(&sQ[k + 1], (unsigned long long)S);
+            }
+            if (hist) atomicAdd(&sH[k], c);
+        }
+        act &= ~m;
+        ++it;
+    }
+    if ((act >> lane) & 1ull) {
+        if (depo) {
+            atomicAdd(&sQ[key], 16777216ull - (unsigned long long)fq);
+            atomicAdd(&sQ[key + 1], (unsigned long long)fq);
+        }
+        if (hist) atomicAdd(&sH[key], 1u);
+    }
+}
+
+__device__ __forceinline__ uint32_t fixed_share(float off)
+{
+    return (uint32_t)__float2uint_rn(off * 16777216.0f);
+}
+
+// Direct HBM deposit of one particle (outside the window, or another segment).
+__device__ __forceinline__ void global_deposit32(const Dev &d, const SegC &S, int s, int cell,
+                                                 float off, bool hist)
+{
+    const uint32_t fq = fixed_share(off);
+    int j1 = cell + 1;
+    if (S.periodic && j1 == S.ncells) j1 = 0;
+    unsigned long long *Q = d.Qi + (int64_t)s * d.nodes_tot + S.gbase;
+    atomicAdd(Q + cell, 16777216ull - fq);
+    atomicAdd(Q + j1, (unsigned long long)fq);
+    if (hist) atomicAdd(d.cellcnt + S.cbase + cell, 1u);
+}
+
+__device__ __forceinline__ void global_deposit64(const Dev &d, const SegC &S, int s, double x,
+                                                 bool hist)
+{
+    double f;
+    const int j = (int)cell_of_x(S, x, f);
+    int j1 = j + 1;
+    if (S.periodic && j1 == S.ncells) j1 = 0;
+    double *Q = d.Qd + (int64_t)s * d.nodes_tot + S.gbase;
+    unsafeAtomicAdd(Q + j, 1.0 - f);
+    unsafeAtomicAdd(Q + j1, f);
+    if (hist) atomicAdd(d.cellcnt + S.cbase + j, 1u);
+}
+
+
+}  // namespace pic
