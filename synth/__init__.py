@@ -162,3 +162,32 @@ def random_field(e, seed=0, amp=0.5):
     j = np.arange(nn)
     E = amp * np.sin(2 * np.pi * k * j / max(nn - 1, 1) + rng.random()) + 0.1 * amp * rng.standard_normal(nn)
     return E.astype(np.float32).astype(np.float64)
+
+
+def quiet_start_state(e):
+    """Cold quiet start of one species with a sinusoidal displacement: x0 = (p + 1/2) L / P
+    moved by (A / k) sin(k x0), k = 2 pi mode / L, rounded to a binary32 in-cell offset so
+    both precisions hold the same positions.  Velocities zero."""
+    N, dx = e["ncells"], e["dx"]
+    sp = e["species"][0]
+    P = sp["ppc"] * N
+    L = N * dx
+    k = 2 * math.pi * e["perturb_mode"] / L
+    x0 = (np.arange(P) + 0.5) * L / P
+    x = x0 + (e["perturb_amp"] / k) * np.sin(k * x0)
+    x = np.where(x < 0, x + L, x)
+    x = np.where(x >= L, x - L, x)
+    g = x / dx
+    cell = np.floor(g).astype(np.int64)
+    off = (g - cell).astype(np.float32).astype(np.float64)
+    bump = off >= 1.0
+    off[bump] = 0.0
+    cell[bump] += 1
+    cell[cell >= N] -= N
+    z = np.zeros(P)
+    return [{"x": (cell + off) * dx, "vx": z.copy(), "vy": z.copy(), "vz": z.copy(),
+             "id": np.arange(P, dtype=np.uint32), "next_id": P}]
+
+
+def rademacher(n, seed=0):
+    return np.random.default_rng(seed).choice([-1.0, 1.0], size=n)
