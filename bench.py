@@ -31,7 +31,7 @@ B_ALG_NODE = 16.0              # two species' int64 charge sums per node
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("pic_kernels.hip", "pic_device.h"):
+    for f in ("pic_pass32.hip", "pic_particle.h", "pic_device.h"):
         with open(os.path.join(ROOT, "paper_2606_28534_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -48,6 +48,17 @@ def traffic_from_profiles(workload_name, pushes_per_launch):
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
     return rec.get("bytes_per_launch")
+
+
+def tuned_shape(pic, work, trial_steps):
+    """Launch shape chosen by the library's autotuner on a throw-away run of the workload."""
+    if trial_steps <= 0:
+        return {}
+    t = pic.Sim(work, fused=True)
+    shape = t.autotune(trial_steps)
+    t.close()
+    del t
+    return shape
 
 
 def cpu_baseline(seed, steps):
@@ -69,6 +80,53 @@ def cpu_baseline(seed, steps):
                       f"{pushes} pushes in {t1 - t0:.1f} s, FP64, one host thread"}
 
 
+def batched_run(pic, shape, steps):
+    """The 64-ensemble batched workload (uneven sizes, one launch per stage for all
+    ensembles), FP32 fused pass in a HIP graph, at the particle-pass launch shape of the
+    main workload."""
+    import torch
+
+    import synth
+
+    work = synth.c3_batched()
+    sim = pic.Sim(work, fused=True, **shape)
+    n_ens = len(work["ensembles"])
+    sim.step(20)
+    torch.cuda.synchronize()
+    p0 = sum(sim.diag(k)["pushes"] for k in range(n_ens))
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    p1 = sum(sim.diag(k)["pushes"] for k in range(n_ens))
+    particles = sum(2 * e["species"][0]["ppc"] * e["ncells"] for e in work["ensembles"])
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return {"value": (p1 - p0) / (t1 - t0), "unit": "particle-pushes/s", "steps": steps,
+            "ms_per_step": (t1 - t0) / steps * 1e3, "ensembles": n_ens, "particles": particles,
+            "cells": sum(e["ncells"] for e in work["ensembles"])}
+
+
+def stream_copy_gbs(torch, gib=4.0, reps=10):
+    """Device-to-device copy bandwidth of a plain torch copy on the same GPU (read + write
+    bytes per second), for context next to the HBM peak."""
+    n = int(gib * (1 << 30)) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"gbs": round(2 * n * 4 / (ms * 1e-3) / 1e9, 1), "bytes": 2 * n * 4, "ms": round(ms, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +138,15 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--ncells", type=int, default=100_000)
     ap.add_argument("--ppc", type=int, default=200)
+    ap.add_argument("--separate", action="store_true",
+                    help="profile the FP32 form with one kernel per stage instead of the fused pass")
+    ap.add_argument("--tune-steps", type=int, default=6,
+                    help="trial steps per candidate launch shape of the autotuner (0 = defaults)")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=40)
+    ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--calib-copy-gib", type=float, default=0.0,
+                    help="also run one elementwise copy of this many GiB (counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -97,8 +164,8 @@ def main():
     torch.cuda.set_device(0)
     work = synth.c2_sheath(seed=args.seed, ncells=args.ncells, ppc=args.ppc)
     e = work["ensembles"][0]
-    sim = pic.Sim(work, fused=True)
-    stream = sim.stream
+    shape = tuned_shape(pic, work, args.tune_steps)
+    sim = pic.Sim(work, fused=not args.separate, **shape)
 
     # warm-up (graph capture happens here)
     sim.step(args.warmup)
@@ -131,7 +198,7 @@ def main():
     traffic = traffic_from_profiles("sheath_1e5", pass_pushes)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_particles<fp32, push|collide|deposit>",
+                "kernel": "k_pass32<push|collide|deposit>",
                 "avg_launch_ms": round(avg_ms, 5), "bytes_alg_per_launch": bytes_per_launch,
                 "launches_timed": launches}
     step_bytes = (B_ALG_PARTICLE + 48.0 / e["sort_every"]) * (pushes / args.steps)
@@ -158,7 +225,22 @@ def main():
         del psim
         torch.cuda.empty_cache()
 
+    batched = None
+    if not args.no_batched:
+        batched = batched_run(pic, shape, args.batched_steps)
+
+    stream = None
+    if not args.no_stream:
+        stream = stream_copy_gbs(torch)
+
     cpu = None if args.no_cpu else cpu_baseline(args.seed, args.cpu_steps)
+    if args.calib_copy_gib > 0:
+        n = int(args.calib_copy_gib * (1 << 30)) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
 
     out = {
         "metric": "particle-pushes/s per full step at 1 MI355X",
@@ -170,10 +252,13 @@ def main():
         "config": {"workload": f"sheath slab {e['ncells']} cells x {e['species'][0]['ppc']} ppc x 2 species, "
                                f"oblique B, 3 collision channels, sort every {e['sort_every']}",
                    "particles": 2 * e["species"][0]["ppc"] * e["ncells"], "seed": args.seed,
-                   "form": "FP32 cell+offset, fused pass, HIP graph", "parallelism": "single GPU"},
+                   "form": "FP32 cell+offset, fused pass, HIP graph", "parallelism": "single GPU",
+                   "launch_shape": shape},
         "roofline": roofline,
         "whole_step": whole_step,
         "plain": plain,
+        "batched": batched,
+        "stream_copy": stream,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -87,6 +87,8 @@ typedef struct {
     int32_t block;       /* threads per block for particle kernels; 0 = default            */
     int32_t grid;        /* persistent blocks for particle kernels; 0 = default            */
     int32_t window;      /* LDS deposit window in nodes (power of two); 0 = default        */
+    int32_t ppt;         /* particles per thread of the FP32 pass (4 or 8); 0 = default    */
+    int32_t sort_ppt;    /* particles per thread of the FP32 sort scatter; 0 = default     */
     const pic_ensemble_desc *ens;              /* [n_ensembles], copied by pic_init       */
 } pic_config;
 
@@ -185,6 +187,34 @@ int pic_set_step(pic_ctx *ctx, int64_t step);
 
 /* Node count of ensemble `ens` (N+1 bounded, N periodic), or a negative error. */
 int64_t pic_nnodes(const pic_ctx *ctx, int32_t ens);
+
+/* Set the uniform external field E_ext of ensemble `ens` (added at the gather). */
+int pic_set_external_field(pic_ctx *ctx, int32_t ens, double E_ext);
+
+/* Scratch bytes pic_adjoint_window needs for `nsteps` steps with a checkpoint every
+ * `ckpt_every` steps (caller-allocated device memory). */
+int pic_adjoint_query(pic_ctx *ctx, int32_t nsteps, int32_t ckpt_every, size_t *bytes);
+
+/* Hand-written discrete adjoint of the collisionless push + deposit + Poisson window
+ * (reading R20): runs `nsteps` steps from the current state, computes the field energy
+ * W = 1/2 eps0 dx sum_j E_j^2 at the final positions, and the exact gradients of that
+ * discrete forward (cell index held locally constant) with respect to the initial x
+ * velocities and to the uniform external field.  Checkpoints every `ckpt_every` steps and
+ * recomputes each segment forward before its reverse sweep.  Requires one ensemble, one
+ * periodic species, no collisions, B = 0 and the FP32 form; no sort runs inside the
+ * window.  dW_dvx (host, length >= particle count) is indexed by particle id.  On return
+ * the particle state is the final state of the window.  Synchronises `stream`. */
+int pic_adjoint_window(pic_ctx *ctx, int32_t nsteps, int32_t ckpt_every, void *scratch,
+                       size_t bytes, double *W, double *dW_dvx, int64_t dvx_len,
+                       double *dW_dEext, void *stream);
+
+/* The library's autotuner: times the particle pass over `trial_steps` steps for every
+ * candidate launch shape (particles per thread x LDS window) and the sort scatter for each
+ * particles-per-thread choice, all with HIP events on `stream`, keeps the fastest, and
+ * writes {ppt, window, sort_ppt} to `shape` (may be NULL).  The trial steps advance the
+ * run like pic_step (the sort is repeated on already-sorted data, which leaves the state
+ * unchanged apart from slot order). */
+int pic_autotune(pic_ctx *ctx, int32_t trial_steps, int32_t *shape, void *stream);
 
 /* Measurement hook: with `enable` != 0, pic_step runs its steps without the graph and
  * brackets every particle-pass launch with HIP events recorded on the caller's stream

@@ -22,7 +22,8 @@ PIC_ABSORBING, PIC_PERIODIC = 0, 1
 EXPORTS = ("pic_query_workspace", "pic_init", "pic_deposit", "pic_solve", "pic_push",
            "pic_collide", "pic_sort", "pic_step", "pic_diag", "pic_get_particles",
            "pic_get_slots", "pic_set_particles", "pic_get_grid", "pic_set_fields", "pic_set_step",
-           "pic_nnodes", "pic_timing", "pic_timing_read", "pic_free", "pic_last_error")
+           "pic_nnodes", "pic_set_external_field", "pic_adjoint_query",
+           "pic_adjoint_window", "pic_autotune", "pic_timing", "pic_timing_read", "pic_free", "pic_last_error")
 
 
 class PicError(RuntimeError):
@@ -49,7 +50,8 @@ class Config(C.Structure):
     _fields_ = [("n_ensembles", C.c_int32), ("precision", C.c_int32), ("boundary", C.c_int32),
                 ("nspecies", C.c_int32), ("collisions", C.c_int32), ("sort_every", C.c_int32),
                 ("fused", C.c_int32), ("block", C.c_int32), ("grid", C.c_int32),
-                ("window", C.c_int32), ("ens", C.POINTER(EnsembleDesc))]
+                ("window", C.c_int32), ("ppt", C.c_int32), ("sort_ppt", C.c_int32),
+                ("ens", C.POINTER(EnsembleDesc))]
 
 
 class DiagOut(C.Structure):
@@ -105,6 +107,11 @@ def load_library():
     L.pic_set_step.argtypes = [P, C.c_int64]
     L.pic_nnodes.argtypes = [P, C.c_int32]
     L.pic_nnodes.restype = C.c_int64
+    L.pic_set_external_field.argtypes = [P, C.c_int32, C.c_double]
+    L.pic_adjoint_query.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]
+    L.pic_adjoint_window.argtypes = [P, C.c_int32, C.c_int32, P, C.c_size_t, C.POINTER(C.c_double),
+                                     P, C.c_int64, C.POINTER(C.c_double), P]
+    L.pic_autotune.argtypes = [P, C.c_int32, P, P]
     L.pic_timing.argtypes = [P, C.c_int32]
     L.pic_timing_read.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64), P]
     L.pic_free.argtypes = [P]
@@ -115,7 +122,7 @@ def load_library():
     return L
 
 
-def make_config(work, fused=True, precision=None, block=0, grid=0, window=0):
+def make_config(work, fused=True, precision=None, block=0, grid=0, window=0, ppt=0, sort_ppt=0):
     """Translate a workload dict ({"ensembles": [...], "precision": "fp32"|"fp64"}) into
     the C configuration.  Returns (Config, keep-alive array)."""
     ens = work["ensembles"]
@@ -142,7 +149,7 @@ def make_config(work, fused=True, precision=None, block=0, grid=0, window=0):
     cfg.collisions = int(e0["collisions"])
     cfg.sort_every = e0["sort_every"]
     cfg.fused = int(fused)
-    cfg.block, cfg.grid, cfg.window = block, grid, window
+    cfg.block, cfg.grid, cfg.window, cfg.ppt, cfg.sort_ppt = block, grid, window, ppt, sort_ppt
     cfg.ens = arr
     return cfg, arr
 
@@ -154,12 +161,13 @@ def _ptr(a):
 class Sim:
     """One run of the PIC MC hot path on the current GPU (torch provides the memory)."""
 
-    def __init__(self, work, fused=True, precision=None, block=0, grid=0, window=0, stream=None):
+    def __init__(self, work, fused=True, precision=None, block=0, grid=0, window=0, ppt=0,
+                 sort_ppt=0, stream=None):
         import torch
 
         self.L = load_library()
         self.work = work
-        self.cfg, self._arr = make_config(work, fused, precision, block, grid, window)
+        self.cfg, self._arr = make_config(work, fused, precision, block, grid, window, ppt, sort_ppt)
         nbytes = C.c_size_t(0)
         self._check(self.L.pic_query_workspace(C.byref(self.cfg), C.byref(nbytes)), None)
         self.ws_bytes = nbytes.value
@@ -209,6 +217,32 @@ class Sim:
 
     def step(self, n=1):
         self._check(self.L.pic_step(self.h, int(n), self._s()))
+
+    def set_external_field(self, E_ext, ens=0):
+        self._check(self.L.pic_set_external_field(self.h, int(ens), float(E_ext)))
+
+    def adjoint_window(self, nsteps, ckpt_every=20):
+        """Run the collisionless window with its hand-written adjoint.  Returns
+        (W, dW/dv_x0 indexed by particle id, dW/dE_ext)."""
+        import torch
+
+        nb = C.c_size_t(0)
+        self._check(self.L.pic_adjoint_query(self.h, int(nsteps), int(ckpt_every), C.byref(nb)))
+        scratch = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+        cap = int(self.work["ensembles"][0]["species"][0]["capacity"])
+        g = np.zeros(cap)
+        W, gE = C.c_double(0), C.c_double(0)
+        self._check(self.L.pic_adjoint_window(self.h, int(nsteps), int(ckpt_every),
+                                              C.c_void_p(scratch.data_ptr()), nb.value, C.byref(W),
+                                              _ptr(g), cap, C.byref(gE), self._s()))
+        del scratch
+        return W.value, g, gE.value
+
+    def autotune(self, trial_steps=10):
+        """Let the library time its launch shapes and keep the fastest; returns the shape."""
+        shape = np.zeros(3, dtype=np.int32)
+        self._check(self.L.pic_autotune(self.h, int(trial_steps), _ptr(shape), self._s()))
+        return {"ppt": int(shape[0]), "window": int(shape[1]), "sort_ppt": int(shape[2])}
 
     def timing(self, enable=True):
         self._check(self.L.pic_timing(self.h, int(bool(enable))))
@@ -276,3 +310,38 @@ class Sim:
         E = np.ascontiguousarray(E, dtype=np.float64)
         assert len(E) == self.nnodes(ens)
         self._check(self.L.pic_set_fields(self.h, int(ens), _ptr(E), self._s()))
+
+
+def _picwindow():
+    import torch
+
+    class PicWindow(torch.autograd.Function):
+        """Field energy W after `nsteps` collisionless steps as a function of the initial
+        x velocities (indexed by particle id) and the uniform external field, with the
+        gradient from the library's hand-written discrete adjoint."""
+
+        @staticmethod
+        def forward(ctx, vx0, E_ext, sim, state, nsteps, ckpt_every):
+            v = vx0.detach().to("cpu", torch.float64).numpy()
+            ids = state["id"]
+            sim.set_external_field(float(E_ext))
+            sim.set_particles(0, 0, state["x"], v[ids], state["vy"], state["vz"], ids, state["next_id"])
+            sim.set_step(0)
+            W, g, gE = sim.adjoint_window(int(nsteps), int(ckpt_every))
+            n = vx0.shape[0]
+            ctx.save_for_backward(torch.as_tensor(g[:n], dtype=vx0.dtype, device=vx0.device),
+                                  torch.as_tensor(gE, dtype=E_ext.dtype, device=E_ext.device))
+            return torch.as_tensor(W, dtype=vx0.dtype, device=vx0.device)
+
+        @staticmethod
+        def backward(ctx, gW):
+            g, gE = ctx.saved_tensors
+            return gW * g, gW * gE, None, None, None, None
+
+    return PicWindow
+
+
+def __getattr__(name):
+    if name == "PicWindow":
+        return _picwindow()
+    raise AttributeError(name)

@@ -149,7 +149,7 @@ int build_plan(const pic_config *cfg, Plan &P, std::string &msg)
     P.cells_tot = cbase;
     P.chunks_tot = chunk0;
     P.bm_words = bm;
-    P.l1_tot = l1 + 1;
+    P.l1_tot = (l1 + 1 + 4095) / 4096 * 4096;  // single-block scan reads 4096-entry tiles
     P.birth_stripe_cap = std::max<int64_t>(4096, (int64_t)std::ceil(4e-3 * (double)ecap / kStripes));
     P.scanpart = std::max(scan_blocks(P.l1_tot), scan_blocks(P.cells_tot)) + 1;
     return PIC_OK;
@@ -216,12 +216,15 @@ size_t carve(const Plan &P, char *base, Dev &d)
     d.cnt = c.take<unsigned long long>((int64_t)kStripes * P.nseg * C_NCNT);
     d.sums = c.take<double>((int64_t)kStripes * P.nseg * S_NSUM);
     d.birth_stripe_cap = P.birth_stripe_cap;
-    d.births = c.take<Birth>(kStripes * P.birth_stripe_cap);
-    d.nbirth = c.take<uint32_t>(kStripes);
-    d.bitmap = c.take<uint32_t>(P.bm_words);
-    d.l1cnt = c.take<uint32_t>(P.l1_tot);
+    d.births = c.take<Birth>(2 * kStripes * P.birth_stripe_cap);
+    d.nbirth = c.take<uint32_t>(2 * kStripes);
+    d.bitmap = c.take<uint32_t>(2 * P.bm_words);
+    d.bm_words = P.bm_words;
+    d.l1cnt = c.take<uint32_t>(2 * P.l1_tot);
     d.l1pre = c.take<uint32_t>(P.l1_tot);
     d.l1_tot = P.l1_tot;
+    d.cand = c.take<uint32_t>(P.cap_tot);
+    d.ctile = c.take<uint32_t>(P.cap_tot / 1024 + 1);
     d.cellcnt = c.take<uint32_t>(P.cells_tot);
     d.cursor = c.take<uint32_t>(P.cells_tot);
     d.segstart = c.take<int64_t>(P.nseg);
@@ -304,7 +307,8 @@ hipError_t enqueue_step(pic_ctx *c, hipStream_t s, bool sort_now)
             c->ev_used += 2;
         }
         if (coll) {
-            if ((e = launch_births(d, f64, true, s)) != hipSuccess) return e;
+            if ((e = launch_candidates(d, c->L, s, f64, sort_now ? 1 : 0)) != hipSuccess) return e;
+            if ((e = launch_births(d, f64, true, true, s)) != hipSuccess) return e;
         } else if ((e = launch_advance(d, s)) != hipSuccess) {
             return e;
         }
@@ -320,7 +324,8 @@ hipError_t enqueue_step(pic_ctx *c, hipStream_t s, bool sort_now)
     }
     if (coll) {
         if ((e = launch_particles(d, c->L, s, f64, SB_COLLIDE, 0)) != hipSuccess) return e;
-        if ((e = launch_births(d, f64, false, s)) != hipSuccess) return e;
+        if ((e = launch_candidates(d, c->L, s, f64, 0)) != hipSuccess) return e;
+        if ((e = launch_births(d, f64, true, false, s)) != hipSuccess) return e;
     }
     if ((e = launch_zero_q(d, f64, s)) != hipSuccess) return e;
     if ((e = launch_particles(d, c->L, s, f64, SB_DEPOSIT, 0)) != hipSuccess) return e;
@@ -358,6 +363,8 @@ Launch default_launch(const pic_config *cfg, const Plan &P)
     Launch L;
     L.block = cfg->block > 0 ? cfg->block : 256;
     L.ppt = (cfg->precision == PIC_FP32_CELLOFF) ? 8 : 4;
+    if (cfg->precision == PIC_FP32_CELLOFF && (cfg->ppt == 4 || cfg->ppt == 8)) L.ppt = cfg->ppt;
+    L.sort_ppt = (cfg->sort_ppt == 4 || cfg->sort_ppt == 8) ? cfg->sort_ppt : 4;
     int64_t tiles = 0;
     for (const SegC &S : P.seg) tiles += (S.cap + (int64_t)L.block * L.ppt - 1) / ((int64_t)L.block * L.ppt);
     int g = cfg->grid > 0 ? cfg->grid : 1024;
@@ -480,7 +487,8 @@ int pic_collide(pic_ctx *c, void *stream)
     hipStream_t s = (hipStream_t)stream;
     HIPC(c, launch_params(c->d, s));
     HIPC(c, launch_particles(c->d, c->L, s, c->P.f64, SB_COLLIDE, 0));
-    HIPC(c, launch_births(c->d, c->P.f64, false, s));
+    HIPC(c, launch_candidates(c->d, c->L, s, c->P.f64, 0));
+    HIPC(c, launch_births(c->d, c->P.f64, false, false, s));
     return PIC_OK;
 }
 
@@ -517,6 +525,9 @@ int pic_step(pic_ctx *c, int32_t nsteps, void *stream)
 int pic_set_step(pic_ctx *c, int64_t step)
 {
     if (!c || step < 0) return PIC_EINVAL;
+    // both birth halves clean, whatever parity the new step has
+    HIPC(c, launch_births_clear_all(c->d, nullptr));
+    HIPC(c, hipDeviceSynchronize());
     HIPC(c, hipMemcpy(c->d.step, &step, sizeof(step), hipMemcpyHostToDevice));
     c->host_step = step;
     return PIC_OK;
@@ -787,6 +798,302 @@ int pic_set_fields(pic_ctx *c, int32_t ens, const double *E, void *stream)
     HIPC(c, launch_field_stats(c->d, c->P.f64, c->P.chunks_tot, s));
     HIPC(c, hipStreamSynchronize(s));
     return PIC_OK;
+}
+
+int pic_set_external_field(pic_ctx *c, int32_t ens, double E_ext)
+{
+    if (!c || ens < 0 || ens >= c->P.nens || !std::isfinite(E_ext)) return PIC_EINVAL;
+    c->P.ens[ens].E_ext = E_ext;
+    c->ens[ens].E_ext = E_ext;
+    HIPC(c, hipMemcpy((void *)(c->d.ens + ens), &c->P.ens[ens], sizeof(EnsC), hipMemcpyHostToDevice));
+    return PIC_OK;
+}
+
+namespace {
+
+struct AdjLayout {
+    int64_t n, nn, nseg_ck, K;
+    size_t off_ck_cell, off_ck_off, off_ck_vx, off_xc, off_xo, off_E, off_lx, off_lv, off_lE, off_lQ,
+        off_tmp, off_ext, off_fin, bytes;
+};
+
+int adj_check(pic_ctx *c, std::string &why)
+{
+    if (c->P.nens != 1 || c->P.nspecies != 1) why = "adjoint needs one ensemble and one species";
+    else if (!c->d.periodic) why = "adjoint needs a periodic domain";
+    else if (c->cfg.collisions) why = "adjoint needs a collisionless run";
+    else if (c->P.f64) why = "adjoint is defined on the FP32 form";
+    else {
+        const SegC &S = c->P.seg[0];
+        if (S.t[0] != 0.0 || S.t[1] != 0.0 || S.t[2] != 0.0) why = "adjoint needs B = 0";
+        else return PIC_OK;
+    }
+    return PIC_EINVAL;
+}
+
+AdjLayout adj_layout(pic_ctx *c, int nsteps, int K)
+{
+    AdjLayout A{};
+    A.n = c->P.seg[0].cap;
+    A.nn = c->P.ens[0].nnodes;
+    A.K = K;
+    A.nseg_ck = (nsteps + K - 1) / K;
+    size_t o = 0;
+    auto take = [&](size_t b) {
+        size_t r = o;
+        o += align_up(std::max<size_t>(b, 1));
+        return r;
+    };
+    A.off_ck_cell = take((size_t)A.nseg_ck * A.n * 4);
+    A.off_ck_off = take((size_t)A.nseg_ck * A.n * 4);
+    A.off_ck_vx = take((size_t)A.nseg_ck * A.n * 4);
+    A.off_xc = take((size_t)K * A.n * 4);
+    A.off_xo = take((size_t)K * A.n * 4);
+    A.off_E = take((size_t)K * A.nn * 8);
+    A.off_lx = take((size_t)A.n * 8);
+    A.off_lv = take((size_t)A.n * 8);
+    A.off_lE = take((size_t)A.nn * 8);
+    A.off_lQ = take((size_t)A.nn * 8);
+    A.off_tmp = take((size_t)A.nn * 8);
+    A.off_ext = take(64);
+    A.off_fin = take((size_t)A.n * 4 * 5);  // final state: cell, off, vx, vy, vz
+    A.bytes = o;
+    return A;
+}
+
+// One forward step of the window (no sort, no collisions); optionally records x^n and E^n.
+hipError_t adj_forward_step(pic_ctx *c, hipStream_t s, int32_t *xc, float *xo, double *E)
+{
+    const Dev &d = c->d;
+    const int64_t n = c->P.seg[0].cap;
+    hipError_t e;
+    if (xc) {
+        if ((e = hipMemcpyAsync(xc, d.cell[0], n * 4, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(xo, d.off[0], n * 4, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+    }
+    if ((e = launch_solve(d, false, c->P.chunks_tot, true, s)) != hipSuccess) return e;
+    if (E && (e = hipMemcpyAsync(E, d.E, c->P.ens[0].nnodes * 8, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+        return e;
+    if ((e = launch_particles(d, c->L, s, false, SB_PUSH | SB_DEPOSIT, 0)) != hipSuccess) return e;
+    return launch_advance(d, s);
+}
+
+}  // namespace
+
+int pic_adjoint_query(pic_ctx *c, int32_t nsteps, int32_t ckpt_every, size_t *bytes)
+{
+    if (!c || !bytes || nsteps < 1 || ckpt_every < 1) return PIC_EINVAL;
+    std::string why;
+    if (adj_check(c, why)) return fail(c, PIC_EINVAL, why);
+    *bytes = adj_layout(c, nsteps, ckpt_every).bytes;
+    return PIC_OK;
+}
+
+int pic_adjoint_window(pic_ctx *c, int32_t nsteps, int32_t ckpt_every, void *scratch, size_t bytes,
+                       double *W, double *dW_dvx, int64_t dvx_len, double *dW_dEext, void *stream)
+{
+    if (!c || !scratch || nsteps < 1 || ckpt_every < 1 || !W || !dW_dvx || !dW_dEext) return PIC_EINVAL;
+    std::string why;
+    if (adj_check(c, why)) return fail(c, PIC_EINVAL, why);
+    const AdjLayout A = adj_layout(c, nsteps, ckpt_every);
+    if (bytes < A.bytes) return fail(c, PIC_EINVAL, "adjoint scratch too small");
+    hipStream_t s = (hipStream_t)stream;
+    Dev &d = c->d;
+    char *base = (char *)scratch;
+    int32_t *ck_cell = (int32_t *)(base + A.off_ck_cell);
+    float *ck_off = (float *)(base + A.off_ck_off);
+    float *ck_vx = (float *)(base + A.off_ck_vx);
+    int32_t *xc = (int32_t *)(base + A.off_xc);
+    float *xo = (float *)(base + A.off_xo);
+    double *Eb = (double *)(base + A.off_E);
+    double *lx = (double *)(base + A.off_lx);
+    double *lv = (double *)(base + A.off_lv);
+    double *lE = (double *)(base + A.off_lE);
+    double *lQ = (double *)(base + A.off_lQ);
+    double *tmp = (double *)(base + A.off_tmp);
+    double *lext = (double *)(base + A.off_ext);
+    char *fin = base + A.off_fin;
+    const int64_t n = A.n, nn = A.nn;
+    const int N = (int)c->P.ens[0].ncells;
+    const SegC &S = c->P.seg[0];
+    const EnsC &En = c->P.ens[0];
+    const double qm = S.h * 2.0 / En.dt;  // q/m
+    // the particle buffer must be buffer 0 and hold no absorbed slots (periodic, no sort here)
+    int32_t b = 0;
+    int64_t nslots = 0;
+    HIPC(c, hipMemcpyAsync(&b, d.cur, 4, hipMemcpyDeviceToHost, s));
+    HIPC(c, hipMemcpyAsync(&nslots, d.n_slots, 8, hipMemcpyDeviceToHost, s));
+    HIPC(c, hipStreamSynchronize(s));
+    if (b != 0) {
+        // move the live buffer to buffer 0 so the recorded pointers stay valid
+        for (int k = 0; k < 5; ++k) {
+            void *dst = k == 0 ? (void *)d.cell[0] : k == 1 ? (void *)d.off[0] : k == 2 ? (void *)d.fvx[0] : k == 3 ? (void *)d.fvy[0] : (void *)d.fvz[0];
+            void *src = k == 0 ? (void *)d.cell[1] : k == 1 ? (void *)d.off[1] : k == 2 ? (void *)d.fvx[1] : k == 3 ? (void *)d.fvy[1] : (void *)d.fvz[1];
+            HIPC(c, hipMemcpyAsync(dst, src, n * 4, hipMemcpyDeviceToDevice, s));
+        }
+        HIPC(c, hipMemcpyAsync(d.id[0], d.id[1], n * 4, hipMemcpyDeviceToDevice, s));
+        const int32_t zero = 0;
+        HIPC(c, hipMemcpyAsync(d.cur, &zero, 4, hipMemcpyHostToDevice, s));
+        HIPC(c, hipStreamSynchronize(s));
+    }
+    if (dvx_len < nslots) return fail(c, PIC_EINVAL, "dW_dvx too short");
+    int64_t step0 = 0;
+    HIPC(c, hipMemcpy(&step0, d.step, 8, hipMemcpyDeviceToHost));
+    // Q^0 from the current positions (they may have been injected)
+    HIPC(c, launch_zero_q(d, false, s));
+    HIPC(c, launch_particles(d, c->L, s, false, SB_DEPOSIT, 0));
+    // forward with checkpoints
+    for (int t = 0; t < nsteps; ++t) {
+        if (t % ckpt_every == 0) {
+            const int64_t k = t / ckpt_every;
+            HIPC(c, hipMemcpyAsync(ck_cell + k * n, d.cell[0], n * 4, hipMemcpyDeviceToDevice, s));
+            HIPC(c, hipMemcpyAsync(ck_off + k * n, d.off[0], n * 4, hipMemcpyDeviceToDevice, s));
+            HIPC(c, hipMemcpyAsync(ck_vx + k * n, d.fvx[0], n * 4, hipMemcpyDeviceToDevice, s));
+        }
+        HIPC(c, adj_forward_step(c, s, nullptr, nullptr, nullptr));
+    }
+    // objective at the final positions
+    HIPC(c, launch_solve(d, false, c->P.chunks_tot, false, s));
+    double fe = 0.0;
+    HIPC(c, hipMemcpyAsync(&fe, d.fe, 8, hipMemcpyDeviceToHost, s));
+    // keep the final state
+    HIPC(c, hipMemcpyAsync(fin, d.cell[0], n * 4, hipMemcpyDeviceToDevice, s));
+    HIPC(c, hipMemcpyAsync(fin + n * 4, d.off[0], n * 4, hipMemcpyDeviceToDevice, s));
+    HIPC(c, hipMemcpyAsync(fin + n * 8, d.fvx[0], n * 4, hipMemcpyDeviceToDevice, s));
+    HIPC(c, hipMemcpyAsync(fin + n * 12, d.fvy[0], n * 4, hipMemcpyDeviceToDevice, s));
+    HIPC(c, hipMemcpyAsync(fin + n * 16, d.fvz[0], n * 4, hipMemcpyDeviceToDevice, s));
+    // seed: lE = eps0 dx E^N -> lQ -> lx; lv = 0
+    HIPC(c, hipMemsetAsync(lx, 0, n * 8, s));
+    HIPC(c, hipMemsetAsync(lv, 0, n * 8, s));
+    HIPC(c, hipMemsetAsync(lE, 0, nn * 8, s));
+    HIPC(c, hipMemsetAsync(lext, 0, 8, s));
+    HIPC(c, launch_adj_seed(d.E, lE, N, En.eps0, En.dx, s));
+    HIPC(c, launch_adj_grid(lE, lQ, tmp, N, En.dx, En.eps0, S.qw, s));
+    HIPC(c, launch_adj_b(d.cell[0], lQ, lx, nslots, En.dx, N, s));
+    // reverse sweep, one checkpoint segment at a time
+    for (int64_t k = A.nseg_ck - 1; k >= 0; --k) {
+        const int t0 = (int)(k * ckpt_every), t1 = std::min(nsteps, t0 + ckpt_every);
+        HIPC(c, hipMemcpyAsync(d.cell[0], ck_cell + k * n, n * 4, hipMemcpyDeviceToDevice, s));
+        HIPC(c, hipMemcpyAsync(d.off[0], ck_off + k * n, n * 4, hipMemcpyDeviceToDevice, s));
+        HIPC(c, hipMemcpyAsync(d.fvx[0], ck_vx + k * n, n * 4, hipMemcpyDeviceToDevice, s));
+        const int64_t st = step0 + t0;
+        HIPC(c, hipMemcpyAsync(d.step, &st, 8, hipMemcpyHostToDevice, s));
+        HIPC(c, launch_zero_q(d, false, s));
+        HIPC(c, launch_particles(d, c->L, s, false, SB_DEPOSIT, 0));
+        for (int t = t0; t < t1; ++t)
+            HIPC(c, adj_forward_step(c, s, xc + (int64_t)(t - t0) * n, xo + (int64_t)(t - t0) * n,
+                                     Eb + (int64_t)(t - t0) * nn));
+        for (int t = t1 - 1; t >= t0; --t) {
+            const int32_t *cx = xc + (int64_t)(t - t0) * n;
+            const float *ox = xo + (int64_t)(t - t0) * n;
+            HIPC(c, launch_adj_a(d, cx, ox, Eb + (int64_t)(t - t0) * nn, lx, lv, lE, lext, nslots, En.dt,
+                                 qm, En.dx, N, s));
+            HIPC(c, launch_adj_grid(lE, lQ, tmp, N, En.dx, En.eps0, S.qw, s));
+            HIPC(c, launch_adj_b(cx, lQ, lx, nslots, En.dx, N, s));
+        }
+        HIPC(c, hipStreamSynchronize(s));
+    }
+    // restore the final state and step count
+    HIPC(c, hipMemcpyAsync(d.cell[0], fin, n * 4, hipMemcpyDeviceToDevice, s));
+    HIPC(c, hipMemcpyAsync(d.off[0], fin + n * 4, n * 4, hipMemcpyDeviceToDevice, s));
+    HIPC(c, hipMemcpyAsync(d.fvx[0], fin + n * 8, n * 4, hipMemcpyDeviceToDevice, s));
+    HIPC(c, hipMemcpyAsync(d.fvy[0], fin + n * 12, n * 4, hipMemcpyDeviceToDevice, s));
+    HIPC(c, hipMemcpyAsync(d.fvz[0], fin + n * 16, n * 4, hipMemcpyDeviceToDevice, s));
+    const int64_t stN = step0 + nsteps;
+    HIPC(c, hipMemcpyAsync(d.step, &stN, 8, hipMemcpyHostToDevice, s));
+    c->host_step = stN;
+    HIPC(c, launch_zero_q(d, false, s));
+    HIPC(c, launch_particles(d, c->L, s, false, SB_DEPOSIT, 0));
+    // gradients by id
+    std::vector<double> glv(nslots);
+    std::vector<uint32_t> ids(nslots);
+    double gext = 0.0;
+    HIPC(c, hipMemcpyAsync(glv.data(), lv, nslots * 8, hipMemcpyDeviceToHost, s));
+    HIPC(c, hipMemcpyAsync(ids.data(), d.id[0], nslots * 4, hipMemcpyDeviceToHost, s));
+    HIPC(c, hipMemcpyAsync(&gext, lext, 8, hipMemcpyDeviceToHost, s));
+    HIPC(c, hipStreamSynchronize(s));
+    for (int64_t i = 0; i < nslots; ++i) {
+        if ((int64_t)ids[i] >= dvx_len) return fail(c, PIC_EINVAL, "particle id beyond dW_dvx");
+        dW_dvx[ids[i]] = glv[i];
+    }
+    *W = fe;
+    *dW_dEext = gext;
+    return check_err(c, s);
+}
+
+int pic_autotune(pic_ctx *c, int32_t trial_steps, int32_t *shape, void *stream)
+{
+    if (!c || trial_steps < 1) return PIC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (!c->P.f64) {
+        const int ppts[2] = {4, 8};
+        const int wins[3] = {256, 512, 1024};
+        double best = 1e300;
+        Launch bestL = c->L;
+        for (int pi = 0; pi < 2; ++pi) {
+            for (int wi = 0; wi < 3; ++wi) {
+                c->L.ppt = ppts[pi];
+                c->L.window = wins[wi];
+                // every candidate starts from freshly sorted particles
+                HIPC(c, launch_particles(c->d, c->L, s, false, SB_HIST, 0));
+                HIPC(c, launch_sort(c->d, false, c->L, s));
+                int rc = pic_timing(c, 1);
+                if (rc) return rc;
+                for (int t = 0; t < trial_steps; ++t) {
+                    HIPC(c, enqueue_step(c, s, is_sort_step(c, c->host_step + 1)));
+                    c->host_step += 1;
+                }
+                double ms = 0.0;
+                int64_t n = 0;
+                rc = pic_timing_read(c, &ms, &n, stream);
+                if (rc) return rc;
+                const double avg = n ? ms / (double)n : 1e300;
+                if (avg < best) {
+                    best = avg;
+                    bestL = c->L;
+                }
+            }
+        }
+        c->L = bestL;
+        pic_timing(c, 0);
+        // sort scatter: repeated sorts of sorted data
+        hipEvent_t e0, e1;
+        HIPC(c, hipEventCreate(&e0));
+        HIPC(c, hipEventCreate(&e1));
+        double bests = 1e300;
+        int bestp = c->L.sort_ppt;
+        for (int pi = 0; pi < 2; ++pi) {
+            c->L.sort_ppt = ppts[pi];
+            HIPC(c, launch_particles(c->d, c->L, s, false, SB_HIST, 0));
+            HIPC(c, launch_sort(c->d, false, c->L, s));
+            HIPC(c, hipEventRecord(e0, s));
+            for (int r = 0; r < 3; ++r) {
+                HIPC(c, launch_particles(c->d, c->L, s, false, SB_HIST, 0));
+                HIPC(c, launch_sort(c->d, false, c->L, s));
+            }
+            HIPC(c, hipEventRecord(e1, s));
+            HIPC(c, hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPC(c, hipEventElapsedTime(&ms, e0, e1));
+            if (ms < bests) {
+                bests = ms;
+                bestp = ppts[pi];
+            }
+        }
+        c->L.sort_ppt = bestp;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (c->graph) {
+            (void)hipGraphExecDestroy(c->graph);
+            c->graph = nullptr;
+        }
+    }
+    if (shape) {
+        shape[0] = c->L.ppt;
+        shape[1] = c->L.window;
+        shape[2] = c->L.sort_ppt;
+    }
+    return check_err(c, s);
 }
 
 int pic_timing(pic_ctx *c, int32_t enable)

@@ -107,13 +107,20 @@ struct Dev {
     int32_t *vcur;            // [1] which vmax2 half holds the current maxima
     unsigned long long *cnt;  // [kStripes][nseg][C_NCNT]
     double *sums;             // [kStripes][nseg][S_NSUM]
-    // births
-    Birth *births;            // [kStripes][birth_stripe_cap]
-    uint32_t *nbirth;         // [kStripes]
+    // births, double-buffered by step parity: step n appends to half n & 1 and its
+    // placement clears half (n + 1) & 1, which step n - 1 used
+    Birth *births;            // [2][kStripes][birth_stripe_cap]
+    uint32_t *nbirth;         // [2][kStripes]
     int64_t birth_stripe_cap;
-    uint32_t *bitmap;         // per-ensemble electron-id bitmaps
-    uint32_t *l1cnt, *l1pre;  // per-ensemble counts per 1024 ids and their scan
+    uint32_t *bitmap;         // [2][bm_words] per-ensemble electron-id bitmaps
+    int64_t bm_words;
+    uint32_t *l1cnt;          // [2][l1_tot] per-ensemble counts per 1024 ids
+    uint32_t *l1pre;          // [l1_tot] scan of the current half
     int64_t l1_tot;
+    // null-collision candidates of the FP32 pass: tile t keeps its candidate slots in
+    // cand[t * tile .. t * tile + ctile[t])
+    uint32_t *cand;           // [cap_tot]
+    uint32_t *ctile;          // [cap_tot / 1024]
     // sort
     uint32_t *cellcnt, *cursor;  // [cells_tot] over all segments (SegC::cbase)
     int64_t *segstart;        // [nseg]
@@ -136,8 +143,10 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
-        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        // one 32x32 -> 64-bit product per word (a single v_mad_u64_u32)
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
         c1 = lo1;
@@ -206,5 +215,16 @@ __device__ __forceinline__ double speed2_rn(double a, double b, double c)
 }
 
 __device__ __forceinline__ int stripe_of_block() { return (int)(blockIdx.x & (kStripes - 1)); }
+
+// One half of the birth buffers.
+struct BirthBuf {
+    Birth *births;
+    uint32_t *nbirth, *bitmap, *l1cnt;
+};
+__device__ __forceinline__ BirthBuf birth_buf(const Dev &d, int parity)
+{
+    return {d.births + (int64_t)parity * kStripes * d.birth_stripe_cap, d.nbirth + parity * kStripes,
+            d.bitmap + (int64_t)parity * d.bm_words, d.l1cnt + (int64_t)parity * d.l1_tot};
+}
 
 }  // namespace pic

@@ -12,11 +12,15 @@ struct Launch {
     int ppt;     // particles per thread per tile (1, 2, 4, 8)
     int grid;    // persistent blocks (multiple of 8 for the XCD-aware mapping)
     int window;  // LDS deposit / sort window in cells
+    int sort_ppt;  // particles per thread of the FP32 sort scatter
 };
 
 enum StageBits : int { SB_PUSH = 1, SB_COLLIDE = 2, SB_DEPOSIT = 4, SB_HIST = 8 };
 
 hipError_t launch_particles(const Dev &d, const Launch &L, hipStream_t s, bool f64, int stages, int hist);
+// After a pass with the COLLIDE stage: the FP32 form's candidate kernel (no-op for FP64,
+// whose pass scatters in place).
+hipError_t launch_candidates(const Dev &d, const Launch &L, hipStream_t s, bool f64, int hist);
 hipError_t launch_init(const Dev &d, bool f64, int sg, int64_t n, int64_t ppc, int init_mode,
                        double vth, double amp, int mode, hipStream_t s);
 hipError_t launch_vmax(const Dev &d, bool f64, hipStream_t s);
@@ -26,11 +30,21 @@ hipError_t launch_field_stats(const Dev &d, bool f64, int64_t nchunks, hipStream
 hipError_t launch_params(const Dev &d, hipStream_t s);
 hipError_t launch_scan(uint32_t *in, uint32_t *out, int64_t n, uint32_t *part, bool zero_in, hipStream_t s);
 int64_t scan_blocks(int64_t n);
-hipError_t launch_births(const Dev &d, bool f64, bool advance, hipStream_t s);
+hipError_t launch_births(const Dev &d, bool f64, bool in_step, bool advance, hipStream_t s);
 hipError_t launch_advance(const Dev &d, hipStream_t s);
+hipError_t launch_births_clear_all(const Dev &d, hipStream_t s);
 hipError_t launch_sort(const Dev &d, bool f64, const Launch &L, hipStream_t s);
 hipError_t launch_pass32(const Dev &d, int ppt, int W, hipStream_t s, int stages, int hist, int64_t cap_tot);
+hipError_t launch_cand32(const Dev &d, int ppt, hipStream_t s, int hist, int64_t cap_tot);
 hipError_t launch_sort32_scatter(const Dev &d, int ppt, int W, hipStream_t s, int64_t cap_tot);
+hipError_t launch_adj_seed(const double *E, double *lE, int N, double eps0, double dx, hipStream_t s);
+hipError_t launch_adj_a(const Dev &d, const int32_t *xc, const float *xo, const double *E, double *lx,
+                        double *lv, double *lE, double *lEext, int64_t n, double dt, double qm,
+                        double dx, int N, hipStream_t s);
+hipError_t launch_adj_grid(double *lE, double *lQ, double *tmp, int N, double dx, double eps0, double qw,
+                           hipStream_t s);
+hipError_t launch_adj_b(const int32_t *xc, const double *lQ, double *lx, int64_t n, double dx, int N,
+                        hipStream_t s);
 hipError_t launch_diag(const Dev &d, bool f64, int sg, double *out, int grid, hipStream_t s);
 
 }  // namespace pic

@@ -289,9 +289,10 @@ __global__ void __launch_bounds__(256) k_particles(Dev d, int W, int hist_rt)
                     else if (ch == 1) {
                         ++tal.iz;
                         // birth record: slot in this block's stripe
-                        const uint32_t slot = atomicAdd(d.nbirth + st, 1u);
+                        const BirthBuf bb = birth_buf(d, (int)(tag & 1u));
+                        const uint32_t slot = atomicAdd(bb.nbirth + st, 1u);
                         if ((int64_t)slot < d.birth_stripe_cap) {
-                            Birth &B = d.births[(int64_t)st * d.birth_stripe_cap + slot];
+                            Birth &B = bb.births[(int64_t)st * d.birth_stripe_cap + slot];
                             B.pid = p[k].id;
                             B.ens = S.ens;
                             if constexpr (!F64) {
@@ -307,8 +308,8 @@ __global__ void __launch_bounds__(256) k_particles(Dev d, int W, int hist_rt)
                                 B.ve[q] = ve[q];
                                 B.vi[q] = vi[q];
                             }
-                            atomicOr(d.bitmap + e.bm_base + (p[k].id >> 5), 1u << (p[k].id & 31));
-                            atomicAdd(d.l1cnt + e.l1_base + (p[k].id >> 10), 1u);
+                            atomicOr(bb.bitmap + e.bm_base + (p[k].id >> 5), 1u << (p[k].id & 31));
+                            atomicAdd(bb.l1cnt + e.l1_base + (p[k].id >> 10), 1u);
                         } else {
                             atomicOr(d.err, (int)E_CAP_BIRTH);
                         }
@@ -535,6 +536,27 @@ __device__ double block_sum(double v, double *s_buf)
     return r;
 }
 
+// N block-wide sums at once (one LDS round); same summation order as block_sum.
+template <int N>
+__device__ void block_sums(double (&v)[N], double *s /* N * 16 doubles */)
+{
+    const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = wave_sum_f64(v[i]);
+    if (lane_id() == 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) s[i * 16 + w] = v[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        double r = 0.0;
+        for (int k = 0; k < nw; ++k) r += s[i * 16 + k];
+        v[i] = r;
+    }
+    __syncthreads();
+}
+
 __device__ __forceinline__ int chunk_ens(const Dev &d, int64_t k)
 {
     int lo = 0, hi = d.nens;
@@ -600,39 +622,42 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve1(Dev d)
         }
         (void)runc;
     }
-    const double A = block_sum(loc, s_buf);
-    const double B = block_sum(sumpre, s_buf);
-    const double TQ = block_sum(totq, s_buf);
-    const double N1 = block_sum(n1, s_buf);
-    const double D = block_sum(dd, s_buf);
-    const double CN = block_sum(cnt, s_buf);
+    __shared__ double s_red[6 * 16];
+    double v[6] = {loc, sumpre, totq, n1, dd, cnt};
+    block_sums<6>(v, s_red);
     if (threadIdx.x == 0) {
         double *g = d.agg + k * A_NAGG;
-        g[A_SUMRHO] = A;
-        g[A_SUMPRE] = B;
-        g[A_TOTQ] = TQ;
-        g[A_N1] = N1;
-        g[A_D] = D;
-        g[A_CNT] = CN;
+        g[A_SUMRHO] = v[0];
+        g[A_SUMPRE] = v[1];
+        g[A_TOTQ] = v[2];
+        g[A_N1] = v[3];
+        g[A_D] = v[4];
+        g[A_CNT] = v[5];
     }
 }
 
 // Reading R11: per-segment null-collision bound from the current max speed and max field.
+// One wave per segment; lanes read the striped speed maxima.
 __device__ void compute_params(const Dev &d)
 {
-    for (int sg = threadIdx.x; sg < d.nseg; sg += blockDim.x) {
+    const int nw = blockDim.x / kWave, w = threadIdx.x / kWave, lane = lane_id();
+    const int half = *d.vcur;
+    for (int sg = w; sg < d.nseg; sg += nw) {
         const SegC &S = d.seg[sg];
         const EnsC &e = d.ens[S.ens];
-        const int half = *d.vcur;
-        unsigned long long m = 0ull;
-        for (int st = 0; st < kStripes; ++st)
-            m = max(m, d.vmax2[((int64_t)half * kStripes + st) * d.nseg + sg]);
-        const double vmax = __dsqrt_rn(__longlong_as_double((long long)m));
-        const double Vb = __dadd_rn(vmax, __dmul_rn(__dmul_rn(S.qm_abs, e.dt),
-                                                    __dadd_rn(d.emax[S.ens], fabs(e.E_ext))));
-        const double numax = __dmul_rn(__dmul_rn(S.ngsT, Vb), kNuSafety);
-        d.numax[sg] = numax;
-        d.pnull[sg] = 1.0 - exp(-__dmul_rn(numax, e.dt));
+        // squared speeds are non-negative doubles: their bit patterns order as integers
+        double m2 = 0.0;
+        if (lane < kStripes)
+            m2 = __longlong_as_double((long long)d.vmax2[((int64_t)half * kStripes + lane) * d.nseg + sg]);
+        m2 = wave_max_f64(m2);
+        if (lane == 0) {
+            const double vmax = __dsqrt_rn(m2);
+            const double Vb = __dadd_rn(vmax, __dmul_rn(__dmul_rn(S.qm_abs, e.dt),
+                                                        __dadd_rn(d.emax[S.ens], fabs(e.E_ext))));
+            const double numax = __dmul_rn(__dmul_rn(S.ngsT, Vb), kNuSafety);
+            d.numax[sg] = numax;
+            d.pnull[sg] = 1.0 - exp(-__dmul_rn(numax, e.dt));
+        }
     }
 }
 
@@ -673,8 +698,10 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve2(Dev d, int zero_q)
         const double apre = block_incl_scan(a, s_buf) - a;  // C_pre at c0
         const double fin = n * apre + g;                    // this range's sum of C over m
         const double fpre = block_incl_scan(fin, s_buf) - fin;
-        const double Stot = block_sum(fin, s_buf);
-        const double Ctot = block_sum(a, s_buf);
+        __shared__ double s_red2[2 * 16];
+        double st[2] = {fin, a};
+        block_sums<2>(st, s_red2);
+        const double Stot = st[0], Ctot = st[1];
         const int64_t me = k - e.chunk0;
         if (me >= c0 && me < c1) {
             double ca = apre, fa = fpre;
@@ -788,9 +815,10 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve2(Dev d, int zero_q)
         }
         __syncthreads();
         em = s_em[0];
-        const double fes = block_sum(fe, s_buf);
-        const double ps = block_sum(phisum, s_buf);
-        const double nf = block_sum((double)nonfin, s_buf);
+        __shared__ double s_red3[3 * 16];
+        double fv[3] = {fe, phisum, (double)nonfin};
+        block_sums<3>(fv, s_red3);
+        const double fes = fv[0], ps = fv[1], nf = fv[2];
         if (threadIdx.x == 0) {
             double *pp = d.part + k * P_NPART;
             pp[P_EMAX] = em;
@@ -807,18 +835,25 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve2(Dev d, int zero_q)
     __syncthreads();
     if (s_last) {
         __threadfence();
-        for (int en = threadIdx.x; en < d.nens; en += blockDim.x) {
+        // one wave per ensemble, lanes over its chunks
+        const int nw = blockDim.x / kWave, w = threadIdx.x / kWave, lane = lane_id();
+        for (int en = w; en < d.nens; en += nw) {
             const EnsC &E = d.ens[en];
             double em = 0.0, f = 0.0, nf = 0.0;
-            for (int64_t c = 0; c < E.nchunks; ++c) {
+            for (int64_t c = lane; c < E.nchunks; c += kWave) {
                 const double *pp = d.part + (E.chunk0 + c) * P_NPART;
                 em = fmax(em, pp[P_EMAX]);
                 f += pp[P_FE];
                 nf += pp[P_NONFIN];
             }
-            d.emax[en] = em;
-            d.fe[en] = 0.5 * E.eps0 * f;
-            if (nf > 0.0) atomicOr(d.err, (int)E_NONFINITE);
+            em = wave_max_f64(em);
+            f = wave_sum_f64(f);
+            nf = wave_sum_f64(nf);
+            if (lane == 0) {
+                d.emax[en] = em;
+                d.fe[en] = 0.5 * E.eps0 * f;
+                if (nf > 0.0) atomicOr(d.err, (int)E_NONFINITE);
+            }
         }
         __syncthreads();
         __threadfence();
@@ -924,8 +959,10 @@ __device__ uint32_t block_excl_scan_u32(uint32_t v, uint32_t *s_buf, uint32_t &t
     return x - v + add;
 }
 
-__global__ void __launch_bounds__(kScanBlock) k_scan_sums(const uint32_t *in, int64_t n, uint32_t *part)
+__global__ void __launch_bounds__(kScanBlock) k_scan_sums(const uint32_t *in, int64_t n, uint32_t *part,
+                                                          const int64_t *parity_step)
 {
+    if (parity_step) in += (int64_t)(*parity_step & 1) * n;
     __shared__ uint32_t s_buf[16];
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
     uint32_t s = 0;
@@ -957,8 +994,10 @@ __global__ void __launch_bounds__(1024) k_scan_part(uint32_t *part, int64_t nb)
 }
 
 __global__ void __launch_bounds__(kScanBlock) k_scan_down(uint32_t *in, uint32_t *out, int64_t n,
-                                                          const uint32_t *part, int zero_in)
+                                                          const uint32_t *part, int zero_in,
+                                                          const int64_t *parity_step)
 {
+    if (parity_step) in += (int64_t)(*parity_step & 1) * n;
     __shared__ uint32_t s_buf[16];
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
     // each thread owns kScanItems consecutive elements
@@ -1002,18 +1041,60 @@ __device__ __forceinline__ void birth_locate(const Dev &d, int64_t k, int &st, u
     idx = (uint32_t)(k - s_pre[lo]);
 }
 
+// Exclusive prefix of the per-stripe birth counts (clamped to the stripe capacity), with the
+// total in s_pre[kStripes].  Called by the first wave of the block.
+__device__ __forceinline__ void stripe_prefix(const BirthBuf &bb, int64_t cap, uint32_t *s_pre)
+{
+    const int lane = lane_id();
+    const uint32_t v = lane < kStripes ? (uint32_t)min((int64_t)bb.nbirth[lane], cap) : 0u;
+    uint32_t inc = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t n = __shfl_up(inc, o);
+        if (lane >= o) inc += n;
+    }
+    if (lane < kStripes) s_pre[lane] = inc - v;
+    if (lane == kStripes - 1) s_pre[kStripes] = inc;
+}
+
+// Births of lower parent id in the same group of 1024 ids: popcount of the group's bitmap
+// words below bit `pid & 1023`.  The group's 32 words are 128-byte aligned.
+__device__ __forceinline__ uint32_t rank_in_group(const uint32_t *group, uint32_t pid)
+{
+    const int lim = (int)(pid & 1023u);
+    const uint4 *wv = (const uint4 *)group;
+    uint32_t r = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const uint4 v = wv[q];
+        const uint32_t ws[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int wb = (q * 4 + t) * 32;
+            const uint32_t m = (wb + 32 <= lim) ? 0xffffffffu : (wb >= lim) ? 0u : ((1u << (lim - wb)) - 1u);
+            r += __popc(ws[t] & m);
+        }
+    }
+    return r;
+}
+
+// Place the births of this step (half p = step & 1): rank by parent id, write the new
+// electron and ion at slot n_slots + rank with id next_id + rank.  With `deferred`, also
+// clear the bitmap and counts of half 1 - p (the previous step's births) and reset its
+// birth counts, so the next step starts on a clean half.  The last block updates the
+// counters, makes the freshly accumulated speed maxima current and (with `advance`)
+// advances the step counter.
 template <bool F64>
-__global__ void k_birth_place(Dev d, int advance)
+__global__ void k_birth_place(Dev d, int deferred, int advance)
 {
     __shared__ uint32_t s_pre[kStripes + 1];
+    __shared__ uint32_t s_old[kStripes + 1];
     __shared__ bool s_last;
-    if (threadIdx.x == 0) {
-        uint32_t a = 0;
-        for (int i = 0; i < kStripes; ++i) {
-            s_pre[i] = a;
-            a += min((int64_t)d.nbirth[i], d.birth_stripe_cap);
-        }
-        s_pre[kStripes] = a;
+    const int p = (int)(*d.step & 1);
+    const BirthBuf bb = birth_buf(d, p), ob = birth_buf(d, 1 - p);
+    if (threadIdx.x < kWave) {
+        stripe_prefix(bb, d.birth_stripe_cap, s_pre);
+        if (deferred) stripe_prefix(ob, d.birth_stripe_cap, s_old);
     }
     __syncthreads();
     const int64_t M = s_pre[kStripes];
@@ -1023,14 +1104,12 @@ __global__ void k_birth_place(Dev d, int advance)
         int st;
         uint32_t idx;
         birth_locate(d, k, st, idx, s_pre);
-        const Birth B = d.births[(int64_t)st * d.birth_stripe_cap + idx];
+        const Birth B = bb.births[(int64_t)st * d.birth_stripe_cap + idx];
         const EnsC &e = d.ens[B.ens];
         const uint32_t pid = B.pid;
         const int64_t g = (int64_t)(pid >> 10);
         uint32_t r = d.l1pre[e.l1_base + g] - d.l1pre[e.l1_base];
-        const int64_t w0 = e.bm_base + (g << 5), wp = e.bm_base + (pid >> 5);
-        for (int64_t w = w0; w < wp; ++w) r += __popc(d.bitmap[w]);
-        r += __popc(d.bitmap[wp] & ((1u << (pid & 31)) - 1u));
+        r += rank_in_group(bb.bitmap + e.bm_base + (g << 5), pid);
         for (int s = 0; s < e.nspecies; ++s) {
             const int sg = e.seg[s];
             const SegC &S = d.seg[sg];
@@ -1060,13 +1139,25 @@ __global__ void k_birth_place(Dev d, int advance)
             d.id[b][i] = d.next_id[sg] + r;
         }
     }
+    if (deferred) {
+        const int64_t Mo = s_old[kStripes];
+        for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < Mo;
+             k += (int64_t)gridDim.x * blockDim.x) {
+            int st;
+            uint32_t idx;
+            birth_locate(d, k, st, idx, s_old);
+            const Birth &B = ob.births[(int64_t)st * d.birth_stripe_cap + idx];
+            const EnsC &e = d.ens[B.ens];
+            ob.bitmap[e.bm_base + (B.pid >> 5)] = 0u;
+            ob.l1cnt[e.l1_base + (B.pid >> 10)] = 0u;
+        }
+    }
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) s_last = (atomicAdd(d.ticket + 1, 1u) == gridDim.x - 1);
     __syncthreads();
     if (!s_last) return;
     __threadfence();
-    // counts of births per ensemble
     for (int en = threadIdx.x; en < d.nens; en += blockDim.x) {
         const EnsC &e = d.ens[en];
         const uint32_t m = d.l1pre[e.l1_base + (e.idcap >> 10)] - d.l1pre[e.l1_base];
@@ -1078,10 +1169,11 @@ __global__ void k_birth_place(Dev d, int advance)
             if (m) atomicAdd(d.cnt + ((int64_t)0 * d.nseg + sg) * C_NCNT + C_CREATED, (unsigned long long)m);
         }
     }
+    if (deferred)
+        for (int i = threadIdx.x; i < kStripes; i += blockDim.x) ob.nbirth[i] = 0u;
     __syncthreads();
     if (threadIdx.x == 0) {
         d.ticket[1] = 0u;
-        // the freshly accumulated maxima become current; clear the other half
         *d.vcur = 1 - *d.vcur;
     }
     __syncthreads();
@@ -1090,23 +1182,18 @@ __global__ void k_birth_place(Dev d, int advance)
         for (int64_t i = threadIdx.x; i < (int64_t)kStripes * d.nseg; i += blockDim.x)
             d.vmax2[(int64_t)old * kStripes * d.nseg + i] = 0ull;
     }
-    (void)advance;
+    __syncthreads();
+    if (threadIdx.x == 0 && advance) *d.step += 1;
 }
 
-// Clear the bitmap words and group counts the births touched, reset the birth counts,
-// and (optionally) advance the step counter.
-__global__ void k_birth_clear(Dev d, int advance)
+// Clear one half (parity -1: the current step's) and reset its counts.
+__global__ void k_birth_clear(Dev d, int parity)
 {
     __shared__ uint32_t s_pre[kStripes + 1];
     __shared__ bool s_last;
-    if (threadIdx.x == 0) {
-        uint32_t a = 0;
-        for (int i = 0; i < kStripes; ++i) {
-            s_pre[i] = a;
-            a += min((int64_t)d.nbirth[i], d.birth_stripe_cap);
-        }
-        s_pre[kStripes] = a;
-    }
+    const int p = parity < 0 ? (int)(*d.step & 1) : parity;
+    const BirthBuf bb = birth_buf(d, p);
+    if (threadIdx.x < kWave) stripe_prefix(bb, d.birth_stripe_cap, s_pre);
     __syncthreads();
     const int64_t M = s_pre[kStripes];
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < M;
@@ -1114,10 +1201,10 @@ __global__ void k_birth_clear(Dev d, int advance)
         int st;
         uint32_t idx;
         birth_locate(d, k, st, idx, s_pre);
-        const Birth &B = d.births[(int64_t)st * d.birth_stripe_cap + idx];
+        const Birth &B = bb.births[(int64_t)st * d.birth_stripe_cap + idx];
         const EnsC &e = d.ens[B.ens];
-        d.bitmap[e.bm_base + (B.pid >> 5)] = 0u;
-        d.l1cnt[e.l1_base + (B.pid >> 10)] = 0u;
+        bb.bitmap[e.bm_base + (B.pid >> 5)] = 0u;
+        bb.l1cnt[e.l1_base + (B.pid >> 10)] = 0u;
     }
     __threadfence();
     __syncthreads();
@@ -1125,10 +1212,31 @@ __global__ void k_birth_clear(Dev d, int advance)
     __syncthreads();
     if (!s_last) return;
     __threadfence();
-    for (int i = threadIdx.x; i < kStripes; i += blockDim.x) d.nbirth[i] = 0u;
-    if (threadIdx.x == 0) {
-        d.ticket[2] = 0u;
-        if (advance) *d.step += 1;
+    for (int i = threadIdx.x; i < kStripes; i += blockDim.x) bb.nbirth[i] = 0u;
+    if (threadIdx.x == 0) d.ticket[2] = 0u;
+}
+
+// Single-block exclusive scan of the current half's per-1024-id counts into l1pre: each
+// thread owns a contiguous run of n / 1024 entries (n is a multiple of 4096), sums it,
+// takes one block-wide scan of the sums, then writes its run.
+__global__ void __launch_bounds__(1024) k_l1_scan_small(Dev d)
+{
+    __shared__ uint32_t s_buf[16];
+    const int p = (int)(*d.step & 1);
+    const uint32_t *in = d.l1cnt + (int64_t)p * d.l1_tot;
+    const int64_t per = d.l1_tot / 1024;  // a multiple of 4
+    const int64_t i0 = (int64_t)threadIdx.x * per;
+    uint32_t sum = 0;
+    for (int64_t i = i0; i < i0 + per; i += 4) {
+        const uint4 v = *(const uint4 *)(in + i);
+        sum += v.x + v.y + v.z + v.w;
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_scan_u32(sum, s_buf, tot);
+    for (int64_t i = i0; i < i0 + per; i += 4) {
+        const uint4 v = *(const uint4 *)(in + i);
+        *(uint4 *)(d.l1pre + i) = make_uint4(ex, ex + v.x, ex + v.x + v.y, ex + v.x + v.y + v.z);
+        ex += v.x + v.y + v.z + v.w;
     }
 }
 
@@ -1359,6 +1467,12 @@ hipError_t launch_particles(const Dev &d, const Launch &L, hipStream_t s, bool f
 #undef PIC_CASE
 }
 
+hipError_t launch_candidates(const Dev &d, const Launch &L, hipStream_t s, bool f64, int hist)
+{
+    if (f64) return hipSuccess;
+    return launch_cand32(d, L.ppt, s, hist, d.cap_tot);
+}
+
 hipError_t launch_init(const Dev &d, bool f64, int sg, int64_t n, int64_t ppc, int init_mode,
                        double vth, double amp, int mode, hipStream_t s)
 {
@@ -1433,28 +1547,52 @@ hipError_t launch_params(const Dev &d, hipStream_t s)
     return hipSuccess;
 }
 
-hipError_t launch_scan(uint32_t *in, uint32_t *out, int64_t n, uint32_t *part, bool zero_in, hipStream_t s)
+static hipError_t launch_scan_sel(uint32_t *in, uint32_t *out, int64_t n, uint32_t *part, bool zero_in,
+                                  const int64_t *parity_step, hipStream_t s)
 {
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
     if (nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(kScanBlock), 0, s, in, n, part);
+    hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(kScanBlock), 0, s, in, n, part, parity_step);
     hipLaunchKernelGGL(k_scan_part, dim3(1), dim3(1024), 0, s, part, nb);
-    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kScanBlock), 0, s, in, out, n, part, zero_in ? 1 : 0);
+    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kScanBlock), 0, s, in, out, n, part, zero_in ? 1 : 0,
+                       parity_step);
     LAUNCH_CHECK();
     return hipSuccess;
 }
 
+hipError_t launch_scan(uint32_t *in, uint32_t *out, int64_t n, uint32_t *part, bool zero_in, hipStream_t s)
+{
+    return launch_scan_sel(in, out, n, part, zero_in, nullptr, s);
+}
+
 int64_t scan_blocks(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
 
-hipError_t launch_births(const Dev &d, bool f64, bool advance, hipStream_t s)
+hipError_t launch_births(const Dev &d, bool f64, bool in_step, bool advance, hipStream_t s)
 {
-    hipError_t e = launch_scan(d.l1cnt, d.l1pre, d.l1_tot, d.scanpart, false, s);
-    if (e != hipSuccess) return e;
+    hipError_t e;
+    if (d.l1_tot <= (int64_t)1 << 18) {
+        hipLaunchKernelGGL(k_l1_scan_small, dim3(1), dim3(1024), 0, s, d);
+        LAUNCH_CHECK();
+    } else if ((e = launch_scan_sel(d.l1cnt, d.l1pre, d.l1_tot, d.scanpart, false, d.step, s)) != hipSuccess) {
+        return e;
+    }
+    const int deferred = in_step ? 1 : 0;
     if (f64)
-        hipLaunchKernelGGL(k_birth_place<true>, dim3(64), dim3(256), 0, s, d, 0);
+        hipLaunchKernelGGL(k_birth_place<true>, dim3(64), dim3(256), 0, s, d, deferred, advance ? 1 : 0);
     else
-        hipLaunchKernelGGL(k_birth_place<false>, dim3(64), dim3(256), 0, s, d, 0);
-    hipLaunchKernelGGL(k_birth_clear, dim3(64), dim3(256), 0, s, d, advance ? 1 : 0);
+        hipLaunchKernelGGL(k_birth_place<false>, dim3(64), dim3(256), 0, s, d, deferred, advance ? 1 : 0);
+    LAUNCH_CHECK();
+    if (!in_step) {
+        hipLaunchKernelGGL(k_birth_clear, dim3(64), dim3(256), 0, s, d, -1);
+        LAUNCH_CHECK();
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_births_clear_all(const Dev &d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_birth_clear, dim3(64), dim3(256), 0, s, d, 0);
+    hipLaunchKernelGGL(k_birth_clear, dim3(64), dim3(256), 0, s, d, 1);
     LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -1471,7 +1609,7 @@ hipError_t launch_sort(const Dev &d, bool f64, const Launch &L, hipStream_t s)
     hipError_t e = launch_scan(d.cellcnt, d.cursor, d.cells_tot, d.scanpart, true, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_segstart, dim3(1), dim3(256), 0, s, d);
-    if (!f64) return launch_sort32_scatter(d, L.ppt, L.window, s, d.cap_tot);
+    if (!f64) return launch_sort32_scatter(d, L.sort_ppt, L.window, s, d.cap_tot);
     const size_t lds = (size_t)L.window * 4;
     if (f64)
         hipLaunchKernelGGL((k_sort_scatter<true, 4>), dim3(L.grid), dim3(L.block), lds, s, d, L.window);

@@ -108,6 +108,8 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
     __shared__ uint32_t s_c[C_NCNT];
     __shared__ double s_ke[2];
     __shared__ int s_c0;
+    __shared__ uint32_t s_nc;
+    __shared__ uint32_t s_cand[COLL ? TILE : 1];
 
     const int64_t t = xcd_tile();
     if (t >= T) return;
@@ -165,6 +167,7 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
     if (tid == 0) {
         s_v2 = 0ull;
         s_c0 = cell[0];
+        s_nc = 0u;
     }
     __syncthreads();
     // deposit window [wbase, wbase + W) around the tile's first cell (pre-push)
@@ -173,81 +176,97 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
 
     uint32_t npush = 0;
     double v2m = 0.0;
-    const double numax = COLL ? d.numax[sg] : 0.0;
-    const double pnull = COLL ? d.pnull[sg] : 0.0;
-    const uint32_t tag = COLL ? (uint32_t)(*d.step) : 0u;
     const int st = stripe_of_block();
 
+    if (PUSH) {
+        // segment constants in registers; the gather table entries are fetched up front,
+        // dead slots (cell = kDead < 0) read entry 0 and are masked below, so the loop
+        // below is straight-line code apart from the rare wall branch
+        const float h = (float)S.h, dtdx = (float)S.dtdx, eext = (float)e.E_ext;
+        const float tv[3] = {(float)S.t[0], (float)S.t[1], (float)S.t[2]};
+        const float sv[3] = {(float)S.s[0], (float)S.s[1], (float)S.s[2]};
+        const int N = S.ncells;
+        const bool per = S.periodic != 0;
+        const float2 *__restrict__ Ecs = d.Ecell + S.gbase;
+        float2 ec[PPT];
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        if (cell[k] == kDead) continue;
-        PS<false> p;
-        p.cell = cell[k];
-        p.off = off[k];
-        if (NEED_V) {
-            p.vx = vx[k];
-            p.vy = vy[k];
-            p.vz = vz[k];
-        }
-        if (PUSH) {
-            ++npush;
-            const int wall = p_push<false>(d, S, e, p);
-            if (wall) {
-                if (wall != 3) {
-                    const double v2 = speed2_rn(p.vx, p.vy, p.vz);
-                    atomicAdd(&s_c[wall == 1 ? C_WALL_L : C_WALL_R], 1u);
-                    atomicAdd(&s_ke[wall - 1], S.halfmw * v2);
-                }
-                cell[k] = kDead;
-                continue;
-            }
-            cell[k] = p.cell;
-            off[k] = p.off;
-            vx[k] = p.vx;
-            vy[k] = p.vy;
-            vz[k] = p.vz;
-        }
-        if (COLL) {
-            p.id = id[k];
-            double ve[3], vi[3];
-            const int ch = p_collide<false>(e, S, s, numax, pnull, tag, p, ve, vi);
-            if (ch >= 0) {
-                atomicAdd(&s_c[C_EL + ch], 1u);
-                vx[k] = p.vx;
-                vy[k] = p.vy;
-                vz[k] = p.vz;
-            }
-            if (ch == 1) {
-                const uint32_t slot = atomicAdd(d.nbirth + st, 1u);
-                if ((int64_t)slot < d.birth_stripe_cap) {
-                    Birth &B = d.births[(int64_t)st * d.birth_stripe_cap + slot];
-                    B.pid = p.id;
-                    B.ens = S.ens;
-                    B.cell = p.cell;
-                    B.off = p.off;
-                    B.x = ((double)p.cell + (double)p.off) * S.dx;
-                    for (int q = 0; q < 3; ++q) {
-                        B.ve[q] = ve[q];
-                        B.vi[q] = vi[q];
+        for (int k = 0; k < PPT; ++k) ec[k] = Ecs[cell[k] < 0 ? 0u : (uint32_t)cell[k]];
+        uint32_t nwl = 0, nwr = 0, bad = 0;
+        double kel = 0.0, ker = 0.0;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const bool alive = cell[k] != kDead;
+            npush += alive ? 1u : 0u;
+            const float Ep = fmaf(off[k], ec[k].y, ec[k].x) + eext;
+            boris<float>(h, tv, sv, Ep, vx[k], vy[k], vz[k]);
+            float o = off[k] + vx[k] * dtdx;
+            const float fl = floorf(o);
+            int c = (alive ? cell[k] : 0) + (int)fl;
+            o -= fl;
+            const bool up = o >= 1.0f;
+            off[k] = up ? o - 1.0f : o;
+            c += up ? 1 : 0;
+            if (per) {
+                c = (c < 0) ? c + N : ((c >= N) ? c - N : c);
+                const bool inv = alive && (c < 0 || c >= N);  // moved more than a period
+                bad |= inv ? 1u : 0u;
+                cell[k] = (alive && !inv) ? c : kDead;
+            } else {
+                const bool out = alive && (c < 0 || c >= N);
+                if (out) {
+                    const double v2 = speed2_rn(vx[k], vy[k], vz[k]);
+                    if (c < 0) {
+                        ++nwl;
+                        kel += S.halfmw * v2;
+                    } else {
+                        ++nwr;
+                        ker += S.halfmw * v2;
                     }
-                    atomicOr(d.bitmap + e.bm_base + (p.id >> 5), 1u << (p.id & 31));
-                    atomicAdd(d.l1cnt + e.l1_base + (p.id >> 10), 1u);
-                } else {
-                    atomicOr(d.err, (int)E_CAP_BIRTH);
                 }
-                v2m = fmax(v2m, speed2_rn(ve[0], ve[1], ve[2]));
-                if (S.other >= 0) {
-                    const int half = 1 - *d.vcur;
-                    atomicMax(d.vmax2 + ((int64_t)half * kStripes + st) * d.nseg + S.other,
-                              dbits(speed2_rn(vi[0], vi[1], vi[2])));
-                }
-                if (DEPO) {
-                    global_deposit32(d, S, s, p.cell, p.off, hist);
-                    if (S.other >= 0) global_deposit32(d, d.seg[S.other], 1, p.cell, p.off, hist);
-                }
+                cell[k] = out ? kDead : cell[k] == kDead ? kDead : c;
             }
-            v2m = fmax(v2m, speed2_rn(vx[k], vy[k], vz[k]));
         }
+        if (nwl) {
+            atomicAdd(&s_c[C_WALL_L], nwl);
+            atomicAdd(&s_ke[0], kel);
+        }
+        if (nwr) {
+            atomicAdd(&s_c[C_WALL_R], nwr);
+            atomicAdd(&s_ke[1], ker);
+        }
+        if (bad) atomicOr(d.err, (int)E_NONFINITE);
+    }
+
+    if (COLL) {
+        // Reading R12 decision R1 < P_null, taken exactly as the integer test
+        // (r >> 9) < ceil(P_null 2^23 - 1/2) on the first Philox word.  Candidates (about
+        // P_null of the particles) are listed for k_cand32, which draws the rest of the
+        // block, picks the channel and scatters; all others keep their velocity.
+        const double pnull = d.pnull[sg];
+        const double X = pnull * 8388608.0 - 0.5;
+        const uint32_t thr = X <= 0.0 ? 0u : (X >= 8388608.0 ? 8388608u : (uint32_t)ceil(X));
+        const uint32_t tag = (uint32_t)(*d.step);
+        const uint32_t seed = S.seed;
+        float v2f = 0.f;
+        uint32_t cmask = 0;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const bool alive = cell[k] != kDead;
+            const uint4 w = philox(id[k], tag, 0u, 0u, seed, (uint32_t)s);
+            const bool cand = alive && (w.x >> 9) < thr;
+            cmask |= (cand ? 1u : 0u) << k;
+            const float vv = fmaf(vx[k], vx[k], fmaf(vy[k], vy[k], vz[k] * vz[k]));
+            v2f = (alive && !cand) ? fmaxf(v2f, vv) : v2f;
+        }
+        if (cmask) {
+            uint32_t q = atomicAdd(&s_nc, (uint32_t)__popc(cmask));
+#pragma unroll
+            for (int k = 0; k < PPT; ++k)
+                if ((cmask >> k) & 1u) s_cand[q++] = (uint32_t)(i0 + k);
+        }
+        // the speed bound of the next step carries a 2^-16 margin, far above the binary32
+        // rounding of |v|^2 here; candidates report their post-collision speed themselves
+        v2m = (double)v2f * (1.0 + 0x1p-20);
     }
 
     // write back
@@ -284,15 +303,15 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
         uint32_t rc = 0, rs = 0;
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-            if (cell[k] == kDead) continue;
-            if (cell[k] != rk) {
+            const bool alive = cell[k] != kDead;
+            if (alive && cell[k] != rk) {
                 if (rk != kDead) emit_run(d, S, s, rk, rc, rs, wbase, W, DEPO, hist, sQ, sH);
                 rk = cell[k];
                 rc = 0;
                 rs = 0;
             }
-            ++rc;
-            if (DEPO) rs += fixed_share(off[k]);
+            rc += alive ? 1u : 0u;
+            if (DEPO) rs += alive ? fixed_share(off[k]) : 0u;
         }
         if (rk != kDead) emit_run(d, S, s, rk, rc, rs, wbase, W, DEPO, hist, sQ, sH);
     }
@@ -326,6 +345,11 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
             }
         }
     }
+    if (COLL) {
+        const uint32_t nc = s_nc;
+        for (uint32_t q = tid; q < nc; q += 256) d.cand[first + q] = s_cand[q];
+        if (tid == 0) d.ctile[t] = nc;
+    }
     if (tid == 0 && (PUSH || COLL)) {
         unsigned long long *c = d.cnt + ((int64_t)st * d.nseg + sg) * C_NCNT;
         for (int k = 0; k < C_NCNT; ++k)
@@ -341,9 +365,139 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
 }
 
 // =======================================================================================
-// Counting sort scatter (FP32 form): thread runs are ranked inside the tile with one LDS
-// atomic each, every cell of the tile reserves its output run with one HBM atomic on the
-// cursor, and the particles are written into the other buffer.  Absorbed slots drop out.
+// Null-collision candidates of the FP32 pass.  A block takes 16 consecutive tiles; their
+// candidate lists are concatenated through a prefix of the tile counts, one candidate per
+// thread.  Each candidate draws the full Philox block 0 again, picks its channel (FP64
+// decision, as in the reference), scatters, and on ionisation appends the new pair.
+// Collision counts and the largest post-collision speed go out once per wave when the
+// wave's candidates share a segment (always, unless the 16 tiles straddle a segment end).
+// =======================================================================================
+constexpr int kCandTiles = 16;
+
+__global__ void __launch_bounds__(256) k_cand32(Dev d, int tile, int64_t T, int hist)
+{
+    __shared__ uint32_t s_pre[kCandTiles + 1];
+    const int64_t t0 = (int64_t)blockIdx.x * kCandTiles;
+    if (threadIdx.x < kWave) {
+        // the first wave loads the tile counts in parallel, resets them and scans
+        const int k = threadIdx.x;
+        const int64_t t = t0 + k;
+        uint32_t c = 0;
+        if (k < kCandTiles && t < T) {
+            c = d.ctile[t];
+            d.ctile[t] = 0u;
+        }
+        uint32_t inc = c;
+#pragma unroll
+        for (int o = 1; o < kCandTiles; o <<= 1) {
+            const uint32_t n = __shfl_up(inc, o);
+            if (k >= o) inc += n;
+        }
+        if (k < kCandTiles) s_pre[k] = inc - c;
+        if (k == kCandTiles - 1) s_pre[kCandTiles] = inc;
+    }
+    __syncthreads();
+    const uint32_t m = s_pre[kCandTiles];
+    if (m == 0) return;
+    const int lane = lane_id();
+    const int b = *d.cur;
+    const uint32_t tag = (uint32_t)(*d.step);
+    const BirthBuf bb = birth_buf(d, (int)(tag & 1u));
+    const int st = (int)(blockIdx.x & (kStripes - 1));
+    for (uint32_t q0 = 0; q0 < m; q0 += blockDim.x) {
+        const uint32_t q = q0 + threadIdx.x;
+        const bool act = q < m;
+        int sg = -1;
+        uint32_t nel = 0, niz = 0, ncx = 0;
+        double v2m = 0.0;
+        if (act) {
+            int k = 0;
+            while (k + 1 < kCandTiles && s_pre[k + 1] <= q) ++k;
+            const int64_t i = d.cand[(t0 + k) * (int64_t)tile + (q - s_pre[k])];
+            sg = seg_of_slot(d, i);
+            const SegC &S = d.seg[sg];
+            const EnsC &e = d.ens[S.ens];
+            const int s = S.species;
+            PS<false> p;
+            p.cell = d.cell[b][i];
+            p.off = d.off[b][i];
+            p.vx = d.fvx[b][i];
+            p.vy = d.fvy[b][i];
+            p.vz = d.fvz[b][i];
+            p.id = d.id[b][i];
+            double ve[3], vi[3];
+            const int ch = p_collide<false>(e, S, s, d.numax[sg], d.pnull[sg], tag, p, ve, vi);
+            if (ch >= 0) {
+                d.fvx[b][i] = p.vx;
+                d.fvy[b][i] = p.vy;
+                d.fvz[b][i] = p.vz;
+                nel = ch == 0;
+                niz = ch == 1;
+                ncx = ch == 2;
+            }
+            v2m = speed2_rn(p.vx, p.vy, p.vz);
+            if (ch == 1) {
+                const uint32_t slot = atomicAdd(bb.nbirth + st, 1u);
+                if ((int64_t)slot < d.birth_stripe_cap) {
+                    Birth &B = bb.births[(int64_t)st * d.birth_stripe_cap + slot];
+                    B.pid = p.id;
+                    B.ens = S.ens;
+                    B.cell = p.cell;
+                    B.off = p.off;
+                    B.x = ((double)p.cell + (double)p.off) * S.dx;
+                    for (int c = 0; c < 3; ++c) {
+                        B.ve[c] = ve[c];
+                        B.vi[c] = vi[c];
+                    }
+                    atomicOr(bb.bitmap + e.bm_base + (p.id >> 5), 1u << (p.id & 31));
+                    atomicAdd(bb.l1cnt + e.l1_base + (p.id >> 10), 1u);
+                } else {
+                    atomicOr(d.err, (int)E_CAP_BIRTH);
+                }
+                v2m = fmax(v2m, speed2_rn(ve[0], ve[1], ve[2]));
+                if (S.other >= 0) {
+                    const int half = 1 - *d.vcur;
+                    atomicMax(d.vmax2 + ((int64_t)half * kStripes + st) * d.nseg + S.other,
+                              dbits(speed2_rn(vi[0], vi[1], vi[2])));
+                }
+                global_deposit32(d, S, s, p.cell, p.off, hist != 0);
+                if (S.other >= 0) global_deposit32(d, d.seg[S.other], 1, p.cell, p.off, hist != 0);
+            }
+        }
+        // tallies: once per wave when all active lanes share a segment
+        const int sg0 = __shfl(sg, __ffsll((long long)__ballot(act)) - 1);
+        const bool uniform = __ballot(act && sg != sg0) == 0ull;
+        const int half = 1 - *d.vcur;
+        if (uniform) {
+            nel = wave_sum_u32(nel);
+            niz = wave_sum_u32(niz);
+            ncx = wave_sum_u32(ncx);
+            v2m = wave_max_f64(v2m);
+            if (lane == 0 && sg0 >= 0) {
+                unsigned long long *c = d.cnt + ((int64_t)st * d.nseg + sg0) * C_NCNT;
+                if (nel) atomicAdd(c + C_EL, (unsigned long long)nel);
+                if (niz) atomicAdd(c + C_IZ, (unsigned long long)niz);
+                if (ncx) atomicAdd(c + C_CX, (unsigned long long)ncx);
+                if (v2m > 0.0)
+                    atomicMax(d.vmax2 + ((int64_t)half * kStripes + st) * d.nseg + sg0, dbits(v2m));
+            }
+        } else if (act) {
+            unsigned long long *c = d.cnt + ((int64_t)st * d.nseg + sg) * C_NCNT;
+            if (nel) atomicAdd(c + C_EL, 1ull);
+            if (niz) atomicAdd(c + C_IZ, 1ull);
+            if (ncx) atomicAdd(c + C_CX, 1ull);
+            if (v2m > 0.0) atomicMax(d.vmax2 + ((int64_t)half * kStripes + st) * d.nseg + sg, dbits(v2m));
+        }
+    }
+}
+
+// =======================================================================================
+// Counting sort scatter (FP32 form).  Thread t owns slots t, t + 256, ... of the tile, so a
+// wave holds 64 consecutive (sorted, so mostly same-cell) particles.  Within a wave the
+// lanes of one cell take consecutive ranks from one LDS atomic of their leader; each cell
+// of the tile then reserves its output run with one HBM atomic on its cursor.  Lanes of
+// one cell thus write consecutive output slots and every store instruction is coalesced.
+// Absorbed slots drop out.
 // =======================================================================================
 template <int PPT>
 __global__ void __launch_bounds__(256) k_sort32(Dev d, int W, int64_t T)
@@ -360,32 +514,27 @@ __global__ void __launch_bounds__(256) k_sort32(Dev d, int W, int64_t T)
     const int64_t last = min(first + TILE, S.base + d.n_slots[sg]);
     if (first >= last) return;
     const int b = *d.cur, nb = 1 - b;
-    const int tid = threadIdx.x;
-    const int64_t i0 = first + (int64_t)tid * PPT;
-    const bool full = (i0 + PPT <= last);
+    const int tid = threadIdx.x, lane = lane_id();
+    const int32_t *__restrict__ icell = d.cell[b];
+    const float *__restrict__ ioff = d.off[b];
+    const float *__restrict__ ivx = d.fvx[b];
+    const float *__restrict__ ivy = d.fvy[b];
+    const float *__restrict__ ivz = d.fvz[b];
+    const uint32_t *__restrict__ iid = d.id[b];
     int cell[PPT];
     float off[PPT], vx[PPT], vy[PPT], vz[PPT];
     uint32_t id[PPT];
-    if (full) {
-        vload<PPT, int32_t, int4>(d.cell[b] + i0, cell);
-        vload<PPT, float, float4>(d.off[b] + i0, off);
-        vload<PPT, float, float4>(d.fvx[b] + i0, vx);
-        vload<PPT, float, float4>(d.fvy[b] + i0, vy);
-        vload<PPT, float, float4>(d.fvz[b] + i0, vz);
-        vload<PPT, uint32_t, uint4>(d.id[b] + i0, id);
-    } else {
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            const int64_t i = i0 + k;
-            cell[k] = kDead;
-            if (i < last) {
-                cell[k] = d.cell[b][i];
-                off[k] = d.off[b][i];
-                vx[k] = d.fvx[b][i];
-                vy[k] = d.fvy[b][i];
-                vz[k] = d.fvz[b][i];
-                id[k] = d.id[b][i];
-            }
+    for (int k = 0; k < PPT; ++k) {
+        const int64_t i = first + (int64_t)k * 256 + tid;
+        cell[k] = kDead;
+        if (i < last) {
+            cell[k] = icell[i];
+            off[k] = ioff[i];
+            vx[k] = ivx[i];
+            vy[k] = ivy[i];
+            vz[k] = ivz[i];
+            id[k] = iid[i];
         }
     }
     int mn = INT32_MAX;
@@ -396,51 +545,49 @@ __global__ void __launch_bounds__(256) k_sort32(Dev d, int W, int64_t T)
     if (tid == 0) s_min = INT32_MAX;
     for (int i = tid; i < W; i += 256) sCnt[i] = 0u;
     __syncthreads();
-    if (lane_id() == 0 && mn != INT32_MAX) atomicMin(&s_min, mn);
+    if (lane == 0 && mn != INT32_MAX) atomicMin(&s_min, mn);
     __syncthreads();
     const int base = s_min;
-    // rank runs: pos[k] is the rank inside the tile's run of that cell (in window) or the
-    // final global position (outside it)
+    uint32_t *__restrict__ cursor = d.cursor + S.cbase;
+    // rank: in-window -> rank inside the tile's run of that cell; outside -> final position
     uint32_t pos[PPT];
     bool inwin[PPT];
-    {
-        int rk = kDead, rstart = 0;
-        uint32_t rc = 0;
-        auto flush = [&](int kend) {
-            if (rk == kDead || rc == 0) return;
-            const int rel = rk - base;
-            const bool w = rel >= 0 && rel < W;
-            const uint32_t r0 = w ? atomicAdd(&sCnt[rel], rc) : atomicAdd(d.cursor + S.cbase + rk, rc);
-            uint32_t r = r0;
 #pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                if (k >= rstart && k < kend && cell[k] == rk) {
-                    pos[k] = r++;
-                    inwin[k] = w;
-                }
-            }
-        };
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            if (cell[k] == kDead) continue;
-            if (cell[k] != rk) {
-                flush(k);
-                rk = cell[k];
-                rc = 0;
-                rstart = k;
-            }
-            ++rc;
+    for (int k = 0; k < PPT; ++k) {
+        const int rel = (cell[k] != kDead) ? cell[k] - base : -1;
+        const int key = (rel >= 0 && rel < W) ? rel : -1;
+        inwin[k] = key >= 0;
+        unsigned long long act = __ballot(key >= 0);
+        int it = 0;
+        while (act != 0ull && it < 8) {
+            const int leader = __ffsll((long long)act) - 1;
+            const int kk = __shfl(key, leader);
+            const bool mine = (key == kk) && ((act >> lane) & 1ull);
+            const unsigned long long m = __ballot(mine);
+            uint32_t r0 = 0;
+            if (lane == leader) r0 = atomicAdd(&sCnt[kk], (uint32_t)__popcll(m));
+            r0 = __shfl(r0, leader);
+            if (mine) pos[k] = r0 + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+            act &= ~m;
+            ++it;
         }
-        flush(PPT);
+        if ((act >> lane) & 1ull) pos[k] = atomicAdd(&sCnt[key], 1u);
+        if (cell[k] != kDead && key < 0) pos[k] = atomicAdd(cursor + cell[k], 1u);
     }
     __syncthreads();
     for (int i = tid; i < W; i += 256) {
         const uint32_t c = sCnt[i];
-        if (c) sCnt[i] = atomicAdd(d.cursor + S.cbase + base + i, c);
+        if (c) sCnt[i] = atomicAdd(cursor + base + i, c);
     }
     __syncthreads();
     const int64_t sbase = S.base - d.segstart[sg];
     const int64_t send = S.base + S.cap;
+    int32_t *__restrict__ ocell = d.cell[nb];
+    float *__restrict__ ooff = d.off[nb];
+    float *__restrict__ ovx = d.fvx[nb];
+    float *__restrict__ ovy = d.fvy[nb];
+    float *__restrict__ ovz = d.fvz[nb];
+    uint32_t *__restrict__ oid = d.id[nb];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         if (cell[k] == kDead) continue;
@@ -450,12 +597,12 @@ __global__ void __launch_bounds__(256) k_sort32(Dev d, int W, int64_t T)
             atomicOr(d.err, (int)E_CAP_PART);
             continue;
         }
-        d.cell[nb][o] = cell[k];
-        d.off[nb][o] = off[k];
-        d.fvx[nb][o] = vx[k];
-        d.fvy[nb][o] = vy[k];
-        d.fvz[nb][o] = vz[k];
-        d.id[nb][o] = id[k];
+        ocell[o] = cell[k];
+        ooff[o] = off[k];
+        ovx[o] = vx[k];
+        ovy[o] = vy[k];
+        ovz[o] = vz[k];
+        oid[o] = id[k];
     }
 }
 
@@ -471,6 +618,9 @@ __global__ void k_sort_finish(Dev d)
 }
 
 // =======================================================================================
+hipError_t launch_pass32_stages(const Dev &d, int ppt, int W, hipStream_t s, int stages, int hist,
+                                int64_t cap_tot);
+
 template <int STAGES>
 static hipError_t launch_pass32_t(const Dev &d, int ppt, int W, hipStream_t s, int hist, int64_t cap_tot)
 {
@@ -487,7 +637,20 @@ static hipError_t launch_pass32_t(const Dev &d, int ppt, int W, hipStream_t s, i
     return hipGetLastError();
 }
 
+hipError_t launch_cand32(const Dev &d, int ppt, hipStream_t s, int hist, int64_t cap_tot)
+{
+    const int tile = 256 * ppt;
+    const int64_t T = cap_tot / tile;
+    hipLaunchKernelGGL(k_cand32, dim3((T + kCandTiles - 1) / kCandTiles), dim3(256), 0, s, d, tile, T, hist);
+    return hipGetLastError();
+}
+
 hipError_t launch_pass32(const Dev &d, int ppt, int W, hipStream_t s, int stages, int hist, int64_t cap_tot)
+{
+    return launch_pass32_stages(d, ppt, W, s, stages, hist, cap_tot);
+}
+
+hipError_t launch_pass32_stages(const Dev &d, int ppt, int W, hipStream_t s, int stages, int hist, int64_t cap_tot)
 {
     switch (stages) {
     case PS_PUSH:

@@ -71,9 +71,12 @@ def test_bench_workload_full_size_one_step(pic):
     """The 1e5-cell x 200-ppc x 2-species workload (4.0e7 particles) at full size: the load
     matches the oracle bit for bit in position, and one fused step matches the oracle's step
     (fields within 1e-5, counts exact up to threshold-flipped collision decisions)."""
+    import bench
+
     work = synth.c2_sheath(seed=1)
     e = work["ensembles"][0]
-    sim = pic.Sim(work, fused=True)
+    shape = bench.tuned_shape(pic, work, 2)   # the launch shape bench.py times
+    sim = pic.Sim(work, fused=True, **shape)
     o = oracle.Oracle(e)
     g0 = sim.grid()
     r0 = o.grid()
@@ -92,7 +95,8 @@ def test_bench_workload_full_size_one_step(pic):
     assert rel(sim.grid()["E"], o.grid()["E"]) <= TOL_FIELD
     del g0, r0
     # one full step from the load (the step re-solves, which is idempotent)
-    sim2 = pic.Sim(work, fused=True)
+    sim.close()
+    sim2 = pic.Sim(work, fused=True, **shape)
     o2 = oracle.Oracle(e)
     sim2.step(1)
     o2.step(1)
