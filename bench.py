@@ -140,8 +140,10 @@ def main():
     ap.add_argument("--ppc", type=int, default=200)
     ap.add_argument("--separate", action="store_true",
                     help="profile the FP32 form with one kernel per stage instead of the fused pass")
-    ap.add_argument("--tune-steps", type=int, default=6,
+    ap.add_argument("--tune-steps", type=int, default=10,
                     help="trial steps per candidate launch shape of the autotuner (0 = defaults)")
+    ap.add_argument("--shape", type=str, default="",
+                    help="fixed launch shape ppt,window,sort_ppt,nontemporal instead of the autotuner")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=40)
     ap.add_argument("--no-stream", action="store_true")
@@ -164,7 +166,11 @@ def main():
     torch.cuda.set_device(0)
     work = synth.c2_sheath(seed=args.seed, ncells=args.ncells, ppc=args.ppc)
     e = work["ensembles"][0]
-    shape = tuned_shape(pic, work, args.tune_steps)
+    if args.shape:
+        ppt, window, sort_ppt, nt = (int(v) for v in args.shape.split(","))
+        shape = {"ppt": ppt, "window": window, "sort_ppt": sort_ppt, "nontemporal": nt}
+    else:
+        shape = tuned_shape(pic, work, args.tune_steps)
     sim = pic.Sim(work, fused=not args.separate, **shape)
 
     # warm-up (graph capture happens here)

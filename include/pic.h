@@ -89,6 +89,8 @@ typedef struct {
     int32_t window;      /* LDS deposit window in nodes (power of two); 0 = default        */
     int32_t ppt;         /* particles per thread of the FP32 pass (4 or 8); 0 = default    */
     int32_t sort_ppt;    /* particles per thread of the FP32 sort scatter; 0 = default     */
+    int32_t nontemporal; /* 1: the fused FP32 pass streams particles with non-temporal
+                          * loads and stores; 0 = ordinary (default)                        */
     const pic_ensemble_desc *ens;              /* [n_ensembles], copied by pic_init       */
 } pic_config;
 
@@ -178,6 +180,11 @@ int pic_set_particles(pic_ctx *ctx, int32_t ens, int32_t species, pic_particles 
 int pic_get_grid(pic_ctx *ctx, int32_t ens, double *Q0, double *Q1, double *rho, double *phi,
                  double *E, void *stream);
 
+/* Copy the FP32 form's gather table of ensemble `ens` to host: per cell j the binary32
+ * pair (E_j, E_{j+1} - E_j) the push interpolates from (E_N is E_0 when periodic);
+ * `out` holds 2 x ncells floats.  PIC_EINVAL for the FP64 form (it gathers from E). */
+int pic_get_gather_table(pic_ctx *ctx, int32_t ens, float *out, void *stream);
+
 /* Replace the self-consistent node field of ensemble `ens` with host values (test hook:
  * push in a given field, e.g. zero). */
 int pic_set_fields(pic_ctx *ctx, int32_t ens, const double *E, void *stream);
@@ -211,7 +218,7 @@ int pic_adjoint_window(pic_ctx *ctx, int32_t nsteps, int32_t ckpt_every, void *s
 /* The library's autotuner: times the particle pass over `trial_steps` steps for every
  * candidate launch shape (particles per thread x LDS window) and the sort scatter for each
  * particles-per-thread choice, all with HIP events on `stream`, keeps the fastest, and
- * writes {ppt, window, sort_ppt} to `shape` (may be NULL).  The trial steps advance the
+ * writes {ppt, window, sort_ppt, nontemporal} to `shape` (4 ints, may be NULL).  The trial steps advance the
  * run like pic_step (the sort is repeated on already-sorted data, which leaves the state
  * unchanged apart from slot order). */
 int pic_autotune(pic_ctx *ctx, int32_t trial_steps, int32_t *shape, void *stream);

@@ -21,7 +21,8 @@ PIC_ABSORBING, PIC_PERIODIC = 0, 1
 
 EXPORTS = ("pic_query_workspace", "pic_init", "pic_deposit", "pic_solve", "pic_push",
            "pic_collide", "pic_sort", "pic_step", "pic_diag", "pic_get_particles",
-           "pic_get_slots", "pic_set_particles", "pic_get_grid", "pic_set_fields", "pic_set_step",
+           "pic_get_slots", "pic_set_particles", "pic_get_grid", "pic_get_gather_table",
+           "pic_set_fields", "pic_set_step",
            "pic_nnodes", "pic_set_external_field", "pic_adjoint_query",
            "pic_adjoint_window", "pic_autotune", "pic_timing", "pic_timing_read", "pic_free", "pic_last_error")
 
@@ -51,6 +52,7 @@ class Config(C.Structure):
                 ("nspecies", C.c_int32), ("collisions", C.c_int32), ("sort_every", C.c_int32),
                 ("fused", C.c_int32), ("block", C.c_int32), ("grid", C.c_int32),
                 ("window", C.c_int32), ("ppt", C.c_int32), ("sort_ppt", C.c_int32),
+                ("nontemporal", C.c_int32),
                 ("ens", C.POINTER(EnsembleDesc))]
 
 
@@ -103,6 +105,7 @@ def load_library():
     L.pic_set_particles.argtypes = [P, C.c_int32, C.c_int32, Particles, C.c_int64, C.c_uint32, P]
     L.pic_get_slots.argtypes = [P, C.c_int32, C.c_int32, C.c_int64, C.c_int64, Particles, P]
     L.pic_get_grid.argtypes = [P, C.c_int32, P, P, P, P, P, P]
+    L.pic_get_gather_table.argtypes = [P, C.c_int32, P, P]
     L.pic_set_fields.argtypes = [P, C.c_int32, P, P]
     L.pic_set_step.argtypes = [P, C.c_int64]
     L.pic_nnodes.argtypes = [P, C.c_int32]
@@ -122,7 +125,8 @@ def load_library():
     return L
 
 
-def make_config(work, fused=True, precision=None, block=0, grid=0, window=0, ppt=0, sort_ppt=0):
+def make_config(work, fused=True, precision=None, block=0, grid=0, window=0, ppt=0, sort_ppt=0,
+                nontemporal=0):
     """Translate a workload dict ({"ensembles": [...], "precision": "fp32"|"fp64"}) into
     the C configuration.  Returns (Config, keep-alive array)."""
     ens = work["ensembles"]
@@ -150,6 +154,7 @@ def make_config(work, fused=True, precision=None, block=0, grid=0, window=0, ppt
     cfg.sort_every = e0["sort_every"]
     cfg.fused = int(fused)
     cfg.block, cfg.grid, cfg.window, cfg.ppt, cfg.sort_ppt = block, grid, window, ppt, sort_ppt
+    cfg.nontemporal = int(nontemporal)
     cfg.ens = arr
     return cfg, arr
 
@@ -162,12 +167,13 @@ class Sim:
     """One run of the PIC MC hot path on the current GPU (torch provides the memory)."""
 
     def __init__(self, work, fused=True, precision=None, block=0, grid=0, window=0, ppt=0,
-                 sort_ppt=0, stream=None):
+                 sort_ppt=0, nontemporal=0, stream=None):
         import torch
 
         self.L = load_library()
         self.work = work
-        self.cfg, self._arr = make_config(work, fused, precision, block, grid, window, ppt, sort_ppt)
+        self.cfg, self._arr = make_config(work, fused, precision, block, grid, window, ppt, sort_ppt,
+                                          nontemporal)
         nbytes = C.c_size_t(0)
         self._check(self.L.pic_query_workspace(C.byref(self.cfg), C.byref(nbytes)), None)
         self.ws_bytes = nbytes.value
@@ -240,9 +246,10 @@ class Sim:
 
     def autotune(self, trial_steps=10):
         """Let the library time its launch shapes and keep the fastest; returns the shape."""
-        shape = np.zeros(3, dtype=np.int32)
+        shape = np.zeros(4, dtype=np.int32)
         self._check(self.L.pic_autotune(self.h, int(trial_steps), _ptr(shape), self._s()))
-        return {"ppt": int(shape[0]), "window": int(shape[1]), "sort_ppt": int(shape[2])}
+        return {"ppt": int(shape[0]), "window": int(shape[1]), "sort_ppt": int(shape[2]),
+                "nontemporal": int(shape[3])}
 
     def timing(self, enable=True):
         self._check(self.L.pic_timing(self.h, int(bool(enable))))
@@ -305,6 +312,14 @@ class Sim:
         self._check(self.L.pic_get_grid(self.h, int(ens), _ptr(Q0), _ptr(Q1), _ptr(rho), _ptr(phi),
                                         _ptr(E), self._s()))
         return {"Q": [Q0, Q1][: self.nspecies], "rho": rho, "phi": phi, "E": E}
+
+    def gather_table(self, ens=0):
+        """The FP32 form's per-cell (E_j, E_{j+1} - E_j) table, shape (ncells, 2), float32."""
+        nn = self.nnodes(ens)
+        ncells = nn if self.work["ensembles"][ens]["periodic"] else nn - 1
+        out = np.zeros((ncells, 2), dtype=np.float32)
+        self._check(self.L.pic_get_gather_table(self.h, int(ens), _ptr(out), self._s()))
+        return out
 
     def set_fields(self, E, ens=0):
         E = np.ascontiguousarray(E, dtype=np.float64)

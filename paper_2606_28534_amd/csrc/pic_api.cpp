@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -30,7 +31,7 @@ struct Plan {
     std::vector<SegC> seg;
     std::vector<EnsC> ens;
     int64_t cap_tot = 0, nodes_tot = 0, cells_tot = 0, chunks_tot = 0;
-    int64_t bm_words = 0, l1_tot = 0, birth_stripe_cap = 0;
+    int64_t birth_stripe_cap = 0, bm_words = 0, g_tot = 0;
     int64_t scanpart = 0;
     size_t bytes = 0;
 };
@@ -62,7 +63,7 @@ int build_plan(const pic_config *cfg, Plan &P, std::string &msg)
     P.nseg = P.nens * P.nspecies;
     P.f64 = cfg->precision == PIC_FP64_PLAIN;
     const bool periodic = cfg->boundary == PIC_PERIODIC;
-    int64_t base = 0, gbase = 0, cbase = 0, chunk0 = 0, bm = 0, l1 = 0, ecap = 0;
+    int64_t base = 0, gbase = 0, cbase = 0, chunk0 = 0, bm = 0, grp = 0, ecap = 0;
     for (int e = 0; e < P.nens; ++e) {
         const pic_ensemble_desc &D = cfg->ens[e];
         if (D.ncells < 2 || D.ncells > (int64_t)1 << 30 || !(D.dx > 0) || !(D.dt > 0) || !(D.eps0 > 0)) {
@@ -90,14 +91,16 @@ int build_plan(const pic_config *cfg, Plan &P, std::string &msg)
         E.seed = D.seed;
         E.periodic = periodic ? 1 : 0;
         E.nspecies = P.nspecies;
-        // birth ranking: ids below 2 x electron capacity (rounded to 1024)
+        // ids (loaded and born) stay below 2 x electron capacity, rounded to 1024
         int64_t idcap = (2 * D.sp[0].capacity + 2048) / 1024 * 1024;
         idcap = std::min<int64_t>(idcap, ((int64_t)1 << 32) - 1024);
         E.idcap = idcap;
+        // birth ranking: a bit per id (whole 128-byte groups) and a count per kGroupIds ids
         E.bm_base = bm;
-        E.l1_base = l1;
-        bm += idcap / 32;
-        l1 += idcap / 1024;
+        E.grp_base = grp;
+        const int64_t ngrp = (idcap + kGroupIds - 1) / kGroupIds;
+        bm += ngrp * kGroupWords;
+        grp += ngrp;
         for (int s = 0; s < P.nspecies; ++s) {
             const pic_species_desc &sp = D.sp[s];
             if (sp.capacity < sp.ppc * D.ncells || sp.capacity < 1 || sp.ppc < 0 || !(sp.m > 0)) {
@@ -112,7 +115,8 @@ int build_plan(const pic_config *cfg, Plan &P, std::string &msg)
             E.qw[s] = sp.q * sp.w;
             SegC S{};
             S.base = base;
-            S.cap = (sp.capacity + kSlotAlign - 1) / kSlotAlign * kSlotAlign;
+            // at least one aligned slot range, so an empty species still has a tile
+            S.cap = std::max<int64_t>((sp.capacity + kSlotAlign - 1) / kSlotAlign, 1) * kSlotAlign;
             S.cbase = cbase;
             S.gbase = gbase;
             S.ens = e;
@@ -145,13 +149,17 @@ int build_plan(const pic_config *cfg, Plan &P, std::string &msg)
         chunk0 += E.nchunks;
     }
     P.cap_tot = base;
+    P.bm_words = bm;
+    P.g_tot = (grp + 1 + 4095) / 4096 * 4096;  // room for the total; whole scan tiles
+    if (P.cap_tot >= ((int64_t)1 << 32)) {
+        msg = "total particle capacity above 2^32 slots";
+        return PIC_EINVAL;
+    }
     P.nodes_tot = gbase;
     P.cells_tot = cbase;
     P.chunks_tot = chunk0;
-    P.bm_words = bm;
-    P.l1_tot = (l1 + 1 + 4095) / 4096 * 4096;  // single-block scan reads 4096-entry tiles
     P.birth_stripe_cap = std::max<int64_t>(4096, (int64_t)std::ceil(4e-3 * (double)ecap / kStripes));
-    P.scanpart = std::max(scan_blocks(P.l1_tot), scan_blocks(P.cells_tot)) + 1;
+    P.scanpart = std::max(scan_blocks(P.g_tot), scan_blocks(P.cells_tot)) + 1;
     return PIC_OK;
 }
 
@@ -218,12 +226,12 @@ size_t carve(const Plan &P, char *base, Dev &d)
     d.birth_stripe_cap = P.birth_stripe_cap;
     d.births = c.take<Birth>(2 * kStripes * P.birth_stripe_cap);
     d.nbirth = c.take<uint32_t>(2 * kStripes);
+    d.crec = c.take<uint4>(2 * P.cap_tot);
     d.bitmap = c.take<uint32_t>(2 * P.bm_words);
     d.bm_words = P.bm_words;
-    d.l1cnt = c.take<uint32_t>(2 * P.l1_tot);
-    d.l1pre = c.take<uint32_t>(P.l1_tot);
-    d.l1_tot = P.l1_tot;
-    d.cand = c.take<uint32_t>(P.cap_tot);
+    d.gcnt = c.take<uint32_t>(2 * P.g_tot);
+    d.gpre = c.take<uint32_t>(P.g_tot);
+    d.g_tot = P.g_tot;
     d.ctile = c.take<uint32_t>(P.cap_tot / 1024 + 1);
     d.cellcnt = c.take<uint32_t>(P.cells_tot);
     d.cursor = c.take<uint32_t>(P.cells_tot);
@@ -362,9 +370,10 @@ Launch default_launch(const pic_config *cfg, const Plan &P)
 {
     Launch L;
     L.block = cfg->block > 0 ? cfg->block : 256;
-    L.ppt = (cfg->precision == PIC_FP32_CELLOFF) ? 8 : 4;
+    L.ppt = 4;  // particles per thread of the FP32 pass (4 or 8; the autotuner may change it)
     if (cfg->precision == PIC_FP32_CELLOFF && (cfg->ppt == 4 || cfg->ppt == 8)) L.ppt = cfg->ppt;
     L.sort_ppt = (cfg->sort_ppt == 4 || cfg->sort_ppt == 8) ? cfg->sort_ppt : 4;
+    L.nt = cfg->nontemporal ? 1 : 0;
     int64_t tiles = 0;
     for (const SegC &S : P.seg) tiles += (S.cap + (int64_t)L.block * L.ppt - 1) / ((int64_t)L.block * L.ppt);
     int g = cfg->grid > 0 ? cfg->grid : 1024;
@@ -788,6 +797,17 @@ int pic_get_grid(pic_ctx *c, int32_t ens, double *Q0, double *Q1, double *rho, d
     return PIC_OK;
 }
 
+int pic_get_gather_table(pic_ctx *c, int32_t ens, float *out, void *stream)
+{
+    if (!c || !out || ens < 0 || ens >= c->P.nens) return PIC_EINVAL;
+    if (c->P.f64) return fail(c, PIC_EINVAL, "the FP64 form has no gather table");
+    hipStream_t s = (hipStream_t)stream;
+    HIPC(c, hipStreamSynchronize(s));
+    const EnsC &En = c->P.ens[ens];
+    HIPC(c, hipMemcpy(out, c->d.Ecell + En.gbase, En.ncells * sizeof(float2), hipMemcpyDeviceToHost));
+    return PIC_OK;
+}
+
 int pic_set_fields(pic_ctx *c, int32_t ens, const double *E, void *stream)
 {
     if (!c || !E || ens < 0 || ens >= c->P.nens) return PIC_EINVAL;
@@ -1028,12 +1048,19 @@ int pic_autotune(pic_ctx *c, int32_t trial_steps, int32_t *shape, void *stream)
     if (!c->P.f64) {
         const int ppts[2] = {4, 8};
         const int wins[3] = {256, 512, 1024};
-        double best = 1e300;
-        Launch bestL = c->L;
-        for (int pi = 0; pi < 2; ++pi) {
-            for (int wi = 0; wi < 3; ++wi) {
-                c->L.ppt = ppts[pi];
-                c->L.window = wins[wi];
+        const bool verbose = std::getenv("PIC_AUTOTUNE_VERBOSE") != nullptr;
+        // candidates: particles per thread x LDS window x (fused pass only) non-temporal
+        // streaming; two rounds in opposite orders; a candidate's score is the sum of its
+        // two median per-launch pass times, so drift of the run's state between trials
+        // cancels
+        const int ncand = c->cfg.fused ? 12 : 6;
+        double score[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int round = 0; round < 2; ++round) {
+            for (int q = 0; q < ncand; ++q) {
+                const int ci = round == 0 ? q : ncand - 1 - q;
+                c->L.ppt = ppts[(ci % 6) / 3];
+                c->L.window = wins[ci % 3];
+                c->L.nt = ci / 6;
                 // every candidate starts from freshly sorted particles
                 HIPC(c, launch_particles(c->d, c->L, s, false, SB_HIST, 0));
                 HIPC(c, launch_sort(c->d, false, c->L, s));
@@ -1043,15 +1070,32 @@ int pic_autotune(pic_ctx *c, int32_t trial_steps, int32_t *shape, void *stream)
                     HIPC(c, enqueue_step(c, s, is_sort_step(c, c->host_step + 1)));
                     c->host_step += 1;
                 }
-                double ms = 0.0;
-                int64_t n = 0;
-                rc = pic_timing_read(c, &ms, &n, stream);
-                if (rc) return rc;
-                const double avg = n ? ms / (double)n : 1e300;
-                if (avg < best) {
-                    best = avg;
-                    bestL = c->L;
+                HIPC(c, hipStreamSynchronize(s));
+                std::vector<double> v;
+                for (int64_t i = 0; i + 1 < c->ev_used; i += 2) {
+                    float ms = 0.f;
+                    HIPC(c, hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
+                    v.push_back(ms);
                 }
+                double med = 1e300;
+                if (!v.empty()) {
+                    std::sort(v.begin(), v.end());
+                    med = v[v.size() / 2];
+                }
+                score[ci] += med;
+                if (verbose)
+                    std::fprintf(stderr, "pic_autotune: ppt %d window %d nt %d round %d median pass %.4f ms\n",
+                                 c->L.ppt, c->L.window, c->L.nt, round, med);
+            }
+        }
+        Launch bestL = c->L;
+        double best = 1e300;
+        for (int ci = 0; ci < ncand; ++ci) {
+            if (score[ci] < best) {
+                best = score[ci];
+                bestL.ppt = ppts[(ci % 6) / 3];
+                bestL.window = wins[ci % 3];
+                bestL.nt = ci / 6;
             }
         }
         c->L = bestL;
@@ -1092,6 +1136,7 @@ int pic_autotune(pic_ctx *c, int32_t trial_steps, int32_t *shape, void *stream)
         shape[0] = c->L.ppt;
         shape[1] = c->L.window;
         shape[2] = c->L.sort_ppt;
+        shape[3] = c->L.nt;
     }
     return check_err(c, s);
 }

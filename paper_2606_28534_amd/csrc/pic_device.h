@@ -22,7 +22,12 @@ constexpr int kWave = 64;             // CDNA wavefront
 constexpr int32_t kDead = INT32_MIN;  // FP32 form: cell of an absorbed slot
 constexpr int kChunk = 2048;          // nodes per block in the field solve
 constexpr int kSolveThreads = 256;
-constexpr int kIdsPerGroup = 1024;    // ids per birth-rank count (32 bitmap words)
+constexpr int kMaxEns = 256;          // ensembles per context
+// Birth ranking: a bit per parent id and a count per group of kGroupIds ids (a birth's rank
+// among its ensemble's births is the scanned count of the groups below its own plus the
+// bits below it in its group).
+constexpr int kGroupIds = 4096;
+constexpr int kGroupWords = kGroupIds / 32;
 constexpr int kScanBlock = 256;
 constexpr int kScanItems = 16;        // elements per thread in the generic scan
 constexpr double kFix = 16777216.0;   // 2^24 fixed-point scale of the deposit
@@ -35,7 +40,7 @@ enum Cnt : int {
 };
 enum Sum : int { S_KE_L = 0, S_KE_R, S_NSUM };
 // Per-chunk solve aggregates.
-enum Agg : int { A_SUMRHO = 0, A_SUMPRE, A_TOTQ, A_N1, A_D, A_CNT, A_NAGG };
+enum Agg : int { A_SUMRHO = 0, A_SUMPRE, A_TOTQ, A_N1, A_D, A_CNT, A_RHO0, A_NAGG };
 enum Part : int { P_EMAX = 0, P_FE, P_PHISUM, P_NONFIN, P_NPART };
 // Error flags (bit mask).
 enum Err : int { E_CAP_PART = 1, E_CAP_BIRTH = 2, E_CAP_ID = 4, E_NONFINITE = 8 };
@@ -58,7 +63,8 @@ struct SegC {
 struct EnsC {
     int64_t ncells, nnodes, gbase;
     int64_t chunk0, nchunks;  // solve chunks [chunk0, chunk0 + nchunks)
-    int64_t bm_base, l1_base, idcap;  // birth ranking: bitmap words, group counts, id limit
+    int64_t idcap;            // ids stay below this (2 x electron capacity, rounded)
+    int64_t bm_base, grp_base;  // birth ranking: first bitmap word, first id-group count
     double dx, dt, eps0, E_ext, L;
     double qw[2];
     double ngs_el, ngs_iz, ngs_cx, eps_iz, vn, m_e, m_n;
@@ -76,6 +82,8 @@ struct Birth {
     double ve[3];
     double vi[3];
 };
+// the birth placement reads (pid, ens) as one 8-byte key
+static_assert(__builtin_offsetof(Birth, pid) == 0 && __builtin_offsetof(Birth, ens) == 4, "Birth key layout");
 
 // Everything a kernel may touch; passed by value.
 struct Dev {
@@ -112,14 +120,14 @@ struct Dev {
     Birth *births;            // [2][kStripes][birth_stripe_cap]
     uint32_t *nbirth;         // [2][kStripes]
     int64_t birth_stripe_cap;
-    uint32_t *bitmap;         // [2][bm_words] per-ensemble electron-id bitmaps
+    uint32_t *bitmap;         // [2][bm_words] per-ensemble bit per parent id
     int64_t bm_words;
-    uint32_t *l1cnt;          // [2][l1_tot] per-ensemble counts per 1024 ids
-    uint32_t *l1pre;          // [l1_tot] scan of the current half
-    int64_t l1_tot;
+    uint32_t *gcnt;           // [2][g_tot] per-ensemble births per group of kGroupIds ids
+    uint32_t *gpre;           // [g_tot] exclusive scan of the current half's gcnt
+    int64_t g_tot;            // a multiple of 4096
     // null-collision candidates of the FP32 pass: tile t keeps its candidate slots in
     // cand[t * tile .. t * tile + ctile[t])
-    uint32_t *cand;           // [cap_tot]
+    uint4 *crec;              // [2 * cap_tot] collision-candidate records, per tile
     uint32_t *ctile;          // [cap_tot / 1024]
     // sort
     uint32_t *cellcnt, *cursor;  // [cells_tot] over all segments (SegC::cbase)
@@ -208,7 +216,7 @@ __device__ __forceinline__ int wave_min_i32(int v)
 __device__ __forceinline__ unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
 
 // |v|^2 in FP64 from the stored components, summed left to right with no fused
-// multiply-add, so both precisions and the reference take identical collision decisions.
+// multiply-add, so both precisions and the CPU oracle take identical collision decisions.
 __device__ __forceinline__ double speed2_rn(double a, double b, double c)
 {
     return __dadd_rn(__dadd_rn(__dmul_rn(a, a), __dmul_rn(b, b)), __dmul_rn(c, c));
@@ -219,12 +227,25 @@ __device__ __forceinline__ int stripe_of_block() { return (int)(blockIdx.x & (kS
 // One half of the birth buffers.
 struct BirthBuf {
     Birth *births;
-    uint32_t *nbirth, *bitmap, *l1cnt;
+    uint32_t *nbirth, *bitmap, *gcnt;
 };
 __device__ __forceinline__ BirthBuf birth_buf(const Dev &d, int parity)
 {
     return {d.births + (int64_t)parity * kStripes * d.birth_stripe_cap, d.nbirth + parity * kStripes,
-            d.bitmap + (int64_t)parity * d.bm_words, d.l1cnt + (int64_t)parity * d.l1_tot};
+            d.bitmap + (int64_t)parity * d.bm_words, d.gcnt + (int64_t)parity * d.g_tot};
+}
+
+// Record a birth of parent `pid` (its bit and its group count) in one half.
+__device__ __forceinline__ void birth_mark(const BirthBuf &bb, const EnsC &e, uint32_t pid)
+{
+    atomicOr(bb.bitmap + e.bm_base + (pid >> 5), 1u << (pid & 31));
+    atomicAdd(bb.gcnt + e.grp_base + pid / kGroupIds, 1u);
+}
+
+__device__ __forceinline__ void birth_unmark(const BirthBuf &bb, const EnsC &e, uint32_t pid)
+{
+    bb.bitmap[e.bm_base + (pid >> 5)] = 0u;
+    bb.gcnt[e.grp_base + pid / kGroupIds] = 0u;
 }
 
 }  // namespace pic

@@ -288,11 +288,17 @@ __global__ void __launch_bounds__(256) k_particles(Dev d, int W, int hist_rt)
                         ++tal.cx;
                     else if (ch == 1) {
                         ++tal.iz;
-                        // birth record: slot in this block's stripe
+                        // birth record: slot in this block's stripe, or in the next ones
+                        // when it is full
                         const BirthBuf bb = birth_buf(d, (int)(tag & 1u));
-                        const uint32_t slot = atomicAdd(bb.nbirth + st, 1u);
+                        int bst = st;
+                        uint32_t slot = atomicAdd(bb.nbirth + bst, 1u);
+                        for (int a = 1; a < kStripes && (int64_t)slot >= d.birth_stripe_cap; ++a) {
+                            bst = (bst + 1) & (kStripes - 1);
+                            slot = atomicAdd(bb.nbirth + bst, 1u);
+                        }
                         if ((int64_t)slot < d.birth_stripe_cap) {
-                            Birth &B = bb.births[(int64_t)st * d.birth_stripe_cap + slot];
+                            Birth &B = bb.births[(int64_t)bst * d.birth_stripe_cap + slot];
                             B.pid = p[k].id;
                             B.ens = S.ens;
                             if constexpr (!F64) {
@@ -308,8 +314,7 @@ __global__ void __launch_bounds__(256) k_particles(Dev d, int W, int hist_rt)
                                 B.ve[q] = ve[q];
                                 B.vi[q] = vi[q];
                             }
-                            atomicOr(bb.bitmap + e.bm_base + (p[k].id >> 5), 1u << (p[k].id & 31));
-                            atomicAdd(bb.l1cnt + e.l1_base + (p[k].id >> 10), 1u);
+                            birth_mark(bb, e, p[k].id);
                         } else {
                             atomicOr(d.err, (int)E_CAP_BIRTH);
                         }
@@ -585,6 +590,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve1(Dev d)
     double loc = 0.0, sumpre = 0.0, totq = 0.0, n1 = 0.0, dd = 0.0, cnt = 0.0;
     // thread-local prefix of interior rho and its running sum
     double rho_loc[kNodesPerThread];
+    double rho_first = 0.0;  // rho of the chunk's first node (thread 0), for the next chunk's solve
 #pragma unroll
     for (int q = 0; q < kNodesPerThread; ++q) {
         const int64_t j = j0 + q;
@@ -595,6 +601,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve1(Dev d)
             d.rho[e.gbase + j] = r;
             totq += r * V;
         }
+        if (q == 0) rho_first = r;
         rho_loc[q] = (j >= 1 && j <= N - 1) ? r : 0.0;
         loc += rho_loc[q];
     }
@@ -633,6 +640,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve1(Dev d)
         g[A_N1] = v[3];
         g[A_D] = v[4];
         g[A_CNT] = v[5];
+        g[A_RHO0] = rho_first;
     }
 }
 
@@ -667,6 +675,7 @@ template <bool F64>
 __global__ void __launch_bounds__(kSolveThreads) k_solve2(Dev d, int zero_q)
 {
     __shared__ double s_buf[8];
+    __shared__ double s_E[F64 ? 1 : kChunk + 1];  // the chunk's node E, for the gather table
     __shared__ double s_C0, s_F0, s_Eh, s_bg, s_Ctot;
     __shared__ bool s_last;
     const int64_t k = blockIdx.x;
@@ -784,11 +793,40 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve2(Dev d, int zero_q)
             Ej = 0.5 * (Em + Ep);
         }
         d.E[e.gbase + j] = Ej;
+        if constexpr (!F64) s_E[j - a] = Ej;
         if (!isfinite(Ej)) nonfin = 1;
         emax = fmax(emax, fabs(Ej));
         fe += Ej * Ej * node_vol(e, j);
         if (j < N) F += Cj[q];
         Cprev = Cj[q];
+    }
+    if constexpr (!F64) {
+        // Gather table of the chunk's cells, (E_j, E_{j+1} - E_j) in binary32.  The node
+        // after the chunk's last cell is the periodic wrap E_0, or the next chunk's first
+        // node, computed here from this chunk's last C and that node's rho (kept by the
+        // first solve pass, since the next chunk rewrites it with the background).
+        const int64_t L = min((int64_t)kChunk, N - a);
+        if (L > 0) {
+            if (e.periodic && a + L == N) {
+                if (threadIdx.x == 0) s_E[L] = 0.5 * ((Eh + ce * s_Ctot) + (Eh + ce * 0.0));
+            } else if (L == kChunk && threadIdx.x == blockDim.x - 1) {
+                const int64_t jn = a + kChunk;
+                const double rn = d.agg[(k + 1) * A_NAGG + A_RHO0];
+                const double Cl = Cj[kNodesPerThread - 1];  // C_{jn-1}
+                const double Em = Eh + ce * Cl;
+                if (!e.periodic && jn == N) {
+                    s_E[L] = Em + rn * node_vol(e, N) / e.eps0;
+                } else {
+                    const double Cn = Cl + (rn + bg);
+                    s_E[L] = 0.5 * (Em + (Eh + ce * Cn));
+                }
+            }
+        }
+        __syncthreads();
+        for (int64_t j = a + threadIdx.x; j < a + L; j += blockDim.x) {
+            const double E0 = s_E[j - a], E1 = s_E[j - a + 1];
+            d.Ecell[e.gbase + j] = make_float2((float)E0, (float)(E1 - E0));
+        }
     }
     // zero the deposit for the next pass when asked (fused step)
     if (zero_q) {
@@ -869,10 +907,11 @@ __global__ void __launch_bounds__(kSolveThreads) k_phi_shift(Dev d)
     const int ei = chunk_ens(d, k);
     const EnsC &e = d.ens[ei];
     __shared__ double s_mean;
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < kWave) {
         double ps = 0.0;
-        for (int64_t c = 0; c < e.nchunks; ++c) ps += d.part[(e.chunk0 + c) * P_NPART + P_PHISUM];
-        s_mean = ps / (double)e.ncells;
+        for (int64_t c = threadIdx.x; c < e.nchunks; c += kWave) ps += d.part[(e.chunk0 + c) * P_NPART + P_PHISUM];
+        ps = wave_sum_f64(ps);
+        if (threadIdx.x == 0) s_mean = ps / (double)e.ncells;
     }
     __syncthreads();
     const int64_t a = (k - e.chunk0) * kChunk;
@@ -1022,9 +1061,10 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_down(uint32_t *in, uint32_t
 }
 
 // =======================================================================================
-// Births: rank by parent id (bitmap popcounts below the id plus the scanned per-1024-id
-// counts), then write the new electron and ion at slot n_slots + rank with id
-// next_id + rank.  The last block updates the counters.
+// Births: a birth's rank among its ensemble's births of the step is the scanned count of
+// the id groups below its own plus the bits below it in its group's 128 bitmap words.  The
+// new electron and ion go to slot n_slots + rank with id next_id + rank.  The last block
+// updates the counters.
 // =======================================================================================
 __device__ __forceinline__ void birth_locate(const Dev &d, int64_t k, int &st, uint32_t &idx,
                                              const uint32_t *s_pre)
@@ -1057,35 +1097,82 @@ __device__ __forceinline__ void stripe_prefix(const BirthBuf &bb, int64_t cap, u
     if (lane == kStripes - 1) s_pre[kStripes] = inc;
 }
 
-// Births of lower parent id in the same group of 1024 ids: popcount of the group's bitmap
-// words below bit `pid & 1023`.  The group's 32 words are 128-byte aligned.
+// Bits of the group's bitmap below `pid` (the group's words are 128-byte aligned); the
+// words are read as independent 16-byte loads four at a time.
 __device__ __forceinline__ uint32_t rank_in_group(const uint32_t *group, uint32_t pid)
 {
-    const int lim = (int)(pid & 1023u);
-    const uint4 *wv = (const uint4 *)group;
+    const int wp = (int)((pid % kGroupIds) >> 5);  // words wholly below pid
+    const uint4 *v = (const uint4 *)group;
     uint32_t r = 0;
+    int q = 0;
+    for (; 4 * (q + 4) <= wp; q += 4) {
+        uint4 a[4];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const uint4 v = wv[q];
-        const uint32_t ws[4] = {v.x, v.y, v.z, v.w};
+        for (int u = 0; u < 4; ++u) a[u] = v[q + u];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int wb = (q * 4 + t) * 32;
-            const uint32_t m = (wb + 32 <= lim) ? 0xffffffffu : (wb >= lim) ? 0u : ((1u << (lim - wb)) - 1u);
-            r += __popc(ws[t] & m);
-        }
+        for (int u = 0; u < 4; ++u) r += __popc(a[u].x) + __popc(a[u].y) + __popc(a[u].z) + __popc(a[u].w);
     }
+    for (; 4 * (q + 1) <= wp; ++q) {
+        const uint4 a = v[q];
+        r += __popc(a.x) + __popc(a.y) + __popc(a.z) + __popc(a.w);
+    }
+    for (int w = 4 * q; w < wp; ++w) r += __popc(group[w]);
+    r += __popc(group[wp] & ((1u << (pid & 31)) - 1u));
     return r;
 }
 
-// Place the births of this step (half p = step & 1): rank by parent id, write the new
-// electron and ion at slot n_slots + rank with id next_id + rank.  With `deferred`, also
-// clear the bitmap and counts of half 1 - p (the previous step's births) and reset its
+// Exclusive scan of the current half's group counts into gpre by one block: each thread
+// owns a contiguous run of g_tot / blockDim counts (g_tot is a multiple of 4096), sums it,
+// takes one block-wide scan of the sums, then writes its run; the run is read in groups of
+// four independent 16-byte loads so their latencies overlap.
+__global__ void __launch_bounds__(1024) k_group_scan(Dev d)
+{
+    __shared__ uint32_t s_buf[16];
+    const int p = (int)(*d.step & 1);
+    const uint4 *in = (const uint4 *)(d.gcnt + (int64_t)p * d.g_tot);
+    const int64_t per = d.g_tot / (4 * (int64_t)blockDim.x);  // uint4 per thread
+    const int64_t i0 = (int64_t)threadIdx.x * per;
+    uint32_t sum = 0;
+    int64_t i = 0;
+    for (; i + 4 <= per; i += 4) {
+        uint4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = in[i0 + i + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) sum += v[u].x + v[u].y + v[u].z + v[u].w;
+    }
+    for (; i < per; ++i) {
+        const uint4 v = in[i0 + i];
+        sum += v.x + v.y + v.z + v.w;
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_scan_u32(sum, s_buf, tot);
+    uint4 *out = (uint4 *)d.gpre;
+    i = 0;
+    for (; i + 4 <= per; i += 4) {
+        uint4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = in[i0 + i + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            out[i0 + i + u] = make_uint4(ex, ex + v[u].x, ex + v[u].x + v[u].y, ex + v[u].x + v[u].y + v[u].z);
+            ex += v[u].x + v[u].y + v[u].z + v[u].w;
+        }
+    }
+    for (; i < per; ++i) {
+        const uint4 v = in[i0 + i];
+        out[i0 + i] = make_uint4(ex, ex + v.x, ex + v.x + v.y, ex + v.x + v.y + v.z);
+        ex += v.x + v.y + v.z + v.w;
+    }
+}
+
+// Place the births of this step (half p = step & 1).  With `deferred`, also clear the
+// bitmap bits and group counts of half 1 - p (the previous step's births) and reset its
 // birth counts, so the next step starts on a clean half.  The last block updates the
 // counters, makes the freshly accumulated speed maxima current and (with `advance`)
 // advances the step counter.
 template <bool F64>
-__global__ void k_birth_place(Dev d, int deferred, int advance)
+__global__ void __launch_bounds__(256) k_birth_place(Dev d, int deferred, int advance)
 {
     __shared__ uint32_t s_pre[kStripes + 1];
     __shared__ uint32_t s_old[kStripes + 1];
@@ -1104,12 +1191,12 @@ __global__ void k_birth_place(Dev d, int deferred, int advance)
         int st;
         uint32_t idx;
         birth_locate(d, k, st, idx, s_pre);
-        const Birth B = bb.births[(int64_t)st * d.birth_stripe_cap + idx];
+        const Birth &B = bb.births[(int64_t)st * d.birth_stripe_cap + idx];
         const EnsC &e = d.ens[B.ens];
         const uint32_t pid = B.pid;
-        const int64_t g = (int64_t)(pid >> 10);
-        uint32_t r = d.l1pre[e.l1_base + g] - d.l1pre[e.l1_base];
-        r += rank_in_group(bb.bitmap + e.bm_base + (g << 5), pid);
+        const int64_t g = pid / kGroupIds;
+        const uint32_t r = d.gpre[e.grp_base + g] - d.gpre[e.grp_base] +
+                           rank_in_group(bb.bitmap + e.bm_base + g * kGroupWords, pid);
         for (int s = 0; s < e.nspecies; ++s) {
             const int sg = e.seg[s];
             const SegC &S = d.seg[sg];
@@ -1147,9 +1234,7 @@ __global__ void k_birth_place(Dev d, int deferred, int advance)
             uint32_t idx;
             birth_locate(d, k, st, idx, s_old);
             const Birth &B = ob.births[(int64_t)st * d.birth_stripe_cap + idx];
-            const EnsC &e = d.ens[B.ens];
-            ob.bitmap[e.bm_base + (B.pid >> 5)] = 0u;
-            ob.l1cnt[e.l1_base + (B.pid >> 10)] = 0u;
+            birth_unmark(ob, d.ens[B.ens], B.pid);
         }
     }
     __threadfence();
@@ -1160,7 +1245,8 @@ __global__ void k_birth_place(Dev d, int deferred, int advance)
     __threadfence();
     for (int en = threadIdx.x; en < d.nens; en += blockDim.x) {
         const EnsC &e = d.ens[en];
-        const uint32_t m = d.l1pre[e.l1_base + (e.idcap >> 10)] - d.l1pre[e.l1_base];
+        const int64_t ngrp = (e.idcap + kGroupIds - 1) / kGroupIds;
+        const uint32_t m = d.gpre[e.grp_base + ngrp] - d.gpre[e.grp_base];
         for (int s = 0; s < e.nspecies; ++s) {
             const int sg = e.seg[s];
             const SegC &S = d.seg[sg];
@@ -1186,7 +1272,7 @@ __global__ void k_birth_place(Dev d, int deferred, int advance)
     if (threadIdx.x == 0 && advance) *d.step += 1;
 }
 
-// Clear one half (parity -1: the current step's) and reset its counts.
+// Clear one half (parity -1: the current step's): its bits and counts, then its birth counts.
 __global__ void k_birth_clear(Dev d, int parity)
 {
     __shared__ uint32_t s_pre[kStripes + 1];
@@ -1202,9 +1288,7 @@ __global__ void k_birth_clear(Dev d, int parity)
         uint32_t idx;
         birth_locate(d, k, st, idx, s_pre);
         const Birth &B = bb.births[(int64_t)st * d.birth_stripe_cap + idx];
-        const EnsC &e = d.ens[B.ens];
-        bb.bitmap[e.bm_base + (B.pid >> 5)] = 0u;
-        bb.l1cnt[e.l1_base + (B.pid >> 10)] = 0u;
+        birth_unmark(bb, d.ens[B.ens], B.pid);
     }
     __threadfence();
     __syncthreads();
@@ -1214,30 +1298,6 @@ __global__ void k_birth_clear(Dev d, int parity)
     __threadfence();
     for (int i = threadIdx.x; i < kStripes; i += blockDim.x) bb.nbirth[i] = 0u;
     if (threadIdx.x == 0) d.ticket[2] = 0u;
-}
-
-// Single-block exclusive scan of the current half's per-1024-id counts into l1pre: each
-// thread owns a contiguous run of n / 1024 entries (n is a multiple of 4096), sums it,
-// takes one block-wide scan of the sums, then writes its run.
-__global__ void __launch_bounds__(1024) k_l1_scan_small(Dev d)
-{
-    __shared__ uint32_t s_buf[16];
-    const int p = (int)(*d.step & 1);
-    const uint32_t *in = d.l1cnt + (int64_t)p * d.l1_tot;
-    const int64_t per = d.l1_tot / 1024;  // a multiple of 4
-    const int64_t i0 = (int64_t)threadIdx.x * per;
-    uint32_t sum = 0;
-    for (int64_t i = i0; i < i0 + per; i += 4) {
-        const uint4 v = *(const uint4 *)(in + i);
-        sum += v.x + v.y + v.z + v.w;
-    }
-    uint32_t tot;
-    uint32_t ex = block_excl_scan_u32(sum, s_buf, tot);
-    for (int64_t i = i0; i < i0 + per; i += 4) {
-        const uint4 v = *(const uint4 *)(in + i);
-        *(uint4 *)(d.l1pre + i) = make_uint4(ex, ex + v.x, ex + v.x + v.y, ex + v.x + v.y + v.z);
-        ex += v.x + v.y + v.z + v.w;
-    }
 }
 
 __global__ void k_advance(Dev d)
@@ -1449,7 +1509,7 @@ static hipError_t launch_particles_t(const Dev &d, const Launch &L, hipStream_t 
 
 hipError_t launch_particles(const Dev &d, const Launch &L, hipStream_t s, bool f64, int stages, int hist)
 {
-    if (!f64) return launch_pass32(d, L.ppt, L.window, s, stages, hist, d.cap_tot);
+    if (!f64) return launch_pass32(d, L.ppt, L.window, s, stages, hist, d.cap_tot, L.nt != 0);
 #define PIC_CASE(ST)                                                          \
     case ST:                                                                  \
         return f64 ? launch_particles_t<true, ST>(d, L, s, hist)              \
@@ -1522,10 +1582,6 @@ hipError_t launch_solve(const Dev &d, bool f64, int64_t nchunks, bool zero_q, hi
         hipLaunchKernelGGL(k_phi_shift, dim3(nchunks), dim3(kSolveThreads), 0, s, d);
         LAUNCH_CHECK();
     }
-    if (!f64) {
-        hipLaunchKernelGGL(k_ecell, dim3(nchunks), dim3(kSolveThreads), 0, s, d);
-        LAUNCH_CHECK();
-    }
     return hipSuccess;
 }
 
@@ -1570,17 +1626,18 @@ int64_t scan_blocks(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
 hipError_t launch_births(const Dev &d, bool f64, bool in_step, bool advance, hipStream_t s)
 {
     hipError_t e;
-    if (d.l1_tot <= (int64_t)1 << 18) {
-        hipLaunchKernelGGL(k_l1_scan_small, dim3(1), dim3(1024), 0, s, d);
+    // the group-count scan: one block up to 2^18 counts, the three-kernel scan above that
+    if (d.g_tot <= (int64_t)1 << 18) {
+        hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(1024), 0, s, d);
         LAUNCH_CHECK();
-    } else if ((e = launch_scan_sel(d.l1cnt, d.l1pre, d.l1_tot, d.scanpart, false, d.step, s)) != hipSuccess) {
+    } else if ((e = launch_scan_sel(d.gcnt, d.gpre, d.g_tot, d.scanpart, false, d.step, s)) != hipSuccess) {
         return e;
     }
-    const int deferred = in_step ? 1 : 0;
+    const int deferred = in_step ? 1 : 0, adv = advance ? 1 : 0;
     if (f64)
-        hipLaunchKernelGGL(k_birth_place<true>, dim3(64), dim3(256), 0, s, d, deferred, advance ? 1 : 0);
+        hipLaunchKernelGGL(k_birth_place<true>, dim3(64), dim3(256), 0, s, d, deferred, adv);
     else
-        hipLaunchKernelGGL(k_birth_place<false>, dim3(64), dim3(256), 0, s, d, deferred, advance ? 1 : 0);
+        hipLaunchKernelGGL(k_birth_place<false>, dim3(64), dim3(256), 0, s, d, deferred, adv);
     LAUNCH_CHECK();
     if (!in_step) {
         hipLaunchKernelGGL(k_birth_clear, dim3(64), dim3(256), 0, s, d, -1);

@@ -207,7 +207,7 @@ __device__ __forceinline__ void three_normals(uint4 w, T z[3])
     z[2] = r2 * c2;
 }
 
-// Null-collision decision (FP64, no contraction: identical to the reference for identical
+// Null-collision decision (FP64, no contraction: identical to the CPU oracle for identical
 // inputs) and scattering kinematics (in the particle precision).  Returns the channel
 // (-1 none, 0 elastic, 1 ionisation, 2 CX); on ionisation fills the new pair.
 template <bool F64>

@@ -17,6 +17,8 @@
 namespace pic {
 
 enum : int { PS_PUSH = 1, PS_COLLIDE = 2, PS_DEPOSIT = 4, PS_HIST = 8 };
+// collision-candidate records staged in LDS per tile (more go straight to HBM)
+constexpr uint32_t kRecLds = 256;
 
 __device__ __forceinline__ int seg_of_slot(const Dev &d, int64_t slot)
 {
@@ -37,30 +39,43 @@ __device__ __forceinline__ int64_t xcd_tile()
     return (int64_t)(blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
 }
 
-template <int PPT, typename T, typename V>
+typedef uint32_t word4 __attribute__((ext_vector_type(4)));
+
+// PPT consecutive 32-bit values as 16-byte vectors, optionally with the non-temporal hint
+// (the particle arrays are streamed once per step).
+template <int PPT, bool NT, typename T>
 __device__ __forceinline__ void vload(const T *p, T (&v)[PPT])
 {
+    static_assert(sizeof(T) == 4, "32-bit words");
 #pragma unroll
     for (int q = 0; q < PPT; q += 4) {
-        const V t = *(const V *)(p + q);
-        v[q] = t.x;
-        v[q + 1] = t.y;
-        v[q + 2] = t.z;
-        v[q + 3] = t.w;
+        word4 t;
+        if constexpr (NT)
+            t = __builtin_nontemporal_load((const word4 *)(p + q));
+        else
+            t = *(const word4 *)(p + q);
+        // copy the lanes out first: a bit_cast of a vector-element lvalue reads element 0
+        const uint32_t e[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[q + u] = __builtin_bit_cast(T, e[u]);
     }
 }
 
-template <int PPT, typename T, typename V>
+template <int PPT, bool NT, typename T>
 __device__ __forceinline__ void vstore(T *p, const T (&v)[PPT])
 {
+    static_assert(sizeof(T) == 4, "32-bit words");
 #pragma unroll
     for (int q = 0; q < PPT; q += 4) {
-        V t;
-        t.x = v[q];
-        t.y = v[q + 1];
-        t.z = v[q + 2];
-        t.w = v[q + 3];
-        *(V *)(p + q) = t;
+        word4 t;
+        t.x = __builtin_bit_cast(uint32_t, v[q]);
+        t.y = __builtin_bit_cast(uint32_t, v[q + 1]);
+        t.z = __builtin_bit_cast(uint32_t, v[q + 2]);
+        t.w = __builtin_bit_cast(uint32_t, v[q + 3]);
+        if constexpr (NT)
+            __builtin_nontemporal_store(t, (word4 *)(p + q));
+        else
+            *(word4 *)(p + q) = t;
     }
 }
 
@@ -89,7 +104,7 @@ __device__ __forceinline__ void emit_run(const Dev &d, const SegC &S, int s, int
     if (hist) atomicAdd(d.cellcnt + S.cbase + cell, cnt);
 }
 
-template <int STAGES, int PPT>
+template <int STAGES, int PPT, bool NT = false>
 __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64_t T)
 {
     constexpr bool PUSH = STAGES & PS_PUSH;
@@ -109,7 +124,7 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
     __shared__ double s_ke[2];
     __shared__ int s_c0;
     __shared__ uint32_t s_nc;
-    __shared__ uint32_t s_cand[COLL ? TILE : 1];
+    __shared__ uint4 s_rec[COLL ? 2 * kRecLds : 1];
 
     const int64_t t = xcd_tile();
     if (t >= T) return;
@@ -130,14 +145,14 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
     float off[PPT], vx[PPT], vy[PPT], vz[PPT];
     uint32_t id[PPT];
     if (full) {
-        vload<PPT, int32_t, int4>(d.cell[b] + i0, cell);
-        vload<PPT, float, float4>(d.off[b] + i0, off);
+        vload<PPT, NT>(d.cell[b] + i0, cell);
+        vload<PPT, NT>(d.off[b] + i0, off);
         if (NEED_V) {
-            vload<PPT, float, float4>(d.fvx[b] + i0, vx);
-            vload<PPT, float, float4>(d.fvy[b] + i0, vy);
-            vload<PPT, float, float4>(d.fvz[b] + i0, vz);
+            vload<PPT, NT>(d.fvx[b] + i0, vx);
+            vload<PPT, NT>(d.fvy[b] + i0, vy);
+            vload<PPT, NT>(d.fvz[b] + i0, vz);
         }
-        if (COLL) vload<PPT, uint32_t, uint4>(d.id[b] + i0, id);
+        if (COLL) vload<PPT, NT>(d.id[b] + i0, id);
     } else {
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
@@ -153,6 +168,30 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
                 }
                 if (COLL) id[k] = d.id[b][i];
             }
+        }
+    }
+
+    // Issue the gather loads and draw the collision test's random word for every particle
+    // before anything waits on shared memory, so the Philox arithmetic (which needs only the
+    // id) runs while the particle and gather-table loads are still in flight.
+    float2 ec[PUSH ? PPT : 1];
+    if (PUSH) {
+        const float2 *__restrict__ Ecs = d.Ecell + S.gbase;
+        // dead slots (cell = kDead < 0) read entry 0 and are masked in the push
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) ec[k] = Ecs[cell[k] < 0 ? 0u : (uint32_t)cell[k]];
+    }
+    uint32_t rmask = 0;  // bit k: particle k's first Philox word passes R1 < P_null
+    if (COLL) {
+        // Reading R12 decision R1 < P_null, taken exactly as the integer test
+        // (r >> 9) < ceil(P_null 2^23 - 1/2) on the first Philox word of block 0.
+        const double X = d.pnull[sg] * 8388608.0 - 0.5;
+        const uint32_t thr = X <= 0.0 ? 0u : (X >= 8388608.0 ? 8388608u : (uint32_t)ceil(X));
+        const uint32_t tag = (uint32_t)(*d.step);
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const uint4 w = philox(id[k], tag, 0u, 0u, S.seed, (uint32_t)s);
+            rmask |= ((w.x >> 9) < thr ? 1u : 0u) << k;
         }
     }
 
@@ -179,18 +218,13 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
     const int st = stripe_of_block();
 
     if (PUSH) {
-        // segment constants in registers; the gather table entries are fetched up front,
-        // dead slots (cell = kDead < 0) read entry 0 and are masked below, so the loop
-        // below is straight-line code apart from the rare wall branch
+        // segment constants in registers; the loop below is straight-line code apart from
+        // the rare wall branch
         const float h = (float)S.h, dtdx = (float)S.dtdx, eext = (float)e.E_ext;
         const float tv[3] = {(float)S.t[0], (float)S.t[1], (float)S.t[2]};
         const float sv[3] = {(float)S.s[0], (float)S.s[1], (float)S.s[2]};
         const int N = S.ncells;
         const bool per = S.periodic != 0;
-        const float2 *__restrict__ Ecs = d.Ecell + S.gbase;
-        float2 ec[PPT];
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) ec[k] = Ecs[cell[k] < 0 ? 0u : (uint32_t)cell[k]];
         uint32_t nwl = 0, nwr = 0, bad = 0;
         double kel = 0.0, ker = 0.0;
 #pragma unroll
@@ -238,31 +272,40 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
     }
 
     if (COLL) {
-        // Reading R12 decision R1 < P_null, taken exactly as the integer test
-        // (r >> 9) < ceil(P_null 2^23 - 1/2) on the first Philox word.  Candidates (about
-        // P_null of the particles) are listed for k_cand32, which draws the rest of the
-        // block, picks the channel and scatters; all others keep their velocity.
-        const double pnull = d.pnull[sg];
-        const double X = pnull * 8388608.0 - 0.5;
-        const uint32_t thr = X <= 0.0 ? 0u : (X >= 8388608.0 ? 8388608u : (uint32_t)ceil(X));
-        const uint32_t tag = (uint32_t)(*d.step);
-        const uint32_t seed = S.seed;
+        // Candidates (the particles still alive after the push whose test passed, about
+        // P_null of them) are listed for k_cand32, which draws the rest of the block, picks
+        // the channel and scatters; all others keep their velocity.
         float v2f = 0.f;
         uint32_t cmask = 0;
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             const bool alive = cell[k] != kDead;
-            const uint4 w = philox(id[k], tag, 0u, 0u, seed, (uint32_t)s);
-            const bool cand = alive && (w.x >> 9) < thr;
+            const bool cand = alive && ((rmask >> k) & 1u);
             cmask |= (cand ? 1u : 0u) << k;
             const float vv = fmaf(vx[k], vx[k], fmaf(vy[k], vy[k], vz[k] * vz[k]));
             v2f = (alive && !cand) ? fmaxf(v2f, vv) : v2f;
         }
         if (cmask) {
+            // one 32-byte record per candidate with its post-push state, so the candidate
+            // kernel reads contiguous records instead of six scattered words; records are
+            // staged in LDS (the first kRecLds of the tile) and flushed coalesced below
             uint32_t q = atomicAdd(&s_nc, (uint32_t)__popc(cmask));
 #pragma unroll
-            for (int k = 0; k < PPT; ++k)
-                if ((cmask >> k) & 1u) s_cand[q++] = (uint32_t)(i0 + k);
+            for (int k = 0; k < PPT; ++k) {
+                if ((cmask >> k) & 1u) {
+                    const uint4 r0 = make_uint4((uint32_t)(i0 + k), (uint32_t)cell[k], __float_as_uint(off[k]), id[k]);
+                    const uint4 r1 = make_uint4(__float_as_uint(vx[k]), __float_as_uint(vy[k]),
+                                                __float_as_uint(vz[k]), (uint32_t)sg);
+                    if (q < kRecLds) {
+                        s_rec[2 * q] = r0;
+                        s_rec[2 * q + 1] = r1;
+                    } else {
+                        d.crec[2 * (first + q)] = r0;
+                        d.crec[2 * (first + q) + 1] = r1;
+                    }
+                    ++q;
+                }
+            }
         }
         // the speed bound of the next step carries a 2^-16 margin, far above the binary32
         // rounding of |v|^2 here; candidates report their post-collision speed themselves
@@ -273,12 +316,12 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
     if (PUSH || COLL) {
         if (full) {
             if (PUSH) {
-                vstore<PPT, int32_t, int4>(d.cell[b] + i0, cell);
-                vstore<PPT, float, float4>(d.off[b] + i0, off);
+                vstore<PPT, NT>(d.cell[b] + i0, cell);
+                vstore<PPT, NT>(d.off[b] + i0, off);
             }
-            vstore<PPT, float, float4>(d.fvx[b] + i0, vx);
-            vstore<PPT, float, float4>(d.fvy[b] + i0, vy);
-            vstore<PPT, float, float4>(d.fvz[b] + i0, vz);
+            vstore<PPT, NT>(d.fvx[b] + i0, vx);
+            vstore<PPT, NT>(d.fvy[b] + i0, vy);
+            vstore<PPT, NT>(d.fvz[b] + i0, vz);
         } else {
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
@@ -346,9 +389,9 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
         }
     }
     if (COLL) {
-        const uint32_t nc = s_nc;
-        for (uint32_t q = tid; q < nc; q += 256) d.cand[first + q] = s_cand[q];
-        if (tid == 0) d.ctile[t] = nc;
+        const uint32_t nl = 2 * min(s_nc, (uint32_t)kRecLds);
+        for (uint32_t i = tid; i < nl; i += 256) d.crec[2 * first + i] = s_rec[i];
+        if (tid == 0) d.ctile[t] = s_nc;
     }
     if (tid == 0 && (PUSH || COLL)) {
         unsigned long long *c = d.cnt + ((int64_t)st * d.nseg + sg) * C_NCNT;
@@ -366,17 +409,23 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
 
 // =======================================================================================
 // Null-collision candidates of the FP32 pass.  A block takes 16 consecutive tiles; their
-// candidate lists are concatenated through a prefix of the tile counts, one candidate per
-// thread.  Each candidate draws the full Philox block 0 again, picks its channel (FP64
-// decision, as in the reference), scatters, and on ionisation appends the new pair.
+// candidate records (post-push state and slot, written by the pass) are concatenated
+// through a prefix of the tile counts, one candidate per thread.  Each candidate draws the
+// full Philox block 0 again, picks its channel (the FP64 decision the CPU oracle takes),
+// scatters, writes its velocity back to its slot, and on ionisation appends the new pair.
 // Collision counts and the largest post-collision speed go out once per wave when the
 // wave's candidates share a segment (always, unless the 16 tiles straddle a segment end).
 // =======================================================================================
-constexpr int kCandTiles = 16;
+constexpr int kCandTiles = 32;
 
 __global__ void __launch_bounds__(256) k_cand32(Dev d, int tile, int64_t T, int hist)
 {
     __shared__ uint32_t s_pre[kCandTiles + 1];
+    // block tallies per segment, indexed from the segment of the block's first tile (the
+    // block's tiles are consecutive, so they span fewer than kCandTiles segments)
+    __shared__ uint32_t s_n[kCandTiles][3];
+    __shared__ unsigned long long s_v[kCandTiles];
+    __shared__ int s_sg0;
     const int64_t t0 = (int64_t)blockIdx.x * kCandTiles;
     if (threadIdx.x < kWave) {
         // the first wave loads the tile counts in parallel, resets them and scans
@@ -393,100 +442,91 @@ __global__ void __launch_bounds__(256) k_cand32(Dev d, int tile, int64_t T, int 
             const uint32_t n = __shfl_up(inc, o);
             if (k >= o) inc += n;
         }
-        if (k < kCandTiles) s_pre[k] = inc - c;
+        if (k < kCandTiles) {
+            s_pre[k] = inc - c;
+            s_n[k][0] = s_n[k][1] = s_n[k][2] = 0u;
+            s_v[k] = 0ull;
+        }
         if (k == kCandTiles - 1) s_pre[kCandTiles] = inc;
+        if (k == 0) s_sg0 = seg_of_slot(d, t0 * (int64_t)tile);
     }
     __syncthreads();
     const uint32_t m = s_pre[kCandTiles];
     if (m == 0) return;
-    const int lane = lane_id();
+    const int sg0 = s_sg0;
     const int b = *d.cur;
     const uint32_t tag = (uint32_t)(*d.step);
     const BirthBuf bb = birth_buf(d, (int)(tag & 1u));
     const int st = (int)(blockIdx.x & (kStripes - 1));
-    for (uint32_t q0 = 0; q0 < m; q0 += blockDim.x) {
-        const uint32_t q = q0 + threadIdx.x;
-        const bool act = q < m;
-        int sg = -1;
-        uint32_t nel = 0, niz = 0, ncx = 0;
-        double v2m = 0.0;
-        if (act) {
-            int k = 0;
-            while (k + 1 < kCandTiles && s_pre[k + 1] <= q) ++k;
-            const int64_t i = d.cand[(t0 + k) * (int64_t)tile + (q - s_pre[k])];
-            sg = seg_of_slot(d, i);
-            const SegC &S = d.seg[sg];
-            const EnsC &e = d.ens[S.ens];
-            const int s = S.species;
-            PS<false> p;
-            p.cell = d.cell[b][i];
-            p.off = d.off[b][i];
-            p.vx = d.fvx[b][i];
-            p.vy = d.fvy[b][i];
-            p.vz = d.fvz[b][i];
-            p.id = d.id[b][i];
-            double ve[3], vi[3];
-            const int ch = p_collide<false>(e, S, s, d.numax[sg], d.pnull[sg], tag, p, ve, vi);
-            if (ch >= 0) {
-                d.fvx[b][i] = p.vx;
-                d.fvy[b][i] = p.vy;
-                d.fvz[b][i] = p.vz;
-                nel = ch == 0;
-                niz = ch == 1;
-                ncx = ch == 2;
-            }
-            v2m = speed2_rn(p.vx, p.vy, p.vz);
-            if (ch == 1) {
-                const uint32_t slot = atomicAdd(bb.nbirth + st, 1u);
-                if ((int64_t)slot < d.birth_stripe_cap) {
-                    Birth &B = bb.births[(int64_t)st * d.birth_stripe_cap + slot];
-                    B.pid = p.id;
-                    B.ens = S.ens;
-                    B.cell = p.cell;
-                    B.off = p.off;
-                    B.x = ((double)p.cell + (double)p.off) * S.dx;
-                    for (int c = 0; c < 3; ++c) {
-                        B.ve[c] = ve[c];
-                        B.vi[c] = vi[c];
-                    }
-                    atomicOr(bb.bitmap + e.bm_base + (p.id >> 5), 1u << (p.id & 31));
-                    atomicAdd(bb.l1cnt + e.l1_base + (p.id >> 10), 1u);
-                } else {
-                    atomicOr(d.err, (int)E_CAP_BIRTH);
-                }
-                v2m = fmax(v2m, speed2_rn(ve[0], ve[1], ve[2]));
-                if (S.other >= 0) {
-                    const int half = 1 - *d.vcur;
-                    atomicMax(d.vmax2 + ((int64_t)half * kStripes + st) * d.nseg + S.other,
-                              dbits(speed2_rn(vi[0], vi[1], vi[2])));
-                }
-                global_deposit32(d, S, s, p.cell, p.off, hist != 0);
-                if (S.other >= 0) global_deposit32(d, d.seg[S.other], 1, p.cell, p.off, hist != 0);
-            }
+    const int half = 1 - *d.vcur;
+    for (uint32_t q = threadIdx.x; q < m; q += blockDim.x) {
+        int k = 0;
+        while (k + 1 < kCandTiles && s_pre[k + 1] <= q) ++k;
+        const uint4 *r = d.crec + 2 * ((t0 + k) * (int64_t)tile + (q - s_pre[k]));
+        const uint4 r0 = r[0], r1 = r[1];
+        const int64_t i = (int64_t)r0.x;
+        const int sg = (int)r1.w;
+        const SegC &S = d.seg[sg];
+        const EnsC &e = d.ens[S.ens];
+        const int s = S.species;
+        PS<false> p;
+        p.cell = (int)r0.y;
+        p.off = __uint_as_float(r0.z);
+        p.id = r0.w;
+        p.vx = __uint_as_float(r1.x);
+        p.vy = __uint_as_float(r1.y);
+        p.vz = __uint_as_float(r1.z);
+        double ve[3], vi[3];
+        const int ch = p_collide<false>(e, S, s, d.numax[sg], d.pnull[sg], tag, p, ve, vi);
+        if (ch >= 0) {
+            d.fvx[b][i] = p.vx;
+            d.fvy[b][i] = p.vy;
+            d.fvz[b][i] = p.vz;
+            atomicAdd(&s_n[sg - sg0][ch], 1u);
         }
-        // tallies: once per wave when all active lanes share a segment
-        const int sg0 = __shfl(sg, __ffsll((long long)__ballot(act)) - 1);
-        const bool uniform = __ballot(act && sg != sg0) == 0ull;
-        const int half = 1 - *d.vcur;
-        if (uniform) {
-            nel = wave_sum_u32(nel);
-            niz = wave_sum_u32(niz);
-            ncx = wave_sum_u32(ncx);
-            v2m = wave_max_f64(v2m);
-            if (lane == 0 && sg0 >= 0) {
-                unsigned long long *c = d.cnt + ((int64_t)st * d.nseg + sg0) * C_NCNT;
-                if (nel) atomicAdd(c + C_EL, (unsigned long long)nel);
-                if (niz) atomicAdd(c + C_IZ, (unsigned long long)niz);
-                if (ncx) atomicAdd(c + C_CX, (unsigned long long)ncx);
-                if (v2m > 0.0)
-                    atomicMax(d.vmax2 + ((int64_t)half * kStripes + st) * d.nseg + sg0, dbits(v2m));
+        double v2m = speed2_rn(p.vx, p.vy, p.vz);
+        if (ch == 1) {
+            // a stripe per wave; a full stripe passes the birth on to the next ones
+            int bst = (int)((blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) & (kStripes - 1));
+            uint32_t slot = atomicAdd(bb.nbirth + bst, 1u);
+            for (int a = 1; a < kStripes && (int64_t)slot >= d.birth_stripe_cap; ++a) {
+                bst = (bst + 1) & (kStripes - 1);
+                slot = atomicAdd(bb.nbirth + bst, 1u);
             }
-        } else if (act) {
+            if ((int64_t)slot < d.birth_stripe_cap) {
+                Birth &B = bb.births[(int64_t)bst * d.birth_stripe_cap + slot];
+                B.pid = p.id;
+                B.ens = S.ens;
+                B.cell = p.cell;
+                B.off = p.off;
+                B.x = ((double)p.cell + (double)p.off) * S.dx;
+                for (int c = 0; c < 3; ++c) {
+                    B.ve[c] = ve[c];
+                    B.vi[c] = vi[c];
+                }
+                birth_mark(bb, e, p.id);
+            } else {
+                atomicOr(d.err, (int)E_CAP_BIRTH);
+            }
+            v2m = fmax(v2m, speed2_rn(ve[0], ve[1], ve[2]));
+            if (S.other >= 0)
+                atomicMax(d.vmax2 + ((int64_t)half * kStripes + st) * d.nseg + S.other,
+                          dbits(speed2_rn(vi[0], vi[1], vi[2])));
+            global_deposit32(d, S, s, p.cell, p.off, hist != 0);
+            if (S.other >= 0) global_deposit32(d, d.seg[S.other], 1, p.cell, p.off, hist != 0);
+        }
+        if (v2m > 0.0) atomicMax(&s_v[sg - sg0], dbits(v2m));
+    }
+    // one set of counter atomics per block and segment
+    __syncthreads();
+    if (threadIdx.x < kCandTiles) {
+        const int j = threadIdx.x, sg = sg0 + j;
+        if (sg < d.nseg) {
             unsigned long long *c = d.cnt + ((int64_t)st * d.nseg + sg) * C_NCNT;
-            if (nel) atomicAdd(c + C_EL, 1ull);
-            if (niz) atomicAdd(c + C_IZ, 1ull);
-            if (ncx) atomicAdd(c + C_CX, 1ull);
-            if (v2m > 0.0) atomicMax(d.vmax2 + ((int64_t)half * kStripes + st) * d.nseg + sg, dbits(v2m));
+            if (s_n[j][0]) atomicAdd(c + C_EL, (unsigned long long)s_n[j][0]);
+            if (s_n[j][1]) atomicAdd(c + C_IZ, (unsigned long long)s_n[j][1]);
+            if (s_n[j][2]) atomicAdd(c + C_CX, (unsigned long long)s_n[j][2]);
+            if (s_v[j]) atomicMax(d.vmax2 + ((int64_t)half * kStripes + st) * d.nseg + sg, s_v[j]);
         }
     }
 }
@@ -619,20 +659,20 @@ __global__ void k_sort_finish(Dev d)
 
 // =======================================================================================
 hipError_t launch_pass32_stages(const Dev &d, int ppt, int W, hipStream_t s, int stages, int hist,
-                                int64_t cap_tot);
+                                int64_t cap_tot, bool nt);
 
-template <int STAGES>
+template <int STAGES, bool NT = false>
 static hipError_t launch_pass32_t(const Dev &d, int ppt, int W, hipStream_t s, int hist, int64_t cap_tot)
 {
     const size_t lds = (size_t)(W + 1) * 8 + (size_t)W * 4;
     if (ppt == 4) {
         const int64_t T = cap_tot / (256 * 4);
         const int64_t G = (T + 7) / 8 * 8;
-        hipLaunchKernelGGL((k_pass32<STAGES, 4>), dim3(G), dim3(256), lds, s, d, W, hist, T);
+        hipLaunchKernelGGL((k_pass32<STAGES, 4, NT>), dim3(G), dim3(256), lds, s, d, W, hist, T);
     } else {
         const int64_t T = cap_tot / (256 * 8);
         const int64_t G = (T + 7) / 8 * 8;
-        hipLaunchKernelGGL((k_pass32<STAGES, 8>), dim3(G), dim3(256), lds, s, d, W, hist, T);
+        hipLaunchKernelGGL((k_pass32<STAGES, 8, NT>), dim3(G), dim3(256), lds, s, d, W, hist, T);
     }
     return hipGetLastError();
 }
@@ -645,13 +685,17 @@ hipError_t launch_cand32(const Dev &d, int ppt, hipStream_t s, int hist, int64_t
     return hipGetLastError();
 }
 
-hipError_t launch_pass32(const Dev &d, int ppt, int W, hipStream_t s, int stages, int hist, int64_t cap_tot)
+hipError_t launch_pass32(const Dev &d, int ppt, int W, hipStream_t s, int stages, int hist, int64_t cap_tot,
+                         bool nt)
 {
-    return launch_pass32_stages(d, ppt, W, s, stages, hist, cap_tot);
+    return launch_pass32_stages(d, ppt, W, s, stages, hist, cap_tot, nt);
 }
 
-hipError_t launch_pass32_stages(const Dev &d, int ppt, int W, hipStream_t s, int stages, int hist, int64_t cap_tot)
+hipError_t launch_pass32_stages(const Dev &d, int ppt, int W, hipStream_t s, int stages, int hist, int64_t cap_tot,
+                                bool nt)
 {
+    if (nt && stages == (PS_PUSH | PS_COLLIDE | PS_DEPOSIT))
+        return launch_pass32_t<PS_PUSH | PS_COLLIDE | PS_DEPOSIT, true>(d, ppt, W, s, hist, cap_tot);
     switch (stages) {
     case PS_PUSH:
         return launch_pass32_t<PS_PUSH>(d, ppt, W, s, hist, cap_tot);

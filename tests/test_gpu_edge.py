@@ -1,0 +1,173 @@
+"""GPU edge cases of the hot path: empty species, one-cell domains, every particle absorbed
+in one step, zero and near-certain collision probability, capacity overflow reported as an
+error, and bad injected states rejected on the host."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity_util import by_id, compare_particles
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pic():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2606_28534_amd as P
+
+    P.load_library()
+    return P
+
+
+def work_of(e, precision="fp32"):
+    return {"name": "edge", "steps": 1, "precision": precision, "ensembles": [e]}
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_empty_species(pic, prec):
+    """No ions at all (ppc 0): the electrons alone match the oracle; with both species empty
+    every count and the field stay zero."""
+    e = synth.ensemble(96, 20, collisions=False, seed=9)
+    e["species"][1]["ppc"] = 0
+    e["species"][1]["capacity"] = 1
+    sim = pic.Sim(work_of(e, prec), fused=True)
+    o = oracle.Oracle(e)
+    sim.step(6)
+    o.step(6)
+    d, od = sim.diag(), o.diag()
+    assert d["count"] == od["count"] and d["count"][1] == 0
+    assert d["wall_count"] == od["wall_count"]
+    compare_particles(sim.particles(0, 0), o.particles(0), e["dx"], prec == "fp64", vtol=1e-4, xtol=1e-4)
+    sim.close()
+    e2 = synth.ensemble(50, 0, collisions=True, seed=2)
+    for sp in e2["species"]:
+        sp["capacity"] = 1
+    sim2 = pic.Sim(work_of(e2, prec), fused=True)
+    sim2.step(3)
+    d2 = sim2.diag()
+    assert d2["count"] == [0, 0] and d2["pushes"] == 0 and d2["coll"] == [0, 0, 0]
+    assert np.all(sim2.grid()["E"] == 0.0)
+    sim2.close()
+
+
+def test_one_cell_domain_rejected(pic):
+    """The library needs N >= 2 cells (it states so in its header): one cell is refused."""
+    e = synth.ensemble(1, 300, collisions=False, seed=4)
+    with pytest.raises(pic.PicError) as ei:
+        pic.Sim(work_of(e), fused=True)
+    assert ei.value.code == pic.PIC_EINVAL
+
+
+@pytest.mark.parametrize("ncells", [2, 3])
+def test_tiny_domain(pic, ncells):
+    """Two and three cells between the walls: steps match the oracle (walls exact)."""
+    e = synth.ensemble(ncells, 300, collisions=False, seed=4, B=synth.oblique_B())
+    sim = pic.Sim(work_of(e), fused=True)
+    o = oracle.Oracle(e)
+    for _ in range(3):
+        sim.step(1)
+        o.step(1)
+        d, od = sim.diag(), o.diag()
+        assert d["wall_count"] == od["wall_count"]
+        assert d["count"] == od["count"]
+    for s in range(2):
+        compare_particles(sim.particles(0, s), o.particles(s), e["dx"], False, vtol=1e-4, xtol=1e-4)
+
+
+def test_everything_absorbed(pic):
+    """Electrons far faster than the domain is long all leave in the first step; the walls
+    tally every one, the next sort compacts them away and later steps run on what is left."""
+    e = synth.ensemble(8, 50, collisions=False, seed=6, T_e=1e8, sort_every=1)
+    sim = pic.Sim(work_of(e), fused=True)
+    o = oracle.Oracle(e)
+    sim.step(1)
+    o.step(1)
+    d, od = sim.diag(), o.diag()
+    assert d["wall_count"] == od["wall_count"]
+    assert d["count"][0] == od["count"][0]
+    n = e["species"][0]["ppc"] * e["ncells"]
+    assert d["wall_count"][0][0] + d["wall_count"][1][0] >= 0.98 * n
+    sim.step(3)
+    o.step(3)
+    assert sim.diag()["count"] == o.diag()["count"]
+    assert len(sim.particles(0, 0)["id"]) == o.diag()["count"][0]
+
+
+def test_zero_collision_rate_is_collisionless(pic):
+    """With every n_g sigma zero the null-collision bound is zero and no particle is a
+    candidate: the run is bit-identical to the collisionless one."""
+    e = synth.ensemble(300, 30, collisions=True, seed=12, B=synth.oblique_B())
+    e["ngs_el"] = e["ngs_iz"] = e["ngs_cx"] = 0.0
+    e2 = dict(e, collisions=False)
+    a, b = pic.Sim(work_of(e), fused=True), pic.Sim(work_of(e2), fused=True)
+    a.step(12)
+    b.step(12)
+    assert a.diag()["coll"] == [0, 0, 0]
+    for s in range(2):
+        pa, pb = by_id(a.particles(0, s)), by_id(b.particles(0, s))
+        for k in ("id", "x", "vx", "vy", "vz"):
+            assert np.array_equal(pa[k], pb[k]), (s, k)
+
+
+def test_near_certain_collisions(pic):
+    """n_g sigma so large that P_null is close to one: nearly every particle is a candidate,
+    so the candidate list is full in every tile.  Decisions and channels match the oracle."""
+    N = 40
+    e = synth.ensemble(N, 1, seed=21)
+    e["ngs_el"], e["ngs_iz"], e["ngs_cx"] = 30.0, 20.0, 5000.0
+    n = 40000
+    for sp in e["species"]:
+        sp["capacity"] = 3 * n
+    st = synth.random_state(e, [n, n], seed=31, vscale=[2.0, 3e-2])
+    sim = pic.Sim(work_of(e), fused=False)
+    sim.set_state(st)
+    sim.set_fields(np.zeros(sim.nnodes()))
+    sim.set_step(3)
+    o = oracle.Oracle(e, init=False)
+    o.set_state(st)
+    o.set_fields(np.zeros(o.nnodes))
+    o.set_step(3)
+    sim.collide()
+    o.collide()
+    gd, od = sim.diag(), o.diag()
+    assert gd["coll"] == od["coll"]
+    assert gd["created"] == od["created"]
+    assert sum(gd["coll"]) > 0.2 * 2 * n
+    for s in range(2):
+        compare_particles(sim.particles(0, s), o.particles(s), e["dx"], False, vtol=1e-5)
+
+
+def test_capacity_overflow_is_reported(pic):
+    """Ionisation that creates more pairs than the capacity holds: the step reports
+    PIC_ECAPACITY (the kernels drop what does not fit) instead of writing out of bounds."""
+    e = synth.ensemble(64, 50, seed=5)
+    e["ngs_iz"], e["eps_iz"] = 50.0, 0.01
+    for sp in e["species"]:
+        sp["capacity"] = sp["ppc"] * e["ncells"] + 8
+    sim = pic.Sim(work_of(e), fused=True)
+    with pytest.raises(pic.PicError) as ei:
+        sim.step(3)
+    assert ei.value.code == pic.PIC_ECAPACITY
+    sim.close()
+
+
+def test_bad_injected_state_rejected(pic):
+    e = synth.ensemble(32, 4, collisions=False, seed=1)
+    sim = pic.Sim(work_of(e), fused=False)
+    st = synth.random_state(e, [100, 100], seed=2)[0]
+    L = e["ncells"] * e["dx"]
+    bad = [dict(st, vx=np.where(np.arange(100) == 7, np.nan, st["vx"])),
+           dict(st, x=np.where(np.arange(100) == 3, L, st["x"])),
+           dict(st, x=np.where(np.arange(100) == 3, -0.1, st["x"])),
+           dict(st, id=np.where(np.arange(100) == 5, 2 ** 31, st["id"]).astype(np.uint32))]
+    for b in bad:
+        with pytest.raises(pic.PicError) as ei:
+            sim.set_particles(0, 0, b["x"], b["vx"], b["vy"], b["vz"], b["id"], b["next_id"])
+        assert ei.value.code == pic.PIC_EINVAL
+    # a good state still goes in afterwards
+    sim.set_particles(0, 0, st["x"], st["vx"], st["vy"], st["vz"], st["id"], st["next_id"])
+    assert len(sim.particles(0, 0)["id"]) == 100

@@ -105,6 +105,35 @@ def test_deposit_and_solve_from_injected_state(pic, prec, periodic):
         assert rel(g[k], r[k]) <= tol, (k, rel(g[k], r[k]))
 
 
+@pytest.mark.parametrize("periodic", [False, True])
+def test_gather_table_matches_node_field(pic, periodic):
+    """The FP32 gather table (E_j, E_{j+1} - E_j) built by the solve, across solve-chunk
+    boundaries (2048 nodes a chunk) and at sizes that are exact multiples of a chunk, against
+    the node field the same solve returns, and the node field against the oracle."""
+    for N in (5, 2047, 2048, 4096, 6661):
+        e = ens_small(ncells=N, ppc=3, periodic=periodic, capacity=4 * N + 64)
+        st = synth.random_state(e, [3 * N + 7, 3 * N + 1], seed=N + 11)
+        sim = pic.Sim(work_of(e, "fp32"), fused=False)
+        sim.set_state(st)
+        o = oracle.Oracle(e, init=False)
+        o.set_state(st)
+        sim.deposit()
+        o.deposit()
+        sim.solve()
+        o.solve()
+        E = sim.grid()["E"]
+        assert rel(E, o.grid()["E"]) <= TOL_FIELD, N
+        t = sim.gather_table()
+        E1 = np.append(E[1:], E[0]) if periodic else E[1:]
+        E0 = E[:N]
+        assert np.array_equal(t[:, 0], E0.astype(np.float32)), N
+        d = E1 - E0
+        # the node after a chunk's last cell is recomputed by that chunk: it may differ from
+        # the stored E in the last FP64 bit, which can move the binary32 rounding by one unit
+        err = np.abs(t[:, 1].astype(np.float64) - d)
+        assert np.all(err <= 2.0 ** -23 * np.abs(d) + 2.0 ** -50 * np.max(np.abs(E))), N
+
+
 def test_scan_solve_equals_thomas_fp64(pic):
     """The two-prefix-sum solve against the oracle's Thomas solve on the same charge."""
     for N in (2, 3, 2047, 2048, 2049, 10007):

@@ -34,7 +34,7 @@ def test_exports_every_declared_symbol(lib):
 
 def test_workspace_query_sizes(lib):
     P, L = lib
-    for work, lo, hi in ((synth.c2_sheath(), 1.5e9, 4e9), (synth.c1_plain_small(), 1e6, 2e8)):
+    for work, lo, hi in ((synth.c2_sheath(), 1.5e9, 5e9), (synth.c1_plain_small(), 1e6, 2e8)):
         cfg, keep = P.make_config(work)
         n = C.c_size_t(0)
         assert L.pic_query_workspace(C.byref(cfg), C.byref(n)) == 0
@@ -43,7 +43,7 @@ def test_workspace_query_sizes(lib):
     cfg, keep = P.make_config(synth.c5_large())
     n = C.c_size_t(0)
     assert L.pic_query_workspace(C.byref(cfg), C.byref(n)) == 0
-    assert n.value < 100e9
+    assert n.value < 150e9  # fits one 288 GB MI355X with room to spare
 
 
 def test_bad_configs_rejected(lib):
