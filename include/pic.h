@@ -89,8 +89,9 @@ typedef struct {
     int32_t window;      /* LDS deposit window in nodes (power of two); 0 = default        */
     int32_t ppt;         /* particles per thread of the FP32 pass (4 or 8); 0 = default    */
     int32_t sort_ppt;    /* particles per thread of the FP32 sort scatter; 0 = default     */
-    int32_t nontemporal; /* 1: the fused FP32 pass streams particles with non-temporal
-                          * loads and stores; 0 = ordinary (default)                        */
+    int32_t nontemporal; /* bit 0: the fused FP32 pass streams particles with non-temporal
+                          * loads and stores; bit 1: so does the FP32 sort scatter;
+                          * 0 = ordinary cached accesses (default)                         */
     const pic_ensemble_desc *ens;              /* [n_ensembles], copied by pic_init       */
 } pic_config;
 
@@ -218,7 +219,8 @@ int pic_adjoint_window(pic_ctx *ctx, int32_t nsteps, int32_t ckpt_every, void *s
 /* The library's autotuner: times the particle pass over `trial_steps` steps for every
  * candidate launch shape (particles per thread x LDS window) and the sort scatter for each
  * particles-per-thread choice, all with HIP events on `stream`, keeps the fastest, and
- * writes {ppt, window, sort_ppt, nontemporal} to `shape` (4 ints, may be NULL).  The trial steps advance the
+ * writes {ppt, window, sort_ppt, pass non-temporal, sort non-temporal} to `shape`
+ * (5 ints, may be NULL).  The trial steps advance the
  * run like pic_step (the sort is repeated on already-sorted data, which leaves the state
  * unchanged apart from slot order). */
 int pic_autotune(pic_ctx *ctx, int32_t trial_steps, int32_t *shape, void *stream);

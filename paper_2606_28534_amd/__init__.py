@@ -246,10 +246,10 @@ class Sim:
 
     def autotune(self, trial_steps=10):
         """Let the library time its launch shapes and keep the fastest; returns the shape."""
-        shape = np.zeros(4, dtype=np.int32)
+        shape = np.zeros(5, dtype=np.int32)
         self._check(self.L.pic_autotune(self.h, int(trial_steps), _ptr(shape), self._s()))
         return {"ppt": int(shape[0]), "window": int(shape[1]), "sort_ppt": int(shape[2]),
-                "nontemporal": int(shape[3])}
+                "nontemporal": int(shape[3]) | (int(shape[4]) << 1)}
 
     def timing(self, enable=True):
         self._check(self.L.pic_timing(self.h, int(bool(enable))))

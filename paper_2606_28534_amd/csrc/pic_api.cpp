@@ -158,7 +158,8 @@ int build_plan(const pic_config *cfg, Plan &P, std::string &msg)
     P.nodes_tot = gbase;
     P.cells_tot = cbase;
     P.chunks_tot = chunk0;
-    P.birth_stripe_cap = std::max<int64_t>(4096, (int64_t)std::ceil(4e-3 * (double)ecap / kStripes));
+    // births per step are ~5e-4 of the electrons; each stripe holds up to 1.5e-4 of them
+    P.birth_stripe_cap = std::max<int64_t>(8192, (int64_t)std::ceil(1.5e-4 * (double)ecap));
     P.scanpart = std::max(scan_blocks(P.g_tot), scan_blocks(P.cells_tot)) + 1;
     return PIC_OK;
 }
@@ -219,10 +220,10 @@ size_t carve(const Plan &P, char *base, Dev &d)
     d.fe = c.take<double>(P.nens);
     d.numax = c.take<double>(P.nseg);
     d.pnull = c.take<double>(P.nseg);
-    d.vmax2 = c.take<unsigned long long>(2 * kStripes * P.nseg);
+    d.vmax2 = c.take<unsigned long long>(2 * kCntStripes * P.nseg);
     d.vcur = c.take<int32_t>(1);
-    d.cnt = c.take<unsigned long long>((int64_t)kStripes * P.nseg * C_NCNT);
-    d.sums = c.take<double>((int64_t)kStripes * P.nseg * S_NSUM);
+    d.cnt = c.take<unsigned long long>((int64_t)kCntStripes * P.nseg * C_NCNT);
+    d.sums = c.take<double>((int64_t)kCntStripes * P.nseg * S_NSUM);
     d.birth_stripe_cap = P.birth_stripe_cap;
     d.births = c.take<Birth>(2 * kStripes * P.birth_stripe_cap);
     d.nbirth = c.take<uint32_t>(2 * kStripes);
@@ -373,7 +374,8 @@ Launch default_launch(const pic_config *cfg, const Plan &P)
     L.ppt = 4;  // particles per thread of the FP32 pass (4 or 8; the autotuner may change it)
     if (cfg->precision == PIC_FP32_CELLOFF && (cfg->ppt == 4 || cfg->ppt == 8)) L.ppt = cfg->ppt;
     L.sort_ppt = (cfg->sort_ppt == 4 || cfg->sort_ppt == 8) ? cfg->sort_ppt : 4;
-    L.nt = cfg->nontemporal ? 1 : 0;
+    L.nt = (cfg->nontemporal & 1) ? 1 : 0;
+    L.sort_nt = (cfg->nontemporal & 2) ? 1 : 0;
     int64_t tiles = 0;
     for (const SegC &S : P.seg) tiles += (S.cap + (int64_t)L.block * L.ppt - 1) / ((int64_t)L.block * L.ppt);
     int g = cfg->grid > 0 ? cfg->grid : 1024;
@@ -553,8 +555,8 @@ int pic_diag(pic_ctx *c, int32_t ens, pic_diag_out *out, void *stream)
     if (!c || !out || ens < 0 || ens >= c->P.nens) return PIC_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const int nseg = c->P.nseg;
-    std::vector<unsigned long long> cnt((size_t)kStripes * nseg * C_NCNT);
-    std::vector<double> sums((size_t)kStripes * nseg * S_NSUM);
+    std::vector<unsigned long long> cnt((size_t)kCntStripes * nseg * C_NCNT);
+    std::vector<double> sums((size_t)kCntStripes * nseg * S_NSUM);
     HIPC(c, hipMemcpyAsync(cnt.data(), c->d.cnt, cnt.size() * 8, hipMemcpyDeviceToHost, s));
     HIPC(c, hipMemcpyAsync(sums.data(), c->d.sums, sums.size() * 8, hipMemcpyDeviceToHost, s));
     double emax = 0, fe = 0;
@@ -583,7 +585,7 @@ int pic_diag(pic_ctx *c, int32_t ens, pic_diag_out *out, void *stream)
         out->charge += D.q * D.w * n;
         unsigned long long a[C_NCNT] = {0};
         double kl = 0, kr = 0;
-        for (int st = 0; st < kStripes; ++st) {
+        for (int st = 0; st < kCntStripes; ++st) {
             for (int k = 0; k < C_NCNT; ++k) a[k] += cnt[((size_t)st * nseg + sg) * C_NCNT + k];
             kl += sums[((size_t)st * nseg + sg) * S_NSUM + S_KE_L];
             kr += sums[((size_t)st * nseg + sg) * S_NSUM + S_KE_R];
@@ -762,7 +764,7 @@ int pic_set_particles(pic_ctx *c, int32_t ens, int32_t species, pic_particles in
     // the speed maxima of the current half are recomputed for every segment
     int32_t vc = 0;
     HIPC(c, hipMemcpy(&vc, c->d.vcur, 4, hipMemcpyDeviceToHost));
-    HIPC(c, hipMemset(c->d.vmax2 + (size_t)vc * kStripes * c->P.nseg, 0, (size_t)kStripes * c->P.nseg * 8));
+    HIPC(c, hipMemset(c->d.vmax2 + (size_t)vc * kCntStripes * c->P.nseg, 0, (size_t)kCntStripes * c->P.nseg * 8));
     HIPC(c, launch_vmax(c->d, c->P.f64, s));
     HIPC(c, hipStreamSynchronize(s));
     return PIC_OK;
@@ -1100,30 +1102,36 @@ int pic_autotune(pic_ctx *c, int32_t trial_steps, int32_t *shape, void *stream)
         }
         c->L = bestL;
         pic_timing(c, 0);
-        // sort scatter: repeated sorts of sorted data
+        // sort scatter: particles per thread x non-temporal streaming, each timed on one
+        // histogram + sort after a few steps of motion since the last sort
         hipEvent_t e0, e1;
         HIPC(c, hipEventCreate(&e0));
         HIPC(c, hipEventCreate(&e1));
         double bests = 1e300;
-        int bestp = c->L.sort_ppt;
-        for (int pi = 0; pi < 2; ++pi) {
-            c->L.sort_ppt = ppts[pi];
+        int bestp = c->L.sort_ppt, bestnt = c->L.sort_nt;
+        for (int ci = 0; ci < 4; ++ci) {
+            c->L.sort_ppt = ppts[ci % 2];
+            c->L.sort_nt = ci / 2;
+            for (int t = 0; t < std::max(trial_steps / 2, 2); ++t) {
+                HIPC(c, enqueue_step(c, s, false));
+                c->host_step += 1;
+            }
+            HIPC(c, hipEventRecord(e0, s));
             HIPC(c, launch_particles(c->d, c->L, s, false, SB_HIST, 0));
             HIPC(c, launch_sort(c->d, false, c->L, s));
-            HIPC(c, hipEventRecord(e0, s));
-            for (int r = 0; r < 3; ++r) {
-                HIPC(c, launch_particles(c->d, c->L, s, false, SB_HIST, 0));
-                HIPC(c, launch_sort(c->d, false, c->L, s));
-            }
             HIPC(c, hipEventRecord(e1, s));
             HIPC(c, hipEventSynchronize(e1));
             float ms = 0.f;
             HIPC(c, hipEventElapsedTime(&ms, e0, e1));
+            if (verbose)
+                std::fprintf(stderr, "pic_autotune: sort ppt %d nt %d %.4f ms\n", c->L.sort_ppt, c->L.sort_nt, ms);
             if (ms < bests) {
                 bests = ms;
-                bestp = ppts[pi];
+                bestp = c->L.sort_ppt;
+                bestnt = c->L.sort_nt;
             }
         }
+        c->L.sort_nt = bestnt;
         c->L.sort_ppt = bestp;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -1137,6 +1145,7 @@ int pic_autotune(pic_ctx *c, int32_t trial_steps, int32_t *shape, void *stream)
         shape[1] = c->L.window;
         shape[2] = c->L.sort_ppt;
         shape[3] = c->L.nt;
+        shape[4] = c->L.sort_nt;
     }
     return check_err(c, s);
 }

@@ -17,7 +17,8 @@
 
 namespace pic {
 
-constexpr int kStripes = 32;          // striped atomic counters
+constexpr int kStripes = 32;          // stripes of the birth list
+constexpr int kCntStripes = 256;      // stripes of the counters, sums and speed maxima
 constexpr int kWave = 64;             // CDNA wavefront
 constexpr int32_t kDead = INT32_MIN;  // FP32 form: cell of an absorbed slot
 constexpr int kChunk = 2048;          // nodes per block in the field solve
@@ -111,10 +112,10 @@ struct Dev {
     double *emax, *fe;        // [nens]
     double *numax, *pnull;    // [nseg]
     // tallies
-    unsigned long long *vmax2;  // [2][kStripes][nseg] max |v|^2 as double bits
+    unsigned long long *vmax2;  // [2][kCntStripes][nseg] max |v|^2 as double bits
     int32_t *vcur;            // [1] which vmax2 half holds the current maxima
-    unsigned long long *cnt;  // [kStripes][nseg][C_NCNT]
-    double *sums;             // [kStripes][nseg][S_NSUM]
+    unsigned long long *cnt;  // [kCntStripes][nseg][C_NCNT]
+    double *sums;             // [kCntStripes][nseg][S_NSUM]
     // births, double-buffered by step parity: step n appends to half n & 1 and its
     // placement clears half (n + 1) & 1, which step n - 1 used
     Birth *births;            // [2][kStripes][birth_stripe_cap]
@@ -222,7 +223,7 @@ __device__ __forceinline__ double speed2_rn(double a, double b, double c)
     return __dadd_rn(__dadd_rn(__dmul_rn(a, a), __dmul_rn(b, b)), __dmul_rn(c, c));
 }
 
-__device__ __forceinline__ int stripe_of_block() { return (int)(blockIdx.x & (kStripes - 1)); }
+__device__ __forceinline__ int stripe_of_block() { return (int)(blockIdx.x & (kCntStripes - 1)); }
 
 // One half of the birth buffers.
 struct BirthBuf {

@@ -14,6 +14,7 @@ struct Launch {
     int window;  // LDS deposit / sort window in cells
     int sort_ppt;  // particles per thread of the FP32 sort scatter
     int nt;        // fused FP32 pass: non-temporal particle loads and stores
+    int sort_nt;   // FP32 sort scatter: non-temporal loads and stores
 };
 
 enum StageBits : int { SB_PUSH = 1, SB_COLLIDE = 2, SB_DEPOSIT = 4, SB_HIST = 8 };
@@ -38,7 +39,7 @@ hipError_t launch_sort(const Dev &d, bool f64, const Launch &L, hipStream_t s);
 hipError_t launch_pass32(const Dev &d, int ppt, int W, hipStream_t s, int stages, int hist, int64_t cap_tot,
                          bool nt);
 hipError_t launch_cand32(const Dev &d, int ppt, hipStream_t s, int hist, int64_t cap_tot);
-hipError_t launch_sort32_scatter(const Dev &d, int ppt, int W, hipStream_t s, int64_t cap_tot);
+hipError_t launch_sort32_scatter(const Dev &d, int ppt, int W, hipStream_t s, int64_t cap_tot, bool nt);
 hipError_t launch_adj_seed(const double *E, double *lE, int N, double eps0, double dx, hipStream_t s);
 hipError_t launch_adj_a(const Dev &d, const int32_t *xc, const float *xo, const double *E, double *lx,
                         double *lv, double *lE, double *lEext, int64_t n, double dt, double qm,

@@ -113,7 +113,7 @@ __device__ void flush_tally(const Dev &d, int seg, Tally &t, bool want_vmax)
         if (a[7] != 0.0) unsafeAtomicAdd(sm + S_KE_R, a[7]);
         if (want_vmax && a[8] > 0.0) {
             const int half = 1 - *d.vcur;
-            atomicMax(d.vmax2 + ((int64_t)half * kStripes + st) * d.nseg + seg, dbits(a[8]));
+            atomicMax(d.vmax2 + ((int64_t)half * kCntStripes + st) * d.nseg + seg, dbits(a[8]));
         }
     }
     __syncthreads();
@@ -291,7 +291,7 @@ __global__ void __launch_bounds__(256) k_particles(Dev d, int W, int hist_rt)
                         // birth record: slot in this block's stripe, or in the next ones
                         // when it is full
                         const BirthBuf bb = birth_buf(d, (int)(tag & 1u));
-                        int bst = st;
+                        int bst = st & (kStripes - 1);
                         uint32_t slot = atomicAdd(bb.nbirth + bst, 1u);
                         for (int a = 1; a < kStripes && (int64_t)slot >= d.birth_stripe_cap; ++a) {
                             bst = (bst + 1) & (kStripes - 1);
@@ -323,7 +323,7 @@ __global__ void __launch_bounds__(256) k_particles(Dev d, int W, int hist_rt)
                         if (S.other >= 0) {
                             const double vi2 = speed2_rn(vi[0], vi[1], vi[2]);
                             const int half = 1 - *d.vcur;
-                            atomicMax(d.vmax2 + ((int64_t)half * kStripes + st) * d.nseg + S.other,
+                            atomicMax(d.vmax2 + ((int64_t)half * kCntStripes + st) * d.nseg + S.other,
                                       dbits(vi2));
                         }
                         if (DEPO) {
@@ -471,7 +471,7 @@ __global__ void k_vmax(Dev d)
         for (int i = 1; i < (int)(blockDim.x / kWave); ++i) m = fmax(m, s_m[i]);
         const int half = *d.vcur;
         if (m > 0.0)
-            atomicMax(d.vmax2 + ((int64_t)half * kStripes + stripe_of_block()) * d.nseg + sg, dbits(m));
+            atomicMax(d.vmax2 + ((int64_t)half * kCntStripes + stripe_of_block()) * d.nseg + sg, dbits(m));
     }
 }
 
@@ -655,8 +655,8 @@ __device__ void compute_params(const Dev &d)
         const EnsC &e = d.ens[S.ens];
         // squared speeds are non-negative doubles: their bit patterns order as integers
         double m2 = 0.0;
-        if (lane < kStripes)
-            m2 = __longlong_as_double((long long)d.vmax2[((int64_t)half * kStripes + lane) * d.nseg + sg]);
+        for (int st = lane; st < kCntStripes; st += kWave)
+            m2 = fmax(m2, __longlong_as_double((long long)d.vmax2[((int64_t)half * kCntStripes + st) * d.nseg + sg]));
         m2 = wave_max_f64(m2);
         if (lane == 0) {
             const double vmax = __dsqrt_rn(m2);
@@ -1265,8 +1265,8 @@ __global__ void __launch_bounds__(256) k_birth_place(Dev d, int deferred, int ad
     __syncthreads();
     {
         const int old = 1 - *d.vcur;
-        for (int64_t i = threadIdx.x; i < (int64_t)kStripes * d.nseg; i += blockDim.x)
-            d.vmax2[(int64_t)old * kStripes * d.nseg + i] = 0ull;
+        for (int64_t i = threadIdx.x; i < (int64_t)kCntStripes * d.nseg; i += blockDim.x)
+            d.vmax2[(int64_t)old * kCntStripes * d.nseg + i] = 0ull;
     }
     __syncthreads();
     if (threadIdx.x == 0 && advance) *d.step += 1;
@@ -1666,7 +1666,7 @@ hipError_t launch_sort(const Dev &d, bool f64, const Launch &L, hipStream_t s)
     hipError_t e = launch_scan(d.cellcnt, d.cursor, d.cells_tot, d.scanpart, true, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_segstart, dim3(1), dim3(256), 0, s, d);
-    if (!f64) return launch_sort32_scatter(d, L.sort_ppt, L.window, s, d.cap_tot);
+    if (!f64) return launch_sort32_scatter(d, L.sort_ppt, L.window, s, d.cap_tot, L.sort_nt != 0);
     const size_t lds = (size_t)L.window * 4;
     if (f64)
         hipLaunchKernelGGL((k_sort_scatter<true, 4>), dim3(L.grid), dim3(L.block), lds, s, d, L.window);

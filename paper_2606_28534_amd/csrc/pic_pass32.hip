@@ -402,7 +402,7 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
         if (s_ke[1] != 0.0) unsafeAtomicAdd(sm + S_KE_R, s_ke[1]);
         if (COLL && s_v2) {
             const int half = 1 - *d.vcur;
-            atomicMax(d.vmax2 + ((int64_t)half * kStripes + st) * d.nseg + sg, s_v2);
+            atomicMax(d.vmax2 + ((int64_t)half * kCntStripes + st) * d.nseg + sg, s_v2);
         }
     }
 }
@@ -422,10 +422,13 @@ __global__ void __launch_bounds__(256) k_cand32(Dev d, int tile, int64_t T, int 
 {
     __shared__ uint32_t s_pre[kCandTiles + 1];
     // block tallies per segment, indexed from the segment of the block's first tile (the
-    // block's tiles are consecutive, so they span fewer than kCandTiles segments)
+    // block's tiles are consecutive, so they span fewer than kCandTiles segments; the last
+    // entry takes the ion segment after them)
     __shared__ uint32_t s_n[kCandTiles][3];
-    __shared__ unsigned long long s_v[kCandTiles];
+    __shared__ unsigned long long s_v[kCandTiles + 1];
     __shared__ int s_sg0;
+    // births of one round of the block: counted in LDS, then one reservation in the list
+    __shared__ uint32_t s_nb, s_bbase;
     const int64_t t0 = (int64_t)blockIdx.x * kCandTiles;
     if (threadIdx.x < kWave) {
         // the first wave loads the tile counts in parallel, resets them and scans
@@ -445,8 +448,8 @@ __global__ void __launch_bounds__(256) k_cand32(Dev d, int tile, int64_t T, int 
         if (k < kCandTiles) {
             s_pre[k] = inc - c;
             s_n[k][0] = s_n[k][1] = s_n[k][2] = 0u;
-            s_v[k] = 0ull;
         }
+        if (k <= kCandTiles) s_v[k] = 0ull;
         if (k == kCandTiles - 1) s_pre[kCandTiles] = inc;
         if (k == 0) s_sg0 = seg_of_slot(d, t0 * (int64_t)tile);
     }
@@ -457,43 +460,65 @@ __global__ void __launch_bounds__(256) k_cand32(Dev d, int tile, int64_t T, int 
     const int b = *d.cur;
     const uint32_t tag = (uint32_t)(*d.step);
     const BirthBuf bb = birth_buf(d, (int)(tag & 1u));
-    const int st = (int)(blockIdx.x & (kStripes - 1));
+    const int st = stripe_of_block();          // counters and speed maxima
+    const int bst = (int)(blockIdx.x & (kStripes - 1));  // birth list
     const int half = 1 - *d.vcur;
-    for (uint32_t q = threadIdx.x; q < m; q += blockDim.x) {
-        int k = 0;
-        while (k + 1 < kCandTiles && s_pre[k + 1] <= q) ++k;
-        const uint4 *r = d.crec + 2 * ((t0 + k) * (int64_t)tile + (q - s_pre[k]));
-        const uint4 r0 = r[0], r1 = r[1];
-        const int64_t i = (int64_t)r0.x;
-        const int sg = (int)r1.w;
-        const SegC &S = d.seg[sg];
-        const EnsC &e = d.ens[S.ens];
-        const int s = S.species;
+    for (uint32_t q0 = 0; q0 < m; q0 += blockDim.x) {
+        const uint32_t q = q0 + threadIdx.x;
+        const bool act = q < m;
+        int ch = -1, sg = 0;
         PS<false> p;
-        p.cell = (int)r0.y;
-        p.off = __uint_as_float(r0.z);
-        p.id = r0.w;
-        p.vx = __uint_as_float(r1.x);
-        p.vy = __uint_as_float(r1.y);
-        p.vz = __uint_as_float(r1.z);
         double ve[3], vi[3];
-        const int ch = p_collide<false>(e, S, s, d.numax[sg], d.pnull[sg], tag, p, ve, vi);
-        if (ch >= 0) {
-            d.fvx[b][i] = p.vx;
-            d.fvy[b][i] = p.vy;
-            d.fvz[b][i] = p.vz;
-            atomicAdd(&s_n[sg - sg0][ch], 1u);
-        }
-        double v2m = speed2_rn(p.vx, p.vy, p.vz);
-        if (ch == 1) {
-            // a stripe per wave; a full stripe passes the birth on to the next ones
-            int bst = (int)((blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) & (kStripes - 1));
-            uint32_t slot = atomicAdd(bb.nbirth + bst, 1u);
-            for (int a = 1; a < kStripes && (int64_t)slot >= d.birth_stripe_cap; ++a) {
-                bst = (bst + 1) & (kStripes - 1);
-                slot = atomicAdd(bb.nbirth + bst, 1u);
+        if (act) {
+            int k = 0;
+            while (k + 1 < kCandTiles && s_pre[k + 1] <= q) ++k;
+            const uint4 *r = d.crec + 2 * ((t0 + k) * (int64_t)tile + (q - s_pre[k]));
+            const uint4 r0 = r[0], r1 = r[1];
+            const int64_t i = (int64_t)r0.x;
+            sg = (int)r1.w;
+            const SegC &S = d.seg[sg];
+            const EnsC &e = d.ens[S.ens];
+            p.cell = (int)r0.y;
+            p.off = __uint_as_float(r0.z);
+            p.id = r0.w;
+            p.vx = __uint_as_float(r1.x);
+            p.vy = __uint_as_float(r1.y);
+            p.vz = __uint_as_float(r1.z);
+            ch = p_collide<false>(e, S, S.species, d.numax[sg], d.pnull[sg], tag, p, ve, vi);
+            if (ch >= 0) {
+                d.fvx[b][i] = p.vx;
+                d.fvy[b][i] = p.vy;
+                d.fvz[b][i] = p.vz;
+                atomicAdd(&s_n[sg - sg0][ch], 1u);
             }
+            double v2m = speed2_rn(p.vx, p.vy, p.vz);
+            if (ch == 1) {
+                v2m = fmax(v2m, speed2_rn(ve[0], ve[1], ve[2]));
+                if (S.other >= 0) {
+                    const unsigned long long vb = dbits(speed2_rn(vi[0], vi[1], vi[2]));
+                    const int jo = S.other - sg0;
+                    if (jo >= 0 && jo <= kCandTiles)
+                        atomicMax(&s_v[jo], vb);
+                    else
+                        atomicMax(d.vmax2 + ((int64_t)half * kCntStripes + st) * d.nseg + S.other, vb);
+                }
+                global_deposit32(d, S, S.species, p.cell, p.off, hist != 0);
+                if (S.other >= 0) global_deposit32(d, d.seg[S.other], 1, p.cell, p.off, hist != 0);
+            }
+            if (v2m > 0.0) atomicMax(&s_v[sg - sg0], dbits(v2m));
+        }
+        // births of this round: one list reservation for the whole block
+        if (threadIdx.x == 0) s_nb = 0u;
+        __syncthreads();
+        uint32_t lb = 0;
+        if (ch == 1) lb = atomicAdd(&s_nb, 1u);
+        __syncthreads();
+        if (threadIdx.x == 0 && s_nb) s_bbase = atomicAdd(bb.nbirth + bst, s_nb);
+        __syncthreads();
+        if (ch == 1) {
+            const uint32_t slot = s_bbase + lb;
             if ((int64_t)slot < d.birth_stripe_cap) {
+                const SegC &S = d.seg[sg];
                 Birth &B = bb.births[(int64_t)bst * d.birth_stripe_cap + slot];
                 B.pid = p.id;
                 B.ens = S.ens;
@@ -504,29 +529,24 @@ __global__ void __launch_bounds__(256) k_cand32(Dev d, int tile, int64_t T, int 
                     B.ve[c] = ve[c];
                     B.vi[c] = vi[c];
                 }
-                birth_mark(bb, e, p.id);
+                birth_mark(bb, d.ens[S.ens], p.id);
             } else {
                 atomicOr(d.err, (int)E_CAP_BIRTH);
             }
-            v2m = fmax(v2m, speed2_rn(ve[0], ve[1], ve[2]));
-            if (S.other >= 0)
-                atomicMax(d.vmax2 + ((int64_t)half * kStripes + st) * d.nseg + S.other,
-                          dbits(speed2_rn(vi[0], vi[1], vi[2])));
-            global_deposit32(d, S, s, p.cell, p.off, hist != 0);
-            if (S.other >= 0) global_deposit32(d, d.seg[S.other], 1, p.cell, p.off, hist != 0);
         }
-        if (v2m > 0.0) atomicMax(&s_v[sg - sg0], dbits(v2m));
+        __syncthreads();  // s_nb and s_bbase are reused by the next round
     }
     // one set of counter atomics per block and segment
-    __syncthreads();
-    if (threadIdx.x < kCandTiles) {
-        const int j = threadIdx.x, sg = sg0 + j;
-        if (sg < d.nseg) {
-            unsigned long long *c = d.cnt + ((int64_t)st * d.nseg + sg) * C_NCNT;
-            if (s_n[j][0]) atomicAdd(c + C_EL, (unsigned long long)s_n[j][0]);
-            if (s_n[j][1]) atomicAdd(c + C_IZ, (unsigned long long)s_n[j][1]);
-            if (s_n[j][2]) atomicAdd(c + C_CX, (unsigned long long)s_n[j][2]);
-            if (s_v[j]) atomicMax(d.vmax2 + ((int64_t)half * kStripes + st) * d.nseg + sg, s_v[j]);
+    if (threadIdx.x <= kCandTiles) {
+        const int j = threadIdx.x, sgj = sg0 + j;
+        if (sgj < d.nseg) {
+            if (j < kCandTiles) {
+                unsigned long long *c = d.cnt + ((int64_t)st * d.nseg + sgj) * C_NCNT;
+                if (s_n[j][0]) atomicAdd(c + C_EL, (unsigned long long)s_n[j][0]);
+                if (s_n[j][1]) atomicAdd(c + C_IZ, (unsigned long long)s_n[j][1]);
+                if (s_n[j][2]) atomicAdd(c + C_CX, (unsigned long long)s_n[j][2]);
+            }
+            if (s_v[j]) atomicMax(d.vmax2 + ((int64_t)half * kCntStripes + st) * d.nseg + sgj, s_v[j]);
         }
     }
 }
@@ -539,7 +559,25 @@ __global__ void __launch_bounds__(256) k_cand32(Dev d, int tile, int64_t T, int 
 // one cell thus write consecutive output slots and every store instruction is coalesced.
 // Absorbed slots drop out.
 // =======================================================================================
-template <int PPT>
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_nt(const T *p)
+{
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
+template <bool NT, typename T>
+__device__ __forceinline__ void st_nt(T *p, T v)
+{
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
+template <int PPT, bool NT>
 __global__ void __launch_bounds__(256) k_sort32(Dev d, int W, int64_t T)
 {
     constexpr int TILE = 256 * PPT;
@@ -569,12 +607,12 @@ __global__ void __launch_bounds__(256) k_sort32(Dev d, int W, int64_t T)
         const int64_t i = first + (int64_t)k * 256 + tid;
         cell[k] = kDead;
         if (i < last) {
-            cell[k] = icell[i];
-            off[k] = ioff[i];
-            vx[k] = ivx[i];
-            vy[k] = ivy[i];
-            vz[k] = ivz[i];
-            id[k] = iid[i];
+            cell[k] = ld_nt<NT>(icell + i);
+            off[k] = ld_nt<NT>(ioff + i);
+            vx[k] = ld_nt<NT>(ivx + i);
+            vy[k] = ld_nt<NT>(ivy + i);
+            vz[k] = ld_nt<NT>(ivz + i);
+            id[k] = ld_nt<NT>(iid + i);
         }
     }
     int mn = INT32_MAX;
@@ -637,12 +675,12 @@ __global__ void __launch_bounds__(256) k_sort32(Dev d, int W, int64_t T)
             atomicOr(d.err, (int)E_CAP_PART);
             continue;
         }
-        ocell[o] = cell[k];
-        ooff[o] = off[k];
-        ovx[o] = vx[k];
-        ovy[o] = vy[k];
-        ovz[o] = vz[k];
-        oid[o] = id[k];
+        st_nt<NT>(ocell + o, cell[k]);
+        st_nt<NT>(ooff + o, off[k]);
+        st_nt<NT>(ovx + o, vx[k]);
+        st_nt<NT>(ovy + o, vy[k]);
+        st_nt<NT>(ovz + o, vz[k]);
+        st_nt<NT>(oid + o, id[k]);
     }
 }
 
@@ -714,16 +752,25 @@ hipError_t launch_pass32_stages(const Dev &d, int ppt, int W, hipStream_t s, int
     }
 }
 
-hipError_t launch_sort32_scatter(const Dev &d, int ppt, int W, hipStream_t s, int64_t cap_tot)
+template <bool NT>
+static void launch_sort32_t(const Dev &d, int ppt, int W, hipStream_t s, int64_t cap_tot)
 {
     const size_t lds = (size_t)W * 4;
     if (ppt == 4) {
         const int64_t T = cap_tot / (256 * 4);
-        hipLaunchKernelGGL((k_sort32<4>), dim3((T + 7) / 8 * 8), dim3(256), lds, s, d, W, T);
+        hipLaunchKernelGGL((k_sort32<4, NT>), dim3((T + 7) / 8 * 8), dim3(256), lds, s, d, W, T);
     } else {
         const int64_t T = cap_tot / (256 * 8);
-        hipLaunchKernelGGL((k_sort32<8>), dim3((T + 7) / 8 * 8), dim3(256), lds, s, d, W, T);
+        hipLaunchKernelGGL((k_sort32<8, NT>), dim3((T + 7) / 8 * 8), dim3(256), lds, s, d, W, T);
     }
+}
+
+hipError_t launch_sort32_scatter(const Dev &d, int ppt, int W, hipStream_t s, int64_t cap_tot, bool nt)
+{
+    if (nt)
+        launch_sort32_t<true>(d, ppt, W, s, cap_tot);
+    else
+        launch_sort32_t<false>(d, ppt, W, s, cap_tot);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(256), 0, s, d);
