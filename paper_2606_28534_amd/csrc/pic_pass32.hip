@@ -214,6 +214,7 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
     const int wbase = (c0 == kDead) ? 0 : max(c0 - W / 4, 0);
 
     uint32_t npush = 0;
+    uint32_t cchg = 0;  // bit k: particle k's cell changed in the push (or it died)
     double v2m = 0.0;
     const int st = stripe_of_block();
 
@@ -244,7 +245,9 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
                 c = (c < 0) ? c + N : ((c >= N) ? c - N : c);
                 const bool inv = alive && (c < 0 || c >= N);  // moved more than a period
                 bad |= inv ? 1u : 0u;
-                cell[k] = (alive && !inv) ? c : kDead;
+                const int cn = (alive && !inv) ? c : kDead;
+                cchg |= (cn != cell[k] ? 1u : 0u) << k;
+                cell[k] = cn;
             } else {
                 const bool out = alive && (c < 0 || c >= N);
                 if (out) {
@@ -257,7 +260,9 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
                         ker += S.halfmw * v2;
                     }
                 }
-                cell[k] = out ? kDead : cell[k] == kDead ? kDead : c;
+                const int cn = out ? kDead : cell[k] == kDead ? kDead : c;
+                cchg |= (cn != cell[k] ? 1u : 0u) << k;
+                cell[k] = cn;
             }
         }
         if (nwl) {
@@ -316,7 +321,15 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
     if (PUSH || COLL) {
         if (full) {
             if (PUSH) {
-                vstore<PPT, NT>(d.cell[b] + i0, cell);
+                // a group of four cells is stored only if one of them changed (the heavy
+                // ions almost never leave their cell in one step)
+#pragma unroll
+                for (int q = 0; q < PPT; q += 4) {
+                    if ((cchg >> q) & 0xFu) {
+                        int c4[4] = {cell[q], cell[q + 1], cell[q + 2], cell[q + 3]};
+                        vstore<4, NT>(d.cell[b] + i0 + q, c4);
+                    }
+                }
                 vstore<PPT, NT>(d.off[b] + i0, off);
             }
             vstore<PPT, NT>(d.fvx[b] + i0, vx);
