@@ -496,7 +496,6 @@ int pic_collide(pic_ctx *c, void *stream)
     if (!c) return PIC_EINVAL;
     if (!c->cfg.collisions) return PIC_OK;
     hipStream_t s = (hipStream_t)stream;
-    HIPC(c, launch_params(c->d, s));
     HIPC(c, launch_particles(c->d, c->L, s, c->P.f64, SB_COLLIDE, 0));
     HIPC(c, launch_candidates(c->d, c->L, s, c->P.f64, 0));
     HIPC(c, launch_births(c->d, c->P.f64, false, false, s));
@@ -562,6 +561,7 @@ int pic_diag(pic_ctx *c, int32_t ens, pic_diag_out *out, void *stream)
     double emax = 0, fe = 0;
     std::vector<double> numax(nseg);
     int64_t step = 0;
+    HIPC(c, launch_field_energy(c->d, s));
     HIPC(c, hipMemcpyAsync(&emax, c->d.emax + ens, 8, hipMemcpyDeviceToHost, s));
     HIPC(c, hipMemcpyAsync(&fe, c->d.fe + ens, 8, hipMemcpyDeviceToHost, s));
     HIPC(c, hipMemcpyAsync(numax.data(), c->d.numax, nseg * 8, hipMemcpyDeviceToHost, s));
@@ -976,6 +976,7 @@ int pic_adjoint_window(pic_ctx *c, int32_t nsteps, int32_t ckpt_every, void *scr
     }
     // objective at the final positions
     HIPC(c, launch_solve(d, false, c->P.chunks_tot, false, s));
+    HIPC(c, launch_field_energy(d, s));
     double fe = 0.0;
     HIPC(c, hipMemcpyAsync(&fe, d.fe, 8, hipMemcpyDeviceToHost, s));
     // keep the final state

@@ -236,6 +236,25 @@ __device__ __forceinline__ BirthBuf birth_buf(const Dev &d, int parity)
             d.bitmap + (int64_t)parity * d.bm_words, d.gcnt + (int64_t)parity * d.g_tot};
 }
 
+// Reading R11, the null-collision bound of segment `sg` from the current striped speed
+// maxima and the ensemble's max |E|: nu_max = n_g sigma_T (vmax + |q/m| dt (max|E| +
+// |E_ext|)) (1 + 2^-16) and P_null = 1 - exp(-nu_max dt).  Called by a whole wave (lanes
+// read the stripes); every lane gets the result.
+__device__ __forceinline__ void seg_params(const Dev &d, int sg, double &numax, double &pnull)
+{
+    const SegC &S = d.seg[sg];
+    const EnsC &e = d.ens[S.ens];
+    const int half = *d.vcur;
+    double m2 = 0.0;  // squared speeds are non-negative: bit patterns order as integers
+    for (int st = lane_id(); st < kCntStripes; st += kWave)
+        m2 = fmax(m2, __longlong_as_double((long long)d.vmax2[((int64_t)half * kCntStripes + st) * d.nseg + sg]));
+    m2 = wave_max_f64(m2);
+    const double vmax = __dsqrt_rn(m2);
+    const double Vb = __dadd_rn(vmax, __dmul_rn(__dmul_rn(S.qm_abs, e.dt), __dadd_rn(d.emax[S.ens], fabs(e.E_ext))));
+    numax = __dmul_rn(__dmul_rn(S.ngsT, Vb), kNuSafety);
+    pnull = 1.0 - exp(-__dmul_rn(numax, e.dt));
+}
+
 // Record a birth of parent `pid` (its bit and its group count) in one half.
 __device__ __forceinline__ void birth_mark(const BirthBuf &bb, const EnsC &e, uint32_t pid)
 {

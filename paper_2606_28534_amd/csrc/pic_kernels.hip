@@ -629,6 +629,8 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve1(Dev d)
         }
         (void)runc;
     }
+    // the ensemble's max |E| is accumulated by the second pass's blocks (atomic max)
+    if (k == e.chunk0 && threadIdx.x == 0) d.emax[ei] = 0.0;
     __shared__ double s_red[6 * 16];
     double v[6] = {loc, sumpre, totq, n1, dd, cnt};
     block_sums<6>(v, s_red);
@@ -645,26 +647,16 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve1(Dev d)
 }
 
 // Reading R11: per-segment null-collision bound from the current max speed and max field.
-// One wave per segment; lanes read the striped speed maxima.
+// One wave per segment (lanes read the striped speed maxima); every lane gets the result.
 __device__ void compute_params(const Dev &d)
 {
-    const int nw = blockDim.x / kWave, w = threadIdx.x / kWave, lane = lane_id();
-    const int half = *d.vcur;
+    const int nw = blockDim.x / kWave, w = threadIdx.x / kWave;
     for (int sg = w; sg < d.nseg; sg += nw) {
-        const SegC &S = d.seg[sg];
-        const EnsC &e = d.ens[S.ens];
-        // squared speeds are non-negative doubles: their bit patterns order as integers
-        double m2 = 0.0;
-        for (int st = lane; st < kCntStripes; st += kWave)
-            m2 = fmax(m2, __longlong_as_double((long long)d.vmax2[((int64_t)half * kCntStripes + st) * d.nseg + sg]));
-        m2 = wave_max_f64(m2);
-        if (lane == 0) {
-            const double vmax = __dsqrt_rn(m2);
-            const double Vb = __dadd_rn(vmax, __dmul_rn(__dmul_rn(S.qm_abs, e.dt),
-                                                        __dadd_rn(d.emax[S.ens], fabs(e.E_ext))));
-            const double numax = __dmul_rn(__dmul_rn(S.ngsT, Vb), kNuSafety);
+        double numax, pnull;
+        seg_params(d, sg, numax, pnull);
+        if (lane_id() == 0) {
             d.numax[sg] = numax;
-            d.pnull[sg] = 1.0 - exp(-__dmul_rn(numax, e.dt));
+            d.pnull[sg] = pnull;
         }
     }
 }
@@ -677,7 +669,6 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve2(Dev d, int zero_q)
     __shared__ double s_buf[8];
     __shared__ double s_E[F64 ? 1 : kChunk + 1];  // the chunk's node E, for the gather table
     __shared__ double s_C0, s_F0, s_Eh, s_bg, s_Ctot;
-    __shared__ bool s_last;
     const int64_t k = blockIdx.x;
     const int ei = chunk_ens(d, k);
     const EnsC &e = d.ens[ei];
@@ -761,7 +752,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve2(Dev d, int zero_q)
     // exclusive prefix of C over m < j (m in [0, N-1])
     const double fex = block_incl_scan(csum, s_buf) - csum;
     double F = s_F0 + fex;
-    double emax = 0.0, fe = 0.0, phisum = 0.0;
+    double emax = 0.0, phisum = 0.0;
     int nonfin = 0;
     // C_{j-1} for the first node of the thread
     double Cprev = (j0 == 0) ? 0.0 : (Cj[0] - rl[0]);
@@ -796,7 +787,6 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve2(Dev d, int zero_q)
         if constexpr (!F64) s_E[j - a] = Ej;
         if (!isfinite(Ej)) nonfin = 1;
         emax = fmax(emax, fabs(Ej));
-        fe += Ej * Ej * node_vol(e, j);
         if (j < N) F += Cj[q];
         Cprev = Cj[q];
     }
@@ -853,50 +843,15 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve2(Dev d, int zero_q)
         }
         __syncthreads();
         em = s_em[0];
-        __shared__ double s_red3[3 * 16];
-        double fv[3] = {fe, phisum, (double)nonfin};
-        block_sums<3>(fv, s_red3);
-        const double fes = fv[0], ps = fv[1], nf = fv[2];
+        __shared__ double s_red3[2 * 16];
+        double fv[2] = {phisum, (double)nonfin};
+        block_sums<2>(fv, s_red3);
         if (threadIdx.x == 0) {
-            double *pp = d.part + k * P_NPART;
-            pp[P_EMAX] = em;
-            pp[P_FE] = fes;
-            pp[P_PHISUM] = ps;
-            pp[P_NONFIN] = nf;
+            d.part[k * P_NPART + P_PHISUM] = fv[0];
+            // |E| >= 0: its bit pattern orders as an unsigned integer
+            atomicMax((unsigned long long *)(d.emax + ei), dbits(em));
+            if (fv[1] > 0.0) atomicOr(d.err, (int)E_NONFINITE);
         }
-    }
-    // the last chunk to finish reduces the partials per ensemble and sets the
-    // null-collision parameters of every segment
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) s_last = (atomicAdd(d.ticket + 0, 1u) == gridDim.x - 1);
-    __syncthreads();
-    if (s_last) {
-        __threadfence();
-        // one wave per ensemble, lanes over its chunks
-        const int nw = blockDim.x / kWave, w = threadIdx.x / kWave, lane = lane_id();
-        for (int en = w; en < d.nens; en += nw) {
-            const EnsC &E = d.ens[en];
-            double em = 0.0, f = 0.0, nf = 0.0;
-            for (int64_t c = lane; c < E.nchunks; c += kWave) {
-                const double *pp = d.part + (E.chunk0 + c) * P_NPART;
-                em = fmax(em, pp[P_EMAX]);
-                f += pp[P_FE];
-                nf += pp[P_NONFIN];
-            }
-            em = wave_max_f64(em);
-            f = wave_sum_f64(f);
-            nf = wave_sum_f64(nf);
-            if (lane == 0) {
-                d.emax[en] = em;
-                d.fe[en] = 0.5 * E.eps0 * f;
-                if (nf > 0.0) atomicOr(d.err, (int)E_NONFINITE);
-            }
-        }
-        __syncthreads();
-        __threadfence();
-        compute_params(d);
-        if (threadIdx.x == 0) d.ticket[0] = 0u;
     }
 }
 
@@ -931,6 +886,22 @@ __global__ void k_ecell(Dev d)
         const double E0 = d.E[e.gbase + j], E1 = d.E[e.gbase + j1];
         d.Ecell[e.gbase + j] = make_float2((float)E0, (float)(E1 - E0));
     }
+}
+
+// Field energy 1/2 eps0 sum_j E_j^2 V_j of every ensemble (for the diagnostics and the
+// adjoint objective; one wave per ensemble).
+__global__ void __launch_bounds__(1024) k_field_energy(Dev d)
+{
+    __shared__ double s_buf[16];
+    const EnsC &e = d.ens[blockIdx.x];  // one block per ensemble
+    double f = 0.0;
+    for (int64_t j = threadIdx.x; j < e.nnodes; j += blockDim.x) {
+        const double E = d.E[e.gbase + j];
+        f += E * E * node_vol(e, j);
+    }
+    double v[1] = {f};
+    block_sums<1>(v, s_buf);
+    if (threadIdx.x == 0) d.fe[blockIdx.x] = 0.5 * e.eps0 * v[0];
 }
 
 // Max |E| and field energy of a field set from the host (test hook).
@@ -1509,6 +1480,11 @@ static hipError_t launch_particles_t(const Dev &d, const Launch &L, hipStream_t 
 
 hipError_t launch_particles(const Dev &d, const Launch &L, hipStream_t s, bool f64, int stages, int hist)
 {
+    // the null-collision bound of every segment from this step's speed and field maxima
+    if (stages & SB_COLLIDE) {
+        hipLaunchKernelGGL(k_params, dim3(1), dim3(256), 0, s, d);
+        LAUNCH_CHECK();
+    }
     if (!f64) return launch_pass32(d, L.ppt, L.window, s, stages, hist, d.cap_tot, L.nt != 0);
 #define PIC_CASE(ST)                                                          \
     case ST:                                                                  \
@@ -1593,6 +1569,13 @@ hipError_t launch_field_stats(const Dev &d, bool f64, int64_t nchunks, hipStream
         hipLaunchKernelGGL(k_ecell, dim3(nchunks), dim3(kSolveThreads), 0, s, d);
         LAUNCH_CHECK();
     }
+    return hipSuccess;
+}
+
+hipError_t launch_field_energy(const Dev &d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_field_energy, dim3(d.nens), dim3(1024), 0, s, d);
+    LAUNCH_CHECK();
     return hipSuccess;
 }
 
