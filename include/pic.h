@@ -225,6 +225,18 @@ int pic_adjoint_window(pic_ctx *ctx, int32_t nsteps, int32_t ckpt_every, void *s
  * unchanged apart from slot order). */
 int pic_autotune(pic_ctx *ctx, int32_t trial_steps, int32_t *shape, void *stream);
 
+/* Device-state checkpoint of the run at a step boundary: the particles in use (in slot
+ * order), the deposited charge, the per-segment slot counts and id counters, the step,
+ * the current speed maxima and the diagnostic counters.  A context created with the same
+ * configuration and loaded from it continues bit for bit as the saved run would have
+ * (random numbers are keyed by particle id and step).  pic_checkpoint_size gives the
+ * bytes of the host buffer pic_save fills (it depends on the slots in use, so query it
+ * right before saving); both synchronise `stream`.  pic_load returns PIC_EINVAL for a
+ * buffer written by a different configuration. */
+int pic_checkpoint_size(pic_ctx *ctx, size_t *bytes, void *stream);
+int pic_save(pic_ctx *ctx, void *host_buf, size_t bytes, void *stream);
+int pic_load(pic_ctx *ctx, const void *host_buf, size_t bytes, void *stream);
+
 /* Measurement hook: with `enable` != 0, pic_step runs its steps without the graph and
  * brackets every particle-pass launch with HIP events recorded on the caller's stream
  * (up to 65536 launches); pic_timing_read synchronises that stream and returns the summed

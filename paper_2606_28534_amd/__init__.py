@@ -24,7 +24,8 @@ EXPORTS = ("pic_query_workspace", "pic_init", "pic_deposit", "pic_solve", "pic_p
            "pic_get_slots", "pic_set_particles", "pic_get_grid", "pic_get_gather_table",
            "pic_set_fields", "pic_set_step",
            "pic_nnodes", "pic_set_external_field", "pic_adjoint_query",
-           "pic_adjoint_window", "pic_autotune", "pic_timing", "pic_timing_read", "pic_free", "pic_last_error")
+           "pic_adjoint_window", "pic_autotune", "pic_checkpoint_size", "pic_save", "pic_load",
+           "pic_timing", "pic_timing_read", "pic_free", "pic_last_error")
 
 
 class PicError(RuntimeError):
@@ -115,6 +116,9 @@ def load_library():
     L.pic_adjoint_window.argtypes = [P, C.c_int32, C.c_int32, P, C.c_size_t, C.POINTER(C.c_double),
                                      P, C.c_int64, C.POINTER(C.c_double), P]
     L.pic_autotune.argtypes = [P, C.c_int32, P, P]
+    L.pic_checkpoint_size.argtypes = [P, C.POINTER(C.c_size_t), P]
+    L.pic_save.argtypes = [P, P, C.c_size_t, P]
+    L.pic_load.argtypes = [P, P, C.c_size_t, P]
     L.pic_timing.argtypes = [P, C.c_int32]
     L.pic_timing_read.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64), P]
     L.pic_free.argtypes = [P]
@@ -250,6 +254,19 @@ class Sim:
         self._check(self.L.pic_autotune(self.h, int(trial_steps), _ptr(shape), self._s()))
         return {"ppt": int(shape[0]), "window": int(shape[1]), "sort_ppt": int(shape[2]),
                 "nontemporal": int(shape[3]) | (int(shape[4]) << 1)}
+
+    def save(self):
+        """Checkpoint of the run at the current step boundary (a host uint8 array)."""
+        nb = C.c_size_t(0)
+        self._check(self.L.pic_checkpoint_size(self.h, C.byref(nb), self._s()))
+        buf = np.empty(nb.value, dtype=np.uint8)
+        self._check(self.L.pic_save(self.h, _ptr(buf), buf.nbytes, self._s()))
+        return buf
+
+    def load(self, buf):
+        """Continue from a checkpoint written by save() of a run with the same configuration."""
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        self._check(self.L.pic_load(self.h, _ptr(buf), buf.nbytes, self._s()))
 
     def timing(self, enable=True):
         self._check(self.L.pic_timing(self.h, int(bool(enable))))

@@ -1151,6 +1151,173 @@ int pic_autotune(pic_ctx *c, int32_t trial_steps, int32_t *shape, void *stream)
     return check_err(c, s);
 }
 
+// ---------------------------------------------------------------------------------------
+// Checkpoint / restart.  Layout: header, per-segment {n_slots, next_id}, then per segment
+// its particle arrays over the slots in use, then Q, the current speed-maxima half and the
+// counters and sums.
+namespace {
+struct CkptHeader {
+    uint64_t magic;
+    int64_t nseg, nens, nodes_tot, cap_tot, f64, step, bytes;
+};
+constexpr uint64_t kCkptMagic = 0x31544b5043494d50ull;  // "PMICPKT1"
+
+size_t ckpt_bytes(const pic_ctx *c, const std::vector<int64_t> &ns)
+{
+    const int64_t per = c->P.f64 ? 36 : 24;
+    size_t b = sizeof(CkptHeader) + (size_t)c->P.nseg * 16;
+    for (int64_t n : ns) b += (size_t)n * per;
+    b += (size_t)2 * c->P.nodes_tot * 8;
+    b += (size_t)kCntStripes * c->P.nseg * 8;
+    b += (size_t)kCntStripes * c->P.nseg * (C_NCNT + S_NSUM) * 8;
+    return b;
+}
+
+int ckpt_counts(pic_ctx *c, hipStream_t s, std::vector<int64_t> &ns, std::vector<uint32_t> &ids)
+{
+    ns.resize(c->P.nseg);
+    ids.resize(c->P.nseg);
+    HIPC(c, hipMemcpyAsync(ns.data(), c->d.n_slots, ns.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPC(c, hipMemcpyAsync(ids.data(), c->d.next_id, ids.size() * 4, hipMemcpyDeviceToHost, s));
+    HIPC(c, hipStreamSynchronize(s));
+    return PIC_OK;
+}
+}  // namespace
+
+int pic_checkpoint_size(pic_ctx *c, size_t *bytes, void *stream)
+{
+    if (!c || !bytes) return PIC_EINVAL;
+    std::vector<int64_t> ns;
+    std::vector<uint32_t> ids;
+    int rc = ckpt_counts(c, (hipStream_t)stream, ns, ids);
+    if (rc) return rc;
+    *bytes = ckpt_bytes(c, ns);
+    return PIC_OK;
+}
+
+int pic_save(pic_ctx *c, void *host_buf, size_t bytes, void *stream)
+{
+    if (!c || !host_buf) return PIC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int64_t> ns;
+    std::vector<uint32_t> ids;
+    int rc = ckpt_counts(c, s, ns, ids);
+    if (rc) return rc;
+    const size_t need = ckpt_bytes(c, ns);
+    if (bytes < need) return fail(c, PIC_EINVAL, "checkpoint buffer too small");
+    const Dev &d = c->d;
+    int32_t cur = 0;
+    int64_t step = 0;
+    HIPC(c, hipMemcpyAsync(&cur, d.cur, 4, hipMemcpyDeviceToHost, s));
+    HIPC(c, hipMemcpyAsync(&step, d.step, 8, hipMemcpyDeviceToHost, s));
+    int32_t vcur = 0;
+    HIPC(c, hipMemcpyAsync(&vcur, d.vcur, 4, hipMemcpyDeviceToHost, s));
+    HIPC(c, hipStreamSynchronize(s));
+    char *o = (char *)host_buf;
+    CkptHeader h{kCkptMagic, c->P.nseg, c->P.nens, c->P.nodes_tot, c->P.cap_tot, c->P.f64 ? 1 : 0, step,
+                 (int64_t)need};
+    std::memcpy(o, &h, sizeof(h));
+    o += sizeof(h);
+    for (int sg = 0; sg < c->P.nseg; ++sg) {
+        const int64_t v[2] = {ns[sg], (int64_t)ids[sg]};
+        std::memcpy(o, v, 16);
+        o += 16;
+    }
+    auto d2h = [&](const void *src, size_t n) -> hipError_t {
+        hipError_t e = n ? hipMemcpyAsync(o, src, n, hipMemcpyDeviceToHost, s) : hipSuccess;
+        o += n;
+        return e;
+    };
+    for (int sg = 0; sg < c->P.nseg; ++sg) {
+        const int64_t base = c->P.seg[sg].base, n = ns[sg];
+        if (c->P.f64) {
+            HIPC(c, d2h(d.x[cur] + base, n * 8));
+            HIPC(c, d2h(d.dvx[cur] + base, n * 8));
+            HIPC(c, d2h(d.dvy[cur] + base, n * 8));
+            HIPC(c, d2h(d.dvz[cur] + base, n * 8));
+        } else {
+            HIPC(c, d2h(d.cell[cur] + base, n * 4));
+            HIPC(c, d2h(d.off[cur] + base, n * 4));
+            HIPC(c, d2h(d.fvx[cur] + base, n * 4));
+            HIPC(c, d2h(d.fvy[cur] + base, n * 4));
+            HIPC(c, d2h(d.fvz[cur] + base, n * 4));
+        }
+        HIPC(c, d2h(d.id[cur] + base, n * 4));
+    }
+    HIPC(c, d2h(c->P.f64 ? (const void *)d.Qd : (const void *)d.Qi, (size_t)2 * c->P.nodes_tot * 8));
+    HIPC(c, d2h(d.vmax2 + (size_t)vcur * kCntStripes * c->P.nseg, (size_t)kCntStripes * c->P.nseg * 8));
+    HIPC(c, d2h(d.cnt, (size_t)kCntStripes * c->P.nseg * C_NCNT * 8));
+    HIPC(c, d2h(d.sums, (size_t)kCntStripes * c->P.nseg * S_NSUM * 8));
+    HIPC(c, hipStreamSynchronize(s));
+    return PIC_OK;
+}
+
+int pic_load(pic_ctx *c, const void *host_buf, size_t bytes, void *stream)
+{
+    if (!c || !host_buf || bytes < sizeof(CkptHeader)) return PIC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    CkptHeader h;
+    std::memcpy(&h, host_buf, sizeof(h));
+    if (h.magic != kCkptMagic || h.nseg != c->P.nseg || h.nens != c->P.nens || h.nodes_tot != c->P.nodes_tot ||
+        h.cap_tot != c->P.cap_tot || h.f64 != (c->P.f64 ? 1 : 0) || (size_t)h.bytes > bytes)
+        return fail(c, PIC_EINVAL, "checkpoint from a different configuration");
+    const char *o = (const char *)host_buf + sizeof(h);
+    std::vector<int64_t> ns(c->P.nseg);
+    std::vector<uint32_t> ids(c->P.nseg);
+    for (int sg = 0; sg < c->P.nseg; ++sg) {
+        int64_t v[2];
+        std::memcpy(v, o, 16);
+        o += 16;
+        if (v[0] < 0 || v[0] > c->P.seg[sg].cap) return fail(c, PIC_EINVAL, "checkpoint slot count");
+        ns[sg] = v[0];
+        ids[sg] = (uint32_t)v[1];
+    }
+    if (ckpt_bytes(c, ns) != (size_t)h.bytes) return fail(c, PIC_EINVAL, "checkpoint size");
+    const Dev &d = c->d;
+    HIPC(c, hipStreamSynchronize(s));
+    // the run continues from buffer 0, both birth halves clean, speed maxima in half 0
+    HIPC(c, launch_births_clear_all(d, s));
+    auto h2d = [&](void *dst, size_t n) -> hipError_t {
+        hipError_t e = n ? hipMemcpyAsync(dst, o, n, hipMemcpyHostToDevice, s) : hipSuccess;
+        o += n;
+        return e;
+    };
+    for (int sg = 0; sg < c->P.nseg; ++sg) {
+        const int64_t base = c->P.seg[sg].base, n = ns[sg];
+        if (c->P.f64) {
+            HIPC(c, h2d(d.x[0] + base, n * 8));
+            HIPC(c, h2d(d.dvx[0] + base, n * 8));
+            HIPC(c, h2d(d.dvy[0] + base, n * 8));
+            HIPC(c, h2d(d.dvz[0] + base, n * 8));
+        } else {
+            HIPC(c, h2d(d.cell[0] + base, n * 4));
+            HIPC(c, h2d(d.off[0] + base, n * 4));
+            HIPC(c, h2d(d.fvx[0] + base, n * 4));
+            HIPC(c, h2d(d.fvy[0] + base, n * 4));
+            HIPC(c, h2d(d.fvz[0] + base, n * 4));
+        }
+        HIPC(c, h2d(d.id[0] + base, n * 4));
+    }
+    HIPC(c, h2d(c->P.f64 ? (void *)d.Qd : (void *)d.Qi, (size_t)2 * c->P.nodes_tot * 8));
+    HIPC(c, h2d(d.vmax2, (size_t)kCntStripes * c->P.nseg * 8));
+    HIPC(c, hipMemsetAsync(d.vmax2 + (size_t)kCntStripes * c->P.nseg, 0, (size_t)kCntStripes * c->P.nseg * 8, s));
+    HIPC(c, h2d(d.cnt, (size_t)kCntStripes * c->P.nseg * C_NCNT * 8));
+    HIPC(c, h2d(d.sums, (size_t)kCntStripes * c->P.nseg * S_NSUM * 8));
+    const int32_t zero = 0;
+    HIPC(c, hipMemcpyAsync(d.n_slots, ns.data(), ns.size() * 8, hipMemcpyHostToDevice, s));
+    HIPC(c, hipMemcpyAsync(d.next_id, ids.data(), ids.size() * 4, hipMemcpyHostToDevice, s));
+    HIPC(c, hipMemcpyAsync(d.cur, &zero, 4, hipMemcpyHostToDevice, s));
+    HIPC(c, hipMemcpyAsync(d.vcur, &zero, 4, hipMemcpyHostToDevice, s));
+    HIPC(c, hipMemcpyAsync(d.step, &h.step, 8, hipMemcpyHostToDevice, s));
+    HIPC(c, hipStreamSynchronize(s));
+    c->host_step = h.step;
+    if (c->graph) {
+        (void)hipGraphExecDestroy(c->graph);
+        c->graph = nullptr;
+    }
+    return check_err(c, s);
+}
+
 int pic_timing(pic_ctx *c, int32_t enable)
 {
     if (!c) return PIC_EINVAL;
