@@ -42,7 +42,8 @@ class _Config(C.Structure):
                 ("sort_every", C.c_int32), ("sp", _Species * 2),
                 ("ngs_el", C.c_double), ("ngs_iz", C.c_double), ("ngs_cx", C.c_double),
                 ("eps_iz", C.c_double), ("T_n", C.c_double), ("m_n", C.c_double),
-                ("perturb_amp", C.c_double), ("perturb_mode", C.c_int32)]
+                ("perturb_amp", C.c_double), ("perturb_mode", C.c_int32),
+                ("floating", C.c_int32), ("smooth", C.c_int32)]
 
 
 class Diag(C.Structure):
@@ -106,6 +107,8 @@ def lib():
         L.orc_boxmuller.argtypes = [C.c_double, C.c_double, C.POINTER(C.c_double),
                                     C.POINTER(C.c_double)]
         L.orc_thomas.argtypes = [C.c_int64, P, P, P, P, P]
+        L.orc_smooth_nodes.argtypes = [C.c_int64, C.c_int32, C.c_int32, P]
+        L.orc_smooth_nodes.restype = None
         _lib = L
     return _lib
 
@@ -134,6 +137,8 @@ def make_config(e):
     c.ngs_el, c.ngs_iz, c.ngs_cx = e["ngs_el"], e["ngs_iz"], e["ngs_cx"]
     c.eps_iz, c.T_n, c.m_n = e["eps_iz"], e["T_n"], e["m_n"]
     c.perturb_amp, c.perturb_mode = e["perturb_amp"], e["perturb_mode"]
+    c.floating = int(e.get("floating", False))
+    c.smooth = int(e.get("smooth", 0))
     return c
 
 
@@ -291,3 +296,10 @@ def thomas(a, b, c, d):
     x = np.zeros(len(b))
     lib().orc_thomas(len(b), _ptr(a), _ptr(b), _ptr(c), _ptr(d), _ptr(x))
     return x
+
+
+def smooth_nodes(rho, periodic, passes):
+    """`passes` of the oracle's 1-2-1 density filter (R23) on a copy of rho."""
+    r = np.array(rho, dtype=np.float64, copy=True)
+    lib().orc_smooth_nodes(len(r), int(bool(periodic)), int(passes), _ptr(r))
+    return r

@@ -336,7 +336,38 @@ void orc_deposit(orc_state *st)
  * Reading R6: E_j = (phi_{j-1} - phi_{j+1}) / (2 dx) inside (and everywhere when periodic);
  *   at a bounded wall Gauss's law over the half cell gives
  *   E_0 = (phi_0 - phi_1)/dx - sigma_0/eps0 and E_N = (phi_{N-1} - phi_N)/dx + sigma_N/eps0
- *   with sigma_j = rho_j V_j.                                                             */
+ *   with sigma_j = rho_j V_j.
+ * Reading R22 (bounded, floating): the walls keep the charge of the particles they absorb
+ *   (the sheath cases of the paper's experimental setup deposit charge on the walls).  The
+ *   system of plasma and walls is isolated, so no field exists left of the left wall, and
+ *   the left wall is the potential reference.  Gauss's law over the left wall and the half
+ *   cell in front of it gives E_{1/2} = (sigma_L + rho_0 V_0)/eps0, with sigma_L = the
+ *   absorbed charge sum_s q_s w_s (particles of s absorbed there); each further cell adds
+ *   rho_j dx / eps0 to the face field, and phi_{j+1} = phi_j - dx E_{j+1/2}.  The right
+ *   wall's potential floats.  R6 gives the wall nodes' E as before.
+ * Reading R23: the density smoothing that the paper's Background section lists in the
+ *   cycle is applied to rho (after the deposit, before the background and the solve).     */
+void orc_smooth_nodes(int64_t nn, int32_t periodic, int32_t passes, double *rho)
+{
+    double *t = (double *)malloc((size_t)nn * sizeof(double));
+    for (int k = 0; k < passes; k++) {
+        memcpy(t, rho, (size_t)nn * sizeof(double));
+        for (int64_t j = 0; j < nn; j++) {
+            double left, right;
+            if (periodic) {
+                left = t[j == 0 ? nn - 1 : j - 1];
+                right = t[j == nn - 1 ? 0 : j + 1];
+            } else {
+                /* a wall node's missing neighbour is its mirror image across the wall */
+                left = t[j == 0 ? 1 : j - 1];
+                right = t[j == nn - 1 ? nn - 2 : j + 1];
+            }
+            rho[j] = 0.25 * left + 0.5 * t[j] + 0.25 * right;
+        }
+    }
+    free(t);
+}
+
 void orc_solve(orc_state *st)
 {
     const orc_config *c = &st->cfg;
@@ -347,6 +378,7 @@ void orc_solve(orc_state *st)
         for (int s = 0; s < c->nspecies; s++) q += c->sp[s].q * c->sp[s].w * st->Q[s][j];
         st->rho[j] = q / node_volume(st, j);
     }
+    if (c->smooth > 0) orc_smooth_nodes(nn, c->periodic, c->smooth, st->rho);
     if (c->periodic) {
         double tot = 0.0;
         for (int64_t j = 0; j < nn; j++) tot += st->rho[j] * node_volume(st, j);
@@ -356,7 +388,16 @@ void orc_solve(orc_state *st)
     int64_t m = N - 1; /* interior unknowns phi_1 .. phi_{N-1} */
     st->phi[0] = 0.0;
     if (!c->periodic) st->phi[N] = 0.0;
-    if (m > 0) {
+    if (!c->periodic && c->floating) {
+        double sigL = 0.0;
+        for (int s = 0; s < c->nspecies; s++)
+            sigL += c->sp[s].q * c->sp[s].w * (double)st->d.wall_count[0][s];
+        double Eface = (sigL + st->rho[0] * node_volume(st, 0)) / c->eps0; /* E_{1/2} */
+        for (int64_t j = 1; j <= N; j++) {
+            st->phi[j] = st->phi[j - 1] - dx * Eface;
+            if (j < N) Eface += st->rho[j] * dx / c->eps0;
+        }
+    } else if (m > 0) {
         double *a = (double *)malloc((size_t)m * sizeof(double));
         double *b = (double *)malloc((size_t)m * sizeof(double));
         double *cc = (double *)malloc((size_t)m * sizeof(double));

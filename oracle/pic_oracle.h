@@ -49,6 +49,8 @@ typedef struct {
     double T_n, m_n;     /* neutral temperature and mass                                      */
     double perturb_amp;  /* quiet start: displacement amplitude A (density ~ 1 - A cos kx)    */
     int32_t perturb_mode;
+    int32_t floating;    /* bounded only: 1 = the walls keep the charge they absorb (R22)     */
+    int32_t smooth;      /* passes of the 1-2-1 filter on rho before the solve (R23), 0 = off */
 } orc_config;
 
 /* Cumulative diagnostics (reset only by orc_create / orc_init). */
@@ -115,6 +117,11 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 void orc_philox_batch(int64_t n, const uint32_t *ctr, const uint32_t *key, uint32_t *out);
 double orc_uniform(uint32_t r);
 void orc_boxmuller(double u1, double u2, double *z0, double *z1);
+
+/* Reading R23: `passes` of the 1-2-1 filter on node densities rho[0 .. nn), in place:
+ * periodic wraps, bounded mirrors at the walls (rho_{-1} = rho_1, rho_{N+1} = rho_{N-1}).
+ * Exposed for pinning. */
+void orc_smooth_nodes(int64_t nn, int32_t periodic, int32_t passes, double *rho);
 
 /* Tridiagonal (Thomas) solve of a_i x_{i-1} + b_i x_i + c_i x_{i+1} = d_i, exposed for pinning. */
 void orc_thomas(int64_t n, const double *a, const double *b, const double *c, const double *d,

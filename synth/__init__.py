@@ -45,7 +45,8 @@ def species(q, m, T, ppc, ncells, cap_factor=1.25, extra=0):
 
 def ensemble(ncells, ppc, *, T_i=1.0 / T_RATIO, B=None, seed=1, periodic=False,
              nspecies=2, collisions=True, sort_every=0, init_mode=0, E_ext=0.0,
-             perturb_amp=0.0, perturb_mode=1, T_e=1.0, cap_factor=1.25, extra=0):
+             perturb_amp=0.0, perturb_mode=1, T_e=1.0, cap_factor=1.25, extra=0,
+             floating=False, smooth=0):
     sp = [species(-1.0, 1.0, T_e, ppc, ncells, cap_factor, extra)]
     if nspecies > 1:
         sp.append(species(+1.0, M_ION, T_i, ppc, ncells, cap_factor, extra))
@@ -59,6 +60,7 @@ def ensemble(ncells, ppc, *, T_i=1.0 / T_RATIO, B=None, seed=1, periodic=False,
         "ngs_el": NGS_EL, "ngs_iz": NGS_IZ, "ngs_cx": NGS_CX, "eps_iz": EPS_IZ,
         "T_n": float(T_i), "m_n": M_ION,
         "perturb_amp": float(perturb_amp), "perturb_mode": int(perturb_mode),
+        "floating": bool(floating), "smooth": int(smooth),
     }
 
 

@@ -245,6 +245,165 @@ def test_poisson_periodic_matches_fft():
 
 
 # ---------------------------------------------------------------------------------------
+# Density smoothing (R23) and floating walls (R22)
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("passes", [1, 2, 3])
+def test_smoothing_periodic_fourier_multiplier(passes):
+    """On a periodic grid the 1-2-1 filter is diagonal in Fourier space: mode m is scaled
+    by cos^2(pi m / N) per pass.  Checked on pure modes and, through the FFT, on noise."""
+    N = 64
+    j = np.arange(N)
+    for m in (0, 1, 5, 16, 31, 32):
+        r = np.cos(2 * np.pi * m * j / N + 0.3)
+        out = oracle.smooth_nodes(r, True, passes)
+        assert np.max(np.abs(out - np.cos(np.pi * m / N) ** (2 * passes) * r)) <= 1e-14
+    r = np.random.default_rng(3).standard_normal(N)
+    mult = np.cos(np.pi * np.arange(N) / N) ** (2 * passes)
+    ref = np.fft.ifft(np.fft.fft(r) * mult).real
+    out = oracle.smooth_nodes(r, True, passes)
+    assert np.max(np.abs(out - ref)) <= 1e-14 * np.abs(r).max() * 10
+    assert abs(out.sum() - r.sum()) <= 1e-13
+
+
+@pytest.mark.parametrize("passes", [1, 2, 4])
+def test_smoothing_bounded_cosine_modes_and_charge(passes):
+    """Bounded grids mirror at the walls, so the wall-symmetric modes cos(pi m j / N) are
+    eigenvectors with factor cos^2(pi m / 2N) per pass (the DCT-I diagonalises the
+    filter); uniform density is unchanged and sum rho V (half volume at the walls) is
+    conserved."""
+    N = 40
+    j = np.arange(N + 1)
+    for m in (0, 1, 7, 20, 39, 40):
+        r = np.cos(np.pi * m * j / N)
+        out = oracle.smooth_nodes(r, False, passes)
+        assert np.max(np.abs(out - np.cos(np.pi * m / (2 * N)) ** (2 * passes) * r)) <= 1e-14
+    import scipy.fft
+    r = np.random.default_rng(4).standard_normal(N + 1)
+    mult = np.cos(np.pi * np.arange(N + 1) / (2 * N)) ** (2 * passes)
+    ref = scipy.fft.idct(scipy.fft.dct(r, type=1) * mult, type=1)
+    out = oracle.smooth_nodes(r, False, passes)
+    assert np.max(np.abs(out - ref)) <= 1e-13
+    V = np.ones(N + 1)
+    V[0] = V[-1] = 0.5
+    assert abs((out * V).sum() - (r * V).sum()) <= 1e-13
+
+
+def test_smoothing_feeds_the_solve():
+    """With smoothing on, the solve's rho is the filtered deposit, and the potential
+    still solves the stencil for that rho."""
+    e, o = _random_two_species(60, seed=12)
+    o.deposit()
+    o.solve()
+    raw = o.grid()["rho"]
+    e2 = dict(e, smooth=2)
+    o2 = oracle.Oracle(e2, init=False)
+    o2.set_state([o.particles(s) for s in range(2)])
+    o2.deposit()
+    o2.solve()
+    g = o2.grid()
+    sm = raw.copy()
+    for _ in range(2):
+        ext = np.concatenate([[sm[1]], sm, [sm[-2]]])
+        sm = 0.25 * ext[:-2] + 0.5 * ext[1:-1] + 0.25 * ext[2:]
+    assert np.max(np.abs(g["rho"] - sm)) <= 1e-13 * np.abs(raw).max()
+    dx = e["dx"]
+    lap = g["phi"][:-2] - 2 * g["phi"][1:-1] + g["phi"][2:]
+    assert np.max(np.abs(lap + g["rho"][1:-1] * dx * dx)) <= 1e-11 * np.abs(g["phi"]).max()
+
+
+def test_floating_poisson_closed_form():
+    """Floating walls, no absorbed charge, one unit particle on every interior node:
+    no field left of x = 0, E_{j+1/2} = rho j dx / eps0, so
+    phi_j = -rho x_j (x_j - dx) / (2 eps0), E_0 = 0 and E_N = rho (N - 1) dx / eps0."""
+    N = 40
+    e = _one_species(N)
+    e["species"][0]["q"] = 1.0
+    e["floating"] = True
+    o = oracle.Oracle(e, init=False)
+    dx = e["dx"]
+    x = np.arange(1, N) * dx
+    n = len(x)
+    o.set_particles(0, x, np.zeros(n), np.zeros(n), np.zeros(n), np.arange(n), n)
+    o.deposit()
+    o.solve()
+    g = o.grid()
+    rho = e["species"][0]["w"] / dx
+    xs = np.arange(N + 1) * dx
+    phi_ref = -rho * xs * (xs - dx) / 2.0
+    assert np.max(np.abs(g["phi"] - phi_ref)) <= 1e-12 * np.abs(phi_ref).max()
+    E_ref = rho * (xs - dx / 2)
+    assert np.max(np.abs(g["E"][1:-1] - E_ref[1:-1])) <= 1e-12 * np.abs(E_ref).max()
+    assert abs(g["E"][0]) <= 1e-14
+    assert abs(g["E"][-1] - rho * (N - 1) * dx) <= 1e-12 * rho * N * dx
+
+
+def test_floating_poisson_wall_charge_gauss_and_banded_solve():
+    """After particles are absorbed at the left wall, the floating solve satisfies: phi_0 = 0,
+    the interior stencil, Gauss over the left wall and half cell with the absorbed charge,
+    and matches a banded solve of the interior with its own phi_N as the right value."""
+    N = 97
+    e = synth.ensemble(N, 7, collisions=False, floating=True)
+    st = synth.random_state(e, [7 * N, 7 * N], seed=17, vscale=[1.0, 0.3])
+    dx, eps0 = e["dx"], e["eps0"]
+    # the first 40 electrons and 25 ions sit near the left wall moving out of it
+    for s, k in ((0, 40), (1, 25)):
+        st[s]["x"][:k] = np.linspace(0.001, 0.05, k)
+        st[s]["vx"][:k] = -1.0
+    o = oracle.Oracle(e, init=False)
+    o.set_state(st)
+    o.set_fields(np.zeros(o.nnodes))
+    o.push()
+    o.walls()
+    o.deposit()
+    o.solve()
+    d = o.diag()
+    assert d["wall_count"][0][0] >= 40 and d["wall_count"][0][1] >= 25
+    sigL = sum(sp["q"] * sp["w"] * d["wall_count"][0][s] for s, sp in enumerate(e["species"]))
+    assert sigL != 0.0
+    g = o.grid()
+    rho, phi, E = g["rho"], g["phi"], g["E"]
+    scale = np.abs(phi).max()
+    assert phi[0] == 0.0
+    lap = phi[:-2] - 2 * phi[1:-1] + phi[2:]
+    assert np.max(np.abs(lap + rho[1:-1] * dx * dx / eps0)) <= 1e-11 * scale
+    assert abs(eps0 * (phi[0] - phi[1]) / dx - (sigL + rho[0] * dx / 2)) <= 1e-11 * max(1.0, abs(sigL))
+    assert abs(E[0] - sigL / eps0) <= 1e-11 * max(1.0, abs(sigL))
+    V = np.full(N + 1, dx)
+    V[0] = V[-1] = dx / 2
+    assert abs(eps0 * (E[-1] - E[0]) - (rho * V).sum()) <= 1e-11 * max(1.0, np.abs(rho * V).sum())
+    m = N - 1
+    ab = np.zeros((3, m))
+    ab[0, 1:] = 1.0
+    ab[1] = -2.0
+    ab[2, :-1] = 1.0
+    rhs = -rho[1:N] * dx * dx / eps0
+    rhs[-1] -= phi[N]
+    ref = scipy.linalg.solve_banded((1, 1), ab, rhs)
+    assert np.max(np.abs(phi[1:N] - ref)) <= 1e-10 * scale
+
+
+def test_floating_walls_hold_the_missing_charge():
+    """A neutral bounded plasma with floating walls: all charge a wall absorbs stays on
+    it, so at every step eps0 E_N equals minus the right wall's charge (no field right
+    of the right wall) while E_0 equals the left wall's charge over eps0."""
+    w = synth.scaled(synth.c1_plain_small(), ncells=48, ppc=40)
+    e = w["ensembles"][0]
+    e["floating"] = True
+    o = oracle.Oracle(e)
+    for _ in range(30):
+        o.step(1)
+        o.solve()
+        d = o.diag()
+        g = o.grid()
+        sig = [sum(sp["q"] * sp["w"] * d["wall_count"][wall][s] for s, sp in enumerate(e["species"]))
+               for wall in range(2)]
+        scale = sum(abs(sp["q"] * sp["w"]) * sp["ppc"] * e["ncells"] for sp in e["species"])
+        assert abs(e["eps0"] * g["E"][0] - sig[0]) <= 1e-12 * scale
+        assert abs(e["eps0"] * g["E"][-1] + sig[1]) <= 1e-12 * scale
+    assert d["wall_count"][0][0] + d["wall_count"][1][0] > 0
+
+
+# ---------------------------------------------------------------------------------------
 # Boris push
 # ---------------------------------------------------------------------------------------
 def _rodrigues(v, axis, ang):
