@@ -108,6 +108,34 @@ def batched_run(pic, shape, steps):
             "cells": sum(e["ncells"] for e in work["ensembles"])}
 
 
+def walls_variant_run(pic, shape, steps, seed, smooth):
+    """The main workload with floating walls (the absorbed charge stays on the walls) and
+    `smooth` passes of the density filter before each solve: the same fused graph, with
+    the solve's wall boundary condition and smoothed density the only differences."""
+    import torch
+
+    import synth
+
+    work = synth.c2_sheath(seed=seed)
+    e = work["ensembles"][0]
+    e["floating"] = True
+    e["smooth"] = smooth
+    sim = pic.Sim(work, fused=True, **shape)
+    sim.step(20)
+    torch.cuda.synchronize()
+    p0 = sim.diag()["pushes"]
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    p1 = sim.diag()["pushes"]
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return {"value": (p1 - p0) / (t1 - t0), "unit": "particle-pushes/s", "steps": steps,
+            "ms_per_step": (t1 - t0) / steps * 1e3, "boundary": "floating", "smooth": smooth}
+
+
 def stream_copy_gbs(torch, gib=4.0, reps=10):
     """Device-to-device copy bandwidth of a plain torch copy on the same GPU (read + write
     bytes per second), for context next to the HBM peak."""
@@ -147,6 +175,11 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=40)
     ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--no-walls-variant", action="store_true")
+    ap.add_argument("--floating", action="store_true",
+                    help="main workload with floating walls (for profiling the variant)")
+    ap.add_argument("--smooth", type=int, default=0,
+                    help="passes of the density filter in the main workload (for profiling)")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="also run one elementwise copy of this many GiB (counter calibration)")
     args = ap.parse_args()
@@ -166,6 +199,8 @@ def main():
     torch.cuda.set_device(0)
     work = synth.c2_sheath(seed=args.seed, ncells=args.ncells, ppc=args.ppc)
     e = work["ensembles"][0]
+    e["floating"] = bool(args.floating)
+    e["smooth"] = int(args.smooth)
     if args.shape:
         ppt, window, sort_ppt, nt = (int(v) for v in args.shape.split(","))
         shape = {"ppt": ppt, "window": window, "sort_ppt": sort_ppt, "nontemporal": nt}
@@ -235,6 +270,10 @@ def main():
     if not args.no_batched:
         batched = batched_run(pic, shape, args.batched_steps)
 
+    walls = None
+    if not args.no_walls_variant:
+        walls = walls_variant_run(pic, shape, args.batched_steps, args.seed, 2)
+
     stream = None
     if not args.no_stream:
         stream = stream_copy_gbs(torch)
@@ -256,7 +295,9 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"sheath slab {e['ncells']} cells x {e['species'][0]['ppc']} ppc x 2 species, "
-                               f"oblique B, 3 collision channels, sort every {e['sort_every']}",
+                               f"oblique B, 3 collision channels, sort every {e['sort_every']}"
+                               + (", floating walls" if args.floating else "")
+                               + (f", {args.smooth} smoothing passes" if args.smooth else ""),
                    "particles": 2 * e["species"][0]["ppc"] * e["ncells"], "seed": args.seed,
                    "form": "FP32 cell+offset, fused pass, HIP graph", "parallelism": "single GPU",
                    "launch_shape": shape},
@@ -264,6 +305,7 @@ def main():
         "whole_step": whole_step,
         "plain": plain,
         "batched": batched,
+        "floating_walls_smoothed": walls,
         "stream_copy": stream,
         "cpu_baseline": cpu,
     }

@@ -45,6 +45,8 @@ extern "C" {
 
 #define PIC_ABSORBING 0      /* grounded absorbing walls at x = 0 and x = L               */
 #define PIC_PERIODIC 1
+#define PIC_FLOATING 2       /* absorbing walls that keep the charge they absorb: no field
+                              * left of x = 0, phi_0 = 0, the right wall floats (R22)      */
 
 #define PIC_MAX_ENSEMBLES 256
 
@@ -77,7 +79,7 @@ typedef struct {
 typedef struct {
     int32_t n_ensembles;
     int32_t precision;   /* PIC_FP64_PLAIN or PIC_FP32_CELLOFF                              */
-    int32_t boundary;    /* PIC_ABSORBING or PIC_PERIODIC (all ensembles)                   */
+    int32_t boundary;    /* PIC_ABSORBING, PIC_PERIODIC or PIC_FLOATING (all ensembles)      */
     int32_t nspecies;    /* 1: electrons on a fixed neutralising background; 2: e + ions   */
     int32_t collisions;  /* 0: collisionless                                               */
     int32_t sort_every;  /* K: counting sort (which also compacts absorbed slots) when the
@@ -92,6 +94,9 @@ typedef struct {
     int32_t nontemporal; /* bit 0: the fused FP32 pass streams particles with non-temporal
                           * loads and stores; bit 1: so does the FP32 sort scatter;
                           * 0 = ordinary cached accesses (default)                         */
+    int32_t smooth;      /* passes (0..4) of the 1-2-1 density filter applied to rho before
+                          * every solve (R23): periodic grids wrap, bounded grids mirror at
+                          * the walls; 0 = off                                              */
     const pic_ensemble_desc *ens;              /* [n_ensembles], copied by pic_init       */
 } pic_config;
 
@@ -131,10 +136,14 @@ int pic_init(const pic_config *cfg, void *workspace, size_t bytes, void *stream,
  * form: FP64 sums).  Replaces the previous Q. */
 int pic_deposit(pic_ctx *ctx, void *stream);
 
-/* Field solve from Q: rho_j = sum_s q_s w_s Q_{s,j} / V_j, the three-point Poisson stencil
- * with grounded walls (R3) or a neutralising background and zero-mean phi (R4), solved
- * exactly by two prefix sums (equivalent to the Thomas solve, R5), node E from the centred
- * difference with the half-cell Gauss rule at walls (R6).  FP64. */
+/* Field solve from Q: rho_j = sum_s q_s w_s Q_{s,j} / V_j, optionally smoothed (R23), the
+ * three-point Poisson stencil with grounded walls (R3), a neutralising background and
+ * zero-mean phi (R4), or floating walls (R22: E_{1/2} = (sigma_L + rho_0 V_0) / eps0 with
+ * sigma_L the charge absorbed so far at the left wall, phi_0 = 0), solved exactly by two
+ * prefix sums (equivalent to the Thomas solve, R5), node E from the centred difference
+ * with the half-cell Gauss rule at walls (R6).  FP64.  The density smoothing and wall
+ * boundary conditions follow the cycle of the paper's Background section and the
+ * charge-depositing walls of its sheath cases (experimental setup). */
 int pic_solve(pic_ctx *ctx, void *stream);
 
 /* Gather E at each particle (linear), Boris push in E + E_ext along x and uniform B,

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libpic.so")
 
 PIC_OK, PIC_EINVAL, PIC_ECAPACITY, PIC_ENONFINITE, PIC_EHIP, PIC_ESTATE = 0, -1, -2, -3, -4, -5
 PIC_FP64_PLAIN, PIC_FP32_CELLOFF = 0, 1
-PIC_ABSORBING, PIC_PERIODIC = 0, 1
+PIC_ABSORBING, PIC_PERIODIC, PIC_FLOATING = 0, 1, 2
 
 EXPORTS = ("pic_query_workspace", "pic_init", "pic_deposit", "pic_solve", "pic_push",
            "pic_collide", "pic_sort", "pic_step", "pic_diag", "pic_get_particles",
@@ -53,7 +53,7 @@ class Config(C.Structure):
                 ("nspecies", C.c_int32), ("collisions", C.c_int32), ("sort_every", C.c_int32),
                 ("fused", C.c_int32), ("block", C.c_int32), ("grid", C.c_int32),
                 ("window", C.c_int32), ("ppt", C.c_int32), ("sort_ppt", C.c_int32),
-                ("nontemporal", C.c_int32),
+                ("nontemporal", C.c_int32), ("smooth", C.c_int32),
                 ("ens", C.POINTER(EnsembleDesc))]
 
 
@@ -152,7 +152,11 @@ def make_config(work, fused=True, precision=None, block=0, grid=0, window=0, ppt
     cfg = Config()
     cfg.n_ensembles = len(ens)
     cfg.precision = PIC_FP64_PLAIN if prec == "fp64" else PIC_FP32_CELLOFF
-    cfg.boundary = PIC_PERIODIC if e0["periodic"] else PIC_ABSORBING
+    if e0["periodic"]:
+        cfg.boundary = PIC_PERIODIC
+    else:
+        cfg.boundary = PIC_FLOATING if e0.get("floating", False) else PIC_ABSORBING
+    cfg.smooth = int(e0.get("smooth", 0))
     cfg.nspecies = e0["nspecies"]
     cfg.collisions = int(e0["collisions"])
     cfg.sort_every = e0["sort_every"]

@@ -54,8 +54,13 @@ int build_plan(const pic_config *cfg, Plan &P, std::string &msg)
         msg = "bad precision";
         return PIC_EINVAL;
     }
-    if (cfg->boundary != PIC_ABSORBING && cfg->boundary != PIC_PERIODIC) {
+    if (cfg->boundary != PIC_ABSORBING && cfg->boundary != PIC_PERIODIC &&
+        cfg->boundary != PIC_FLOATING) {
         msg = "bad boundary";
+        return PIC_EINVAL;
+    }
+    if (cfg->smooth < 0 || cfg->smooth > kMaxSmooth) {
+        msg = "smooth must be in [0, " + std::to_string(kMaxSmooth) + "]";
         return PIC_EINVAL;
     }
     P.nens = cfg->n_ensembles;
@@ -90,6 +95,8 @@ int build_plan(const pic_config *cfg, Plan &P, std::string &msg)
         E.m_n = D.m_n;
         E.seed = D.seed;
         E.periodic = periodic ? 1 : 0;
+        E.floating = cfg->boundary == PIC_FLOATING ? 1 : 0;
+        E.smooth = cfg->smooth;
         E.nspecies = P.nspecies;
         // ids (loaded and born) stay below 2 x electron capacity, rounded to 1024
         int64_t idcap = (2 * D.sp[0].capacity + 2048) / 1024 * 1024;
@@ -844,6 +851,7 @@ int adj_check(pic_ctx *c, std::string &why)
     if (c->P.nens != 1 || c->P.nspecies != 1) why = "adjoint needs one ensemble and one species";
     else if (!c->d.periodic) why = "adjoint needs a periodic domain";
     else if (c->cfg.collisions) why = "adjoint needs a collisionless run";
+    else if (c->cfg.smooth) why = "adjoint is defined without density smoothing";
     else if (c->P.f64) why = "adjoint is defined on the FP32 form";
     else {
         const SegC &S = c->P.seg[0];

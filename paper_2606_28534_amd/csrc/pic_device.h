@@ -24,6 +24,7 @@ constexpr int32_t kDead = INT32_MIN;  // FP32 form: cell of an absorbed slot
 constexpr int kChunk = 2048;          // nodes per block in the field solve
 constexpr int kSolveThreads = 256;
 constexpr int kMaxEns = 256;          // ensembles per context
+constexpr int kMaxSmooth = 4;         // passes of the density filter
 // Birth ranking: a bit per parent id and a count per group of kGroupIds ids (a birth's rank
 // among its ensemble's births is the scanned count of the groups below its own plus the
 // bits below it in its group).
@@ -72,6 +73,8 @@ struct EnsC {
     int32_t seg[2];
     uint32_t seed;
     int32_t periodic, nspecies;
+    int32_t floating;         // bounded walls keep their absorbed charge (R22)
+    int32_t smooth;           // passes of the 1-2-1 density filter (R23)
 };
 
 struct Birth {

@@ -511,6 +511,38 @@ __device__ __forceinline__ double node_vol(const EnsC &e, int64_t j)
     return e.dx;
 }
 
+// Reading R23: p passes of the 1-2-1 filter equal one binomial stencil of width 2p + 1
+// (weights C(2p, p + i) / 4^p) applied to the periodic extension of rho, or on a bounded
+// grid to its even extension across both walls (a pass maps an even extension to an even
+// extension, with rho_{-1} = rho_1 at the wall, so the passes compose into the stencil).
+// Each node therefore reads its 2p + 1 neighbours once instead of p sweeps over the grid.
+__device__ __forceinline__ int64_t smooth_fold(const EnsC &e, int64_t m)
+{
+    if (e.periodic) {
+        const int64_t n = e.ncells;
+        m %= n;
+        return m < 0 ? m + n : m;
+    }
+    const int64_t n2 = 2 * e.ncells;
+    m %= n2;
+    if (m < 0) m += n2;
+    return m > e.ncells ? n2 - m : m;
+}
+
+template <bool F64>
+__device__ __forceinline__ double node_rho(const Dev &d, const EnsC &e, int64_t j)
+{
+    if (e.smooth == 0) return node_charge<F64>(d, e, j) / node_vol(e, j);
+    const int p = e.smooth;
+    double r = 0.0, c = 1.0;  // c = C(2p, k), exact in binary64
+    for (int k = 0; k <= 2 * p; ++k) {
+        const int64_t m = smooth_fold(e, j - p + k);
+        r += c * (node_charge<F64>(d, e, m) / node_vol(e, m));
+        c = c * (double)(2 * p - k) / (double)(k + 1);
+    }
+    return r * (1.0 / (double)(1 << (2 * p)));
+}
+
 // Block-wide inclusive scan of one double per thread (256 threads).
 __device__ double block_incl_scan(double v, double *s_buf)
 {
@@ -596,10 +628,9 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve1(Dev d)
         const int64_t j = j0 + q;
         double r = 0.0;
         if (j < nn) {
-            const double V = node_vol(e, j);
-            r = node_charge<F64>(d, e, j) / V;
+            r = node_rho<F64>(d, e, j);
             d.rho[e.gbase + j] = r;
-            totq += r * V;
+            totq += r * node_vol(e, j);
         }
         if (q == 0) rho_first = r;
         rho_loc[q] = (j >= 1 && j <= N - 1) ? r : 0.0;
@@ -715,10 +746,26 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve2(Dev d, int zero_q)
             s_C0 = ca;
             s_F0 = fa;
         }
+        // Reading R22: floating walls fix E_{1/2} by Gauss's law over the left wall (the
+        // charge absorbed there, q w per particle, from the exact wall counts) and the half
+        // cell in front of it; otherwise phi_N = 0 (or periodicity) fixes it.
+        double sigL = 0.0;
+        if (e.floating) {
+            double nabs[2] = {0.0, 0.0};  // counts < 2^53: exact in binary64
+            for (int st = threadIdx.x; st < kCntStripes; st += blockDim.x)
+                for (int s = 0; s < e.nspecies; ++s)
+                    nabs[s] += (double)d.cnt[((int64_t)st * d.nseg + e.seg[s]) * C_NCNT + C_WALL_L];
+            __shared__ double s_red4[2 * 16];
+            block_sums<2>(nabs, s_red4);
+            for (int s = 0; s < e.nspecies; ++s) sigL += e.qw[s] * nabs[s];
+        }
         if (threadIdx.x == 0) {
             s_bg = bg;
             s_Ctot = Ctot;
-            s_Eh = -ce * Stot / (double)N;
+            if (e.floating)
+                s_Eh = (sigL + d.agg[e.chunk0 * A_NAGG + A_RHO0] * node_vol(e, 0)) / e.eps0;
+            else
+                s_Eh = -ce * Stot / (double)N;
         }
     }
     __syncthreads();
@@ -761,7 +808,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve2(Dev d, int zero_q)
         const int64_t j = j0 + q;
         if (j >= nn) break;
         double phi = -dx * ((double)j * Eh + ce * F);
-        if (!e.periodic && j == N) phi = 0.0;
+        if (!e.periodic && !e.floating && j == N) phi = 0.0;
         if (j == 0) phi = 0.0;
         d.phi[e.gbase + j] = phi;
         phisum += phi;
