@@ -353,15 +353,45 @@ hipError_t enqueue_step(pic_ctx *c, hipStream_t s, bool sort_now)
     return hipSuccess;
 }
 
+// One sort cycle (K steps) of the fused step with collisions, for graph capture.  The
+// births of step i - 1 are ranked and placed by extra blocks of step i's two solve
+// kernels instead of kernels of their own: the placement touches new particle slots, the
+// slot and id counters, the birth lists and bitmaps, the speed-maximum halves and the step
+// counter, the solve only the grid, so they run side by side, and the collision
+// parameters and the particle pass after them see both.  The last step's births are
+// placed before the sort, in line.  The state after the cycle is the same as after K
+// calls of enqueue_step.
+hipError_t enqueue_cycle_merged(pic_ctx *c, hipStream_t s)
+{
+    const Dev &d = c->d;
+    const bool f64 = c->P.f64;
+    const int K = c->sort_every;
+    const int stages = SB_PUSH | SB_COLLIDE | SB_DEPOSIT;
+    hipError_t e;
+    for (int i = 0; i < K; ++i) {
+        const int hist = (i == K - 1) ? 1 : 0;
+        if ((e = launch_solve(d, f64, c->P.chunks_tot, true, s, i > 0)) != hipSuccess) return e;
+        if ((e = launch_particles(d, c->L, s, f64, stages, hist)) != hipSuccess) return e;
+        if ((e = launch_candidates(d, c->L, s, f64, hist)) != hipSuccess) return e;
+    }
+    if ((e = launch_births(d, f64, true, true, s)) != hipSuccess) return e;
+    return launch_sort(d, f64, c->L, s);
+}
+
 int build_graph(pic_ctx *c)
 {
     if (c->graph) return PIC_OK;
     if (!c->cap_stream) HIPC(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    const bool merged = c->cfg.collisions != 0 && births_fit_solve(c->d);
     hipGraph_t g = nullptr;
     HIPC(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int i = 0; i < c->sort_every && e == hipSuccess; ++i)
-        e = enqueue_step(c, c->cap_stream, i == c->sort_every - 1);
+    if (merged) {
+        e = enqueue_cycle_merged(c, c->cap_stream);
+    } else {
+        for (int i = 0; i < c->sort_every && e == hipSuccess; ++i)
+            e = enqueue_step(c, c->cap_stream, i == c->sort_every - 1);
+    }
     hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
     if (e != hipSuccess) return hipfail(c, e, "graph capture");
     if (e2 != hipSuccess) return hipfail(c, e2, "hipStreamEndCapture");

@@ -516,31 +516,31 @@ __device__ __forceinline__ double node_vol(const EnsC &e, int64_t j)
 // grid to its even extension across both walls (a pass maps an even extension to an even
 // extension, with rho_{-1} = rho_1 at the wall, so the passes compose into the stencil).
 // Each node therefore reads its 2p + 1 neighbours once instead of p sweeps over the grid.
+// smooth_fold maps a node index in [-p, nn - 1 + p] onto the grid (p <= 4 and N >= 2, so a
+// couple of wraps or reflections at most).
 __device__ __forceinline__ int64_t smooth_fold(const EnsC &e, int64_t m)
 {
+    const int64_t n = e.ncells;
     if (e.periodic) {
-        const int64_t n = e.ncells;
-        m %= n;
-        return m < 0 ? m + n : m;
+        while (m < 0) m += n;
+        while (m >= n) m -= n;
+        return m;
     }
-    const int64_t n2 = 2 * e.ncells;
-    m %= n2;
-    if (m < 0) m += n2;
-    return m > e.ncells ? n2 - m : m;
+    for (int it = 0; it < 8; ++it) {
+        if (m < 0)
+            m = -m;
+        else if (m > n)
+            m = 2 * n - m;
+        else
+            break;
+    }
+    return m;
 }
 
 template <bool F64>
-__device__ __forceinline__ double node_rho(const Dev &d, const EnsC &e, int64_t j)
+__device__ __forceinline__ double node_rho_raw(const Dev &d, const EnsC &e, int64_t j)
 {
-    if (e.smooth == 0) return node_charge<F64>(d, e, j) / node_vol(e, j);
-    const int p = e.smooth;
-    double r = 0.0, c = 1.0;  // c = C(2p, k), exact in binary64
-    for (int k = 0; k <= 2 * p; ++k) {
-        const int64_t m = smooth_fold(e, j - p + k);
-        r += c * (node_charge<F64>(d, e, m) / node_vol(e, m));
-        c = c * (double)(2 * p - k) / (double)(k + 1);
-    }
-    return r * (1.0 / (double)(1 << (2 * p)));
+    return node_charge<F64>(d, e, j) / node_vol(e, j);
 }
 
 // Block-wide inclusive scan of one double per thread (256 threads).
@@ -608,10 +608,23 @@ __device__ __forceinline__ int chunk_ens(const Dev &d, int64_t k)
 }
 
 constexpr int kNodesPerThread = kChunk / kSolveThreads;
+constexpr int kPlaceBlocks = 64;  // blocks that place a step's births
 
+// Birth ranking and placement, callable by a block of a kernel of their own or by extra
+// blocks of the two solve kernels (defined with the births below).
+__device__ void group_scan_body(const Dev &d);
 template <bool F64>
-__global__ void __launch_bounds__(kSolveThreads) k_solve1(Dev d)
+__device__ void birth_place_body(const Dev &d, int deferred, int advance, int bid, int nblk);
+
+// Blocks [0, nchunks) solve; with `scan`, one more block scans the group counts of the
+// previous step's births (independent data), so that scan costs no launch of its own.
+template <bool F64>
+__global__ void __launch_bounds__(kSolveThreads) k_solve1(Dev d, int nchunks, int scan)
 {
+    if ((int)blockIdx.x >= nchunks) {
+        if (scan) group_scan_body(d);
+        return;
+    }
     __shared__ double s_buf[8];
     const int64_t k = blockIdx.x;
     const int ei = chunk_ens(d, k);
@@ -623,12 +636,34 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve1(Dev d)
     // thread-local prefix of interior rho and its running sum
     double rho_loc[kNodesPerThread];
     double rho_first = 0.0;  // rho of the chunk's first node (thread 0), for the next chunk's solve
+    // smoothing (R23): the chunk's raw densities and a halo of p nodes each side, folded
+    // onto the grid, staged in LDS with coalesced loads; s_raw[i] is node a - p + i
+    __shared__ double s_raw[kChunk + 2 * kMaxSmooth];
+    const int p = e.smooth;
+    if (p > 0) {
+        for (int i = threadIdx.x; i < kChunk + 2 * p; i += blockDim.x) {
+            const int64_t m = a - p + i;
+            s_raw[i] = (m <= nn - 1 + p) ? node_rho_raw<F64>(d, e, smooth_fold(e, m)) : 0.0;
+        }
+        __syncthreads();
+    }
+    const double pscale = 1.0 / (double)(1 << (2 * p));
 #pragma unroll
     for (int q = 0; q < kNodesPerThread; ++q) {
         const int64_t j = j0 + q;
         double r = 0.0;
         if (j < nn) {
-            r = node_rho<F64>(d, e, j);
+            if (p == 0) {
+                r = node_rho_raw<F64>(d, e, j);
+            } else {
+                double c = 1.0;  // C(2p, k), exact in binary64
+                const int i0 = (int)(j - a);
+                for (int k = 0; k <= 2 * p; ++k) {
+                    r += c * s_raw[i0 + k];
+                    c = c * (double)(2 * p - k) / (double)(k + 1);
+                }
+                r *= pscale;
+            }
             d.rho[e.gbase + j] = r;
             totq += r * node_vol(e, j);
         }
@@ -694,9 +729,16 @@ __device__ void compute_params(const Dev &d)
 
 __global__ void k_params(Dev d) { compute_params(d); }
 
+// Blocks [0, nchunks) solve; blocks beyond place the previous step's births (they touch
+// particle slots beyond the ones in use, the id and slot counters, the birth lists, the
+// speed-maximum halves and the step counter, none of which the solve reads or writes).
 template <bool F64>
-__global__ void __launch_bounds__(kSolveThreads) k_solve2(Dev d, int zero_q)
+__global__ void __launch_bounds__(kSolveThreads) k_solve2(Dev d, int zero_q, int nchunks)
 {
+    if ((int)blockIdx.x >= nchunks) {
+        birth_place_body<F64>(d, 1, 1, (int)blockIdx.x - nchunks, (int)gridDim.x - nchunks);
+        return;
+    }
     __shared__ double s_buf[8];
     __shared__ double s_E[F64 ? 1 : kChunk + 1];  // the chunk's node E, for the gather table
     __shared__ double s_C0, s_F0, s_Eh, s_bg, s_Ctot;
@@ -713,6 +755,13 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve2(Dev d, int zero_q)
         const int64_t nc = e.nchunks;
         const int64_t R = (nc + blockDim.x - 1) / blockDim.x;
         const int64_t c0 = (int64_t)threadIdx.x * R, c1 = min(c0 + R, nc);
+        // floating walls (R22): the particles absorbed so far at the left wall, per
+        // species, from the exact striped wall counts (sums < 2^53: exact in binary64)
+        double nabs[2] = {0.0, 0.0};
+        if (e.floating)
+            for (int st = threadIdx.x; st < kCntStripes; st += blockDim.x)
+                for (int s = 0; s < e.nspecies; ++s)
+                    nabs[s] += (double)d.cnt[((int64_t)st * d.nseg + e.seg[s]) * C_NCNT + C_WALL_L];
         double tq = 0.0;
         for (int64_t c = c0; c < c1; ++c) tq += d.agg[(e.chunk0 + c) * A_NAGG + A_TOTQ];
         const double tqs = block_sum(tq, s_buf);
@@ -729,9 +778,9 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve2(Dev d, int zero_q)
         const double apre = block_incl_scan(a, s_buf) - a;  // C_pre at c0
         const double fin = n * apre + g;                    // this range's sum of C over m
         const double fpre = block_incl_scan(fin, s_buf) - fin;
-        __shared__ double s_red2[2 * 16];
-        double st[2] = {fin, a};
-        block_sums<2>(st, s_red2);
+        __shared__ double s_red2[4 * 16];
+        double st[4] = {fin, a, nabs[0], nabs[1]};
+        block_sums<4>(st, s_red2);
         const double Stot = st[0], Ctot = st[1];
         const int64_t me = k - e.chunk0;
         if (me >= c0 && me < c1) {
@@ -747,18 +796,10 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve2(Dev d, int zero_q)
             s_F0 = fa;
         }
         // Reading R22: floating walls fix E_{1/2} by Gauss's law over the left wall (the
-        // charge absorbed there, q w per particle, from the exact wall counts) and the half
-        // cell in front of it; otherwise phi_N = 0 (or periodicity) fixes it.
+        // charge absorbed there, q w per particle) and the half cell in front of it;
+        // otherwise phi_N = 0 (or periodicity) fixes it.
         double sigL = 0.0;
-        if (e.floating) {
-            double nabs[2] = {0.0, 0.0};  // counts < 2^53: exact in binary64
-            for (int st = threadIdx.x; st < kCntStripes; st += blockDim.x)
-                for (int s = 0; s < e.nspecies; ++s)
-                    nabs[s] += (double)d.cnt[((int64_t)st * d.nseg + e.seg[s]) * C_NCNT + C_WALL_L];
-            __shared__ double s_red4[2 * 16];
-            block_sums<2>(nabs, s_red4);
-            for (int s = 0; s < e.nspecies; ++s) sigL += e.qw[s] * nabs[s];
-        }
+        for (int s = 0; s < e.nspecies; ++s) sigL += e.qw[s] * st[2 + s];
         if (threadIdx.x == 0) {
             s_bg = bg;
             s_Ctot = Ctot;
@@ -1143,7 +1184,7 @@ __device__ __forceinline__ uint32_t rank_in_group(const uint32_t *group, uint32_
 // owns a contiguous run of g_tot / blockDim counts (g_tot is a multiple of 4096), sums it,
 // takes one block-wide scan of the sums, then writes its run; the run is read in groups of
 // four independent 16-byte loads so their latencies overlap.
-__global__ void __launch_bounds__(1024) k_group_scan(Dev d)
+__device__ void group_scan_body(const Dev &d)
 {
     __shared__ uint32_t s_buf[16];
     const int p = (int)(*d.step & 1);
@@ -1184,13 +1225,15 @@ __global__ void __launch_bounds__(1024) k_group_scan(Dev d)
     }
 }
 
+__global__ void __launch_bounds__(1024) k_group_scan(Dev d) { group_scan_body(d); }
+
 // Place the births of this step (half p = step & 1).  With `deferred`, also clear the
 // bitmap bits and group counts of half 1 - p (the previous step's births) and reset its
 // birth counts, so the next step starts on a clean half.  The last block updates the
 // counters, makes the freshly accumulated speed maxima current and (with `advance`)
 // advances the step counter.
 template <bool F64>
-__global__ void __launch_bounds__(256) k_birth_place(Dev d, int deferred, int advance)
+__device__ void birth_place_body(const Dev &d, int deferred, int advance, int bid, int nblk)
 {
     __shared__ uint32_t s_pre[kStripes + 1];
     __shared__ uint32_t s_old[kStripes + 1];
@@ -1204,8 +1247,8 @@ __global__ void __launch_bounds__(256) k_birth_place(Dev d, int deferred, int ad
     __syncthreads();
     const int64_t M = s_pre[kStripes];
     const int b = *d.cur;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < M;
-         k += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t k = (int64_t)bid * blockDim.x + threadIdx.x; k < M;
+         k += (int64_t)nblk * blockDim.x) {
         int st;
         uint32_t idx;
         birth_locate(d, k, st, idx, s_pre);
@@ -1246,8 +1289,8 @@ __global__ void __launch_bounds__(256) k_birth_place(Dev d, int deferred, int ad
     }
     if (deferred) {
         const int64_t Mo = s_old[kStripes];
-        for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < Mo;
-             k += (int64_t)gridDim.x * blockDim.x) {
+        for (int64_t k = (int64_t)bid * blockDim.x + threadIdx.x; k < Mo;
+             k += (int64_t)nblk * blockDim.x) {
             int st;
             uint32_t idx;
             birth_locate(d, k, st, idx, s_old);
@@ -1257,7 +1300,7 @@ __global__ void __launch_bounds__(256) k_birth_place(Dev d, int deferred, int ad
     }
     __threadfence();
     __syncthreads();
-    if (threadIdx.x == 0) s_last = (atomicAdd(d.ticket + 1, 1u) == gridDim.x - 1);
+    if (threadIdx.x == 0) s_last = (atomicAdd(d.ticket + 1, 1u) == (unsigned)(nblk - 1));
     __syncthreads();
     if (!s_last) return;
     __threadfence();
@@ -1288,6 +1331,12 @@ __global__ void __launch_bounds__(256) k_birth_place(Dev d, int deferred, int ad
     }
     __syncthreads();
     if (threadIdx.x == 0 && advance) *d.step += 1;
+}
+
+template <bool F64>
+__global__ void __launch_bounds__(256) k_birth_place(Dev d, int deferred, int advance)
+{
+    birth_place_body<F64>(d, deferred, advance, (int)blockIdx.x, (int)gridDim.x);
 }
 
 // Clear one half (parity -1: the current step's): its bits and counts, then its birth counts.
@@ -1591,14 +1640,20 @@ hipError_t launch_zero_q(const Dev &d, bool f64, hipStream_t s)
     return hipSuccess;
 }
 
-hipError_t launch_solve(const Dev &d, bool f64, int64_t nchunks, bool zero_q, hipStream_t s)
+bool births_fit_solve(const Dev &d) { return d.g_tot <= (int64_t)1 << 18; }
+
+hipError_t launch_solve(const Dev &d, bool f64, int64_t nchunks, bool zero_q, hipStream_t s,
+                        bool with_births)
 {
+    const int nc = (int)nchunks, zq = zero_q ? 1 : 0;
+    const int scan = with_births ? 1 : 0;
+    const dim3 g1(nc + scan), g2(nc + (with_births ? kPlaceBlocks : 0));
     if (f64) {
-        hipLaunchKernelGGL(k_solve1<true>, dim3(nchunks), dim3(kSolveThreads), 0, s, d);
-        hipLaunchKernelGGL(k_solve2<true>, dim3(nchunks), dim3(kSolveThreads), 0, s, d, zero_q ? 1 : 0);
+        hipLaunchKernelGGL(k_solve1<true>, g1, dim3(kSolveThreads), 0, s, d, nc, scan);
+        hipLaunchKernelGGL(k_solve2<true>, g2, dim3(kSolveThreads), 0, s, d, zq, nc);
     } else {
-        hipLaunchKernelGGL(k_solve1<false>, dim3(nchunks), dim3(kSolveThreads), 0, s, d);
-        hipLaunchKernelGGL(k_solve2<false>, dim3(nchunks), dim3(kSolveThreads), 0, s, d, zero_q ? 1 : 0);
+        hipLaunchKernelGGL(k_solve1<false>, g1, dim3(kSolveThreads), 0, s, d, nc, scan);
+        hipLaunchKernelGGL(k_solve2<false>, g2, dim3(kSolveThreads), 0, s, d, zq, nc);
     }
     LAUNCH_CHECK();
     if (d.periodic) {
@@ -1665,9 +1720,9 @@ hipError_t launch_births(const Dev &d, bool f64, bool in_step, bool advance, hip
     }
     const int deferred = in_step ? 1 : 0, adv = advance ? 1 : 0;
     if (f64)
-        hipLaunchKernelGGL(k_birth_place<true>, dim3(64), dim3(256), 0, s, d, deferred, adv);
+        hipLaunchKernelGGL(k_birth_place<true>, dim3(kPlaceBlocks), dim3(256), 0, s, d, deferred, adv);
     else
-        hipLaunchKernelGGL(k_birth_place<false>, dim3(64), dim3(256), 0, s, d, deferred, adv);
+        hipLaunchKernelGGL(k_birth_place<false>, dim3(kPlaceBlocks), dim3(256), 0, s, d, deferred, adv);
     LAUNCH_CHECK();
     if (!in_step) {
         hipLaunchKernelGGL(k_birth_clear, dim3(64), dim3(256), 0, s, d, -1);
