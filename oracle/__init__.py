@@ -43,7 +43,8 @@ class _Config(C.Structure):
                 ("ngs_el", C.c_double), ("ngs_iz", C.c_double), ("ngs_cx", C.c_double),
                 ("eps_iz", C.c_double), ("T_n", C.c_double), ("m_n", C.c_double),
                 ("perturb_amp", C.c_double), ("perturb_mode", C.c_int32),
-                ("floating", C.c_int32), ("smooth", C.c_int32)]
+                ("floating", C.c_int32), ("smooth", C.c_int32), ("recycle", C.c_int32),
+                ("neutral_capacity", C.c_int64), ("src_pairs", C.c_int64), ("src_frac", C.c_double)]
 
 
 class Diag(C.Structure):
@@ -51,7 +52,8 @@ class Diag(C.Structure):
                 ("field_energy", C.c_double), ("wall_count", (C.c_int64 * 2) * 2),
                 ("wall_charge", (C.c_double * 2) * 2), ("wall_ke", (C.c_double * 2) * 2),
                 ("coll", C.c_int64 * 3), ("created", C.c_int64 * 2), ("pushes", C.c_int64),
-                ("step", C.c_int64)]
+                ("step", C.c_int64), ("neutral_count", C.c_int64), ("neutral_wall", C.c_int64 * 2),
+                ("recycled", C.c_int64), ("sourced", C.c_int64)]
 
     def as_dict(self):
         return {
@@ -61,7 +63,9 @@ class Diag(C.Structure):
             "wall_charge": [list(r) for r in self.wall_charge],
             "wall_ke": [list(r) for r in self.wall_ke],
             "coll": list(self.coll), "created": list(self.created), "pushes": self.pushes,
-            "step": self.step,
+            "step": self.step, "neutral_count": self.neutral_count,
+            "neutral_wall": list(self.neutral_wall), "recycled": self.recycled,
+            "sourced": self.sourced,
         }
 
 
@@ -139,6 +143,10 @@ def make_config(e):
     c.perturb_amp, c.perturb_mode = e["perturb_amp"], e["perturb_mode"]
     c.floating = int(e.get("floating", False))
     c.smooth = int(e.get("smooth", 0))
+    c.recycle = int(e.get("recycle", False))
+    c.neutral_capacity = int(e.get("neutral_capacity", 0))
+    c.src_pairs = int(e.get("src_pairs", 0))
+    c.src_frac = float(e.get("src_frac", 0.5))
     return c
 
 
@@ -210,7 +218,7 @@ class Oracle:
             self.set_particles(s, st["x"], st["vx"], st["vy"], st["vz"], st["id"], st["next_id"])
 
     def particles(self, s):
-        cap = self.e["species"][s]["capacity"]
+        cap = self.e["species"][s]["capacity"] if s < 2 else int(self.e.get("neutral_capacity", 0))
         x = np.empty(cap + 1)
         vx, vy, vz = np.empty(cap + 1), np.empty(cap + 1), np.empty(cap + 1)
         ids = np.empty(cap + 1, dtype=np.uint32)

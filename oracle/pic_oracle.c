@@ -40,6 +40,10 @@ struct orc_state {
     uint32_t *last_id[2];
     int64_t last_n[2];
     double numax[2], pnull[2];
+    /* recycled neutrals (R24): absolute x, velocity, id (the id of the ion they came from) */
+    double *nx, *nvx, *nvy, *nvz;
+    uint32_t *nid;
+    int64_t nneu, ncap;
     int err;
 };
 
@@ -181,6 +185,12 @@ orc_state *orc_create(const orc_config *cfg)
     st->rho = (double *)calloc((size_t)st->nnodes + 1, sizeof(double));
     st->phi = (double *)calloc((size_t)st->nnodes + 1, sizeof(double));
     st->E = (double *)calloc((size_t)st->nnodes + 1, sizeof(double));
+    st->ncap = cfg->recycle ? cfg->neutral_capacity : 0;
+    st->nx = (double *)calloc((size_t)st->ncap + 1, sizeof(double));
+    st->nvx = (double *)calloc((size_t)st->ncap + 1, sizeof(double));
+    st->nvy = (double *)calloc((size_t)st->ncap + 1, sizeof(double));
+    st->nvz = (double *)calloc((size_t)st->ncap + 1, sizeof(double));
+    st->nid = (uint32_t *)calloc((size_t)st->ncap + 1, sizeof(uint32_t));
     return st;
 }
 
@@ -200,6 +210,11 @@ void orc_free(orc_state *st)
     free(st->rho);
     free(st->phi);
     free(st->E);
+    free(st->nx);
+    free(st->nvx);
+    free(st->nvy);
+    free(st->nvz);
+    free(st->nid);
     free(st);
 }
 
@@ -264,6 +279,7 @@ void orc_init(orc_state *st)
         recompute_vmax(st, s);
     }
     st->step = 0;
+    st->nneu = 0;
     memset(&st->d, 0, sizeof(st->d));
     orc_deposit(st);
 }
@@ -271,6 +287,16 @@ void orc_init(orc_state *st)
 int orc_set_particles(orc_state *st, int s, int64_t n, const double *x, const double *vx,
                       const double *vy, const double *vz, const uint32_t *id, uint32_t next_id)
 {
+    if (s == 2) {
+        if (n < 0 || n > st->ncap) return -1;
+        memcpy(st->nx, x, (size_t)n * sizeof(double));
+        memcpy(st->nvx, vx, (size_t)n * sizeof(double));
+        memcpy(st->nvy, vy, (size_t)n * sizeof(double));
+        memcpy(st->nvz, vz, (size_t)n * sizeof(double));
+        memcpy(st->nid, id, (size_t)n * sizeof(uint32_t));
+        st->nneu = n;
+        return 0;
+    }
     if (s < 0 || s >= st->cfg.nspecies || n > st->cap[s] || n < 0) return -1;
     memcpy(st->x[s], x, (size_t)n * sizeof(double));
     memcpy(st->vx[s], vx, (size_t)n * sizeof(double));
@@ -286,6 +312,15 @@ int orc_set_particles(orc_state *st, int s, int64_t n, const double *x, const do
 int64_t orc_get_particles(const orc_state *st, int s, double *x, double *vx, double *vy,
                           double *vz, uint32_t *id)
 {
+    if (s == 2) {
+        int64_t m = st->nneu;
+        if (x) memcpy(x, st->nx, (size_t)m * sizeof(double));
+        if (vx) memcpy(vx, st->nvx, (size_t)m * sizeof(double));
+        if (vy) memcpy(vy, st->nvy, (size_t)m * sizeof(double));
+        if (vz) memcpy(vz, st->nvz, (size_t)m * sizeof(double));
+        if (id) memcpy(id, st->nid, (size_t)m * sizeof(uint32_t));
+        return m;
+    }
     int64_t n = st->n[s];
     if (x) memcpy(x, st->x[s], (size_t)n * sizeof(double));
     if (vx) memcpy(vx, st->vx[s], (size_t)n * sizeof(double));
@@ -295,7 +330,7 @@ int64_t orc_get_particles(const orc_state *st, int s, double *x, double *vx, dou
     return n;
 }
 
-uint32_t orc_next_id(const orc_state *st, int s) { return st->next_id[s]; }
+uint32_t orc_next_id(const orc_state *st, int s) { return (s >= 0 && s < 2) ? st->next_id[s] : 0u; }
 int64_t orc_nnodes(const orc_state *st) { return st->nnodes; }
 void orc_set_step(orc_state *st, int64_t step) { st->step = step; }
 
@@ -482,15 +517,51 @@ void orc_push(orc_state *st)
         }
         st->d.pushes += st->n[s];
     }
+    /* recycled neutrals carry no charge: they stream freely */
+    for (int64_t p = 0; p < st->nneu; p++) st->nx[p] += c->dt * st->nvx[p];
+}
+
+/* Reading R24: an ion absorbed at a wall returns from that wall as a D neutral (the
+ * sheath cases recycle D+ ions into D neutrals at the walls), with recycling coefficient
+ * one.  The neutral keeps the ion's id and draws Philox block 0 of key (seed, 2) with the
+ * step tag: u1 gives the inward normal speed from the flux-weighted half-Maxwellian at the
+ * neutral temperature T_n, v_w sqrt(-2 ln u1) with v_w = sqrt(T_n / m_n); (u2, u3) give
+ * the two tangential components (Box-Muller, times v_w); it leaves the wall during the
+ * step, so it starts u4 dt |v_x| inside the wall it came from.                            */
+static void emit_neutral(orc_state *st, uint32_t ion_id, int wall)
+{
+    const orc_config *c = &st->cfg;
+    if (st->nneu >= st->ncap) {
+        st->err = 3;
+        return;
+    }
+    uint32_t w[4];
+    draw_block(st, 2, ion_id, (uint32_t)st->step, 0u, w);
+    double vw = sqrt(c->T_n / c->m_n);
+    double vn = vw * sqrt(-2.0 * log(orc_uniform(w[0])));
+    double vy, vz;
+    orc_boxmuller(orc_uniform(w[1]), orc_uniform(w[2]), &vy, &vz);
+    double depth = orc_uniform(w[3]) * c->dt * vn;
+    int64_t k = st->nneu++;
+    st->nx[k] = wall == 0 ? depth : dlen(st) - depth;
+    st->nvx[k] = wall == 0 ? vn : -vn;
+    st->nvy[k] = vw * vy;
+    st->nvz[k] = vw * vz;
+    st->nid[k] = ion_id;
+    st->d.recycled += 1;
 }
 
 /* Reading R8: bounded walls absorb every particle with x < 0 or x >= L (count, charge and
  * kinetic energy tallied per wall); survivors keep their order.  Periodic: wrap into
- * [0, L).                                                                                  */
+ * [0, L).  Neutrals leave through either wall (counted); then the ions absorbed in this
+ * call return as neutrals (R24).                                                           */
 void orc_walls(orc_state *st)
 {
     const orc_config *c = &st->cfg;
     double L = dlen(st);
+    uint32_t *rec_id = NULL;
+    int *rec_wall = NULL;
+    int64_t nrec = 0, reccap = 0;
     for (int s = 0; s < c->nspecies; s++) {
         const orc_species *sp = &c->sp[s];
         if (c->periodic) {
@@ -511,6 +582,16 @@ void orc_walls(orc_state *st)
                 st->d.wall_count[wall][s] += 1;
                 st->d.wall_charge[wall][s] += sp->q * sp->w;
                 st->d.wall_ke[wall][s] += 0.5 * sp->m * sp->w * v2;
+                if (c->recycle && s == 1) {
+                    if (nrec == reccap) {
+                        reccap = reccap ? 2 * reccap : 1024;
+                        rec_id = (uint32_t *)realloc(rec_id, (size_t)reccap * sizeof(uint32_t));
+                        rec_wall = (int *)realloc(rec_wall, (size_t)reccap * sizeof(int));
+                    }
+                    rec_id[nrec] = st->id[s][p];
+                    rec_wall[nrec] = wall;
+                    nrec++;
+                }
                 continue;
             }
             st->x[s][k] = x;
@@ -522,6 +603,24 @@ void orc_walls(orc_state *st)
         }
         st->n[s] = k;
     }
+    int64_t k = 0;
+    for (int64_t p = 0; p < st->nneu; p++) {
+        double x = st->nx[p];
+        if (x < 0.0 || x >= L) {
+            st->d.neutral_wall[x < 0.0 ? 0 : 1] += 1;
+            continue;
+        }
+        st->nx[k] = x;
+        st->nvx[k] = st->nvx[p];
+        st->nvy[k] = st->nvy[p];
+        st->nvz[k] = st->nvz[p];
+        st->nid[k] = st->nid[p];
+        k++;
+    }
+    st->nneu = k;
+    for (int64_t r = 0; r < nrec; r++) emit_neutral(st, rec_id[r], rec_wall[r]);
+    free(rec_id);
+    free(rec_wall);
 }
 
 /* ------------------------------------------------------------------------------------ */
@@ -541,7 +640,15 @@ void orc_walls(orc_state *st)
  *   (direction R3, R4) and the new electron (direction block 1 words 1-2); the new ion and a
  *   charge-exchanged ion take neutral velocities, three normals of block 2 at T_n.
  * Reading R14: created particles are ordered by parent id and numbered next_id, next_id+1,
- *   ... in that order, then appended after the survivors of each species.                */
+ *   ... in that order, then appended after the survivors of each species.
+ * Reading R25: the volumetric source of the non-uniform sheath case creates src_pairs
+ *   electron-ion pairs per step, uniform over [0, src_frac L): pair k of step n takes its
+ *   position from word 0 of Philox block 4 of key (seed, 0) with counter (k, n), the
+ *   electron three normals of block 5 of key (seed, 0) at T_e and the ion three normals of
+ *   block 5 of key (seed, 1) at T_i.  Both members sit at the same x.  A step's source
+ *   pairs take the ids (and slots) before its ionisation births: next_id + k for pair k,
+ *   the births follow from next_id + src_pairs.  Like births they are pushed from the next
+ *   step on.                                                                              */
 typedef struct {
     uint32_t pid;
     double x;
@@ -648,6 +755,30 @@ void orc_collide(orc_state *st)
             }
         }
     }
+    for (int64_t k = 0; k < c->src_pairs && c->nspecies > 1; k++) {
+        uint32_t w[4], z0w[4], z1w[4];
+        double z[3];
+        draw_block(st, 0, (uint32_t)k, tag, 4u, w);
+        double x = c->src_frac * dlen(st) * orc_uniform(w[0]);
+        draw_block(st, 0, (uint32_t)k, tag, 5u, z0w);
+        draw_block(st, 1, (uint32_t)k, tag, 5u, z1w);
+        for (int s = 0; s < 2; s++) {
+            int64_t j = st->n[s];
+            if (j >= st->cap[s]) {
+                st->err = 3;
+                continue;
+            }
+            double vt = sqrt(c->sp[s].T / c->sp[s].m);
+            three_normals(s == 0 ? z0w : z1w, z);
+            st->x[s][j] = x;
+            st->vx[s][j] = vt * z[0];
+            st->vy[s][j] = vt * z[1];
+            st->vz[s][j] = vt * z[2];
+            st->id[s][j] = st->next_id[s]++;
+            st->n[s] = j + 1;
+        }
+        st->d.sourced += 1;
+    }
     if (nb > 0) {
         qsort(births, (size_t)nb, sizeof(orc_birth), birth_cmp);
         int ns = c->nspecies;
@@ -726,7 +857,7 @@ void orc_step(orc_state *st, int64_t nsteps)
         orc_solve(st);
         orc_push(st);
         orc_walls(st);
-        if (c->collisions) orc_collide(st);
+        if (c->collisions || c->src_pairs > 0) orc_collide(st);
         else
             for (int s = 0; s < c->nspecies; s++) recompute_vmax(st, s);
         orc_deposit(st);
@@ -771,6 +902,7 @@ void orc_get_diag(orc_state *st, orc_diag *out)
     for (int64_t j = 0; j < st->nnodes; j++) fe += st->E[j] * st->E[j] * node_volume(st, j);
     d.field_energy = 0.5 * c->eps0 * fe;
     d.step = st->step;
+    d.neutral_count = st->nneu;
     *out = d;
 }
 

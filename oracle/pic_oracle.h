@@ -51,6 +51,11 @@ typedef struct {
     int32_t perturb_mode;
     int32_t floating;    /* bounded only: 1 = the walls keep the charge they absorb (R22)     */
     int32_t smooth;      /* passes of the 1-2-1 filter on rho before the solve (R23), 0 = off */
+    int32_t recycle;     /* bounded, two species: ions absorbed at a wall return as neutrals
+                            (R24), held in a neutral set of `neutral_capacity` particles      */
+    int64_t neutral_capacity;
+    int64_t src_pairs;   /* electron-ion pairs created per step by the volumetric source (R25) */
+    double src_frac;     /* the source fills [0, src_frac L)                                  */
 } orc_config;
 
 /* Cumulative diagnostics (reset only by orc_create / orc_init). */
@@ -66,6 +71,10 @@ typedef struct {
     int64_t created[2];          /* particles created per species                            */
     int64_t pushes;              /* sum over steps of the particles pushed                   */
     int64_t step;
+    int64_t neutral_count;       /* recycled neutrals alive (R24)                            */
+    int64_t neutral_wall[2];     /* neutrals that left through the left / right wall         */
+    int64_t recycled;            /* neutrals created from absorbed ions                      */
+    int64_t sourced;             /* pairs created by the volumetric source (R25)             */
 } orc_diag;
 
 typedef struct orc_state orc_state;
@@ -83,7 +92,8 @@ void orc_init(orc_state *st);
 void orc_init_particle(const orc_config *cfg, int s, int64_t p, double *x, double *vx, double *vy,
                        double *vz);
 
-/* Inject / read back a species' particles: absolute x, velocity, id. */
+/* Inject / read back a species' particles: absolute x, velocity, id.  Species 2 is the
+ * recycled neutral set (R24; its next_id argument is ignored).                           */
 int orc_set_particles(orc_state *st, int s, int64_t n, const double *x, const double *vx,
                       const double *vy, const double *vz, const uint32_t *id, uint32_t next_id);
 int64_t orc_get_particles(const orc_state *st, int s, double *x, double *vx, double *vy,
@@ -96,7 +106,8 @@ void orc_solve(orc_state *st);                   /* Q -> rho -> phi -> E (Thomas
 void orc_set_fields(orc_state *st, const double *E);  /* replace E (self part)           */
 void orc_push(orc_state *st);                    /* gather + Boris + position update      */
 void orc_walls(orc_state *st);                   /* absorb (bounded) or wrap (periodic)   */
-void orc_collide(orc_state *st);                 /* null-collision MC + creation          */
+void orc_collide(orc_state *st);                 /* null-collision MC, volumetric source
+                                                    pairs (R25) and ionisation births      */
 void orc_sort(orc_state *st);                    /* stable counting sort by cell          */
 void orc_step(orc_state *st, int64_t nsteps);    /* full steps, including the step count  */
 

@@ -46,7 +46,8 @@ def species(q, m, T, ppc, ncells, cap_factor=1.25, extra=0):
 def ensemble(ncells, ppc, *, T_i=1.0 / T_RATIO, B=None, seed=1, periodic=False,
              nspecies=2, collisions=True, sort_every=0, init_mode=0, E_ext=0.0,
              perturb_amp=0.0, perturb_mode=1, T_e=1.0, cap_factor=1.25, extra=0,
-             floating=False, smooth=0):
+             floating=False, smooth=0, recycle=False, neutral_capacity=0, src_pairs=0,
+             src_frac=0.5):
     sp = [species(-1.0, 1.0, T_e, ppc, ncells, cap_factor, extra)]
     if nspecies > 1:
         sp.append(species(+1.0, M_ION, T_i, ppc, ncells, cap_factor, extra))
@@ -61,6 +62,8 @@ def ensemble(ncells, ppc, *, T_i=1.0 / T_RATIO, B=None, seed=1, periodic=False,
         "T_n": float(T_i), "m_n": M_ION,
         "perturb_amp": float(perturb_amp), "perturb_mode": int(perturb_mode),
         "floating": bool(floating), "smooth": int(smooth),
+        "recycle": bool(recycle), "neutral_capacity": int(neutral_capacity),
+        "src_pairs": int(src_pairs), "src_frac": float(src_frac),
     }
 
 
@@ -112,6 +115,31 @@ def c5_large(seed=1, ncells=1_000_000, ppc=500):
             "ensembles": [e]}
 
 
+def c6_sheath_recycling(seed=1, ncells=100_000, ppc=200):
+    """The uniform-load sheath case with its three species: the 1e5-cell, 200 ppc slab
+    with floating walls that keep the absorbed charge and recycle every absorbed ion into a
+    D neutral (electrons, ions, neutrals)."""
+    e = ensemble(ncells, ppc, seed=seed, B=oblique_B(), sort_every=20, floating=True,
+                 recycle=True, neutral_capacity=ppc * ncells // 4)
+    return {"name": f"sheath-recycling-{ncells}cells-{ppc}ppc", "steps": 1000,
+            "precision": "fp32", "ensembles": [e]}
+
+
+def c7_sheath_source(seed=1, ncells=100_000, ref_ppc=200, pairs_per_step=20_000,
+                     capacity=25_000_000):
+    """The non-uniform-load sheath case: an initially empty 1e5-cell slab filled by a
+    volumetric source of electron-ion pairs in its left half, floating recycling walls.
+    Macro-particle weight as for 200 ppc at the reference density."""
+    e = ensemble(ncells, 0, seed=seed, B=oblique_B(), sort_every=20, floating=True,
+                 recycle=True, neutral_capacity=capacity // 4, src_pairs=pairs_per_step,
+                 src_frac=0.5)
+    for sp in e["species"]:
+        sp["w"] = DX / ref_ppc
+        sp["capacity"] = int(capacity)
+    return {"name": f"sheath-source-{ncells}cells", "steps": 1000, "precision": "fp32",
+            "ensembles": [e]}
+
+
 def scaled(work, ncells=None, ppc=None, steps=None):
     """The same physics at a smaller size (cells and/or ppc), for oracle-sized checks."""
     w = copy.deepcopy(work)
@@ -122,6 +150,8 @@ def scaled(work, ncells=None, ppc=None, steps=None):
             sp["ppc"] = int(p)
             sp["w"] = e["dx"] / p
             sp["capacity"] = int(math.ceil(1.25 * p * n)) + 64
+        if e.get("recycle"):
+            e["neutral_capacity"] = int(math.ceil(0.25 * (ppc or e["species"][0]["ppc"]) * n)) + 64
         e["ncells"] = int(n)
     if steps is not None:
         w["steps"] = int(steps)

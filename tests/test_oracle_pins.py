@@ -19,6 +19,7 @@ import scipy.stats
 
 import oracle
 import synth
+from parity_util import by_id
 
 TORCH_INC = None
 try:
@@ -401,6 +402,178 @@ def test_floating_walls_hold_the_missing_charge():
         assert abs(e["eps0"] * g["E"][0] - sig[0]) <= 1e-12 * scale
         assert abs(e["eps0"] * g["E"][-1] + sig[1]) <= 1e-12 * scale
     assert d["wall_count"][0][0] + d["wall_count"][1][0] > 0
+
+
+# ---------------------------------------------------------------------------------------
+# Wall recycling (R24) and the volumetric source (R25)
+# ---------------------------------------------------------------------------------------
+def _recycling_setup(n_ions, N=64, seed=41):
+    e = synth.ensemble(N, 1, collisions=False, recycle=True, neutral_capacity=4 * n_ions)
+    for sp in e["species"]:
+        sp["capacity"] = 4 * n_ions
+    rng = np.random.default_rng(seed)
+    L, dx = N * e["dx"], e["dx"]
+    # ions within a cell of either wall, all moving out of the domain this step
+    side = rng.random(n_ions) < 0.5
+    x = np.where(side, rng.random(n_ions) * 0.5 * dx, L - rng.random(n_ions) * 0.5 * dx)
+    vx = np.where(side, -1.0, 1.0) * (dx / e["dt"])
+    st = [
+        {"x": np.array([0.5 * L]), "vx": np.zeros(1), "vy": np.zeros(1), "vz": np.zeros(1),
+         "id": np.array([0], dtype=np.uint32), "next_id": 1},
+        {"x": x, "vx": vx, "vy": np.zeros(n_ions), "vz": np.zeros(n_ions),
+         "id": rng.permutation(n_ions).astype(np.uint32) + 7, "next_id": n_ions + 7},
+    ]
+    return e, st
+
+
+def test_recycled_neutrals_ids_speeds_and_depths():
+    """Every ion absorbed at a wall returns from that wall as a neutral with its id; the
+    inward normal speed follows the flux-weighted half-Maxwellian (Rayleigh in units of
+    v_w = sqrt(T_n / m_n)), the tangential components are normal, and the start depth is
+    a uniform fraction of dt |v_x|."""
+    n = 20000
+    e, st = _recycling_setup(n)
+    o = oracle.Oracle(e, init=False)
+    o.set_state(st)
+    o.set_fields(np.zeros(o.nnodes))
+    o.push()
+    o.walls()
+    d = o.diag()
+    assert d["wall_count"][0][1] + d["wall_count"][1][1] == n
+    assert d["recycled"] == n and d["neutral_count"] == n
+    nt = o.particles(2)
+    assert np.array_equal(np.sort(nt["id"]), np.sort(st[1]["id"]))
+    vw = math.sqrt(e["T_n"] / e["m_n"])
+    L = e["ncells"] * e["dx"]
+    left = nt["x"] < 0.5 * L
+    # ions absorbed on the left come back from the left, moving right (and vice versa)
+    ion_left = dict(zip(st[1]["id"].tolist(), (st[1]["vx"] < 0).tolist()))
+    assert all(ion_left[i] == bool(l) for i, l in zip(nt["id"].tolist(), left.tolist()))
+    assert np.all(nt["vx"][left] > 0) and np.all(nt["vx"][~left] < 0)
+    sp = np.abs(nt["vx"]) / vw
+    assert scipy.stats.kstest(sp, "rayleigh").pvalue > 1e-3
+    assert scipy.stats.kstest(nt["vy"] / vw, "norm").pvalue > 1e-3
+    assert scipy.stats.kstest(nt["vz"] / vw, "norm").pvalue > 1e-3
+    depth = np.where(left, nt["x"], L - nt["x"]) / (e["dt"] * np.abs(nt["vx"]))
+    assert np.all((depth > 0) & (depth < 1))
+    assert scipy.stats.kstest(depth, "uniform").pvalue > 1e-3
+    assert np.all((nt["x"] >= 0) & (nt["x"] < L))
+
+
+def test_neutrals_stream_freely_and_leave_exactly():
+    """Neutrals feel no field: x(t) = x0 + t v_x, and each leaves through the wall it
+    reaches, counted once."""
+    N = 64
+    e = synth.ensemble(N, 10, collisions=False, recycle=True, neutral_capacity=5000)
+    st = synth.random_state(e, [640, 640], seed=3)
+    o = oracle.Oracle(e, init=False)
+    o.set_state(st)
+    rng = np.random.default_rng(8)
+    L, dt = N * e["dx"], e["dt"]
+    m = 3000
+    x0 = rng.random(m) * L
+    v = rng.standard_normal(m) * 3.0
+    o.set_particles(2, x0, v, rng.standard_normal(m), rng.standard_normal(m),
+                    np.arange(m, dtype=np.uint32), 0)
+    E = synth.random_field(e, seed=4)
+    o.set_fields(E)   # a field acts on the charged species only
+    for k in range(1, 41):
+        o.push()
+        o.walls()
+        xs = x0 + k * dt * v
+        d = o.diag()
+        gone = np.zeros(m, dtype=bool)
+        for kk in range(1, k + 1):
+            xk = x0 + kk * dt * v
+            gone |= (xk < 0) | (xk >= L)
+        assert d["neutral_count"] == m - gone.sum()
+        nt = o.particles(2)
+        ref = dict(zip(np.arange(m)[~gone].tolist(), xs[~gone].tolist()))
+        assert np.max(np.abs(nt["x"] - np.array([ref[i] for i in nt["id"].tolist()]))) < 1e-11
+    exits_left = np.array([((x0[i] + np.arange(1, 41) * dt * v[i]) < 0).any() for i in range(m)])
+    exits_right = np.array([((x0[i] + np.arange(1, 41) * dt * v[i]) >= L).any() for i in range(m)])
+    assert d["neutral_wall"] == [int(exits_left.sum()), int(exits_right.sum())]
+    assert d["recycled"] == d["wall_count"][0][1] + d["wall_count"][1][1]
+
+
+def test_source_pairs_law_and_ids():
+    """The volumetric source creates src_pairs neutral pairs per step, uniform over
+    [0, src_frac L), both members at the same x, velocities Maxwellian at the species
+    temperatures, ids next_id + k; its pairs take their ids before the step's births."""
+    N, S = 200, 6000
+    e = synth.ensemble(N, 0, collisions=False, src_pairs=S, src_frac=0.5)
+    for sp in e["species"]:
+        sp["w"] = e["dx"] / 50
+        sp["capacity"] = 3 * S
+    o = oracle.Oracle(e)
+    o.set_step(5)
+    o.collide()
+    d = o.diag()
+    assert d["sourced"] == S and d["count"] == [S, S]
+    pe, pi = by_id(o.particles(0)), by_id(o.particles(1))
+    assert np.array_equal(pe["id"], np.arange(S)) and np.array_equal(pi["id"], np.arange(S))
+    assert np.array_equal(pe["x"], pi["x"])
+    L = N * e["dx"]
+    assert scipy.stats.kstest(pe["x"] / (0.5 * L), "uniform").pvalue > 1e-3
+    # pair k sits at src_frac L u, u from word 0 of block 4 of key (seed, 0), counter (k, step)
+    for k in (0, 1, 17, S - 1):
+        u = oracle.uniform(oracle.philox([k, 5, 4, 0], [e["seed"], 0])[0])
+        assert pe["x"][k] == 0.5 * L * u
+    for p, sp in ((pe, e["species"][0]), (pi, e["species"][1])):
+        vt = math.sqrt(sp["T"] / sp["m"])
+        for k in ("vx", "vy", "vz"):
+            assert scipy.stats.kstest(p[k] / vt, "norm").pvalue > 1e-3
+    assert d["charge"] == pytest.approx(0.0, abs=1e-9)
+    # a different step tag draws different pairs
+    o2 = oracle.Oracle(e)
+    o2.set_step(6)
+    o2.collide()
+    assert not np.array_equal(by_id(o2.particles(0))["x"], pe["x"])
+    # with ionisation on, the step's births are numbered after its source pairs
+    e3 = dict(e, collisions=True, ngs_iz=5.0, ngs_el=0.0, ngs_cx=0.0)
+    st = synth.random_state(e3, [2000, 2000], seed=2, vscale=[3.0, 0.01])
+    o3 = oracle.Oracle(e3, init=False)
+    o3.set_state(st)
+    o3.set_fields(np.zeros(o3.nnodes))
+    o3.collide()
+    d3 = o3.diag()
+    assert d3["created"][0] > 0 and d3["sourced"] == S
+    ids = np.sort(o3.particles(0)["id"])
+    n0 = st[0]["next_id"]
+    new = ids[ids >= n0]
+    assert np.array_equal(new, np.arange(n0, n0 + S + d3["created"][0]))
+    pe3 = by_id(o3.particles(0))
+    xs = dict(zip(pe3["id"].tolist(), pe3["x"].tolist()))
+    for k in range(S):
+        u = oracle.uniform(oracle.philox([k, 0, 4, 0], [e["seed"], 0])[0])
+        assert xs[n0 + k] == 0.5 * L * u
+
+
+def test_particle_bookkeeping_with_source_recycling_and_collisions():
+    """Over a collisional run with floating recycling walls and the source, every count
+    closes exactly: charged = load + created + sourced - absorbed; neutrals alive + gone =
+    recycled = ions absorbed; plasma plus wall charge stays zero."""
+    N = 96
+    e = synth.ensemble(N, 20, collisions=True, B=synth.oblique_B(), floating=True, recycle=True,
+                       neutral_capacity=20000, src_pairs=40, src_frac=0.5)
+    e["ngs_el"], e["ngs_iz"] = 0.1, 0.2
+    e["species"][1]["m"] = e["m_n"] = 100.0   # light, hot ions reach the walls within the run
+    e["species"][1]["T"] = e["T_n"] = 1.0
+    for sp in e["species"]:
+        sp["capacity"] = 20000
+    o = oracle.Oracle(e)
+    n0 = [sp["ppc"] * N for sp in e["species"]]
+    for _ in range(3):
+        o.step(10)
+        d = o.diag()
+        for s in range(2):
+            absorbed = d["wall_count"][0][s] + d["wall_count"][1][s]
+            assert d["count"][s] == n0[s] + d["created"][s] + d["sourced"] - absorbed
+        assert d["recycled"] == d["wall_count"][0][1] + d["wall_count"][1][1]
+        assert d["neutral_count"] + sum(d["neutral_wall"]) == d["recycled"]
+        wallq = sum(d["wall_charge"][w][s] for w in range(2) for s in range(2))
+        assert abs(d["charge"] + wallq) <= 1e-9
+    assert d["recycled"] > 0 and d["sourced"] == 30 * 40
 
 
 # ---------------------------------------------------------------------------------------
