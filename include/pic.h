@@ -74,6 +74,14 @@ typedef struct {
     double T_n, m_n;                           /* neutral temperature and mass             */
     double perturb_amp;                        /* quiet start displacement amplitude A     */
     int32_t perturb_mode;                      /* quiet start mode number                  */
+    /* The paper's sheath cases (its table of sheath cases): FP32 form and two species only. */
+    int32_t recycle;          /* bounded walls: every absorbed ion returns from its wall as a
+                                 neutral (species index 2 in pic_get/set_particles), reading
+                                 R24; 0 = off                                              */
+    int64_t neutral_capacity; /* neutrals held when recycling                              */
+    int64_t src_pairs;        /* volumetric source: electron-ion pairs created per step
+                                 uniformly over [0, src_frac L) (R25); 0 = off              */
+    double src_frac;          /* in (0, 1]                                                 */
 } pic_ensemble_desc;
 
 typedef struct {
@@ -115,6 +123,10 @@ typedef struct {
     int64_t step;                /* steps taken                                             */
     double numax[2];             /* null-collision frequency bound of the last collide     */
     double emax;                 /* max |E| of the last solved / set field                  */
+    int64_t neutral_count;       /* recycled neutrals alive (R24)                           */
+    int64_t neutral_wall[2];     /* neutrals that left through the left / right wall        */
+    int64_t recycled;            /* neutrals created from absorbed ions (cumulative)        */
+    int64_t sourced;             /* pairs created by the volumetric source (cumulative)     */
 } pic_diag_out;
 
 /* Host-side particle exchange: absolute position x in [0, L), velocity, id. */
@@ -148,12 +160,14 @@ int pic_solve(pic_ctx *ctx, void *stream);
 
 /* Gather E at each particle (linear), Boris push in E + E_ext along x and uniform B,
  * position update, absorbing walls (R8: absorbed slots are marked dead and tallied; the
- * next sort compacts them) or periodic wrap. */
+ * next sort compacts them) or periodic wrap.  With recycling (R24) the neutrals stream
+ * freely, leave through the walls, and the ions absorbed in this push return as neutrals. */
 int pic_push(pic_ctx *ctx, void *stream);
 
 /* Null-collision Monte Carlo (R9-R14): per-particle Philox decision against the bound
  * nu_max, channel choice, scattering kinematics, ionisation births appended with ids
- * next_id + rank of the parent id. */
+ * next_id + rank of the parent id.  The step's volumetric source pairs (R25) are created
+ * here too, numbered before the births. */
 int pic_collide(pic_ctx *ctx, void *stream);
 
 /* Counting sort of each species by cell (histogram, exclusive scan, scatter); drops the
@@ -170,7 +184,8 @@ int pic_step(pic_ctx *ctx, int32_t nsteps, void *stream);
 int pic_diag(pic_ctx *ctx, int32_t ens, pic_diag_out *out, void *stream);
 
 /* Copy the alive particles of (ens, species) to host arrays of length >= `cap`; `count`
- * receives the number written.  Order unspecified (compare by id). */
+ * receives the number written.  Order unspecified (compare by id).  Species 2 is the
+ * recycled neutral set (R24). */
 int pic_get_particles(pic_ctx *ctx, int32_t ens, int32_t species, pic_particles out,
                       int64_t cap, int64_t *count, void *stream);
 
@@ -181,7 +196,8 @@ int pic_get_slots(pic_ctx *ctx, int32_t ens, int32_t species, int64_t first, int
                   pic_particles out, void *stream);
 
 /* Replace the particles of (ens, species) with `count` host particles (x in [0, L));
- * next_id is the id the next created particle of this species receives. */
+ * next_id is the id the next created particle of this species receives (ignored for the
+ * neutral set, species 2, whose ids are those of the ions they came from). */
 int pic_set_particles(pic_ctx *ctx, int32_t ens, int32_t species, pic_particles in,
                       int64_t count, uint32_t next_id, void *stream);
 

@@ -45,7 +45,9 @@ class EnsembleDesc(C.Structure):
                 ("seed", C.c_uint32), ("init_mode", C.c_int32), ("sp", SpeciesDesc * 2),
                 ("ngs_el", C.c_double), ("ngs_iz", C.c_double), ("ngs_cx", C.c_double),
                 ("eps_iz", C.c_double), ("T_n", C.c_double), ("m_n", C.c_double),
-                ("perturb_amp", C.c_double), ("perturb_mode", C.c_int32)]
+                ("perturb_amp", C.c_double), ("perturb_mode", C.c_int32),
+                ("recycle", C.c_int32), ("neutral_capacity", C.c_int64), ("src_pairs", C.c_int64),
+                ("src_frac", C.c_double)]
 
 
 class Config(C.Structure):
@@ -62,7 +64,9 @@ class DiagOut(C.Structure):
                 ("field_energy", C.c_double), ("wall_count", (C.c_int64 * 2) * 2),
                 ("wall_charge", (C.c_double * 2) * 2), ("wall_ke", (C.c_double * 2) * 2),
                 ("coll", C.c_int64 * 3), ("created", C.c_int64 * 2), ("pushes", C.c_int64),
-                ("step", C.c_int64), ("numax", C.c_double * 2), ("emax", C.c_double)]
+                ("step", C.c_int64), ("numax", C.c_double * 2), ("emax", C.c_double),
+                ("neutral_count", C.c_int64), ("neutral_wall", C.c_int64 * 2),
+                ("recycled", C.c_int64), ("sourced", C.c_int64)]
 
     def as_dict(self):
         return {
@@ -73,6 +77,8 @@ class DiagOut(C.Structure):
             "wall_ke": [list(r) for r in self.wall_ke],
             "coll": list(self.coll), "created": list(self.created), "pushes": self.pushes,
             "step": self.step, "numax": list(self.numax), "emax": self.emax,
+            "neutral_count": self.neutral_count, "neutral_wall": list(self.neutral_wall),
+            "recycled": self.recycled, "sourced": self.sourced,
         }
 
 
@@ -147,6 +153,10 @@ def make_config(work, fused=True, precision=None, block=0, grid=0, window=0, ppt
         d.ngs_el, d.ngs_iz, d.ngs_cx = e["ngs_el"], e["ngs_iz"], e["ngs_cx"]
         d.eps_iz, d.T_n, d.m_n = e["eps_iz"], e["T_n"], e["m_n"]
         d.perturb_amp, d.perturb_mode = e["perturb_amp"], e["perturb_mode"]
+        d.recycle = int(e.get("recycle", False))
+        d.neutral_capacity = int(e.get("neutral_capacity", 0))
+        d.src_pairs = int(e.get("src_pairs", 0))
+        d.src_frac = float(e.get("src_frac", 0.5))
     e0 = ens[0]
     prec = precision or work.get("precision", "fp32")
     cfg = Config()
@@ -293,7 +303,10 @@ class Sim:
         return int(self.L.pic_nnodes(self.h, int(ens)))
 
     def particles(self, ens=0, s=0):
-        cap = int(self.work["ensembles"][ens]["species"][s]["capacity"])
+        """Alive particles of species s (2: the recycled neutrals) as host arrays."""
+        e = self.work["ensembles"][ens]
+        cap = int(e["species"][s]["capacity"]) if s < 2 else int(e.get("neutral_capacity", 0))
+        cap = max(cap, 1)
         x, vx, vy, vz = (np.empty(cap) for _ in range(4))
         ids = np.empty(cap, dtype=np.uint32)
         p = Particles(x.ctypes.data_as(C.POINTER(C.c_double)), vx.ctypes.data_as(C.POINTER(C.c_double)),

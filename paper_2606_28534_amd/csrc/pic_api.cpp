@@ -33,6 +33,7 @@ struct Plan {
     int64_t cap_tot = 0, nodes_tot = 0, cells_tot = 0, chunks_tot = 0;
     int64_t birth_stripe_cap = 0, bm_words = 0, g_tot = 0;
     int64_t scanpart = 0;
+    int64_t ncap_tot = 0, rec_cap = 0, src_tot = 0;  // neutrals (R24), source (R25)
     size_t bytes = 0;
 };
 
@@ -69,6 +70,7 @@ int build_plan(const pic_config *cfg, Plan &P, std::string &msg)
     P.f64 = cfg->precision == PIC_FP64_PLAIN;
     const bool periodic = cfg->boundary == PIC_PERIODIC;
     int64_t base = 0, gbase = 0, cbase = 0, chunk0 = 0, bm = 0, grp = 0, ecap = 0;
+    int64_t nbase = 0, src_base = 0, icap = 0;
     for (int e = 0; e < P.nens; ++e) {
         const pic_ensemble_desc &D = cfg->ens[e];
         if (D.ncells < 2 || D.ncells > (int64_t)1 << 30 || !(D.dx > 0) || !(D.dt > 0) || !(D.eps0 > 0)) {
@@ -98,6 +100,29 @@ int build_plan(const pic_config *cfg, Plan &P, std::string &msg)
         E.floating = cfg->boundary == PIC_FLOATING ? 1 : 0;
         E.smooth = cfg->smooth;
         E.nspecies = P.nspecies;
+        // the sheath cases' recycling walls (R24) and volumetric source (R25)
+        if (D.recycle || D.src_pairs) {
+            if (P.f64 || P.nspecies != 2) {
+                msg = "ensemble " + std::to_string(e) + ": recycling and the source need the FP32 form and two species";
+                return PIC_EINVAL;
+            }
+            if (D.recycle && (periodic || D.neutral_capacity < 1 || !(D.m_n > 0))) {
+                msg = "ensemble " + std::to_string(e) + ": recycling needs bounded walls, neutral_capacity >= 1 and m_n > 0";
+                return PIC_EINVAL;
+            }
+            if (D.src_pairs < 0 || D.src_pairs > ((int64_t)1 << 24) || !(D.src_frac > 0.0 && D.src_frac <= 1.0)) {
+                msg = "ensemble " + std::to_string(e) + ": src_pairs must be in [0, 2^24] and src_frac in (0, 1]";
+                return PIC_EINVAL;
+            }
+        }
+        E.recycle = D.recycle ? 1 : 0;
+        E.nbase = nbase;
+        E.ncap = D.recycle ? (D.neutral_capacity + 255) / 256 * 256 : 0;
+        nbase += E.ncap;
+        E.src_pairs = D.src_pairs;
+        E.src_base = src_base;
+        src_base += D.src_pairs;
+        E.src_x = D.src_frac * ((double)D.ncells * D.dx);
         // ids (loaded and born) stay below 2 x electron capacity, rounded to 1024
         int64_t idcap = (2 * D.sp[0].capacity + 2048) / 1024 * 1024;
         idcap = std::min<int64_t>(idcap, ((int64_t)1 << 32) - 1024);
@@ -144,6 +169,9 @@ int build_plan(const pic_config *cfg, Plan &P, std::string &msg)
             S.qm_abs = std::fabs(sp.q / sp.m);
             S.seed = D.seed;
             S.other = (s == 0 && P.nspecies > 1) ? (int32_t)(P.seg.size() + 1) : -1;
+            S.recycle = (s == 1 && D.recycle) ? 1 : 0;
+            S.vth = std::sqrt(sp.T / sp.m);
+            if (s == 1) icap += sp.capacity;
             E.seg[s] = (int32_t)P.seg.size();
             P.seg.push_back(S);
             base += S.cap;
@@ -156,6 +184,10 @@ int build_plan(const pic_config *cfg, Plan &P, std::string &msg)
         chunk0 += E.nchunks;
     }
     P.cap_tot = base;
+    P.ncap_tot = nbase;
+    P.src_tot = src_base;
+    // absorbed ions listed per step: generous against the ions within v dt of a wall
+    P.rec_cap = nbase ? std::max<int64_t>(65536, icap / 256) : 0;
     P.bm_words = bm;
     P.g_tot = (grp + 1 + 4095) / 4096 * 4096;  // room for the total; whole scan tiles
     if (P.cap_tot >= ((int64_t)1 << 32)) {
@@ -245,6 +277,21 @@ size_t carve(const Plan &P, char *base, Dev &d)
     d.cursor = c.take<uint32_t>(P.cells_tot);
     d.segstart = c.take<int64_t>(P.nseg);
     d.scanpart = c.take<uint32_t>(P.scanpart);
+    for (int b = 0; b < 2; ++b) {
+        d.ncell[b] = c.take<int32_t>(P.ncap_tot);
+        d.noff[b] = c.take<float>(P.ncap_tot);
+        d.nvx[b] = c.take<float>(P.ncap_tot);
+        d.nvy[b] = c.take<float>(P.ncap_tot);
+        d.nvz[b] = c.take<float>(P.ncap_tot);
+        d.nid[b] = c.take<uint32_t>(P.ncap_tot);
+    }
+    d.ncap_tot = P.ncap_tot;
+    d.ncur = c.take<int32_t>(1);
+    d.nneu = c.take<unsigned long long>(2 * P.nens);
+    d.recs = c.take<uint2>(P.rec_cap);
+    d.rec_cap = P.rec_cap;
+    d.nrec = c.take<uint32_t>(1);
+    d.src_tot = P.src_tot;
     d.ticket = c.take<uint32_t>(8);
     d.err = c.take<int32_t>(1);
     c.take<double>(2 * kDiagGrid);  // diag scratch (last region)
@@ -322,8 +369,10 @@ hipError_t enqueue_step(pic_ctx *c, hipStream_t s, bool sort_now)
             if ((e = hipEventRecord(c->ev[c->ev_used + 1], s)) != hipSuccess) return e;
             c->ev_used += 2;
         }
+        if (coll && (e = launch_candidates(d, c->L, s, f64, sort_now ? 1 : 0)) != hipSuccess) return e;
+        if ((e = launch_neutrals(d, s)) != hipSuccess) return e;
+        if ((e = launch_source(d, sort_now ? 1 : 0, s)) != hipSuccess) return e;
         if (coll) {
-            if ((e = launch_candidates(d, c->L, s, f64, sort_now ? 1 : 0)) != hipSuccess) return e;
             if ((e = launch_births(d, f64, true, true, s)) != hipSuccess) return e;
         } else if ((e = launch_advance(d, s)) != hipSuccess) {
             return e;
@@ -338,11 +387,13 @@ hipError_t enqueue_step(pic_ctx *c, hipStream_t s, bool sort_now)
         if ((e = hipEventRecord(c->ev[c->ev_used + 1], s)) != hipSuccess) return e;
         c->ev_used += 2;
     }
+    if ((e = launch_neutrals(d, s)) != hipSuccess) return e;
     if (coll) {
         if ((e = launch_particles(d, c->L, s, f64, SB_COLLIDE, 0)) != hipSuccess) return e;
         if ((e = launch_candidates(d, c->L, s, f64, 0)) != hipSuccess) return e;
-        if ((e = launch_births(d, f64, true, false, s)) != hipSuccess) return e;
     }
+    if ((e = launch_source(d, 0, s)) != hipSuccess) return e;
+    if (coll && (e = launch_births(d, f64, true, false, s)) != hipSuccess) return e;
     if ((e = launch_zero_q(d, f64, s)) != hipSuccess) return e;
     if ((e = launch_particles(d, c->L, s, f64, SB_DEPOSIT, 0)) != hipSuccess) return e;
     if ((e = launch_advance(d, s)) != hipSuccess) return e;
@@ -373,6 +424,8 @@ hipError_t enqueue_cycle_merged(pic_ctx *c, hipStream_t s)
         if ((e = launch_solve(d, f64, c->P.chunks_tot, true, s, i > 0)) != hipSuccess) return e;
         if ((e = launch_particles(d, c->L, s, f64, stages, hist)) != hipSuccess) return e;
         if ((e = launch_candidates(d, c->L, s, f64, hist)) != hipSuccess) return e;
+        if ((e = launch_neutrals(d, s)) != hipSuccess) return e;
+        if ((e = launch_source(d, hist, s)) != hipSuccess) return e;
     }
     if ((e = launch_births(d, f64, true, true, s)) != hipSuccess) return e;
     return launch_sort(d, f64, c->L, s);
@@ -525,17 +578,20 @@ int pic_push(pic_ctx *c, void *stream)
 {
     if (!c) return PIC_EINVAL;
     HIPC(c, launch_particles(c->d, c->L, (hipStream_t)stream, c->P.f64, SB_PUSH, 0));
+    HIPC(c, launch_neutrals(c->d, (hipStream_t)stream));
     return PIC_OK;
 }
 
 int pic_collide(pic_ctx *c, void *stream)
 {
     if (!c) return PIC_EINVAL;
-    if (!c->cfg.collisions) return PIC_OK;
     hipStream_t s = (hipStream_t)stream;
-    HIPC(c, launch_particles(c->d, c->L, s, c->P.f64, SB_COLLIDE, 0));
-    HIPC(c, launch_candidates(c->d, c->L, s, c->P.f64, 0));
-    HIPC(c, launch_births(c->d, c->P.f64, false, false, s));
+    if (c->cfg.collisions) {
+        HIPC(c, launch_particles(c->d, c->L, s, c->P.f64, SB_COLLIDE, 0));
+        HIPC(c, launch_candidates(c->d, c->L, s, c->P.f64, 0));
+    }
+    HIPC(c, launch_source(c->d, 0, s));
+    if (c->cfg.collisions) HIPC(c, launch_births(c->d, c->P.f64, false, false, s));
     return PIC_OK;
 }
 
@@ -638,10 +694,23 @@ int pic_diag(pic_ctx *c, int32_t ens, pic_diag_out *out, void *stream)
         if (sp == 0) {
             out->coll[0] = (int64_t)a[C_EL];
             out->coll[1] = (int64_t)a[C_IZ];
+            out->sourced = (int64_t)a[C_SOURCED];
         } else {
             out->coll[2] = (int64_t)a[C_CX];
+            out->recycled = (int64_t)a[C_RECYCLED];
+            out->neutral_wall[0] = (int64_t)a[C_NWALL_L];
+            out->neutral_wall[1] = (int64_t)a[C_NWALL_R];
         }
         out->numax[sp] = numax[sg];
+    }
+    if (E.recycle) {
+        int32_t nc = 0;
+        unsigned long long nn = 0;
+        HIPC(c, hipMemcpyAsync(&nc, c->d.ncur, 4, hipMemcpyDeviceToHost, s));
+        HIPC(c, hipStreamSynchronize(s));
+        HIPC(c, hipMemcpyAsync(&nn, c->d.nneu + (int64_t)nc * c->P.nens + ens, 8, hipMemcpyDeviceToHost, s));
+        HIPC(c, hipStreamSynchronize(s));
+        out->neutral_count = std::min<int64_t>((int64_t)nn, E.ncap);
     }
     out->field_energy = fe;
     out->emax = emax;
@@ -649,9 +718,95 @@ int pic_diag(pic_ctx *c, int32_t ens, pic_diag_out *out, void *stream)
     return check_err(c, s);
 }
 
+namespace {
+// The recycled neutral set of an ensemble (species index 2): current buffer and count.
+int neutral_state(pic_ctx *c, int32_t ens, hipStream_t s, int32_t &b, int64_t &n)
+{
+    unsigned long long nn = 0;
+    HIPC(c, hipMemcpyAsync(&b, c->d.ncur, 4, hipMemcpyDeviceToHost, s));
+    HIPC(c, hipStreamSynchronize(s));
+    HIPC(c, hipMemcpyAsync(&nn, c->d.nneu + (int64_t)b * c->P.nens + ens, 8, hipMemcpyDeviceToHost, s));
+    HIPC(c, hipStreamSynchronize(s));
+    n = std::min<int64_t>((int64_t)nn, c->P.ens[ens].ncap);
+    return PIC_OK;
+}
+
+int get_neutrals(pic_ctx *c, int32_t ens, pic_particles out, int64_t cap, int64_t *count, hipStream_t s)
+{
+    const EnsC &E = c->P.ens[ens];
+    int32_t b = 0;
+    int64_t n = 0;
+    int rc = neutral_state(c, ens, s, b, n);
+    if (rc) return rc;
+    if (n > cap) return fail(c, PIC_EINVAL, "output capacity too small");
+    std::vector<int32_t> cell(n);
+    std::vector<float> off(n), vx(n), vy(n), vz(n);
+    const Dev &d = c->d;
+    if (n) {
+        HIPC(c, hipMemcpy(cell.data(), d.ncell[b] + E.nbase, n * 4, hipMemcpyDeviceToHost));
+        HIPC(c, hipMemcpy(off.data(), d.noff[b] + E.nbase, n * 4, hipMemcpyDeviceToHost));
+        HIPC(c, hipMemcpy(vx.data(), d.nvx[b] + E.nbase, n * 4, hipMemcpyDeviceToHost));
+        HIPC(c, hipMemcpy(vy.data(), d.nvy[b] + E.nbase, n * 4, hipMemcpyDeviceToHost));
+        HIPC(c, hipMemcpy(vz.data(), d.nvz[b] + E.nbase, n * 4, hipMemcpyDeviceToHost));
+        HIPC(c, hipMemcpy(out.id, d.nid[b] + E.nbase, n * 4, hipMemcpyDeviceToHost));
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        out.x[i] = ((double)cell[i] + (double)off[i]) * E.dx;
+        out.vx[i] = vx[i];
+        out.vy[i] = vy[i];
+        out.vz[i] = vz[i];
+    }
+    *count = n;
+    return PIC_OK;
+}
+
+int set_neutrals(pic_ctx *c, int32_t ens, pic_particles in, int64_t count, hipStream_t s)
+{
+    const EnsC &E = c->P.ens[ens];
+    if (count < 0 || count > E.ncap) return fail(c, PIC_EINVAL, "count above the neutral capacity");
+    std::vector<int32_t> cell(count);
+    std::vector<float> off(count), vx(count), vy(count), vz(count);
+    for (int64_t i = 0; i < count; ++i) {
+        if (!(in.x[i] >= 0.0 && in.x[i] < E.L)) return fail(c, PIC_EINVAL, "x outside [0, L)");
+        const double g = in.x[i] / E.dx;
+        const double jf = std::floor(g);
+        int cl = (int)jf;
+        float o = (float)(g - jf);
+        if (o >= 1.0f) {
+            o = 0.0f;
+            cl += 1;
+        }
+        if (cl >= E.ncells) return fail(c, PIC_EINVAL, "x rounds to L");
+        cell[i] = cl;
+        off[i] = o;
+        vx[i] = (float)in.vx[i];
+        vy[i] = (float)in.vy[i];
+        vz[i] = (float)in.vz[i];
+    }
+    int32_t b = 0;
+    int64_t n = 0;
+    int rc = neutral_state(c, ens, s, b, n);
+    if (rc) return rc;
+    const Dev &d = c->d;
+    if (count) {
+        HIPC(c, hipMemcpy(d.ncell[b] + E.nbase, cell.data(), count * 4, hipMemcpyHostToDevice));
+        HIPC(c, hipMemcpy(d.noff[b] + E.nbase, off.data(), count * 4, hipMemcpyHostToDevice));
+        HIPC(c, hipMemcpy(d.nvx[b] + E.nbase, vx.data(), count * 4, hipMemcpyHostToDevice));
+        HIPC(c, hipMemcpy(d.nvy[b] + E.nbase, vy.data(), count * 4, hipMemcpyHostToDevice));
+        HIPC(c, hipMemcpy(d.nvz[b] + E.nbase, vz.data(), count * 4, hipMemcpyHostToDevice));
+        HIPC(c, hipMemcpy(d.nid[b] + E.nbase, in.id, count * 4, hipMemcpyHostToDevice));
+    }
+    const unsigned long long nn = (unsigned long long)count;
+    HIPC(c, hipMemcpy(d.nneu + (int64_t)b * c->P.nens + ens, &nn, 8, hipMemcpyHostToDevice));
+    return PIC_OK;
+}
+}  // namespace
+
 int pic_get_particles(pic_ctx *c, int32_t ens, int32_t species, pic_particles out, int64_t cap,
                       int64_t *count, void *stream)
 {
+    if (c && count && ens >= 0 && ens < c->P.nens && species == 2 && c->P.ens[ens].recycle)
+        return get_neutrals(c, ens, out, cap, count, (hipStream_t)stream);
     if (!c || !count || ens < 0 || ens >= c->P.nens || species < 0 || species >= c->P.nspecies)
         return fail(c, PIC_EINVAL, "bad ensemble/species");
     hipStream_t s = (hipStream_t)stream;
@@ -747,6 +902,8 @@ int pic_get_slots(pic_ctx *c, int32_t ens, int32_t species, int64_t first, int64
 int pic_set_particles(pic_ctx *c, int32_t ens, int32_t species, pic_particles in, int64_t count,
                       uint32_t next_id, void *stream)
 {
+    if (c && ens >= 0 && ens < c->P.nens && species == 2 && c->P.ens[ens].recycle)
+        return set_neutrals(c, ens, in, count, (hipStream_t)stream);
     if (!c || ens < 0 || ens >= c->P.nens || species < 0 || species >= c->P.nspecies || count < 0)
         return fail(c, PIC_EINVAL, "bad ensemble/species/count");
     const int sg = c->P.ens[ens].seg[species];
@@ -1196,15 +1353,16 @@ int pic_autotune(pic_ctx *c, int32_t trial_steps, int32_t *shape, void *stream)
 namespace {
 struct CkptHeader {
     uint64_t magic;
-    int64_t nseg, nens, nodes_tot, cap_tot, f64, step, bytes;
+    int64_t nseg, nens, nodes_tot, cap_tot, f64, step, bytes, ncap_tot;
 };
-constexpr uint64_t kCkptMagic = 0x31544b5043494d50ull;  // "PMICPKT1"
+constexpr uint64_t kCkptMagic = 0x32544b5043494d50ull;  // "PMICPKT2"
 
+// ns: slots in use per segment, then neutrals per ensemble (recycling runs)
 size_t ckpt_bytes(const pic_ctx *c, const std::vector<int64_t> &ns)
 {
     const int64_t per = c->P.f64 ? 36 : 24;
-    size_t b = sizeof(CkptHeader) + (size_t)c->P.nseg * 16;
-    for (int64_t n : ns) b += (size_t)n * per;
+    size_t b = sizeof(CkptHeader) + (size_t)c->P.nseg * 16 + (size_t)c->P.nens * 8;
+    for (size_t i = 0; i < ns.size(); ++i) b += (size_t)ns[i] * (i < (size_t)c->P.nseg ? per : 24);
     b += (size_t)2 * c->P.nodes_tot * 8;
     b += (size_t)kCntStripes * c->P.nseg * 8;
     b += (size_t)kCntStripes * c->P.nseg * (C_NCNT + S_NSUM) * 8;
@@ -1213,11 +1371,19 @@ size_t ckpt_bytes(const pic_ctx *c, const std::vector<int64_t> &ns)
 
 int ckpt_counts(pic_ctx *c, hipStream_t s, std::vector<int64_t> &ns, std::vector<uint32_t> &ids)
 {
-    ns.resize(c->P.nseg);
+    ns.assign(c->P.nseg + c->P.nens, 0);
     ids.resize(c->P.nseg);
-    HIPC(c, hipMemcpyAsync(ns.data(), c->d.n_slots, ns.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPC(c, hipMemcpyAsync(ns.data(), c->d.n_slots, (size_t)c->P.nseg * 8, hipMemcpyDeviceToHost, s));
     HIPC(c, hipMemcpyAsync(ids.data(), c->d.next_id, ids.size() * 4, hipMemcpyDeviceToHost, s));
     HIPC(c, hipStreamSynchronize(s));
+    for (int en = 0; en < c->P.nens; ++en) {
+        if (!c->P.ens[en].recycle) continue;
+        int32_t b = 0;
+        int64_t n = 0;
+        int rc = neutral_state(c, en, s, b, n);
+        if (rc) return rc;
+        ns[c->P.nseg + en] = n;
+    }
     return PIC_OK;
 }
 }  // namespace
@@ -1252,8 +1418,13 @@ int pic_save(pic_ctx *c, void *host_buf, size_t bytes, void *stream)
     HIPC(c, hipMemcpyAsync(&vcur, d.vcur, 4, hipMemcpyDeviceToHost, s));
     HIPC(c, hipStreamSynchronize(s));
     char *o = (char *)host_buf;
+    int32_t ncur = 0;
+    if (c->P.ncap_tot) {
+        HIPC(c, hipMemcpyAsync(&ncur, d.ncur, 4, hipMemcpyDeviceToHost, s));
+        HIPC(c, hipStreamSynchronize(s));
+    }
     CkptHeader h{kCkptMagic, c->P.nseg, c->P.nens, c->P.nodes_tot, c->P.cap_tot, c->P.f64 ? 1 : 0, step,
-                 (int64_t)need};
+                 (int64_t)need, c->P.ncap_tot};
     std::memcpy(o, &h, sizeof(h));
     o += sizeof(h);
     for (int sg = 0; sg < c->P.nseg; ++sg) {
@@ -1261,6 +1432,8 @@ int pic_save(pic_ctx *c, void *host_buf, size_t bytes, void *stream)
         std::memcpy(o, v, 16);
         o += 16;
     }
+    std::memcpy(o, ns.data() + c->P.nseg, (size_t)c->P.nens * 8);
+    o += (size_t)c->P.nens * 8;
     auto d2h = [&](const void *src, size_t n) -> hipError_t {
         hipError_t e = n ? hipMemcpyAsync(o, src, n, hipMemcpyDeviceToHost, s) : hipSuccess;
         o += n;
@@ -1282,6 +1455,15 @@ int pic_save(pic_ctx *c, void *host_buf, size_t bytes, void *stream)
         }
         HIPC(c, d2h(d.id[cur] + base, n * 4));
     }
+    for (int en = 0; en < c->P.nens; ++en) {
+        const int64_t base = c->P.ens[en].nbase, n = ns[c->P.nseg + en];
+        HIPC(c, d2h(d.ncell[ncur] + base, n * 4));
+        HIPC(c, d2h(d.noff[ncur] + base, n * 4));
+        HIPC(c, d2h(d.nvx[ncur] + base, n * 4));
+        HIPC(c, d2h(d.nvy[ncur] + base, n * 4));
+        HIPC(c, d2h(d.nvz[ncur] + base, n * 4));
+        HIPC(c, d2h(d.nid[ncur] + base, n * 4));
+    }
     HIPC(c, d2h(c->P.f64 ? (const void *)d.Qd : (const void *)d.Qi, (size_t)2 * c->P.nodes_tot * 8));
     HIPC(c, d2h(d.vmax2 + (size_t)vcur * kCntStripes * c->P.nseg, (size_t)kCntStripes * c->P.nseg * 8));
     HIPC(c, d2h(d.cnt, (size_t)kCntStripes * c->P.nseg * C_NCNT * 8));
@@ -1297,10 +1479,11 @@ int pic_load(pic_ctx *c, const void *host_buf, size_t bytes, void *stream)
     CkptHeader h;
     std::memcpy(&h, host_buf, sizeof(h));
     if (h.magic != kCkptMagic || h.nseg != c->P.nseg || h.nens != c->P.nens || h.nodes_tot != c->P.nodes_tot ||
-        h.cap_tot != c->P.cap_tot || h.f64 != (c->P.f64 ? 1 : 0) || (size_t)h.bytes > bytes)
+        h.cap_tot != c->P.cap_tot || h.f64 != (c->P.f64 ? 1 : 0) || (size_t)h.bytes > bytes ||
+        h.ncap_tot != c->P.ncap_tot)
         return fail(c, PIC_EINVAL, "checkpoint from a different configuration");
     const char *o = (const char *)host_buf + sizeof(h);
-    std::vector<int64_t> ns(c->P.nseg);
+    std::vector<int64_t> ns(c->P.nseg + c->P.nens);
     std::vector<uint32_t> ids(c->P.nseg);
     for (int sg = 0; sg < c->P.nseg; ++sg) {
         int64_t v[2];
@@ -1310,6 +1493,11 @@ int pic_load(pic_ctx *c, const void *host_buf, size_t bytes, void *stream)
         ns[sg] = v[0];
         ids[sg] = (uint32_t)v[1];
     }
+    std::memcpy(ns.data() + c->P.nseg, o, (size_t)c->P.nens * 8);
+    o += (size_t)c->P.nens * 8;
+    for (int en = 0; en < c->P.nens; ++en)
+        if (ns[c->P.nseg + en] < 0 || ns[c->P.nseg + en] > c->P.ens[en].ncap)
+            return fail(c, PIC_EINVAL, "checkpoint neutral count");
     if (ckpt_bytes(c, ns) != (size_t)h.bytes) return fail(c, PIC_EINVAL, "checkpoint size");
     const Dev &d = c->d;
     HIPC(c, hipStreamSynchronize(s));
@@ -1335,6 +1523,26 @@ int pic_load(pic_ctx *c, const void *host_buf, size_t bytes, void *stream)
             HIPC(c, h2d(d.fvz[0] + base, n * 4));
         }
         HIPC(c, h2d(d.id[0] + base, n * 4));
+    }
+    // neutrals continue from buffer 0, with the other buffer and the absorbed-ion list empty
+    std::vector<unsigned long long> nn(2 * (size_t)c->P.nens, 0ull);
+    for (int en = 0; en < c->P.nens; ++en) {
+        const int64_t base = c->P.ens[en].nbase, n = ns[c->P.nseg + en];
+        nn[en] = (unsigned long long)n;
+        HIPC(c, h2d(d.ncell[0] + base, n * 4));
+        HIPC(c, h2d(d.noff[0] + base, n * 4));
+        HIPC(c, h2d(d.nvx[0] + base, n * 4));
+        HIPC(c, h2d(d.nvy[0] + base, n * 4));
+        HIPC(c, h2d(d.nvz[0] + base, n * 4));
+        HIPC(c, h2d(d.nid[0] + base, n * 4));
+    }
+    HIPC(c, hipMemcpyAsync(d.nneu, nn.data(), nn.size() * 8, hipMemcpyHostToDevice, s));
+    {
+        const int32_t z = 0;
+        const uint32_t zu = 0;
+        HIPC(c, hipMemcpyAsync(d.ncur, &z, 4, hipMemcpyHostToDevice, s));
+        HIPC(c, hipMemcpyAsync(d.nrec, &zu, 4, hipMemcpyHostToDevice, s));
+        HIPC(c, hipStreamSynchronize(s));
     }
     HIPC(c, h2d(c->P.f64 ? (void *)d.Qd : (void *)d.Qi, (size_t)2 * c->P.nodes_tot * 8));
     HIPC(c, h2d(d.vmax2, (size_t)kCntStripes * c->P.nseg * 8));

@@ -38,7 +38,10 @@ constexpr int64_t kSlotAlign = 4096;  // segment slot ranges are multiples of th
 
 // Counter slots per (stripe, segment).
 enum Cnt : int {
-    C_PUSH = 0, C_WALL_L, C_WALL_R, C_EL, C_IZ, C_CX, C_CREATED, C_NCNT
+    C_PUSH = 0, C_WALL_L, C_WALL_R, C_EL, C_IZ, C_CX, C_CREATED,
+    C_RECYCLED, C_NWALL_L, C_NWALL_R,  // ion segment: recycled neutrals (R24)
+    C_SOURCED,                         // electron segment: source pairs (R25)
+    C_NCNT
 };
 enum Sum : int { S_KE_L = 0, S_KE_R, S_NSUM };
 // Per-chunk solve aggregates.
@@ -59,6 +62,8 @@ struct SegC {
     double ngsT, qm_abs;      // n_g sigma_total, |q/m|
     uint32_t seed;
     int32_t other;            // ion segment of this ensemble (electron segments), else -1
+    int32_t recycle;          // ion segment of a recycling ensemble (R24)
+    double vth;               // sqrt(T / m): the source's Maxwellian (R25)
 };
 
 // Constant per ensemble.
@@ -75,6 +80,11 @@ struct EnsC {
     int32_t periodic, nspecies;
     int32_t floating;         // bounded walls keep their absorbed charge (R22)
     int32_t smooth;           // passes of the 1-2-1 density filter (R23)
+    int32_t recycle;          // absorbed ions return as neutrals (R24)
+    int64_t nbase, ncap;      // neutral slots [nbase, nbase + ncap) in each neutral buffer
+    int64_t src_pairs;        // volumetric source pairs per step (R25)
+    int64_t src_base;         // first of this ensemble's pairs in the source launch
+    double src_x;             // the source fills [0, src_x)
 };
 
 struct Birth {
@@ -136,6 +146,18 @@ struct Dev {
     // sort
     uint32_t *cellcnt, *cursor;  // [cells_tot] over all segments (SegC::cbase)
     int64_t *segstart;        // [nseg]
+    // recycled neutrals (R24): two buffers; a step streams buffer *ncur into the other,
+    // appends the neutrals born from the absorbed ions listed by the pass, then flips
+    int32_t *ncell[2];
+    float *noff[2], *nvx[2], *nvy[2], *nvz[2];
+    uint32_t *nid[2];
+    int64_t ncap_tot;
+    int32_t *ncur;            // [1]
+    unsigned long long *nneu; // [2][nens] neutrals per ensemble in each buffer
+    uint2 *recs;              // [rec_cap] absorbed ions of the step: (id, ens << 1 | wall)
+    int64_t rec_cap;
+    uint32_t *nrec;           // [1]
+    int64_t src_tot;          // source pairs per step over all ensembles (R25)
     // scan scratch, tickets, errors
     uint32_t *scanpart;       // [<= 1 << 16]
     uint32_t *ticket;         // [8]

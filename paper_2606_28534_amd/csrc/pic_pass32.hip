@@ -259,6 +259,15 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
                         ++nwr;
                         ker += S.halfmw * v2;
                     }
+                    if (S.recycle) {
+                        // reading R24: list the absorbed ion; it returns as a neutral
+                        const uint32_t pid = COLL ? id[k] : d.id[b][i0 + k];
+                        const uint32_t r = atomicAdd(d.nrec, 1u);
+                        if ((int64_t)r < d.rec_cap)
+                            d.recs[r] = make_uint2(pid, ((uint32_t)S.ens << 1) | (c < 0 ? 0u : 1u));
+                        else
+                            atomicOr(d.err, (int)E_CAP_PART);
+                    }
                 }
                 const int cn = out ? kDead : cell[k] == kDead ? kDead : c;
                 cchg |= (cn != cell[k] ? 1u : 0u) << k;

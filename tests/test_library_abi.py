@@ -76,3 +76,53 @@ def test_null_context_calls_fail_cleanly(lib):
         assert getattr(L, n)(None, None) == P.PIC_EINVAL
     assert L.pic_step(None, 1, None) == P.PIC_EINVAL
     assert L.pic_last_error(None) == b"null context"
+
+
+def _c_layout(tmp_path, struct, fields):
+    """sizeof and offsetof of a struct in include/pic.h, from a C program built with gcc."""
+    src = tmp_path / "layout.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pic.h"', "int main(void) {",
+             f'  printf("%zu\\n", sizeof({struct}));']
+    lines += [f'  printf("%zu\\n", offsetof({struct}, {f}));' for f in fields]
+    lines += ["  return 0;", "}"]
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    import subprocess
+
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    return int(out[0]), [int(v) for v in out[1:]]
+
+
+@pytest.mark.parametrize("struct,cls", [("pic_species_desc", "SpeciesDesc"),
+                                        ("pic_ensemble_desc", "EnsembleDesc"),
+                                        ("pic_config", "Config"), ("pic_diag_out", "DiagOut")])
+def test_binding_structs_match_the_header(lib, tmp_path, struct, cls):
+    P, L = lib
+    ct = getattr(P, cls)
+    names = [f[0] for f in ct._fields_]
+    size, offs = _c_layout(tmp_path, struct, names)
+    assert C.sizeof(ct) == size, (struct, C.sizeof(ct), size)
+    assert [getattr(ct, n).offset for n in names] == offs, struct
+
+
+def test_sheath_case_configs_validated(lib):
+    """Recycling and the source need the FP32 form and two species; recycling needs
+    bounded walls and room for neutrals; the source region is a fraction in (0, 1]."""
+    P, L = lib
+    n = C.c_size_t(0)
+    ok = synth.c7_sheath_source(ncells=2000, capacity=200_000)
+    cfg, keep = P.make_config(ok)
+    assert L.pic_query_workspace(C.byref(cfg), C.byref(n)) == 0
+    cfg, keep = P.make_config(synth.c6_sheath_recycling(ncells=2000, ppc=20))
+    assert L.pic_query_workspace(C.byref(cfg), C.byref(n)) == 0
+    cfg, keep = P.make_config(ok, precision="fp64")
+    assert L.pic_query_workspace(C.byref(cfg), C.byref(n)) == P.PIC_EINVAL
+    for change in ({"src_frac": 0.0}, {"src_frac": 1.5}, {"src_pairs": -1},
+                   {"neutral_capacity": 0}):
+        e = dict(ok["ensembles"][0], **change)
+        cfg, keep = P.make_config(dict(ok, ensembles=[e]))
+        assert L.pic_query_workspace(C.byref(cfg), C.byref(n)) == P.PIC_EINVAL, change
+    e = dict(ok["ensembles"][0], periodic=True, floating=False)
+    cfg, keep = P.make_config(dict(ok, ensembles=[e]))
+    assert L.pic_query_workspace(C.byref(cfg), C.byref(n)) == P.PIC_EINVAL
