@@ -136,6 +136,35 @@ def walls_variant_run(pic, shape, steps, seed, smooth):
             "ms_per_step": (t1 - t0) / steps * 1e3, "boundary": "floating", "smooth": smooth}
 
 
+def sheath_case_run(pic, shape, case, seed, warmup, steps):
+    """The paper's two sheath cases at 1e5 cells: "recycling" is the uniform load with its
+    three species (4.0e7 charged particles, ions recycled into neutrals at floating walls);
+    "source" is the initially empty slab filled by 2e4 electron-ion pairs per step in its
+    left half (measured after `warmup` steps of filling).  Same fused graph and launch
+    shape as the main workload."""
+    import torch
+
+    import synth
+
+    work = synth.c6_sheath_recycling(seed=seed) if case == "recycling" else synth.c7_sheath_source(seed=seed)
+    sim = pic.Sim(work, fused=True, **shape)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    d0 = sim.diag()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    d1 = sim.diag()
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return {"value": (d1["pushes"] - d0["pushes"]) / (t1 - t0), "unit": "particle-pushes/s",
+            "steps": steps, "after_steps": warmup, "ms_per_step": (t1 - t0) / steps * 1e3,
+            "charged_particles": sum(d1["count"]), "neutrals": d1["neutral_count"],
+            "recycled": d1["recycled"], "sourced": d1["sourced"]}
+
+
 def stream_copy_gbs(torch, gib=4.0, reps=10):
     """Device-to-device copy bandwidth of a plain torch copy on the same GPU (read + write
     bytes per second), for context next to the HBM peak."""
@@ -176,6 +205,10 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=40)
     ap.add_argument("--no-stream", action="store_true")
     ap.add_argument("--no-walls-variant", action="store_true")
+    ap.add_argument("--no-sheath-cases", action="store_true")
+    ap.add_argument("--case", choices=["sheath", "recycling", "source"], default="sheath",
+                    help="main workload: the sheath slab (default) or one of the paper's two "
+                         "sheath cases (for profiling them)")
     ap.add_argument("--floating", action="store_true",
                     help="main workload with floating walls (for profiling the variant)")
     ap.add_argument("--smooth", type=int, default=0,
@@ -197,7 +230,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
-    work = synth.c2_sheath(seed=args.seed, ncells=args.ncells, ppc=args.ppc)
+    if args.case == "recycling":
+        work = synth.c6_sheath_recycling(seed=args.seed, ncells=args.ncells, ppc=args.ppc)
+    elif args.case == "source":
+        work = synth.c7_sheath_source(seed=args.seed, ncells=args.ncells)
+    else:
+        work = synth.c2_sheath(seed=args.seed, ncells=args.ncells, ppc=args.ppc)
     e = work["ensembles"][0]
     e["floating"] = bool(args.floating)
     e["smooth"] = int(args.smooth)
@@ -236,7 +274,8 @@ def main():
     bytes_per_launch = (B_ALG_PARTICLE * pass_pushes + B_ALG_CELL * e["ncells"]
                         + B_ALG_NODE * (e["ncells"] + 1))
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = traffic_from_profiles("sheath_1e5", pass_pushes)
+    plain_sheath = args.case == "sheath" and not args.floating and not args.smooth
+    traffic = traffic_from_profiles("sheath_1e5", pass_pushes) if plain_sheath else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_pass32<push|collide|deposit>",
@@ -273,6 +312,10 @@ def main():
     walls = None
     if not args.no_walls_variant:
         walls = walls_variant_run(pic, shape, args.batched_steps, args.seed, 2)
+    cases = None
+    if not args.no_sheath_cases:
+        cases = {"recycling": sheath_case_run(pic, shape, "recycling", args.seed, 20, args.batched_steps),
+                 "source": sheath_case_run(pic, shape, "source", args.seed, 200, args.batched_steps)}
 
     stream = None
     if not args.no_stream:
@@ -294,10 +337,11 @@ def main():
         "ms_per_step": wall / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"sheath slab {e['ncells']} cells x {e['species'][0]['ppc']} ppc x 2 species, "
-                               f"oblique B, 3 collision channels, sort every {e['sort_every']}"
-                               + (", floating walls" if args.floating else "")
-                               + (f", {args.smooth} smoothing passes" if args.smooth else ""),
+        "config": {"workload": (f"sheath slab {e['ncells']} cells x {e['species'][0]['ppc']} ppc x 2 species, "
+                                f"oblique B, 3 collision channels, sort every {e['sort_every']}"
+                                + (", floating walls" if args.floating else "")
+                                + (f", {args.smooth} smoothing passes" if args.smooth else ""))
+                               if args.case == "sheath" else work["name"],
                    "particles": 2 * e["species"][0]["ppc"] * e["ncells"], "seed": args.seed,
                    "form": "FP32 cell+offset, fused pass, HIP graph", "parallelism": "single GPU",
                    "launch_shape": shape},
@@ -306,6 +350,7 @@ def main():
         "plain": plain,
         "batched": batched,
         "floating_walls_smoothed": walls,
+        "sheath_cases": cases,
         "stream_copy": stream,
         "cpu_baseline": cpu,
     }

@@ -79,18 +79,20 @@ __device__ __forceinline__ void neutral_append(const Dev &d, const EnsC &e, int 
 // absorbed into neutrals.  Philox block 0 of key (seed, 2), counter (ion id, step): u1 the
 // inward normal speed v_w sqrt(-2 ln u1) (flux-weighted half-Maxwellian at T_n), (u2, u3)
 // the tangential components by Box-Muller, u4 the fraction of dt |v_x| it has flown.
+// The last block to finish makes the streamed buffer current, empties the other one and
+// clears the absorbed-ion list.
 __global__ void __launch_bounds__(256) k_neutrals(Dev d)
 {
-    __shared__ unsigned long long s_n[3];  // left exits, right exits, recycled
-    if (threadIdx.x < 3) s_n[threadIdx.x] = 0ull;
+    __shared__ unsigned long long s_n[2];  // left and right exits
+    __shared__ bool s_last;
+    if (threadIdx.x < 2) s_n[threadIdx.x] = 0ull;
     __syncthreads();
     const int cur = *d.ncur, nb = 1 - cur;
     const int en = (int)blockIdx.y;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int ion_seg = -1;
-    if (en < d.nens) {
+    if (en < d.nens && d.ens[en].recycle) {
         const EnsC &e = d.ens[en];
-        if (!e.recycle) return;
         ion_seg = e.seg[1];
         const int64_t n = min((int64_t)d.nneu[(int64_t)cur * d.nens + en], e.ncap);
         const float dtdx = (float)(e.dt / e.dx);
@@ -128,7 +130,7 @@ __global__ void __launch_bounds__(256) k_neutrals(Dev d)
         }
         if (wl) atomicAdd(&s_n[0], (unsigned long long)wl);
         if (wr) atomicAdd(&s_n[1], (unsigned long long)wr);
-    } else {
+    } else if (en == d.nens) {
         const int64_t nr = min((int64_t)*d.nrec, d.rec_cap);
         const uint32_t tag = (uint32_t)(*d.step);
         for (int64_t r0 = (int64_t)blockIdx.x * blockDim.x; r0 < nr; r0 += stride) {
@@ -169,7 +171,6 @@ __global__ void __launch_bounds__(256) k_neutrals(Dev d)
             d.nid[nb][i] = rec.x;
             atomicAdd(d.cnt + ((int64_t)stripe_of_block() * d.nseg + e.seg[1]) * C_NCNT + C_RECYCLED, 1ull);
         }
-        return;
     }
     __syncthreads();
     if (threadIdx.x == 0 && ion_seg >= 0) {
@@ -177,18 +178,18 @@ __global__ void __launch_bounds__(256) k_neutrals(Dev d)
         if (s_n[0]) atomicAdd(c + C_NWALL_L, s_n[0]);
         if (s_n[1]) atomicAdd(c + C_NWALL_R, s_n[1]);
     }
-}
-
-// Make the streamed buffer current, empty the other one and the absorbed-ion list.
-__global__ void k_neutral_flip(Dev d)
-{
-    const int cur = *d.ncur;
+    __threadfence();
     __syncthreads();
-    for (int en = threadIdx.x; en < d.nens; en += blockDim.x) d.nneu[(int64_t)cur * d.nens + en] = 0ull;
+    if (threadIdx.x == 0) s_last = (atomicAdd(d.ticket + 5, 1u) == gridDim.x * gridDim.y - 1);
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    for (int e2 = threadIdx.x; e2 < d.nens; e2 += blockDim.x) d.nneu[(int64_t)cur * d.nens + e2] = 0ull;
     __syncthreads();
     if (threadIdx.x == 0) {
-        *d.ncur = 1 - cur;
+        *d.ncur = nb;
         *d.nrec = 0u;
+        d.ticket[5] = 0u;
     }
 }
 
@@ -295,7 +296,6 @@ hipError_t launch_neutrals(const Dev &d, hipStream_t s)
 {
     if (d.ncap_tot == 0) return hipSuccess;
     hipLaunchKernelGGL(k_neutrals, dim3(kNeutralBlocks, d.nens + 1), dim3(256), 0, s, d);
-    hipLaunchKernelGGL(k_neutral_flip, dim3(1), dim3(256), 0, s, d);
     LAUNCH_CHECK();
     return hipSuccess;
 }
