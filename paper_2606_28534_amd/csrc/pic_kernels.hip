@@ -1298,12 +1298,14 @@ __device__ void birth_place_body(const Dev &d, int deferred, int advance, int bi
             birth_unmark(ob, d.ens[B.ens], B.pid);
         }
     }
-    __threadfence();
+    // The last block only updates counters that no block of this launch reads after taking
+    // its ticket (each block's loads have returned before its barrier), and the next kernel
+    // sees every write, so no device-scope fence is needed here; on gfx950 such a fence
+    // writes back the XCD's L2 and costs microseconds per block.
     __syncthreads();
     if (threadIdx.x == 0) s_last = (atomicAdd(d.ticket + 1, 1u) == (unsigned)(nblk - 1));
     __syncthreads();
     if (!s_last) return;
-    __threadfence();
     for (int en = threadIdx.x; en < d.nens; en += blockDim.x) {
         const EnsC &e = d.ens[en];
         const int64_t ngrp = (e.idcap + kGroupIds - 1) / kGroupIds;
@@ -1357,12 +1359,11 @@ __global__ void k_birth_clear(Dev d, int parity)
         const Birth &B = bb.births[(int64_t)st * d.birth_stripe_cap + idx];
         birth_unmark(bb, d.ens[B.ens], B.pid);
     }
-    __threadfence();
+    // as in the placement: the last block only resets the counts (no fence needed)
     __syncthreads();
     if (threadIdx.x == 0) s_last = (atomicAdd(d.ticket + 2, 1u) == gridDim.x - 1);
     __syncthreads();
     if (!s_last) return;
-    __threadfence();
     for (int i = threadIdx.x; i < kStripes; i += blockDim.x) bb.nbirth[i] = 0u;
     if (threadIdx.x == 0) d.ticket[2] = 0u;
 }

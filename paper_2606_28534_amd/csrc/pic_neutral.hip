@@ -19,7 +19,7 @@ namespace pic {
         if (_e != hipSuccess) return _e;   \
     } while (0)
 
-constexpr int kNeutralBlocks = 512;  // blocks per ensemble of the neutral kernel
+constexpr int kNeutralBlocks = 128;  // blocks per ensemble of the neutral kernel (each takes a ticket)
 
 // x in [0, L) (FP64) to the FP32 form's cell and offset, as the host upload converts it; a
 // value that rounds up to L stays in the last cell.
@@ -178,12 +178,13 @@ __global__ void __launch_bounds__(256) k_neutrals(Dev d)
         if (s_n[0]) atomicAdd(c + C_NWALL_L, s_n[0]);
         if (s_n[1]) atomicAdd(c + C_NWALL_R, s_n[1]);
     }
-    __threadfence();
+    // The last block only empties the buffer every block has finished reading and flips;
+    // no block of this launch reads what it writes, so no device-scope fence is needed
+    // (on gfx950 one writes back the XCD's L2 and costs microseconds per block).
     __syncthreads();
     if (threadIdx.x == 0) s_last = (atomicAdd(d.ticket + 5, 1u) == gridDim.x * gridDim.y - 1);
     __syncthreads();
     if (!s_last) return;
-    __threadfence();
     for (int e2 = threadIdx.x; e2 < d.nens; e2 += blockDim.x) d.nneu[(int64_t)cur * d.nens + e2] = 0ull;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -272,12 +273,12 @@ __global__ void __launch_bounds__(256) k_source(Dev d, int hist)
         atomicMax(d.vmax2 + ((int64_t)half * kCntStripes + st) * d.nseg + e.seg[0], dbits(v2e));
         atomicMax(d.vmax2 + ((int64_t)half * kCntStripes + st) * d.nseg + e.seg[1], dbits(v2i));
     }
-    __threadfence();
+    // the last block advances counters every block read before taking its ticket (no fence
+    // needed, as in the neutral kernel)
     __syncthreads();
     if (threadIdx.x == 0) s_last = (atomicAdd(d.ticket + 4, 1u) == gridDim.x - 1);
     __syncthreads();
     if (!s_last) return;
-    __threadfence();
     for (int e2 = threadIdx.x; e2 < d.nens; e2 += blockDim.x) {
         const EnsC &e = d.ens[e2];
         if (e.src_pairs == 0) continue;
