@@ -44,7 +44,8 @@ class _Config(C.Structure):
                 ("eps_iz", C.c_double), ("T_n", C.c_double), ("m_n", C.c_double),
                 ("perturb_amp", C.c_double), ("perturb_mode", C.c_int32),
                 ("floating", C.c_int32), ("smooth", C.c_int32), ("recycle", C.c_int32),
-                ("neutral_capacity", C.c_int64), ("src_pairs", C.c_int64), ("src_frac", C.c_double)]
+                ("neutral_capacity", C.c_int64), ("src_pairs", C.c_int64), ("src_frac", C.c_double),
+                ("cx_relative", C.c_int32)]
 
 
 class Diag(C.Structure):
@@ -147,6 +148,7 @@ def make_config(e):
     c.neutral_capacity = int(e.get("neutral_capacity", 0))
     c.src_pairs = int(e.get("src_pairs", 0))
     c.src_frac = float(e.get("src_frac", 0.5))
+    c.cx_relative = int(e.get("cx_relative", False))
     return c
 
 

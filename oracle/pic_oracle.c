@@ -22,6 +22,10 @@
 #define ORC_TWO_PI 6.283185307179586476925286766559
 /* Inflation of the null-collision frequency bound (reading R11). */
 #define ORC_NU_SAFETY (1.0 + 1.0 / 65536.0)
+/* Reading R26: a Box-Muller radius is at most sqrt(-2 ln 2^-24) (the smallest uniform is
+ * 2^-24), and a neutral velocity's first two normals share one radius, so
+ * |v_n| <= sqrt(2) sqrt(48 ln 2) v_tn = sqrt(96 ln 2) v_tn.                               */
+#define ORC_VN_BOUND (sqrt(96.0 * log(2.0)))
 #define ORC_INIT_TAG 0xFFFFFFFFu
 
 struct orc_state {
@@ -673,6 +677,7 @@ void orc_collide(orc_state *st)
         double ngsT = (s == 0) ? c->ngs_el + c->ngs_iz : c->ngs_cx;
         double qm = fabs(sp->q / sp->m);
         double Vb = st->vmax[s] + qm * c->dt * (st->Emax + fabs(c->E_ext));
+        if (s == 1 && c->cx_relative) Vb += ORC_VN_BOUND * sqrt(c->T_n / c->m_n);
         double numax = ngsT * Vb * ORC_NU_SAFETY;
         double pnull = 1.0 - exp(-numax * c->dt);
         st->numax[s] = numax;
@@ -701,6 +706,16 @@ void orc_collide(orc_state *st)
                     chan = 0;
                 else if (thr < nu_el + nu_iz)
                     chan = 1;
+            } else if (c->cx_relative) {
+                /* R26: the target neutral is drawn first (block 2) and the rate uses the
+                 * relative speed; a charge exchange hands the ion that neutral's velocity */
+                uint32_t w2[4];
+                double z[3];
+                draw_block(st, s, pid, tag, 2u, w2);
+                three_normals(w2, z);
+                double gx = vx - vn * z[0], gy = vy - vn * z[1], gz = vz - vn * z[2];
+                double g = sqrt(gx * gx + gy * gy + gz * gz);
+                if (thr < c->ngs_cx * g) chan = 2;
             } else {
                 if (thr < c->ngs_cx * spd) chan = 2;
             }

@@ -56,6 +56,7 @@ typedef struct {
     int64_t neutral_capacity;
     int64_t src_pairs;   /* electron-ion pairs created per step by the volumetric source (R25) */
     double src_frac;     /* the source fills [0, src_frac L)                                  */
+    int32_t cx_relative; /* ion CX rate from the speed relative to a sampled neutral (R26)    */
 } orc_config;
 
 /* Cumulative diagnostics (reset only by orc_create / orc_init). */

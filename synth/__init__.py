@@ -47,7 +47,7 @@ def ensemble(ncells, ppc, *, T_i=1.0 / T_RATIO, B=None, seed=1, periodic=False,
              nspecies=2, collisions=True, sort_every=0, init_mode=0, E_ext=0.0,
              perturb_amp=0.0, perturb_mode=1, T_e=1.0, cap_factor=1.25, extra=0,
              floating=False, smooth=0, recycle=False, neutral_capacity=0, src_pairs=0,
-             src_frac=0.5):
+             src_frac=0.5, cx_relative=False):
     sp = [species(-1.0, 1.0, T_e, ppc, ncells, cap_factor, extra)]
     if nspecies > 1:
         sp.append(species(+1.0, M_ION, T_i, ppc, ncells, cap_factor, extra))
@@ -64,6 +64,7 @@ def ensemble(ncells, ppc, *, T_i=1.0 / T_RATIO, B=None, seed=1, periodic=False,
         "floating": bool(floating), "smooth": int(smooth),
         "recycle": bool(recycle), "neutral_capacity": int(neutral_capacity),
         "src_pairs": int(src_pairs), "src_frac": float(src_frac),
+        "cx_relative": bool(cx_relative),
     }
 
 

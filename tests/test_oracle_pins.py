@@ -739,6 +739,47 @@ def test_null_collision_counts_match_probabilities():
             assert abs(mu - (r * e["dt"]).sum()) <= 0.5 * mu
 
 
+@pytest.mark.parametrize("a", [0.0, 0.7, 3.0])
+def test_relative_speed_cx_rate_and_partner_law(a):
+    """Reading R26: ions moving at a v_tn along x charge-exchange at the expected rate of the
+    speed relative to a Maxwellian neutral, E|u - v| = v_tn [sqrt(2/pi) e^(-a^2/2) +
+    (a + 1/a) erf(a / sqrt 2)] (and sqrt(8/pi) v_tn at rest, where the lab-frame rate would
+    give none); for ions at rest the chosen partners' speeds follow the rate-weighted law
+    chi with 4 degrees of freedom (chi with 3 for an unweighted draw)."""
+    n = 200_000
+    e = synth.ensemble(32, 1, collisions=True, cx_relative=True)
+    e["ngs_el"], e["ngs_iz"], e["ngs_cx"] = 0.0, 0.0, 30.0
+    for sp in e["species"]:
+        sp["capacity"] = 2 * n
+    vt = math.sqrt(e["T_n"] / e["m_n"])
+    rng = np.random.default_rng(12)
+    L = 32 * e["dx"]
+    st = [{"x": rng.random(4) * L, "vx": np.zeros(4), "vy": np.zeros(4), "vz": np.zeros(4),
+           "id": np.arange(4, dtype=np.uint32), "next_id": 4},
+          {"x": rng.random(n) * L, "vx": np.full(n, a * vt), "vy": np.zeros(n), "vz": np.zeros(n),
+           "id": np.arange(n, dtype=np.uint32), "next_id": n}]
+    o = oracle.Oracle(e, init=False)
+    o.set_state(st)
+    o.set_fields(np.zeros(o.nnodes))
+    o.collide()
+    nu, pn = o.last_numax()
+    chan, ids = o.last_channels(1)
+    if a == 0.0:
+        mean_g = math.sqrt(8 / math.pi) * vt
+    else:
+        mean_g = vt * (math.sqrt(2 / math.pi) * math.exp(-a * a / 2)
+                       + (a + 1 / a) * math.erf(a / math.sqrt(2)))
+    p = pn[1] * e["ngs_cx"] * mean_g / nu[1]
+    got = np.count_nonzero(chan == 2)
+    assert abs(got - n * p) <= 4 * math.sqrt(n * p * (1 - p)) + 1, (got, n * p)
+    if a == 0.0:
+        pi = by_id(o.particles(1))
+        hit = np.isin(pi["id"], ids[chan == 2])
+        sp = np.sqrt(pi["vx"][hit] ** 2 + pi["vy"][hit] ** 2 + pi["vz"][hit] ** 2) / vt
+        assert scipy.stats.kstest(sp, scipy.stats.chi(4).cdf).pvalue > 1e-3
+        assert scipy.stats.kstest(sp, scipy.stats.chi(3).cdf).pvalue < 1e-6
+
+
 def test_collision_kinematics_identities_and_creation():
     n = 100_000
     e, st, o = _collision_setup(n, (0.2, 0.3, 40.0), seed=33)
