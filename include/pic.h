@@ -82,6 +82,9 @@ typedef struct {
     int64_t src_pairs;        /* volumetric source: electron-ion pairs created per step
                                  uniformly over [0, src_frac L) (R25); 0 = off              */
     double src_frac;          /* in (0, 1]                                                 */
+    int32_t cx_relative;      /* ion charge exchange at the speed relative to a neutral drawn
+                                 from the background Maxwellian (R26), which then becomes the
+                                 ion's velocity; 0 = the lab-frame ion speed (R10)          */
 } pic_ensemble_desc;
 
 typedef struct {

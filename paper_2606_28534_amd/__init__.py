@@ -47,7 +47,7 @@ class EnsembleDesc(C.Structure):
                 ("eps_iz", C.c_double), ("T_n", C.c_double), ("m_n", C.c_double),
                 ("perturb_amp", C.c_double), ("perturb_mode", C.c_int32),
                 ("recycle", C.c_int32), ("neutral_capacity", C.c_int64), ("src_pairs", C.c_int64),
-                ("src_frac", C.c_double)]
+                ("src_frac", C.c_double), ("cx_relative", C.c_int32)]
 
 
 class Config(C.Structure):
@@ -157,6 +157,7 @@ def make_config(work, fused=True, precision=None, block=0, grid=0, window=0, ppt
         d.neutral_capacity = int(e.get("neutral_capacity", 0))
         d.src_pairs = int(e.get("src_pairs", 0))
         d.src_frac = float(e.get("src_frac", 0.5))
+        d.cx_relative = int(e.get("cx_relative", False))
     e0 = ens[0]
     prec = precision or work.get("precision", "fp32")
     cfg = Config()

@@ -93,6 +93,10 @@ int build_plan(const pic_config *cfg, Plan &P, std::string &msg)
         E.ngs_cx = D.ngs_cx;
         E.eps_iz = D.eps_iz;
         E.vn = (D.m_n > 0) ? std::sqrt(D.T_n / D.m_n) : 0.0;
+        // reading R26: a Box-Muller radius is at most sqrt(48 ln 2) (uniforms >= 2^-24) and two
+        // of a neutral's three normals share one radius: |v_n| <= sqrt(96 ln 2) v_tn
+        E.cx_rel = D.cx_relative ? 1 : 0;
+        E.vn_max = D.cx_relative ? std::sqrt(96.0 * std::log(2.0)) * E.vn : 0.0;
         E.m_e = D.sp[0].m;
         E.m_n = D.m_n;
         E.seed = D.seed;

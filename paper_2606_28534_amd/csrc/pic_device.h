@@ -85,6 +85,8 @@ struct EnsC {
     int64_t src_pairs;        // volumetric source pairs per step (R25)
     int64_t src_base;         // first of this ensemble's pairs in the source launch
     double src_x;             // the source fills [0, src_x)
+    int32_t cx_rel;           // CX at the speed relative to a sampled neutral (R26)
+    double vn_max;            // bound on a sampled neutral's speed when cx_rel, else 0
 };
 
 struct Birth {
@@ -275,7 +277,9 @@ __device__ __forceinline__ void seg_params(const Dev &d, int sg, double &numax, 
         m2 = fmax(m2, __longlong_as_double((long long)d.vmax2[((int64_t)half * kCntStripes + st) * d.nseg + sg]));
     m2 = wave_max_f64(m2);
     const double vmax = __dsqrt_rn(m2);
-    const double Vb = __dadd_rn(vmax, __dmul_rn(__dmul_rn(S.qm_abs, e.dt), __dadd_rn(d.emax[S.ens], fabs(e.E_ext))));
+    double Vb = __dadd_rn(vmax, __dmul_rn(__dmul_rn(S.qm_abs, e.dt), __dadd_rn(d.emax[S.ens], fabs(e.E_ext))));
+    // reading R26: the relative speed to a sampled neutral exceeds the ion's by at most vn_max
+    if (S.species == 1) Vb = __dadd_rn(Vb, e.vn_max);
     numax = __dmul_rn(__dmul_rn(S.ngsT, Vb), kNuSafety);
     pnull = 1.0 - exp(-__dmul_rn(numax, e.dt));
 }

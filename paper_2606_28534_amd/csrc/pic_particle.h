@@ -230,6 +230,21 @@ __device__ __forceinline__ int p_collide(const EnsC &e, const SegC &S, int s, do
             chan = 0;
         else if (thr < __dadd_rn(nu_el, nu_iz))
             chan = 1;
+    } else if (e.cx_rel) {
+        // reading R26: the target neutral (block 2) is drawn first; the rate takes the
+        // relative speed, and a charge exchange hands the ion the neutral's velocity
+        double zn[3];
+        three_normals<double>(draw(S.seed, s, p.id, tag, 2u), zn);
+        const double gx = __dsub_rn((double)p.vx, __dmul_rn(e.vn, zn[0]));
+        const double gy = __dsub_rn((double)p.vy, __dmul_rn(e.vn, zn[1]));
+        const double gz = __dsub_rn((double)p.vz, __dmul_rn(e.vn, zn[2]));
+        if (thr < __dmul_rn(e.ngs_cx, __dsqrt_rn(speed2_rn(gx, gy, gz)))) {
+            p.vx = (T)(e.vn * zn[0]);
+            p.vy = (T)(e.vn * zn[1]);
+            p.vz = (T)(e.vn * zn[2]);
+            return 2;
+        }
+        return -1;
     } else {
         if (thr < __dmul_rn(e.ngs_cx, spd)) chan = 2;
     }

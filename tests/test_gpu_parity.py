@@ -215,6 +215,46 @@ def test_collide_from_injected_state(pic, prec):
 
 
 @pytest.mark.parametrize("prec", PRECISIONS)
+def test_collide_relative_speed_cx_from_injected_state(pic, prec):
+    """Reading R26 (ion charge exchange at the speed relative to a sampled neutral): the
+    bound, the decisions and the post-exchange ion velocities against the oracle."""
+    N = 64
+    e = ens_small(ncells=N, ppc=1)
+    e["cx_relative"] = True
+    e["ngs_el"], e["ngs_iz"], e["ngs_cx"] = 0.2, 0.3, 40.0
+    n = 60000
+    for sp in e["species"]:
+        sp["capacity"] = 3 * n
+    st = synth.random_state(e, [n, n], seed=29, vscale=[1.5, 3e-3])
+    sim = pic.Sim(work_of(e, prec), fused=False)
+    sim.set_state(st)
+    sim.set_fields(np.zeros(sim.nnodes()))
+    sim.set_step(9)
+    o = oracle.Oracle(e, init=False)
+    o.set_state(st)
+    o.set_fields(np.zeros(o.nnodes))
+    o.set_step(9)
+    sim.collide()
+    o.collide()
+    gd, od = sim.diag(), o.diag()
+    nu_o, _ = o.last_numax()
+    assert np.allclose(gd["numax"], nu_o, rtol=1e-15, atol=0)
+    assert od["coll"][2] > 1000
+    # the relative speed goes through the device's log / sincos: a decision within an ulp
+    # of its threshold may flip
+    assert abs(gd["coll"][2] - od["coll"][2]) <= 2
+    assert gd["coll"][:2] == od["coll"][:2]
+    excl = None
+    if gd["coll"][2] != od["coll"][2]:
+        # leave out the ions whose decision flipped and compare the rest
+        gi, oi = by_id(sim.particles(0, 1)), by_id(o.particles(1))
+        excl = gi["id"][np.abs(gi["vx"] - oi["vx"]) > 1e-3 * np.abs(oi["vx"]).max()]
+    for s in range(2):
+        compare_particles(sim.particles(0, s), o.particles(s), e["dx"], prec == "fp64",
+                          vtol=(1e-12 if prec == "fp64" else 1e-5), exclude=excl if s == 1 else None)
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
 def test_sort_groups_by_cell(pic, prec):
     N = 1000
     e = ens_small(ncells=N, ppc=5, capacity=20000)
