@@ -367,8 +367,10 @@ hipError_t enqueue_step(pic_ctx *c, hipStream_t s, bool sort_now)
     if (c->cfg.fused) {
         if ((e = launch_solve(d, f64, c->P.chunks_tot, true, s)) != hipSuccess) return e;
         const int stages = coll ? (SB_PUSH | SB_COLLIDE | SB_DEPOSIT) : (SB_PUSH | SB_DEPOSIT);
+        // the measurement hook times the particle pass alone: the bound kernel goes first
+        if (coll && (e = launch_params(d, s)) != hipSuccess) return e;
         if (tm && (e = hipEventRecord(c->ev[c->ev_used], s)) != hipSuccess) return e;
-        if ((e = launch_particles(d, c->L, s, f64, stages, sort_now ? 1 : 0)) != hipSuccess) return e;
+        if ((e = launch_particles(d, c->L, s, f64, stages, sort_now ? 1 : 0, false)) != hipSuccess) return e;
         if (tm) {
             if ((e = hipEventRecord(c->ev[c->ev_used + 1], s)) != hipSuccess) return e;
             c->ev_used += 2;

@@ -19,7 +19,10 @@ struct Launch {
 
 enum StageBits : int { SB_PUSH = 1, SB_COLLIDE = 2, SB_DEPOSIT = 4, SB_HIST = 8 };
 
-hipError_t launch_particles(const Dev &d, const Launch &L, hipStream_t s, bool f64, int stages, int hist);
+// With the COLLIDE stage the null-collision bound kernel runs first unless `with_params`
+// is false (the caller launched it).
+hipError_t launch_particles(const Dev &d, const Launch &L, hipStream_t s, bool f64, int stages, int hist,
+                            bool with_params = true);
 hipError_t launch_field_energy(const Dev &d, hipStream_t s);
 // After a pass with the COLLIDE stage: the FP32 form's candidate kernel (no-op for FP64,
 // whose pass scatters in place).

@@ -1575,10 +1575,11 @@ static hipError_t launch_particles_t(const Dev &d, const Launch &L, hipStream_t 
     return hipSuccess;
 }
 
-hipError_t launch_particles(const Dev &d, const Launch &L, hipStream_t s, bool f64, int stages, int hist)
+hipError_t launch_particles(const Dev &d, const Launch &L, hipStream_t s, bool f64, int stages, int hist,
+                            bool with_params)
 {
     // the null-collision bound of every segment from this step's speed and field maxima
-    if (stages & SB_COLLIDE) {
+    if ((stages & SB_COLLIDE) && with_params) {
         hipLaunchKernelGGL(k_params, dim3(1), dim3(256), 0, s, d);
         LAUNCH_CHECK();
     }
