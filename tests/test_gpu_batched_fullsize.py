@@ -166,3 +166,26 @@ def test_large_share_properties(pic):
     sim.close()
     del sim
     torch.cuda.empty_cache()
+
+
+def test_large_share_one_percent_slice_matches_oracle(pic):
+    """A 1% slice of the 1e9-particle workload at its own density (1e4 cells x 500 ppc x 2
+    species, sort every 10): three fused steps against the oracle's."""
+    work = synth.c5_large(seed=1, ncells=10_000, ppc=500)
+    e = work["ensembles"][0]
+    sim = pic.Sim(work, fused=True)
+    o = oracle.Oracle(e)
+    sim.step(3)
+    o.step(3)
+    gd, od = sim.diag(), o.diag()
+    assert gd["wall_count"] == od["wall_count"]
+    assert gd["pushes"] == od["pushes"]
+    for s in range(2):
+        # FP32 velocities can flip a collision decision that sits within rounding of its
+        # threshold; each flip can change a count by one
+        assert abs(gd["count"][s] - od["count"][s]) <= 5, (s, gd["count"], od["count"])
+        assert abs(gd["ke"][s] - od["ke"][s]) <= 1e-4 * abs(od["ke"][s])
+    for k in range(3):
+        assert abs(gd["coll"][k] - od["coll"][k]) <= 5, (k, gd["coll"], od["coll"])
+    g, r = sim.grid(), o.grid()
+    assert rel(g["E"], r["E"]) <= 1e-5

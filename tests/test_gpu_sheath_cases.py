@@ -237,3 +237,33 @@ def test_sheath_cases_bookkeeping_at_full_size(pic, case):
            for wl in range(2)]
     assert abs(g["E"][0] - sig[0]) <= 1e-9 * scale
     assert abs(g["E"][-1] + sig[1]) <= 1e-9 * scale
+
+
+def test_batched_mixed_sheath_features(pic):
+    """Four ensembles in one run, with recycling and the source switched on in different
+    combinations (and different sizes): each one against its own oracle over 20 fused
+    steps, so per-ensemble neutral sets, source ranges and counters stay apart."""
+    ens = []
+    for k, (rec, src, n) in enumerate(((True, 200, 700), (False, 0, 900), (False, 150, 500), (True, 0, 1100))):
+        e = synth.ensemble(n, 20, collisions=False, B=synth.oblique_B(), sort_every=20, floating=True,
+                           recycle=rec, neutral_capacity=30000 if rec else 0, src_pairs=src,
+                           src_frac=0.5, seed=31 + k)
+        light_ions(e)
+        for sp in e["species"]:
+            sp["capacity"] = 80000
+        ens.append(e)
+    work = {"name": "mixed", "steps": 20, "precision": "fp32", "ensembles": ens}
+    sim = pic.Sim(work, fused=True)
+    sim.step(20)
+    for k, e in enumerate(ens):
+        o = oracle.Oracle(e)
+        o.step(20)
+        gd, od = sim.diag(k), o.diag()
+        for key in ("count", "wall_count", "sourced", "recycled", "neutral_count", "neutral_wall"):
+            assert gd[key] == od[key], (k, key, gd[key], od[key])
+        for s in range(2):
+            compare_particles(sim.particles(k, s), o.particles(s), e["dx"], False, vtol=1e-4, xtol=1e-4)
+        if e["recycle"]:
+            G, O = by_id(sim.particles(k, 2)), by_id(o.particles(2))
+            assert np.array_equal(G["id"], O["id"])
+        assert rel(sim.grid(k)["E"], o.grid()["E"]) <= 1e-4
