@@ -896,3 +896,25 @@ def test_sort_does_not_change_physics():
             assert np.allclose(pa[k][ia], pb[k][ib], rtol=1e-9, atol=1e-12)
     assert np.allclose(a.grid()["E"], b.grid()["E"], rtol=1e-9, atol=1e-12)
     assert a.error == 0
+
+
+# ---------------------------------------------------------------------------------------
+# The workload recipes against the sizes the paper states for its sheath cases
+# ---------------------------------------------------------------------------------------
+def test_sheath_case_recipes_match_the_papers_sizes():
+    """tests/golden/sheath_cases.json holds the sizes the paper's table of sheath cases
+    states.  The synthetic recipes at those cell counts give its particle count (3M cells x
+    200 ppc x 2 charged species = 1.2e9), three species when recycling, and an empty slab
+    filled over its left half for the non-uniform case."""
+    import json
+
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "sheath_cases.json")))
+    u = g["uniform_load"]
+    e = synth.c6_sheath_recycling(ncells=u["cells"], ppc=u["initial_ppc_per_charged_species"])["ensembles"][0]
+    n = sum(sp["ppc"] * e["ncells"] for sp in e["species"])
+    assert n == pytest.approx(u["initial_particles_approx"], rel=1e-9)
+    assert len(e["species"]) + (1 if e["recycle"] else 0) == u["species"]
+    nu = g["non_uniform_load"]
+    e2 = synth.c7_sheath_source(ncells=nu["cells"])["ensembles"][0]
+    assert all(sp["ppc"] == 0 for sp in e2["species"]) == nu["initially_empty"]
+    assert e2["src_frac"] == 0.5 and e2["src_pairs"] > 0
