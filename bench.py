@@ -281,7 +281,12 @@ def main():
                 "kernel": "k_pass32<push|collide|deposit>",
                 "avg_launch_ms": round(avg_ms, 5), "bytes_alg_per_launch": bytes_per_launch,
                 "launches_timed": launches}
-    step_bytes = (B_ALG_PARTICLE + 48.0 / e["sort_every"]) * (pushes / args.steps)
+    # algorithmic bytes of a whole step: 44 B per push, the sort's 48 B per particle every K
+    # steps, 40 B per node for the grid (Q written and read, E written and read) and 24 B per
+    # created particle
+    created = sum(d1["created"]) - sum(d0["created"])
+    step_bytes = ((B_ALG_PARTICLE + 48.0 / e["sort_every"]) * (pushes / args.steps)
+                  + 40.0 * (e["ncells"] + 1) + 24.0 * created / args.steps)
     whole_step = {"bytes_alg_per_step": step_bytes,
                   "frac_of_hbm_peak": round(step_bytes / (wall / args.steps) / 1e9 / HBM_PEAK_GBS, 4)}
     del sim

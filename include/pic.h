@@ -103,7 +103,8 @@ typedef struct {
     int32_t ppt;         /* particles per thread of the FP32 pass (4 or 8); 0 = default    */
     int32_t sort_ppt;    /* particles per thread of the FP32 sort scatter; 0 = default     */
     int32_t nontemporal; /* bit 0: the fused FP32 pass streams particles with non-temporal
-                          * loads and stores; bit 1: so does the FP32 sort scatter;
+                          * loads and stores; bit 1: the FP32 sort scatter reads its input
+                          * with non-temporal loads;
                           * 0 = ordinary cached accesses (default)                         */
     int32_t smooth;      /* passes (0..4) of the 1-2-1 density filter applied to rho before
                           * every solve (R23): periodic grids wrap, bounded grids mirror at

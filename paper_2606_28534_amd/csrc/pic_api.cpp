@@ -365,10 +365,10 @@ hipError_t enqueue_step(pic_ctx *c, hipStream_t s, bool sort_now)
     hipError_t e;
     const bool tm = c->timing && c->ev_used + 2 <= (int64_t)c->ev.size();
     if (c->cfg.fused) {
-        if ((e = launch_solve(d, f64, c->P.chunks_tot, true, s)) != hipSuccess) return e;
+        // the solve's last block computes the collision bound, so the measurement hook
+        // times the particle pass alone
+        if ((e = launch_solve(d, f64, c->P.chunks_tot, true, s, false, coll)) != hipSuccess) return e;
         const int stages = coll ? (SB_PUSH | SB_COLLIDE | SB_DEPOSIT) : (SB_PUSH | SB_DEPOSIT);
-        // the measurement hook times the particle pass alone: the bound kernel goes first
-        if (coll && (e = launch_params(d, s)) != hipSuccess) return e;
         if (tm && (e = hipEventRecord(c->ev[c->ev_used], s)) != hipSuccess) return e;
         if ((e = launch_particles(d, c->L, s, f64, stages, sort_now ? 1 : 0, false)) != hipSuccess) return e;
         if (tm) {
@@ -427,8 +427,8 @@ hipError_t enqueue_cycle_merged(pic_ctx *c, hipStream_t s)
     hipError_t e;
     for (int i = 0; i < K; ++i) {
         const int hist = (i == K - 1) ? 1 : 0;
-        if ((e = launch_solve(d, f64, c->P.chunks_tot, true, s, i > 0)) != hipSuccess) return e;
-        if ((e = launch_particles(d, c->L, s, f64, stages, hist)) != hipSuccess) return e;
+        if ((e = launch_solve(d, f64, c->P.chunks_tot, true, s, i > 0, true)) != hipSuccess) return e;
+        if ((e = launch_particles(d, c->L, s, f64, stages, hist, false)) != hipSuccess) return e;
         if ((e = launch_candidates(d, c->L, s, f64, hist)) != hipSuccess) return e;
         if ((e = launch_neutrals(d, s)) != hipSuccess) return e;
         if ((e = launch_source(d, hist, s)) != hipSuccess) return e;

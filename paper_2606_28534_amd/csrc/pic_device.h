@@ -267,17 +267,18 @@ __device__ __forceinline__ BirthBuf birth_buf(const Dev &d, int parity)
 // maxima and the ensemble's max |E|: nu_max = n_g sigma_T (vmax + |q/m| dt (max|E| +
 // |E_ext|)) (1 + 2^-16) and P_null = 1 - exp(-nu_max dt).  Called by a whole wave (lanes
 // read the stripes); every lane gets the result.
-__device__ __forceinline__ void seg_params(const Dev &d, int sg, double &numax, double &pnull)
+// `half` is the vmax2 half holding the current maxima and `emax` the ensemble's max |E|.
+__device__ __forceinline__ void seg_params(const Dev &d, int sg, int half, double emax, double &numax,
+                                           double &pnull)
 {
     const SegC &S = d.seg[sg];
     const EnsC &e = d.ens[S.ens];
-    const int half = *d.vcur;
     double m2 = 0.0;  // squared speeds are non-negative: bit patterns order as integers
     for (int st = lane_id(); st < kCntStripes; st += kWave)
         m2 = fmax(m2, __longlong_as_double((long long)d.vmax2[((int64_t)half * kCntStripes + st) * d.nseg + sg]));
     m2 = wave_max_f64(m2);
     const double vmax = __dsqrt_rn(m2);
-    double Vb = __dadd_rn(vmax, __dmul_rn(__dmul_rn(S.qm_abs, e.dt), __dadd_rn(d.emax[S.ens], fabs(e.E_ext))));
+    double Vb = __dadd_rn(vmax, __dmul_rn(__dmul_rn(S.qm_abs, e.dt), __dadd_rn(emax, fabs(e.E_ext))));
     // reading R26: the relative speed to a sampled neutral exceeds the ion's by at most vn_max
     if (S.species == 1) Vb = __dadd_rn(Vb, e.vn_max);
     numax = __dmul_rn(__dmul_rn(S.ngsT, Vb), kNuSafety);

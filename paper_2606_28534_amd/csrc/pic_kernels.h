@@ -32,9 +32,10 @@ hipError_t launch_init(const Dev &d, bool f64, int sg, int64_t n, int64_t ppc, i
 hipError_t launch_vmax(const Dev &d, bool f64, hipStream_t s);
 hipError_t launch_zero_q(const Dev &d, bool f64, hipStream_t s);
 // The field solve; with `with_births` its two kernels also scan and place the previous
-// step's births in extra blocks (needs births_fit_solve: the one-block group scan).
+// step's births in extra blocks (needs births_fit_solve: the one-block group scan); with
+// `with_params` the second kernel's last block computes the null-collision bound.
 hipError_t launch_solve(const Dev &d, bool f64, int64_t nchunks, bool zero_q, hipStream_t s,
-                        bool with_births = false);
+                        bool with_births = false, bool with_params = false);
 bool births_fit_solve(const Dev &d);
 hipError_t launch_field_stats(const Dev &d, bool f64, int64_t nchunks, hipStream_t s);
 hipError_t launch_params(const Dev &d, hipStream_t s);

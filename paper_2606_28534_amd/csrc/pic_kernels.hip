@@ -714,12 +714,20 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve1(Dev d, int nchunks, in
 
 // Reading R11: per-segment null-collision bound from the current max speed and max field.
 // One wave per segment (lanes read the striped speed maxima); every lane gets the result.
-__device__ void compute_params(const Dev &d)
+// With `coherent`, the current half and max |E| were written by other blocks of the same
+// launch (the last block of the second solve kernel computes the bound), so they are read
+// with atomics, which see every block's atomic updates without a fence.
+__device__ void compute_params(const Dev &d, bool coherent)
 {
     const int nw = blockDim.x / kWave, w = threadIdx.x / kWave;
+    const int half = coherent ? atomicAdd(d.vcur, 0) : *d.vcur;
     for (int sg = w; sg < d.nseg; sg += nw) {
         double numax, pnull;
-        seg_params(d, sg, numax, pnull);
+        const int en = d.seg[sg].ens;
+        const double emax = coherent
+            ? __longlong_as_double((long long)atomicMax((unsigned long long *)(d.emax + en), 0ull))
+            : d.emax[en];
+        seg_params(d, sg, half, emax, numax, pnull);
         if (lane_id() == 0) {
             d.numax[sg] = numax;
             d.pnull[sg] = pnull;
@@ -727,18 +735,11 @@ __device__ void compute_params(const Dev &d)
     }
 }
 
-__global__ void k_params(Dev d) { compute_params(d); }
+__global__ void k_params(Dev d) { compute_params(d, false); }
 
-// Blocks [0, nchunks) solve; blocks beyond place the previous step's births (they touch
-// particle slots beyond the ones in use, the id and slot counters, the birth lists, the
-// speed-maximum halves and the step counter, none of which the solve reads or writes).
 template <bool F64>
-__global__ void __launch_bounds__(kSolveThreads) k_solve2(Dev d, int zero_q, int nchunks)
+__device__ void solve2_body(const Dev &d, int zero_q)
 {
-    if ((int)blockIdx.x >= nchunks) {
-        birth_place_body<F64>(d, 1, 1, (int)blockIdx.x - nchunks, (int)gridDim.x - nchunks);
-        return;
-    }
     __shared__ double s_buf[8];
     __shared__ double s_E[F64 ? 1 : kChunk + 1];  // the chunk's node E, for the gather table
     __shared__ double s_C0, s_F0, s_Eh, s_bg, s_Ctot;
@@ -941,6 +942,30 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve2(Dev d, int zero_q, int
             if (fv[1] > 0.0) atomicOr(d.err, (int)E_NONFINITE);
         }
     }
+}
+
+// Blocks [0, nchunks) solve; blocks beyond place the previous step's births (they touch
+// particle slots beyond the ones in use, the id and slot counters, the birth lists, the
+// speed-maximum halves and the step counter, none of which the solve reads or writes).
+// With `params`, the last block to finish computes the next pass's null-collision bound
+// (R11) from this solve's max |E| and the current speed maxima, in place of a kernel of
+// its own; it reads what other blocks of this launch updated (max |E|, and the maxima half
+// the placement made current) through atomics, which need no fence.
+template <bool F64>
+__global__ void __launch_bounds__(kSolveThreads) k_solve2(Dev d, int zero_q, int nchunks, int params)
+{
+    if ((int)blockIdx.x >= nchunks)
+        birth_place_body<F64>(d, 1, 1, (int)blockIdx.x - nchunks, (int)gridDim.x - nchunks);
+    else
+        solve2_body<F64>(d, zero_q);
+    if (!params) return;
+    __shared__ bool s_last;
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = (atomicAdd(d.ticket + 6, 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (!s_last) return;
+    compute_params(d, true);
+    if (threadIdx.x == 0) d.ticket[6] = 0u;
 }
 
 // Periodic only: subtract the mean of phi and build the gather table.
@@ -1323,7 +1348,7 @@ __device__ void birth_place_body(const Dev &d, int deferred, int advance, int bi
     __syncthreads();
     if (threadIdx.x == 0) {
         d.ticket[1] = 0u;
-        *d.vcur = 1 - *d.vcur;
+        atomicExch(d.vcur, 1 - *d.vcur);  // atomic: the bound may be computed in this launch
     }
     __syncthreads();
     {
@@ -1645,17 +1670,17 @@ hipError_t launch_zero_q(const Dev &d, bool f64, hipStream_t s)
 bool births_fit_solve(const Dev &d) { return d.g_tot <= (int64_t)1 << 18; }
 
 hipError_t launch_solve(const Dev &d, bool f64, int64_t nchunks, bool zero_q, hipStream_t s,
-                        bool with_births)
+                        bool with_births, bool with_params)
 {
     const int nc = (int)nchunks, zq = zero_q ? 1 : 0;
-    const int scan = with_births ? 1 : 0;
+    const int scan = with_births ? 1 : 0, par = with_params ? 1 : 0;
     const dim3 g1(nc + scan), g2(nc + (with_births ? kPlaceBlocks : 0));
     if (f64) {
         hipLaunchKernelGGL(k_solve1<true>, g1, dim3(kSolveThreads), 0, s, d, nc, scan);
-        hipLaunchKernelGGL(k_solve2<true>, g2, dim3(kSolveThreads), 0, s, d, zq, nc);
+        hipLaunchKernelGGL(k_solve2<true>, g2, dim3(kSolveThreads), 0, s, d, zq, nc, par);
     } else {
         hipLaunchKernelGGL(k_solve1<false>, g1, dim3(kSolveThreads), 0, s, d, nc, scan);
-        hipLaunchKernelGGL(k_solve2<false>, g2, dim3(kSolveThreads), 0, s, d, zq, nc);
+        hipLaunchKernelGGL(k_solve2<false>, g2, dim3(kSolveThreads), 0, s, d, zq, nc, par);
     }
     LAUNCH_CHECK();
     if (d.periodic) {

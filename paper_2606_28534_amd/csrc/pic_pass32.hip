@@ -591,14 +591,6 @@ __device__ __forceinline__ T ld_nt(const T *p)
         return *p;
 }
 
-template <bool NT, typename T>
-__device__ __forceinline__ void st_nt(T *p, T v)
-{
-    if constexpr (NT)
-        __builtin_nontemporal_store(v, p);
-    else
-        *p = v;
-}
 
 template <int PPT, bool NT>
 __global__ void __launch_bounds__(256) k_sort32(Dev d, int W, int64_t T)
@@ -698,12 +690,13 @@ __global__ void __launch_bounds__(256) k_sort32(Dev d, int W, int64_t T)
             atomicOr(d.err, (int)E_CAP_PART);
             continue;
         }
-        st_nt<NT>(ocell + o, cell[k]);
-        st_nt<NT>(ooff + o, off[k]);
-        st_nt<NT>(ovx + o, vx[k]);
-        st_nt<NT>(ovy + o, vy[k]);
-        st_nt<NT>(ovz + o, vz[k]);
-        st_nt<NT>(oid + o, id[k]);
+        // the output runs are scattered: ordinary stores (non-temporal ones measured slower)
+        ocell[o] = cell[k];
+        ooff[o] = off[k];
+        ovx[o] = vx[k];
+        ovy[o] = vy[k];
+        ovz[o] = vz[k];
+        oid[o] = id[k];
     }
 }
 
