@@ -165,6 +165,35 @@ def sheath_case_run(pic, shape, case, seed, warmup, steps):
             "recycled": d1["recycled"], "sourced": d1["sourced"]}
 
 
+def large_run(pic, shape, seed, warmup, steps):
+    """The large single-GPU share: 1e6 cells x 500 ppc x 2 species (1.0e9 particles, about
+    60 GB of HBM), oblique B, three channels with births, sort every 10 steps."""
+    import torch
+
+    import synth
+
+    work = synth.c5_large(seed=seed)
+    sim = pic.Sim(work, fused=True, **shape)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    p0 = sim.diag()["pushes"]
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    p1 = sim.diag()["pushes"]
+    ws = sim.ws_bytes
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    pushes = p1 - p0
+    return {"value": pushes / (t1 - t0), "unit": "particle-pushes/s", "steps": steps,
+            "after_steps": warmup, "ms_per_step": (t1 - t0) / steps * 1e3,
+            "particles": 2 * work["ensembles"][0]["species"][0]["ppc"] * work["ensembles"][0]["ncells"],
+            "workspace_gb": round(ws / 1e9, 1),
+            "frac_of_hbm_peak_46.8B": round((B_ALG_PARTICLE + 48.0 / 10) * pushes / (t1 - t0) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def stream_copy_gbs(torch, gib=4.0, reps=10):
     """Device-to-device copy bandwidth of a plain torch copy on the same GPU (read + write
     bytes per second), for context next to the HBM peak."""
@@ -206,6 +235,7 @@ def main():
     ap.add_argument("--no-stream", action="store_true")
     ap.add_argument("--no-walls-variant", action="store_true")
     ap.add_argument("--no-sheath-cases", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--case", choices=["sheath", "recycling", "source"], default="sheath",
                     help="main workload: the sheath slab (default) or one of the paper's two "
                          "sheath cases (for profiling them)")
@@ -322,6 +352,10 @@ def main():
         cases = {"recycling": sheath_case_run(pic, shape, "recycling", args.seed, 20, args.batched_steps),
                  "source": sheath_case_run(pic, shape, "source", args.seed, 200, args.batched_steps)}
 
+    large = None
+    if not args.no_large:
+        large = large_run(pic, shape, args.seed, 10, 20)
+
     stream = None
     if not args.no_stream:
         stream = stream_copy_gbs(torch)
@@ -356,6 +390,7 @@ def main():
         "batched": batched,
         "floating_walls_smoothed": walls,
         "sheath_cases": cases,
+        "large": large,
         "stream_copy": stream,
         "cpu_baseline": cpu,
     }

@@ -546,7 +546,7 @@ __device__ __forceinline__ double node_rho_raw(const Dev &d, const EnsC &e, int6
 // Block-wide inclusive scan of one double per thread (256 threads).
 __device__ double block_incl_scan(double v, double *s_buf)
 {
-    const int lane = lane_id(), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int lane = lane_id(), w = threadIdx.x / kWave;
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
         const double n = __shfl_up(v, o);
@@ -557,7 +557,6 @@ __device__ double block_incl_scan(double v, double *s_buf)
     double add = 0.0;
     for (int i = 0; i < w; ++i) add += s_buf[i];
     __syncthreads();
-    (void)nw;
     return v + add;
 }
 
@@ -673,7 +672,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve1(Dev d, int nchunks, in
     }
     const double excl = block_incl_scan(loc, s_buf) - loc;
     // integer counts in this thread's node range: interior nodes and the prefix weights
-    double run = excl, runc = 0.0;
+    double run = excl;
     int64_t c1_before = 0;  // interior nodes in [a, j0)
     {
         const int64_t lo = max(a, (int64_t)1), hi = min(j0, N);  // [lo, hi) interior, i < j0
@@ -693,7 +692,6 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve1(Dev d, int nchunks, in
             dd += (double)c1;
             cnt += 1.0;
         }
-        (void)runc;
     }
     // the ensemble's max |E| is accumulated by the second pass's blocks (atomic max)
     if (k == e.chunk0 && threadIdx.x == 0) d.emax[ei] = 0.0;
