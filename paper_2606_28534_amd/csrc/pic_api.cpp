@@ -522,6 +522,8 @@ int pic_init(const pic_config *cfg, void *workspace, size_t bytes, void *stream,
     carve(c->P, c->ws, c->d);
     c->d.periodic = cfg->boundary == PIC_PERIODIC;
     c->d.collisions = cfg->collisions;
+    for (int e = 0; e < cfg->n_ensembles; ++e)
+        if (cfg->ens[e].cx_relative) c->d.any_cx_rel = 1;
     c->diag_scratch = (double *)(c->ws + need - align_up(2 * kDiagGrid * sizeof(double)));
     c->L = default_launch(cfg, c->P);
     c->sort_every = cfg->sort_every > 0 ? cfg->sort_every : kCompactEvery;

@@ -104,6 +104,7 @@ static_assert(__builtin_offsetof(Birth, pid) == 0 && __builtin_offsetof(Birth, e
 // Everything a kernel may touch; passed by value.
 struct Dev {
     int32_t nseg, nens, nspecies, periodic, collisions;
+    int32_t any_cx_rel;       // some ensemble uses relative-speed charge exchange (R26)
     const SegC *seg;
     const EnsC *ens;
     // particles (buffer b in {0,1}); FP32 and FP64 forms

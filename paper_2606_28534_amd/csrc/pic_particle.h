@@ -209,8 +209,10 @@ __device__ __forceinline__ void three_normals(uint4 w, T z[3])
 
 // Null-collision decision (FP64, no contraction: identical to the CPU oracle for identical
 // inputs) and scattering kinematics (in the particle precision).  Returns the channel
-// (-1 none, 0 elastic, 1 ionisation, 2 CX); on ionisation fills the new pair.
-template <bool F64>
+// (-1 none, 0 elastic, 1 ionisation, 2 CX); on ionisation fills the new pair.  CXREL = false
+// compiles the relative-speed charge exchange (R26) out, which keeps the FP32 candidate
+// kernel's registers (and so its occupancy) to what the other channels need.
+template <bool F64, bool CXREL = true>
 __device__ __forceinline__ int p_collide(const EnsC &e, const SegC &S, int s, double numax,
                                          double pnull, uint32_t tag, PS<F64> &p, double ve[3],
                                          double vi[3])
@@ -230,7 +232,7 @@ __device__ __forceinline__ int p_collide(const EnsC &e, const SegC &S, int s, do
             chan = 0;
         else if (thr < __dadd_rn(nu_el, nu_iz))
             chan = 1;
-    } else if (e.cx_rel) {
+    } else if (CXREL && e.cx_rel) {
         // reading R26: the target neutral (block 2) is drawn first; the rate takes the
         // relative speed, and a charge exchange hands the ion the neutral's velocity
         double zn[3];

@@ -441,6 +441,7 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
 // =======================================================================================
 constexpr int kCandTiles = 32;
 
+template <bool CXREL>
 __global__ void __launch_bounds__(256) k_cand32(Dev d, int tile, int64_t T, int hist)
 {
     __shared__ uint32_t s_pre[kCandTiles + 1];
@@ -507,7 +508,7 @@ __global__ void __launch_bounds__(256) k_cand32(Dev d, int tile, int64_t T, int 
             p.vx = __uint_as_float(r1.x);
             p.vy = __uint_as_float(r1.y);
             p.vz = __uint_as_float(r1.z);
-            ch = p_collide<false>(e, S, S.species, d.numax[sg], d.pnull[sg], tag, p, ve, vi);
+            ch = p_collide<false, CXREL>(e, S, S.species, d.numax[sg], d.pnull[sg], tag, p, ve, vi);
             if (ch >= 0) {
                 d.fvx[b][i] = p.vx;
                 d.fvy[b][i] = p.vy;
@@ -735,7 +736,11 @@ hipError_t launch_cand32(const Dev &d, int ppt, hipStream_t s, int hist, int64_t
 {
     const int tile = 256 * ppt;
     const int64_t T = cap_tot / tile;
-    hipLaunchKernelGGL(k_cand32, dim3((T + kCandTiles - 1) / kCandTiles), dim3(256), 0, s, d, tile, T, hist);
+    const dim3 g((unsigned)((T + kCandTiles - 1) / kCandTiles));
+    if (d.any_cx_rel)
+        hipLaunchKernelGGL(k_cand32<true>, g, dim3(256), 0, s, d, tile, T, hist);
+    else
+        hipLaunchKernelGGL(k_cand32<false>, g, dim3(256), 0, s, d, tile, T, hist);
     return hipGetLastError();
 }
 
