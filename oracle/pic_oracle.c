@@ -646,8 +646,9 @@ void orc_walls(orc_state *st)
  * Reading R14: created particles are ordered by parent id and numbered next_id, next_id+1,
  *   ... in that order, then appended after the survivors of each species.
  * Reading R25: the volumetric source of the non-uniform sheath case creates src_pairs
- *   electron-ion pairs per step, uniform over [0, src_frac L): pair k of step n takes its
- *   position from word 0 of Philox block 4 of key (seed, 0) with counter (k, n), the
+ *   electron-ion pairs per step, spread uniformly over [0, src_frac L) by stratified
+ *   sampling: pair k of step n lies in the k-th of src_pairs equal sub-intervals, at the
+ *   fraction u of it given by word 0 of Philox block 4 of key (seed, 0) with counter (k, n); the
  *   electron three normals of block 5 of key (seed, 0) at T_e and the ion three normals of
  *   block 5 of key (seed, 1) at T_i.  Both members sit at the same x.  A step's source
  *   pairs take the ids (and slots) before its ionisation births: next_id + k for pair k,
@@ -774,7 +775,7 @@ void orc_collide(orc_state *st)
         uint32_t w[4], z0w[4], z1w[4];
         double z[3];
         draw_block(st, 0, (uint32_t)k, tag, 4u, w);
-        double x = c->src_frac * dlen(st) * orc_uniform(w[0]);
+        double x = c->src_frac * dlen(st) * (((double)k + orc_uniform(w[0])) / (double)c->src_pairs);
         draw_block(st, 0, (uint32_t)k, tag, 5u, z0w);
         draw_block(st, 1, (uint32_t)k, tag, 5u, z1w);
         for (int s = 0; s < 2; s++) {

@@ -194,8 +194,10 @@ __global__ void __launch_bounds__(256) k_neutrals(Dev d)
     }
 }
 
-// Reading R25: pair k of ensemble e in step n (tag n).  Position: word 0 of Philox block 4
-// of key (seed, 0), counter (k, n); electron velocity: three normals of block 5 of key
+// Reading R25: pair k of ensemble e in step n (tag n).  Position: stratified, in the k-th of
+// the src_pairs equal parts of [0, src_x), at the fraction given by word 0 of Philox block 4
+// of key (seed, 0), counter (k, n), so a step's pairs come out in cell order (their tiles
+// deposit through the LDS window like sorted particles); electron velocity: three normals of block 5 of key
 // (seed, 0) at v_th,e; ion velocity: three normals of block 5 of key (seed, 1) at v_th,i.
 // The pair takes slot and id n_slots + k, next_id + k of its species (before the step's
 // ionisation births, which the placement numbers from the advanced counters), deposits its
@@ -224,7 +226,7 @@ __global__ void __launch_bounds__(256) k_source(Dev d, int hist)
         const EnsC &e = d.ens[en];
         const int64_t k = g - e.src_base;
         const uint4 w = draw(e.seed, 0, (uint32_t)k, tag, 4u);
-        const double x = e.src_x * u01d(w.x);
+        const double x = e.src_x * (((double)k + u01d(w.x)) / (double)e.src_pairs);
         int c;
         float o;
         x_to_celloff(x, e.dx, (int)e.ncells, c, o);

@@ -497,9 +497,10 @@ def test_neutrals_stream_freely_and_leave_exactly():
 
 
 def test_source_pairs_law_and_ids():
-    """The volumetric source creates src_pairs neutral pairs per step, uniform over
-    [0, src_frac L), both members at the same x, velocities Maxwellian at the species
-    temperatures, ids next_id + k; its pairs take their ids before the step's births."""
+    """The volumetric source creates src_pairs neutral pairs per step, stratified over
+    [0, src_frac L) (pair k uniform within the k-th equal part), both members at the same x,
+    velocities Maxwellian at the species temperatures, ids next_id + k; its pairs take their
+    ids before the step's births."""
     N, S = 200, 6000
     e = synth.ensemble(N, 0, collisions=False, src_pairs=S, src_frac=0.5)
     for sp in e["species"]:
@@ -514,11 +515,14 @@ def test_source_pairs_law_and_ids():
     assert np.array_equal(pe["id"], np.arange(S)) and np.array_equal(pi["id"], np.arange(S))
     assert np.array_equal(pe["x"], pi["x"])
     L = N * e["dx"]
-    assert scipy.stats.kstest(pe["x"] / (0.5 * L), "uniform").pvalue > 1e-3
-    # pair k sits at src_frac L u, u from word 0 of block 4 of key (seed, 0), counter (k, step)
+    # one pair per stratum, and within its stratum at a uniform fraction
+    frac = pe["x"] * S / (0.5 * L) - np.arange(S)
+    assert np.all((frac > 0) & (frac < 1))
+    assert scipy.stats.kstest(frac, "uniform").pvalue > 1e-3
+    # pair k's fraction is word 0 of block 4 of key (seed, 0), counter (k, step)
     for k in (0, 1, 17, S - 1):
         u = oracle.uniform(oracle.philox([k, 5, 4, 0], [e["seed"], 0])[0])
-        assert pe["x"][k] == 0.5 * L * u
+        assert pe["x"][k] == 0.5 * L * ((k + u) / S)
     for p, sp in ((pe, e["species"][0]), (pi, e["species"][1])):
         vt = math.sqrt(sp["T"] / sp["m"])
         for k in ("vx", "vy", "vz"):
@@ -546,7 +550,7 @@ def test_source_pairs_law_and_ids():
     xs = dict(zip(pe3["id"].tolist(), pe3["x"].tolist()))
     for k in range(S):
         u = oracle.uniform(oracle.philox([k, 0, 4, 0], [e["seed"], 0])[0])
-        assert xs[n0 + k] == 0.5 * L * u
+        assert xs[n0 + k] == 0.5 * L * ((k + u) / S)
 
 
 def test_particle_bookkeeping_with_source_recycling_and_collisions():
