@@ -97,9 +97,12 @@ typedef struct {
                             step count reaches a multiple of K; 0 = compaction-only sort
                             every 20 steps, physics unchanged either way                    */
     int32_t fused;       /* 0: one kernel per stage; 1: fused particle pass + HIP graph    */
-    int32_t block;       /* threads per block for particle kernels; 0 = default            */
-    int32_t grid;        /* persistent blocks for particle kernels; 0 = default            */
-    int32_t window;      /* LDS deposit window in nodes (power of two); 0 = default        */
+    int32_t block;       /* threads per block of the FP64 particle kernels (64, 128 or
+                            256); 0 = default 256                                           */
+    int32_t grid;        /* persistent blocks for the FP64 particle kernels; 0 = default   */
+    int32_t window;      /* widest span of cells a tile deposits (and, on sort steps,
+                            counts) through LDS, in [16, 4096]; a tile's window covers only
+                            its own cells, so this bounds LDS per block; 0 = default 2048   */
     int32_t ppt;         /* particles per thread of the FP32 pass (4 or 8); 0 = default    */
     int32_t sort_ppt;    /* particles per thread of the FP32 sort scatter; 0 = default     */
     int32_t nontemporal; /* bit 0: the fused FP32 pass streams particles with non-temporal

@@ -64,6 +64,14 @@ int build_plan(const pic_config *cfg, Plan &P, std::string &msg)
         msg = "smooth must be in [0, " + std::to_string(kMaxSmooth) + "]";
         return PIC_EINVAL;
     }
+    if (cfg->window != 0 && (cfg->window < 16 || cfg->window > 4096)) {
+        msg = "window must be 0 (default) or in [16, 4096]";
+        return PIC_EINVAL;
+    }
+    if (cfg->block != 0 && cfg->block != 64 && cfg->block != 128 && cfg->block != 256) {
+        msg = "block must be 0 (default), 64, 128 or 256";
+        return PIC_EINVAL;
+    }
     P.nens = cfg->n_ensembles;
     P.nspecies = cfg->nspecies;
     P.nseg = P.nens * P.nspecies;
@@ -477,7 +485,7 @@ Launch default_launch(const pic_config *cfg, const Plan &P)
     int g = cfg->grid > 0 ? cfg->grid : 1024;
     g = (int)std::min<int64_t>(g, std::max<int64_t>(8, (tiles + 7) / 8 * 8));
     L.grid = std::max(8, g / 8 * 8);
-    L.window = cfg->window > 0 ? cfg->window : 512;
+    L.window = cfg->window > 0 ? cfg->window : 2048;
     return L;
 }
 
@@ -1253,7 +1261,7 @@ int pic_autotune(pic_ctx *c, int32_t trial_steps, int32_t *shape, void *stream)
     hipStream_t s = (hipStream_t)stream;
     if (!c->P.f64) {
         const int ppts[2] = {4, 8};
-        const int wins[3] = {256, 512, 1024};
+        const int wins[3] = {1024, 2048, 4096};
         const bool verbose = std::getenv("PIC_AUTOTUNE_VERBOSE") != nullptr;
         // candidates: particles per thread x LDS window x (fused pass only) non-temporal
         // streaming; two rounds in opposite orders; a candidate's score is the sum of its

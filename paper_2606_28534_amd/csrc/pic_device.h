@@ -240,6 +240,12 @@ __device__ __forceinline__ int wave_min_i32(int v)
     for (int m = 32; m >= 1; m >>= 1) v = min(v, __shfl_xor(v, m));
     return v;
 }
+__device__ __forceinline__ int wave_max_i32(int v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = max(v, __shfl_xor(v, m));
+    return v;
+}
 
 // Double bits of a non-negative value order like unsigned integers.
 __device__ __forceinline__ unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }

@@ -120,53 +120,15 @@ __device__ void flush_tally(const Dev &d, int seg, Tally &t, bool want_vmax)
     t.zero();
 }
 
-struct Window {
-    int seg;   // segment the window belongs to (-1 none)
-    int base;  // first cell
-};
-
-__device__ void window_flush(const Dev &d, const Window &w, int W, unsigned long long *sQ,
-                             uint32_t *sH, bool hist)
-{
-    __syncthreads();
-    if (w.seg >= 0) {
-        const SegC &S = d.seg[w.seg];
-        const int s = S.species;
-        const int nn = S.periodic ? S.ncells : S.ncells + 1;
-        unsigned long long *Q = d.Qi + (int64_t)s * d.nodes_tot + S.gbase;
-        for (int i = threadIdx.x; i <= W; i += blockDim.x) {
-            const unsigned long long v = sQ[i];
-            if (v) {
-                int node = w.base + i;
-                if (S.periodic && node >= S.ncells) node -= S.ncells;
-                if (node < nn) atomicAdd(Q + node, v);
-                sQ[i] = 0ull;
-            }
-            if (hist && i < W) {
-                const uint32_t c = sH[i];
-                if (c) {
-                    const int cell = w.base + i;
-                    if (cell < S.ncells) atomicAdd(d.cellcnt + S.cbase + cell, c);
-                    sH[i] = 0u;
-                }
-            }
-        }
-    } else {
-        for (int i = threadIdx.x; i <= W; i += blockDim.x) {
-            sQ[i] = 0ull;
-            if (i < W) sH[i] = 0u;
-        }
-    }
-    __syncthreads();
-}
-
 // =======================================================================================
-// The particle pass.
+// The FP64 particle pass (the FP32 form runs in k_pass32).  A persistent grid walks the
+// tiles of all segments; each stage is optional, so the same kernel serves the fused pass
+// and the separate stages.  The deposit goes straight to the int64 node array.
 // =======================================================================================
 enum Stage : int { ST_PUSH = 1, ST_COLLIDE = 2, ST_DEPOSIT = 4, ST_HIST = 8 };
 
-template <bool F64, int STAGES, int PPT>
-__global__ void __launch_bounds__(256) k_particles(Dev d, int W, int hist_rt)
+template <int STAGES, int PPT>
+__global__ void __launch_bounds__(256) k_particles(Dev d, int hist_rt)
 {
     constexpr bool PUSH = STAGES & ST_PUSH;
     constexpr bool COLL = STAGES & ST_COLLIDE;
@@ -175,13 +137,8 @@ __global__ void __launch_bounds__(256) k_particles(Dev d, int W, int hist_rt)
     const bool hist = HISTC || (hist_rt != 0);
     constexpr bool NEED_V = PUSH || COLL;
     constexpr bool NEED_ID = COLL;
-    constexpr bool WINDOW = !F64 && (DEPO || HISTC);
 
-    extern __shared__ unsigned long long s_dyn[];
-    unsigned long long *sQ = s_dyn;                  // [W + 1]
-    uint32_t *sH = (uint32_t *)(s_dyn + (W + 1));    // [W]
     __shared__ int64_t s_tpre[kMaxSeg + 1];
-    __shared__ int s_c0;
 
     const int BLOCK = blockDim.x;
     const int64_t TILE = (int64_t)BLOCK * PPT;
@@ -194,13 +151,6 @@ __global__ void __launch_bounds__(256) k_particles(Dev d, int W, int hist_rt)
     const uint32_t tag = (uint32_t)step;
     const int st = stripe_of_block();
 
-    Window win{-1, 0};
-    if constexpr (WINDOW) {
-        for (int i = threadIdx.x; i <= W; i += BLOCK) {
-            sQ[i] = 0ull;
-            if (i < W) sH[i] = 0u;
-        }
-    }
     Tally tal;
     tal.zero();
     int tseg = -1;
@@ -219,28 +169,15 @@ __global__ void __launch_bounds__(256) k_particles(Dev d, int W, int hist_rt)
         const int64_t first = S.base + lt * TILE;
         const int64_t last = S.base + min((lt + 1) * TILE, d.n_slots[sg]);
 
-        PS<F64> p[PPT];
+        PS<true> p[PPT];
         bool live[PPT];
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             const int64_t i = first + (int64_t)k * BLOCK + threadIdx.x;
             live[k] = false;
             if (i < last) {
-                p_load<F64>(d, b, i, p[k], NEED_V, NEED_ID);
-                live[k] = p_alive<F64>(p[k]);
-            }
-        }
-        // The sliding deposit window: decided from the tile's first slot before the push.
-        if constexpr (WINDOW) {
-            if (threadIdx.x == 0) s_c0 = live[0] ? p[0].cell : kDead;
-            __syncthreads();
-            const int c0 = s_c0;
-            const bool reseg = (win.seg != sg);
-            const bool slide = (c0 != kDead) && (c0 < win.base || c0 > win.base + W / 2);
-            if (reseg || slide) {
-                window_flush(d, win, W, sQ, sH, hist);
-                win.seg = sg;
-                win.base = (c0 == kDead) ? 0 : max(c0 - W / 8, 0);
+                p_load<true>(d, b, i, p[k], NEED_V, NEED_ID);
+                live[k] = p_alive<true>(p[k]);
             }
         }
         const double numax = COLL ? d.numax[sg] : 0.0;
@@ -249,141 +186,94 @@ __global__ void __launch_bounds__(256) k_particles(Dev d, int W, int hist_rt)
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             const int64_t i = first + (int64_t)k * BLOCK + threadIdx.x;
-            int key = -1;
-            uint32_t fq = 0;
-            if (live[k]) {
-                if (PUSH) {
-                    ++tal.push;
-                    const int wall = p_push<F64>(d, S, e, p[k]);
-                    if (wall == 3) {
-                        p_kill<F64>(p[k]);
-                        live[k] = false;
-                        if constexpr (!F64)
-                            d.cell[b][i] = kDead;
-                        else
-                            d.x[b][i] = -1.0;
-                    } else if (wall) {
-                        const double v2 = speed2_rn((double)p[k].vx, (double)p[k].vy, (double)p[k].vz);
-                        if (wall == 1) {
-                            ++tal.wl;
-                            tal.kel += S.halfmw * v2;
-                        } else {
-                            ++tal.wr;
-                            tal.ker += S.halfmw * v2;
-                        }
-                        p_kill<F64>(p[k]);
-                        live[k] = false;
-                        if constexpr (!F64)
-                            d.cell[b][i] = kDead;
-                        else
-                            d.x[b][i] = -1.0;
-                    }
-                }
-                if (COLL && live[k]) {
-                    double ve[3], vi[3];
-                    const int ch = p_collide<F64>(e, S, s, numax, pnull, tag, p[k], ve, vi);
-                    if (ch == 0)
-                        ++tal.el;
-                    else if (ch == 2)
-                        ++tal.cx;
-                    else if (ch == 1) {
-                        ++tal.iz;
-                        // birth record: slot in this block's stripe, or in the next ones
-                        // when it is full
-                        const BirthBuf bb = birth_buf(d, (int)(tag & 1u));
-                        int bst = st & (kStripes - 1);
-                        uint32_t slot = atomicAdd(bb.nbirth + bst, 1u);
-                        for (int a = 1; a < kStripes && (int64_t)slot >= d.birth_stripe_cap; ++a) {
-                            bst = (bst + 1) & (kStripes - 1);
-                            slot = atomicAdd(bb.nbirth + bst, 1u);
-                        }
-                        if ((int64_t)slot < d.birth_stripe_cap) {
-                            Birth &B = bb.births[(int64_t)bst * d.birth_stripe_cap + slot];
-                            B.pid = p[k].id;
-                            B.ens = S.ens;
-                            if constexpr (!F64) {
-                                B.cell = p[k].cell;
-                                B.off = p[k].off;
-                                B.x = ((double)p[k].cell + (double)p[k].off) * S.dx;
-                            } else {
-                                B.cell = 0;
-                                B.off = 0.f;
-                                B.x = p[k].x;
-                            }
-                            for (int q = 0; q < 3; ++q) {
-                                B.ve[q] = ve[q];
-                                B.vi[q] = vi[q];
-                            }
-                            birth_mark(bb, e, p[k].id);
-                        } else {
-                            atomicOr(d.err, (int)E_CAP_BIRTH);
-                        }
-                        const double ve2 = speed2_rn(ve[0], ve[1], ve[2]);
-                        tal.v2max = fmax(tal.v2max, ve2);
-                        if (S.other >= 0) {
-                            const double vi2 = speed2_rn(vi[0], vi[1], vi[2]);
-                            const int half = 1 - *d.vcur;
-                            atomicMax(d.vmax2 + ((int64_t)half * kCntStripes + st) * d.nseg + S.other,
-                                      dbits(vi2));
-                        }
-                        if (DEPO) {
-                            // the new pair sits at the parent's position
-                            if constexpr (!F64) {
-                                global_deposit32(d, S, s, p[k].cell, p[k].off, hist);
-                                if (S.other >= 0)
-                                    global_deposit32(d, d.seg[S.other], 1, p[k].cell, p[k].off, hist);
-                            } else {
-                                global_deposit64(d, S, s, p[k].x, hist);
-                                if (S.other >= 0) global_deposit64(d, d.seg[S.other], 1, p[k].x, hist);
-                            }
-                        }
-                    }
-                    tal.v2max = fmax(tal.v2max, speed2_rn((double)p[k].vx, (double)p[k].vy, (double)p[k].vz));
-                }
-                if (live[k] && (PUSH || COLL)) {
-                    if constexpr (!F64) {
-                        if (PUSH) {
-                            d.cell[b][i] = p[k].cell;
-                            d.off[b][i] = p[k].off;
-                        }
-                        d.fvx[b][i] = p[k].vx;
-                        d.fvy[b][i] = p[k].vy;
-                        d.fvz[b][i] = p[k].vz;
+            if (!live[k]) continue;
+            if (PUSH) {
+                ++tal.push;
+                const int wall = p_push<true>(d, S, e, p[k]);
+                if (wall == 3) {
+                    p_kill<true>(p[k]);
+                    live[k] = false;
+                    d.x[b][i] = -1.0;
+                } else if (wall) {
+                    const double v2 = speed2_rn((double)p[k].vx, (double)p[k].vy, (double)p[k].vz);
+                    if (wall == 1) {
+                        ++tal.wl;
+                        tal.kel += S.halfmw * v2;
                     } else {
-                        if (PUSH) d.x[b][i] = p[k].x;
-                        d.dvx[b][i] = p[k].vx;
-                        d.dvy[b][i] = p[k].vy;
-                        d.dvz[b][i] = p[k].vz;
+                        ++tal.wr;
+                        tal.ker += S.halfmw * v2;
                     }
-                }
-                if (live[k] && (DEPO || HISTC)) {
-                    if constexpr (!F64) {
-                        const int rel = p[k].cell - win.base;
-                        if (rel >= 0 && rel < W) {
-                            key = rel;
-                            fq = DEPO ? fixed_share(p[k].off) : 0u;
-                        } else {
-                            if (DEPO)
-                                global_deposit32(d, S, s, p[k].cell, p[k].off, hist);
-                            else
-                                atomicAdd(d.cellcnt + S.cbase + p[k].cell, 1u);
-                        }
-                    } else {
-                        if (DEPO)
-                            global_deposit64(d, S, s, p[k].x, hist);
-                        else {
-                            double f;
-                            const int j = p_cell<true>(S, p[k], f);
-                            atomicAdd(d.cellcnt + S.cbase + j, 1u);
-                        }
-                    }
+                    p_kill<true>(p[k]);
+                    live[k] = false;
+                    d.x[b][i] = -1.0;
                 }
             }
-            if constexpr (WINDOW) wave_window_deposit(key, fq, DEPO, hist, sQ, sH);
+            if (COLL && live[k]) {
+                double ve[3], vi[3];
+                const int ch = p_collide<true>(e, S, s, numax, pnull, tag, p[k], ve, vi);
+                if (ch == 0)
+                    ++tal.el;
+                else if (ch == 2)
+                    ++tal.cx;
+                else if (ch == 1) {
+                    ++tal.iz;
+                    // birth record: slot in this block's stripe, or in the next ones when
+                    // it is full
+                    const BirthBuf bb = birth_buf(d, (int)(tag & 1u));
+                    int bst = st & (kStripes - 1);
+                    uint32_t slot = atomicAdd(bb.nbirth + bst, 1u);
+                    for (int a = 1; a < kStripes && (int64_t)slot >= d.birth_stripe_cap; ++a) {
+                        bst = (bst + 1) & (kStripes - 1);
+                        slot = atomicAdd(bb.nbirth + bst, 1u);
+                    }
+                    if ((int64_t)slot < d.birth_stripe_cap) {
+                        Birth &B = bb.births[(int64_t)bst * d.birth_stripe_cap + slot];
+                        B.pid = p[k].id;
+                        B.ens = S.ens;
+                        B.cell = 0;
+                        B.off = 0.f;
+                        B.x = p[k].x;
+                        for (int q = 0; q < 3; ++q) {
+                            B.ve[q] = ve[q];
+                            B.vi[q] = vi[q];
+                        }
+                        birth_mark(bb, e, p[k].id);
+                    } else {
+                        atomicOr(d.err, (int)E_CAP_BIRTH);
+                    }
+                    const double ve2 = speed2_rn(ve[0], ve[1], ve[2]);
+                    tal.v2max = fmax(tal.v2max, ve2);
+                    if (S.other >= 0) {
+                        const double vi2 = speed2_rn(vi[0], vi[1], vi[2]);
+                        const int half = 1 - *d.vcur;
+                        atomicMax(d.vmax2 + ((int64_t)half * kCntStripes + st) * d.nseg + S.other,
+                                  dbits(vi2));
+                    }
+                    if (DEPO) {
+                        // the new pair sits at the parent's position
+                        global_deposit64(d, S, s, p[k].x, hist);
+                        if (S.other >= 0) global_deposit64(d, d.seg[S.other], 1, p[k].x, hist);
+                    }
+                }
+                tal.v2max = fmax(tal.v2max, speed2_rn((double)p[k].vx, (double)p[k].vy, (double)p[k].vz));
+            }
+            if (live[k] && (PUSH || COLL)) {
+                if (PUSH) d.x[b][i] = p[k].x;
+                d.dvx[b][i] = p[k].vx;
+                d.dvy[b][i] = p[k].vy;
+                d.dvz[b][i] = p[k].vz;
+            }
+            if (live[k] && (DEPO || HISTC)) {
+                if (DEPO)
+                    global_deposit64(d, S, s, p[k].x, hist);
+                else {
+                    double f;
+                    const int j = p_cell<true>(S, p[k], f);
+                    atomicAdd(d.cellcnt + S.cbase + j, 1u);
+                }
+            }
         }
-        if constexpr (WINDOW) __syncthreads();
     }
-    if constexpr (WINDOW) window_flush(d, win, W, sQ, sH, hist);
     if ((PUSH || COLL) && tseg >= 0) flush_tally(d, tseg, tal, COLL);
 }
 
@@ -1397,12 +1287,13 @@ __global__ void k_advance(Dev d)
 }
 
 // =======================================================================================
-// Counting sort by cell: the histogram is in cellcnt, scanned into cursor (global
-// positions over the concatenated segments).  Each tile ranks its particles per cell in
-// LDS (wave-leader reservation), reserves one run per cell with one HBM atomic, and
-// scatters into the other buffer.  Absorbed slots are dropped.
+// Counting sort by cell of the FP64 form (the FP32 form runs in k_sort32): the histogram
+// is in cellcnt, scanned into cursor (global positions over the concatenated segments).
+// Each tile ranks its particles per cell in LDS (wave-leader reservation), reserves one
+// run per cell with one HBM atomic, and scatters into the other buffer.  Absorbed slots
+// are dropped.
 // =======================================================================================
-template <bool F64, int PPT>
+template <int PPT>
 __global__ void __launch_bounds__(256) k_sort_scatter(Dev d, int W)
 {
     extern __shared__ unsigned long long s_dyn[];
@@ -1434,13 +1325,9 @@ __global__ void __launch_bounds__(256) k_sort_scatter(Dev d, int W)
             const int64_t i = first + (int64_t)k * BLOCK + threadIdx.x;
             cell[k] = kDead;
             if (i < last) {
-                if constexpr (!F64) {
-                    cell[k] = d.cell[b][i];
-                } else {
-                    const double x = d.x[b][i];
-                    double f;
-                    cell[k] = (x >= 0.0) ? (int)cell_of_x(S, x, f) : kDead;
-                }
+                const double x = d.x[b][i];
+                double f;
+                cell[k] = (x >= 0.0) ? (int)cell_of_x(S, x, f) : kDead;
             }
             if (cell[k] != kDead) mn = min(mn, cell[k]);
         }
@@ -1493,18 +1380,10 @@ __global__ void __launch_bounds__(256) k_sort_scatter(Dev d, int W)
                 atomicOr(d.err, (int)E_CAP_PART);
                 continue;
             }
-            if constexpr (!F64) {
-                d.cell[nb][o] = cell[k];
-                d.off[nb][o] = d.off[b][i];
-                d.fvx[nb][o] = d.fvx[b][i];
-                d.fvy[nb][o] = d.fvy[b][i];
-                d.fvz[nb][o] = d.fvz[b][i];
-            } else {
-                d.x[nb][o] = d.x[b][i];
-                d.dvx[nb][o] = d.dvx[b][i];
-                d.dvy[nb][o] = d.dvy[b][i];
-                d.dvz[nb][o] = d.dvz[b][i];
-            }
+            d.x[nb][o] = d.x[b][i];
+            d.dvx[nb][o] = d.dvx[b][i];
+            d.dvy[nb][o] = d.dvy[b][i];
+            d.dvz[nb][o] = d.dvz[b][i];
             d.id[nb][o] = d.id[b][i];
         }
         __syncthreads();
@@ -1576,22 +1455,21 @@ __global__ void k_diag(Dev d, int sg, double *out /* [grid][2] */)
         if (_e != hipSuccess) return _e;                        \
     } while (0)
 
-template <bool F64, int STAGES>
+template <int STAGES>
 static hipError_t launch_particles_t(const Dev &d, const Launch &L, hipStream_t s, int hist)
 {
-    const size_t lds = (size_t)(L.window + 1) * 8 + (size_t)L.window * 4;
     switch (L.ppt) {
     case 1:
-        hipLaunchKernelGGL((k_particles<F64, STAGES, 1>), dim3(L.grid), dim3(L.block), lds, s, d, L.window, hist);
+        hipLaunchKernelGGL((k_particles<STAGES, 1>), dim3(L.grid), dim3(L.block), 0, s, d, hist);
         break;
     case 2:
-        hipLaunchKernelGGL((k_particles<F64, STAGES, 2>), dim3(L.grid), dim3(L.block), lds, s, d, L.window, hist);
+        hipLaunchKernelGGL((k_particles<STAGES, 2>), dim3(L.grid), dim3(L.block), 0, s, d, hist);
         break;
     case 8:
-        hipLaunchKernelGGL((k_particles<F64, STAGES, 8>), dim3(L.grid), dim3(L.block), lds, s, d, L.window, hist);
+        hipLaunchKernelGGL((k_particles<STAGES, 8>), dim3(L.grid), dim3(L.block), 0, s, d, hist);
         break;
     default:
-        hipLaunchKernelGGL((k_particles<F64, STAGES, 4>), dim3(L.grid), dim3(L.block), lds, s, d, L.window, hist);
+        hipLaunchKernelGGL((k_particles<STAGES, 4>), dim3(L.grid), dim3(L.block), 0, s, d, hist);
         break;
     }
     LAUNCH_CHECK();
@@ -1607,10 +1485,9 @@ hipError_t launch_particles(const Dev &d, const Launch &L, hipStream_t s, bool f
         LAUNCH_CHECK();
     }
     if (!f64) return launch_pass32(d, L.ppt, L.window, s, stages, hist, d.cap_tot, L.nt != 0);
-#define PIC_CASE(ST)                                                          \
-    case ST:                                                                  \
-        return f64 ? launch_particles_t<true, ST>(d, L, s, hist)              \
-                   : launch_particles_t<false, ST>(d, L, s, hist);
+#define PIC_CASE(ST) \
+    case ST:         \
+        return launch_particles_t<ST>(d, L, s, hist);
     switch (stages) {
         PIC_CASE(ST_PUSH)
         PIC_CASE(ST_COLLIDE)
@@ -1778,10 +1655,7 @@ hipError_t launch_sort(const Dev &d, bool f64, const Launch &L, hipStream_t s)
     hipLaunchKernelGGL(k_segstart, dim3(1), dim3(256), 0, s, d);
     if (!f64) return launch_sort32_scatter(d, L.sort_ppt, L.window, s, d.cap_tot, L.sort_nt != 0);
     const size_t lds = (size_t)L.window * 4;
-    if (f64)
-        hipLaunchKernelGGL((k_sort_scatter<true, 4>), dim3(L.grid), dim3(L.block), lds, s, d, L.window);
-    else
-        hipLaunchKernelGGL((k_sort_scatter<false, 4>), dim3(L.grid), dim3(L.block), lds, s, d, L.window);
+    hipLaunchKernelGGL((k_sort_scatter<4>), dim3(L.grid), dim3(L.block), lds, s, d, L.window);
     LAUNCH_CHECK();
     return hipSuccess;
 }

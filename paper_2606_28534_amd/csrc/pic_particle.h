@@ -293,41 +293,9 @@ __device__ __forceinline__ int p_collide(const EnsC &e, const SegC &S, int s, do
 }
 
 // =======================================================================================
-// Deposit machinery (FP32 form): a wave-level segmented reduction by cell, then one LDS
-// atomic per distinct cell and wave, then one HBM atomic per window node at flush.
+// Deposit helpers of the FP32 form: the 2^-24 fixed-point share of the right node, and the
+// direct HBM deposit of one particle.
 // =======================================================================================
-__device__ __forceinline__ void wave_window_deposit(int key, uint32_t fq, bool depo, bool hist,
-                                                    unsigned long long *sQ, uint32_t *sH)
-{
-    const int lane = lane_id();
-    unsigned long long act = __ballot(key >= 0);
-    int it = 0;
-    while (act != 0ull && it < 8) {
-        const int leader = __ffsll((long long)act) - 1;
-        const int k = __shfl(key, leader);
-        const bool mine = (key == k) && ((act >> lane) & 1ull);
-        const unsigned long long m = __ballot(mine);
-        const uint32_t S = wave_sum_u32(mine ? fq : 0u);
-        if (lane == leader) {
-            const uint32_t c = (uint32_t)__popcll(m);
-            if (depo) {
-                atomicAdd(&sQ[k], (unsigned long long)c * 16777216ull - (unsigned long long)S);
-                atomicAdd(&sQ[k + 1], (unsigned long long)S);
-            }
-            if (hist) atomicAdd(&sH[k], c);
-        }
-        act &= ~m;
-        ++it;
-    }
-    if ((act >> lane) & 1ull) {
-        if (depo) {
-            atomicAdd(&sQ[key], 16777216ull - (unsigned long long)fq);
-            atomicAdd(&sQ[key + 1], (unsigned long long)fq);
-        }
-        if (hist) atomicAdd(&sH[key], 1u);
-    }
-}
-
 __device__ __forceinline__ uint32_t fixed_share(float off)
 {
     return (uint32_t)__float2uint_rn(off * 16777216.0f);

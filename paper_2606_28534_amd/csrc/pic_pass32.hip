@@ -6,10 +6,10 @@
 // sorted by cell every K steps, a thread's slots almost always sit in one cell: the thread
 // merges them into runs of equal cell before touching shared memory, so the cloud-in-cell
 // deposit costs one LDS atomic pair per run and one HBM atomic per window node and block.
-// Tiles are mapped to blocks XCD-major: blocks are dispatched round-robin over the 8 XCDs,
-// so block b takes tile (b % 8) * (G / 8) + b / 8 and each XCD streams one contiguous
-// eighth of the slots (and, sorted, of the cells), keeping its L2 share of the gather table
-// and of the deposit nodes local.
+// The window spans the tile's own cells (pre-push, plus a margin for the step's motion), up
+// to the launch's maximum: a sorted tile clears and flushes a few nodes, a tile of freshly
+// appended particles spread over many cells still deposits through LDS.
+// Block b takes tile b (see tile_of_block for why not an XCD-major order).
 #include "pic_device.h"
 #include "pic_kernels.h"
 #include "pic_particle.h"
@@ -80,6 +80,9 @@ __device__ __forceinline__ void vstore(T *p, const T (&v)[PPT])
     }
 }
 
+// Cells a particle may move in one step and still deposit through the tile's window.
+constexpr int kWinMargin = 2;
+
 // One run of equal cells into the LDS window (or straight to HBM outside it).
 __device__ __forceinline__ void emit_run(const Dev &d, const SegC &S, int s, int cell, uint32_t cnt,
                                          uint32_t sum, int wbase, int W, bool depo, bool hist,
@@ -119,11 +122,11 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
 
     extern __shared__ unsigned long long s_dyn[];
     unsigned long long *sQ = s_dyn;                // [W + 1]
-    uint32_t *sH = (uint32_t *)(s_dyn + (W + 1));  // [W]
+    uint32_t *sH = (uint32_t *)(s_dyn + (W + 1));  // [W], allocated when the histogram is on
     __shared__ unsigned long long s_v2;
     __shared__ uint32_t s_c[C_NCNT];
     __shared__ double s_ke[2];
-    __shared__ int s_c0;
+    __shared__ int s_wmn[4], s_wmx[4];
     __shared__ uint32_t s_nc;
     __shared__ uint4 s_rec[COLL ? 2 * kRecLds : 1];
 
@@ -197,22 +200,44 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
     }
 
     if (WIN) {
-        for (int i = tid; i <= W; i += 256) {
-            sQ[i] = 0ull;
-            if (i < W) sH[i] = 0u;
+        // the tile's live cells before the push, per wave
+        int mn = INT32_MAX, mx = -1;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            if (cell[k] != kDead) {
+                mn = min(mn, cell[k]);
+                mx = max(mx, cell[k]);
+            }
+        }
+        mn = wave_min_i32(mn);
+        mx = wave_max_i32(mx);
+        if (lane_id() == 0) {
+            s_wmn[tid / kWave] = mn;
+            s_wmx[tid / kWave] = mx;
         }
     }
     if (tid < C_NCNT) s_c[tid] = 0u;
     if (tid < 2) s_ke[tid] = 0.0;
     if (tid == 0) {
         s_v2 = 0ull;
-        s_c0 = cell[0];
         s_nc = 0u;
     }
     __syncthreads();
-    // deposit window [wbase, wbase + W) around the tile's first cell (pre-push)
-    const int c0 = s_c0;
-    const int wbase = (c0 == kDead) ? 0 : max(c0 - W / 4, 0);
+    // deposit window: cells [wbase, wbase + Wt) and nodes [wbase, wbase + Wt], covering the
+    // tile's cells and kWinMargin more on each side, at most W cells
+    int wbase = 0, Wt = 0;
+    if (WIN) {
+        const int mn = min(min(s_wmn[0], s_wmn[1]), min(s_wmn[2], s_wmn[3]));
+        const int mx = max(max(s_wmx[0], s_wmx[1]), max(s_wmx[2], s_wmx[3]));
+        if (mx >= 0) {
+            wbase = max(mn - kWinMargin, 0);
+            Wt = min(mx + kWinMargin + 1 - wbase, W);
+            for (int i = tid; i <= Wt; i += 256) {
+                sQ[i] = 0ull;
+                if (hist && i < Wt) sH[i] = 0u;
+            }
+        }
+    }
 
     uint32_t npush = 0;
     uint32_t cchg = 0;  // bit k: particle k's cell changed in the push (or it died)
@@ -365,13 +390,14 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
 
     // deposit / histogram by runs of equal cell
     if (WIN) {
+        __syncthreads();  // the window is cleared
         int rk = kDead;
         uint32_t rc = 0, rs = 0;
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             const bool alive = cell[k] != kDead;
             if (alive && cell[k] != rk) {
-                if (rk != kDead) emit_run(d, S, s, rk, rc, rs, wbase, W, DEPO, hist, sQ, sH);
+                if (rk != kDead) emit_run(d, S, s, rk, rc, rs, wbase, Wt, DEPO, hist, sQ, sH);
                 rk = cell[k];
                 rc = 0;
                 rs = 0;
@@ -379,7 +405,7 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
             rc += alive ? 1u : 0u;
             if (DEPO) rs += alive ? fixed_share(off[k]) : 0u;
         }
-        if (rk != kDead) emit_run(d, S, s, rk, rc, rs, wbase, W, DEPO, hist, sQ, sH);
+        if (rk != kDead) emit_run(d, S, s, rk, rc, rs, wbase, Wt, DEPO, hist, sQ, sH);
     }
 
     // block tallies
@@ -395,7 +421,7 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
     if (WIN) {
         const int nn = S.periodic ? S.ncells : S.ncells + 1;
         unsigned long long *Q = d.Qi + (int64_t)s * d.nodes_tot + S.gbase;
-        for (int i = tid; i <= W; i += 256) {
+        for (int i = tid; Wt > 0 && i <= Wt; i += 256) {
             if (DEPO) {
                 const unsigned long long v = sQ[i];
                 if (v) {
@@ -404,7 +430,7 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
                     if (node < nn) atomicAdd(Q + node, v);
                 }
             }
-            if (hist && i < W) {
+            if (hist && i < Wt) {
                 const uint32_t c = sH[i];
                 const int cl = wbase + i;
                 if (c && cl < S.ncells) atomicAdd(d.cellcnt + S.cbase + cl, c);
@@ -599,7 +625,7 @@ __global__ void __launch_bounds__(256) k_sort32(Dev d, int W, int64_t T)
     constexpr int TILE = 256 * PPT;
     extern __shared__ unsigned long long s_dyn[];
     uint32_t *sCnt = (uint32_t *)s_dyn;  // [W]
-    __shared__ int s_min;
+    __shared__ int s_wmn[4], s_wmx[4];
     const int64_t t = tile_of_block();
     if (t >= T) return;
     const int64_t first = t * TILE;
@@ -631,17 +657,27 @@ __global__ void __launch_bounds__(256) k_sort32(Dev d, int W, int64_t T)
             id[k] = ld_nt<NT>(iid + i);
         }
     }
-    int mn = INT32_MAX;
+    // the counting window spans the tile's live cells, at most W of them
+    int mn = INT32_MAX, mx = -1;
 #pragma unroll
-    for (int k = 0; k < PPT; ++k)
-        if (cell[k] != kDead) mn = min(mn, cell[k]);
+    for (int k = 0; k < PPT; ++k) {
+        if (cell[k] != kDead) {
+            mn = min(mn, cell[k]);
+            mx = max(mx, cell[k]);
+        }
+    }
     mn = wave_min_i32(mn);
-    if (tid == 0) s_min = INT32_MAX;
-    for (int i = tid; i < W; i += 256) sCnt[i] = 0u;
+    mx = wave_max_i32(mx);
+    if (lane == 0) {
+        s_wmn[tid / kWave] = mn;
+        s_wmx[tid / kWave] = mx;
+    }
     __syncthreads();
-    if (lane == 0 && mn != INT32_MAX) atomicMin(&s_min, mn);
+    const int base = min(min(s_wmn[0], s_wmn[1]), min(s_wmn[2], s_wmn[3]));
+    const int top = max(max(s_wmx[0], s_wmx[1]), max(s_wmx[2], s_wmx[3]));
+    const int Wt = top >= 0 ? min(top - base + 1, W) : 0;
+    for (int i = tid; i < Wt; i += 256) sCnt[i] = 0u;
     __syncthreads();
-    const int base = s_min;
     uint32_t *__restrict__ cursor = d.cursor + S.cbase;
     // rank: in-window -> rank inside the tile's run of that cell; outside -> final position
     uint32_t pos[PPT];
@@ -649,7 +685,7 @@ __global__ void __launch_bounds__(256) k_sort32(Dev d, int W, int64_t T)
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const int rel = (cell[k] != kDead) ? cell[k] - base : -1;
-        const int key = (rel >= 0 && rel < W) ? rel : -1;
+        const int key = (rel >= 0 && rel < Wt) ? rel : -1;
         inwin[k] = key >= 0;
         unsigned long long act = __ballot(key >= 0);
         int it = 0;
@@ -669,7 +705,7 @@ __global__ void __launch_bounds__(256) k_sort32(Dev d, int W, int64_t T)
         if (cell[k] != kDead && key < 0) pos[k] = atomicAdd(cursor + cell[k], 1u);
     }
     __syncthreads();
-    for (int i = tid; i < W; i += 256) {
+    for (int i = tid; i < Wt; i += 256) {
         const uint32_t c = sCnt[i];
         if (c) sCnt[i] = atomicAdd(cursor + base + i, c);
     }
@@ -719,7 +755,8 @@ hipError_t launch_pass32_stages(const Dev &d, int ppt, int W, hipStream_t s, int
 template <int STAGES, bool NT = false>
 static hipError_t launch_pass32_t(const Dev &d, int ppt, int W, hipStream_t s, int hist, int64_t cap_tot)
 {
-    const size_t lds = (size_t)(W + 1) * 8 + (size_t)W * 4;
+    const bool with_hist = (STAGES & PS_HIST) || hist;
+    const size_t lds = (size_t)(W + 1) * 8 + (with_hist ? (size_t)W * 4 : 0);
     if (ppt == 4) {
         const int64_t T = cap_tot / (256 * 4);
         const int64_t G = (T + 7) / 8 * 8;

@@ -64,6 +64,15 @@ def test_bad_configs_rejected(lib):
     cfg, keep = P.make_config(work)
     cfg.n_ensembles = 0
     assert L.pic_query_workspace(C.byref(cfg), C.byref(n)) == P.PIC_EINVAL
+    # launch-shape fields out of range: LDS window span and FP64 block size
+    for field, value in (("window", 8), ("window", 8192), ("block", 512), ("block", 96)):
+        cfg, keep = P.make_config(work)
+        setattr(cfg, field, value)
+        assert L.pic_query_workspace(C.byref(cfg), C.byref(n)) == P.PIC_EINVAL, (field, value)
+    for field, value in (("window", 16), ("window", 4096), ("block", 128)):
+        cfg, keep = P.make_config(work)
+        setattr(cfg, field, value)
+        assert L.pic_query_workspace(C.byref(cfg), C.byref(n)) == 0, (field, value)
     # init refuses a workspace that is too small before touching the GPU
     cfg, keep = P.make_config(work)
     h = C.c_void_p()
