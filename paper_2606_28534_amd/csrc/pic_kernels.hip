@@ -517,7 +517,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve1(Dev d, int nchunks, in
     __shared__ double s_buf[8];
     const int64_t k = blockIdx.x;
     const int ei = chunk_ens(d, k);
-    const EnsC &e = d.ens[ei];
+    const EnsC e = d.ens[ei];
     const int64_t N = e.ncells, nn = e.nnodes;
     const int64_t a = (k - e.chunk0) * kChunk;
     const int64_t j0 = a + (int64_t)threadIdx.x * kNodesPerThread;
@@ -633,7 +633,7 @@ __device__ void solve2_body(const Dev &d, int zero_q)
     __shared__ double s_C0, s_F0, s_Eh, s_bg, s_Ctot;
     const int64_t k = blockIdx.x;
     const int ei = chunk_ens(d, k);
-    const EnsC &e = d.ens[ei];
+    const EnsC e = d.ens[ei];
     const int64_t N = e.ncells, nn = e.nnodes;
     const int64_t a = (k - e.chunk0) * kChunk;
     const double dx = e.dx, ce = e.dx / e.eps0;
@@ -861,7 +861,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_phi_shift(Dev d)
 {
     const int64_t k = blockIdx.x;
     const int ei = chunk_ens(d, k);
-    const EnsC &e = d.ens[ei];
+    const EnsC e = d.ens[ei];
     __shared__ double s_mean;
     if (threadIdx.x < kWave) {
         double ps = 0.0;
@@ -880,7 +880,7 @@ __global__ void k_ecell(Dev d)
 {
     const int64_t k = blockIdx.x;
     const int ei = chunk_ens(d, k);
-    const EnsC &e = d.ens[ei];
+    const EnsC e = d.ens[ei];
     const int64_t a = (k - e.chunk0) * kChunk;
     for (int64_t j = a + threadIdx.x; j < min(a + kChunk, e.ncells); j += blockDim.x) {
         const int64_t j1 = (e.periodic && j + 1 == e.ncells) ? 0 : j + 1;
@@ -894,7 +894,7 @@ __global__ void k_ecell(Dev d)
 __global__ void __launch_bounds__(1024) k_field_energy(Dev d)
 {
     __shared__ double s_buf[16];
-    const EnsC &e = d.ens[blockIdx.x];  // one block per ensemble
+    const EnsC e = d.ens[blockIdx.x];  // one block per ensemble
     double f = 0.0;
     for (int64_t j = threadIdx.x; j < e.nnodes; j += blockDim.x) {
         const double E = d.E[e.gbase + j];

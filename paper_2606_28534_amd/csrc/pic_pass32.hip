@@ -526,8 +526,9 @@ __global__ void __launch_bounds__(256) k_cand32(Dev d, int tile, int64_t T, int 
             const uint4 r0 = r[0], r1 = r[1];
             const int64_t i = (int64_t)r0.x;
             sg = (int)r1.w;
-            const SegC &S = d.seg[sg];
-            const EnsC &e = d.ens[S.ens];
+            // copies: the stores below cannot alias them, so no field is read twice
+            const SegC S = d.seg[sg];
+            const EnsC e = d.ens[S.ens];
             p.cell = (int)r0.y;
             p.off = __uint_as_float(r0.z);
             p.id = r0.w;
