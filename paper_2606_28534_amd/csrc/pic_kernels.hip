@@ -378,23 +378,6 @@ __global__ void k_vmax(Dev d)
 // at bounded walls.  Periodic runs add the uniform background that cancels the deposited
 // charge and shift phi to zero mean afterwards.
 // =======================================================================================
-template <bool F64>
-__device__ __forceinline__ double node_charge(const Dev &d, const EnsC &e, int64_t j)
-{
-    double q = 0.0;
-    for (int s = 0; s < e.nspecies; ++s) {
-        double Q;
-        if constexpr (!F64) {
-            const long long qi = (long long)d.Qi[(int64_t)s * d.nodes_tot + e.gbase + j];
-            Q = (double)qi * (1.0 / kFix);
-        } else {
-            Q = d.Qd[(int64_t)s * d.nodes_tot + e.gbase + j];
-        }
-        q += e.qw[s] * Q;
-    }
-    return q;
-}
-
 __device__ __forceinline__ double node_vol(const EnsC &e, int64_t j)
 {
     if (!e.periodic && (j == 0 || j == e.ncells)) return 0.5 * e.dx;
@@ -427,10 +410,46 @@ __device__ __forceinline__ int64_t smooth_fold(const EnsC &e, int64_t m)
     return m;
 }
 
-template <bool F64>
-__device__ __forceinline__ double node_rho_raw(const Dev &d, const EnsC &e, int64_t j)
+// One species' deposited charge at NQ nodes (offsets into the node arrays), all loads
+// issued before the first is used.
+template <bool F64, int NQ>
+__device__ __forceinline__ void node_q_row(const Dev &d, int64_t row, const int64_t (&at)[NQ],
+                                           double (&Q)[NQ])
 {
-    return node_charge<F64>(d, e, j) / node_vol(e, j);
+    if constexpr (!F64) {
+        unsigned long long raw[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) raw[q] = d.Qi[row + at[q]];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) Q[q] = (double)(long long)raw[q] * (1.0 / kFix);
+    } else {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) Q[q] = d.Qd[row + at[q]];
+    }
+}
+
+// Charge density sum_s q_s w_s Q_s(j) / vol(j) at NQ nodes per thread (entries with ok[q]
+// false give 0).  The loads are unconditional (node 0 stands in for unused entries), so the
+// thread waits for memory once instead of once per node and species.
+template <bool F64, int NQ>
+__device__ __forceinline__ void node_rho_raw(const Dev &d, const EnsC &e, const int64_t (&j)[NQ],
+                                             const bool (&ok)[NQ], double (&r)[NQ])
+{
+    static_assert(sizeof(e.qw) / sizeof(e.qw[0]) == 2, "at most two charged species");
+    int64_t at[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) at[q] = e.gbase + (ok[q] ? j[q] : 0);
+    double Q0[NQ], Q1[NQ];
+    node_q_row<F64, NQ>(d, 0, at, Q0);
+    const bool two = e.nspecies > 1;
+    if (two) node_q_row<F64, NQ>(d, d.nodes_tot, at, Q1);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double c = 0.0;
+        c += e.qw[0] * Q0[q];
+        if (two) c += e.qw[1] * Q1[q];
+        r[q] = ok[q] ? c / node_vol(e, j[q]) : 0.0;
+    }
 }
 
 // Block-wide inclusive scan of one double per thread (256 threads).
@@ -529,30 +548,54 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve1(Dev d, int nchunks, in
     // onto the grid, staged in LDS with coalesced loads; s_raw[i] is node a - p + i
     __shared__ double s_raw[kChunk + 2 * kMaxSmooth];
     const int p = e.smooth;
+    double rq[kNodesPerThread];
     if (p > 0) {
-        for (int i = threadIdx.x; i < kChunk + 2 * p; i += blockDim.x) {
+        constexpr int kStage = (kChunk + 2 * kMaxSmooth + kSolveThreads - 1) / kSolveThreads;
+        int64_t jm[kStage];
+        bool ok[kStage];
+        double rr[kStage];
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int i = threadIdx.x + u * kSolveThreads;
             const int64_t m = a - p + i;
-            s_raw[i] = (m <= nn - 1 + p) ? node_rho_raw<F64>(d, e, smooth_fold(e, m)) : 0.0;
+            ok[u] = i < kChunk + 2 * p && m <= nn - 1 + p;
+            jm[u] = ok[u] ? smooth_fold(e, m) : 0;
+        }
+        node_rho_raw<F64, kStage>(d, e, jm, ok, rr);
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int i = threadIdx.x + u * kSolveThreads;
+            if (i < kChunk + 2 * p) s_raw[i] = rr[u];
         }
         __syncthreads();
+        const double pscale = 1.0 / (double)(1 << (2 * p));
+#pragma unroll
+        for (int q = 0; q < kNodesPerThread; ++q) {
+            double r = 0.0;
+            double c = 1.0;  // C(2p, k), exact in binary64
+            const int i0 = (int)(j0 + q - a);
+            for (int k = 0; k <= 2 * p; ++k) {
+                r += c * s_raw[i0 + k];
+                c = c * (double)(2 * p - k) / (double)(k + 1);
+            }
+            rq[q] = r * pscale;
+        }
+    } else {
+        int64_t jq[kNodesPerThread];
+        bool ok[kNodesPerThread];
+#pragma unroll
+        for (int q = 0; q < kNodesPerThread; ++q) {
+            jq[q] = j0 + q;
+            ok[q] = jq[q] < nn;
+        }
+        node_rho_raw<F64, kNodesPerThread>(d, e, jq, ok, rq);
     }
-    const double pscale = 1.0 / (double)(1 << (2 * p));
 #pragma unroll
     for (int q = 0; q < kNodesPerThread; ++q) {
         const int64_t j = j0 + q;
         double r = 0.0;
         if (j < nn) {
-            if (p == 0) {
-                r = node_rho_raw<F64>(d, e, j);
-            } else {
-                double c = 1.0;  // C(2p, k), exact in binary64
-                const int i0 = (int)(j - a);
-                for (int k = 0; k <= 2 * p; ++k) {
-                    r += c * s_raw[i0 + k];
-                    c = c * (double)(2 * p - k) / (double)(k + 1);
-                }
-                r *= pscale;
-            }
+            r = rq[q];
             d.rho[e.gbase + j] = r;
             totq += r * node_vol(e, j);
         }
@@ -704,12 +747,19 @@ __device__ void solve2_body(const Dev &d, int zero_q)
     // local inclusive prefix of interior rho' (with background) -> C_j
     double rl[kNodesPerThread + 1];
     double loc = 0.0;
+    double rv[kNodesPerThread];  // all loads before the first store
+#pragma unroll
+    for (int q = 0; q < kNodesPerThread; ++q) {
+        const bool in = j0 + q < nn;
+        const double v = d.rho[e.gbase + (in ? j0 + q : 0)];
+        rv[q] = in ? v : 0.0;
+    }
 #pragma unroll
     for (int q = 0; q < kNodesPerThread; ++q) {
         const int64_t j = j0 + q;
         double r = 0.0;
         if (j < nn) {
-            const double rj = d.rho[e.gbase + j] + bg;
+            const double rj = rv[q] + bg;
             if (e.periodic) d.rho[e.gbase + j] = rj;  // report rho with the background
             if (j >= 1 && j <= N - 1) r = rj;
         }
