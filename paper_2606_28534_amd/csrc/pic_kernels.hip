@@ -689,11 +689,16 @@ __device__ void solve2_body(const Dev &d, int zero_q)
         const int64_t c0 = (int64_t)threadIdx.x * R, c1 = min(c0 + R, nc);
         // floating walls (R22): the particles absorbed so far at the left wall, per
         // species, from the exact striped wall counts (sums < 2^53: exact in binary64)
+        // (species loops run over the two array entries with constant indices, so that the
+        // local copy of the ensemble stays in registers)
         double nabs[2] = {0.0, 0.0};
         if (e.floating)
-            for (int st = threadIdx.x; st < kCntStripes; st += blockDim.x)
-                for (int s = 0; s < e.nspecies; ++s)
-                    nabs[s] += (double)d.cnt[((int64_t)st * d.nseg + e.seg[s]) * C_NCNT + C_WALL_L];
+            for (int st = threadIdx.x; st < kCntStripes; st += blockDim.x) {
+#pragma unroll
+                for (int s = 0; s < 2; ++s)
+                    if (s < e.nspecies)
+                        nabs[s] += (double)d.cnt[((int64_t)st * d.nseg + e.seg[s]) * C_NCNT + C_WALL_L];
+            }
         double tq = 0.0;
         for (int64_t c = c0; c < c1; ++c) tq += d.agg[(e.chunk0 + c) * A_NAGG + A_TOTQ];
         const double tqs = block_sum(tq, s_buf);
@@ -731,7 +736,9 @@ __device__ void solve2_body(const Dev &d, int zero_q)
         // charge absorbed there, q w per particle) and the half cell in front of it;
         // otherwise phi_N = 0 (or periodicity) fixes it.
         double sigL = 0.0;
-        for (int s = 0; s < e.nspecies; ++s) sigL += e.qw[s] * st[2 + s];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+            if (s < e.nspecies) sigL += e.qw[s] * st[2 + s];
         if (threadIdx.x == 0) {
             s_bg = bg;
             s_Ctot = Ctot;
@@ -1123,23 +1130,23 @@ __device__ __forceinline__ void stripe_prefix(const BirthBuf &bb, int64_t cap, u
 // words are read as independent 16-byte loads four at a time.
 __device__ __forceinline__ uint32_t rank_in_group(const uint32_t *group, uint32_t pid)
 {
+    static_assert(kGroupWords % 64 == 0, "whole batches of 64 words per group");
     const int wp = (int)((pid % kGroupIds) >> 5);  // words wholly below pid
     const uint4 *v = (const uint4 *)group;
-    uint32_t r = 0;
-    int q = 0;
-    for (; 4 * (q + 4) <= wp; q += 4) {
-        uint4 a[4];
+    uint32_t r = __popc(group[wp] & ((1u << (pid & 31)) - 1u));
+    // batches of 64 words, each batch's sixteen 16-byte loads in flight at once; words at
+    // or above wp are masked
+    for (int w0 = 0; w0 < wp; w0 += 64) {
+        uint4 a[16];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) a[u] = v[q + u];
+        for (int u = 0; u < 16; ++u) a[u] = v[w0 / 4 + u];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) r += __popc(a[u].x) + __popc(a[u].y) + __popc(a[u].z) + __popc(a[u].w);
+        for (int u = 0; u < 16; ++u) {
+            const int w = w0 + 4 * u;
+            r += (w < wp ? __popc(a[u].x) : 0u) + (w + 1 < wp ? __popc(a[u].y) : 0u) +
+                 (w + 2 < wp ? __popc(a[u].z) : 0u) + (w + 3 < wp ? __popc(a[u].w) : 0u);
+        }
     }
-    for (; 4 * (q + 1) <= wp; ++q) {
-        const uint4 a = v[q];
-        r += __popc(a.x) + __popc(a.y) + __popc(a.z) + __popc(a.w);
-    }
-    for (int w = 4 * q; w < wp; ++w) r += __popc(group[w]);
-    r += __popc(group[wp] & ((1u << (pid & 31)) - 1u));
     return r;
 }
 
@@ -1215,15 +1222,18 @@ __device__ void birth_place_body(const Dev &d, int deferred, int advance, int bi
         int st;
         uint32_t idx;
         birth_locate(d, k, st, idx, s_pre);
-        const Birth &B = bb.births[(int64_t)st * d.birth_stripe_cap + idx];
-        const EnsC &e = d.ens[B.ens];
+        // copies: the particle stores below cannot alias them, so nothing is read twice
+        const Birth B = bb.births[(int64_t)st * d.birth_stripe_cap + idx];
+        const EnsC e = d.ens[B.ens];
         const uint32_t pid = B.pid;
         const int64_t g = pid / kGroupIds;
         const uint32_t r = d.gpre[e.grp_base + g] - d.gpre[e.grp_base] +
                            rank_in_group(bb.bitmap + e.bm_base + g * kGroupWords, pid);
-        for (int s = 0; s < e.nspecies; ++s) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            if (s >= e.nspecies) break;
             const int sg = e.seg[s];
-            const SegC &S = d.seg[sg];
+            const SegC S = d.seg[sg];
             const int64_t slot = d.n_slots[sg] + r;
             if (slot >= S.cap) {
                 atomicOr(d.err, (int)E_CAP_PART);
@@ -1234,18 +1244,20 @@ __device__ void birth_place_body(const Dev &d, int deferred, int advance, int bi
                 continue;
             }
             const int64_t i = S.base + slot;
-            const double *v = (s == 0) ? B.ve : B.vi;
+            const double v0 = s == 0 ? B.ve[0] : B.vi[0];
+            const double v1 = s == 0 ? B.ve[1] : B.vi[1];
+            const double v2 = s == 0 ? B.ve[2] : B.vi[2];
             if constexpr (!F64) {
                 d.cell[b][i] = B.cell;
                 d.off[b][i] = B.off;
-                d.fvx[b][i] = (float)v[0];
-                d.fvy[b][i] = (float)v[1];
-                d.fvz[b][i] = (float)v[2];
+                d.fvx[b][i] = (float)v0;
+                d.fvy[b][i] = (float)v1;
+                d.fvz[b][i] = (float)v2;
             } else {
                 d.x[b][i] = B.x;
-                d.dvx[b][i] = v[0];
-                d.dvy[b][i] = v[1];
-                d.dvz[b][i] = v[2];
+                d.dvx[b][i] = v0;
+                d.dvy[b][i] = v1;
+                d.dvz[b][i] = v2;
             }
             d.id[b][i] = d.next_id[sg] + r;
         }
