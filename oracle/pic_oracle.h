@@ -15,6 +15,55 @@
  * with every unstated choice fixed by a written reading (the R-tags in the comments).
  *
  * Units are normalised: eps0 = e = m_e = n0 = T_e = 1, so omega_pe = v_th,e = lambda_D = 1.
+ *
+ * Readings.  Where the paper leaves a choice open, the sources follow these readings and
+ * cite them by tag:
+ *   R1  normalised units (eps0 = e = m_e = n0 = T_e = 1), dx = lambda_D / 2, omega_pe dt = 0.1.
+ *   R2  state (x^n, v^{n-1/2}, Q^n); a step is solve, gather + Boris push, walls,
+ *       null-collision MC, births, deposit of Q^{n+1}, and a sort every K steps; v^{-1/2}
+ *       is loaded directly.
+ *   R3  bounded walls are grounded (phi_0 = phi_N = 0); absorbed charge is tallied only.
+ *   R4  periodic grids: a uniform background cancels the deposited charge, phi_0 = 0, then
+ *       phi is shifted to zero mean.
+ *   R5  the three-point Poisson stencil; the GPU solves it exactly with two prefix sums.
+ *   R6  node E is the centred difference, with the half-cell Gauss law at bounded walls;
+ *       E_ext is added at the gather.
+ *   R7  sheath workloads: B = 2 (cos 80 deg, sin 80 deg, 0), i.e. |q_e| B / m_e = 2 omega_pe.
+ *   R8  a particle is absorbed iff x < 0 or x >= L (cell < 0 or cell >= N in the FP32 form);
+ *       count, charge and kinetic energy are tallied per wall and species.
+ *   R9  channels: electron elastic (n_g sigma = 0.01), electron ionisation (0.005 above
+ *       eps_iz = 1.576), ion charge exchange (1.0); T_n = T_i, m_n = m_i = 73440.
+ *   R10 nu_k = n_g sigma_k |v| with the lab-frame speed.
+ *   R11 null-collision bound nu_max = n_g sigma_T (v_max + |q/m| dt (max|E| + |E_ext|))
+ *       (1 + 2^-16) from the speeds at the start of the step, so it holds before the push.
+ *   R12 candidate iff R1 < P_null (Philox block 0 of the step); channel = first k with
+ *       R2 nu_max < sum_{i<=k} nu_i; compared in FP64 without fused multiply-add.
+ *   R13 lab-frame isotropic scattering: elastic energy loss 2 m_e / m_n (1 - cos theta);
+ *       ionisation splits the energy above threshold; new and exchanged ions at T_n.
+ *   R14 births are ranked by parent id and take ids next_id + rank, after the slots in use.
+ *   R15 deposit shares (2^24 - f_q, f_q), f_q = rint(f 2^24), summed in int64.
+ *   R16 sort every K = 20 steps (10 for the 1e9-particle workload); K = 0 still compacts
+ *       every 20 steps.
+ *   R17 Philox4x32-10, key (seed, species), counter (id, tag, block, 0);
+ *       u = ((r >> 9) + 1/2) 2^-23; normals by Box-Muller.
+ *   R18 batched ensembles: sizes, ppc and temperatures come from the input generator;
+ *       ensemble seed = index + 1.
+ *   R19 quiet start x0 = (p + 1/2) L / P displaced by (A/k) sin(k x0), A = 0.01, cold
+ *       electrons on a fixed background.
+ *   R20 adjoint objective W = 1/2 eps0 dx sum_j E_j^2 after a collisionless periodic
+ *       window, differentiated with respect to every initial v_x and E_ext (the exact
+ *       transpose of the FP32 forward with cells held fixed).
+ *   R21 adjoint window: the Langmuir workload, 200 steps, a checkpoint every 20.
+ *   R22 floating walls keep the charge absorbed; E_{1/2} = (sigma_L + rho_0 V_0) / eps0
+ *       with phi_0 = 0, and the right wall floats.
+ *   R23 smoothing: p passes of the 1-2-1 filter on rho before the solve (periodic grids
+ *       wrap, bounded grids mirror at the walls).
+ *   R24 recycling: an absorbed ion returns from its wall as a neutral with the ion's id and
+ *       a wall-flux Maxwellian velocity; neutrals stream freely and leave at the walls.
+ *   R25 volumetric source: src_pairs electron-ion pairs per step, both at one x, stratified
+ *       over [0, src_frac L); their ids precede the step's births.
+ *   R26 relative-speed charge exchange: the rate uses the speed relative to a sampled
+ *       neutral, and an exchanged ion takes that neutral's velocity.
  */
 #ifndef PIC_ORACLE_H
 #define PIC_ORACLE_H

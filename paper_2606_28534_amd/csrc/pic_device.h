@@ -251,7 +251,8 @@ __device__ __forceinline__ int wave_max_i32(int v)
 __device__ __forceinline__ unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
 
 // |v|^2 in FP64 from the stored components, summed left to right with no fused
-// multiply-add, so both precisions and the CPU oracle take identical collision decisions.
+// multiply-add, so the collision decision is a function of the stored values alone: the
+// same in both precisions and in any implementation that rounds this way.
 __device__ __forceinline__ double speed2_rn(double a, double b, double c)
 {
     return __dadd_rn(__dadd_rn(__dmul_rn(a, a), __dmul_rn(b, b)), __dmul_rn(c, c));

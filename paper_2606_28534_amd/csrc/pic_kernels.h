@@ -8,13 +8,13 @@ namespace pic {
 
 // Launch shape of the particle kernels.
 struct Launch {
-    int block;   // threads per block (multiple of 64, <= 256)
-    int ppt;     // particles per thread per tile (1, 2, 4, 8)
-    int grid;    // persistent blocks (multiple of 8 for the XCD-aware mapping)
-    int window;  // LDS deposit / sort window in cells
+    int block;   // threads per block of the FP64 kernels (64, 128 or 256)
+    int ppt;     // particles per thread per tile (FP32 pass: 4 or 8)
+    int grid;    // persistent blocks of the FP64 kernels (multiple of 8 for the XCD-aware mapping)
+    int window;  // widest LDS window span, in cells, of the FP32 pass and of the sorts
     int sort_ppt;  // particles per thread of the FP32 sort scatter
     int nt;        // fused FP32 pass: non-temporal particle loads and stores
-    int sort_nt;   // FP32 sort scatter: non-temporal loads and stores
+    int sort_nt;   // FP32 sort scatter: non-temporal loads
 };
 
 enum StageBits : int { SB_PUSH = 1, SB_COLLIDE = 2, SB_DEPOSIT = 4, SB_HIST = 8 };

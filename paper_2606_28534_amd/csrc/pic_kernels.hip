@@ -1,13 +1,13 @@
 // pic_kernels.hip -- gfx950 kernels of the electrostatic 1D3V PIC Monte Carlo step.
 //
-// One particle-pass template covers every particle stage: gather + Boris push + walls,
+// This file holds the field solve, the birth ranking and placement, particle loading,
+// diagnostics, the scans of the sort, and the FP64 (plain x, v) particle pass and sort
+// scatter; the FP32 cell+offset pass, candidates and sort are in pic_pass32.hip.  The FP64
+// pass covers every particle stage with one template: gather + Boris push + walls,
 // null-collision MC, cloud-in-cell deposit and the sort histogram are compile-time stage
-// bits, so the separate-stage verbs and the fused step run the same per-particle code.
-// The pass is HBM-bound (about 44 B of particle traffic per particle and step in the FP32
-// cell+offset form): it streams each segment's slots once, coalesced, with persistent
-// blocks that own contiguous, XCD-local runs of tiles; the deposit goes through a sliding
-// LDS window after a wavefront segmented reduction, so the HBM atomics are per node and
-// per window, not per particle.
+// bits, so its separate-stage verbs and its fused step run the same per-particle code.  It
+// streams each segment's slots once, coalesced, with persistent blocks that own contiguous,
+// XCD-local runs of tiles, and deposits with FP64 atomics.
 #include <type_traits>
 
 #include "pic_device.h"
@@ -17,8 +17,8 @@
 namespace pic {
 
 // =======================================================================================
-// Tile scheduling: live tiles are enumerated over all segments; block b owns a contiguous
-// run of them.  Blocks are dispatched round-robin over the 8 XCDs, so block b is mapped
+// Tile scheduling of the persistent FP64 kernels: live tiles are enumerated over all
+// segments; block b owns a contiguous run of them.  Blocks are dispatched round-robin over the 8 XCDs, so block b is mapped
 // to run (b % 8) * (G / 8) + b / 8: each XCD gets one contiguous eighth of the particles
 // (and of the cells, once sorted), which keeps its L2 working set to its own part of the
 // grid.

@@ -207,8 +207,8 @@ __device__ __forceinline__ void three_normals(uint4 w, T z[3])
     z[2] = r2 * c2;
 }
 
-// Null-collision decision (FP64, no contraction: identical to the CPU oracle for identical
-// inputs) and scattering kinematics (in the particle precision).  Returns the channel
+// Null-collision decision (FP64, no contraction: fixed by the inputs and the rounding, R12)
+// and scattering kinematics (in the particle precision).  Returns the channel
 // (-1 none, 0 elastic, 1 ionisation, 2 CX); on ionisation fills the new pair.  CXREL = false
 // compiles the relative-speed charge exchange (R26) out, which keeps the FP32 candidate
 // kernel's registers (and so its occupancy) to what the other channels need.

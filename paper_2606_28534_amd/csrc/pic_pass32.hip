@@ -457,13 +457,13 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
 }
 
 // =======================================================================================
-// Null-collision candidates of the FP32 pass.  A block takes 16 consecutive tiles; their
-// candidate records (post-push state and slot, written by the pass) are concatenated
+// Null-collision candidates of the FP32 pass.  A block takes kCandTiles consecutive tiles;
+// their candidate records (post-push state and slot, written by the pass) are concatenated
 // through a prefix of the tile counts, one candidate per thread.  Each candidate draws the
-// full Philox block 0 again, picks its channel (the FP64 decision the CPU oracle takes),
-// scatters, writes its velocity back to its slot, and on ionisation appends the new pair.
-// Collision counts and the largest post-collision speed go out once per wave when the
-// wave's candidates share a segment (always, unless the 16 tiles straddle a segment end).
+// full Philox block 0 again, picks its channel (in FP64, the same decision in both
+// precisions), scatters, writes its velocity back to its slot, and on ionisation appends
+// the new pair.  Collision counts and the largest post-collision speed are gathered in LDS
+// per segment and go out once per block and segment.
 // =======================================================================================
 constexpr int kCandTiles = 32;
 
