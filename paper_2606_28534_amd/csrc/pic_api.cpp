@@ -323,6 +323,10 @@ struct pic_ctx {
     Launch L{};
     int64_t host_step = 0;
     int sort_every = 0;  // effective cadence (>= 1)
+    // The histogram of the current cells has been scanned into the sort cursors, so the
+    // next fused FP32 step can sort inside its particle pass.  Any call that moves, adds or
+    // removes particles between steps clears it (that step then sorts the usual way).
+    bool sort_ready = false;
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph = nullptr;
     std::string msg;
@@ -362,38 +366,58 @@ int check_err(pic_ctx *c, hipStream_t s)
     return PIC_OK;
 }
 
-bool is_sort_step(const pic_ctx *c, int64_t step_after) { return step_after % c->sort_every == 0; }
-
-// Enqueue one full step; `sort_now` when the step count after it is a multiple of K.
-hipError_t enqueue_step(pic_ctx *c, hipStream_t s, bool sort_now)
+// Enqueue one full step from step count n; the step sorts when n + 1 is a multiple of K
+// (never with `no_sort`).  The fused FP32 step pipelines the sort (K >= 2): the step before
+// a sort step counts the cells after its push and scans the counts, and the sort step's
+// particle pass writes every particle at its place in cell order (`ready` carries that
+// state between the two steps).  Otherwise the sort step counts and then sorts in kernels
+// of its own.
+hipError_t enqueue_step(pic_ctx *c, hipStream_t s, int64_t n, bool &ready, bool no_sort)
 {
     const Dev &d = c->d;
     const bool f64 = c->P.f64;
     const bool coll = c->cfg.collisions != 0;
+    const int K = c->sort_every;
+    const bool sort_now = !no_sort && (n + 1) % K == 0;
     hipError_t e;
     const bool tm = c->timing && c->ev_used + 2 <= (int64_t)c->ev.size();
     if (c->cfg.fused) {
+        const bool piped = !f64 && K >= 2 && !no_sort;
+        const bool sorting = piped && sort_now && ready;
+        const bool prep = piped && (n + 2) % K == 0;
+        const int hist = (prep || (sort_now && !sorting)) ? 1 : 0;
         // the solve's last block computes the collision bound, so the measurement hook
         // times the particle pass alone
         if ((e = launch_solve(d, f64, c->P.chunks_tot, true, s, false, coll)) != hipSuccess) return e;
         const int stages = coll ? (SB_PUSH | SB_COLLIDE | SB_DEPOSIT) : (SB_PUSH | SB_DEPOSIT);
         if (tm && (e = hipEventRecord(c->ev[c->ev_used], s)) != hipSuccess) return e;
-        if ((e = launch_particles(d, c->L, s, f64, stages, sort_now ? 1 : 0, false)) != hipSuccess) return e;
+        if (sorting)
+            e = launch_pass32_sort(d, c->L.ppt, c->L.window, s, coll, d.cap_tot, c->L.nt != 0);
+        else
+            e = launch_particles(d, c->L, s, f64, stages, hist, false);
+        if (e != hipSuccess) return e;
         if (tm) {
             if ((e = hipEventRecord(c->ev[c->ev_used + 1], s)) != hipSuccess) return e;
             c->ev_used += 2;
         }
-        if (coll && (e = launch_candidates(d, c->L, s, f64, sort_now ? 1 : 0)) != hipSuccess) return e;
+        if (coll && (e = launch_candidates(d, c->L, s, f64, hist)) != hipSuccess) return e;
         if ((e = launch_neutrals(d, s)) != hipSuccess) return e;
-        if ((e = launch_source(d, sort_now ? 1 : 0, s)) != hipSuccess) return e;
+        if ((e = launch_source(d, hist, s)) != hipSuccess) return e;
         if (coll) {
             if ((e = launch_births(d, f64, true, true, s)) != hipSuccess) return e;
         } else if ((e = launch_advance(d, s)) != hipSuccess) {
             return e;
         }
-        if (sort_now && (e = launch_sort(d, f64, c->L, s)) != hipSuccess) return e;
+        if (sort_now && !sorting && (e = launch_sort(d, f64, c->L, s)) != hipSuccess) return e;
+        if (prep && !sort_now) {
+            if ((e = launch_sort_prepare(d, s)) != hipSuccess) return e;
+            ready = true;
+        } else {
+            ready = false;
+        }
         return hipSuccess;
     }
+    ready = false;
     if ((e = launch_solve(d, f64, c->P.chunks_tot, false, s)) != hipSuccess) return e;
     if (tm && (e = hipEventRecord(c->ev[c->ev_used], s)) != hipSuccess) return e;
     if ((e = launch_particles(d, c->L, s, f64, SB_PUSH, 0)) != hipSuccess) return e;
@@ -424,25 +448,33 @@ hipError_t enqueue_step(pic_ctx *c, hipStream_t s, bool sort_now)
 // slot and id counters, the birth lists and bitmaps, the speed-maximum halves and the step
 // counter, the solve only the grid, so they run side by side, and the collision
 // parameters and the particle pass after them see both.  The last step's births are
-// placed before the sort, in line.  The state after the cycle is the same as after K
-// calls of enqueue_step.
+// placed in line at the end (before the sort when it has kernels of its own).  The FP32
+// form pipelines the sort as enqueue_step does: step K - 2 counts and scans, step K - 1's
+// pass sorts.  The state after the cycle is the same as after K calls of enqueue_step.
 hipError_t enqueue_cycle_merged(pic_ctx *c, hipStream_t s)
 {
     const Dev &d = c->d;
     const bool f64 = c->P.f64;
     const int K = c->sort_every;
     const int stages = SB_PUSH | SB_COLLIDE | SB_DEPOSIT;
+    const bool piped = !f64 && K >= 2;
     hipError_t e;
     for (int i = 0; i < K; ++i) {
-        const int hist = (i == K - 1) ? 1 : 0;
+        const bool sorting = piped && i == K - 1;
+        const int hist = (piped ? i == K - 2 : i == K - 1) ? 1 : 0;
         if ((e = launch_solve(d, f64, c->P.chunks_tot, true, s, i > 0, true)) != hipSuccess) return e;
-        if ((e = launch_particles(d, c->L, s, f64, stages, hist, false)) != hipSuccess) return e;
+        if (sorting)
+            e = launch_pass32_sort(d, c->L.ppt, c->L.window, s, true, d.cap_tot, c->L.nt != 0);
+        else
+            e = launch_particles(d, c->L, s, f64, stages, hist, false);
+        if (e != hipSuccess) return e;
         if ((e = launch_candidates(d, c->L, s, f64, hist)) != hipSuccess) return e;
         if ((e = launch_neutrals(d, s)) != hipSuccess) return e;
         if ((e = launch_source(d, hist, s)) != hipSuccess) return e;
+        if (piped && i == K - 2 && (e = launch_sort_prepare(d, s)) != hipSuccess) return e;
     }
     if ((e = launch_births(d, f64, true, true, s)) != hipSuccess) return e;
-    return launch_sort(d, f64, c->L, s);
+    return piped ? hipSuccess : launch_sort(d, f64, c->L, s);
 }
 
 int build_graph(pic_ctx *c)
@@ -456,8 +488,10 @@ int build_graph(pic_ctx *c)
     if (merged) {
         e = enqueue_cycle_merged(c, c->cap_stream);
     } else {
+        // a cycle starts at a multiple of K, with no sort prepared
+        bool ready = false;
         for (int i = 0; i < c->sort_every && e == hipSuccess; ++i)
-            e = enqueue_step(c, c->cap_stream, i == c->sort_every - 1);
+            e = enqueue_step(c, c->cap_stream, i, ready, false);
     }
     hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
     if (e != hipSuccess) return hipfail(c, e, "graph capture");
@@ -593,6 +627,7 @@ int pic_solve(pic_ctx *c, void *stream)
 int pic_push(pic_ctx *c, void *stream)
 {
     if (!c) return PIC_EINVAL;
+    c->sort_ready = false;  // particles or the step count change: no prepared sort
     HIPC(c, launch_particles(c->d, c->L, (hipStream_t)stream, c->P.f64, SB_PUSH, 0));
     HIPC(c, launch_neutrals(c->d, (hipStream_t)stream));
     return PIC_OK;
@@ -601,6 +636,7 @@ int pic_push(pic_ctx *c, void *stream)
 int pic_collide(pic_ctx *c, void *stream)
 {
     if (!c) return PIC_EINVAL;
+    c->sort_ready = false;  // particles or the step count change: no prepared sort
     hipStream_t s = (hipStream_t)stream;
     if (c->cfg.collisions) {
         HIPC(c, launch_particles(c->d, c->L, s, c->P.f64, SB_COLLIDE, 0));
@@ -614,6 +650,7 @@ int pic_collide(pic_ctx *c, void *stream)
 int pic_sort(pic_ctx *c, void *stream)
 {
     if (!c) return PIC_EINVAL;
+    c->sort_ready = false;  // particles or the step count change: no prepared sort
     hipStream_t s = (hipStream_t)stream;
     HIPC(c, launch_particles(c->d, c->L, s, c->P.f64, SB_HIST, 0));
     HIPC(c, launch_sort(c->d, c->P.f64, c->L, s));
@@ -630,10 +667,11 @@ int pic_step(pic_ctx *c, int32_t nsteps, void *stream)
             int rc = build_graph(c);
             if (rc) return rc;
             HIPC(c, hipGraphLaunch(c->graph, s));
+            c->sort_ready = false;
             c->host_step += K;
             nsteps -= K;
         } else {
-            HIPC(c, enqueue_step(c, s, is_sort_step(c, c->host_step + 1)));
+            HIPC(c, enqueue_step(c, s, c->host_step, c->sort_ready, false));
             c->host_step += 1;
             nsteps -= 1;
         }
@@ -644,6 +682,7 @@ int pic_step(pic_ctx *c, int32_t nsteps, void *stream)
 int pic_set_step(pic_ctx *c, int64_t step)
 {
     if (!c || step < 0) return PIC_EINVAL;
+    c->sort_ready = false;  // particles or the step count change: no prepared sort
     // both birth halves clean, whatever parity the new step has
     HIPC(c, launch_births_clear_all(c->d, nullptr));
     HIPC(c, hipDeviceSynchronize());
@@ -922,6 +961,7 @@ int pic_set_particles(pic_ctx *c, int32_t ens, int32_t species, pic_particles in
         return set_neutrals(c, ens, in, count, (hipStream_t)stream);
     if (!c || ens < 0 || ens >= c->P.nens || species < 0 || species >= c->P.nspecies || count < 0)
         return fail(c, PIC_EINVAL, "bad ensemble/species/count");
+    c->sort_ready = false;  // particles or the step count change: no prepared sort
     const int sg = c->P.ens[ens].seg[species];
     const SegC &S = c->P.seg[sg];
     if (count > S.cap) return fail(c, PIC_EINVAL, "count above capacity");
@@ -1126,6 +1166,7 @@ int pic_adjoint_window(pic_ctx *c, int32_t nsteps, int32_t ckpt_every, void *scr
                        double *W, double *dW_dvx, int64_t dvx_len, double *dW_dEext, void *stream)
 {
     if (!c || !scratch || nsteps < 1 || ckpt_every < 1 || !W || !dW_dvx || !dW_dEext) return PIC_EINVAL;
+    c->sort_ready = false;  // particles or the step count change: no prepared sort
     std::string why;
     if (adj_check(c, why)) return fail(c, PIC_EINVAL, why);
     const AdjLayout A = adj_layout(c, nsteps, ckpt_every);
@@ -1278,10 +1319,11 @@ int pic_autotune(pic_ctx *c, int32_t trial_steps, int32_t *shape, void *stream)
                 // every candidate starts from freshly sorted particles
                 HIPC(c, launch_particles(c->d, c->L, s, false, SB_HIST, 0));
                 HIPC(c, launch_sort(c->d, false, c->L, s));
+                c->sort_ready = false;
                 int rc = pic_timing(c, 1);
                 if (rc) return rc;
                 for (int t = 0; t < trial_steps; ++t) {
-                    HIPC(c, enqueue_step(c, s, is_sort_step(c, c->host_step + 1)));
+                    HIPC(c, enqueue_step(c, s, c->host_step, c->sort_ready, false));
                     c->host_step += 1;
                 }
                 HIPC(c, hipStreamSynchronize(s));
@@ -1325,12 +1367,13 @@ int pic_autotune(pic_ctx *c, int32_t trial_steps, int32_t *shape, void *stream)
             c->L.sort_ppt = ppts[ci % 2];
             c->L.sort_nt = ci / 2;
             for (int t = 0; t < std::max(trial_steps / 2, 2); ++t) {
-                HIPC(c, enqueue_step(c, s, false));
+                HIPC(c, enqueue_step(c, s, c->host_step, c->sort_ready, true));
                 c->host_step += 1;
             }
             HIPC(c, hipEventRecord(e0, s));
             HIPC(c, launch_particles(c->d, c->L, s, false, SB_HIST, 0));
             HIPC(c, launch_sort(c->d, false, c->L, s));
+            c->sort_ready = false;
             HIPC(c, hipEventRecord(e1, s));
             HIPC(c, hipEventSynchronize(e1));
             float ms = 0.f;
@@ -1491,6 +1534,7 @@ int pic_save(pic_ctx *c, void *host_buf, size_t bytes, void *stream)
 int pic_load(pic_ctx *c, const void *host_buf, size_t bytes, void *stream)
 {
     if (!c || !host_buf || bytes < sizeof(CkptHeader)) return PIC_EINVAL;
+    c->sort_ready = false;  // particles or the step count change: no prepared sort
     hipStream_t s = (hipStream_t)stream;
     CkptHeader h;
     std::memcpy(&h, host_buf, sizeof(h));

@@ -45,6 +45,11 @@ hipError_t launch_births(const Dev &d, bool f64, bool in_step, bool advance, hip
 hipError_t launch_advance(const Dev &d, hipStream_t s);
 hipError_t launch_births_clear_all(const Dev &d, hipStream_t s);
 hipError_t launch_sort(const Dev &d, bool f64, const Launch &L, hipStream_t s);
+// The first half of a sort: the histogram's scan into run cursors and the segment starts.
+hipError_t launch_sort_prepare(const Dev &d, hipStream_t s);
+// FP32 fused pass that also scatters into cell order (after launch_sort_prepare), then the
+// slot counts and the buffer flip.
+hipError_t launch_pass32_sort(const Dev &d, int ppt, int W, hipStream_t s, bool coll, int64_t cap_tot, bool nt);
 hipError_t launch_pass32(const Dev &d, int ppt, int W, hipStream_t s, int stages, int hist, int64_t cap_tot,
                          bool nt);
 hipError_t launch_cand32(const Dev &d, int ppt, hipStream_t s, int hist, int64_t cap_tot);

@@ -1710,11 +1710,18 @@ hipError_t launch_advance(const Dev &d, hipStream_t s)
     return hipSuccess;
 }
 
-hipError_t launch_sort(const Dev &d, bool f64, const Launch &L, hipStream_t s)
+hipError_t launch_sort_prepare(const Dev &d, hipStream_t s)
 {
     hipError_t e = launch_scan(d.cellcnt, d.cursor, d.cells_tot, d.scanpart, true, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_segstart, dim3(1), dim3(256), 0, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort(const Dev &d, bool f64, const Launch &L, hipStream_t s)
+{
+    hipError_t e = launch_sort_prepare(d, s);
+    if (e != hipSuccess) return e;
     if (!f64) return launch_sort32_scatter(d, L.sort_ppt, L.window, s, d.cap_tot, L.sort_nt != 0);
     const size_t lds = (size_t)L.window * 4;
     hipLaunchKernelGGL((k_sort_scatter<4>), dim3(L.grid), dim3(L.block), lds, s, d, L.window);

@@ -108,7 +108,11 @@ __device__ __forceinline__ void emit_run(const Dev &d, const SegC &S, int s, int
     if (hist) atomicAdd(d.cellcnt + S.cbase + cell, cnt);
 }
 
-template <int STAGES, int PPT, bool NT = false>
+// With SORT (a fused pass on the step after a histogram step) every live particle is written
+// to the other buffer at its place in cell order instead of in place: the tile ranks its
+// particles by their cell before the push (the cells the previous pass counted) in LDS and
+// reserves one run per cell, as the sort scatter does, so the pass also sorts and compacts.
+template <int STAGES, int PPT, bool NT = false, bool SORT = false>
 __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64_t T)
 {
     constexpr bool PUSH = STAGES & PS_PUSH;
@@ -117,8 +121,10 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
     constexpr bool HISTC = STAGES & PS_HIST;
     constexpr bool WIN = DEPO || HISTC;
     constexpr bool NEED_V = PUSH || COLL;
+    constexpr bool NEED_ID = COLL || SORT;
     constexpr int TILE = 256 * PPT;
     static_assert(PPT % 4 == 0, "PPT must be a multiple of 4");
+    static_assert(!SORT || (PUSH && DEPO && !HISTC), "the sorting pass is a fused pass");
 
     extern __shared__ unsigned long long s_dyn[];
     unsigned long long *sQ = s_dyn;                // [W + 1]
@@ -156,7 +162,7 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
             vload<PPT, NT>(d.fvy[b] + i0, vy);
             vload<PPT, NT>(d.fvz[b] + i0, vz);
         }
-        if (COLL) vload<PPT, NT>(d.id[b] + i0, id);
+        if (NEED_ID) vload<PPT, NT>(d.id[b] + i0, id);
     } else {
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
@@ -170,7 +176,7 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
                     vy[k] = d.fvy[b][i];
                     vz[k] = d.fvz[b][i];
                 }
-                if (COLL) id[k] = d.id[b][i];
+                if (NEED_ID) id[k] = d.id[b][i];
             }
         }
     }
@@ -238,6 +244,59 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
             }
         }
     }
+    // sorting pass: destinations in the other buffer (-1: none)
+    int64_t dst[SORT ? PPT : 1];
+    if constexpr (SORT) {
+        const int mn = min(min(s_wmn[0], s_wmn[1]), min(s_wmn[2], s_wmn[3]));
+        const int mx = max(max(s_wmx[0], s_wmx[1]), max(s_wmx[2], s_wmx[3]));
+        const int Ws = mx >= 0 ? min(mx - mn + 1, W) : 0;
+        uint32_t *sCnt = sH;  // no histogram in this pass
+        for (int i = tid; i < Ws; i += 256) sCnt[i] = 0u;
+        __syncthreads();
+        uint32_t *__restrict__ cursor = d.cursor + S.cbase;
+        const int lane = lane_id();
+        uint32_t pos[PPT];
+        bool inwin[PPT];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int rel = (cell[k] != kDead) ? cell[k] - mn : -1;
+            const int key = (rel >= 0 && rel < Ws) ? rel : -1;
+            inwin[k] = key >= 0;
+            unsigned long long act = __ballot(key >= 0);
+            int it = 0;
+            while (act != 0ull && it < 8) {
+                const int leader = __ffsll((long long)act) - 1;
+                const int kk = __shfl(key, leader);
+                const bool mine = (key == kk) && ((act >> lane) & 1ull);
+                const unsigned long long m = __ballot(mine);
+                uint32_t r0 = 0;
+                if (lane == leader) r0 = atomicAdd(&sCnt[kk], (uint32_t)__popcll(m));
+                r0 = __shfl(r0, leader);
+                if (mine) pos[k] = r0 + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+                act &= ~m;
+                ++it;
+            }
+            if ((act >> lane) & 1ull) pos[k] = atomicAdd(&sCnt[key], 1u);
+            if (cell[k] != kDead && key < 0) pos[k] = atomicAdd(cursor + cell[k], 1u);
+        }
+        __syncthreads();
+        for (int i = tid; i < Ws; i += 256) {
+            const uint32_t c = sCnt[i];
+            if (c) sCnt[i] = atomicAdd(cursor + mn + i, c);
+        }
+        __syncthreads();
+        const int64_t sbase = S.base - d.segstart[sg];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            dst[k] = -1;
+            if (cell[k] == kDead) continue;
+            const int64_t o = sbase + (int64_t)(inwin[k] ? sCnt[cell[k] - mn] + pos[k] : pos[k]);
+            if (o < S.base || o >= S.base + S.cap)
+                atomicOr(d.err, (int)E_CAP_PART);
+            else
+                dst[k] = o;
+        }
+    }
 
     uint32_t npush = 0;
     uint32_t cchg = 0;  // bit k: particle k's cell changed in the push (or it died)
@@ -287,7 +346,7 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
                     }
                     if (S.recycle) {
                         // reading R24: list the absorbed ion; it returns as a neutral
-                        const uint32_t pid = COLL ? id[k] : d.id[b][i0 + k];
+                        const uint32_t pid = NEED_ID ? id[k] : d.id[b][i0 + k];
                         const uint32_t r = atomicAdd(d.nrec, 1u);
                         if ((int64_t)r < d.rec_cap)
                             d.recs[r] = make_uint2(pid, ((uint32_t)S.ens << 1) | (c < 0 ? 0u : 1u));
@@ -320,7 +379,7 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             const bool alive = cell[k] != kDead;
-            const bool cand = alive && ((rmask >> k) & 1u);
+            const bool cand = alive && ((rmask >> k) & 1u) && (!SORT || dst[SORT ? k : 0] >= 0);
             cmask |= (cand ? 1u : 0u) << k;
             const float vv = fmaf(vx[k], vx[k], fmaf(vy[k], vy[k], vz[k] * vz[k]));
             v2f = (alive && !cand) ? fmaxf(v2f, vv) : v2f;
@@ -333,7 +392,8 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 if ((cmask >> k) & 1u) {
-                    const uint4 r0 = make_uint4((uint32_t)(i0 + k), (uint32_t)cell[k], __float_as_uint(off[k]), id[k]);
+                    const uint32_t slot = SORT ? (uint32_t)dst[SORT ? k : 0] : (uint32_t)(i0 + k);
+                    const uint4 r0 = make_uint4(slot, (uint32_t)cell[k], __float_as_uint(off[k]), id[k]);
                     const uint4 r1 = make_uint4(__float_as_uint(vx[k]), __float_as_uint(vy[k]),
                                                 __float_as_uint(vz[k]), (uint32_t)sg);
                     if (q < kRecLds) {
@@ -353,7 +413,20 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
     }
 
     // write back
-    if (PUSH || COLL) {
+    if constexpr (SORT) {
+        const int nb = 1 - b;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int64_t o = dst[SORT ? k : 0];
+            if (o < 0) continue;
+            d.cell[nb][o] = cell[k];
+            d.off[nb][o] = off[k];
+            d.fvx[nb][o] = vx[k];
+            d.fvy[nb][o] = vy[k];
+            d.fvz[nb][o] = vz[k];
+            d.id[nb][o] = id[k];
+        }
+    } else if (PUSH || COLL) {
         if (full) {
             if (PUSH) {
                 // a group of four cells is stored only if one of them changed (the heavy
@@ -753,20 +826,37 @@ __global__ void k_sort_finish(Dev d)
 hipError_t launch_pass32_stages(const Dev &d, int ppt, int W, hipStream_t s, int stages, int hist,
                                 int64_t cap_tot, bool nt);
 
-template <int STAGES, bool NT = false>
+template <int STAGES, bool NT = false, bool SORT = false>
 static hipError_t launch_pass32_t(const Dev &d, int ppt, int W, hipStream_t s, int hist, int64_t cap_tot)
 {
-    const bool with_hist = (STAGES & PS_HIST) || hist;
+    // the sorting pass counts its runs where the histogram would go
+    const bool with_hist = (STAGES & PS_HIST) || hist || SORT;
     const size_t lds = (size_t)(W + 1) * 8 + (with_hist ? (size_t)W * 4 : 0);
     if (ppt == 4) {
         const int64_t T = cap_tot / (256 * 4);
         const int64_t G = (T + 7) / 8 * 8;
-        hipLaunchKernelGGL((k_pass32<STAGES, 4, NT>), dim3(G), dim3(256), lds, s, d, W, hist, T);
+        hipLaunchKernelGGL((k_pass32<STAGES, 4, NT, SORT>), dim3(G), dim3(256), lds, s, d, W, hist, T);
     } else {
         const int64_t T = cap_tot / (256 * 8);
         const int64_t G = (T + 7) / 8 * 8;
-        hipLaunchKernelGGL((k_pass32<STAGES, 8, NT>), dim3(G), dim3(256), lds, s, d, W, hist, T);
+        hipLaunchKernelGGL((k_pass32<STAGES, 8, NT, SORT>), dim3(G), dim3(256), lds, s, d, W, hist, T);
     }
+    return hipGetLastError();
+}
+
+// The fused pass that also sorts (after launch_sort_prepare on the previous step's
+// histogram), then the new slot counts and the buffer flip.
+hipError_t launch_pass32_sort(const Dev &d, int ppt, int W, hipStream_t s, bool coll, int64_t cap_tot, bool nt)
+{
+    hipError_t e;
+    if (coll && nt)
+        e = launch_pass32_t<PS_PUSH | PS_COLLIDE | PS_DEPOSIT, true, true>(d, ppt, W, s, 0, cap_tot);
+    else if (coll)
+        e = launch_pass32_t<PS_PUSH | PS_COLLIDE | PS_DEPOSIT, false, true>(d, ppt, W, s, 0, cap_tot);
+    else
+        e = launch_pass32_t<PS_PUSH | PS_DEPOSIT, false, true>(d, ppt, W, s, 0, cap_tot);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(256), 0, s, d);
     return hipGetLastError();
 }
 

@@ -340,10 +340,13 @@ def test_fused_equals_separate_and_graph_equals_eager(pic):
     fused_graph = pic.Sim(work_of(e), fused=True)
     fused_eager = pic.Sim(work_of(e), fused=True)
     separate = pic.Sim(work_of(e), fused=False)
-    fused_graph.step(25)           # one graph replay (20 steps) + 5 eager steps
-    for _ in range(25):
+    # two graph replays (20 steps each, the sort inside the last pass of each) + 5 eager
+    # steps; the eager run sorts inside its passes at steps 20 and 40; the separate stages
+    # sort in kernels of their own
+    fused_graph.step(45)
+    for _ in range(45):
         fused_eager.step(1)
-    separate.step(25)
+    separate.step(45)
     a, b, c = _state(fused_graph), _state(fused_eager), _state(separate)
     for s in range(2):
         for k in ("id", "x", "vx", "vy", "vz"):
@@ -395,3 +398,29 @@ def test_launch_shape_leaves_results_unchanged(pic, fused, shape):
     assert da["wall_count"] == db["wall_count"]
     for s in range(2):
         assert np.array_equal(ref.grid()["Q"][s], alt.grid()["Q"][s])
+
+
+def test_fused_sort_orders_by_the_cells_before_the_push(pic):
+    """The fused FP32 step sorts inside the particle pass of the sort step, by the cells
+    the particles held before that push.  Afterwards the particles that existed before the
+    step lie in ascending cell order up to the step's largest displacement, and the pairs
+    the step created follow all of them."""
+    w = synth.scaled(synth.c2_sheath(), ncells=1200, ppc=30)
+    e = w["ensembles"][0]
+    e["ngs_el"], e["ngs_iz"] = 0.1, 0.2
+    for sp in e["species"]:
+        sp["capacity"] *= 2
+    sim = pic.Sim(work_of(e), fused=True)
+    sim.step(19)
+    idmax = [int(sim.particles(0, s)["id"].max()) for s in range(2)]
+    sim.step(1)  # the sort step (K = 20)
+    assert sim.diag()["created"][0] > 0
+    for s in range(2):
+        p = sim.particles(0, s)  # live particles in slot order
+        old = p["id"] <= idmax[s]
+        assert np.all(np.flatnonzero(~old) > np.flatnonzero(old).max()), s
+        cell = np.floor(p["x"][old] / e["dx"]).astype(np.int64)
+        reach = int(np.ceil(np.max(np.abs(p["vx"][old])) * e["dt"] / e["dx"]))
+        behind = np.maximum.accumulate(cell) - cell
+        assert np.all(behind <= 2 * reach), (s, int(behind.max()), reach)
+        assert np.mean(np.diff(cell) < 0) < 0.5
