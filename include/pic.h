@@ -320,7 +320,8 @@ int pic_load(pic_ctx *ctx, const void *host_buf, size_t bytes, void *stream);
 
 /* Measurement hook: with `enable` != 0, pic_step runs its steps without the graph and
  * brackets every particle-pass launch with HIP events recorded on the caller's stream
- * (up to 65536 launches); pic_timing_read synchronises that stream and returns the summed
+ * (up to 65536 launches), except the fused FP32 passes that also sort (one per K steps,
+ * a kernel of their own); pic_timing_read synchronises that stream and returns the summed
  * kernel time in milliseconds and the number of timed launches.  Enabling again resets. */
 int pic_timing(pic_ctx *ctx, int32_t enable);
 int pic_timing_read(pic_ctx *ctx, double *ms_total, int64_t *launches, void *stream);

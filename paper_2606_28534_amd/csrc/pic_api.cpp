@@ -380,10 +380,11 @@ hipError_t enqueue_step(pic_ctx *c, hipStream_t s, int64_t n, bool &ready, bool 
     const int K = c->sort_every;
     const bool sort_now = !no_sort && (n + 1) % K == 0;
     hipError_t e;
-    const bool tm = c->timing && c->ev_used + 2 <= (int64_t)c->ev.size();
+    bool tm = c->timing && c->ev_used + 2 <= (int64_t)c->ev.size();
     if (c->cfg.fused) {
         const bool piped = !f64 && K >= 2 && !no_sort;
         const bool sorting = piped && sort_now && ready;
+        tm = tm && !sorting;  // the measurement hook times the plain pass only
         const bool prep = piped && (n + 2) % K == 0;
         const int hist = (prep || (sort_now && !sorting)) ? 1 : 0;
         // the solve's last block computes the collision bound, so the measurement hook
