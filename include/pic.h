@@ -232,8 +232,11 @@ int pic_sort(pic_ctx *ctx, void *stream);
 
 /* nsteps full steps (R2 order): solve, push + walls, collide, deposit, and a sort when
  * the new step count is a multiple of K.  With cfg.fused = 1 the particle stages run as
- * one pass per step and the steps replay a captured HIP graph.  Synchronises the stream
- * once at the end to read the sticky error flags. */
+ * one pass per step and the steps replay a captured HIP graph; in the FP32 form with
+ * K >= 2 the step before a sort step also counts the cells, and the sort step's pass
+ * writes the particles in the order of the cells they held before its push (so the
+ * particles are ordered by cell up to that push, and the sort costs no kernel of its
+ * own).  Synchronises the stream once at the end to read the sticky error flags. */
 int pic_step(pic_ctx *ctx, int32_t nsteps, void *stream);
 
 /* Scalars of ensemble `ens` (synchronises `stream`). */
