@@ -108,6 +108,49 @@ __device__ __forceinline__ void emit_run(const Dev &d, const SegC &S, int s, int
     if (hist) atomicAdd(d.cellcnt + S.cbase + cell, cnt);
 }
 
+// Counting-sort ranking of one tile.  A particle whose cell lies in the window
+// [base, base + Ws) gets its rank inside the tile's run of that cell (wave-leader
+// aggregation: one LDS atomic per distinct cell and wave); any other live particle takes its
+// final position from the global cursor of its cell at once.
+template <int PPT>
+__device__ __forceinline__ void tile_rank(const int (&cell)[PPT], int base, int Ws, uint32_t *sCnt,
+                                          uint32_t *cursor, uint32_t (&pos)[PPT], bool (&inwin)[PPT])
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int rel = (cell[k] != kDead) ? cell[k] - base : -1;
+        const int key = (rel >= 0 && rel < Ws) ? rel : -1;
+        inwin[k] = key >= 0;
+        unsigned long long act = __ballot(key >= 0);
+        int it = 0;
+        while (act != 0ull && it < 8) {
+            const int leader = __ffsll((long long)act) - 1;
+            const int kk = __shfl(key, leader);
+            const bool mine = (key == kk) && ((act >> lane) & 1ull);
+            const unsigned long long m = __ballot(mine);
+            uint32_t r0 = 0;
+            if (lane == leader) r0 = atomicAdd(&sCnt[kk], (uint32_t)__popcll(m));
+            r0 = __shfl(r0, leader);
+            if (mine) pos[k] = r0 + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+            act &= ~m;
+            ++it;
+        }
+        if ((act >> lane) & 1ull) pos[k] = atomicAdd(&sCnt[key], 1u);
+        if (cell[k] != kDead && key < 0) pos[k] = atomicAdd(cursor + cell[k], 1u);
+    }
+}
+
+// After tile_rank and a barrier: one run per window cell is reserved in the global order,
+// turning the tile's counts in sCnt into the runs' first positions (a barrier must follow).
+__device__ __forceinline__ void tile_reserve(uint32_t *sCnt, int Ws, uint32_t *cursor, int base)
+{
+    for (int i = threadIdx.x; i < Ws; i += blockDim.x) {
+        const uint32_t c = sCnt[i];
+        if (c) sCnt[i] = atomicAdd(cursor + base + i, c);
+    }
+}
+
 // With SORT (a fused pass on the step after a histogram step) every live particle is written
 // to the other buffer at its place in cell order instead of in place: the tile ranks its
 // particles by their cell before the push (the cells the previous pass counted) in LDS and
@@ -253,37 +296,12 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
         uint32_t *sCnt = sH;  // no histogram in this pass
         for (int i = tid; i < Ws; i += 256) sCnt[i] = 0u;
         __syncthreads();
-        uint32_t *__restrict__ cursor = d.cursor + S.cbase;
-        const int lane = lane_id();
+        uint32_t *cursor = d.cursor + S.cbase;
         uint32_t pos[PPT];
         bool inwin[PPT];
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            const int rel = (cell[k] != kDead) ? cell[k] - mn : -1;
-            const int key = (rel >= 0 && rel < Ws) ? rel : -1;
-            inwin[k] = key >= 0;
-            unsigned long long act = __ballot(key >= 0);
-            int it = 0;
-            while (act != 0ull && it < 8) {
-                const int leader = __ffsll((long long)act) - 1;
-                const int kk = __shfl(key, leader);
-                const bool mine = (key == kk) && ((act >> lane) & 1ull);
-                const unsigned long long m = __ballot(mine);
-                uint32_t r0 = 0;
-                if (lane == leader) r0 = atomicAdd(&sCnt[kk], (uint32_t)__popcll(m));
-                r0 = __shfl(r0, leader);
-                if (mine) pos[k] = r0 + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-                act &= ~m;
-                ++it;
-            }
-            if ((act >> lane) & 1ull) pos[k] = atomicAdd(&sCnt[key], 1u);
-            if (cell[k] != kDead && key < 0) pos[k] = atomicAdd(cursor + cell[k], 1u);
-        }
+        tile_rank<PPT>(cell, mn, Ws, sCnt, cursor, pos, inwin);
         __syncthreads();
-        for (int i = tid; i < Ws; i += 256) {
-            const uint32_t c = sCnt[i];
-            if (c) sCnt[i] = atomicAdd(cursor + mn + i, c);
-        }
+        tile_reserve(sCnt, Ws, cursor, mn);
         __syncthreads();
         const int64_t sbase = S.base - d.segstart[sg];
 #pragma unroll
@@ -753,36 +771,11 @@ __global__ void __launch_bounds__(256) k_sort32(Dev d, int W, int64_t T)
     for (int i = tid; i < Wt; i += 256) sCnt[i] = 0u;
     __syncthreads();
     uint32_t *__restrict__ cursor = d.cursor + S.cbase;
-    // rank: in-window -> rank inside the tile's run of that cell; outside -> final position
     uint32_t pos[PPT];
     bool inwin[PPT];
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const int rel = (cell[k] != kDead) ? cell[k] - base : -1;
-        const int key = (rel >= 0 && rel < Wt) ? rel : -1;
-        inwin[k] = key >= 0;
-        unsigned long long act = __ballot(key >= 0);
-        int it = 0;
-        while (act != 0ull && it < 8) {
-            const int leader = __ffsll((long long)act) - 1;
-            const int kk = __shfl(key, leader);
-            const bool mine = (key == kk) && ((act >> lane) & 1ull);
-            const unsigned long long m = __ballot(mine);
-            uint32_t r0 = 0;
-            if (lane == leader) r0 = atomicAdd(&sCnt[kk], (uint32_t)__popcll(m));
-            r0 = __shfl(r0, leader);
-            if (mine) pos[k] = r0 + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-            act &= ~m;
-            ++it;
-        }
-        if ((act >> lane) & 1ull) pos[k] = atomicAdd(&sCnt[key], 1u);
-        if (cell[k] != kDead && key < 0) pos[k] = atomicAdd(cursor + cell[k], 1u);
-    }
+    tile_rank<PPT>(cell, base, Wt, sCnt, cursor, pos, inwin);
     __syncthreads();
-    for (int i = tid; i < Wt; i += 256) {
-        const uint32_t c = sCnt[i];
-        if (c) sCnt[i] = atomicAdd(cursor + base + i, c);
-    }
+    tile_reserve(sCnt, Wt, cursor, base);
     __syncthreads();
     const int64_t sbase = S.base - d.segstart[sg];
     const int64_t send = S.base + S.cap;
