@@ -10,6 +10,8 @@
 // to the launch's maximum: a sorted tile clears and flushes a few nodes, a tile of freshly
 // appended particles spread over many cells still deposits through LDS.
 // Block b takes tile b (see tile_of_block for why not an XCD-major order).
+#include <algorithm>
+
 #include "pic_device.h"
 #include "pic_kernels.h"
 #include "pic_particle.h"
@@ -819,11 +821,18 @@ __global__ void k_sort_finish(Dev d)
 hipError_t launch_pass32_stages(const Dev &d, int ppt, int W, hipStream_t s, int stages, int hist,
                                 int64_t cap_tot, bool nt);
 
+// A pass that also counts cells (or sorts) needs 4 more bytes of LDS per window cell; its
+// window span is capped so that its LDS stays within what the plain pass's occupancy allows
+// (12 B per cell x 1024 cells + the static 8 KB, seven blocks per CU).  Cells outside the
+// window go to HBM atomics, so the cap changes no result.
+constexpr int kCountWindowMax = 1024;
+
 template <int STAGES, bool NT = false, bool SORT = false>
 static hipError_t launch_pass32_t(const Dev &d, int ppt, int W, hipStream_t s, int hist, int64_t cap_tot)
 {
     // the sorting pass counts its runs where the histogram would go
     const bool with_hist = (STAGES & PS_HIST) || hist || SORT;
+    if (with_hist) W = std::min(W, kCountWindowMax);
     const size_t lds = (size_t)(W + 1) * 8 + (with_hist ? (size_t)W * 4 : 0);
     if (ppt == 4) {
         const int64_t T = cap_tot / (256 * 4);
