@@ -236,9 +236,9 @@ def main():
     ap.add_argument("--no-walls-variant", action="store_true")
     ap.add_argument("--no-sheath-cases", action="store_true")
     ap.add_argument("--no-large", action="store_true")
-    ap.add_argument("--case", choices=["sheath", "recycling", "source"], default="sheath",
-                    help="main workload: the sheath slab (default) or one of the paper's two "
-                         "sheath cases (for profiling them)")
+    ap.add_argument("--case", choices=["sheath", "recycling", "source", "large"], default="sheath",
+                    help="main workload: the sheath slab (default), one of the paper's two "
+                         "sheath cases, or the 1e9-particle share (for profiling them)")
     ap.add_argument("--floating", action="store_true",
                     help="main workload with floating walls (for profiling the variant)")
     ap.add_argument("--smooth", type=int, default=0,
@@ -264,11 +264,16 @@ def main():
         work = synth.c6_sheath_recycling(seed=args.seed, ncells=args.ncells, ppc=args.ppc)
     elif args.case == "source":
         work = synth.c7_sheath_source(seed=args.seed, ncells=args.ncells)
+    elif args.case == "large":
+        work = synth.c5_large(seed=args.seed)
     else:
         work = synth.c2_sheath(seed=args.seed, ncells=args.ncells, ppc=args.ppc)
     e = work["ensembles"][0]
-    e["floating"] = bool(args.floating)
-    e["smooth"] = int(args.smooth)
+    # the variants switch features on; the sheath cases keep their own walls and filter
+    if args.floating:
+        e["floating"] = True
+    if args.smooth:
+        e["smooth"] = int(args.smooth)
     if args.shape:
         ppt, window, sort_ppt, nt = (int(v) for v in args.shape.split(","))
         shape = {"ppt": ppt, "window": window, "sort_ppt": sort_ppt, "nontemporal": nt}
