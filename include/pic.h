@@ -142,9 +142,10 @@ typedef struct {
     int32_t boundary;    /* PIC_ABSORBING, PIC_PERIODIC or PIC_FLOATING (all ensembles)      */
     int32_t nspecies;    /* 1: electrons on a fixed neutralising background; 2: e + ions   */
     int32_t collisions;  /* 0: collisionless                                               */
-    int32_t sort_every;  /* K: counting sort (which also compacts absorbed slots) when the
-                            step count reaches a multiple of K; 0 = compaction-only sort
-                            every 20 steps, physics unchanged either way                    */
+    int32_t sort_every;  /* K in [0, 4096]: counting sort (which also compacts absorbed
+                            slots) when the step count reaches a multiple of K; 0 =
+                            compaction-only sort every 20 steps, physics unchanged either
+                            way                                                             */
     int32_t fused;       /* 0: one kernel per stage; 1: fused particle pass + HIP graph    */
     int32_t block;       /* threads per block of the FP64 particle kernels (64, 128 or
                             256); 0 = default 256                                           */

@@ -68,6 +68,10 @@ int build_plan(const pic_config *cfg, Plan &P, std::string &msg)
         msg = "window must be 0 (default) or in [16, 4096]";
         return PIC_EINVAL;
     }
+    if (cfg->sort_every < 0 || cfg->sort_every > 4096) {
+        msg = "sort_every must be in [0, 4096] (a fused run captures one sort cycle as a graph)";
+        return PIC_EINVAL;
+    }
     if (cfg->block != 0 && cfg->block != 64 && cfg->block != 128 && cfg->block != 256) {
         msg = "block must be 0 (default), 64, 128 or 256";
         return PIC_EINVAL;

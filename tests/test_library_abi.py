@@ -65,7 +65,8 @@ def test_bad_configs_rejected(lib):
     cfg.n_ensembles = 0
     assert L.pic_query_workspace(C.byref(cfg), C.byref(n)) == P.PIC_EINVAL
     # launch-shape fields out of range: LDS window span and FP64 block size
-    for field, value in (("window", 8), ("window", 8192), ("block", 512), ("block", 96)):
+    for field, value in (("window", 8), ("window", 8192), ("block", 512), ("block", 96),
+                         ("sort_every", -1), ("sort_every", 5000)):
         cfg, keep = P.make_config(work)
         setattr(cfg, field, value)
         assert L.pic_query_workspace(C.byref(cfg), C.byref(n)) == P.PIC_EINVAL, (field, value)
