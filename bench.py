@@ -37,9 +37,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(workload_name, pushes_per_launch):
-    """HBM bytes per launch of the fused pass from the committed PMC summary, or None when
-    the summary is missing or was taken on a different kernel source."""
+def traffic_from_profiles(workload_name, bytes_alg_per_launch):
+    """HBM bytes per launch of the fused pass from the committed PMC summary, scaled from
+    the counted run's launches to this run's by their algorithmic bytes (the counted run is
+    shorter, so it pushes fewer particles per launch); None when the summary is missing or
+    was taken on a different kernel source."""
     p = os.path.join(ROOT, "profiles", f"pmc_fused_pass_{workload_name}.json")
     if not os.path.exists(p):
         return None
@@ -47,7 +49,10 @@ def traffic_from_profiles(workload_name, pushes_per_launch):
         rec = json.load(fh)
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return rec.get("bytes_per_launch")
+    measured, counted_alg = rec.get("bytes_per_launch"), rec.get("bytes_alg_per_launch")
+    if measured is None or not counted_alg:
+        return None
+    return round(measured * bytes_alg_per_launch / counted_alg)
 
 
 def tuned_shape(pic, work, trial_steps):
@@ -312,7 +317,7 @@ def main():
                         + B_ALG_NODE * (e["ncells"] + 1))
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     plain_sheath = args.case == "sheath" and not args.floating and not args.smooth
-    traffic = traffic_from_profiles("sheath_1e5", pass_pushes) if plain_sheath else None
+    traffic = traffic_from_profiles("sheath_1e5", bytes_per_launch) if plain_sheath else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_pass32<push|collide|deposit>",
