@@ -302,8 +302,9 @@ int pic_adjoint_window(pic_ctx *ctx, int32_t nsteps, int32_t ckpt_every, void *s
                        double *dW_dEext, void *stream);
 
 /* The library's autotuner: times the particle pass over `trial_steps` steps for every
- * candidate launch shape (particles per thread x LDS window) and the sort scatter for each
- * particles-per-thread choice, all with HIP events on `stream`, keeps the fastest, and
+ * candidate launch shape (particles per thread x widest LDS window span x, for the fused
+ * pass, non-temporal streaming) and the sort scatter for each particles-per-thread and
+ * non-temporal-load choice, all with HIP events on `stream`, keeps the fastest, and
  * writes {ppt, window, sort_ppt, pass non-temporal, sort non-temporal} to `shape`
  * (5 ints, may be NULL).  The trial steps advance the
  * run like pic_step (the sort is repeated on already-sorted data, which leaves the state
