@@ -305,6 +305,15 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
             }
         }
     }
+    // The segment constants of the push and of the bounds below, read into registers before
+    // any global store or atomic (after one, a read through the segment reference would be
+    // repeated, since the store might alias it).
+    const float h = (float)S.h, dtdx = (float)S.dtdx, eext = (float)e.E_ext;
+    const float tv[3] = {(float)S.t[0], (float)S.t[1], (float)S.t[2]};
+    const float sv[3] = {(float)S.s[0], (float)S.s[1], (float)S.s[2]};
+    const int N = S.ncells;
+    const bool per = S.periodic != 0;
+    const int64_t seg_lo = S.base, seg_hi = S.base + S.cap;
     // sorting pass: destinations in the other buffer (-1: none)
     int64_t dst[SORT ? PPT : 1];
     if constexpr (SORT) {
@@ -327,7 +336,7 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
             dst[k] = -1;
             if (cell[k] == kDead) continue;
             const int64_t o = sbase + (int64_t)(inwin[k] ? sCnt[cell[k] - mn] + pos[k] : pos[k]);
-            if (o < S.base || o >= S.base + S.cap)
+            if (o < seg_lo || o >= seg_hi)
                 atomicOr(d.err, (int)E_CAP_PART);
             else
                 dst[k] = o;
@@ -340,13 +349,7 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
     const int st = stripe_of_block();
 
     if (PUSH) {
-        // segment constants in registers; the loop below is straight-line code apart from
-        // the rare wall branch
-        const float h = (float)S.h, dtdx = (float)S.dtdx, eext = (float)e.E_ext;
-        const float tv[3] = {(float)S.t[0], (float)S.t[1], (float)S.t[2]};
-        const float sv[3] = {(float)S.s[0], (float)S.s[1], (float)S.s[2]};
-        const int N = S.ncells;
-        const bool per = S.periodic != 0;
+        // the loop below is straight-line code apart from the rare wall branch
         uint32_t nwl = 0, nwr = 0, bad = 0;
         double kel = 0.0, ker = 0.0;
 #pragma unroll
