@@ -82,11 +82,19 @@ __device__ __forceinline__ void vstore(T *p, const T (&v)[PPT])
     }
 }
 
+// A segment's grid placement and shape, held in registers by the pass (read before its first
+// global store, so no store can force them to be read again).
+struct SegGrid {
+    int64_t gbase, cbase;
+    int ncells;
+    bool periodic;
+};
+
 // Cells a particle may move in one step and still deposit through the tile's window.
 constexpr int kWinMargin = 2;
 
 // One run of equal cells into the LDS window (or straight to HBM outside it).
-__device__ __forceinline__ void emit_run(const Dev &d, const SegC &S, int s, int cell, uint32_t cnt,
+__device__ __forceinline__ void emit_run(const Dev &d, const SegGrid &G, int s, int cell, uint32_t cnt,
                                          uint32_t sum, int wbase, int W, bool depo, bool hist,
                                          unsigned long long *sQ, uint32_t *sH)
 {
@@ -102,12 +110,12 @@ __device__ __forceinline__ void emit_run(const Dev &d, const SegC &S, int s, int
     }
     if (depo) {
         int j1 = cell + 1;
-        if (S.periodic && j1 == S.ncells) j1 = 0;
-        unsigned long long *Q = d.Qi + (int64_t)s * d.nodes_tot + S.gbase;
+        if (G.periodic && j1 == G.ncells) j1 = 0;
+        unsigned long long *Q = d.Qi + (int64_t)s * d.nodes_tot + G.gbase;
         atomicAdd(Q + cell, (unsigned long long)cnt * 16777216ull - (unsigned long long)sum);
         atomicAdd(Q + j1, (unsigned long long)sum);
     }
-    if (hist) atomicAdd(d.cellcnt + S.cbase + cell, cnt);
+    if (hist) atomicAdd(d.cellcnt + G.cbase + cell, cnt);
 }
 
 // Counting-sort ranking of one tile.  A particle whose cell lies in the window
@@ -314,6 +322,7 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
     const int N = S.ncells;
     const bool per = S.periodic != 0;
     const int64_t seg_lo = S.base, seg_hi = S.base + S.cap;
+    const SegGrid G{S.gbase, S.cbase, N, per};
     // sorting pass: destinations in the other buffer (-1: none)
     int64_t dst[SORT ? PPT : 1];
     if constexpr (SORT) {
@@ -509,7 +518,7 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
         for (int k = 0; k < PPT; ++k) {
             const bool alive = cell[k] != kDead;
             if (alive && cell[k] != rk) {
-                if (rk != kDead) emit_run(d, S, s, rk, rc, rs, wbase, Wt, DEPO, hist, sQ, sH);
+                if (rk != kDead) emit_run(d, G, s, rk, rc, rs, wbase, Wt, DEPO, hist, sQ, sH);
                 rk = cell[k];
                 rc = 0;
                 rs = 0;
@@ -517,7 +526,7 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
             rc += alive ? 1u : 0u;
             if (DEPO) rs += alive ? fixed_share(off[k]) : 0u;
         }
-        if (rk != kDead) emit_run(d, S, s, rk, rc, rs, wbase, Wt, DEPO, hist, sQ, sH);
+        if (rk != kDead) emit_run(d, G, s, rk, rc, rs, wbase, Wt, DEPO, hist, sQ, sH);
     }
 
     // block tallies
@@ -531,21 +540,21 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
     }
     __syncthreads();
     if (WIN) {
-        const int nn = S.periodic ? S.ncells : S.ncells + 1;
-        unsigned long long *Q = d.Qi + (int64_t)s * d.nodes_tot + S.gbase;
+        const int nn = G.periodic ? G.ncells : G.ncells + 1;
+        unsigned long long *Q = d.Qi + (int64_t)s * d.nodes_tot + G.gbase;
         for (int i = tid; Wt > 0 && i <= Wt; i += 256) {
             if (DEPO) {
                 const unsigned long long v = sQ[i];
                 if (v) {
                     int node = wbase + i;
-                    if (S.periodic && node >= S.ncells) node -= S.ncells;
+                    if (G.periodic && node >= G.ncells) node -= G.ncells;
                     if (node < nn) atomicAdd(Q + node, v);
                 }
             }
             if (hist && i < Wt) {
                 const uint32_t c = sH[i];
                 const int cl = wbase + i;
-                if (c && cl < S.ncells) atomicAdd(d.cellcnt + S.cbase + cl, c);
+                if (c && cl < G.ncells) atomicAdd(d.cellcnt + G.cbase + cl, c);
             }
         }
     }
