@@ -103,6 +103,8 @@ def lib():
         L.orc_last_channels.argtypes = [P, C.c_int, P, P]
         L.orc_last_channels.restype = C.c_int64
         L.orc_last_numax.argtypes = [P, P, P]
+        L.orc_moments.argtypes = [P, C.c_int, P, P, P, P, P]
+        L.orc_moments.restype = None
         L.orc_set_step.argtypes = [P, C.c_int64]
         L.orc_init_particle.argtypes = [C.POINTER(_Config), C.c_int, C.c_int64, P, P, P, P]
         L.orc_philox4x32_10.argtypes = [P, P, P]
@@ -243,6 +245,12 @@ class Oracle:
         d = Diag()
         self.L.orc_get_diag(self.h, C.byref(d))
         return d.as_dict()
+
+    def moments(self, s):
+        """Node moments of species s (reading R27): dict of n, ux, uy, uz, T per node."""
+        out = {k: np.zeros(self.nnodes) for k in ("n", "ux", "uy", "uz", "T")}
+        self.L.orc_moments(self.h, int(s), *(_ptr(out[k]) for k in ("n", "ux", "uy", "uz", "T")))
+        return out
 
     def last_channels(self, s):
         cap = self.e["species"][s]["capacity"]

@@ -159,6 +159,21 @@ static double node_volume(const orc_state *st, int64_t j)
 
 static double speed2(double vx, double vy, double vz) { return vx * vx + vy * vy + vz * vz; }
 
+/* Cell j = floor(x / dx) and fraction f = x / dx - j of a position inside the grid.
+ * Reading R8 keeps every x < L inside, but for a dx that is not a power of two x / dx can
+ * round up to N for x just below L: such a particle belongs to the last cell (f = 1).
+ * Returns -1 for a position outside [0, L).                                              */
+static int64_t cell_index(const orc_state *st, double x, double *f)
+{
+    const orc_config *c = &st->cfg;
+    double g = x / c->dx;
+    double jf = floor(g);
+    if (!(x >= 0.0) || !(x < dlen(st))) return -1;
+    if (jf > (double)(c->ncells - 1)) jf = (double)(c->ncells - 1);
+    *f = g - jf;
+    return (int64_t)jf;
+}
+
 static void recompute_vmax(orc_state *st, int s)
 {
     double m2 = 0.0;
@@ -349,16 +364,14 @@ void orc_deposit(orc_state *st)
         double *Q = st->Q[s];
         memset(Q, 0, (size_t)(st->nnodes + 1) * sizeof(double));
         for (int64_t p = 0; p < st->n[s]; p++) {
-            double g = st->x[s][p] / c->dx;
-            double jf = floor(g);
-            double f = g - jf;
-            int64_t j = (int64_t)jf;
-            int64_t j1 = j + 1;
-            if (c->periodic && j1 == c->ncells) j1 = 0;
-            if (j < 0 || j >= c->ncells) {
+            double f = 0.0;
+            int64_t j = cell_index(st, st->x[s][p], &f);
+            if (j < 0) {
                 st->err = 2;
                 continue;
             }
+            int64_t j1 = j + 1;
+            if (c->periodic && j1 == c->ncells) j1 = 0;
             Q[j] += 1.0 - f;
             Q[j1] += f;
         }
@@ -500,10 +513,12 @@ void orc_push(orc_state *st)
         double sf = 2.0 / (1.0 + tt);
         double sv[3] = {sf * t[0], sf * t[1], sf * t[2]};
         for (int64_t p = 0; p < st->n[s]; p++) {
-            double g = st->x[s][p] / c->dx;
-            double jf = floor(g);
-            double f = g - jf;
-            int64_t j = (int64_t)jf;
+            double f = 0.0;
+            int64_t j = cell_index(st, st->x[s][p], &f);
+            if (j < 0) {
+                st->err = 2;
+                continue;
+            }
             int64_t j1 = j + 1;
             if (c->periodic && j1 == c->ncells) j1 = 0;
             double Ep = (1.0 - f) * st->E[j] + f * st->E[j1] + c->E_ext;
@@ -821,8 +836,8 @@ void orc_collide(orc_state *st)
 }
 
 /* ------------------------------------------------------------------------------------ */
-/* Stable counting sort of each species by cell index floor(x / dx): histogram, exclusive
- * scan, scatter in input order.                                                           */
+/* Stable counting sort of each species by cell index floor(x / dx) (folded into the last
+ * cell when it rounds up to N): histogram, exclusive scan, scatter in input order.                                                           */
 void orc_sort(orc_state *st)
 {
     const orc_config *c = &st->cfg;
@@ -833,7 +848,12 @@ void orc_sort(orc_state *st)
         int64_t *cellof = (int64_t *)malloc((size_t)(n + 1) * sizeof(int64_t));
         memset(start, 0, (size_t)(N + 1) * sizeof(int64_t));
         for (int64_t p = 0; p < n; p++) {
-            cellof[p] = (int64_t)floor(st->x[s][p] / c->dx);
+            double f = 0.0;
+            cellof[p] = cell_index(st, st->x[s][p], &f);
+            if (cellof[p] < 0) {  /* not a valid state: keep the particle, first cell */
+                st->err = 2;
+                cellof[p] = 0;
+            }
             start[cellof[p] + 1] += 1;
         }
         for (int64_t j = 0; j < N; j++) start[j + 1] += start[j];
@@ -920,6 +940,57 @@ void orc_get_diag(orc_state *st, orc_diag *out)
     d.step = st->step;
     d.neutral_count = st->nneu;
     *out = d;
+}
+
+/* Node moments of species s (reading R27): with the cloud-in-cell shares S_j(x_p) of the
+ * deposit, W_j = sum_p S_j, the number density n_j = w_s W_j / V_j, the mean velocity
+ * u_j = sum_p S_j v_p / W_j (three components) and the temperature
+ * T_j = (m_s / 3) (sum_p S_j |v_p|^2 / W_j - |u_j|^2); u_j = T_j = 0 where W_j = 0.
+ * Output arrays of length nnodes: n, ux, uy, uz, T (any may be NULL).                     */
+void orc_moments(const orc_state *st, int s, double *n, double *ux, double *uy, double *uz,
+                 double *T)
+{
+    const orc_config *c = &st->cfg;
+    int64_t nn = st->nnodes;
+    double *W = (double *)calloc((size_t)nn + 1, sizeof(double));
+    double *Wv[3];
+    for (int k = 0; k < 3; k++) Wv[k] = (double *)calloc((size_t)nn + 1, sizeof(double));
+    double *Wv2 = (double *)calloc((size_t)nn + 1, sizeof(double));
+    if (s >= 0 && s < c->nspecies) {
+        for (int64_t p = 0; p < st->n[s]; p++) {
+            double f = 0.0;
+            int64_t j = cell_index(st, st->x[s][p], &f);
+            if (j < 0) continue;
+            int64_t j1 = j + 1;
+            if (c->periodic && j1 == c->ncells) j1 = 0;
+            double v[3] = {st->vx[s][p], st->vy[s][p], st->vz[s][p]};
+            double v2 = speed2(v[0], v[1], v[2]);
+            double sh[2] = {1.0 - f, f};
+            int64_t nd[2] = {j, j1};
+            for (int a = 0; a < 2; a++) {
+                W[nd[a]] += sh[a];
+                for (int k = 0; k < 3; k++) Wv[k][nd[a]] += sh[a] * v[k];
+                Wv2[nd[a]] += sh[a] * v2;
+            }
+        }
+    }
+    double w = (s >= 0 && s < c->nspecies) ? c->sp[s].w : 0.0;
+    double m = (s >= 0 && s < c->nspecies) ? c->sp[s].m : 0.0;
+    for (int64_t j = 0; j < nn; j++) {
+        double u[3] = {0.0, 0.0, 0.0}, t = 0.0;
+        if (W[j] > 0.0) {
+            for (int k = 0; k < 3; k++) u[k] = Wv[k][j] / W[j];
+            t = (m / 3.0) * (Wv2[j] / W[j] - speed2(u[0], u[1], u[2]));
+        }
+        if (n) n[j] = w * W[j] / node_volume(st, j);
+        if (ux) ux[j] = u[0];
+        if (uy) uy[j] = u[1];
+        if (uz) uz[j] = u[2];
+        if (T) T[j] = t;
+    }
+    free(W);
+    for (int k = 0; k < 3; k++) free(Wv[k]);
+    free(Wv2);
 }
 
 int64_t orc_last_channels(const orc_state *st, int s, int32_t *chan, uint32_t *ids)

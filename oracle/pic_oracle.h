@@ -64,6 +64,9 @@
  *       over [0, src_frac L); their ids precede the step's births.
  *   R26 relative-speed charge exchange: the rate uses the speed relative to a sampled
  *       neutral, and an exchanged ion takes that neutral's velocity.
+ *   R27 node moments per species from the cloud-in-cell shares S_j of the deposit:
+ *       n_j = w sum S_j / V_j, u_j = sum S_j v / sum S_j, T_j = (m/3)(sum S_j |v|^2 /
+ *       sum S_j - |u_j|^2), zero mean and temperature at nodes no particle touches.
  */
 #ifndef PIC_ORACLE_H
 #define PIC_ORACLE_H
@@ -168,6 +171,11 @@ void orc_get_grid(const orc_state *st, double *Q0, double *Q1, double *rho, doub
 void orc_get_diag(orc_state *st, orc_diag *out);
 /* Collision bookkeeping of the last orc_collide call: per alive particle (post-wall order)
  * the channel taken (-1 none, 0 elastic, 1 ionisation, 2 CX), and nu_max per species. */
+/* Node moments of species s from the cloud-in-cell shares (reading R27): number density
+ * n_j = w W_j / V_j, mean velocity u_j and temperature T_j = (m/3)(<|v|^2>_j - |u_j|^2),
+ * each an array of nnodes (NULL skips it). */
+void orc_moments(const orc_state *st, int s, double *n, double *ux, double *uy, double *uz,
+                 double *T);
 int64_t orc_last_channels(const orc_state *st, int s, int32_t *chan, uint32_t *ids);
 void orc_last_numax(const orc_state *st, double *numax, double *pnull);
 void orc_set_step(orc_state *st, int64_t step);

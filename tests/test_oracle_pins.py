@@ -922,3 +922,247 @@ def test_sheath_case_recipes_match_the_papers_sizes():
     e2 = synth.c7_sheath_source(ncells=nu["cells"])["ensembles"][0]
     assert all(sp["ppc"] == 0 for sp in e2["species"]) == nu["initially_empty"]
     assert e2["src_frac"] == 0.5 and e2["src_pairs"] > 0
+
+
+# ---------------------------------------------------------------------------------------
+# Diagnostics: kinetic energy, absorbed kinetic energy, field energy (its node volumes)
+# ---------------------------------------------------------------------------------------
+def test_kinetic_energy_equipartition_of_the_load():
+    """A Maxwellian load at T_s holds (3/2) T_s per particle on average: KE_s ~ 3/2 P w T
+    within sampling error (the sum of |v|^2 / v_th^2 is chi-square with 3P degrees of
+    freedom).  Masses 1 and 73440, weights w = dx / ppc != 1 and the factor 1/2 all enter."""
+    e = synth.ensemble(200, 150, collisions=False)
+    o = oracle.Oracle(e)
+    d = o.diag()
+    for s, sp in enumerate(e["species"]):
+        P = sp["ppc"] * e["ncells"]
+        mean = 1.5 * P * sp["w"] * sp["T"]
+        sigma = mean * math.sqrt(2.0 / (3.0 * P))
+        assert abs(d["ke"][s] - mean) <= 4.0 * sigma, (s, d["ke"][s], mean, sigma)
+        assert d["count"][s] == P
+    assert d["charge"] == pytest.approx(0.0, abs=1e-9)
+
+
+def test_kinetic_energy_of_hand_placed_particles():
+    """Three electrons and two ions with speeds 5, 3, 1 and 2, 7 (Pythagorean triples),
+    with weights and masses away from one: KE_s = 1/2 m w sum |v|^2 by hand."""
+    e = synth.ensemble(16, 1, collisions=False)
+    e["species"][0]["w"], e["species"][1]["w"] = 0.375, 2.5
+    o = oracle.Oracle(e, init=False)
+    dx = e["dx"]
+    o.set_particles(0, [1.1 * dx, 5.5 * dx, 9.0 * dx], [3.0, 2.0, 0.0], [4.0, 1.0, 0.0],
+                    [0.0, 2.0, -1.0], [0, 1, 2], 3)
+    o.set_particles(1, [2.0 * dx, 3.25 * dx], [0.0, 2.0], [-2.0, 3.0], [0.0, 6.0], [0, 1], 2)
+    d = o.diag()
+    # electrons: |v|^2 = 25 + 9 + 1 = 35, m = 1, w = 0.375 -> 6.5625
+    assert d["ke"][0] == pytest.approx(6.5625, rel=1e-15)
+    # ions: |v|^2 = 4 + 49 = 53, m = 73440, w = 2.5 -> 4865400
+    assert d["ke"][1] == pytest.approx(4865400.0, rel=1e-15)
+    assert d["count"] == [3, 2]
+    assert d["charge"] == pytest.approx(-3 * 0.375 + 2 * 2.5, rel=1e-15)
+
+
+@pytest.mark.parametrize("bfield", [False, True])
+def test_wall_kinetic_energy_closes_the_energy_balance(bfield):
+    """In zero E the push keeps every speed (Boris rotates v about B), so whatever kinetic
+    energy leaves the plasma is exactly what the walls tally: KE(0) = KE(n) + sum wall_ke,
+    at every step, per species; and the left / right split matches the exits a free
+    streamer makes (B = 0)."""
+    N = 64
+    e = synth.ensemble(N, 100, collisions=False, B=synth.oblique_B() if bfield else None)
+    e["species"][1]["w"] = 0.02
+    st = synth.random_state(e, [4000, 4000], seed=33, vscale=[1.0, 0.3])
+    o = oracle.Oracle(e, init=False)
+    o.set_state(st)
+    o.set_fields(np.zeros(o.nnodes))
+    ke0 = o.diag()["ke"]
+    L, dt = N * e["dx"], e["dt"]
+    # free streamers, advanced by the same repeated FP64 additions
+    x = [st[s]["x"].astype(np.float64).copy() for s in range(2)]
+    for n in range(1, 41):
+        o.push()
+        o.walls()
+        d = o.diag()
+        for s in range(2):
+            absorbed = d["wall_ke"][0][s] + d["wall_ke"][1][s]
+            assert abs(d["ke"][s] + absorbed - ke0[s]) <= 1e-12 * ke0[s], (n, s)
+            if not bfield:
+                sp = e["species"][s]
+                v = np.stack([st[s]["vx"], st[s]["vy"], st[s]["vz"]]).astype(np.float64)
+                inside = (x[s] >= 0) & (x[s] < L)
+                x[s] = np.where(inside, x[s] + dt * st[s]["vx"].astype(np.float64), x[s])
+                e2 = 0.5 * sp["m"] * sp["w"] * (v * v).sum(axis=0)
+                x_s = x[s]
+                assert d["wall_ke"][0][s] == pytest.approx(e2[x_s < 0].sum(), rel=1e-12)
+                assert d["wall_ke"][1][s] == pytest.approx(e2[x_s >= L].sum(), rel=1e-12)
+    assert min(d["wall_count"][w][s] for w in range(2) for s in range(2)) > 10
+
+
+def test_field_energy_periodic_single_mode():
+    """Periodic grid, E_j = A sin(2 pi m j / N): discrete orthogonality gives
+    sum_j E_j^2 dx = A^2 L / 2 exactly, so W = eps0 A^2 L / 4."""
+    N, A, m = 96, 0.7, 5
+    e = synth.ensemble(N, 1, nspecies=1, periodic=True, collisions=False)
+    e["eps0"] = 2.0
+    o = oracle.Oracle(e, init=False)
+    j = np.arange(N)
+    o.set_fields(A * np.sin(2 * np.pi * m * j / N))
+    L = N * e["dx"]
+    assert o.diag()["field_energy"] == pytest.approx(e["eps0"] * A * A * L / 4.0, rel=1e-13)
+
+
+@pytest.mark.parametrize("m", [1, 4, 17])
+def test_field_energy_bounded_uses_half_cells_at_the_walls(m):
+    """Bounded grid, E_j = cos(pi m j / N) on nodes 0..N: the trapezoid sum (wall nodes
+    weighted dx / 2) of cos^2 is exactly L / 2 for 0 < m < N (orthogonality of DCT-I); a
+    full cell at the walls would add dx."""
+    N = 40
+    e = synth.ensemble(N, 1, nspecies=1, collisions=False)
+    o = oracle.Oracle(e, init=False)
+    j = np.arange(N + 1)
+    o.set_fields(np.cos(np.pi * m * j / N))
+    L = N * e["dx"]
+    assert o.diag()["field_energy"] == pytest.approx(0.5 * e["eps0"] * L / 2.0, rel=1e-13)
+
+
+def test_field_energy_of_uniform_charge_closed_form():
+    """Uniform charge on every node, walls included (two unit particles per interior node,
+    one on each wall node): the grounded solve gives the linear E_j = rho (x_j - L/2) / eps0
+    at every node (the half-cell Gauss rule at the walls included).  The trapezoid sum of
+    the quadratic E^2 is exact up to its Euler-Maclaurin term:
+    W = rho^2 / (2 eps0) (L^3 / 12 + dx^2 L / 6)."""
+    N = 30
+    e = _one_species(N)
+    e["species"][0]["q"] = 1.0
+    o = oracle.Oracle(e, init=False)
+    dx = e["dx"]
+    L = N * dx
+    x = np.concatenate([np.repeat(np.arange(1, N) * dx, 2), [0.0, np.nextafter(L, 0.0)]])
+    n = len(x)
+    o.set_particles(0, x, np.zeros(n), np.zeros(n), np.zeros(n), np.arange(n), n)
+    o.deposit()
+    o.solve()
+    g = o.grid()
+    rho = 2.0 * e["species"][0]["w"] / dx
+    assert np.max(np.abs(g["rho"] - rho)) <= 1e-12 * rho
+    xs = np.arange(N + 1) * dx
+    assert np.max(np.abs(g["E"] - rho * (xs - L / 2))) <= 1e-11 * rho * L
+    W = rho * rho / (2 * e["eps0"]) * (L**3 / 12.0 + dx * dx * L / 6.0)
+    assert o.diag()["field_energy"] == pytest.approx(W, rel=1e-11)
+
+
+# ---------------------------------------------------------------------------------------
+# Positions that round up to the last node (x just below L, dx not a power of two)
+# ---------------------------------------------------------------------------------------
+def test_position_rounding_to_L_stays_in_the_last_cell():
+    N = 10
+    e = _one_species(N)
+    e["dx"] = 0.35
+    L = N * e["dx"]
+    x = np.nextafter(L, 0.0)
+    assert x < L and x / e["dx"] == N           # the case: x / dx rounds up to N
+    o = oracle.Oracle(e, init=False)
+    xs = [x, 0.45, 2.0]
+    o.set_particles(0, xs, [0.0, 0.0, 0.0], [0.0] * 3, [0.0] * 3, [0, 1, 2], 3)
+    o.deposit()
+    Q = o.grid()["Q"][0]
+    assert o.error == 0
+    nodes = np.arange(N + 1) * e["dx"]
+    assert Q.sum() == pytest.approx(3.0, rel=1e-15)
+    assert (Q * nodes).sum() == pytest.approx(sum(xs), rel=1e-14)   # CIC first moment
+    assert Q[N] == pytest.approx(1.0, abs=1e-12)                     # all on the wall node
+    # the gather interpolates E_N there, and the sort keeps it last
+    E = np.arange(N + 1, dtype=np.float64)
+    o.set_fields(E)
+    o.push()
+    p = o.particles(0)
+    h = e["species"][0]["q"] / e["species"][0]["m"] * e["dt"]
+    assert p["vx"][0] == pytest.approx(h * E[N], rel=1e-12)
+    o.set_particles(0, xs, [0.0] * 3, [0.0] * 3, [0.0] * 3, [0, 1, 2], 3)
+    o.sort()
+    assert list(o.particles(0)["id"]) == [1, 2, 0]
+    assert o.error == 0
+
+
+# ---------------------------------------------------------------------------------------
+# Node moments (R27)
+# ---------------------------------------------------------------------------------------
+def test_moments_of_two_hand_placed_particles():
+    """Two particles in cell 3 at fractions 1/4 and 3/4 with v_x = +1 and -1: node 3 gets
+    shares 3/4, 1/4, node 4 shares 1/4, 3/4, so n = w / dx, u_x = +1/2 and -1/2, and
+    T = (m/3)(1 - 1/4) = m / 4 at both; every other node is empty."""
+    N = 8
+    e = _one_species(N)
+    e["species"][0]["m"], e["species"][0]["w"] = 3.0, 0.6
+    o = oracle.Oracle(e, init=False)
+    dx = e["dx"]
+    o.set_particles(0, [3.25 * dx, 3.75 * dx], [1.0, -1.0], [0.0, 0.0], [0.0, 0.0], [0, 1], 2)
+    mo = o.moments(0)
+    assert mo["n"][3] == pytest.approx(0.6 / dx, rel=1e-15)
+    assert mo["n"][4] == pytest.approx(0.6 / dx, rel=1e-15)
+    assert mo["ux"][3] == pytest.approx(0.5, rel=1e-15) and mo["ux"][4] == pytest.approx(-0.5, rel=1e-15)
+    assert mo["T"][3] == pytest.approx(0.75, rel=1e-14) and mo["T"][4] == pytest.approx(0.75, rel=1e-14)
+    others = np.r_[0:3, 5:N + 1]
+    for k in ("n", "ux", "uy", "uz", "T"):
+        assert np.all(mo[k][others] == 0.0)
+
+
+def test_moments_of_a_cold_drifting_beam_are_exact():
+    """Every particle moves with the same velocity: the mean velocity is that velocity and
+    the temperature vanishes at every touched node, to rounding."""
+    N = 50
+    e = synth.ensemble(N, 20, nspecies=1, collisions=False)
+    st = synth.random_state(e, [1000], seed=41)
+    u = (0.3, -1.7, 2.2)
+    o = oracle.Oracle(e, init=False)
+    n = len(st[0]["x"])
+    o.set_particles(0, st[0]["x"], np.full(n, u[0]), np.full(n, u[1]), np.full(n, u[2]), st[0]["id"], n)
+    mo = o.moments(0)
+    touched = mo["n"] > 0
+    assert touched.sum() >= N - 2
+    for k, uk in zip(("ux", "uy", "uz"), u):
+        assert np.max(np.abs(mo[k][touched] - uk)) <= 1e-14 * abs(uk)
+    assert np.max(np.abs(mo["T"][touched])) <= 1e-13 * 9.0
+
+
+def test_moments_of_the_maxwellian_load():
+    """The uniform Maxwellian load: n ~ n0 = 1 (the weight is dx / ppc), u ~ 0 and T ~ T_s
+    at every node, walls included (half cells there), within a few sampling sigmas."""
+    ppc = 2000
+    e = synth.ensemble(60, ppc, collisions=False)
+    o = oracle.Oracle(e)
+    for s, sp in enumerate(e["species"]):
+        mo = o.moments(s)
+        # about ppc particles' shares per node (ppc / 2 at the walls); loose sampling bounds
+        assert np.max(np.abs(mo["n"] - 1.0)) <= 6.0 / math.sqrt(ppc / 2)
+        vth = math.sqrt(sp["T"] / sp["m"])
+        for k in ("ux", "uy", "uz"):
+            assert np.max(np.abs(mo[k])) <= 6.0 * vth / math.sqrt(ppc / 2)
+        assert np.max(np.abs(mo["T"] / sp["T"] - 1.0)) <= 6.0 * math.sqrt(2.0 / 3.0) / math.sqrt(ppc / 2)
+
+
+def test_moments_sum_to_count_momentum_and_kinetic_energy():
+    """The shares of one particle sum to one, so the moments integrate back exactly:
+    sum_j n_j V_j = w P, sum_j n_j u_j V_j = w sum_p v_p and
+    sum_j n_j V_j (3 T_j / m + |u_j|^2) m / 2 = KE (the kinetic-energy diagnostic)."""
+    for periodic in (False, True):
+        e = synth.ensemble(77, 30, collisions=False, periodic=periodic)
+        st = synth.random_state(e, [2000, 1500], seed=43, vscale=[1.3, 0.01])
+        o = oracle.Oracle(e, init=False)
+        o.set_state(st)
+        d = o.diag()
+        V = np.full(o.nnodes, e["dx"])
+        if not periodic:
+            V[0] = V[-1] = e["dx"] / 2
+        for s, sp in enumerate(e["species"]):
+            mo = o.moments(s)
+            nV = mo["n"] * V
+            assert nV.sum() == pytest.approx(sp["w"] * len(st[s]["x"]), rel=1e-13)
+            for k in ("vx", "vy", "vz"):
+                vk = st[s][k].astype(np.float64)
+                ref = sp["w"] * vk.sum()
+                got = (nV * mo["u" + k[1]]).sum()
+                assert abs(got - ref) <= 1e-12 * sp["w"] * np.abs(vk).sum()
+            u2 = mo["ux"] ** 2 + mo["uy"] ** 2 + mo["uz"] ** 2
+            ke = (nV * (3.0 * mo["T"] / sp["m"] + u2)).sum() * sp["m"] / 2.0
+            assert ke == pytest.approx(d["ke"][s], rel=1e-12)
