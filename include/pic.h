@@ -72,6 +72,9 @@
  *       over [0, src_frac L); their ids precede the step's births.
  *   R26 relative-speed charge exchange: the rate uses the speed relative to a sampled
  *       neutral, and an exchanged ion takes that neutral's velocity.
+ *   R27 node moments per species from the cloud-in-cell shares S_j of the deposit:
+ *       n_j = w sum S_j / V_j, u_j = sum S_j v / sum S_j, T_j = (m/3)(sum S_j |v|^2 /
+ *       sum S_j - |u_j|^2), zero mean and temperature at nodes no particle touches.
  */
 #ifndef PIC_H
 #define PIC_H
@@ -233,15 +236,39 @@ int pic_sort(pic_ctx *ctx, void *stream);
 
 /* nsteps full steps (R2 order): solve, push + walls, collide, deposit, and a sort when
  * the new step count is a multiple of K.  With cfg.fused = 1 the particle stages run as
- * one pass per step and the steps replay a captured HIP graph; in the FP32 form with
+ * one pass per step and the steps replay captured HIP graphs (see pic_graph_prepare);
+ * in the FP32 form with
  * K >= 2 the step before a sort step also counts the cells, and the sort step's pass
  * writes the particles in the order of the cells they held before its push (so the
  * particles are ordered by cell up to that push, and the sort costs no kernel of its
  * own).  Synchronises the stream once at the end to read the sticky error flags. */
 int pic_step(pic_ctx *ctx, int32_t nsteps, void *stream);
 
-/* Scalars of ensemble `ens` (synchronises `stream`). */
-int pic_diag(pic_ctx *ctx, int32_t ens, pic_diag_out *out, void *stream);
+/* Instantiate, without running them, the HIP graphs that pic_step(ctx, nsteps) would
+ * replay from the current state, so that a later pic_step of that many steps spends no
+ * time on capture (e.g. before a timed or latency-bound loop).  A fused run replays one
+ * graph per window of up to K steps: whole sort cycles from whatever phase of the cycle
+ * the run is in, then a shorter tail, which replays from a graph only if this call
+ * prepared it (otherwise those steps run eagerly).  Graphs stay valid until pic_load,
+ * pic_autotune or pic_free.  A no-op for cfg.fused = 0. */
+int pic_graph_prepare(pic_ctx *ctx, int32_t nsteps);
+
+/* Number of graph replays pic_step has made on this context (so a caller can tell that a
+ * run went through the graph path). */
+int pic_graph_launches(const pic_ctx *ctx, int64_t *launches);
+
+/* Diagnostics of ensemble `ens` (synchronises `stream`).  `out` receives the scalars.
+ * `moments_dev` is NULL or device memory of 5 x nspecies x nnodes doubles (nnodes from
+ * pic_nnodes), laid out [species][quantity][node] with the quantities, per node j, of
+ * reading R27 computed from the cloud-in-cell shares S_j of the deposit: number density
+ * n_j = w sum S_j / V_j (V_j = dx, dx/2 at bounded walls), mean velocity
+ * u_j = sum S_j v / sum S_j (x, y, z) and temperature
+ * T_j = (m/3)(sum S_j |v|^2 / sum S_j - |u_j|^2), with u_j = T_j = 0 at nodes no particle
+ * touches.  These are the per-species density, flow and temperature profiles that the
+ * paper's input-parameter table switches on as time-averaged output and its in-situ
+ * analysis plots (results section).  Sums in FP64 atomics: the last bits depend on order.
+ * The library overwrites the whole array; the caller owns it. */
+int pic_diag(pic_ctx *ctx, int32_t ens, pic_diag_out *out, double *moments_dev, void *stream);
 
 /* Copy the alive particles of (ens, species) to host arrays of length >= `cap`; `count`
  * receives the number written.  Order unspecified (compare by id).  Species 2 is the

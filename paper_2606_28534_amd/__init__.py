@@ -25,7 +25,8 @@ EXPORTS = ("pic_query_workspace", "pic_init", "pic_deposit", "pic_solve", "pic_p
            "pic_set_fields", "pic_set_step",
            "pic_nnodes", "pic_set_external_field", "pic_adjoint_query",
            "pic_adjoint_window", "pic_autotune", "pic_checkpoint_size", "pic_save", "pic_load",
-           "pic_timing", "pic_timing_read", "pic_free", "pic_last_error")
+           "pic_timing", "pic_timing_read", "pic_graph_prepare", "pic_graph_launches",
+           "pic_free", "pic_last_error")
 
 
 class PicError(RuntimeError):
@@ -106,7 +107,7 @@ def load_library():
     for n in ("pic_deposit", "pic_solve", "pic_push", "pic_collide", "pic_sort"):
         getattr(L, n).argtypes = [P, P]
     L.pic_step.argtypes = [P, C.c_int32, P]
-    L.pic_diag.argtypes = [P, C.c_int32, C.POINTER(DiagOut), P]
+    L.pic_diag.argtypes = [P, C.c_int32, C.POINTER(DiagOut), P, P]
     L.pic_get_particles.argtypes = [P, C.c_int32, C.c_int32, Particles, C.c_int64,
                                     C.POINTER(C.c_int64), P]
     L.pic_set_particles.argtypes = [P, C.c_int32, C.c_int32, Particles, C.c_int64, C.c_uint32, P]
@@ -126,6 +127,8 @@ def load_library():
     L.pic_save.argtypes = [P, P, C.c_size_t, P]
     L.pic_load.argtypes = [P, P, C.c_size_t, P]
     L.pic_timing.argtypes = [P, C.c_int32]
+    L.pic_graph_prepare.argtypes = [P, C.c_int32]
+    L.pic_graph_launches.argtypes = [P, C.POINTER(C.c_int64)]
     L.pic_timing_read.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64), P]
     L.pic_free.argtypes = [P]
     L.pic_free.restype = None
@@ -243,6 +246,16 @@ class Sim:
     def step(self, n=1):
         self._check(self.L.pic_step(self.h, int(n), self._s()))
 
+    def prepare(self, n):
+        """Instantiate the HIP graphs that step(n) would replay from here (no steps run)."""
+        self._check(self.L.pic_graph_prepare(self.h, int(n)))
+
+    def graph_launches(self):
+        """Graph replays made by step() so far."""
+        n = C.c_int64(0)
+        self._check(self.L.pic_graph_launches(self.h, C.byref(n)))
+        return n.value
+
     def set_external_field(self, E_ext, ens=0):
         self._check(self.L.pic_set_external_field(self.h, int(ens), float(E_ext)))
 
@@ -297,8 +310,22 @@ class Sim:
     # ---- data exchange ------------------------------------------------------------------
     def diag(self, ens=0):
         d = DiagOut()
-        self._check(self.L.pic_diag(self.h, int(ens), C.byref(d), self._s()))
+        self._check(self.L.pic_diag(self.h, int(ens), C.byref(d), None, self._s()))
         return d.as_dict()
+
+    def moments(self, ens=0):
+        """Node moments (reading R27) of each species of ensemble `ens`: a list of dicts
+        with n, ux, uy, uz, T per node (host arrays), computed by the library's kernels
+        into a device buffer through pic_diag."""
+        import torch
+
+        nn = self.nnodes(ens)
+        buf = torch.empty(self.nspecies * 5 * nn, dtype=torch.float64, device="cuda")
+        d = DiagOut()
+        self._check(self.L.pic_diag(self.h, int(ens), C.byref(d), C.c_void_p(buf.data_ptr()), self._s()))
+        m = buf.cpu().numpy().reshape(self.nspecies, 5, nn)
+        return [{k: m[s, q].copy() for q, k in enumerate(("n", "ux", "uy", "uz", "T"))}
+                for s in range(self.nspecies)]
 
     def nnodes(self, ens=0):
         return int(self.L.pic_nnodes(self.h, int(ens)))

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -187,6 +188,7 @@ int build_plan(const pic_config *cfg, Plan &P, std::string &msg)
             S.other = (s == 0 && P.nspecies > 1) ? (int32_t)(P.seg.size() + 1) : -1;
             S.recycle = (s == 1 && D.recycle) ? 1 : 0;
             S.vth = std::sqrt(sp.T / sp.m);
+            S.w = sp.w;
             if (s == 1) icap += sp.capacity;
             E.seg[s] = (int32_t)P.seg.size();
             P.seg.push_back(S);
@@ -332,7 +334,11 @@ struct pic_ctx {
     // removes particles between steps clears it (that step then sorts the usual way).
     bool sort_ready = false;
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t graph = nullptr;
+    // captured windows of the fused step, keyed by (first step's phase in the sort cycle,
+    // number of steps); each replays from that phase with the prepared-sort state the
+    // phase implies
+    std::map<int64_t, hipGraphExec_t> graphs;
+    int64_t graph_launches = 0;
     std::string msg;
     // measurement hook
     bool timing = false;
@@ -447,27 +453,40 @@ hipError_t enqueue_step(pic_ctx *c, hipStream_t s, int64_t n, bool &ready, bool 
     return hipSuccess;
 }
 
-// One sort cycle (K steps) of the fused step with collisions, for graph capture.  The
-// births of step i - 1 are ranked and placed by extra blocks of step i's two solve
-// kernels instead of kernels of their own: the placement touches new particle slots, the
-// slot and id counters, the birth lists and bitmaps, the speed-maximum halves and the step
-// counter, the solve only the grid, so they run side by side, and the collision
-// parameters and the particle pass after them see both.  The last step's births are
-// placed in line at the end (before the sort when it has kernels of its own).  The FP32
-// form pipelines the sort as enqueue_step does: step K - 2 counts and scans, step K - 1's
-// pass sorts.  The state after the cycle is the same as after K calls of enqueue_step.
-hipError_t enqueue_cycle_merged(pic_ctx *c, hipStream_t s)
+// A window of `len` steps of the fused step, starting at step count n0, for graph capture.
+// With collisions (and births small enough for the solve's extra blocks) the births of
+// step i - 1 are ranked and placed by extra blocks of step i's two solve kernels instead
+// of kernels of their own: the placement touches new particle slots, the slot and id
+// counters, the birth lists and bitmaps, the speed-maximum halves and the step counter,
+// the solve only the grid, so they run side by side, and the collision parameters and the
+// particle pass after them see both.  A step that sorts in kernels of its own (FP64, K = 1,
+// or no prepared counts) places its births in line before its sort, and so does the last
+// step of the window.  The FP32 form pipelines the sort as enqueue_step does: the step
+// before a sort step counts and scans, the sort step's pass sorts.  `ready` is the
+// prepared-sort state on entry and on exit.  The state after the window is the same as
+// after `len` calls of enqueue_step.
+hipError_t enqueue_window(pic_ctx *c, hipStream_t s, int64_t n0, int len, bool &ready)
 {
     const Dev &d = c->d;
     const bool f64 = c->P.f64;
+    const bool coll = c->cfg.collisions != 0;
+    hipError_t e;
+    if (!coll || !births_fit_solve(d)) {
+        for (int i = 0; i < len; ++i)
+            if ((e = enqueue_step(c, s, n0 + i, ready, false)) != hipSuccess) return e;
+        return hipSuccess;
+    }
     const int K = c->sort_every;
     const int stages = SB_PUSH | SB_COLLIDE | SB_DEPOSIT;
     const bool piped = !f64 && K >= 2;
-    hipError_t e;
-    for (int i = 0; i < K; ++i) {
-        const bool sorting = piped && i == K - 1;
-        const int hist = (piped ? i == K - 2 : i == K - 1) ? 1 : 0;
-        if ((e = launch_solve(d, f64, c->P.chunks_tot, true, s, i > 0, true)) != hipSuccess) return e;
+    bool pending = false;  // births of the previous step not placed yet
+    for (int i = 0; i < len; ++i) {
+        const int64_t n = n0 + i;
+        const bool sort_now = (n + 1) % K == 0;
+        const bool sorting = piped && sort_now && ready;
+        const bool prep = piped && (n + 2) % K == 0;
+        const int hist = (prep || (sort_now && !sorting)) ? 1 : 0;
+        if ((e = launch_solve(d, f64, c->P.chunks_tot, true, s, pending, true)) != hipSuccess) return e;
         if (sorting)
             e = launch_pass32_sort(d, c->L.ppt, c->L.window, s, true, d.cap_tot, c->L.nt != 0);
         else
@@ -476,36 +495,100 @@ hipError_t enqueue_cycle_merged(pic_ctx *c, hipStream_t s)
         if ((e = launch_candidates(d, c->L, s, f64, hist)) != hipSuccess) return e;
         if ((e = launch_neutrals(d, s)) != hipSuccess) return e;
         if ((e = launch_source(d, hist, s)) != hipSuccess) return e;
-        if (piped && i == K - 2 && (e = launch_sort_prepare(d, s)) != hipSuccess) return e;
+        if (sort_now && !sorting) {
+            if ((e = launch_births(d, f64, true, true, s)) != hipSuccess) return e;
+            if ((e = launch_sort(d, f64, c->L, s)) != hipSuccess) return e;
+            pending = false;
+        } else {
+            pending = true;
+        }
+        if (prep && !sort_now) {
+            if ((e = launch_sort_prepare(d, s)) != hipSuccess) return e;
+            ready = true;
+        } else {
+            ready = false;
+        }
     }
-    if ((e = launch_births(d, f64, true, true, s)) != hipSuccess) return e;
-    return piped ? hipSuccess : launch_sort(d, f64, c->L, s);
+    if (pending && (e = launch_births(d, f64, true, true, s)) != hipSuccess) return e;
+    return hipSuccess;
 }
 
-int build_graph(pic_ctx *c)
+// The prepared-sort state a window starting at step count n needs: in steady state the
+// step before a sort step has prepared it (FP32 form, K >= 2).
+bool ready_expected(const pic_ctx *c, int64_t n)
 {
-    if (c->graph) return PIC_OK;
+    const int K = c->sort_every;
+    return !c->P.f64 && K >= 2 && (n + 1) % K == 0;
+}
+
+// The prepared-sort state after step n (the same after an eager step and a window).
+bool ready_after(const pic_ctx *c, int64_t n)
+{
+    const int K = c->sort_every;
+    return !c->P.f64 && K >= 2 && (n + 2) % K == 0;
+}
+
+int64_t window_key(const pic_ctx *c, int64_t n, int len)
+{
+    return (n % c->sort_every) * (int64_t)(c->sort_every + 1) + len;
+}
+
+void drop_graphs(pic_ctx *c)
+{
+    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+}
+
+// Capture and instantiate the window of `len` steps starting at step count n (if absent).
+int build_window_graph(pic_ctx *c, int64_t n, int len, hipGraphExec_t *out)
+{
+    const int64_t key = window_key(c, n, len);
+    auto it = c->graphs.find(key);
+    if (it != c->graphs.end()) {
+        *out = it->second;
+        return PIC_OK;
+    }
     if (!c->cap_stream) HIPC(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-    const bool merged = c->cfg.collisions != 0 && births_fit_solve(c->d);
     hipGraph_t g = nullptr;
     HIPC(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e = hipSuccess;
-    if (merged) {
-        e = enqueue_cycle_merged(c, c->cap_stream);
-    } else {
-        // a cycle starts at a multiple of K, with no sort prepared
-        bool ready = false;
-        for (int i = 0; i < c->sort_every && e == hipSuccess; ++i)
-            e = enqueue_step(c, c->cap_stream, i, ready, false);
-    }
+    bool ready = ready_expected(c, n);
+    hipError_t e = enqueue_window(c, c->cap_stream, n, len, ready);
     hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
-    if (e != hipSuccess) return hipfail(c, e, "graph capture");
-    if (e2 != hipSuccess) return hipfail(c, e2, "hipStreamEndCapture");
-    e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
-        c->graph = nullptr;
-        return hipfail(c, e, "hipGraphInstantiate");
+        if (g) (void)hipGraphDestroy(g);
+        return hipfail(c, e, "graph capture");
+    }
+    if (e2 != hipSuccess) return hipfail(c, e2, "hipStreamEndCapture");
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hipfail(c, e, "hipGraphInstantiate");
+    c->graphs[key] = x;
+    *out = x;
+    return PIC_OK;
+}
+
+// The windows pic_step(nsteps) replays from the current state: whole sort cycles, then a
+// shorter tail that replays only if it was prepared (graph_tail).  A window is used only
+// when the prepared-sort state is the one its first phase expects.
+template <typename F>
+int plan_windows(pic_ctx *c, int64_t nsteps, bool graph_tail, F &&visit)
+{
+    int64_t n = c->host_step;
+    bool ready = c->sort_ready;
+    const int K = c->sort_every;
+    while (nsteps > 0) {
+        const int len = (int)std::min<int64_t>(nsteps, K);
+        const bool ok = c->cfg.fused && !c->timing && ready == ready_expected(c, n) &&
+                        (len == K || graph_tail || c->graphs.count(window_key(c, n, len)));
+        int rc = visit(n, ok ? len : 1, ok);
+        if (rc) return rc;
+        const int adv = ok ? len : 1;
+        // the prepared-sort state after the window or the eager step, whatever it was on
+        // entry: set by a step before a sort step (FP32, K >= 2)
+        ready = ready_after(c, n + adv - 1);
+        n += adv;
+        nsteps -= adv;
     }
     return PIC_OK;
 }
@@ -666,22 +749,40 @@ int pic_step(pic_ctx *c, int32_t nsteps, void *stream)
 {
     if (!c || nsteps < 0) return PIC_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    const int K = c->sort_every;
-    while (nsteps > 0) {
-        if (c->cfg.fused && !c->timing && c->host_step % K == 0 && nsteps >= K) {
-            int rc = build_graph(c);
-            if (rc) return rc;
-            HIPC(c, hipGraphLaunch(c->graph, s));
-            c->sort_ready = false;
-            c->host_step += K;
-            nsteps -= K;
+    int rc = plan_windows(c, nsteps, false, [&](int64_t n, int len, bool graph) -> int {
+        if (graph) {
+            hipGraphExec_t x = nullptr;
+            int r = build_window_graph(c, n, len, &x);
+            if (r) return r;
+            HIPC(c, hipGraphLaunch(x, s));
+            c->graph_launches += 1;
+            c->sort_ready = ready_after(c, n + len - 1);
         } else {
-            HIPC(c, enqueue_step(c, s, c->host_step, c->sort_ready, false));
-            c->host_step += 1;
-            nsteps -= 1;
+            HIPC(c, enqueue_step(c, s, n, c->sort_ready, false));
         }
-    }
+        c->host_step = n + len;
+        return PIC_OK;
+    });
+    if (rc) return rc;
     return check_err(c, s);
+}
+
+int pic_graph_prepare(pic_ctx *c, int32_t nsteps)
+{
+    if (!c || nsteps < 0) return PIC_EINVAL;
+    if (!c->cfg.fused) return PIC_OK;
+    return plan_windows(c, nsteps, true, [&](int64_t n, int len, bool graph) -> int {
+        if (!graph) return PIC_OK;
+        hipGraphExec_t x = nullptr;
+        return build_window_graph(c, n, len, &x);
+    });
+}
+
+int pic_graph_launches(const pic_ctx *c, int64_t *launches)
+{
+    if (!c || !launches) return PIC_EINVAL;
+    *launches = c->graph_launches;
+    return PIC_OK;
 }
 
 int pic_set_step(pic_ctx *c, int64_t step)
@@ -702,10 +803,15 @@ int64_t pic_nnodes(const pic_ctx *c, int32_t ens)
     return c->P.ens[ens].nnodes;
 }
 
-int pic_diag(pic_ctx *c, int32_t ens, pic_diag_out *out, void *stream)
+int pic_diag(pic_ctx *c, int32_t ens, pic_diag_out *out, double *moments_dev, void *stream)
 {
     if (!c || !out || ens < 0 || ens >= c->P.nens) return PIC_EINVAL;
     hipStream_t s = (hipStream_t)stream;
+    if (moments_dev) {
+        const EnsC &Em = c->P.ens[ens];
+        for (int sp = 0; sp < c->P.nspecies; ++sp)
+            HIPC(c, launch_moments(c->d, c->P.f64, Em.seg[sp], Em.nnodes, moments_dev + (int64_t)sp * 5 * Em.nnodes, s));
+    }
     const int nseg = c->P.nseg;
     std::vector<unsigned long long> cnt((size_t)kCntStripes * nseg * C_NCNT);
     std::vector<double> sums((size_t)kCntStripes * nseg * S_NSUM);
@@ -1395,10 +1501,7 @@ int pic_autotune(pic_ctx *c, int32_t trial_steps, int32_t *shape, void *stream)
         c->L.sort_ppt = bestp;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        if (c->graph) {
-            (void)hipGraphExecDestroy(c->graph);
-            c->graph = nullptr;
-        }
+        drop_graphs(c);
     }
     if (shape) {
         shape[0] = c->L.ppt;
@@ -1622,10 +1725,7 @@ int pic_load(pic_ctx *c, const void *host_buf, size_t bytes, void *stream)
     HIPC(c, hipMemcpyAsync(d.step, &h.step, 8, hipMemcpyHostToDevice, s));
     HIPC(c, hipStreamSynchronize(s));
     c->host_step = h.step;
-    if (c->graph) {
-        (void)hipGraphExecDestroy(c->graph);
-        c->graph = nullptr;
-    }
+    drop_graphs(c);
     return check_err(c, s);
 }
 
@@ -1660,7 +1760,7 @@ void pic_free(pic_ctx *c)
 {
     if (!c) return;
     for (auto &e : c->ev) (void)hipEventDestroy(e);
-    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    drop_graphs(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
 }

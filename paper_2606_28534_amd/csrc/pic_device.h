@@ -64,6 +64,7 @@ struct SegC {
     int32_t other;            // ion segment of this ensemble (electron segments), else -1
     int32_t recycle;          // ion segment of a recycling ensemble (R24)
     double vth;               // sqrt(T / m): the source's Maxwellian (R25)
+    double w;                 // macro-particle weight
 };
 
 // Constant per ensemble.

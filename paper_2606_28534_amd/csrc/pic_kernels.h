@@ -63,6 +63,9 @@ hipError_t launch_adj_grid(double *lE, double *lQ, double *tmp, int N, double dx
 hipError_t launch_adj_b(const int32_t *xc, const double *lQ, double *lx, int64_t n, double dx, int N,
                         hipStream_t s);
 hipError_t launch_diag(const Dev &d, bool f64, int sg, double *out, int grid, hipStream_t s);
+// Node moments of segment sg (reading R27) into out[5][nn] (n, ux, uy, uz, T); nn is the
+// node count of the segment's ensemble.  `out` is device memory the launch overwrites.
+hipError_t launch_moments(const Dev &d, bool f64, int sg, int64_t nn, double *out, hipStream_t s);
 // Recycled neutrals of the step (stream, recycle the absorbed ions the pass listed, flip
 // buffers) and the volumetric source pairs (FP32 form; no-ops when unused).
 hipError_t launch_neutrals(const Dev &d, hipStream_t s);

@@ -180,6 +180,12 @@ def test_push_walls_from_injected_state(pic, prec, bfield):
     for w in range(2):
         for s in range(2):
             assert abs(gd["wall_count"][w][s] - od["wall_count"][w][s]) <= 0
+            # absorbed kinetic energy per wall and species (a moment: rel 1e-4)
+            assert abs(gd["wall_ke"][w][s] - od["wall_ke"][w][s]) <= TOL_MOMENT * abs(od["wall_ke"][w][s]), \
+                (w, s, gd["wall_ke"][w][s], od["wall_ke"][w][s])
+            # count x q w on the GPU, a running sum of q w in the oracle
+            assert abs(gd["wall_charge"][w][s] - od["wall_charge"][w][s]) <= 1e-12 * abs(od["wall_charge"][w][s])
+    assert sum(od["wall_count"][w][s] for w in range(2) for s in range(2)) > 100
     assert gd["pushes"] == od["pushes"]
 
 
@@ -295,10 +301,13 @@ def test_collisionless_window_20_steps(pic, prec):
         vt = 1e-9 if prec == "fp64" else 1e-4
         compare_particles(gp, op, e["dx"], prec == "fp64", vtol=vt, xtol=(1e-8 if prec == "fp64" else 1e-4))
     g, r = sim.grid(), o.grid()
-    assert rel(g["E"], r["E"]) <= (1e-8 if prec == "fp64" else 1e-4)
-    for k in ("ke",):
-        for s in range(2):
-            assert abs(gd[k][s] - od[k][s]) <= TOL_MOMENT * abs(od[k][s])
+    for k in ("rho", "phi", "E"):
+        assert rel(g[k], r[k]) <= (1e-8 if prec == "fp64" else TOL_FIELD), (k, rel(g[k], r[k]))
+    for s in range(2):
+        assert abs(gd["ke"][s] - od["ke"][s]) <= TOL_MOMENT * abs(od["ke"][s])
+        for w in range(2):
+            assert abs(gd["wall_ke"][w][s] - od["wall_ke"][w][s]) <= TOL_MOMENT * abs(od["wall_ke"][w][s]), \
+                (w, s, gd["wall_ke"][w][s], od["wall_ke"][w][s])
 
 
 @pytest.mark.parametrize("prec", PRECISIONS)
@@ -450,3 +459,34 @@ def test_short_sort_cadences_agree_across_paths(pic, K):
             assert np.array_equal(a[s][k], c[s][k]), (K, s, k)
     assert graph.diag()["created"] == sep.diag()["created"]
     assert np.array_equal(graph.grid()["Q"][0], sep.grid()["Q"][0])
+
+
+@pytest.mark.parametrize("K,warm,steps", [(20, 5, 20), (20, 7, 33), (3, 2, 10), (4, 0, 9)])
+def test_graphs_replay_from_any_phase(pic, K, warm, steps):
+    """After `warm` eager steps the run is at an arbitrary phase of its sort cycle: the
+    prepared graphs (a whole cycle from that phase, then a shorter tail) replay the rest and
+    reach the state of a run stepped one step at a time, bit for bit; with K = 3 and two
+    warm steps the first replayed step is a sort step."""
+    w = synth.scaled(synth.c2_sheath(), ncells=1000, ppc=30)
+    e = w["ensembles"][0]
+    e["ngs_el"], e["ngs_iz"] = 0.1, 0.2
+    e["sort_every"] = K
+    for sp in e["species"]:
+        sp["capacity"] *= 2
+    g, ref = pic.Sim(work_of(e), fused=True), pic.Sim(work_of(e), fused=True)
+    for _ in range(warm):
+        g.step(1)
+    n0 = g.graph_launches()
+    g.prepare(steps)
+    g.step(steps)
+    expect = steps // K + (1 if steps % K else 0)
+    assert g.graph_launches() - n0 == expect
+    for _ in range(warm + steps):
+        ref.step(1)
+    a, b = _state(g), _state(ref)
+    for s in range(2):
+        for k in ("id", "x", "vx", "vy", "vz"):
+            assert np.array_equal(a[s][k], b[s][k]), (K, warm, s, k)
+    assert g.diag()["created"] == ref.diag()["created"]
+    assert g.diag()["step"] == warm + steps
+    assert np.array_equal(g.grid()["Q"][0], ref.grid()["Q"][0])

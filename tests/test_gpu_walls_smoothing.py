@@ -127,8 +127,8 @@ def test_floating_smoothed_window_20_steps(pic, prec):
         compare_particles(sim.particles(0, s), o.particles(s), e["dx"], prec == "fp64", vtol=vt,
                           xtol=(1e-8 if prec == "fp64" else 1e-4))
     g, r = sim.grid(), o.grid()
-    assert rel(g["E"], r["E"]) <= (1e-8 if prec == "fp64" else 1e-4)
-    assert rel(g["phi"], r["phi"]) <= (1e-8 if prec == "fp64" else 1e-4)
+    assert rel(g["E"], r["E"]) <= (1e-8 if prec == "fp64" else TOL_FIELD), rel(g["E"], r["E"])
+    assert rel(g["phi"], r["phi"]) <= (1e-8 if prec == "fp64" else TOL_FIELD), rel(g["phi"], r["phi"])
     for s in range(2):
         assert abs(gd["ke"][s] - od["ke"][s]) <= TOL_MOMENT * abs(od["ke"][s])
 
