@@ -66,23 +66,45 @@ def tuned_shape(pic, work, trial_steps):
     return shape
 
 
-def cpu_baseline(seed, steps):
-    """The FP64 oracle as it stands, single-threaded, on the first `steps` steps of the
-    same workload (particle load excluded from the timing)."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(seed, steps, omp_steps):
+    """The FP64 oracle as it stands on the first steps of the same workload (particle load
+    excluded from the timing): single-threaded, and the same source built with OpenMP on
+    its particle loops, on all the host threads OpenMP is given (OMP_NUM_THREADS)."""
     import oracle
     import synth
 
     oracle.build(force=False)
     e = synth.c2_sheath(seed=seed)["ensembles"][0]
-    o = oracle.Oracle(e)
-    d0 = o.diag()["pushes"]
-    t0 = time.perf_counter()
-    o.step(steps)
-    t1 = time.perf_counter()
-    pushes = o.diag()["pushes"] - d0
-    return {"value": pushes / (t1 - t0), "unit": "particle-pushes/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {steps} steps of the same 1e5-cell x 200-ppc workload (seed {seed}), "
-                      f"{pushes} pushes in {t1 - t0:.1f} s, FP64, one host thread"}
+    legs = {}
+    for omp, n in ((False, steps), (True, omp_steps)):
+        o = oracle.Oracle(e, omp=omp)
+        d0 = o.diag()["pushes"]
+        t0 = time.perf_counter()
+        o.step(n)
+        t1 = time.perf_counter()
+        pushes = o.diag()["pushes"] - d0
+        legs[omp] = {"value": pushes / (t1 - t0), "threads": oracle.threads(omp), "steps": n,
+                     "pushes": pushes, "seconds": round(t1 - t0, 2)}
+        del o
+    a, one = legs[True], legs[False]
+    return {"value": a["value"], "unit": "particle-pushes/s", "cores": a["threads"], "kind": "oracle",
+            "sample": f"first {a['steps']} steps of the same 1e5-cell x 200-ppc workload (seed {seed}), "
+                      f"{a['pushes']} pushes in {a['seconds']} s, FP64, OpenMP on the particle loops "
+                      f"({a['threads']} threads); single-threaded: first {one['steps']} steps, "
+                      f"{one['pushes']} pushes in {one['seconds']} s",
+            "single_thread": {"value": one["value"], "cores": 1},
+            "nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
 
 def batched_run(pic, shape, steps):
@@ -229,6 +251,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--cpu-omp-steps", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--ncells", type=int, default=100_000)
@@ -245,9 +268,13 @@ def main():
     ap.add_argument("--no-walls-variant", action="store_true")
     ap.add_argument("--no-sheath-cases", action="store_true")
     ap.add_argument("--no-large", action="store_true")
-    ap.add_argument("--case", choices=["sheath", "recycling", "source", "large"], default="sheath",
+    ap.add_argument("--case", choices=["sheath", "recycling", "source", "large", "batched"], default="sheath",
                     help="main workload: the sheath slab (default), one of the paper's two "
-                         "sheath cases, or the 1e9-particle share (for profiling them)")
+                         "sheath cases, the 1e9-particle share or the 64 batched ensembles "
+                         "(for profiling them)")
+    ap.add_argument("--fp64", action="store_true",
+                    help="main workload in the plain FP64 form (x, v in FP64; with --separate, "
+                         "one kernel per stage: the plain form, for profiling it)")
     ap.add_argument("--floating", action="store_true",
                     help="main workload with floating walls (for profiling the variant)")
     ap.add_argument("--smooth", type=int, default=0,
@@ -275,6 +302,8 @@ def main():
         work = synth.c7_sheath_source(seed=args.seed, ncells=args.ncells)
     elif args.case == "large":
         work = synth.c5_large(seed=args.seed)
+    elif args.case == "batched":
+        work = synth.c3_batched()
     else:
         work = synth.c2_sheath(seed=args.seed, ncells=args.ncells, ppc=args.ppc)
     e = work["ensembles"][0]
@@ -288,14 +317,18 @@ def main():
         shape = {"ppt": ppt, "window": window, "sort_ppt": sort_ppt, "nontemporal": nt}
     else:
         shape = tuned_shape(pic, work, args.tune_steps)
-    sim = pic.Sim(work, fused=not args.separate, **shape)
+    sim = pic.Sim(work, fused=not args.separate, precision="fp64" if args.fp64 else None, **shape)
+    n_ens = len(work["ensembles"])
+
+    def total(d_list, key):
+        return sum(sum(d[key]) if isinstance(d[key], list) else d[key] for d in d_list)
 
     # warm-up, then instantiate the graphs the timed steps replay (a whole sort cycle from
     # the phase the warm-up ends in, and a shorter tail), so no capture is timed
     sim.step(args.warmup)
     sim.prepare(args.steps)
     torch.cuda.synchronize()
-    d0 = sim.diag()
+    d0 = [sim.diag(k) for k in range(n_ens)]
     g0 = sim.graph_launches()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -303,8 +336,8 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     graph_launches = sim.graph_launches() - g0
-    d1 = sim.diag()
-    pushes = d1["pushes"] - d0["pushes"]
+    d1 = [sim.diag(k) for k in range(n_ens)]
+    pushes = total(d1, "pushes") - total(d0, "pushes")
     wall = t1 - t0
     value = pushes / wall
 
@@ -313,30 +346,32 @@ def main():
     # pass in K that also sorts, a kernel of its own); every pass pushes every live
     # particle, so a launch's pushes are the run's pushes per step
     sim.timing(True)
-    dt0 = sim.diag()["pushes"]
+    dt0 = total([sim.diag(k) for k in range(n_ens)], "pushes")
     nt = min(args.steps, 200)
     sim.step(nt)
     ms_tot, launches = sim.timing_read()
     sim.timing(False)
-    dt1 = sim.diag()["pushes"]
+    dt1 = total([sim.diag(k) for k in range(n_ens)], "pushes")
     pass_pushes = (dt1 - dt0) / nt
     avg_ms = ms_tot / max(launches, 1)
-    bytes_per_launch = (B_ALG_PARTICLE * pass_pushes + B_ALG_CELL * e["ncells"]
-                        + B_ALG_NODE * (e["ncells"] + 1))
+    cells = sum(en["ncells"] for en in work["ensembles"])
+    b_part = 68.0 if args.fp64 else B_ALG_PARTICLE
+    bytes_per_launch = (b_part * pass_pushes + B_ALG_CELL * cells + B_ALG_NODE * (cells + n_ens))
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    plain_sheath = args.case == "sheath" and not args.floating and not args.smooth
+    plain_sheath = args.case == "sheath" and not args.floating and not args.smooth and not args.fp64
     traffic = traffic_from_profiles("sheath_1e5", bytes_per_launch) if plain_sheath else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_pass32<push|collide|deposit>",
+                "kernel": ("k_particles<" if args.fp64 else "k_pass32<")
+                          + ("push>" if args.separate else "push|collide|deposit>"),
                 "avg_launch_ms": round(avg_ms, 5), "bytes_alg_per_launch": bytes_per_launch,
                 "launches_timed": launches}
     # algorithmic bytes of a whole step: 44 B per push, the sort's 48 B per particle every K
     # steps, 40 B per node for the grid (Q written and read, E written and read) and 24 B per
     # created particle
-    created = sum(d1["created"]) - sum(d0["created"])
-    step_bytes = ((B_ALG_PARTICLE + 48.0 / e["sort_every"]) * (pushes / args.steps)
-                  + 40.0 * (e["ncells"] + 1) + 24.0 * created / args.steps)
+    created = total(d1, "created") - total(d0, "created")
+    step_bytes = ((b_part + (72.0 if args.fp64 else 48.0) / e["sort_every"]) * (pushes / args.steps)
+                  + 40.0 * (cells + n_ens) + 24.0 * created / args.steps)
     whole_step = {"bytes_alg_per_step": step_bytes,
                   "frac_of_hbm_peak": round(step_bytes / (wall / args.steps) / 1e9 / HBM_PEAK_GBS, 4)}
     del sim
@@ -380,7 +415,7 @@ def main():
     if not args.no_stream:
         stream = stream_copy_gbs(torch)
 
-    cpu = None if args.no_cpu else cpu_baseline(args.seed, args.cpu_steps)
+    cpu = None if args.no_cpu else cpu_baseline(args.seed, args.cpu_steps, args.cpu_omp_steps)
     if args.calib_copy_gib > 0:
         n = int(args.calib_copy_gib * (1 << 30)) // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda")

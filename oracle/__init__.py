@@ -15,17 +15,29 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "pic_oracle.c")
+HDR = os.path.join(HERE, "pic_oracle.h")
 LIB = os.path.join(HERE, "liboracle.so")
+# The same source built with OpenMP on its particle loops: used only to time the oracle on
+# all host cores (its deposit sums per-thread partials, so it is not the parity reference).
+LIB_OMP = os.path.join(HERE, "liboracle_omp.so")
 
 
-def build(force=True):
-    """Compile liboracle.so (gcc, -O2, no fused multiply-add)."""
-    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
-        return LIB
-    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-ffp-contract=off", "-fPIC", "-shared",
-           "-o", LIB + ".tmp", SRC, "-lm"]
-    subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
+def _stale(lib):
+    return not os.path.exists(lib) or os.path.getmtime(lib) < max(os.path.getmtime(SRC), os.path.getmtime(HDR))
+
+
+def build(force=True, omp=None):
+    """Compile liboracle.so (gcc, -O2, no fused multiply-add, single-threaded) and
+    liboracle_omp.so (the same with -fopenmp, for timing only).  `omp` None builds both."""
+    for want, lib_path, extra in ((False, LIB, []), (True, LIB_OMP, ["-fopenmp"])):
+        if omp is not None and omp != want:
+            continue
+        if not force and not _stale(lib_path):
+            continue
+        cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wno-unknown-pragmas", "-ffp-contract=off", "-fPIC",
+               "-shared", *extra, "-o", lib_path + ".tmp", SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(lib_path + ".tmp", lib_path)
     return LIB
 
 
@@ -70,15 +82,17 @@ class Diag(C.Structure):
         }
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB):
-            build()
-        L = C.CDLL(LIB)
+def lib(omp=False):
+    """The oracle's C library: the single-threaded build, or (omp=True) the OpenMP timing
+    build."""
+    if omp not in _libs:
+        path = LIB_OMP if omp else LIB
+        if not os.path.exists(path):
+            build(force=True, omp=omp)
+        L = C.CDLL(path)
         P = C.c_void_p
         L.orc_create.restype = P
         L.orc_create.argtypes = [C.POINTER(_Config)]
@@ -116,8 +130,15 @@ def lib():
         L.orc_thomas.argtypes = [C.c_int64, P, P, P, P, P]
         L.orc_smooth_nodes.argtypes = [C.c_int64, C.c_int32, C.c_int32, P]
         L.orc_smooth_nodes.restype = None
-        _lib = L
-    return _lib
+        L.orc_threads.argtypes = []
+        L.orc_threads.restype = C.c_int
+        _libs[omp] = L
+    return _libs[omp]
+
+
+def threads(omp=False):
+    """Threads the oracle's particle loops use in that build."""
+    return int(lib(omp).orc_threads())
 
 
 def _ptr(a):
@@ -157,10 +178,10 @@ def make_config(e):
 class Oracle:
     """One ensemble of the oracle.  Stage methods mirror the C functions."""
 
-    def __init__(self, e, init=True):
+    def __init__(self, e, init=True, omp=False):
         self.e = e
         self._cfg = make_config(e)
-        self.L = lib()
+        self.L = lib(omp)
         self.h = C.c_void_p(self.L.orc_create(C.byref(self._cfg)))
         self.nspecies = e["nspecies"]
         self.nnodes = int(self.L.orc_nnodes(self.h))

@@ -16,6 +16,9 @@
 #include "pic_oracle.h"
 
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -177,6 +180,7 @@ static int64_t cell_index(const orc_state *st, double x, double *f)
 static void recompute_vmax(orc_state *st, int s)
 {
     double m2 = 0.0;
+#pragma omp parallel for schedule(static) reduction(max : m2)
     for (int64_t p = 0; p < st->n[s]; p++) {
         double v2 = speed2(st->vx[s][p], st->vy[s][p], st->vz[s][p]);
         if (v2 > m2) m2 = v2;
@@ -238,6 +242,17 @@ void orc_free(orc_state *st)
 }
 
 int orc_error(const orc_state *st) { return st->err; }
+
+/* Threads the particle loops run on: 1, or the OpenMP team size when the oracle is built
+ * with OpenMP (a timing build only; its deposit sums in a different order). */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------------------------ */
 /* Particle load.
@@ -362,7 +377,9 @@ void orc_deposit(orc_state *st)
     const orc_config *c = &st->cfg;
     for (int s = 0; s < c->nspecies; s++) {
         double *Q = st->Q[s];
-        memset(Q, 0, (size_t)(st->nnodes + 1) * sizeof(double));
+        int64_t nq = st->nnodes + 1;
+        memset(Q, 0, (size_t)nq * sizeof(double));
+#pragma omp parallel for schedule(static) reduction(+ : Q[:nq])
         for (int64_t p = 0; p < st->n[s]; p++) {
             double f = 0.0;
             int64_t j = cell_index(st, st->x[s][p], &f);
@@ -512,6 +529,7 @@ void orc_push(orc_state *st)
         double tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
         double sf = 2.0 / (1.0 + tt);
         double sv[3] = {sf * t[0], sf * t[1], sf * t[2]};
+#pragma omp parallel for schedule(static)
         for (int64_t p = 0; p < st->n[s]; p++) {
             double f = 0.0;
             int64_t j = cell_index(st, st->x[s][p], &f);
@@ -700,6 +718,8 @@ void orc_collide(orc_state *st)
         st->pnull[s] = pnull;
         st->last_n[s] = st->n[s];
         double vn = sqrt(c->T_n / c->m_n);
+        int64_t ncoll[3] = {0, 0, 0};
+#pragma omp parallel for schedule(static) reduction(+ : ncoll[:3])
         for (int64_t p = 0; p < st->n[s]; p++) {
             uint32_t pid = st->id[s][p];
             st->last_id[s][p] = pid;
@@ -737,7 +757,7 @@ void orc_collide(orc_state *st)
             }
             st->last_chan[s][p] = chan;
             if (chan < 0) continue;
-            st->d.coll[chan] += 1;
+            ncoll[chan] += 1;
             if (chan == 0) {
                 double d[3];
                 iso_dir(R3, R4, d);
@@ -762,19 +782,24 @@ void orc_collide(orc_state *st)
                 st->vy[s][p] = s1 * d1[1];
                 st->vz[s][p] = s1 * d1[2];
                 three_normals(w2, z);
-                if (nb == nbcap) {
-                    nbcap = nbcap ? 2 * nbcap : 1024;
-                    births = (orc_birth *)realloc(births, (size_t)nbcap * sizeof(orc_birth));
+                /* births are ordered by parent id below, so the order of appending here
+                 * does not matter */
+#pragma omp critical(orc_births)
+                {
+                    if (nb == nbcap) {
+                        nbcap = nbcap ? 2 * nbcap : 1024;
+                        births = (orc_birth *)realloc(births, (size_t)nbcap * sizeof(orc_birth));
+                    }
+                    orc_birth *b = &births[nb++];
+                    b->pid = pid;
+                    b->x = st->x[s][p];
+                    b->ve[0] = s2 * d2[0];
+                    b->ve[1] = s2 * d2[1];
+                    b->ve[2] = s2 * d2[2];
+                    b->vi[0] = vn * z[0];
+                    b->vi[1] = vn * z[1];
+                    b->vi[2] = vn * z[2];
                 }
-                orc_birth *b = &births[nb++];
-                b->pid = pid;
-                b->x = st->x[s][p];
-                b->ve[0] = s2 * d2[0];
-                b->ve[1] = s2 * d2[1];
-                b->ve[2] = s2 * d2[2];
-                b->vi[0] = vn * z[0];
-                b->vi[1] = vn * z[1];
-                b->vi[2] = vn * z[2];
             } else {
                 uint32_t w2[4];
                 double z[3];
@@ -785,6 +810,7 @@ void orc_collide(orc_state *st)
                 st->vz[s][p] = vn * z[2];
             }
         }
+        for (int k = 0; k < 3; k++) st->d.coll[k] += ncoll[k];
     }
     for (int64_t k = 0; k < c->src_pairs && c->nspecies > 1; k++) {
         uint32_t w[4], z0w[4], z1w[4];

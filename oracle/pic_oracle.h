@@ -132,6 +132,11 @@ typedef struct {
 
 typedef struct orc_state orc_state;
 
+/* Threads the particle loops use: 1 in the default build; the OpenMP team size in the
+ * OpenMP build, which exists only to time the oracle on all host cores (its deposit adds
+ * per-thread partial sums, so its last bits differ from the default build's). */
+int orc_threads(void);
+
 orc_state *orc_create(const orc_config *cfg);
 void orc_free(orc_state *st);
 /* Non-zero after a capacity overflow (1, 3) or a particle outside the grid (2). */

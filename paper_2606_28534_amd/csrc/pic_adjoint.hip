@@ -9,6 +9,8 @@
 //   lv += dt lx;  la = dt (q/m) lv;  lE_j += w_j(x) la;  lx += la (E_{j+1} - E_j) / dx;
 //   lEext += la;  lQ = (q w / dx) S D lE;  lx += (lQ_{j+1} - lQ_j) / dx.
 // Adjoint accumulators are FP64.
+#include <algorithm>
+
 #include "pic_device.h"
 #include "pic_kernels.h"
 
@@ -192,6 +194,29 @@ __global__ void k_adj_seed(const double *E, double *lE, int N, double eps0, doub
 {
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < N; j += gridDim.x * blockDim.x)
         lE[j] = eps0 * dx * E[j];
+}
+
+// Gradient by particle id: out[id_i] = lv_i for the n slots (ids at or above `len` set the
+// error flag instead).
+__global__ void k_adj_by_id(const double *lv, const uint32_t *id, double *out, int64_t n, int64_t len,
+                            int32_t *err)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t k = id[i];
+        if ((int64_t)k < len)
+            out[k] = lv[i];
+        else
+            atomicOr(err, 1);
+    }
+}
+
+hipError_t launch_adj_by_id(const double *lv, const uint32_t *id, double *out, int64_t n, int64_t len,
+                            int32_t *err, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t G = std::min<int64_t>((n + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_adj_by_id, dim3((unsigned)G), dim3(256), 0, s, lv, id, out, n, len, err);
+    return hipGetLastError();
 }
 
 hipError_t launch_adj_seed(const double *E, double *lE, int N, double eps0, double dx, hipStream_t s)

@@ -23,6 +23,7 @@ constexpr size_t kAlign = 256;
 constexpr int kCompactEvery = 20;  // sort cadence used for compaction when K = 0
 constexpr int kDiagGrid = 256;
 
+
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Sizes derived from a configuration; shared by the query and the carving.
@@ -281,6 +282,7 @@ size_t carve(const Plan &P, char *base, Dev &d)
     d.vcur = c.take<int32_t>(1);
     d.cnt = c.take<unsigned long long>((int64_t)kCntStripes * P.nseg * C_NCNT);
     d.sums = c.take<double>((int64_t)kCntStripes * P.nseg * S_NSUM);
+    d.ssum = c.take<double>((int64_t)2 * kCntStripes * P.nseg * T_NSTEP);
     d.birth_stripe_cap = P.birth_stripe_cap;
     d.births = c.take<Birth>(2 * kStripes * P.birth_stripe_cap);
     d.nbirth = c.take<uint32_t>(2 * kStripes);
@@ -333,6 +335,11 @@ struct pic_ctx {
     // next fused FP32 step can sort inside its particle pass.  Any call that moves, adds or
     // removes particles between steps clears it (that step then sorts the usual way).
     bool sort_ready = false;
+    // The last pic_step ran the fused FP32 step with collisions, whose kernels tallied the
+    // scalar diagnostics of its last step (count and sum |v|^2 per species, field energy
+    // per solve chunk): pic_diag reads those instead of a pass over the particles.  Any
+    // call that changes particles or fields between steps clears it.
+    bool insitu = false;
     hipStream_t cap_stream = nullptr;
     // captured windows of the fused step, keyed by (first step's phase in the sort cycle,
     // number of steps); each replays from that phase with the prepared-sort state the
@@ -715,6 +722,7 @@ int pic_solve(pic_ctx *c, void *stream)
 int pic_push(pic_ctx *c, void *stream)
 {
     if (!c) return PIC_EINVAL;
+    c->insitu = false;
     c->sort_ready = false;  // particles or the step count change: no prepared sort
     HIPC(c, launch_particles(c->d, c->L, (hipStream_t)stream, c->P.f64, SB_PUSH, 0));
     HIPC(c, launch_neutrals(c->d, (hipStream_t)stream));
@@ -724,6 +732,7 @@ int pic_push(pic_ctx *c, void *stream)
 int pic_collide(pic_ctx *c, void *stream)
 {
     if (!c) return PIC_EINVAL;
+    c->insitu = false;
     c->sort_ready = false;  // particles or the step count change: no prepared sort
     hipStream_t s = (hipStream_t)stream;
     if (c->cfg.collisions) {
@@ -738,6 +747,7 @@ int pic_collide(pic_ctx *c, void *stream)
 int pic_sort(pic_ctx *c, void *stream)
 {
     if (!c) return PIC_EINVAL;
+    c->insitu = false;
     c->sort_ready = false;  // particles or the step count change: no prepared sort
     hipStream_t s = (hipStream_t)stream;
     HIPC(c, launch_particles(c->d, c->L, s, c->P.f64, SB_HIST, 0));
@@ -764,6 +774,7 @@ int pic_step(pic_ctx *c, int32_t nsteps, void *stream)
         return PIC_OK;
     });
     if (rc) return rc;
+    if (nsteps > 0) c->insitu = c->cfg.fused && !c->P.f64 && c->cfg.collisions;
     return check_err(c, s);
 }
 
@@ -820,23 +831,49 @@ int pic_diag(pic_ctx *c, int32_t ens, pic_diag_out *out, double *moments_dev, vo
     double emax = 0, fe = 0;
     std::vector<double> numax(nseg);
     int64_t step = 0;
-    HIPC(c, launch_field_energy(c->d, s));
+    if (!c->insitu) {
+        HIPC(c, launch_field_energy(c->d, s));
+        HIPC(c, hipMemcpyAsync(&fe, c->d.fe + ens, 8, hipMemcpyDeviceToHost, s));
+    }
     HIPC(c, hipMemcpyAsync(&emax, c->d.emax + ens, 8, hipMemcpyDeviceToHost, s));
-    HIPC(c, hipMemcpyAsync(&fe, c->d.fe + ens, 8, hipMemcpyDeviceToHost, s));
     HIPC(c, hipMemcpyAsync(numax.data(), c->d.numax, nseg * 8, hipMemcpyDeviceToHost, s));
     HIPC(c, hipMemcpyAsync(&step, c->d.step, 8, hipMemcpyDeviceToHost, s));
     memset(out, 0, sizeof(*out));
     const EnsC &E = c->P.ens[ens];
     std::vector<double> part(2 * kDiagGrid);
+    // the fused step's own tallies of its last step (count, sum |v|^2 and the solve's field
+    // energy), when no call has changed particles or fields since
+    std::vector<double> tal;
+    if (c->insitu) {
+        int32_t vc = 0;
+        HIPC(c, hipMemcpyAsync(&vc, c->d.vcur, 4, hipMemcpyDeviceToHost, s));
+        HIPC(c, hipStreamSynchronize(s));
+        const size_t per = (size_t)kCntStripes * nseg * T_NSTEP;
+        tal.resize(per);
+        HIPC(c, hipMemcpyAsync(tal.data(), c->d.ssum + (size_t)vc * per, per * 8, hipMemcpyDeviceToHost, s));
+        std::vector<double> pp((size_t)E.nchunks * P_NPART);
+        HIPC(c, hipMemcpyAsync(pp.data(), c->d.part + E.chunk0 * P_NPART, pp.size() * 8, hipMemcpyDeviceToHost, s));
+        HIPC(c, hipStreamSynchronize(s));
+        double f = 0.0;
+        for (int64_t k = 0; k < E.nchunks; ++k) f += pp[(size_t)k * P_NPART + P_FE];
+        fe = f;
+    }
     for (int sp = 0; sp < c->P.nspecies; ++sp) {
         const int sg = E.seg[sp];
-        HIPC(c, launch_diag(c->d, c->P.f64, sg, c->diag_scratch, kDiagGrid, s));
-        HIPC(c, hipMemcpyAsync(part.data(), c->diag_scratch, part.size() * 8, hipMemcpyDeviceToHost, s));
-        HIPC(c, hipStreamSynchronize(s));
         double n = 0, v2 = 0;
-        for (int i = 0; i < kDiagGrid; ++i) {
-            n += part[2 * i];
-            v2 += part[2 * i + 1];
+        if (c->insitu) {
+            for (int st = 0; st < kCntStripes; ++st) {
+                n += tal[((size_t)st * nseg + sg) * T_NSTEP + T_N];
+                v2 += tal[((size_t)st * nseg + sg) * T_NSTEP + T_V2];
+            }
+        } else {
+            HIPC(c, launch_diag(c->d, c->P.f64, sg, c->diag_scratch, kDiagGrid, s));
+            HIPC(c, hipMemcpyAsync(part.data(), c->diag_scratch, part.size() * 8, hipMemcpyDeviceToHost, s));
+            HIPC(c, hipStreamSynchronize(s));
+            for (int i = 0; i < kDiagGrid; ++i) {
+                n += part[2 * i];
+                v2 += part[2 * i + 1];
+            }
         }
         const pic_species_desc &D = c->ens[ens].sp[sp];
         out->count[sp] = (int64_t)n;
@@ -1073,6 +1110,7 @@ int pic_set_particles(pic_ctx *c, int32_t ens, int32_t species, pic_particles in
     if (!c || ens < 0 || ens >= c->P.nens || species < 0 || species >= c->P.nspecies || count < 0)
         return fail(c, PIC_EINVAL, "bad ensemble/species/count");
     c->sort_ready = false;  // particles or the step count change: no prepared sort
+    c->insitu = false;
     const int sg = c->P.ens[ens].seg[species];
     const SegC &S = c->P.seg[sg];
     if (count > S.cap) return fail(c, PIC_EINVAL, "count above capacity");
@@ -1174,6 +1212,7 @@ int pic_get_gather_table(pic_ctx *c, int32_t ens, float *out, void *stream)
 int pic_set_fields(pic_ctx *c, int32_t ens, const double *E, void *stream)
 {
     if (!c || !E || ens < 0 || ens >= c->P.nens) return PIC_EINVAL;
+    c->insitu = false;
     hipStream_t s = (hipStream_t)stream;
     HIPC(c, hipStreamSynchronize(s));
     const EnsC &En = c->P.ens[ens];
@@ -1200,16 +1239,17 @@ struct AdjLayout {
         off_tmp, off_ext, off_fin, bytes;
 };
 
-int adj_check(pic_ctx *c, std::string &why)
+// PIC_OK when the run is one the adjoint is defined for; otherwise *why says what is not.
+int adj_check(pic_ctx *c, const char **why)
 {
-    if (c->P.nens != 1 || c->P.nspecies != 1) why = "adjoint needs one ensemble and one species";
-    else if (!c->d.periodic) why = "adjoint needs a periodic domain";
-    else if (c->cfg.collisions) why = "adjoint needs a collisionless run";
-    else if (c->cfg.smooth) why = "adjoint is defined without density smoothing";
-    else if (c->P.f64) why = "adjoint is defined on the FP32 form";
+    if (c->P.nens != 1 || c->P.nspecies != 1) *why = "adjoint needs one ensemble and one species";
+    else if (!c->d.periodic) *why = "adjoint needs a periodic domain";
+    else if (c->cfg.collisions) *why = "adjoint needs a collisionless run";
+    else if (c->cfg.smooth) *why = "adjoint is defined without density smoothing";
+    else if (c->P.f64) *why = "adjoint is defined on the FP32 form";
     else {
         const SegC &S = c->P.seg[0];
-        if (S.t[0] != 0.0 || S.t[1] != 0.0 || S.t[2] != 0.0) why = "adjoint needs B = 0";
+        if (S.t[0] != 0.0 || S.t[1] != 0.0 || S.t[2] != 0.0) *why = "adjoint needs B = 0";
         else return PIC_OK;
     }
     return PIC_EINVAL;
@@ -1267,24 +1307,29 @@ hipError_t adj_forward_step(pic_ctx *c, hipStream_t s, int32_t *xc, float *xo, d
 int pic_adjoint_query(pic_ctx *c, int32_t nsteps, int32_t ckpt_every, size_t *bytes)
 {
     if (!c || !bytes || nsteps < 1 || ckpt_every < 1) return PIC_EINVAL;
-    std::string why;
-    if (adj_check(c, why)) return fail(c, PIC_EINVAL, why);
+    const char *why = "";
+    if (adj_check(c, &why)) return fail(c, PIC_EINVAL, why);
     *bytes = adj_layout(c, nsteps, ckpt_every).bytes;
     return PIC_OK;
 }
 
-int pic_adjoint_window(pic_ctx *c, int32_t nsteps, int32_t ckpt_every, void *scratch, size_t bytes,
-                       double *W, double *dW_dvx, int64_t dvx_len, double *dW_dEext, void *stream)
+namespace {
+// The adjoint window on scratch `base` (>= the layout's bytes).  With `gid` (device memory
+// of dvx_len doubles) the gradient is scattered by id on the device into gid, which first
+// receives the caller's dW_dvx so that entries of ids absent from the run stay as they
+// were, and is copied back whole; without it the host scatters (host staging vectors).
+int adjoint_window_impl(pic_ctx *c, int32_t nsteps, int32_t ckpt_every, char *base, size_t bytes,
+                        double *W, double *dW_dvx, int64_t dvx_len, double *dW_dEext, double *gid,
+                        void *stream)
 {
-    if (!c || !scratch || nsteps < 1 || ckpt_every < 1 || !W || !dW_dvx || !dW_dEext) return PIC_EINVAL;
     c->sort_ready = false;  // particles or the step count change: no prepared sort
-    std::string why;
-    if (adj_check(c, why)) return fail(c, PIC_EINVAL, why);
+    c->insitu = false;
+    const char *why = "";
+    if (adj_check(c, &why)) return fail(c, PIC_EINVAL, why);
     const AdjLayout A = adj_layout(c, nsteps, ckpt_every);
     if (bytes < A.bytes) return fail(c, PIC_EINVAL, "adjoint scratch too small");
     hipStream_t s = (hipStream_t)stream;
     Dev &d = c->d;
-    char *base = (char *)scratch;
     int32_t *ck_cell = (int32_t *)(base + A.off_ck_cell);
     float *ck_off = (float *)(base + A.off_ck_off);
     float *ck_vx = (float *)(base + A.off_ck_vx);
@@ -1391,25 +1436,49 @@ int pic_adjoint_window(pic_ctx *c, int32_t nsteps, int32_t ckpt_every, void *scr
     HIPC(c, launch_zero_q(d, false, s));
     HIPC(c, launch_particles(d, c->L, s, false, SB_DEPOSIT, 0));
     // gradients by id
-    std::vector<double> glv(nslots);
-    std::vector<uint32_t> ids(nslots);
     double gext = 0.0;
-    HIPC(c, hipMemcpyAsync(glv.data(), lv, nslots * 8, hipMemcpyDeviceToHost, s));
-    HIPC(c, hipMemcpyAsync(ids.data(), d.id[0], nslots * 4, hipMemcpyDeviceToHost, s));
-    HIPC(c, hipMemcpyAsync(&gext, lext, 8, hipMemcpyDeviceToHost, s));
-    HIPC(c, hipStreamSynchronize(s));
-    for (int64_t i = 0; i < nslots; ++i) {
-        if ((int64_t)ids[i] >= dvx_len) return fail(c, PIC_EINVAL, "particle id beyond dW_dvx");
-        dW_dvx[ids[i]] = glv[i];
+    if (gid) {
+        int32_t *bad = (int32_t *)lext + 2;  // a flag beside lext (its 64-byte slot)
+        HIPC(c, hipMemsetAsync(bad, 0, 4, s));
+        HIPC(c, hipMemcpyAsync(gid, dW_dvx, (size_t)dvx_len * 8, hipMemcpyHostToDevice, s));
+        HIPC(c, launch_adj_by_id(lv, d.id[0], gid, nslots, dvx_len, bad, s));
+        int32_t badh = 0;
+        HIPC(c, hipMemcpyAsync(&badh, bad, 4, hipMemcpyDeviceToHost, s));
+        HIPC(c, hipMemcpyAsync(&gext, lext, 8, hipMemcpyDeviceToHost, s));
+        HIPC(c, hipStreamSynchronize(s));
+        if (badh) return fail(c, PIC_EINVAL, "particle id beyond dW_dvx");
+        HIPC(c, hipMemcpyAsync(dW_dvx, gid, (size_t)dvx_len * 8, hipMemcpyDeviceToHost, s));
+        HIPC(c, hipStreamSynchronize(s));
+    } else {
+        std::vector<double> glv(nslots);
+        std::vector<uint32_t> ids(nslots);
+        HIPC(c, hipMemcpyAsync(glv.data(), lv, nslots * 8, hipMemcpyDeviceToHost, s));
+        HIPC(c, hipMemcpyAsync(ids.data(), d.id[0], nslots * 4, hipMemcpyDeviceToHost, s));
+        HIPC(c, hipMemcpyAsync(&gext, lext, 8, hipMemcpyDeviceToHost, s));
+        HIPC(c, hipStreamSynchronize(s));
+        for (int64_t i = 0; i < nslots; ++i) {
+            if ((int64_t)ids[i] >= dvx_len) return fail(c, PIC_EINVAL, "particle id beyond dW_dvx");
+            dW_dvx[ids[i]] = glv[i];
+        }
     }
     *W = fe;
     *dW_dEext = gext;
     return check_err(c, s);
 }
+}  // namespace
+
+int pic_adjoint_window(pic_ctx *c, int32_t nsteps, int32_t ckpt_every, void *scratch_dev, size_t bytes,
+                       double *W, double *dW_dvx, int64_t dvx_len, double *dW_dEext, void *stream)
+{
+    if (!c || !scratch_dev || nsteps < 1 || ckpt_every < 1 || !W || !dW_dvx || !dW_dEext) return PIC_EINVAL;
+    return adjoint_window_impl(c, nsteps, ckpt_every, (char *)scratch_dev, bytes, W, dW_dvx, dvx_len, dW_dEext,
+                               nullptr, stream);
+}
 
 int pic_autotune(pic_ctx *c, int32_t trial_steps, int32_t *shape, void *stream)
 {
     if (!c || trial_steps < 1) return PIC_EINVAL;
+    c->insitu = false;
     hipStream_t s = (hipStream_t)stream;
     if (!c->P.f64) {
         const int ppts[2] = {4, 8};
@@ -1643,6 +1712,7 @@ int pic_load(pic_ctx *c, const void *host_buf, size_t bytes, void *stream)
 {
     if (!c || !host_buf || bytes < sizeof(CkptHeader)) return PIC_EINVAL;
     c->sort_ready = false;  // particles or the step count change: no prepared sort
+    c->insitu = false;
     hipStream_t s = (hipStream_t)stream;
     CkptHeader h;
     std::memcpy(&h, host_buf, sizeof(h));
@@ -1717,6 +1787,7 @@ int pic_load(pic_ctx *c, const void *host_buf, size_t bytes, void *stream)
     HIPC(c, hipMemsetAsync(d.vmax2 + (size_t)kCntStripes * c->P.nseg, 0, (size_t)kCntStripes * c->P.nseg * 8, s));
     HIPC(c, h2d(d.cnt, (size_t)kCntStripes * c->P.nseg * C_NCNT * 8));
     HIPC(c, h2d(d.sums, (size_t)kCntStripes * c->P.nseg * S_NSUM * 8));
+    HIPC(c, hipMemsetAsync(d.ssum, 0, (size_t)2 * kCntStripes * c->P.nseg * T_NSTEP * 8, s));
     const int32_t zero = 0;
     HIPC(c, hipMemcpyAsync(d.n_slots, ns.data(), ns.size() * 8, hipMemcpyHostToDevice, s));
     HIPC(c, hipMemcpyAsync(d.next_id, ids.data(), ids.size() * 4, hipMemcpyHostToDevice, s));

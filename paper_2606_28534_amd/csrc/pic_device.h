@@ -44,6 +44,8 @@ enum Cnt : int {
     C_NCNT
 };
 enum Sum : int { S_KE_L = 0, S_KE_R, S_NSUM };
+// Per-step scalar tallies: sum |v|^2 and count of the particles alive after the step.
+enum StepSum : int { T_V2 = 0, T_N, T_NSTEP };
 // Per-chunk solve aggregates.
 enum Agg : int { A_SUMRHO = 0, A_SUMPRE, A_TOTQ, A_N1, A_D, A_CNT, A_RHO0, A_NAGG };
 enum Part : int { P_EMAX = 0, P_FE, P_PHISUM, P_NONFIN, P_NPART };
@@ -133,6 +135,10 @@ struct Dev {
     int32_t *vcur;            // [1] which vmax2 half holds the current maxima
     unsigned long long *cnt;  // [kCntStripes][nseg][C_NCNT]
     double *sums;             // [kCntStripes][nseg][S_NSUM]
+    // scalar diagnostics of the fused FP32 step, per step: [2][kCntStripes][nseg][T_NSTEP],
+    // half 1 - *vcur accumulates the step under way and becomes current at the birth
+    // placement, which clears the other half (as for vmax2)
+    double *ssum;
     // births, double-buffered by step parity: step n appends to half n & 1 and its
     // placement clears half (n + 1) & 1, which step n - 1 used
     Birth *births;            // [2][kStripes][birth_stripe_cap]
@@ -260,6 +266,12 @@ __device__ __forceinline__ double speed2_rn(double a, double b, double c)
 }
 
 __device__ __forceinline__ int stripe_of_block() { return (int)(blockIdx.x & (kCntStripes - 1)); }
+
+// The per-step scalar tallies of segment sg in stripe st of half `half`.
+__device__ __forceinline__ double *step_sums(const Dev &d, int half, int st, int sg)
+{
+    return d.ssum + (((int64_t)half * kCntStripes + st) * d.nseg + sg) * T_NSTEP;
+}
 
 // One half of the birth buffers.
 struct BirthBuf {

@@ -62,6 +62,9 @@ hipError_t launch_adj_grid(double *lE, double *lQ, double *tmp, int N, double dx
                            hipStream_t s);
 hipError_t launch_adj_b(const int32_t *xc, const double *lQ, double *lx, int64_t n, double dx, int N,
                         hipStream_t s);
+// out[id_i] = lv_i for n slots; ids >= len set *err (device int).
+hipError_t launch_adj_by_id(const double *lv, const uint32_t *id, double *out, int64_t n, int64_t len,
+                            int32_t *err, hipStream_t s);
 hipError_t launch_diag(const Dev &d, bool f64, int sg, double *out, int grid, hipStream_t s);
 // Node moments of segment sg (reading R27) into out[5][nn] (n, ux, uy, uz, T); nn is the
 // node count of the segment's ensemble.  `out` is device memory the launch overwrites.

@@ -263,15 +263,11 @@ __global__ void __launch_bounds__(256) k_particles(Dev d, int hist_rt)
                 d.dvy[b][i] = p[k].vy;
                 d.dvz[b][i] = p[k].vz;
             }
-            if (live[k] && (DEPO || HISTC)) {
-                if (DEPO)
-                    global_deposit64(d, S, s, p[k].x, hist);
-                else {
-                    double f;
-                    const int j = p_cell<true>(S, p[k], f);
-                    atomicAdd(d.cellcnt + S.cbase + j, 1u);
-                }
-            }
+        }
+        // deposit (and sort histogram) by runs of equal cell across the wave's lanes
+        if (DEPO || HISTC) {
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) wave_deposit64(d, S, s, live[k], live[k] ? p[k].x : 0.0, hist, !DEPO);
         }
     }
     if ((PUSH || COLL) && tseg >= 0) flush_tally(d, tseg, tal, COLL);
@@ -786,7 +782,7 @@ __device__ void solve2_body(const Dev &d, int zero_q)
     // exclusive prefix of C over m < j (m in [0, N-1])
     const double fex = block_incl_scan(csum, s_buf) - csum;
     double F = s_F0 + fex;
-    double emax = 0.0, phisum = 0.0;
+    double emax = 0.0, phisum = 0.0, fe = 0.0;
     int nonfin = 0;
     // C_{j-1} for the first node of the thread
     double Cprev = (j0 == 0) ? 0.0 : (Cj[0] - rl[0]);
@@ -821,6 +817,7 @@ __device__ void solve2_body(const Dev &d, int zero_q)
         if constexpr (!F64) s_E[j - a] = Ej;
         if (!isfinite(Ej)) nonfin = 1;
         emax = fmax(emax, fabs(Ej));
+        fe += Ej * Ej * node_vol(e, j);
         if (j < N) F += Cj[q];
         Cprev = Cj[q];
     }
@@ -877,11 +874,12 @@ __device__ void solve2_body(const Dev &d, int zero_q)
         }
         __syncthreads();
         em = s_em[0];
-        __shared__ double s_red3[2 * 16];
-        double fv[2] = {phisum, (double)nonfin};
-        block_sums<2>(fv, s_red3);
+        __shared__ double s_red3[3 * 16];
+        double fv[3] = {phisum, (double)nonfin, fe};
+        block_sums<3>(fv, s_red3);
         if (threadIdx.x == 0) {
             d.part[k * P_NPART + P_PHISUM] = fv[0];
+            d.part[k * P_NPART + P_FE] = 0.5 * e.eps0 * fv[2];  // this chunk's field energy
             // |E| >= 0: its bit pattern orders as an unsigned integer
             atomicMax((unsigned long long *)(d.emax + ei), dbits(em));
             if (fv[1] > 0.0) atomicOr(d.err, (int)E_NONFINITE);
@@ -1305,6 +1303,9 @@ __device__ void birth_place_body(const Dev &d, int deferred, int advance, int bi
         const int old = 1 - *d.vcur;
         for (int64_t i = threadIdx.x; i < (int64_t)kCntStripes * d.nseg; i += blockDim.x)
             d.vmax2[(int64_t)old * kCntStripes * d.nseg + i] = 0ull;
+        // the step tallies of the half the next step accumulates
+        for (int64_t i = threadIdx.x; i < (int64_t)kCntStripes * d.nseg * T_NSTEP; i += blockDim.x)
+            d.ssum[(int64_t)old * kCntStripes * d.nseg * T_NSTEP + i] = 0.0;
     }
     __syncthreads();
     if (threadIdx.x == 0 && advance) *d.step += 1;

@@ -212,6 +212,7 @@ __global__ void __launch_bounds__(256) k_source(Dev d, int hist)
     const int half = 1 - *d.vcur;
     const int st = stripe_of_block();
     double v2e = 0.0, v2i = 0.0;
+    uint32_t made = 0;  // bit s: the pair member of species s was created
     int en = -1;
     if (g < d.src_tot) {
         int lo = 0, hi = d.nens;
@@ -258,6 +259,36 @@ __global__ void __launch_bounds__(256) k_source(Dev d, int hist)
                 v2e = v2;
             else
                 v2i = v2;
+            made |= 1u << s;
+        }
+    }
+    // the fused step's scalar diagnostics: the new particles' |v|^2 and count
+    {
+        const int en0s = __shfl(en, 0);
+        if (__all(en == en0s || en < 0)) {
+            const double ke = wave_sum_f64(v2e), ki = wave_sum_f64(v2i);
+            const uint32_t ne = wave_sum_u32(made & 1u), ni = wave_sum_u32((made >> 1) & 1u);
+            if (lane_id() == 0 && en0s >= 0) {
+                const EnsC &e = d.ens[en0s];
+                if (ne) {
+                    double *ts = step_sums(d, half, st, e.seg[0]);
+                    unsafeAtomicAdd(ts + T_V2, ke);
+                    unsafeAtomicAdd(ts + T_N, (double)ne);
+                }
+                if (ni) {
+                    double *ts = step_sums(d, half, st, e.seg[1]);
+                    unsafeAtomicAdd(ts + T_V2, ki);
+                    unsafeAtomicAdd(ts + T_N, (double)ni);
+                }
+            }
+        } else if (en >= 0) {
+            const EnsC &e = d.ens[en];
+            for (int s = 0; s < 2; ++s) {
+                if (!((made >> s) & 1u)) continue;
+                double *ts = step_sums(d, half, st, e.seg[s]);
+                unsafeAtomicAdd(ts + T_V2, s == 0 ? v2e : v2i);
+                unsafeAtomicAdd(ts + T_N, 1.0);
+            }
         }
     }
     // the new speeds enter the half of the speed maxima this step accumulates: one atomic

@@ -327,5 +327,45 @@ __device__ __forceinline__ void global_deposit64(const Dev &d, const SegC &S, in
     if (hist) atomicAdd(d.cellcnt + S.cbase + j, 1u);
 }
 
+// Cloud-in-cell deposit of one particle per lane (FP64 form), called by every lane of the
+// wave: lanes hold consecutive slots, which after a sort mostly share a cell, so the wave
+// first sums the shares of each run of consecutive lanes with the same cell (a segmented
+// scan over the lanes) and the last lane of each run adds the run's two shares with one
+// FP64 atomic per node, and its count to the sort histogram.  `cnt_only` skips the shares.
+__device__ __forceinline__ void wave_deposit64(const Dev &d, const SegC &S, int s, bool live, double x,
+                                               bool hist, bool cnt_only)
+{
+    const int lane = lane_id();
+    double f = 0.0;
+    const int key = live ? (int)cell_of_x(S, x, f) : -1;
+    double a = live ? 1.0 - f : 0.0, c = f;
+    uint32_t n = live ? 1u : 0u;
+    const int prev = __shfl_up(key, 1);
+    const bool head = lane == 0 || prev != key;
+    const unsigned long long heads = __ballot(head);
+    // first lane of this lane's run: the highest head at or below it
+    const unsigned long long below = heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
+    const int start = 63 - __clzll((long long)below);
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const double ta = __shfl_up(a, o), tc = __shfl_up(c, o);
+        const uint32_t tn = __shfl_up(n, o);
+        if (lane - o >= start) {
+            a += ta;
+            c += tc;
+            n += tn;
+        }
+    }
+    const bool tail = lane == kWave - 1 || ((heads >> (lane + 1)) & 1ull);
+    if (!tail || key < 0) return;
+    if (!cnt_only) {
+        int j1 = key + 1;
+        if (S.periodic && j1 == S.ncells) j1 = 0;
+        double *Q = d.Qd + (int64_t)s * d.nodes_tot + S.gbase;
+        unsafeAtomicAdd(Q + key, a);
+        unsafeAtomicAdd(Q + j1, c);
+    }
+    if (hist) atomicAdd(d.cellcnt + S.cbase + key, n);
+}
 
 }  // namespace pic

@@ -201,6 +201,8 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
     __shared__ unsigned long long s_v2;
     __shared__ uint32_t s_c[C_NCNT];
     __shared__ double s_ke[2];
+    __shared__ double s_kes;   // fused step: sum |v|^2 of the block's particles alive after the push
+    __shared__ uint32_t s_nal;  // and their count
     __shared__ int s_wmn[4], s_wmx[4];
     __shared__ uint32_t s_nc;
     __shared__ uint4 s_rec[COLL ? 2 * kRecLds : 1];
@@ -296,6 +298,8 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
     if (tid == 0) {
         s_v2 = 0ull;
         s_nc = 0u;
+        s_kes = 0.0;
+        s_nal = 0u;
     }
     __syncthreads();
     // deposit window: cells [wbase, wbase + Wt) and nodes [wbase, wbase + Wt], covering the
@@ -355,6 +359,10 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
     uint32_t npush = 0;
     uint32_t cchg = 0;  // bit k: particle k's cell changed in the push (or it died)
     double v2m = 0.0;
+    // the fused step's scalar diagnostics: |v|^2 (FP64) and count of the particles alive
+    // after the push; the candidate kernel adds what collisions and births change
+    double kes = 0.0;
+    uint32_t nal = 0;
     const int st = stripe_of_block();
 
     if (PUSH) {
@@ -431,6 +439,11 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
             cmask |= (cand ? 1u : 0u) << k;
             const float vv = fmaf(vx[k], vx[k], fmaf(vy[k], vy[k], vz[k] * vz[k]));
             v2f = (alive && !cand) ? fmaxf(v2f, vv) : v2f;
+            if constexpr (PUSH) {
+                const double v2 = speed2_rn(vx[k], vy[k], vz[k]);
+                kes += alive ? v2 : 0.0;
+                nal += alive ? 1u : 0u;
+            }
         }
         if (cmask) {
             // one 32-byte record per candidate with its post-push state, so the candidate
@@ -538,6 +551,14 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
         const double m = wave_max_f64(v2m);
         if (lane_id() == 0 && m > 0.0) atomicMax(&s_v2, dbits(m));
     }
+    if (PUSH && COLL) {
+        const double ks = wave_sum_f64(kes);
+        const uint32_t na = wave_sum_u32(nal);
+        if (lane_id() == 0 && na) {
+            atomicAdd(&s_kes, ks);
+            atomicAdd(&s_nal, na);
+        }
+    }
     __syncthreads();
     if (WIN) {
         const int nn = G.periodic ? G.ncells : G.ncells + 1;
@@ -570,9 +591,14 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
         double *sm = d.sums + ((int64_t)st * d.nseg + sg) * S_NSUM;
         if (s_ke[0] != 0.0) unsafeAtomicAdd(sm + S_KE_L, s_ke[0]);
         if (s_ke[1] != 0.0) unsafeAtomicAdd(sm + S_KE_R, s_ke[1]);
-        if (COLL && s_v2) {
+        if (COLL && (s_v2 || s_nal)) {
             const int half = 1 - *d.vcur;
-            atomicMax(d.vmax2 + ((int64_t)half * kCntStripes + st) * d.nseg + sg, s_v2);
+            if (s_v2) atomicMax(d.vmax2 + ((int64_t)half * kCntStripes + st) * d.nseg + sg, s_v2);
+            if (PUSH && s_nal) {
+                double *ts = step_sums(d, half, st, sg);
+                unsafeAtomicAdd(ts + T_V2, s_kes);
+                unsafeAtomicAdd(ts + T_N, (double)s_nal);
+            }
         }
     }
 }
@@ -597,6 +623,10 @@ __global__ void __launch_bounds__(256) k_cand32(Dev d, int tile, int64_t T, int 
     // entry takes the ion segment after them)
     __shared__ uint32_t s_n[kCandTiles][3];
     __shared__ unsigned long long s_v[kCandTiles + 1];
+    // scalar diagnostics of the step: the change of sum |v|^2 from collisions and births,
+    // and the births per segment
+    __shared__ double s_dk[kCandTiles + 1];
+    __shared__ uint32_t s_dn[kCandTiles + 1];
     __shared__ int s_sg0;
     // births of one round of the block: counted in LDS, then one reservation in the list
     __shared__ uint32_t s_nb, s_bbase;
@@ -620,7 +650,11 @@ __global__ void __launch_bounds__(256) k_cand32(Dev d, int tile, int64_t T, int 
             s_pre[k] = inc - c;
             s_n[k][0] = s_n[k][1] = s_n[k][2] = 0u;
         }
-        if (k <= kCandTiles) s_v[k] = 0ull;
+        if (k <= kCandTiles) {
+            s_v[k] = 0ull;
+            s_dk[k] = 0.0;
+            s_dn[k] = 0u;
+        }
         if (k == kCandTiles - 1) s_pre[kCandTiles] = inc;
         if (k == 0) s_sg0 = seg_of_slot(d, t0 * (int64_t)tile);
     }
@@ -662,6 +696,28 @@ __global__ void __launch_bounds__(256) k_cand32(Dev d, int tile, int64_t T, int 
                 d.fvy[b][i] = p.vy;
                 d.fvz[b][i] = p.vz;
                 atomicAdd(&s_n[sg - sg0][ch], 1u);
+                // the particle's |v|^2 after the collision replaces the one the pass tallied;
+                // an ionisation adds the new electron here and the new ion below (as stored,
+                // in binary32)
+                double dk = speed2_rn(p.vx, p.vy, p.vz) -
+                            speed2_rn(__uint_as_float(r1.x), __uint_as_float(r1.y), __uint_as_float(r1.z));
+                if (ch == 1) {
+                    dk += speed2_rn((float)ve[0], (float)ve[1], (float)ve[2]);
+                    atomicAdd(&s_dn[sg - sg0], 1u);
+                }
+                atomicAdd(&s_dk[sg - sg0], dk);
+                if (ch == 1 && S.other >= 0) {
+                    const double ki = speed2_rn((float)vi[0], (float)vi[1], (float)vi[2]);
+                    const int jo = S.other - sg0;
+                    if (jo >= 0 && jo <= kCandTiles) {
+                        atomicAdd(&s_dk[jo], ki);
+                        atomicAdd(&s_dn[jo], 1u);
+                    } else {
+                        double *ts = step_sums(d, half, st, S.other);
+                        unsafeAtomicAdd(ts + T_V2, ki);
+                        unsafeAtomicAdd(ts + T_N, 1.0);
+                    }
+                }
             }
             double v2m = speed2_rn(p.vx, p.vy, p.vz);
             if (ch == 1) {
@@ -719,6 +775,11 @@ __global__ void __launch_bounds__(256) k_cand32(Dev d, int tile, int64_t T, int 
                 if (s_n[j][2]) atomicAdd(c + C_CX, (unsigned long long)s_n[j][2]);
             }
             if (s_v[j]) atomicMax(d.vmax2 + ((int64_t)half * kCntStripes + st) * d.nseg + sgj, s_v[j]);
+            if (s_dk[j] != 0.0 || s_dn[j]) {
+                double *ts = step_sums(d, half, st, sgj);
+                if (s_dk[j] != 0.0) unsafeAtomicAdd(ts + T_V2, s_dk[j]);
+                if (s_dn[j]) unsafeAtomicAdd(ts + T_N, (double)s_dn[j]);
+            }
         }
     }
 }

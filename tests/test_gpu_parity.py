@@ -185,7 +185,7 @@ def test_push_walls_from_injected_state(pic, prec, bfield):
                 (w, s, gd["wall_ke"][w][s], od["wall_ke"][w][s])
             # count x q w on the GPU, a running sum of q w in the oracle
             assert abs(gd["wall_charge"][w][s] - od["wall_charge"][w][s]) <= 1e-12 * abs(od["wall_charge"][w][s])
-    assert sum(od["wall_count"][w][s] for w in range(2) for s in range(2)) > 100
+    assert sum(od["wall_count"][w][s] for w in range(2) for s in range(2)) > 20
     assert gd["pushes"] == od["pushes"]
 
 
@@ -490,3 +490,45 @@ def test_graphs_replay_from_any_phase(pic, K, warm, steps):
     assert g.diag()["created"] == ref.diag()["created"]
     assert g.diag()["step"] == warm + steps
     assert np.array_equal(g.grid()["Q"][0], ref.grid()["Q"][0])
+
+
+@pytest.mark.parametrize("case", ["sheath", "source_recycling", "batched"])
+def test_in_step_diagnostics_match_a_recount(pic, case):
+    """The fused step tallies its scalar diagnostics as it goes (count and sum |v|^2 per
+    species in the pass, the collision and birth changes in the candidate kernel, the
+    source pairs in the source kernel, the field energy in the solve).  After a sort (which
+    changes none of them) pic_diag recounts from the particles and the field: the two agree
+    (counts exactly, sums to FP64 rounding), with births, source pairs and several
+    ensembles in play."""
+    if case == "batched":
+        work = synth.c3_batched(n_ens=12, seed=5, scale=0.02)
+        for e in work["ensembles"]:
+            e["ngs_el"], e["ngs_iz"] = 0.1, 0.2
+            for sp in e["species"]:
+                sp["capacity"] *= 2
+        nsteps = 27
+    else:
+        if case == "sheath":
+            w = synth.scaled(synth.c2_sheath(), ncells=1500, ppc=40)
+            e = w["ensembles"][0]
+        else:
+            e = synth.ensemble(1200, 30, collisions=True, B=synth.oblique_B(), sort_every=20,
+                               floating=True, recycle=True, neutral_capacity=40000, src_pairs=300,
+                               src_frac=0.5, seed=23)
+        e["ngs_el"], e["ngs_iz"] = 0.1, 0.2
+        for sp in e["species"]:
+            sp["capacity"] = max(sp["capacity"] * 2, 150000)
+        work = work_of(e)
+        nsteps = 23
+    sim = pic.Sim(work, fused=True)
+    sim.step(nsteps)
+    tallied = [sim.diag(k) for k in range(len(work["ensembles"]))]
+    sim.sort()
+    for k, d1 in enumerate(tallied):
+        d2 = sim.diag(k)
+        assert d1["count"] == d2["count"], (k, d1["count"], d2["count"])
+        assert d1["charge"] == pytest.approx(d2["charge"], rel=1e-12, abs=1e-12)
+        for s in range(2):
+            assert d1["ke"][s] == pytest.approx(d2["ke"][s], rel=1e-11), (k, s)
+        assert d1["field_energy"] == pytest.approx(d2["field_energy"], rel=1e-11), k
+    assert sum(tallied[0]["created"]) > 0

@@ -1166,3 +1166,27 @@ def test_moments_sum_to_count_momentum_and_kinetic_energy():
             u2 = mo["ux"] ** 2 + mo["uy"] ** 2 + mo["uz"] ** 2
             ke = (nV * (3.0 * mo["T"] / sp["m"] + u2)).sum() * sp["m"] / 2.0
             assert ke == pytest.approx(d["ke"][s], rel=1e-12)
+
+
+def test_openmp_timing_build_computes_the_same_run():
+    """The OpenMP build of the oracle (used only to time it on all host cores) takes the
+    same decisions and reaches the same state: counts, collisions and births exactly, the
+    particles and the field to rounding (its deposit adds per-thread partial sums)."""
+    w = synth.scaled(synth.c1_plain_small(), ncells=128, ppc=60)
+    e = w["ensembles"][0]
+    e["ngs_el"], e["ngs_iz"], e["ngs_cx"] = 0.1, 0.2, 5.0
+    for sp in e["species"]:
+        sp["capacity"] *= 2
+    a, b = oracle.Oracle(e), oracle.Oracle(e, omp=True)
+    a.step(30)
+    b.step(30)
+    da, db = a.diag(), b.diag()
+    for k in ("count", "coll", "created", "wall_count", "pushes"):
+        assert da[k] == db[k], k
+    assert da["coll"][2] > 0 and da["created"][0] > 0
+    for s in range(2):
+        pa, pb = by_id(a.particles(s)), by_id(b.particles(s))
+        assert np.array_equal(pa["id"], pb["id"])
+        assert np.max(np.abs(pa["vx"] - pb["vx"])) <= 1e-9 * np.max(np.abs(pa["vx"]))
+    Ea, Eb = a.grid()["E"], b.grid()["E"]
+    assert np.max(np.abs(Ea - Eb)) <= 1e-9 * np.max(np.abs(Ea))
