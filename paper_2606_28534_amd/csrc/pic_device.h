@@ -265,6 +265,11 @@ __device__ __forceinline__ double speed2_rn(double a, double b, double c)
     return __dadd_rn(__dadd_rn(__dmul_rn(a, a), __dmul_rn(b, b)), __dmul_rn(c, c));
 }
 
+// |v|^2 in binary32 (two fused multiply-adds): the FP32 pass's per-particle speed for its
+// collision bound and its kinetic-energy tally; the candidate kernel takes the same
+// expression off for a particle that collides, so the two cancel exactly.
+__device__ __forceinline__ float speed2_f32(float a, float b, float c) { return fmaf(a, a, fmaf(b, b, c * c)); }
+
 __device__ __forceinline__ int stripe_of_block() { return (int)(blockIdx.x & (kCntStripes - 1)); }
 
 // The per-step scalar tallies of segment sg in stripe st of half `half`.

@@ -170,7 +170,10 @@ __device__ __forceinline__ int p_push(const Dev &d, const SegC &S, const EnsC &e
         }
         p.x = x;
         if (x >= 0.0 && x < L) return 0;
-        return (x < 0.0) ? 1 : 2;  // NaN counts as the right wall
+        // a non-finite position (from a non-finite field) leaves at the right wall and the
+        // step reports PIC_ENONFINITE
+        if (!(fabs(x) <= 1.0e300)) atomicOr(d.err, (int)E_NONFINITE);
+        return (x < 0.0) ? 1 : 2;
     }
 }
 

@@ -359,9 +359,10 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
     uint32_t npush = 0;
     uint32_t cchg = 0;  // bit k: particle k's cell changed in the push (or it died)
     double v2m = 0.0;
-    // the fused step's scalar diagnostics: |v|^2 (FP64) and count of the particles alive
-    // after the push; the candidate kernel adds what collisions and births change
-    double kes = 0.0;
+    // the fused step's scalar diagnostics: |v|^2 and count of the particles alive after the
+    // push (|v|^2 per particle and the thread's few particles summed in binary32, FP64 from
+    // the wave sum on); the candidate kernel adds what collisions and births change
+    float kes = 0.f;
     uint32_t nal = 0;
     const int st = stripe_of_block();
 
@@ -376,8 +377,14 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
             const float Ep = fmaf(off[k], ec[k].y, ec[k].x) + eext;
             boris<float>(h, tv, sv, Ep, vx[k], vy[k], vz[k]);
             float o = off[k] + vx[k] * dtdx;
+            // a non-finite field or velocity makes o NaN or infinite (and a step of 2^30
+            // cells is no valid motion): such a particle is dropped and the step reports
+            // PIC_ENONFINITE; o is replaced before its conversion to a cell shift
+            const bool fin = fabsf(o) < 1073741824.0f;
+            o = fin ? o : 0.0f;
+            bad |= (alive && !fin) ? 1u : 0u;
             const float fl = floorf(o);
-            int c = (alive ? cell[k] : 0) + (int)fl;
+            int c = ((alive && fin) ? cell[k] : 0) + (int)fl;
             o -= fl;
             const bool up = o >= 1.0f;
             off[k] = up ? o - 1.0f : o;
@@ -386,11 +393,11 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
                 c = (c < 0) ? c + N : ((c >= N) ? c - N : c);
                 const bool inv = alive && (c < 0 || c >= N);  // moved more than a period
                 bad |= inv ? 1u : 0u;
-                const int cn = (alive && !inv) ? c : kDead;
+                const int cn = (alive && fin && !inv) ? c : kDead;
                 cchg |= (cn != cell[k] ? 1u : 0u) << k;
                 cell[k] = cn;
             } else {
-                const bool out = alive && (c < 0 || c >= N);
+                const bool out = alive && fin && (c < 0 || c >= N);
                 if (out) {
                     const double v2 = speed2_rn(vx[k], vy[k], vz[k]);
                     if (c < 0) {
@@ -410,7 +417,7 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
                             atomicOr(d.err, (int)E_CAP_PART);
                     }
                 }
-                const int cn = out ? kDead : cell[k] == kDead ? kDead : c;
+                const int cn = (out || !fin) ? kDead : cell[k] == kDead ? kDead : c;
                 cchg |= (cn != cell[k] ? 1u : 0u) << k;
                 cell[k] = cn;
             }
@@ -437,11 +444,10 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
             const bool alive = cell[k] != kDead;
             const bool cand = alive && ((rmask >> k) & 1u) && (!SORT || dst[SORT ? k : 0] >= 0);
             cmask |= (cand ? 1u : 0u) << k;
-            const float vv = fmaf(vx[k], vx[k], fmaf(vy[k], vy[k], vz[k] * vz[k]));
+            const float vv = speed2_f32(vx[k], vy[k], vz[k]);
             v2f = (alive && !cand) ? fmaxf(v2f, vv) : v2f;
             if constexpr (PUSH) {
-                const double v2 = speed2_rn(vx[k], vy[k], vz[k]);
-                kes += alive ? v2 : 0.0;
+                kes += alive ? vv : 0.f;
                 nal += alive ? 1u : 0u;
             }
         }
@@ -552,7 +558,7 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
         if (lane_id() == 0 && m > 0.0) atomicMax(&s_v2, dbits(m));
     }
     if (PUSH && COLL) {
-        const double ks = wave_sum_f64(kes);
+        const double ks = wave_sum_f64((double)kes);
         const uint32_t na = wave_sum_u32(nal);
         if (lane_id() == 0 && na) {
             atomicAdd(&s_kes, ks);
@@ -696,11 +702,12 @@ __global__ void __launch_bounds__(256) k_cand32(Dev d, int tile, int64_t T, int 
                 d.fvy[b][i] = p.vy;
                 d.fvz[b][i] = p.vz;
                 atomicAdd(&s_n[sg - sg0][ch], 1u);
-                // the particle's |v|^2 after the collision replaces the one the pass tallied;
-                // an ionisation adds the new electron here and the new ion below (as stored,
-                // in binary32)
+                // the particle's |v|^2 after the collision replaces the one the pass tallied
+                // (taken off exactly as the pass computed it); an ionisation adds the new
+                // electron here and the new ion below (as stored, in binary32)
                 double dk = speed2_rn(p.vx, p.vy, p.vz) -
-                            speed2_rn(__uint_as_float(r1.x), __uint_as_float(r1.y), __uint_as_float(r1.z));
+                            (double)speed2_f32(__uint_as_float(r1.x), __uint_as_float(r1.y),
+                                               __uint_as_float(r1.z));
                 if (ch == 1) {
                     dk += speed2_rn((float)ve[0], (float)ve[1], (float)ve[2]);
                     atomicAdd(&s_dn[sg - sg0], 1u);

@@ -56,8 +56,10 @@ def test_restart_is_bit_identical(pic, prec, fused, at):
     else:
         assert np.allclose(da["numax"], db["numax"], rtol=1e-12, atol=0)
     # the order of particles inside a cell after a sort is not fixed (atomic slot
-    # reservations), so sums over slots may differ in their last bits
-    assert np.allclose(da["ke"], db["ke"], rtol=1e-13, atol=0)
+    # reservations), so sums over slots may differ in their last bits; the fused FP32 step
+    # tallies |v|^2 in binary32 over each thread's slots (which particles share a thread
+    # follows that order), so its energies agree to binary32 rounding
+    assert np.allclose(da["ke"], db["ke"], rtol=(1e-6 if (prec == "fp32" and fused) else 1e-13), atol=0)
     for s in range(2):
         pa, pb = by_id(a.particles(0, s)), by_id(b.particles(0, s))
         assert np.array_equal(pa["id"], pb["id"]), s
@@ -87,3 +89,46 @@ def test_load_rejects_other_configuration(pic):
     assert ei.value.code == pic.PIC_EINVAL
     with pytest.raises(pic.PicError):
         b.load(buf[:100])
+
+
+@pytest.mark.parametrize("prec,collisions", [("fp32", False), ("fp64", False), ("fp64", True)])
+def test_restart_matches_the_oracle_window(pic, prec, collisions):
+    """Save at step 13, load into a fresh context, run on to step 20 and compare with the
+    FP64 oracle's uninterrupted 20-step window by particle id (the window tolerances of the
+    parity tests: fields rel 1e-5 in the FP32 form; counts exact, collisions included in
+    the FP64 form, whose decisions are taken on FP64 velocities like the oracle's)."""
+    import oracle
+    from parity_util import TOL_FIELD, TOL_MOMENT, compare_particles, rel
+
+    w = synth.scaled(synth.c2_sheath(), ncells=1500, ppc=40)
+    e = w["ensembles"][0]
+    e["collisions"] = collisions
+    if collisions:
+        e["ngs_el"], e["ngs_iz"] = 0.05, 0.05
+        for sp in e["species"]:
+            sp["capacity"] *= 2
+    work = {"name": "ckpt-oracle", "steps": 1, "precision": prec, "ensembles": [e]}
+    fused = prec == "fp32"
+    a = pic.Sim(work, fused=fused)
+    a.step(13)
+    buf = a.save()
+    a.close()
+    b = pic.Sim(work, fused=fused)
+    b.load(buf)
+    b.step(7)
+    o = oracle.Oracle(e)
+    o.step(20)
+    gd, od = b.diag(), o.diag()
+    assert gd["step"] == od["step"] == 20
+    for key in ("count", "wall_count", "pushes", "coll", "created"):
+        assert gd[key] == od[key], (key, gd[key], od[key])
+    if collisions:
+        assert sum(od["coll"]) > 0 and sum(od["created"]) > 0
+    for s in range(2):
+        vt, xt = (1e-9, 1e-8) if prec == "fp64" else (1e-4, 1e-4)
+        compare_particles(b.particles(0, s), o.particles(s), e["dx"], prec == "fp64", vtol=vt, xtol=xt)
+        assert abs(gd["ke"][s] - od["ke"][s]) <= TOL_MOMENT * abs(od["ke"][s])
+    g, r = b.grid(), o.grid()
+    for k in ("rho", "phi", "E"):
+        assert rel(g[k], r[k]) <= (1e-8 if prec == "fp64" else TOL_FIELD), (k, rel(g[k], r[k]))
+    b.close()

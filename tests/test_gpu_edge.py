@@ -171,3 +171,46 @@ def test_bad_injected_state_rejected(pic):
     # a good state still goes in afterwards
     sim.set_particles(0, 0, st["x"], st["vx"], st["vy"], st["vz"], st["id"], st["next_id"])
     assert len(sim.particles(0, 0)["id"]) == 100
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("periodic", [False, True])
+def test_nonfinite_field_is_reported(pic, prec, periodic):
+    """A NaN node field (put in through the test hook) reaches the particles of the cells
+    beside that node.  The push drops them (the FP32 pass replaces a non-finite offset
+    before it becomes a cell shift; the FP64 push clamps the cell of a non-finite x and
+    kills the particle) and sets the sticky flag, which the next call that reads the flags
+    reports as PIC_ENONFINITE.  Particles away from the node are pushed as usual."""
+    N = 64
+    e = synth.ensemble(N, 20, collisions=False, periodic=periodic, seed=9)
+    sim = pic.Sim(work_of(e, prec), fused=False)
+    E = np.zeros(sim.nnodes())
+    E[10] = np.nan
+    sim.set_fields(E)
+    n0 = len(sim.particles(0, 0)["id"])
+    sim.push()
+    with pytest.raises(pic.PicError) as ei:
+        sim.diag()
+    assert ei.value.code == pic.PIC_ENONFINITE
+    # the particles of cells 9 and 10 (the two that interpolate from node 10) are gone,
+    # the others are still there (nothing else moves them out in one step at E = 0)
+    p = sim.particles(0, 0)
+    left = n0 - len(p["id"])
+    assert 2 * 20 <= left <= 2 * 20 + 12, left
+    assert np.all(np.isfinite(p["x"])) and np.all(np.isfinite(p["vx"]))
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_nonfinite_step_is_reported(pic, prec):
+    """A charge weight so large that the field overflows (q w = 1e306 at 20 particles per
+    cell: the prefix sums reach infinity) makes the solve's field non-finite; pic_step
+    reports PIC_ENONFINITE after the step (the push drops every particle the field
+    reaches, as above)."""
+    e = synth.ensemble(64, 20, collisions=False, nspecies=1, seed=4, sort_every=5)
+    e["species"][0]["w"] = 1e306
+    sim = pic.Sim(work_of(e, prec), fused=(prec == "fp32"))
+    with pytest.raises(pic.PicError) as ei:
+        sim.step(1)
+    assert ei.value.code == pic.PIC_ENONFINITE
+    sim.close()

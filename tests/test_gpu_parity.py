@@ -498,8 +498,10 @@ def test_in_step_diagnostics_match_a_recount(pic, case):
     species in the pass, the collision and birth changes in the candidate kernel, the
     source pairs in the source kernel, the field energy in the solve).  After a sort (which
     changes none of them) pic_diag recounts from the particles and the field: the two agree
-    (counts exactly, sums to FP64 rounding), with births, source pairs and several
-    ensembles in play."""
+    (counts exactly, the charge and the field energy to FP64 rounding), with births, source
+    pairs and several ensembles in play.  The pass tallies |v|^2 in binary32 (per particle
+    and over a thread's <= 8 particles, relative rounding <= 8 x 2^-24 each) where the
+    recount takes it in FP64, so the kinetic energies agree to 1e-6."""
     if case == "batched":
         work = synth.c3_batched(n_ens=12, seed=5, scale=0.02)
         for e in work["ensembles"]:
@@ -529,6 +531,6 @@ def test_in_step_diagnostics_match_a_recount(pic, case):
         assert d1["count"] == d2["count"], (k, d1["count"], d2["count"])
         assert d1["charge"] == pytest.approx(d2["charge"], rel=1e-12, abs=1e-12)
         for s in range(2):
-            assert d1["ke"][s] == pytest.approx(d2["ke"][s], rel=1e-11), (k, s)
+            assert d1["ke"][s] == pytest.approx(d2["ke"][s], rel=1e-6), (k, s)
         assert d1["field_energy"] == pytest.approx(d2["field_energy"], rel=1e-11), k
     assert sum(tallied[0]["created"]) > 0
