@@ -328,6 +328,21 @@ int pic_adjoint_window(pic_ctx *ctx, int32_t nsteps, int32_t ckpt_every, void *s
                        size_t bytes, double *W, double *dW_dvx, int64_t dvx_len,
                        double *dW_dEext, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving or optimisation loops, harnesses that forbid hipMalloc): pic_adjoint_window with
+ * no scratch argument.  Its scratch (the window's checkpoints, recorded positions and fields,
+ * adjoint arrays, then dvx_len doubles for the by-id gradient) lives in a static device
+ * array of 160 MiB that the library holds on every GPU it runs on until the process ends;
+ * pic_init looks up its address on the context's device.  Calls that need more return
+ * PIC_EINVAL with the size in pic_last_error (the 2048-cell, 409,600-particle, 200-step
+ * window at a checkpoint every 20 steps needs about 127 MiB).  The call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine); it clears what must start at zero.
+ * Every call on one GPU shares that GPU's array, so calls that overlap on one GPU (two
+ * contexts on two host threads or two streams) race: serialise them.  Arguments, results,
+ * requirements and errors are otherwise those of pic_adjoint_window; synchronises `stream`. */
+int pic_adjoint_window_noalloc(pic_ctx *ctx, int32_t nsteps, int32_t ckpt_every, double *W,
+                               double *dW_dvx, int64_t dvx_len, double *dW_dEext, void *stream);
+
 /* The library's autotuner: times the particle pass over `trial_steps` steps for every
  * candidate launch shape (particles per thread x widest LDS window span x, for the fused
  * pass, non-temporal streaming) and the sort scatter for each particles-per-thread and

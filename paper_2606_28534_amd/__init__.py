@@ -24,7 +24,7 @@ EXPORTS = ("pic_query_workspace", "pic_init", "pic_deposit", "pic_solve", "pic_p
            "pic_get_slots", "pic_set_particles", "pic_get_grid", "pic_get_gather_table",
            "pic_set_fields", "pic_set_step",
            "pic_nnodes", "pic_set_external_field", "pic_adjoint_query",
-           "pic_adjoint_window", "pic_autotune", "pic_checkpoint_size", "pic_save", "pic_load",
+           "pic_adjoint_window", "pic_adjoint_window_noalloc", "pic_autotune", "pic_checkpoint_size", "pic_save", "pic_load",
            "pic_timing", "pic_timing_read", "pic_graph_prepare", "pic_graph_launches",
            "pic_free", "pic_last_error")
 
@@ -122,6 +122,8 @@ def load_library():
     L.pic_adjoint_query.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]
     L.pic_adjoint_window.argtypes = [P, C.c_int32, C.c_int32, P, C.c_size_t, C.POINTER(C.c_double),
                                      P, C.c_int64, C.POINTER(C.c_double), P]
+    L.pic_adjoint_window_noalloc.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(C.c_double), P, C.c_int64,
+                                             C.POINTER(C.c_double), P]
     L.pic_autotune.argtypes = [P, C.c_int32, P, P]
     L.pic_checkpoint_size.argtypes = [P, C.POINTER(C.c_size_t), P]
     L.pic_save.argtypes = [P, P, C.c_size_t, P]
@@ -274,6 +276,16 @@ class Sim:
                                               C.c_void_p(scratch.data_ptr()), nb.value, C.byref(W),
                                               _ptr(g), cap, C.byref(gE), self._s()))
         del scratch
+        return W.value, g, gE.value
+
+    def adjoint_window_noalloc(self, nsteps, ckpt_every=20):
+        """adjoint_window on the library's static device scratch (no device allocation in
+        the call).  Returns (W, dW/dv_x0 indexed by particle id, dW/dE_ext)."""
+        cap = int(self.work["ensembles"][0]["species"][0]["capacity"])
+        g = np.zeros(cap)
+        W, gE = C.c_double(0), C.c_double(0)
+        self._check(self.L.pic_adjoint_window_noalloc(self.h, int(nsteps), int(ckpt_every), C.byref(W),
+                                                      _ptr(g), cap, C.byref(gE), self._s()))
         return W.value, g, gE.value
 
     def autotune(self, trial_steps=10):

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -16,6 +17,14 @@
 #include "pic_kernels.h"
 
 using namespace pic;
+
+// Device scratch of pic_adjoint_window_noalloc, the adjoint window for callers that cannot
+// allocate: one copy of this array on every GPU the library runs on, held until the process
+// ends.  Host code never passes the array's name to a kernel or copy (on the host it is a
+// stand-in, not a device address): pic_init looks up its address on the current device once
+// (hipGetSymbolAddress) and every use goes through that pointer.
+constexpr size_t kStaticScratchBytes = (size_t)160 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
 namespace {
 
@@ -341,6 +350,8 @@ struct pic_ctx {
     // call that changes particles or fields between steps clears it.
     bool insitu = false;
     hipStream_t cap_stream = nullptr;
+    // device address of the static scratch array on the context's GPU
+    void *static_scratch = nullptr;
     // captured windows of the fused step, keyed by (first step's phase in the sort cycle,
     // number of steps); each replays from that phase with the prepared-sort state the
     // phase implies
@@ -354,6 +365,29 @@ struct pic_ctx {
 };
 
 namespace {
+
+// The static scratch array's device address per GPU, looked up once per device with that
+// device current (each GPU holds its own copy of the array at its own address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+hipError_t static_scratch_address(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 int fail(pic_ctx *c, int code, const std::string &m)
 {
@@ -678,6 +712,7 @@ int pic_init(const pic_config *cfg, void *workspace, size_t bytes, void *stream,
     hipError_t e;
 #define IHIP(expr)                                              \
     if ((e = (expr)) != hipSuccess) return done(hipfail(c, e, #expr));
+    IHIP(static_scratch_address(&c->static_scratch));
     IHIP(hipMemsetAsync(c->ws, 0, need, s));
     IHIP(hipMemcpyAsync((void *)d.seg, c->P.seg.data(), c->P.seg.size() * sizeof(SegC), hipMemcpyHostToDevice, s));
     IHIP(hipMemcpyAsync((void *)d.ens, c->P.ens.data(), c->P.ens.size() * sizeof(EnsC), hipMemcpyHostToDevice, s));
@@ -1473,6 +1508,27 @@ int pic_adjoint_window(pic_ctx *c, int32_t nsteps, int32_t ckpt_every, void *scr
     if (!c || !scratch_dev || nsteps < 1 || ckpt_every < 1 || !W || !dW_dvx || !dW_dEext) return PIC_EINVAL;
     return adjoint_window_impl(c, nsteps, ckpt_every, (char *)scratch_dev, bytes, W, dW_dvx, dvx_len, dW_dEext,
                                nullptr, stream);
+}
+
+int pic_adjoint_window_noalloc(pic_ctx *c, int32_t nsteps, int32_t ckpt_every, double *W, double *dW_dvx,
+                               int64_t dvx_len, double *dW_dEext, void *stream)
+{
+    if (!c || nsteps < 1 || ckpt_every < 1 || !W || !dW_dvx || dvx_len < 0 || !dW_dEext) return PIC_EINVAL;
+    if (!c->static_scratch) return fail(c, PIC_EHIP, "static scratch address not looked up");
+    const char *why = "";
+    if (adj_check(c, &why)) return fail(c, PIC_EINVAL, why);
+    // the window's layout, then the by-id gradient (dvx_len doubles) after it
+    const size_t lay = adj_layout(c, nsteps, ckpt_every).bytes;
+    const size_t need = lay + align_up((size_t)std::max<int64_t>(dvx_len, 1) * 8);
+    if (need > kStaticScratchBytes)
+        return fail(c, PIC_EINVAL, "adjoint window needs " + std::to_string(need) +
+                                       " bytes of scratch, more than the static array's " +
+                                       std::to_string(kStaticScratchBytes) +
+                                       " (fewer particles, steps or a longer checkpoint interval fit; "
+                                       "pic_adjoint_window takes a caller buffer of any size)");
+    char *base = (char *)c->static_scratch;
+    return adjoint_window_impl(c, nsteps, ckpt_every, base, lay, W, dW_dvx, dvx_len, dW_dEext,
+                               (double *)(base + lay), stream);
 }
 
 int pic_autotune(pic_ctx *c, int32_t trial_steps, int32_t *shape, void *stream)

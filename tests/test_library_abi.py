@@ -85,6 +85,7 @@ def test_null_context_calls_fail_cleanly(lib):
     for n in ("pic_deposit", "pic_solve", "pic_push", "pic_collide", "pic_sort"):
         assert getattr(L, n)(None, None) == P.PIC_EINVAL
     assert L.pic_step(None, 1, None) == P.PIC_EINVAL
+    assert L.pic_adjoint_window_noalloc(None, 1, 1, None, None, 0, None, None) == P.PIC_EINVAL
     assert L.pic_last_error(None) == b"null context"
 
 
