@@ -88,7 +88,7 @@ extern "C" {
 #define PIC_OK 0
 #define PIC_EINVAL (-1)      /* bad configuration, index or size                          */
 #define PIC_ECAPACITY (-2)   /* particle, birth or id capacity exceeded: state undefined  */
-#define PIC_ENONFINITE (-3)  /* NaN or Inf met in the field solve                          */
+#define PIC_ENONFINITE (-3)  /* NaN or Inf in the field solve or a particle's motion       */
 #define PIC_EHIP (-4)        /* HIP runtime error; message in pic_last_error               */
 #define PIC_ESTATE (-5)      /* call not valid in the current state                        */
 
@@ -200,12 +200,15 @@ int pic_query_workspace(const pic_config *cfg, size_t *bytes);
 
 /* Create a context on `workspace` (>= the queried size, device memory) and load the
  * particles: reading R17 (random load) or R19 (quiet start) per ensemble, then the
- * cloud-in-cell deposit Q^0.  The step counter starts at 0. */
+ * cloud-in-cell deposit Q^0.  The step counter starts at 0.  This is the particle load
+ * that opens the cycle of the paper's Background section, at the particles per cell of
+ * its sheath-case table (experimental setup). */
 int pic_init(const pic_config *cfg, void *workspace, size_t bytes, void *stream, pic_ctx **out);
 
 /* Cloud-in-cell deposit (Birdsall-Langdon linear weighting) of every alive particle into
- * the per-species node sums Q_s (FP32 form: int64 fixed point, 2^24 per particle; FP64
- * form: FP64 sums).  Replaces the previous Q. */
+ * the per-species node sums Q_s (FP32 form: int64 fixed point, 2^24 per particle, R15;
+ * FP64 form: FP64 sums).  Replaces the previous Q.  The "deposition to the grid" step of
+ * the cycle in the paper's Background section. */
 int pic_deposit(pic_ctx *ctx, void *stream);
 
 /* Field solve from Q: rho_j = sum_s q_s w_s Q_{s,j} / V_j, optionally smoothed (R23), the
@@ -221,21 +224,30 @@ int pic_solve(pic_ctx *ctx, void *stream);
 /* Gather E at each particle (linear), Boris push in E + E_ext along x and uniform B,
  * position update, absorbing walls (R8: absorbed slots are marked dead and tallied; the
  * next sort compacts them) or periodic wrap.  With recycling (R24) the neutrals stream
- * freely, leave through the walls, and the ions absorbed in this push return as neutrals. */
+ * freely, leave through the walls, and the ions absorbed in this push return as neutrals.
+ * The "force interpolation" and "mover" steps of the cycle in the paper's Background
+ * section (the mover is where its profiles put most of the time: performance results), in
+ * the magnetised layer between absorbing walls of its sheath cases (experimental setup). */
 int pic_push(pic_ctx *ctx, void *stream);
 
 /* Null-collision Monte Carlo (R9-R14): per-particle Philox decision against the bound
  * nu_max, channel choice, scattering kinematics, ionisation births appended with ids
  * next_id + rank of the parent id.  The step's volumetric source pairs (R25) are created
- * here too, numbered before the births. */
+ * here too, numbered before the births.  The "Monte Carlo collisions" step of the cycle in
+ * the paper's Background section, against the uniform neutral background of its sheath
+ * cases (experimental setup). */
 int pic_collide(pic_ctx *ctx, void *stream);
 
 /* Counting sort of each species by cell (histogram, exclusive scan, scatter); drops the
- * absorbed slots, so it is also the stream compaction.  Order inside a cell is unspecified. */
+ * absorbed slots, so it is also the stream compaction.  Order inside a cell is unspecified.
+ * The "natural sorting" of particles by cell that the paper's Background section credits
+ * for faster collision operators (its arranger, the other large item of its profiles:
+ * performance results). */
 int pic_sort(pic_ctx *ctx, void *stream);
 
 /* nsteps full steps (R2 order): solve, push + walls, collide, deposit, and a sort when
- * the new step count is a multiple of K.  With cfg.fused = 1 the particle stages run as
+ * the new step count is a multiple of K: the whole cycle of the paper's Background
+ * section, once per time step.  With cfg.fused = 1 the particle stages run as
  * one pass per step and the steps replay captured HIP graphs (see pic_graph_prepare);
  * in the FP32 form with
  * K >= 2 the step before a sort step also counts the cells, and the sort step's pass

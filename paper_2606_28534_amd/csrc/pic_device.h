@@ -270,6 +270,12 @@ __device__ __forceinline__ double speed2_rn(double a, double b, double c)
 // expression off for a particle that collides, so the two cancel exactly.
 __device__ __forceinline__ float speed2_f32(float a, float b, float c) { return fmaf(a, a, fmaf(b, b, c * c)); }
 
+// A tile's candidate count (at most 2048) as the pass writes it, tagged with the tile's
+// segment (< 1024) and ensemble (< 1024), so the candidate kernel learns all three from one
+// load.
+constexpr uint32_t kCandCountMask = 0xFFFu;
+__device__ __forceinline__ uint32_t cand_tag(int sg, int ens) { return ((uint32_t)sg << 12) | ((uint32_t)ens << 22); }
+
 __device__ __forceinline__ int stripe_of_block() { return (int)(blockIdx.x & (kCntStripes - 1)); }
 
 // The per-step scalar tallies of segment sg in stripe st of half `half`.
