@@ -93,19 +93,24 @@ struct SegGrid {
 // Cells a particle may move in one step and still deposit through the tile's window.
 constexpr int kWinMargin = 2;
 
+// The LDS window holds one 64-bit word per cell: the count of the cell's particles in the
+// high 24 bits and the sum of their right-node shares (R15) in the low 40, so one LDS
+// atomic per run serves the deposit and the sort histogram alike.  A tile holds at most
+// 2048 particles, so the count stays below 2^12 and the share sum below 2^35.  The flush
+// gives node j the left shares of cell j, count x 2^24 - sum, plus the right shares of
+// cell j - 1.
+constexpr int kWinShift = 40;
+constexpr unsigned long long kWinSumMask = (1ull << kWinShift) - 1ull;
+
 // One run of equal cells into the LDS window (or straight to HBM outside it).
 __device__ __forceinline__ void emit_run(const Dev &d, const SegGrid &G, int s, int cell, uint32_t cnt,
                                          uint32_t sum, int wbase, int W, bool depo, bool hist,
-                                         unsigned long long *sQ, uint32_t *sH)
+                                         unsigned long long *sA)
 {
     if (cnt == 0) return;
     const int rel = cell - wbase;
     if (rel >= 0 && rel < W) {
-        if (depo) {
-            atomicAdd(&sQ[rel], (unsigned long long)cnt * 16777216ull - (unsigned long long)sum);
-            atomicAdd(&sQ[rel + 1], (unsigned long long)sum);
-        }
-        if (hist) atomicAdd(&sH[rel], cnt);
+        if (depo || hist) atomicAdd(&sA[rel], ((unsigned long long)cnt << kWinShift) | (unsigned long long)sum);
         return;
     }
     if (depo) {
@@ -196,8 +201,8 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
     static_assert(!SORT || (PUSH && DEPO && !HISTC), "the sorting pass is a fused pass");
 
     extern __shared__ unsigned long long s_dyn[];
-    unsigned long long *sQ = s_dyn;                // [W + 1]
-    uint32_t *sH = (uint32_t *)(s_dyn + (W + 1));  // [W], allocated when the histogram is on
+    unsigned long long *sA = s_dyn;             // [W]: count and right-share sum per cell
+    uint32_t *sCnt = (uint32_t *)(s_dyn + W);   // [W], the sorting pass's tile ranking
     __shared__ unsigned long long s_v2;
     __shared__ uint32_t s_c[C_NCNT];
     __shared__ double s_ke[2];
@@ -311,10 +316,7 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
         if (mx >= 0) {
             wbase = max(mn - kWinMargin, 0);
             Wt = min(mx + kWinMargin + 1 - wbase, W);
-            for (int i = tid; i <= Wt; i += 256) {
-                sQ[i] = 0ull;
-                if (hist && i < Wt) sH[i] = 0u;
-            }
+            for (int i = tid; i < Wt; i += 256) sA[i] = 0ull;
         }
     }
     // The segment constants of the push and of the bounds below, read into registers before
@@ -327,13 +329,14 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
     const bool per = S.periodic != 0;
     const int64_t seg_lo = S.base, seg_hi = S.base + S.cap;
     const SegGrid G{S.gbase, S.cbase, N, per};
+    // the tile's candidate count goes out tagged with its segment and ensemble (cand_tag)
+    const uint32_t ctag = COLL ? cand_tag(sg, S.ens) : 0u;
     // sorting pass: destinations in the other buffer (-1: none)
     int64_t dst[SORT ? PPT : 1];
     if constexpr (SORT) {
         const int mn = min(min(s_wmn[0], s_wmn[1]), min(s_wmn[2], s_wmn[3]));
         const int mx = max(max(s_wmx[0], s_wmx[1]), max(s_wmx[2], s_wmx[3]));
         const int Ws = mx >= 0 ? min(mx - mn + 1, W) : 0;
-        uint32_t *sCnt = sH;  // no histogram in this pass
         for (int i = tid; i < Ws; i += 256) sCnt[i] = 0u;
         __syncthreads();
         uint32_t *cursor = d.cursor + S.cbase;
@@ -361,14 +364,15 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
     double v2m = 0.0;
     // the fused step's scalar diagnostics: |v|^2 and count of the particles alive after the
     // push (|v|^2 per particle and the thread's few particles summed in binary32, FP64 from
-    // the wave sum on); the candidate kernel adds what collisions and births change
+    // the wave sum on; the count is the pushes less the absorptions); the candidate kernel
+    // adds what collisions and births change
     float kes = 0.f;
-    uint32_t nal = 0;
+    uint32_t nwl = 0, nwr = 0;
     const int st = stripe_of_block();
 
     if (PUSH) {
         // the loop below is straight-line code apart from the rare wall branch
-        uint32_t nwl = 0, nwr = 0, bad = 0;
+        uint32_t bad = 0;
         double kel = 0.0, ker = 0.0;
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
@@ -444,12 +448,11 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
             const bool alive = cell[k] != kDead;
             const bool cand = alive && ((rmask >> k) & 1u) && (!SORT || dst[SORT ? k : 0] >= 0);
             cmask |= (cand ? 1u : 0u) << k;
-            const float vv = speed2_f32(vx[k], vy[k], vz[k]);
-            v2f = (alive && !cand) ? fmaxf(v2f, vv) : v2f;
-            if constexpr (PUSH) {
-                kes += alive ? vv : 0.f;
-                nal += alive ? 1u : 0u;
-            }
+            // |v|^2 of a live particle, 0 for a dead slot (whose velocity is stale): the
+            // energy tally and, for the particles that keep their velocity, the speed bound
+            const float vv = alive ? speed2_f32(vx[k], vy[k], vz[k]) : 0.f;
+            v2f = cand ? v2f : fmaxf(v2f, vv);
+            if constexpr (PUSH) kes += vv;
         }
         if (cmask) {
             // one 32-byte record per candidate with its post-push state, so the candidate
@@ -537,7 +540,7 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
         for (int k = 0; k < PPT; ++k) {
             const bool alive = cell[k] != kDead;
             if (alive && cell[k] != rk) {
-                if (rk != kDead) emit_run(d, G, s, rk, rc, rs, wbase, Wt, DEPO, hist, sQ, sH);
+                if (rk != kDead) emit_run(d, G, s, rk, rc, rs, wbase, Wt, DEPO, hist, sA);
                 rk = cell[k];
                 rc = 0;
                 rs = 0;
@@ -545,7 +548,7 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
             rc += alive ? 1u : 0u;
             if (DEPO) rs += alive ? fixed_share(off[k]) : 0u;
         }
-        if (rk != kDead) emit_run(d, G, s, rk, rc, rs, wbase, Wt, DEPO, hist, sQ, sH);
+        if (rk != kDead) emit_run(d, G, s, rk, rc, rs, wbase, Wt, DEPO, hist, sA);
     }
 
     // block tallies
@@ -559,7 +562,7 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
     }
     if (PUSH && COLL) {
         const double ks = wave_sum_f64((double)kes);
-        const uint32_t na = wave_sum_u32(nal);
+        const uint32_t na = wave_sum_u32(npush - nwl - nwr);
         if (lane_id() == 0 && na) {
             atomicAdd(&s_kes, ks);
             atomicAdd(&s_nal, na);
@@ -570,25 +573,27 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
         const int nn = G.periodic ? G.ncells : G.ncells + 1;
         unsigned long long *Q = d.Qi + (int64_t)s * d.nodes_tot + G.gbase;
         for (int i = tid; Wt > 0 && i <= Wt; i += 256) {
+            const unsigned long long a = i < Wt ? sA[i] : 0ull;       // cell wbase + i
+            const unsigned long long am = i > 0 ? sA[i - 1] : 0ull;   // cell wbase + i - 1
+            const unsigned long long c = a >> kWinShift;
             if (DEPO) {
-                const unsigned long long v = sQ[i];
+                const unsigned long long v = (c << 24) - (a & kWinSumMask) + (am & kWinSumMask);
                 if (v) {
                     int node = wbase + i;
                     if (G.periodic && node >= G.ncells) node -= G.ncells;
                     if (node < nn) atomicAdd(Q + node, v);
                 }
             }
-            if (hist && i < Wt) {
-                const uint32_t c = sH[i];
+            if (hist && c) {
                 const int cl = wbase + i;
-                if (c && cl < G.ncells) atomicAdd(d.cellcnt + G.cbase + cl, c);
+                if (cl < G.ncells) atomicAdd(d.cellcnt + G.cbase + cl, (uint32_t)c);
             }
         }
     }
     if (COLL) {
         const uint32_t nl = 2 * min(s_nc, (uint32_t)kRecLds);
         for (uint32_t i = tid; i < nl; i += 256) d.crec[2 * first + i] = s_rec[i];
-        if (tid == 0) d.ctile[t] = s_nc;
+        if (tid == 0) d.ctile[t] = s_nc | ctag;
     }
     if (tid == 0 && (PUSH || COLL)) {
         unsigned long long *c = d.cnt + ((int64_t)st * d.nseg + sg) * C_NCNT;
@@ -617,130 +622,205 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
 // precisions), scatters, writes its velocity back to its slot, and on ionisation appends
 // the new pair.  Collision counts and the largest post-collision speed are gathered in LDS
 // per segment and go out once per block and segment.
+//
+// The block's critical path is a chain of dependent global round trips, so it is kept
+// short: the tile counts carry their tile's segment and ensemble (cand_tag), so one load
+// gives the block what it needs to stage those segments' constants and collision bounds
+// in LDS, in the same round trip as the candidate records; then the birth reservation.
 // =======================================================================================
 constexpr int kCandTiles = 32;
+constexpr int kCandSegs = 12;  // segments a block stages (more: read from global memory)
 
 template <bool CXREL>
 __global__ void __launch_bounds__(256) k_cand32(Dev d, int tile, int64_t T, int hist)
 {
     __shared__ uint32_t s_pre[kCandTiles + 1];
-    // block tallies per segment, indexed from the segment of the block's first tile (the
-    // block's tiles are consecutive, so they span fewer than kCandTiles segments; the last
-    // entry takes the ion segment after them)
-    __shared__ uint32_t s_n[kCandTiles][3];
-    __shared__ unsigned long long s_v[kCandTiles + 1];
+    __shared__ int s_tj[kCandTiles];  // staged entry of each tile's segment (-1: not staged)
+    // staged segment constants: entry j is segment s_sg[j] of ensemble s_en[j]
+    __shared__ SegC s_seg[kCandSegs];
+    __shared__ EnsC s_ens[kCandSegs];
+    __shared__ double s_nu[kCandSegs][2];  // nu_max, P_null
+    __shared__ int s_sg[kCandSegs], s_en[kCandSegs];
+    __shared__ int s_ns;
+    // block tallies per staged entry (segments that are not staged send theirs with
+    // atomics of their own)
+    __shared__ uint32_t s_n[kCandSegs][3];
+    __shared__ unsigned long long s_v[kCandSegs];
     // scalar diagnostics of the step: the change of sum |v|^2 from collisions and births,
     // and the births per segment
-    __shared__ double s_dk[kCandTiles + 1];
-    __shared__ uint32_t s_dn[kCandTiles + 1];
-    __shared__ int s_sg0;
+    __shared__ double s_dk[kCandSegs];
+    __shared__ uint32_t s_dn[kCandSegs];
     // births of one round of the block: counted in LDS, then one reservation in the list
     __shared__ uint32_t s_nb, s_bbase;
     const int64_t t0 = (int64_t)blockIdx.x * kCandTiles;
+    // per-launch values, read with the tile counts
+    const int b = *d.cur;
+    const uint32_t tag = (uint32_t)(*d.step);
+    const int half = 1 - *d.vcur;
     if (threadIdx.x < kWave) {
-        // the first wave loads the tile counts in parallel, resets them and scans
+        // the first wave loads the tile counts in parallel, resets them, scans, and lists
+        // the distinct segments of the tiles that hold candidates
         const int k = threadIdx.x;
         const int64_t t = t0 + k;
-        uint32_t c = 0;
+        uint32_t w = 0;
         if (k < kCandTiles && t < T) {
-            c = d.ctile[t];
+            w = d.ctile[t];
             d.ctile[t] = 0u;
         }
+        const uint32_t c = w & kCandCountMask;
         uint32_t inc = c;
 #pragma unroll
         for (int o = 1; o < kCandTiles; o <<= 1) {
             const uint32_t n = __shfl_up(inc, o);
             if (k >= o) inc += n;
         }
+        // a tile opens a new entry when it holds candidates and its segment differs from
+        // that of the last earlier tile with candidates (segments grow with the slot, so
+        // the keys of such tiles never decrease: the previous one is the running maximum
+        // over the lanes below)
+        const int key = c ? (int)((w >> 12) & 0x3FFu) : -1;
+        int pm = key;
+#pragma unroll
+        for (int o = 1; o < kCandTiles; o <<= 1) {
+            const int n = __shfl_up(pm, o);
+            if (k >= o) pm = max(pm, n);
+        }
+        int before = __shfl_up(pm, 1);
+        if (k == 0) before = -1;
+        const bool head = key >= 0 && key != before;
+        const unsigned long long hm = __ballot(head);
+        const int hidx = __popcll(hm & ((1ull << k) - 1ull)) - (head ? 0 : 1);  // entry of the run k is in
         if (k < kCandTiles) {
             s_pre[k] = inc - c;
-            s_n[k][0] = s_n[k][1] = s_n[k][2] = 0u;
+            s_tj[k] = (key >= 0 && hidx < kCandSegs) ? hidx : -1;
         }
-        if (k <= kCandTiles) {
+        if (k == kCandTiles - 1) s_pre[kCandTiles] = inc;
+        if (head && hidx < kCandSegs) {
+            s_sg[hidx] = key;
+            s_en[hidx] = (int)(w >> 22);
+        }
+        if (k == 0) s_ns = min(__popcll(hm), kCandSegs);
+        if (k < kCandSegs) {
+            s_n[k][0] = s_n[k][1] = s_n[k][2] = 0u;
             s_v[k] = 0ull;
             s_dk[k] = 0.0;
             s_dn[k] = 0u;
         }
-        if (k == kCandTiles - 1) s_pre[kCandTiles] = inc;
-        if (k == 0) s_sg0 = seg_of_slot(d, t0 * (int64_t)tile);
     }
     __syncthreads();
     const uint32_t m = s_pre[kCandTiles];
     if (m == 0) return;
-    const int sg0 = s_sg0;
-    const int b = *d.cur;
-    const uint32_t tag = (uint32_t)(*d.step);
+    {
+        // stage the segments' constants (word copies; all loads in one round trip)
+        const int ns = s_ns;
+        constexpr int WS = sizeof(SegC) / 4, WE = sizeof(EnsC) / 4;
+        static_assert(sizeof(SegC) % 4 == 0 && sizeof(EnsC) % 4 == 0, "word copies");
+        for (int i = threadIdx.x; i < ns * (WS + WE + 2); i += blockDim.x) {
+            const int j = i / (WS + WE + 2), o = i % (WS + WE + 2);
+            if (o < WS)
+                ((uint32_t *)&s_seg[j])[o] = ((const uint32_t *)(d.seg + s_sg[j]))[o];
+            else if (o < WS + WE)
+                ((uint32_t *)&s_ens[j])[o - WS] = ((const uint32_t *)(d.ens + s_en[j]))[o - WS];
+            else if (o == WS + WE)
+                s_nu[j][0] = d.numax[s_sg[j]];
+            else
+                s_nu[j][1] = d.pnull[s_sg[j]];
+        }
+    }
     const BirthBuf bb = birth_buf(d, (int)(tag & 1u));
     const int st = stripe_of_block();          // counters and speed maxima
     const int bst = (int)(blockIdx.x & (kStripes - 1));  // birth list
-    const int half = 1 - *d.vcur;
     for (uint32_t q0 = 0; q0 < m; q0 += blockDim.x) {
         const uint32_t q = q0 + threadIdx.x;
         const bool act = q < m;
-        int ch = -1, sg = 0;
+        // this candidate's tile: the last k with s_pre[k] <= q (tiles without candidates
+        // share their prefix with the next tile, which this picks)
+        int k = 0;
+        uint4 r0 = make_uint4(0u, 0u, 0u, 0u), r1 = r0;
+        if (act) {
+            int lo = 0, hi = kCandTiles;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (s_pre[mid] <= q)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            k = lo;
+            const uint4 *r = d.crec + 2 * ((t0 + k) * (int64_t)tile + (q - s_pre[k]));
+            r0 = r[0];
+            r1 = r[1];
+        }
+        if (q0 == 0) __syncthreads();  // the staged constants are in place
+        int ch = -1, sg = 0, j = -1;
         PS<false> p;
         double ve[3], vi[3];
+        int64_t i = 0;
+        int oth = -1;  // the ion segment of an electron segment (births)
         if (act) {
-            int k = 0;
-            while (k + 1 < kCandTiles && s_pre[k + 1] <= q) ++k;
-            const uint4 *r = d.crec + 2 * ((t0 + k) * (int64_t)tile + (q - s_pre[k]));
-            const uint4 r0 = r[0], r1 = r[1];
-            const int64_t i = (int64_t)r0.x;
+            j = s_tj[k];
+            i = (int64_t)r0.x;
             sg = (int)r1.w;
-            // copies: the stores below cannot alias them, so no field is read twice
-            const SegC S = d.seg[sg];
-            const EnsC e = d.ens[S.ens];
             p.cell = (int)r0.y;
             p.off = __uint_as_float(r0.z);
             p.id = r0.w;
             p.vx = __uint_as_float(r1.x);
             p.vy = __uint_as_float(r1.y);
             p.vz = __uint_as_float(r1.z);
-            ch = p_collide<false, CXREL>(e, S, S.species, d.numax[sg], d.pnull[sg], tag, p, ve, vi);
-            if (ch >= 0) {
-                d.fvx[b][i] = p.vx;
-                d.fvy[b][i] = p.vy;
-                d.fvz[b][i] = p.vz;
-                atomicAdd(&s_n[sg - sg0][ch], 1u);
-                // the particle's |v|^2 after the collision replaces the one the pass tallied
-                // (taken off exactly as the pass computed it); an ionisation adds the new
-                // electron here and the new ion below (as stored, in binary32)
-                double dk = speed2_rn(p.vx, p.vy, p.vz) -
-                            (double)speed2_f32(__uint_as_float(r1.x), __uint_as_float(r1.y),
-                                               __uint_as_float(r1.z));
-                if (ch == 1) {
-                    dk += speed2_rn((float)ve[0], (float)ve[1], (float)ve[2]);
-                    atomicAdd(&s_dn[sg - sg0], 1u);
-                }
-                atomicAdd(&s_dk[sg - sg0], dk);
-                if (ch == 1 && S.other >= 0) {
-                    const double ki = speed2_rn((float)vi[0], (float)vi[1], (float)vi[2]);
-                    const int jo = S.other - sg0;
-                    if (jo >= 0 && jo <= kCandTiles) {
-                        atomicAdd(&s_dk[jo], ki);
-                        atomicAdd(&s_dn[jo], 1u);
-                    } else {
-                        double *ts = step_sums(d, half, st, S.other);
-                        unsafeAtomicAdd(ts + T_V2, ki);
-                        unsafeAtomicAdd(ts + T_N, 1.0);
-                    }
-                }
+            if (j >= 0) {
+                const SegC &S = s_seg[j];
+                const EnsC &e = s_ens[j];
+                oth = S.other;
+                ch = p_collide<false, CXREL>(e, S, S.species, s_nu[j][0], s_nu[j][1], tag, p, ve, vi);
+            } else {
+                const SegC S = d.seg[sg];
+                const EnsC e = d.ens[S.ens];
+                oth = S.other;
+                ch = p_collide<false, CXREL>(e, S, S.species, d.numax[sg], d.pnull[sg], tag, p, ve, vi);
             }
+        }
+        if (ch >= 0) {
+            d.fvx[b][i] = p.vx;
+            d.fvy[b][i] = p.vy;
+            d.fvz[b][i] = p.vz;
+            // the particle's |v|^2 after the collision replaces the one the pass tallied
+            // (taken off exactly as the pass computed it); an ionisation adds the new
+            // electron here and the new ion below (as stored, in binary32)
+            double dk = speed2_rn(p.vx, p.vy, p.vz) -
+                        (double)speed2_f32(__uint_as_float(r1.x), __uint_as_float(r1.y), __uint_as_float(r1.z));
+            if (ch == 1) dk += speed2_rn((float)ve[0], (float)ve[1], (float)ve[2]);
+            if (j >= 0) {
+                atomicAdd(&s_n[j][ch], 1u);
+                atomicAdd(&s_dk[j], dk);
+                if (ch == 1) atomicAdd(&s_dn[j], 1u);
+            } else {
+                unsigned long long *c = d.cnt + ((int64_t)st * d.nseg + sg) * C_NCNT;
+                atomicAdd(c + (ch == 0 ? C_EL : ch == 1 ? C_IZ : C_CX), 1ull);
+                double *ts = step_sums(d, half, st, sg);
+                unsafeAtomicAdd(ts + T_V2, dk);
+                if (ch == 1) unsafeAtomicAdd(ts + T_N, 1.0);
+            }
+        }
+        if (act) {
             double v2m = speed2_rn(p.vx, p.vy, p.vz);
             if (ch == 1) {
                 v2m = fmax(v2m, speed2_rn(ve[0], ve[1], ve[2]));
-                if (S.other >= 0) {
-                    const unsigned long long vb = dbits(speed2_rn(vi[0], vi[1], vi[2]));
-                    const int jo = S.other - sg0;
-                    if (jo >= 0 && jo <= kCandTiles)
-                        atomicMax(&s_v[jo], vb);
-                    else
-                        atomicMax(d.vmax2 + ((int64_t)half * kCntStripes + st) * d.nseg + S.other, vb);
+                if (oth >= 0) {
+                    // the new ion: its speed bound and diagnostics go to the ion segment
+                    // directly (one of a few per block)
+                    const double ki = speed2_rn((float)vi[0], (float)vi[1], (float)vi[2]);
+                    double *ts = step_sums(d, half, st, oth);
+                    unsafeAtomicAdd(ts + T_V2, ki);
+                    unsafeAtomicAdd(ts + T_N, 1.0);
+                    atomicMax(d.vmax2 + ((int64_t)half * kCntStripes + st) * d.nseg + oth,
+                              dbits(speed2_rn(vi[0], vi[1], vi[2])));
                 }
-                global_deposit32(d, S, S.species, p.cell, p.off, hist != 0);
-                if (S.other >= 0) global_deposit32(d, d.seg[S.other], 1, p.cell, p.off, hist != 0);
             }
-            if (v2m > 0.0) atomicMax(&s_v[sg - sg0], dbits(v2m));
+            if (j >= 0) {
+                if (v2m > 0.0) atomicMax(&s_v[j], dbits(v2m));
+            } else if (v2m > 0.0) {
+                atomicMax(d.vmax2 + ((int64_t)half * kCntStripes + st) * d.nseg + sg, dbits(v2m));
+            }
         }
         // births of this round: one list reservation for the whole block
         if (threadIdx.x == 0) s_nb = 0u;
@@ -749,44 +829,54 @@ __global__ void __launch_bounds__(256) k_cand32(Dev d, int tile, int64_t T, int 
         if (ch == 1) lb = atomicAdd(&s_nb, 1u);
         __syncthreads();
         if (threadIdx.x == 0 && s_nb) s_bbase = atomicAdd(bb.nbirth + bst, s_nb);
+        // the deposit of the new pair (the fused step's; the separate stages deposit all
+        // particles afresh), while the reservation is in flight
+        if (ch == 1) {
+            const SegC Se = j >= 0 ? s_seg[j] : d.seg[sg];
+            global_deposit32(d, Se, Se.species, p.cell, p.off, hist != 0);
+            if (oth >= 0) {
+                const SegC So = d.seg[oth];
+                global_deposit32(d, So, 1, p.cell, p.off, hist != 0);
+            }
+        }
         __syncthreads();
         if (ch == 1) {
             const uint32_t slot = s_bbase + lb;
             if ((int64_t)slot < d.birth_stripe_cap) {
-                const SegC &S = d.seg[sg];
+                const int ens = j >= 0 ? s_seg[j].ens : d.seg[sg].ens;
+                const double dx = j >= 0 ? s_seg[j].dx : d.seg[sg].dx;
                 Birth &B = bb.births[(int64_t)bst * d.birth_stripe_cap + slot];
                 B.pid = p.id;
-                B.ens = S.ens;
+                B.ens = ens;
                 B.cell = p.cell;
                 B.off = p.off;
-                B.x = ((double)p.cell + (double)p.off) * S.dx;
+                B.x = ((double)p.cell + (double)p.off) * dx;
                 for (int c = 0; c < 3; ++c) {
                     B.ve[c] = ve[c];
                     B.vi[c] = vi[c];
                 }
-                birth_mark(bb, d.ens[S.ens], p.id);
+                if (j >= 0)
+                    birth_mark(bb, s_ens[j], p.id);
+                else
+                    birth_mark(bb, d.ens[ens], p.id);
             } else {
                 atomicOr(d.err, (int)E_CAP_BIRTH);
             }
         }
         __syncthreads();  // s_nb and s_bbase are reused by the next round
     }
-    // one set of counter atomics per block and segment
-    if (threadIdx.x <= kCandTiles) {
-        const int j = threadIdx.x, sgj = sg0 + j;
-        if (sgj < d.nseg) {
-            if (j < kCandTiles) {
-                unsigned long long *c = d.cnt + ((int64_t)st * d.nseg + sgj) * C_NCNT;
-                if (s_n[j][0]) atomicAdd(c + C_EL, (unsigned long long)s_n[j][0]);
-                if (s_n[j][1]) atomicAdd(c + C_IZ, (unsigned long long)s_n[j][1]);
-                if (s_n[j][2]) atomicAdd(c + C_CX, (unsigned long long)s_n[j][2]);
-            }
-            if (s_v[j]) atomicMax(d.vmax2 + ((int64_t)half * kCntStripes + st) * d.nseg + sgj, s_v[j]);
-            if (s_dk[j] != 0.0 || s_dn[j]) {
-                double *ts = step_sums(d, half, st, sgj);
-                if (s_dk[j] != 0.0) unsafeAtomicAdd(ts + T_V2, s_dk[j]);
-                if (s_dn[j]) unsafeAtomicAdd(ts + T_N, (double)s_dn[j]);
-            }
+    // one set of counter atomics per block and staged segment
+    if ((int)threadIdx.x < s_ns) {
+        const int j = threadIdx.x, sgj = s_sg[j];
+        unsigned long long *c = d.cnt + ((int64_t)st * d.nseg + sgj) * C_NCNT;
+        if (s_n[j][0]) atomicAdd(c + C_EL, (unsigned long long)s_n[j][0]);
+        if (s_n[j][1]) atomicAdd(c + C_IZ, (unsigned long long)s_n[j][1]);
+        if (s_n[j][2]) atomicAdd(c + C_CX, (unsigned long long)s_n[j][2]);
+        if (s_v[j]) atomicMax(d.vmax2 + ((int64_t)half * kCntStripes + st) * d.nseg + sgj, s_v[j]);
+        if (s_dk[j] != 0.0 || s_dn[j]) {
+            double *ts = step_sums(d, half, st, sgj);
+            if (s_dk[j] != 0.0) unsafeAtomicAdd(ts + T_V2, s_dk[j]);
+            if (s_dn[j]) unsafeAtomicAdd(ts + T_N, (double)s_dn[j]);
         }
     }
 }
@@ -917,19 +1007,18 @@ __global__ void k_sort_finish(Dev d)
 hipError_t launch_pass32_stages(const Dev &d, int ppt, int W, hipStream_t s, int stages, int hist,
                                 int64_t cap_tot, bool nt);
 
-// A pass that also counts cells (or sorts) needs 4 more bytes of LDS per window cell; its
-// window span is capped so that its LDS stays within what the plain pass's occupancy allows
-// (12 B per cell x 1024 cells + the static 8 KB, seven blocks per CU).  Cells outside the
-// window go to HBM atomics, so the cap changes no result.
+// The sorting pass ranks its tile in 4 more bytes of LDS per window cell; its window span
+// is capped so that its LDS stays within what the plain pass's occupancy allows (12 B per
+// cell x 1024 cells + the static LDS, seven blocks per CU).  Cells outside the window go
+// to HBM atomics, so the cap changes no result.  (Counting cells costs no LDS of its own:
+// the window's words carry the counts.)
 constexpr int kCountWindowMax = 1024;
 
 template <int STAGES, bool NT = false, bool SORT = false>
 static hipError_t launch_pass32_t(const Dev &d, int ppt, int W, hipStream_t s, int hist, int64_t cap_tot)
 {
-    // the sorting pass counts its runs where the histogram would go
-    const bool with_hist = (STAGES & PS_HIST) || hist || SORT;
-    if (with_hist) W = std::min(W, kCountWindowMax);
-    const size_t lds = (size_t)(W + 1) * 8 + (with_hist ? (size_t)W * 4 : 0);
+    if (SORT) W = std::min(W, kCountWindowMax);
+    const size_t lds = (size_t)W * 8 + (SORT ? (size_t)W * 4 : 0);
     if (ppt == 4) {
         const int64_t T = cap_tot / (256 * 4);
         const int64_t G = (T + 7) / 8 * 8;
