@@ -52,7 +52,7 @@
  *   R15 deposit shares (2^24 - f_q, f_q), f_q = rint(f 2^24), summed in int64.
  *   R16 sort every K = 20 steps (10 for the 1e9-particle workload); K = 0 still compacts
  *       every 20 steps.
- *   R17 Philox4x32-10, key (seed, species), counter (id, tag, block, 0);
+ *   R17 Philox4x32-7 (seven rounds), key (seed, species), counter (id, tag, block, 0);
  *       u = ((r >> 9) + 1/2) 2^-23; normals by Box-Muller.
  *   R18 batched ensembles: sizes, ppc and temperatures come from the input generator;
  *       ensemble seed = index + 1.

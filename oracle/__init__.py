@@ -121,7 +121,7 @@ def lib(omp=False):
         L.orc_moments.restype = None
         L.orc_set_step.argtypes = [P, C.c_int64]
         L.orc_init_particle.argtypes = [C.POINTER(_Config), C.c_int, C.c_int64, P, P, P, P]
-        L.orc_philox4x32_10.argtypes = [P, P, P]
+        L.orc_philox4x32.argtypes = [P, P, P]
         L.orc_philox_batch.argtypes = [C.c_int64, P, P, P]
         L.orc_uniform.argtypes = [C.c_uint32]
         L.orc_uniform.restype = C.c_double
@@ -303,16 +303,16 @@ def init_particles(e, s, ps):
 
 
 def philox(ctr, key):
-    """Philox4x32-10 of counter (4 words) and key (2 words) -> 4 words."""
+    """Philox4x32 (seven rounds, reading R17) of counter (4 words) and key (2 words) -> 4 words."""
     c = np.ascontiguousarray(ctr, dtype=np.uint32)
     k = np.ascontiguousarray(key, dtype=np.uint32)
     out = np.zeros(4, dtype=np.uint32)
-    lib().orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    lib().orc_philox4x32(_ptr(c), _ptr(k), _ptr(out))
     return out
 
 
 def philox_batch(ctr, key):
-    """Row-wise Philox4x32-10: ctr (n, 4), key (n, 2) -> (n, 4)."""
+    """Row-wise Philox4x32 (seven rounds): ctr (n, 4), key (n, 2) -> (n, 4)."""
     c = np.ascontiguousarray(ctr, dtype=np.uint32)
     k = np.ascontiguousarray(key, dtype=np.uint32)
     out = np.zeros((len(c), 4), dtype=np.uint32)

@@ -55,15 +55,17 @@ struct orc_state {
 };
 
 /* ------------------------------------------------------------------------------------ */
-/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2,
- * 3", SC'11): ten rounds of two 32x32->64 multiplies on counter words 0 and 2 with the
- * published multipliers, the high halves xored with the other counter words and the
- * round key, and the key bumped by the published Weyl constants between rounds.      */
-void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+/* Philox4x32 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3",
+ * SC'11) with ORC_PHILOX_ROUNDS rounds (reading R17: seven, the smallest round count the
+ * paper finds Crush-resistant for this generator): each round takes two 32x32->64
+ * multiplies on counter words 0 and 2 with the published multipliers, xors the high halves
+ * with the other counter words and the round key, and the key is bumped by the published
+ * Weyl constants between rounds.                                                         */
+void orc_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
 {
     uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
     uint32_t k0 = key[0], k1 = key[1];
-    for (int r = 0; r < 10; r++) {
+    for (int r = 0; r < ORC_PHILOX_ROUNDS; r++) {
         if (r > 0) {
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
@@ -87,7 +89,7 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 
 void orc_philox_batch(int64_t n, const uint32_t *ctr, const uint32_t *key, uint32_t *out)
 {
-    for (int64_t i = 0; i < n; i++) orc_philox4x32_10(ctr + 4 * i, key + 2 * i, out + 4 * i);
+    for (int64_t i = 0; i < n; i++) orc_philox4x32(ctr + 4 * i, key + 2 * i, out + 4 * i);
 }
 
 /* Reading R17: u = ((r >> 9) + 1/2) * 2^-23, an odd multiple of 2^-24 in (0, 1); exactly
@@ -107,7 +109,7 @@ static void draw_block(const orc_state *st, int s, uint32_t id, uint32_t tag, ui
 {
     uint32_t ctr[4] = {id, tag, blk, 0u};
     uint32_t key[2] = {st->cfg.seed, (uint32_t)s};
-    orc_philox4x32_10(ctr, key, w);
+    orc_philox4x32(ctr, key, w);
 }
 
 /* Three standard normals from one Philox block: (w0, w1) -> z0, z1 and (w2, w3) -> z2. */
@@ -276,7 +278,7 @@ void orc_init_particle(const orc_config *c, int s, int64_t p, double *xo, double
     if (c->init_mode == 0) {
         int64_t cell = p / ppc;
         uint32_t ctr[4] = {(uint32_t)p, ORC_INIT_TAG, 0u, 0u};
-        orc_philox4x32_10(ctr, key, w);
+        orc_philox4x32(ctr, key, w);
         x = ((double)cell + orc_uniform(w[0])) * c->dx;
     } else {
         double k = ORC_TWO_PI * (double)c->perturb_mode / L;
@@ -286,7 +288,7 @@ void orc_init_particle(const orc_config *c, int s, int64_t p, double *xo, double
         while (x >= L) x -= L;
     }
     uint32_t ctr1[4] = {(uint32_t)p, ORC_INIT_TAG, 1u, 0u};
-    orc_philox4x32_10(ctr1, key, w);
+    orc_philox4x32(ctr1, key, w);
     three_normals(w, z);
     *xo = x;
     *vx = vth * z[0];

@@ -44,7 +44,7 @@
  *   R15 deposit shares (2^24 - f_q, f_q), f_q = rint(f 2^24), summed in int64.
  *   R16 sort every K = 20 steps (10 for the 1e9-particle workload); K = 0 still compacts
  *       every 20 steps.
- *   R17 Philox4x32-10, key (seed, species), counter (id, tag, block, 0);
+ *   R17 Philox4x32-7 (seven rounds), key (seed, species), counter (id, tag, block, 0);
  *       u = ((r >> 9) + 1/2) 2^-23; normals by Box-Muller.
  *   R18 batched ensembles: sizes, ppc and temperatures come from the input generator;
  *       ensemble seed = index + 1.
@@ -185,8 +185,10 @@ int64_t orc_last_channels(const orc_state *st, int s, int32_t *chan, uint32_t *i
 void orc_last_numax(const orc_state *st, double *numax, double *pnull);
 void orc_set_step(orc_state *st, int64_t step);
 
-/* Philox4x32-10 block and the derived variates, exposed for pinning. */
-void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* Philox4x32 block (ORC_PHILOX_ROUNDS rounds) and the derived variates, exposed for
+ * pinning. */
+#define ORC_PHILOX_ROUNDS 7
+void orc_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 /* n independent blocks: ctr[4n], key[2n] -> out[4n]. */
 void orc_philox_batch(int64_t n, const uint32_t *ctr, const uint32_t *key, uint32_t *out);
 double orc_uniform(uint32_t r);

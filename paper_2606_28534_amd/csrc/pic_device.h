@@ -175,14 +175,17 @@ struct Dev {
 };
 
 // ---------------------------------------------------------------------------------------
-// Philox4x32-10 (Salmon et al., SC'11): ten rounds; each multiplies counter words 0 and 2
-// by the published constants, xors the high halves with the other counter words and the
-// round key, and bumps the key by the published Weyl increments between rounds.
+// Philox4x32 (Salmon et al., SC'11) with kPhiloxRounds = 7 rounds (reading R17: the
+// paper's smallest Crush-resistant count for this generator): each round multiplies counter
+// words 0 and 2 by the published constants, xors the high halves with the other counter
+// words and the round key, and bumps the key by the published Weyl increments between
+// rounds.
+constexpr int kPhiloxRounds = 7;
 __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                         uint32_t k0, uint32_t k1)
 {
 #pragma unroll
-    for (int r = 0; r < 10; ++r) {
+    for (int r = 0; r < kPhiloxRounds; ++r) {
         if (r) {
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;

@@ -664,6 +664,18 @@ __device__ void compute_params(const Dev &d, bool coherent)
 
 __global__ void k_params(Dev d) { compute_params(d, false); }
 
+// Inclusive prefix sum over the 64 lanes of a wave (FP64).
+__device__ __forceinline__ double wave_incl_scan_f64(double v)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const double n = __shfl_up(v, o);
+        if (lane >= o) v += n;
+    }
+    return v;
+}
+
 template <bool F64>
 __device__ void solve2_body(const Dev &d, int zero_q)
 {
@@ -676,20 +688,32 @@ __device__ void solve2_body(const Dev &d, int zero_q)
     const int64_t N = e.ncells, nn = e.nnodes;
     const int64_t a = (k - e.chunk0) * kChunk;
     const double dx = e.dx, ce = e.dx / e.eps0;
-    // Scan of the ensemble's chunk aggregates, in parallel: thread t owns the contiguous
-    // chunk range [t R, (t+1) R).  C_pre(c) = sum_{c'<c} A'(c') and
+    const int64_t j0 = a + (int64_t)threadIdx.x * kNodesPerThread;
+    // this thread's densities (written by the first pass), loaded before the chunk scan so
+    // the two round trips overlap
+    double rv[kNodesPerThread];
+#pragma unroll
+    for (int q = 0; q < kNodesPerThread; ++q) {
+        const bool in = j0 + q < nn;
+        const double v = d.rho[e.gbase + (in ? j0 + q : 0)];
+        rv[q] = in ? v : 0.0;
+    }
+    // Scan of the ensemble's chunk aggregates by the first wave, in parallel: lane l owns
+    // the contiguous chunk range [l R, (l+1) R).  C_pre(c) = sum_{c'<c} A'(c') and
     // F_pre(c) = sum_{c'<c} (cnt(c') C_pre(c') + B'(c')) are two nested exclusive scans.
-    {
+    // (Wave shuffles only: no block barrier inside the scan.)
+    if (threadIdx.x < kWave) {
+        const int lane = (int)threadIdx.x;
         const int64_t nc = e.nchunks;
-        const int64_t R = (nc + blockDim.x - 1) / blockDim.x;
-        const int64_t c0 = (int64_t)threadIdx.x * R, c1 = min(c0 + R, nc);
+        const int64_t R = (nc + kWave - 1) / kWave;
+        const int64_t c0 = (int64_t)lane * R, c1 = min(c0 + R, nc);
         // floating walls (R22): the particles absorbed so far at the left wall, per
         // species, from the exact striped wall counts (sums < 2^53: exact in binary64)
         // (species loops run over the two array entries with constant indices, so that the
         // local copy of the ensemble stays in registers)
         double nabs[2] = {0.0, 0.0};
         if (e.floating)
-            for (int st = threadIdx.x; st < kCntStripes; st += blockDim.x) {
+            for (int st = lane; st < kCntStripes; st += kWave) {
 #pragma unroll
                 for (int s = 0; s < 2; ++s)
                     if (s < e.nspecies)
@@ -697,7 +721,7 @@ __device__ void solve2_body(const Dev &d, int zero_q)
             }
         double tq = 0.0;
         for (int64_t c = c0; c < c1; ++c) tq += d.agg[(e.chunk0 + c) * A_NAGG + A_TOTQ];
-        const double tqs = block_sum(tq, s_buf);
+        const double tqs = wave_sum_f64(tq);
         const double bg = e.periodic ? -tqs / e.L : 0.0;
         double a = 0.0, g = 0.0, n = 0.0;  // local A sum, local sum of cnt*Cpre_local + B, cnt sum
         for (int64_t c = c0; c < c1; ++c) {
@@ -708,13 +732,11 @@ __device__ void solve2_body(const Dev &d, int zero_q)
             n += gg[A_CNT];
             a += A;
         }
-        const double apre = block_incl_scan(a, s_buf) - a;  // C_pre at c0
-        const double fin = n * apre + g;                    // this range's sum of C over m
-        const double fpre = block_incl_scan(fin, s_buf) - fin;
-        __shared__ double s_red2[4 * 16];
-        double st[4] = {fin, a, nabs[0], nabs[1]};
-        block_sums<4>(st, s_red2);
-        const double Stot = st[0], Ctot = st[1];
+        const double apre = wave_incl_scan_f64(a) - a;  // C_pre at c0
+        const double fin = n * apre + g;                // this range's sum of C over m
+        const double fpre = wave_incl_scan_f64(fin) - fin;
+        const double Stot = wave_sum_f64(fin), Ctot = wave_sum_f64(a);
+        const double nab0 = wave_sum_f64(nabs[0]), nab1 = wave_sum_f64(nabs[1]);
         const int64_t me = k - e.chunk0;
         if (me >= c0 && me < c1) {
             double ca = apre, fa = fpre;
@@ -731,11 +753,8 @@ __device__ void solve2_body(const Dev &d, int zero_q)
         // Reading R22: floating walls fix E_{1/2} by Gauss's law over the left wall (the
         // charge absorbed there, q w per particle) and the half cell in front of it;
         // otherwise phi_N = 0 (or periodicity) fixes it.
-        double sigL = 0.0;
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
-            if (s < e.nspecies) sigL += e.qw[s] * st[2 + s];
-        if (threadIdx.x == 0) {
+        const double sigL = e.qw[0] * nab0 + (e.nspecies > 1 ? e.qw[1] * nab1 : 0.0);
+        if (lane == 0) {
             s_bg = bg;
             s_Ctot = Ctot;
             if (e.floating)
@@ -746,17 +765,9 @@ __device__ void solve2_body(const Dev &d, int zero_q)
     }
     __syncthreads();
     const double bg = s_bg, Eh = s_Eh;
-    const int64_t j0 = a + (int64_t)threadIdx.x * kNodesPerThread;
     // local inclusive prefix of interior rho' (with background) -> C_j
     double rl[kNodesPerThread + 1];
     double loc = 0.0;
-    double rv[kNodesPerThread];  // all loads before the first store
-#pragma unroll
-    for (int q = 0; q < kNodesPerThread; ++q) {
-        const bool in = j0 + q < nn;
-        const double v = d.rho[e.gbase + (in ? j0 + q : 0)];
-        rv[q] = in ? v : 0.0;
-    }
 #pragma unroll
     for (int q = 0; q < kNodesPerThread; ++q) {
         const int64_t j = j0 + q;

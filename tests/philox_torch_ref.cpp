@@ -1,8 +1,9 @@
-// Independent Philox4x32-10 reference for the oracle's pin: PyTorch's own header-only
+// Independent Philox4x32 reference for the oracle's pin: PyTorch's own header-only
 // engine (ATen/core/PhiloxRNGEngine.h, BSD licence), driven through its public API.
 // The engine's seed is the 64-bit key (word 0 low, word 1 high), its subsequence the
 // counter words 2-3 and its offset the counter words 0-1; four calls return the block.
-// Usage: philox_torch_ref N SEED OUTFILE  -> N records of 10 uint32 (ctr[4] key[2] out[4]).
+// The engine's call operator takes the round count (10 by default).
+// Usage: philox_torch_ref N SEED OUTFILE ROUNDS -> N records of 10 uint32 (ctr[4] key[2] out[4]).
 #include <ATen/core/PhiloxRNGEngine.h>
 #include <cstdint>
 #include <cstdio>
@@ -16,7 +17,8 @@ static uint64_t splitmix64(uint64_t &s) {
 }
 
 int main(int argc, char **argv) {
-  if (argc != 4) return 2;
+  if (argc != 5) return 2;
+  const int rounds = std::atoi(argv[4]);
   long n = std::atol(argv[1]);
   uint64_t s = std::strtoull(argv[2], nullptr, 10);
   FILE *f = std::fopen(argv[3], "wb");
@@ -33,7 +35,7 @@ int main(int argc, char **argv) {
     uint64_t subseq = (uint64_t)rec[2] | ((uint64_t)rec[3] << 32);
     uint64_t offset = (uint64_t)rec[0] | ((uint64_t)rec[1] << 32);
     at::philox_engine eng(seed, subseq, offset);
-    for (int k = 0; k < 4; k++) rec[6 + k] = eng();
+    for (int k = 0; k < 4; k++) rec[6 + k] = eng(rounds);
     std::fwrite(rec, sizeof(uint32_t), 10, f);
   }
   std::fclose(f);

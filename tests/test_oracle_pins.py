@@ -33,7 +33,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 # ---------------------------------------------------------------------------------------
-# Philox4x32-10 and the derived variates
+# Philox4x32 (seven rounds, reading R17) and the derived variates
 # ---------------------------------------------------------------------------------------
 @pytest.mark.skipif(TORCH_INC is None, reason="torch headers not found")
 def test_philox_matches_pytorch_header(tmp_path):
@@ -42,10 +42,15 @@ def test_philox_matches_pytorch_header(tmp_path):
                     os.path.join(HERE, "philox_torch_ref.cpp")], check=True)
     out = tmp_path / "ref.bin"
     n = 1_000_000
-    subprocess.run([str(exe), str(n), "20261202", str(out)], check=True)
+    subprocess.run([str(exe), str(n), "20261202", str(out), "7"], check=True)
     rec = np.fromfile(out, dtype=np.uint32).reshape(-1, 10)
     got = oracle.philox_batch(rec[:, :4], rec[:, 4:6])
     assert np.array_equal(got, rec[:, 6:10])
+    # and the reference at its default ten rounds differs: the pin sees the round count
+    out10 = tmp_path / "ref10.bin"
+    subprocess.run([str(exe), "1000", "20261202", str(out10), "10"], check=True)
+    rec10 = np.fromfile(out10, dtype=np.uint32).reshape(-1, 10)
+    assert not np.array_equal(oracle.philox_batch(rec10[:, :4], rec10[:, 4:6]), rec10[:, 6:10])
 
 
 def test_uniform_is_exact_open_interval():
@@ -738,7 +743,7 @@ def test_null_collision_counts_match_probabilities():
             p = pn[s] * r / nu[s]
             mu, sd = p.sum(), math.sqrt((p * (1 - p)).sum())
             got = np.count_nonzero(chan == k)
-            assert abs(got - mu) <= 4 * sd + 1, (s, k, got, mu, sd)
+            assert abs(got - mu) <= 3 * sd, (s, k, got, mu, sd)
             # for small nu dt the count is close to sum nu_k dt
             assert abs(mu - (r * e["dt"]).sum()) <= 0.5 * mu
 
