@@ -385,6 +385,14 @@ int pic_load(pic_ctx *ctx, const void *host_buf, size_t bytes, void *stream);
 int pic_timing(pic_ctx *ctx, int32_t enable);
 int pic_timing_read(pic_ctx *ctx, double *ms_total, int64_t *launches, void *stream);
 
+/* Measurement hook: copy `bytes` (a multiple of 16) of device memory from `src` to `dst`
+ * (not overlapping) with the particle pass's access pattern: 256 threads a block, four
+ * consecutive 32-bit words a thread, one 16-byte load and one 16-byte store, non-temporal
+ * when `nontemporal` is non-zero.  Its bandwidth and its traffic counters are the
+ * reference the pass is read against (the counters' scale, the achievable stream rate).
+ * Asynchronous on `stream`; PIC_EINVAL for a null pointer or a size not a multiple of 16. */
+int pic_stream_copy(const void *src, void *dst, size_t bytes, int32_t nontemporal, void *stream);
+
 void pic_free(pic_ctx *ctx);
 const char *pic_last_error(const pic_ctx *ctx);
 

@@ -25,7 +25,7 @@ EXPORTS = ("pic_query_workspace", "pic_init", "pic_deposit", "pic_solve", "pic_p
            "pic_set_fields", "pic_set_step",
            "pic_nnodes", "pic_set_external_field", "pic_adjoint_query",
            "pic_adjoint_window", "pic_adjoint_window_noalloc", "pic_autotune", "pic_checkpoint_size", "pic_save", "pic_load",
-           "pic_timing", "pic_timing_read", "pic_graph_prepare", "pic_graph_launches",
+           "pic_timing", "pic_timing_read", "pic_stream_copy", "pic_graph_prepare", "pic_graph_launches",
            "pic_free", "pic_last_error")
 
 
@@ -132,12 +132,28 @@ def load_library():
     L.pic_graph_prepare.argtypes = [P, C.c_int32]
     L.pic_graph_launches.argtypes = [P, C.POINTER(C.c_int64)]
     L.pic_timing_read.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64), P]
+    L.pic_stream_copy.argtypes = [P, P, C.c_size_t, C.c_int32, P]
     L.pic_free.argtypes = [P]
     L.pic_free.restype = None
     L.pic_last_error.argtypes = [P]
     L.pic_last_error.restype = C.c_char_p
     _lib = L
     return L
+
+
+def stream_copy(src, dst, nontemporal=True, stream=None):
+    """Copy device tensor `src` into `dst` (same byte size, a multiple of 16) with the
+    particle pass's access pattern (the library's measurement hook)."""
+    import torch
+
+    L = load_library()
+    nb = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nb
+    st = stream if stream is not None else torch.cuda.current_stream()
+    rc = L.pic_stream_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nb,
+                           1 if nontemporal else 0, C.c_void_p(st.cuda_stream))
+    if rc != PIC_OK:
+        raise PicError(rc, "pic_stream_copy")
 
 
 def make_config(work, fused=True, precision=None, block=0, grid=0, window=0, ppt=0, sort_ppt=0,

@@ -1883,6 +1883,13 @@ int pic_timing_read(pic_ctx *c, double *ms_total, int64_t *launches, void *strea
     return PIC_OK;
 }
 
+int pic_stream_copy(const void *src, void *dst, size_t bytes, int32_t nontemporal, void *stream)
+{
+    if (!src || !dst || bytes % 16 != 0 || bytes / 16 > ((size_t)1 << 31) * 64) return PIC_EINVAL;
+    const hipError_t e = launch_stream_copy(src, dst, (int64_t)(bytes / 4), nontemporal != 0, (hipStream_t)stream);
+    return e == hipSuccess ? PIC_OK : PIC_EHIP;
+}
+
 void pic_free(pic_ctx *c)
 {
     if (!c) return;

@@ -1047,6 +1047,33 @@ hipError_t launch_pass32_sort(const Dev &d, int ppt, int W, hipStream_t s, bool 
     return hipGetLastError();
 }
 
+// A plain copy with the pass's access pattern (256 threads a block, four consecutive 32-bit
+// words a thread, one 16-byte load and store each, optionally non-temporal): the measured
+// bandwidth and traffic counters of the pass's own kind of stream, for reference.
+template <bool NT>
+__global__ void __launch_bounds__(256) k_stream_copy(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst,
+                                                     int64_t nwords)
+{
+    const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+    if (i0 + 4 > nwords) return;  // nwords is a multiple of 4
+    uint32_t v[4];
+    vload<4, NT>(src + i0, v);
+    vstore<4, NT>(dst + i0, v);
+}
+
+hipError_t launch_stream_copy(const void *src, void *dst, int64_t nwords, bool nt, hipStream_t s)
+{
+    const int64_t G = (nwords / 4 + 255) / 256;
+    if (G == 0) return hipSuccess;
+    if (nt)
+        hipLaunchKernelGGL(k_stream_copy<true>, dim3((unsigned)G), dim3(256), 0, s, (const uint32_t *)src,
+                           (uint32_t *)dst, nwords);
+    else
+        hipLaunchKernelGGL(k_stream_copy<false>, dim3((unsigned)G), dim3(256), 0, s, (const uint32_t *)src,
+                           (uint32_t *)dst, nwords);
+    return hipGetLastError();
+}
+
 hipError_t launch_cand32(const Dev &d, int ppt, hipStream_t s, int hist, int64_t cap_tot)
 {
     const int tile = 256 * ppt;
