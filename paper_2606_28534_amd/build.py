@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpic.so")
-SOURCES = ["pic_kernels.hip", "pic_pass32.hip", "pic_neutral.hip", "pic_adjoint.hip", "pic_moments.hip",
+SOURCES = ["pic_kernels.hip", "pic_pass32.hip", "pic_after.hip", "pic_adjoint.hip", "pic_moments.hip",
            "pic_api.cpp"]
 ARCH = os.environ.get("PIC_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -322,6 +322,7 @@ size_t carve(const Plan &P, char *base, Dev &d)
     d.nrec = c.take<uint32_t>(1);
     d.src_tot = P.src_tot;
     d.ticket = c.take<uint32_t>(8);
+    d.tq = c.take<uint32_t>(16);
     d.err = c.take<int32_t>(1);
     c.take<double>(2 * kDiagGrid);  // diag scratch (last region)
     return c.off;
@@ -417,6 +418,19 @@ int check_err(pic_ctx *c, hipStream_t s)
     return PIC_OK;
 }
 
+// The fused step's work after its particle pass: collision candidates (with collisions),
+// recycled neutrals and the volumetric source; one launch in the FP32 form.
+hipError_t launch_after_pass(pic_ctx *c, hipStream_t s, int hist)
+{
+    const Dev &d = c->d;
+    const bool coll = c->cfg.collisions != 0;
+    if (!c->P.f64) return launch_after(d, c->L.ppt, s, hist, d.cap_tot, coll);
+    hipError_t e;
+    if (coll && (e = launch_candidates(d, c->L, s, true, hist)) != hipSuccess) return e;
+    if ((e = launch_neutrals(d, s)) != hipSuccess) return e;
+    return launch_source(d, hist, s);
+}
+
 // Enqueue one full step from step count n; the step sorts when n + 1 is a multiple of K
 // (never with `no_sort`).  The fused FP32 step pipelines the sort (K >= 2): the step before
 // a sort step counts the cells after its push and scans the counts, and the sort step's
@@ -452,9 +466,7 @@ hipError_t enqueue_step(pic_ctx *c, hipStream_t s, int64_t n, bool &ready, bool 
             if ((e = hipEventRecord(c->ev[c->ev_used + 1], s)) != hipSuccess) return e;
             c->ev_used += 2;
         }
-        if (coll && (e = launch_candidates(d, c->L, s, f64, hist)) != hipSuccess) return e;
-        if ((e = launch_neutrals(d, s)) != hipSuccess) return e;
-        if ((e = launch_source(d, hist, s)) != hipSuccess) return e;
+        if ((e = launch_after_pass(c, s, hist)) != hipSuccess) return e;
         if (coll) {
             if ((e = launch_births(d, f64, true, true, s)) != hipSuccess) return e;
         } else if ((e = launch_advance(d, s)) != hipSuccess) {
@@ -533,9 +545,7 @@ hipError_t enqueue_window(pic_ctx *c, hipStream_t s, int64_t n0, int len, bool &
         else
             e = launch_particles(d, c->L, s, f64, stages, hist, false);
         if (e != hipSuccess) return e;
-        if ((e = launch_candidates(d, c->L, s, f64, hist)) != hipSuccess) return e;
-        if ((e = launch_neutrals(d, s)) != hipSuccess) return e;
-        if ((e = launch_source(d, hist, s)) != hipSuccess) return e;
+        if ((e = launch_after_pass(c, s, hist)) != hipSuccess) return e;
         if (sort_now && !sorting) {
             if ((e = launch_births(d, f64, true, true, s)) != hipSuccess) return e;
             if ((e = launch_sort(d, f64, c->L, s)) != hipSuccess) return e;

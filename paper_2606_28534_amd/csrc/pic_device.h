@@ -171,6 +171,7 @@ struct Dev {
     // scan scratch, tickets, errors
     uint32_t *scanpart;       // [<= 1 << 16]
     uint32_t *ticket;         // [8]
+    uint32_t *tq;             // [16]: the FP64 pass's eight tile queues and its exit ticket
     int32_t *err;             // [1]
 };
 

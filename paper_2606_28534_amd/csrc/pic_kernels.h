@@ -53,6 +53,8 @@ hipError_t launch_pass32_sort(const Dev &d, int ppt, int W, hipStream_t s, bool 
 hipError_t launch_pass32(const Dev &d, int ppt, int W, hipStream_t s, int stages, int hist, int64_t cap_tot,
                          bool nt);
 hipError_t launch_cand32(const Dev &d, int ppt, hipStream_t s, int hist, int64_t cap_tot);
+// the fused step's candidates, neutrals and source as one launch (FP32 form)
+hipError_t launch_after(const Dev &d, int ppt, hipStream_t s, int hist, int64_t cap_tot, bool coll);
 hipError_t launch_stream_copy(const void *src, void *dst, int64_t nwords, bool nt, hipStream_t s);
 hipError_t launch_sort32_scatter(const Dev &d, int ppt, int W, hipStream_t s, int64_t cap_tot, bool nt);
 hipError_t launch_adj_seed(const double *E, double *lE, int N, double eps0, double dx, hipStream_t s);

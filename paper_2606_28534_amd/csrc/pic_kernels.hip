@@ -6,8 +6,9 @@
 // pass covers every particle stage with one template: gather + Boris push + walls,
 // null-collision MC, cloud-in-cell deposit and the sort histogram are compile-time stage
 // bits, so its separate-stage verbs and its fused step run the same per-particle code.  It
-// streams each segment's slots once, coalesced, with persistent blocks that own contiguous,
-// XCD-local runs of tiles, and deposits with FP64 atomics.
+// streams each segment's slots once, coalesced, with persistent blocks that take tiles from
+// per-XCD queues and steal from the others when theirs is empty (load balancing inside the
+// GPU), and deposits with FP64 atomics.
 #include <type_traits>
 
 #include "pic_device.h"
@@ -18,7 +19,8 @@ namespace pic {
 
 // =======================================================================================
 // Tile scheduling of the persistent FP64 kernels: live tiles are enumerated over all
-// segments; block b owns a contiguous run of them.  Blocks are dispatched round-robin over the 8 XCDs, so block b is mapped
+// segments.  The particle pass takes them from queues (tq_grab); the sort scatter gives
+// block b a contiguous run of them.  Blocks are dispatched round-robin over the 8 XCDs, so block b is mapped
 // to run (b % 8) * (G / 8) + b / 8: each XCD gets one contiguous eighth of the particles
 // (and of the cells, once sorted), which keeps its L2 working set to its own part of the
 // grid.
@@ -56,6 +58,24 @@ __device__ __forceinline__ int seg_of_tile(const int64_t *s_tpre, int nseg, int6
             hi = mid;
     }
     return lo;
+}
+
+// Single-GPU load balancing of the persistent FP64 pass (the analogue, inside one GPU, of
+// the paper's particle load balancing between ranks): the live tiles are split into eight
+// contiguous queues, one per XCD (queue x holds tiles [x T / 8, (x + 1) T / 8)), and a
+// block takes kGrabTiles tiles at a time from the queue of its own XCD (blocks are
+// dispatched round-robin over the XCDs), with the next grab in flight while it works; when
+// that queue is empty it takes from the others in turn.  Blocks that draw slow tiles (many
+// cell changes, births spread over the domain, atomics on shared nodes) simply take fewer,
+// so the launch ends when the work does, not when the slowest static share does.  A queue
+// counter is the number of tiles handed out; the last block to finish resets them.
+constexpr int kGrabTiles = 2;
+constexpr int kTileQueues = 8;
+
+// First tile of the next grab from queue x (a value >= the queue's end means empty).
+__device__ __forceinline__ int64_t tq_grab(const Dev &d, int x, int64_t T)
+{
+    return (int64_t)x * T / kTileQueues + (int64_t)atomicAdd(d.tq + x, (uint32_t)kGrabTiles);
 }
 
 __device__ __forceinline__ void block_run(int64_t T, int64_t &t0, int64_t &t1)
@@ -144,8 +164,6 @@ __global__ void __launch_bounds__(256) k_particles(Dev d, int hist_rt)
     const int64_t TILE = (int64_t)BLOCK * PPT;
     sched_prefix(d, TILE, s_tpre);
     const int64_t T = s_tpre[d.nseg];
-    int64_t t0, t1;
-    block_run(T, t0, t1);
     const int b = *d.cur;
     const int64_t step = *d.step;
     const uint32_t tag = (uint32_t)step;
@@ -154,9 +172,32 @@ __global__ void __launch_bounds__(256) k_particles(Dev d, int hist_rt)
     Tally tal;
     tal.zero();
     int tseg = -1;
+    // tile queues: own XCD's first, then the others in turn (see tq_grab)
+    __shared__ int64_t s_grab;
+    __shared__ bool s_last;
+    const int xq = (int)(blockIdx.x % kTileQueues);
+    int qi = 0;
+    if (threadIdx.x == 0) s_grab = tq_grab(d, xq, T);
     __syncthreads();
+    int64_t g0 = s_grab;
 
-    for (int64_t t = t0; t < t1; ++t) {
+    for (;;) {
+        const int x = (xq + qi) % kTileQueues;
+        const int64_t qend = (int64_t)(x + 1) * T / kTileQueues;
+        if (g0 >= qend) {
+            // this queue is empty: try the next one, or stop after the last
+            if (++qi == kTileQueues) break;
+            __syncthreads();
+            if (threadIdx.x == 0) s_grab = tq_grab(d, (xq + qi) % kTileQueues, T);
+            __syncthreads();
+            g0 = s_grab;
+            continue;
+        }
+        // the next grab from the same queue, in flight while these tiles are processed
+        __syncthreads();
+        if (threadIdx.x == 0) s_grab = tq_grab(d, x, T);
+        const int64_t g1 = min(g0 + kGrabTiles, qend);
+    for (int64_t t = g0; t < g1; ++t) {
         const int sg = seg_of_tile(s_tpre, d.nseg, t);
         const SegC &S = d.seg[sg];
         const EnsC &e = d.ens[S.ens];
@@ -270,7 +311,15 @@ __global__ void __launch_bounds__(256) k_particles(Dev d, int hist_rt)
             for (int k = 0; k < PPT; ++k) wave_deposit64(d, S, s, live[k], live[k] ? p[k].x : 0.0, hist, !DEPO);
         }
     }
+        __syncthreads();
+        g0 = s_grab;
+    }
     if ((PUSH || COLL) && tseg >= 0) flush_tally(d, tseg, tal, COLL);
+    // the last block to finish resets the queues (every block has stopped taking tiles)
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(d.tq + kTileQueues, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (s_last && threadIdx.x <= kTileQueues) d.tq[threadIdx.x] = 0u;
 }
 
 // =======================================================================================

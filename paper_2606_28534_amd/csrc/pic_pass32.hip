@@ -615,273 +615,6 @@ __global__ void __launch_bounds__(256) k_pass32(Dev d, int W, int hist_rt, int64
 }
 
 // =======================================================================================
-// Null-collision candidates of the FP32 pass.  A block takes kCandTiles consecutive tiles;
-// their candidate records (post-push state and slot, written by the pass) are concatenated
-// through a prefix of the tile counts, one candidate per thread.  Each candidate draws the
-// full Philox block 0 again, picks its channel (in FP64, the same decision in both
-// precisions), scatters, writes its velocity back to its slot, and on ionisation appends
-// the new pair.  Collision counts and the largest post-collision speed are gathered in LDS
-// per segment and go out once per block and segment.
-//
-// The block's critical path is a chain of dependent global round trips, so it is kept
-// short: the tile counts carry their tile's segment and ensemble (cand_tag), so one load
-// gives the block what it needs to stage those segments' constants and collision bounds
-// in LDS, in the same round trip as the candidate records; then the birth reservation.
-// =======================================================================================
-constexpr int kCandTiles = 32;
-constexpr int kCandSegs = 12;  // segments a block stages (more: read from global memory)
-
-template <bool CXREL>
-__global__ void __launch_bounds__(256) k_cand32(Dev d, int tile, int64_t T, int hist)
-{
-    __shared__ uint32_t s_pre[kCandTiles + 1];
-    __shared__ int s_tj[kCandTiles];  // staged entry of each tile's segment (-1: not staged)
-    // staged segment constants: entry j is segment s_sg[j] of ensemble s_en[j]
-    __shared__ SegC s_seg[kCandSegs];
-    __shared__ EnsC s_ens[kCandSegs];
-    __shared__ double s_nu[kCandSegs][2];  // nu_max, P_null
-    __shared__ int s_sg[kCandSegs], s_en[kCandSegs];
-    __shared__ int s_ns;
-    // block tallies per staged entry (segments that are not staged send theirs with
-    // atomics of their own)
-    __shared__ uint32_t s_n[kCandSegs][3];
-    __shared__ unsigned long long s_v[kCandSegs];
-    // scalar diagnostics of the step: the change of sum |v|^2 from collisions and births,
-    // and the births per segment
-    __shared__ double s_dk[kCandSegs];
-    __shared__ uint32_t s_dn[kCandSegs];
-    // births of one round of the block: counted in LDS, then one reservation in the list
-    __shared__ uint32_t s_nb, s_bbase;
-    const int64_t t0 = (int64_t)blockIdx.x * kCandTiles;
-    // per-launch values, read with the tile counts
-    const int b = *d.cur;
-    const uint32_t tag = (uint32_t)(*d.step);
-    const int half = 1 - *d.vcur;
-    if (threadIdx.x < kWave) {
-        // the first wave loads the tile counts in parallel, resets them, scans, and lists
-        // the distinct segments of the tiles that hold candidates
-        const int k = threadIdx.x;
-        const int64_t t = t0 + k;
-        uint32_t w = 0;
-        if (k < kCandTiles && t < T) {
-            w = d.ctile[t];
-            d.ctile[t] = 0u;
-        }
-        const uint32_t c = w & kCandCountMask;
-        uint32_t inc = c;
-#pragma unroll
-        for (int o = 1; o < kCandTiles; o <<= 1) {
-            const uint32_t n = __shfl_up(inc, o);
-            if (k >= o) inc += n;
-        }
-        // a tile opens a new entry when it holds candidates and its segment differs from
-        // that of the last earlier tile with candidates (segments grow with the slot, so
-        // the keys of such tiles never decrease: the previous one is the running maximum
-        // over the lanes below)
-        const int key = c ? (int)((w >> 12) & 0x3FFu) : -1;
-        int pm = key;
-#pragma unroll
-        for (int o = 1; o < kCandTiles; o <<= 1) {
-            const int n = __shfl_up(pm, o);
-            if (k >= o) pm = max(pm, n);
-        }
-        int before = __shfl_up(pm, 1);
-        if (k == 0) before = -1;
-        const bool head = key >= 0 && key != before;
-        const unsigned long long hm = __ballot(head);
-        const int hidx = __popcll(hm & ((1ull << k) - 1ull)) - (head ? 0 : 1);  // entry of the run k is in
-        if (k < kCandTiles) {
-            s_pre[k] = inc - c;
-            s_tj[k] = (key >= 0 && hidx < kCandSegs) ? hidx : -1;
-        }
-        if (k == kCandTiles - 1) s_pre[kCandTiles] = inc;
-        if (head && hidx < kCandSegs) {
-            s_sg[hidx] = key;
-            s_en[hidx] = (int)(w >> 22);
-        }
-        if (k == 0) s_ns = min(__popcll(hm), kCandSegs);
-        if (k < kCandSegs) {
-            s_n[k][0] = s_n[k][1] = s_n[k][2] = 0u;
-            s_v[k] = 0ull;
-            s_dk[k] = 0.0;
-            s_dn[k] = 0u;
-        }
-    }
-    __syncthreads();
-    const uint32_t m = s_pre[kCandTiles];
-    if (m == 0) return;
-    {
-        // stage the segments' constants (word copies; all loads in one round trip)
-        const int ns = s_ns;
-        constexpr int WS = sizeof(SegC) / 4, WE = sizeof(EnsC) / 4;
-        static_assert(sizeof(SegC) % 4 == 0 && sizeof(EnsC) % 4 == 0, "word copies");
-        for (int i = threadIdx.x; i < ns * (WS + WE + 2); i += blockDim.x) {
-            const int j = i / (WS + WE + 2), o = i % (WS + WE + 2);
-            if (o < WS)
-                ((uint32_t *)&s_seg[j])[o] = ((const uint32_t *)(d.seg + s_sg[j]))[o];
-            else if (o < WS + WE)
-                ((uint32_t *)&s_ens[j])[o - WS] = ((const uint32_t *)(d.ens + s_en[j]))[o - WS];
-            else if (o == WS + WE)
-                s_nu[j][0] = d.numax[s_sg[j]];
-            else
-                s_nu[j][1] = d.pnull[s_sg[j]];
-        }
-    }
-    const BirthBuf bb = birth_buf(d, (int)(tag & 1u));
-    const int st = stripe_of_block();          // counters and speed maxima
-    const int bst = (int)(blockIdx.x & (kStripes - 1));  // birth list
-    for (uint32_t q0 = 0; q0 < m; q0 += blockDim.x) {
-        const uint32_t q = q0 + threadIdx.x;
-        const bool act = q < m;
-        // this candidate's tile: the last k with s_pre[k] <= q (tiles without candidates
-        // share their prefix with the next tile, which this picks)
-        int k = 0;
-        uint4 r0 = make_uint4(0u, 0u, 0u, 0u), r1 = r0;
-        if (act) {
-            int lo = 0, hi = kCandTiles;
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (s_pre[mid] <= q)
-                    lo = mid;
-                else
-                    hi = mid;
-            }
-            k = lo;
-            const uint4 *r = d.crec + 2 * ((t0 + k) * (int64_t)tile + (q - s_pre[k]));
-            r0 = r[0];
-            r1 = r[1];
-        }
-        if (q0 == 0) __syncthreads();  // the staged constants are in place
-        int ch = -1, sg = 0, j = -1;
-        PS<false> p;
-        double ve[3], vi[3];
-        int64_t i = 0;
-        int oth = -1;  // the ion segment of an electron segment (births)
-        if (act) {
-            j = s_tj[k];
-            i = (int64_t)r0.x;
-            sg = (int)r1.w;
-            p.cell = (int)r0.y;
-            p.off = __uint_as_float(r0.z);
-            p.id = r0.w;
-            p.vx = __uint_as_float(r1.x);
-            p.vy = __uint_as_float(r1.y);
-            p.vz = __uint_as_float(r1.z);
-            if (j >= 0) {
-                const SegC &S = s_seg[j];
-                const EnsC &e = s_ens[j];
-                oth = S.other;
-                ch = p_collide<false, CXREL>(e, S, S.species, s_nu[j][0], s_nu[j][1], tag, p, ve, vi);
-            } else {
-                const SegC S = d.seg[sg];
-                const EnsC e = d.ens[S.ens];
-                oth = S.other;
-                ch = p_collide<false, CXREL>(e, S, S.species, d.numax[sg], d.pnull[sg], tag, p, ve, vi);
-            }
-        }
-        if (ch >= 0) {
-            d.fvx[b][i] = p.vx;
-            d.fvy[b][i] = p.vy;
-            d.fvz[b][i] = p.vz;
-            // the particle's |v|^2 after the collision replaces the one the pass tallied
-            // (taken off exactly as the pass computed it); an ionisation adds the new
-            // electron here and the new ion below (as stored, in binary32)
-            double dk = speed2_rn(p.vx, p.vy, p.vz) -
-                        (double)speed2_f32(__uint_as_float(r1.x), __uint_as_float(r1.y), __uint_as_float(r1.z));
-            if (ch == 1) dk += speed2_rn((float)ve[0], (float)ve[1], (float)ve[2]);
-            if (j >= 0) {
-                atomicAdd(&s_n[j][ch], 1u);
-                atomicAdd(&s_dk[j], dk);
-                if (ch == 1) atomicAdd(&s_dn[j], 1u);
-            } else {
-                unsigned long long *c = d.cnt + ((int64_t)st * d.nseg + sg) * C_NCNT;
-                atomicAdd(c + (ch == 0 ? C_EL : ch == 1 ? C_IZ : C_CX), 1ull);
-                double *ts = step_sums(d, half, st, sg);
-                unsafeAtomicAdd(ts + T_V2, dk);
-                if (ch == 1) unsafeAtomicAdd(ts + T_N, 1.0);
-            }
-        }
-        if (act) {
-            double v2m = speed2_rn(p.vx, p.vy, p.vz);
-            if (ch == 1) {
-                v2m = fmax(v2m, speed2_rn(ve[0], ve[1], ve[2]));
-                if (oth >= 0) {
-                    // the new ion: its speed bound and diagnostics go to the ion segment
-                    // directly (one of a few per block)
-                    const double ki = speed2_rn((float)vi[0], (float)vi[1], (float)vi[2]);
-                    double *ts = step_sums(d, half, st, oth);
-                    unsafeAtomicAdd(ts + T_V2, ki);
-                    unsafeAtomicAdd(ts + T_N, 1.0);
-                    atomicMax(d.vmax2 + ((int64_t)half * kCntStripes + st) * d.nseg + oth,
-                              dbits(speed2_rn(vi[0], vi[1], vi[2])));
-                }
-            }
-            if (j >= 0) {
-                if (v2m > 0.0) atomicMax(&s_v[j], dbits(v2m));
-            } else if (v2m > 0.0) {
-                atomicMax(d.vmax2 + ((int64_t)half * kCntStripes + st) * d.nseg + sg, dbits(v2m));
-            }
-        }
-        // births of this round: one list reservation for the whole block
-        if (threadIdx.x == 0) s_nb = 0u;
-        __syncthreads();
-        uint32_t lb = 0;
-        if (ch == 1) lb = atomicAdd(&s_nb, 1u);
-        __syncthreads();
-        if (threadIdx.x == 0 && s_nb) s_bbase = atomicAdd(bb.nbirth + bst, s_nb);
-        // the deposit of the new pair (the fused step's; the separate stages deposit all
-        // particles afresh), while the reservation is in flight
-        if (ch == 1) {
-            const SegC Se = j >= 0 ? s_seg[j] : d.seg[sg];
-            global_deposit32(d, Se, Se.species, p.cell, p.off, hist != 0);
-            if (oth >= 0) {
-                const SegC So = d.seg[oth];
-                global_deposit32(d, So, 1, p.cell, p.off, hist != 0);
-            }
-        }
-        __syncthreads();
-        if (ch == 1) {
-            const uint32_t slot = s_bbase + lb;
-            if ((int64_t)slot < d.birth_stripe_cap) {
-                const int ens = j >= 0 ? s_seg[j].ens : d.seg[sg].ens;
-                const double dx = j >= 0 ? s_seg[j].dx : d.seg[sg].dx;
-                Birth &B = bb.births[(int64_t)bst * d.birth_stripe_cap + slot];
-                B.pid = p.id;
-                B.ens = ens;
-                B.cell = p.cell;
-                B.off = p.off;
-                B.x = ((double)p.cell + (double)p.off) * dx;
-                for (int c = 0; c < 3; ++c) {
-                    B.ve[c] = ve[c];
-                    B.vi[c] = vi[c];
-                }
-                if (j >= 0)
-                    birth_mark(bb, s_ens[j], p.id);
-                else
-                    birth_mark(bb, d.ens[ens], p.id);
-            } else {
-                atomicOr(d.err, (int)E_CAP_BIRTH);
-            }
-        }
-        __syncthreads();  // s_nb and s_bbase are reused by the next round
-    }
-    // one set of counter atomics per block and staged segment
-    if ((int)threadIdx.x < s_ns) {
-        const int j = threadIdx.x, sgj = s_sg[j];
-        unsigned long long *c = d.cnt + ((int64_t)st * d.nseg + sgj) * C_NCNT;
-        if (s_n[j][0]) atomicAdd(c + C_EL, (unsigned long long)s_n[j][0]);
-        if (s_n[j][1]) atomicAdd(c + C_IZ, (unsigned long long)s_n[j][1]);
-        if (s_n[j][2]) atomicAdd(c + C_CX, (unsigned long long)s_n[j][2]);
-        if (s_v[j]) atomicMax(d.vmax2 + ((int64_t)half * kCntStripes + st) * d.nseg + sgj, s_v[j]);
-        if (s_dk[j] != 0.0 || s_dn[j]) {
-            double *ts = step_sums(d, half, st, sgj);
-            if (s_dk[j] != 0.0) unsafeAtomicAdd(ts + T_V2, s_dk[j]);
-            if (s_dn[j]) unsafeAtomicAdd(ts + T_N, (double)s_dn[j]);
-        }
-    }
-}
-
-// =======================================================================================
 // Counting sort scatter (FP32 form).  Thread t owns slots t, t + 256, ... of the tile, so a
 // wave holds 64 consecutive (sorted, so mostly same-cell) particles.  Within a wave the
 // lanes of one cell take consecutive ranks from one LDS atomic of their leader; each cell
@@ -1074,17 +807,6 @@ hipError_t launch_stream_copy(const void *src, void *dst, int64_t nwords, bool n
     return hipGetLastError();
 }
 
-hipError_t launch_cand32(const Dev &d, int ppt, hipStream_t s, int hist, int64_t cap_tot)
-{
-    const int tile = 256 * ppt;
-    const int64_t T = cap_tot / tile;
-    const dim3 g((unsigned)((T + kCandTiles - 1) / kCandTiles));
-    if (d.any_cx_rel)
-        hipLaunchKernelGGL(k_cand32<true>, g, dim3(256), 0, s, d, tile, T, hist);
-    else
-        hipLaunchKernelGGL(k_cand32<false>, g, dim3(256), 0, s, d, tile, T, hist);
-    return hipGetLastError();
-}
 
 hipError_t launch_pass32(const Dev &d, int ppt, int W, hipStream_t s, int stages, int hist, int64_t cap_tot,
                          bool nt)
