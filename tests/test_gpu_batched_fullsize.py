@@ -50,6 +50,36 @@ def test_batched_equals_each_ensemble_alone(pic):
         alone.close()
 
 
+@pytest.mark.parametrize("fused", [False, True])
+def test_batched_fp64_queues_equal_each_ensemble_alone(pic, fused):
+    """The FP64 form's persistent pass takes its tiles from per-XCD queues and steals from
+    the others (load balancing inside the GPU).  Twelve uneven ensembles (a 64x spread of
+    cells, own seeds, collisions with births) advanced together give each ensemble's own
+    run: counts exactly, particles and fields to the rounding of the FP64 deposit atomics,
+    whose order follows the schedule.  Several steps, so the queues are reused after
+    their reset."""
+    work = synth.c3_batched(n_ens=12, seed=11, scale=0.02)
+    work["precision"] = "fp64"
+    for e in work["ensembles"]:
+        e["ngs_el"], e["ngs_iz"] = 0.05, 0.1
+        for sp in e["species"]:
+            sp["capacity"] *= 2
+    batch = pic.Sim(work, fused=fused)
+    batch.step(8)
+    for k in (0, 5, 11):
+        alone = pic.Sim(_single(work, k), fused=fused)
+        alone.step(8)
+        da, db = batch.diag(k), alone.diag(0)
+        for key in ("count", "coll", "created", "wall_count", "pushes"):
+            assert da[key] == db[key], (k, key, da[key], db[key])
+        for s in range(2):
+            compare_particles(batch.particles(k, s), alone.particles(0, s), work["ensembles"][k]["dx"], True,
+                              vtol=1e-9, xtol=1e-9)
+        assert rel(batch.grid(k)["E"], alone.grid(0)["E"]) <= 1e-9
+        alone.close()
+    batch.close()
+
+
 def test_batched_collisionless_window_matches_oracle(pic):
     work = synth.c3_batched(n_ens=12, seed=7, scale=0.03)
     for e in work["ensembles"]:

@@ -334,6 +334,31 @@ def test_one_full_step_with_collisions(pic, prec):
     if prec == "fp64":
         for s in range(2):
             compare_particles(sim.particles(0, s), o.particles(s), e["dx"], True, vtol=1e-11, xtol=1e-10)
+    else:
+        # every particle by id, births included, except the few whose collision decision
+        # flipped (a velocity within binary32 rounding of a channel threshold): those show as
+        # ids on one side only (a flipped ionisation) or as a velocity that differs by far
+        # more than rounding; the kinematics run in binary32 (vtol 1e-5 of the largest speed)
+        for s in range(2):
+            G, O = by_id(sim.particles(0, s)), by_id(o.particles(s))
+            odd = np.setxor1d(G["id"], O["id"])
+            common = np.intersect1d(G["id"], O["id"])
+            Gc = {k: v[np.isin(G["id"], common)] for k, v in G.items()}
+            Oc = {k: v[np.isin(O["id"], common)] for k, v in O.items()}
+            vmax = max(np.max(np.abs(Oc[k])) for k in ("vx", "vy", "vz"))
+            far = np.zeros(len(common), dtype=bool)
+            for k in ("vx", "vy", "vz"):
+                far |= np.abs(Gc[k] - Oc[k]) > 1e-3 * vmax
+            flipped = np.concatenate([odd, Gc["id"][far]])
+            assert len(flipped) <= 2 * slack, (s, len(odd), int(far.sum()))
+            compare_particles(sim.particles(0, s), o.particles(s), e["dx"], False, vtol=1e-5,
+                              exclude=flipped)
+    # E^1: both sides solve the charge this step deposited (births included)
+    sim.solve()
+    o.solve()
+    g, r = sim.grid(), o.grid()
+    for k in ("rho", "phi", "E"):
+        assert rel(g[k], r[k]) <= (1e-10 if prec == "fp64" else TOL_FIELD), (k, rel(g[k], r[k]))
 
 
 def _state(sim, nspec=2):
