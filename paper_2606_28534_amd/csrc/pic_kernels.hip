@@ -159,6 +159,8 @@ __global__ void __launch_bounds__(256) k_particles(Dev d, int hist_rt)
     constexpr bool NEED_ID = COLL;
 
     __shared__ int64_t s_tpre[kMaxSeg + 1];
+    __shared__ double s_win[DEPO ? kWin64 : 1];  // the tile's deposit window
+    __shared__ int s_mm[8];
 
     const int BLOCK = blockDim.x;
     const int64_t TILE = (int64_t)BLOCK * PPT;
@@ -249,9 +251,10 @@ __global__ void __launch_bounds__(256) k_particles(Dev d, int hist_rt)
                     d.x[b][i] = -1.0;
                 }
             }
+            int ch = -1;  // collision channel (-1: none)
             if (COLL && live[k]) {
                 double ve[3], vi[3];
-                const int ch = p_collide<true>(e, S, s, numax, pnull, tag, p[k], ve, vi);
+                ch = p_collide<true>(e, S, s, numax, pnull, tag, p[k], ve, vi);
                 if (ch == 0)
                     ++tal.el;
                 else if (ch == 2)
@@ -298,17 +301,21 @@ __global__ void __launch_bounds__(256) k_particles(Dev d, int hist_rt)
                 }
                 tal.v2max = fmax(tal.v2max, speed2_rn((double)p[k].vx, (double)p[k].vy, (double)p[k].vz));
             }
-            if (live[k] && (PUSH || COLL)) {
+            // the collide stage alone writes back only the velocities it changed
+            if (live[k] && (PUSH || ch >= 0)) {
                 if (PUSH) d.x[b][i] = p[k].x;
                 d.dvx[b][i] = p[k].vx;
                 d.dvy[b][i] = p[k].vy;
                 d.dvz[b][i] = p[k].vz;
             }
         }
-        // deposit (and sort histogram) by runs of equal cell across the wave's lanes
-        if (DEPO || HISTC) {
+        // deposit through the tile's LDS window (and sort histogram), by runs of equal cell
+        // across the wave's lanes
+        if constexpr (DEPO) {
+            tile_deposit64<PPT>(d, S, s, live, p, hist, s_win, s_mm);
+        } else if (HISTC) {
 #pragma unroll
-            for (int k = 0; k < PPT; ++k) wave_deposit64(d, S, s, live[k], live[k] ? p[k].x : 0.0, hist, !DEPO);
+            for (int k = 0; k < PPT; ++k) wave_deposit64(d, S, s, live[k], live[k] ? p[k].x : 0.0, hist, true);
         }
     }
         __syncthreads();

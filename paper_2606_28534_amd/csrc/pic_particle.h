@@ -330,13 +330,21 @@ __device__ __forceinline__ void global_deposit64(const Dev &d, const SegC &S, in
     if (hist) atomicAdd(d.cellcnt + S.cbase + j, 1u);
 }
 
+// The FP64 deposit window of one tile: nodes [base, base + n) accumulate in LDS (FP64 LDS
+// atomics) and are added to the node array once per tile; n = 0 sends every share to HBM.
+struct Win64 {
+    double *w;
+    int base, n;
+};
+
 // Cloud-in-cell deposit of one particle per lane (FP64 form), called by every lane of the
 // wave: lanes hold consecutive slots, which after a sort mostly share a cell, so the wave
 // first sums the shares of each run of consecutive lanes with the same cell (a segmented
-// scan over the lanes) and the last lane of each run adds the run's two shares with one
-// FP64 atomic per node, and its count to the sort histogram.  `cnt_only` skips the shares.
+// scan over the lanes) and the last lane of each run adds the run's two shares, into the
+// tile's LDS window when both nodes lie in it and with one FP64 atomic per node otherwise,
+// and its count to the sort histogram.  `cnt_only` skips the shares.
 __device__ __forceinline__ void wave_deposit64(const Dev &d, const SegC &S, int s, bool live, double x,
-                                               bool hist, bool cnt_only)
+                                               bool hist, bool cnt_only, const Win64 &W = Win64{nullptr, 0, 0})
 {
     const int lane = lane_id();
     double f = 0.0;
@@ -362,13 +370,71 @@ __device__ __forceinline__ void wave_deposit64(const Dev &d, const SegC &S, int 
     const bool tail = lane == kWave - 1 || ((heads >> (lane + 1)) & 1ull);
     if (!tail || key < 0) return;
     if (!cnt_only) {
-        int j1 = key + 1;
-        if (S.periodic && j1 == S.ncells) j1 = 0;
-        double *Q = d.Qd + (int64_t)s * d.nodes_tot + S.gbase;
-        unsafeAtomicAdd(Q + key, a);
-        unsafeAtomicAdd(Q + j1, c);
+        const int r = key - W.base;
+        if (r >= 0 && r + 1 < W.n) {
+            // node wbase + r + 1 may be N of a periodic grid: the flush wraps it to node 0
+            unsafeAtomicAdd(W.w + r, a);
+            unsafeAtomicAdd(W.w + r + 1, c);
+        } else {
+            int j1 = key + 1;
+            if (S.periodic && j1 == S.ncells) j1 = 0;
+            double *Q = d.Qd + (int64_t)s * d.nodes_tot + S.gbase;
+            unsafeAtomicAdd(Q + key, a);
+            unsafeAtomicAdd(Q + j1, c);
+        }
     }
     if (hist) atomicAdd(d.cellcnt + S.cbase + key, n);
+}
+
+// Deposit of one FP64 tile through an LDS window over the nodes of its cells (at most
+// kWin64 nodes from the lowest cell of the tile; shares beyond it go to HBM atomics): the
+// window is cleared, the waves add their merged runs into it, and each nonzero node is
+// added to the node array with one FP64 atomic.  Called by every thread of the block;
+// `s_mm` holds 8 ints.  The next call's barriers order its clearing after this flush.
+constexpr int kWin64 = 1024;
+
+template <int PPT>
+__device__ __forceinline__ void tile_deposit64(const Dev &d, const SegC &S, int s, const bool (&live)[PPT],
+                                               const PS<true> (&p)[PPT], bool hist, double *s_win, int *s_mm)
+{
+    int mn = INT32_MAX, mx = -1;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        if (!live[k]) continue;
+        double f;
+        const int j = (int)cell_of_x(S, p[k].x, f);
+        mn = min(mn, j);
+        mx = max(mx, j);
+    }
+    mn = wave_min_i32(mn);
+    mx = wave_max_i32(mx);
+    const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    if (lane_id() == 0) {
+        s_mm[w] = mn;
+        s_mm[4 + w] = mx;
+    }
+    __syncthreads();
+    mn = s_mm[0];
+    mx = s_mm[4];
+    for (int i = 1; i < nw; ++i) {
+        mn = min(mn, s_mm[i]);
+        mx = max(mx, s_mm[4 + i]);
+    }
+    const int n = mx >= 0 ? min(mx - mn + 2, kWin64) : 0;  // nodes mn .. mx + 1
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s_win[i] = 0.0;
+    __syncthreads();
+    const Win64 W{s_win, mn, n};
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) wave_deposit64(d, S, s, live[k], live[k] ? p[k].x : 0.0, hist, false, W);
+    __syncthreads();
+    double *Q = d.Qd + (int64_t)s * d.nodes_tot + S.gbase;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double v = s_win[i];
+        if (v == 0.0) continue;
+        int node = mn + i;
+        if (S.periodic && node >= S.ncells) node -= S.ncells;
+        unsafeAtomicAdd(Q + node, v);
+    }
 }
 
 }  // namespace pic
