@@ -11,6 +11,7 @@
 // GPU), and deposits with FP64 atomics.
 #include <type_traits>
 
+#include "pic.h"
 #include "pic_device.h"
 #include "pic_kernels.h"
 #include "pic_particle.h"
@@ -1267,48 +1268,86 @@ __global__ void __launch_bounds__(1024) k_group_scan(Dev d) { group_scan_body(d)
 // birth counts, so the next step starts on a clean half.  The last block updates the
 // counters, makes the freshly accumulated speed maxima current and (with `advance`)
 // advances the step counter.
+// The constants a birth's placement needs, staged in LDS by every placing block (one round
+// trip, beside the stripe counts), so that a birth's chain of dependent loads is its record
+// and then its rank: per ensemble the birth-ranking bases, id capacity and segments, per
+// segment the slot base and capacity and the slots and ids in use before the placement.
+struct PlaceEns {
+    int64_t bm_base, grp_base, idcap;
+    int32_t seg[2];
+    int32_t nspecies;
+};
+struct PlaceSeg {
+    int64_t base, cap, n_slots;
+    uint32_t next_id;
+};
+
 template <bool F64>
 __device__ void birth_place_body(const Dev &d, int deferred, int advance, int bid, int nblk)
 {
     __shared__ uint32_t s_pre[kStripes + 1];
     __shared__ uint32_t s_old[kStripes + 1];
     __shared__ bool s_last;
-    const int p = (int)(*d.step & 1);
+    __shared__ PlaceEns s_pe[PIC_MAX_ENSEMBLES];
+    __shared__ PlaceSeg s_ps[2 * PIC_MAX_ENSEMBLES];
+    const int64_t step = *d.step;
+    const int vc = *d.vcur;
+    const int p = (int)(step & 1);
     const BirthBuf bb = birth_buf(d, p), ob = birth_buf(d, 1 - p);
     if (threadIdx.x < kWave) {
         stripe_prefix(bb, d.birth_stripe_cap, s_pre);
         if (deferred) stripe_prefix(ob, d.birth_stripe_cap, s_old);
     }
+    for (int en = threadIdx.x; en < d.nens; en += blockDim.x) {
+        const EnsC &e = d.ens[en];
+        s_pe[en] = PlaceEns{e.bm_base, e.grp_base, e.idcap, {e.seg[0], e.seg[1]}, e.nspecies};
+    }
+    for (int sg = threadIdx.x; sg < d.nseg; sg += blockDim.x) {
+        const SegC &S = d.seg[sg];
+        s_ps[sg] = PlaceSeg{S.base, S.cap, d.n_slots[sg], d.next_id[sg]};
+    }
     __syncthreads();
-    const int64_t M = s_pre[kStripes];
+    const int64_t M = s_pre[kStripes], Mo = deferred ? (int64_t)s_old[kStripes] : 0;
     const int b = *d.cur;
-    for (int64_t k = (int64_t)bid * blockDim.x + threadIdx.x; k < M;
+    // this step's births (k < M) and, with `deferred`, the previous step's (k < Mo), whose
+    // bits and group counts are cleared; both records are loaded before either is used
+    for (int64_t k = (int64_t)bid * blockDim.x + threadIdx.x; k < max(M, Mo);
          k += (int64_t)nblk * blockDim.x) {
-        int st;
-        uint32_t idx;
-        birth_locate(d, k, st, idx, s_pre);
+        const bool nw = k < M, od = k < Mo;
+        int st = 0, sto = 0;
+        uint32_t idx = 0, idxo = 0;
+        if (nw) birth_locate(d, k, st, idx, s_pre);
+        if (od) birth_locate(d, k, sto, idxo, s_old);
         // copies: the particle stores below cannot alias them, so nothing is read twice
-        const Birth B = bb.births[(int64_t)st * d.birth_stripe_cap + idx];
-        const EnsC e = d.ens[B.ens];
+        Birth B{};
+        uint2 okey = make_uint2(0u, 0u);
+        if (nw) B = bb.births[(int64_t)st * d.birth_stripe_cap + idx];
+        if (od) okey = *(const uint2 *)&ob.births[(int64_t)sto * d.birth_stripe_cap + idxo];
+        if (od) {
+            const PlaceEns &E = s_pe[okey.y];
+            ob.bitmap[E.bm_base + (okey.x >> 5)] = 0u;
+            ob.gcnt[E.grp_base + okey.x / kGroupIds] = 0u;
+        }
+        if (!nw) continue;
+        const PlaceEns &E = s_pe[B.ens];
         const uint32_t pid = B.pid;
         const int64_t g = pid / kGroupIds;
-        const uint32_t r = d.gpre[e.grp_base + g] - d.gpre[e.grp_base] +
-                           rank_in_group(bb.bitmap + e.bm_base + g * kGroupWords, pid);
+        const uint32_t r = d.gpre[E.grp_base + g] - d.gpre[E.grp_base] +
+                           rank_in_group(bb.bitmap + E.bm_base + g * kGroupWords, pid);
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
-            if (s >= e.nspecies) break;
-            const int sg = e.seg[s];
-            const SegC S = d.seg[sg];
-            const int64_t slot = d.n_slots[sg] + r;
-            if (slot >= S.cap) {
+            if (s >= E.nspecies) break;
+            const PlaceSeg &P = s_ps[E.seg[s]];
+            const int64_t slot = P.n_slots + r;
+            if (slot >= P.cap) {
                 atomicOr(d.err, (int)E_CAP_PART);
                 continue;
             }
-            if ((int64_t)d.next_id[sg] + r >= e.idcap) {
+            if ((int64_t)P.next_id + r >= E.idcap) {
                 atomicOr(d.err, (int)E_CAP_ID);
                 continue;
             }
-            const int64_t i = S.base + slot;
+            const int64_t i = P.base + slot;
             const double v0 = s == 0 ? B.ve[0] : B.vi[0];
             const double v1 = s == 0 ? B.ve[1] : B.vi[1];
             const double v2 = s == 0 ? B.ve[2] : B.vi[2];
@@ -1324,22 +1363,11 @@ __device__ void birth_place_body(const Dev &d, int deferred, int advance, int bi
                 d.dvy[b][i] = v1;
                 d.dvz[b][i] = v2;
             }
-            d.id[b][i] = d.next_id[sg] + r;
-        }
-    }
-    if (deferred) {
-        const int64_t Mo = s_old[kStripes];
-        for (int64_t k = (int64_t)bid * blockDim.x + threadIdx.x; k < Mo;
-             k += (int64_t)nblk * blockDim.x) {
-            int st;
-            uint32_t idx;
-            birth_locate(d, k, st, idx, s_old);
-            const Birth &B = ob.births[(int64_t)st * d.birth_stripe_cap + idx];
-            birth_unmark(ob, d.ens[B.ens], B.pid);
+            d.id[b][i] = P.next_id + r;
         }
     }
     // The last block only updates counters that no block of this launch reads after taking
-    // its ticket (each block's loads have returned before its barrier), and the next kernel
+    // its ticket (each block staged them before its first barrier), and the next kernel
     // sees every write, so no device-scope fence is needed here; on gfx950 such a fence
     // writes back the XCD's L2 and costs microseconds per block.
     __syncthreads();
@@ -1347,35 +1375,30 @@ __device__ void birth_place_body(const Dev &d, int deferred, int advance, int bi
     __syncthreads();
     if (!s_last) return;
     for (int en = threadIdx.x; en < d.nens; en += blockDim.x) {
-        const EnsC &e = d.ens[en];
-        const int64_t ngrp = (e.idcap + kGroupIds - 1) / kGroupIds;
-        const uint32_t m = d.gpre[e.grp_base + ngrp] - d.gpre[e.grp_base];
-        for (int s = 0; s < e.nspecies; ++s) {
-            const int sg = e.seg[s];
-            const SegC &S = d.seg[sg];
-            d.n_slots[sg] = min(d.n_slots[sg] + (int64_t)m, S.cap);
-            d.next_id[sg] += m;
+        const PlaceEns &E = s_pe[en];
+        const int64_t ngrp = (E.idcap + kGroupIds - 1) / kGroupIds;
+        const uint32_t m = d.gpre[E.grp_base + ngrp] - d.gpre[E.grp_base];
+        for (int s = 0; s < E.nspecies; ++s) {
+            const int sg = E.seg[s];
+            const PlaceSeg &P = s_ps[sg];
+            d.n_slots[sg] = min(P.n_slots + (int64_t)m, P.cap);
+            d.next_id[sg] = P.next_id + m;
             if (m) atomicAdd(d.cnt + ((int64_t)0 * d.nseg + sg) * C_NCNT + C_CREATED, (unsigned long long)m);
         }
     }
     if (deferred)
         for (int i = threadIdx.x; i < kStripes; i += blockDim.x) ob.nbirth[i] = 0u;
-    __syncthreads();
     if (threadIdx.x == 0) {
         d.ticket[1] = 0u;
-        atomicExch(d.vcur, 1 - *d.vcur);  // atomic: the bound may be computed in this launch
+        atomicExch(d.vcur, 1 - vc);  // atomic: the bound may be computed in this launch
     }
-    __syncthreads();
-    {
-        const int old = 1 - *d.vcur;
-        for (int64_t i = threadIdx.x; i < (int64_t)kCntStripes * d.nseg; i += blockDim.x)
-            d.vmax2[(int64_t)old * kCntStripes * d.nseg + i] = 0ull;
-        // the step tallies of the half the next step accumulates
-        for (int64_t i = threadIdx.x; i < (int64_t)kCntStripes * d.nseg * T_NSTEP; i += blockDim.x)
-            d.ssum[(int64_t)old * kCntStripes * d.nseg * T_NSTEP + i] = 0.0;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0 && advance) *d.step += 1;
+    // the half that held the current maxima accumulates the next step's, and the step
+    // tallies of that half restart
+    for (int64_t i = threadIdx.x; i < (int64_t)kCntStripes * d.nseg; i += blockDim.x)
+        d.vmax2[(int64_t)vc * kCntStripes * d.nseg + i] = 0ull;
+    for (int64_t i = threadIdx.x; i < (int64_t)kCntStripes * d.nseg * T_NSTEP; i += blockDim.x)
+        d.ssum[(int64_t)vc * kCntStripes * d.nseg * T_NSTEP + i] = 0.0;
+    if (threadIdx.x == 0 && advance) *d.step = step + 1;
 }
 
 template <bool F64>
