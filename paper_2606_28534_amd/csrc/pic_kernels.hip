@@ -201,9 +201,10 @@ __global__ void __launch_bounds__(256) k_particles(Dev d, int hist_rt)
         if (threadIdx.x == 0) s_grab = tq_grab(d, x, T);
         const int64_t g1 = min(g0 + kGrabTiles, qend);
     for (int64_t t = g0; t < g1; ++t) {
-        const int sg = seg_of_tile(s_tpre, d.nseg, t);
+        const int sg = __builtin_amdgcn_readfirstlane(seg_of_tile(s_tpre, d.nseg, t));
         const SegC &S = d.seg[sg];
         const EnsC &e = d.ens[S.ens];
+        const Seg64 G = seg64(S, e);  // gather, push and deposit constants in registers
         const int s = S.species;
         if (sg != tseg) {
             if (tseg >= 0 && (PUSH || COLL)) flush_tally(d, tseg, tal, COLL);
@@ -213,27 +214,32 @@ __global__ void __launch_bounds__(256) k_particles(Dev d, int hist_rt)
         const int64_t first = S.base + lt * TILE;
         const int64_t last = S.base + min((lt + 1) * TILE, d.n_slots[sg]);
 
+        // every particle's loads are issued before any is tested, so the tile waits for
+        // memory once
         PS<true> p[PPT];
         bool live[PPT];
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             const int64_t i = first + (int64_t)k * BLOCK + threadIdx.x;
-            live[k] = false;
-            if (i < last) {
-                p_load<true>(d, b, i, p[k], NEED_V, NEED_ID);
-                live[k] = p_alive<true>(p[k]);
-            }
+            p[k].x = -1.0;
+            if (i < last) p_load<true>(d, b, i, p[k], NEED_V, NEED_ID);
         }
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) live[k] = p_alive<true>(p[k]);
         const double numax = COLL ? d.numax[sg] : 0.0;
         const double pnull = COLL ? d.pnull[sg] : 0.0;
-
+        // The tile in phases, each over all its particles: push (every gather issued before
+        // any particle is pushed), collide, write back.  A particle still goes through push
+        // then collide, and the push constants are dead once the pushes are done.
+        if constexpr (PUSH) {
+            double Eg[PPT];
+            gather64<PPT>(d, G, p, Eg);
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            const int64_t i = first + (int64_t)k * BLOCK + threadIdx.x;
-            if (!live[k]) continue;
-            if (PUSH) {
+            for (int k = 0; k < PPT; ++k) {
+                if (!live[k]) continue;
+                const int64_t i = first + (int64_t)k * BLOCK + threadIdx.x;
                 ++tal.push;
-                const int wall = p_push<true>(d, S, e, p[k]);
+                const int wall = p_push64(d, G, p[k], Eg[k]);
                 if (wall == 3) {
                     p_kill<true>(p[k]);
                     live[k] = false;
@@ -252,15 +258,19 @@ __global__ void __launch_bounds__(256) k_particles(Dev d, int hist_rt)
                     d.x[b][i] = -1.0;
                 }
             }
-            int ch = -1;  // collision channel (-1: none)
+        }
+        int ch[PPT];  // collision channel (-1: none)
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            ch[k] = -1;
             if (COLL && live[k]) {
                 double ve[3], vi[3];
-                ch = p_collide<true>(e, S, s, numax, pnull, tag, p[k], ve, vi);
-                if (ch == 0)
+                ch[k] = p_collide<true>(e, S, s, numax, pnull, tag, p[k], ve, vi);
+                if (ch[k] == 0)
                     ++tal.el;
-                else if (ch == 2)
+                else if (ch[k] == 2)
                     ++tal.cx;
-                else if (ch == 1) {
+                else if (ch[k] == 1) {
                     ++tal.iz;
                     // birth record: slot in this block's stripe, or in the next ones when
                     // it is full
@@ -302,21 +312,28 @@ __global__ void __launch_bounds__(256) k_particles(Dev d, int hist_rt)
                 }
                 tal.v2max = fmax(tal.v2max, speed2_rn((double)p[k].vx, (double)p[k].vy, (double)p[k].vz));
             }
-            // the collide stage alone writes back only the velocities it changed
-            if (live[k] && (PUSH || ch >= 0)) {
-                if (PUSH) d.x[b][i] = p[k].x;
-                d.dvx[b][i] = p[k].vx;
-                d.dvy[b][i] = p[k].vy;
-                d.dvz[b][i] = p[k].vz;
-            }
+        }
+        // write back (the collide stage alone only the velocities it changed)
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            if (!(live[k] && (PUSH || ch[k] >= 0))) continue;
+            const int64_t i = first + (int64_t)k * BLOCK + threadIdx.x;
+            if (PUSH) d.x[b][i] = p[k].x;
+            d.dvx[b][i] = p[k].vx;
+            d.dvy[b][i] = p[k].vy;
+            d.dvz[b][i] = p[k].vz;
         }
         // deposit through the tile's LDS window (and sort histogram), by runs of equal cell
         // across the wave's lanes
         if constexpr (DEPO) {
-            tile_deposit64<PPT>(d, S, s, live, p, hist, s_win, s_mm);
+            tile_deposit64<PPT>(d, G, s, live, p, hist, s_win, s_mm);
         } else if (HISTC) {
 #pragma unroll
-            for (int k = 0; k < PPT; ++k) wave_deposit64(d, S, s, live[k], live[k] ? p[k].x : 0.0, hist, true);
+            for (int k = 0; k < PPT; ++k) {
+                double f = 0.0;
+                const int key = live[k] ? (int)cell_of_x64(G, p[k].x, f) : -1;
+                wave_deposit64(d, G, s, key, f, hist, true);
+            }
         }
     }
         __syncthreads();

@@ -39,8 +39,9 @@ __device__ __forceinline__ void p_load(const Dev &d, int b, int64_t i, PS<F64> &
             p.vz = d.fvz[b][i];
         }
     } else {
+        // every load is issued at once (a dead slot's velocity is read and not used), so a
+        // tile waits for memory once
         p.x = d.x[b][i];
-        if (!(p.x >= 0.0)) return;
         if (need_v) {
             p.vx = d.dvx[b][i];
             p.vy = d.dvy[b][i];
@@ -109,6 +110,82 @@ __device__ __forceinline__ void boris(T h, const T t[3], const T s[3], T Ep, T &
     vz = az;
 }
 
+// The segment constants of the FP64 gather, push and deposit, copied into registers once
+// per tile: after a particle store or atomic, a read through a reference into global
+// memory would be repeated, since the store might alias it.
+struct Seg64 {
+    int64_t gbase, cbase;
+    int32_t ncells, periodic;
+    double dx, dt, h, t[3], s[3], L, E_ext;
+    double rdx;  // 1 / dx when dx is a power of two (x / dx = x * rdx exactly), else 0
+};
+
+__device__ __forceinline__ Seg64 seg64(const SegC &S, const EnsC &e)
+{
+    int ex;
+    const bool pow2 = frexp(S.dx, &ex) == 0.5;  // dx = 2^(ex - 1)
+    return Seg64{S.gbase, S.cbase, S.ncells, S.periodic, S.dx, S.dt, S.h,
+                 {S.t[0], S.t[1], S.t[2]}, {S.s[0], S.s[1], S.s[2]}, e.L, e.E_ext,
+                 pow2 ? ldexp(1.0, 1 - ex) : 0.0};
+}
+
+// Cell index and fraction of x (as cell_of_x; the division is a multiplication, with the
+// same result, when dx is a power of two).
+__device__ __forceinline__ int64_t cell_of_x64(const Seg64 &G, double x, double &f)
+{
+    const double g = G.rdx != 0.0 ? x * G.rdx : x / G.dx;
+    double jf = floor(g);
+    if (jf > (double)(G.ncells - 1)) jf = (double)(G.ncells - 1);
+    if (!(jf >= 0.0)) jf = 0.0;
+    f = g - jf;
+    return (int64_t)jf;
+}
+
+// FP64 gather of PPT particles, every load issued before any is used: the field at each
+// particle (linear weighting of node E, plus E_ext).  A dead slot (x < 0) reads node 0.
+template <int PPT>
+__device__ __forceinline__ void gather64(const Dev &d, const Seg64 &G, const PS<true> (&p)[PPT], double (&Ep)[PPT])
+{
+    double f[PPT], E0[PPT], E1[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int64_t j = cell_of_x64(G, p[k].x, f[k]);
+        int64_t j1 = j + 1;
+        if (G.periodic && j1 == G.ncells) j1 = 0;
+        E0[k] = d.E[G.gbase + j];
+        E1[k] = d.E[G.gbase + j1];
+    }
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) Ep[k] = (1.0 - f[k]) * E0[k] + f[k] * E1[k] + G.E_ext;
+}
+
+// FP64 Boris push, position update and walls with the gathered field.
+__device__ __forceinline__ int p_push64(const Dev &d, const Seg64 &G, PS<true> &p, double Ep)
+{
+    boris<double>(G.h, G.t, G.s, Ep, p.vx, p.vy, p.vz);
+    double x = p.x + G.dt * p.vx;
+    const double L = G.L;
+    if (G.periodic) {
+        if (x < 0.0)
+            x += L;
+        else if (x >= L)
+            x -= L;
+        if (x >= L) x -= L;  // x + L rounded up to L
+        p.x = x;
+        if (!(x >= 0.0 && x < L)) {
+            atomicOr(d.err, (int)E_NONFINITE);
+            return 3;
+        }
+        return 0;
+    }
+    p.x = x;
+    if (x >= 0.0 && x < L) return 0;
+    // a non-finite position (from a non-finite field) leaves at the right wall and the
+    // step reports PIC_ENONFINITE
+    if (!(fabs(x) <= 1.0e300)) atomicOr(d.err, (int)E_NONFINITE);
+    return (x < 0.0) ? 1 : 2;
+}
+
 // Gather (linear weighting of node E), Boris push, position update, walls.
 // Returns 0 alive, 1 absorbed at the left wall, 2 at the right wall.
 template <bool F64>
@@ -147,33 +224,13 @@ __device__ __forceinline__ int p_push(const Dev &d, const SegC &S, const EnsC &e
         if (c >= S.ncells) return 2;
         return 0;
     } else {
-        double f;
-        const int64_t j = cell_of_x(S, p.x, f);
-        int64_t j1 = j + 1;
-        if (S.periodic && j1 == S.ncells) j1 = 0;
-        const double Ep = (1.0 - f) * d.E[S.gbase + j] + f * d.E[S.gbase + j1] + e.E_ext;
-        boris<double>(S.h, S.t, S.s, Ep, p.vx, p.vy, p.vz);
-        double x = p.x + S.dt * p.vx;
-        const double L = e.L;
-        if (S.periodic) {
-            if (x < 0.0)
-                x += L;
-            else if (x >= L)
-                x -= L;
-            if (x >= L) x -= L;  // x + L rounded up to L
-            p.x = x;
-            if (!(x >= 0.0 && x < L)) {
-                atomicOr(d.err, (int)E_NONFINITE);
-                return 3;
-            }
-            return 0;
-        }
-        p.x = x;
-        if (x >= 0.0 && x < L) return 0;
-        // a non-finite position (from a non-finite field) leaves at the right wall and the
-        // step reports PIC_ENONFINITE
-        if (!(fabs(x) <= 1.0e300)) atomicOr(d.err, (int)E_NONFINITE);
-        return (x < 0.0) ? 1 : 2;
+        const Seg64 G = seg64(S, e);
+        PS<true> q[1] = {p};
+        double Ep[1];
+        gather64<1>(d, G, q, Ep);
+        const int w = p_push64(d, G, q[0], Ep[0]);
+        p = q[0];
+        return w;
     }
 }
 
@@ -338,17 +395,17 @@ struct Win64 {
 };
 
 // Cloud-in-cell deposit of one particle per lane (FP64 form), called by every lane of the
-// wave: lanes hold consecutive slots, which after a sort mostly share a cell, so the wave
-// first sums the shares of each run of consecutive lanes with the same cell (a segmented
-// scan over the lanes) and the last lane of each run adds the run's two shares, into the
-// tile's LDS window when both nodes lie in it and with one FP64 atomic per node otherwise,
-// and its count to the sort histogram.  `cnt_only` skips the shares.
-__device__ __forceinline__ void wave_deposit64(const Dev &d, const SegC &S, int s, bool live, double x,
+// wave with the lane's cell (key < 0: none) and in-cell fraction: lanes hold consecutive
+// slots, which after a sort mostly share a cell, so the wave first sums the shares of each
+// run of consecutive lanes with the same cell (a segmented scan over the lanes) and the
+// last lane of each run adds the run's two shares, into the tile's LDS window when both
+// nodes lie in it and with one FP64 atomic per node otherwise, and its count to the sort
+// histogram.  `cnt_only` skips the shares.
+__device__ __forceinline__ void wave_deposit64(const Dev &d, const Seg64 &S, int s, int key, double f,
                                                bool hist, bool cnt_only, const Win64 &W = Win64{nullptr, 0, 0})
 {
     const int lane = lane_id();
-    double f = 0.0;
-    const int key = live ? (int)cell_of_x(S, x, f) : -1;
+    const bool live = key >= 0;
     double a = live ? 1.0 - f : 0.0, c = f;
     uint32_t n = live ? 1u : 0u;
     const int prev = __shfl_up(key, 1);
@@ -394,17 +451,20 @@ __device__ __forceinline__ void wave_deposit64(const Dev &d, const SegC &S, int 
 constexpr int kWin64 = 1024;
 
 template <int PPT>
-__device__ __forceinline__ void tile_deposit64(const Dev &d, const SegC &S, int s, const bool (&live)[PPT],
+__device__ __forceinline__ void tile_deposit64(const Dev &d, const Seg64 &S, int s, const bool (&live)[PPT],
                                                const PS<true> (&p)[PPT], bool hist, double *s_win, int *s_mm)
 {
     int mn = INT32_MAX, mx = -1;
+    int key[PPT];
+    double f[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        if (!live[k]) continue;
-        double f;
-        const int j = (int)cell_of_x(S, p[k].x, f);
-        mn = min(mn, j);
-        mx = max(mx, j);
+        f[k] = 0.0;
+        key[k] = live[k] ? (int)cell_of_x64(S, p[k].x, f[k]) : -1;
+        if (live[k]) {
+            mn = min(mn, key[k]);
+            mx = max(mx, key[k]);
+        }
     }
     mn = wave_min_i32(mn);
     mx = wave_max_i32(mx);
@@ -425,7 +485,7 @@ __device__ __forceinline__ void tile_deposit64(const Dev &d, const SegC &S, int 
     __syncthreads();
     const Win64 W{s_win, mn, n};
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) wave_deposit64(d, S, s, live[k], live[k] ? p[k].x : 0.0, hist, false, W);
+    for (int k = 0; k < PPT; ++k) wave_deposit64(d, S, s, key[k], f[k], hist, false, W);
     __syncthreads();
     double *Q = d.Qd + (int64_t)s * d.nodes_tot + S.gbase;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
