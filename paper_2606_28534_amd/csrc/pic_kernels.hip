@@ -28,13 +28,20 @@ namespace pic {
 // =======================================================================================
 constexpr int kMaxSeg = 512;
 
-__device__ __forceinline__ void sched_prefix(const Dev &d, int64_t tile, int64_t *s_tpre)
+__device__ __forceinline__ void sched_prefix(const Dev &d, int64_t tile, int64_t *s_tpre,
+                                             int64_t *s_lim = nullptr)
 {
-    // s_tpre[i] = sum over segments < i of ceil(n_slots / tile); nseg <= kMaxSeg.
+    // s_tpre[i] = sum over segments < i of ceil(n_slots / tile); nseg <= kMaxSeg.  With
+    // s_lim, also each segment's first slot and end of its slots in use, [2 i] and [2 i + 1].
     __shared__ int64_t s_tmp[kMaxSeg];
     for (int i = threadIdx.x; i < d.nseg; i += blockDim.x) {
         int64_t n = d.n_slots[i];
         s_tmp[i] = (n + tile - 1) / tile;
+        if (s_lim) {
+            const int64_t base = d.seg[i].base;
+            s_lim[2 * i] = base;
+            s_lim[2 * i + 1] = base + n;
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -160,12 +167,13 @@ __global__ void __launch_bounds__(256) k_particles(Dev d, int hist_rt)
     constexpr bool NEED_ID = COLL;
 
     __shared__ int64_t s_tpre[kMaxSeg + 1];
+    __shared__ int64_t s_lim[2 * kMaxSeg];       // each segment's slots in use, from LDS
     __shared__ double s_win[DEPO ? kWin64 : 1];  // the tile's deposit window
     __shared__ int s_mm[8];
 
     const int BLOCK = blockDim.x;
     const int64_t TILE = (int64_t)BLOCK * PPT;
-    sched_prefix(d, TILE, s_tpre);
+    sched_prefix(d, TILE, s_tpre, s_lim);
     const int64_t T = s_tpre[d.nseg];
     const int b = *d.cur;
     const int64_t step = *d.step;
@@ -210,9 +218,10 @@ __global__ void __launch_bounds__(256) k_particles(Dev d, int hist_rt)
             if (tseg >= 0 && (PUSH || COLL)) flush_tally(d, tseg, tal, COLL);
             tseg = sg;
         }
+        // the tile's slots from LDS, so its loads wait on nothing in global memory
         const int64_t lt = t - s_tpre[sg];
-        const int64_t first = S.base + lt * TILE;
-        const int64_t last = S.base + min((lt + 1) * TILE, d.n_slots[sg]);
+        const int64_t first = s_lim[2 * sg] + lt * TILE;
+        const int64_t last = min(first + TILE, s_lim[2 * sg + 1]);
 
         // every particle's loads are issued before any is tested, so the tile waits for
         // memory once
