@@ -1634,21 +1634,25 @@ __global__ void k_diag(Dev d, int sg, double *out /* [grid][2] */)
         if (_e != hipSuccess) return _e;                        \
     } while (0)
 
+// The persistent FP64 pass: stages that push or collide run on half the grid, the deposit
+// and histogram on all of it (on the 4e7-particle slab, push and collide were fastest at two
+// blocks per CU and the deposit at three to four; more blocks slowed every stage).
 template <int STAGES>
 static hipError_t launch_particles_t(const Dev &d, const Launch &L, hipStream_t s, int hist)
 {
+    const int grid = (STAGES & (ST_PUSH | ST_COLLIDE)) ? std::max(8, L.grid / 16 * 8) : L.grid;
     switch (L.ppt) {
     case 1:
-        hipLaunchKernelGGL((k_particles<STAGES, 1>), dim3(L.grid), dim3(L.block), 0, s, d, hist);
+        hipLaunchKernelGGL((k_particles<STAGES, 1>), dim3(grid), dim3(L.block), 0, s, d, hist);
         break;
     case 2:
-        hipLaunchKernelGGL((k_particles<STAGES, 2>), dim3(L.grid), dim3(L.block), 0, s, d, hist);
+        hipLaunchKernelGGL((k_particles<STAGES, 2>), dim3(grid), dim3(L.block), 0, s, d, hist);
         break;
     case 8:
-        hipLaunchKernelGGL((k_particles<STAGES, 8>), dim3(L.grid), dim3(L.block), 0, s, d, hist);
+        hipLaunchKernelGGL((k_particles<STAGES, 8>), dim3(grid), dim3(L.block), 0, s, d, hist);
         break;
     default:
-        hipLaunchKernelGGL((k_particles<STAGES, 4>), dim3(L.grid), dim3(L.block), 0, s, d, hist);
+        hipLaunchKernelGGL((k_particles<STAGES, 4>), dim3(grid), dim3(L.block), 0, s, d, hist);
         break;
     }
     LAUNCH_CHECK();
