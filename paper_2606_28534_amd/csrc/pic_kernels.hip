@@ -77,7 +77,7 @@ __device__ __forceinline__ int seg_of_tile(const int64_t *s_tpre, int nseg, int6
 // cell changes, births spread over the domain, atomics on shared nodes) simply take fewer,
 // so the launch ends when the work does, not when the slowest static share does.  A queue
 // counter is the number of tiles handed out; the last block to finish resets them.
-constexpr int kGrabTiles = 2;
+constexpr int kGrabTiles = 4;
 constexpr int kTileQueues = 8;
 
 // First tile of the next grab from queue x (a value >= the queue's end means empty).
