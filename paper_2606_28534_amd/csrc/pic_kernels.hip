@@ -8,7 +8,7 @@
 // bits, so its separate-stage verbs and its fused step run the same per-particle code.  It
 // streams each segment's slots once, coalesced, with persistent blocks that take tiles from
 // per-XCD queues and steal from the others when theirs is empty (load balancing inside the
-// GPU), and deposits with FP64 atomics.
+// GPU), and deposits with FP64 atomics, each tile's shares merged first in an LDS window.
 #include <type_traits>
 
 #include "pic.h"
@@ -151,7 +151,8 @@ __device__ void flush_tally(const Dev &d, int seg, Tally &t, bool want_vmax)
 // =======================================================================================
 // The FP64 particle pass (the FP32 form runs in k_pass32).  A persistent grid walks the
 // tiles of all segments; each stage is optional, so the same kernel serves the fused pass
-// and the separate stages.  The deposit goes straight to the int64 node array.
+// and the separate stages.  The deposit adds each tile's shares into an LDS window of FP64
+// nodes, then each touched node into the FP64 node array with one atomic.
 // =======================================================================================
 enum Stage : int { ST_PUSH = 1, ST_COLLIDE = 2, ST_DEPOSIT = 4, ST_HIST = 8 };
 
