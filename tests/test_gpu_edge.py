@@ -214,3 +214,29 @@ def test_nonfinite_step_is_reported(pic, prec):
         sim.step(1)
     assert ei.value.code == pic.PIC_ENONFINITE
     sim.close()
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_fp64_grid_sizes_leave_results_unchanged(pic, fused):
+    """The persistent FP64 pass at 16 and 64 blocks (its push and collide stages at half of
+    that, so a few blocks steal almost every tile, and one tile can hold shares of cells
+    beyond its LDS window) against the default grid: counts exact, particles and field to
+    the rounding of the FP64 deposit atomics, whose order follows the schedule."""
+    e = synth.ensemble(3000, 30, collisions=True, seed=77, sort_every=5)
+    e["ngs_el"], e["ngs_iz"] = 0.1, 0.2
+    for sp in e["species"]:
+        sp["capacity"] *= 2
+    ref = pic.Sim(work_of(e, "fp64"), fused=fused)
+    ref.step(12)
+    for grid in (16, 64):
+        sim = pic.Sim(work_of(e, "fp64"), fused=fused, grid=grid)
+        sim.step(12)
+        a, b = sim.diag(), ref.diag()
+        for key in ("count", "coll", "created", "wall_count", "pushes"):
+            assert a[key] == b[key], (grid, key, a[key], b[key])
+        for s in range(2):
+            compare_particles(sim.particles(0, s), ref.particles(0, s), e["dx"], True, vtol=1e-9, xtol=1e-9)
+        E, Er = sim.grid()["E"], ref.grid()["E"]
+        assert np.max(np.abs(E - Er)) <= 1e-9 * np.max(np.abs(Er)), grid
+        sim.close()
+    ref.close()
