@@ -152,8 +152,9 @@ typedef struct {
     int32_t fused;       /* 0: one kernel per stage; 1: fused particle pass + HIP graph    */
     int32_t block;       /* threads per block of the FP64 particle kernels (64, 128 or
                             256); 0 = default 256                                           */
-    int32_t grid;        /* persistent blocks of the FP64 deposit (its push and collide
-                            stages take half); 0 = default                                 */
+    int32_t grid;        /* blocks of the FP64 particle kernels: the deposit and histogram
+                            take this many, push and collide half, the sort scatter eight
+                            times as many; 0 = default (1024)                              */
     int32_t window;      /* widest span of cells a tile deposits (and, on sort steps,
                             counts) through LDS, in [16, 4096]; a tile's window covers only
                             its own cells, so this bounds LDS per block; 0 = default 2048   */

@@ -169,7 +169,7 @@ __global__ void __launch_bounds__(256) k_particles(Dev d, int hist_rt)
 
     __shared__ int64_t s_tpre[kMaxSeg + 1];
     __shared__ int64_t s_lim[2 * kMaxSeg];       // each segment's slots in use, from LDS
-    __shared__ double s_win[DEPO ? kWin64 : 1];  // the tile's deposit window
+    __shared__ double s_win[(DEPO || HISTC) ? kWin64 : 1];  // the tile's deposit (or count) window
     __shared__ int s_mm[8];
 
     const int BLOCK = blockDim.x;
@@ -338,12 +338,7 @@ __global__ void __launch_bounds__(256) k_particles(Dev d, int hist_rt)
         if constexpr (DEPO) {
             tile_deposit64<PPT>(d, G, s, live, p, hist, s_win, s_mm);
         } else if (HISTC) {
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                double f = 0.0;
-                const int key = live[k] ? (int)cell_of_x64(G, p[k].x, f) : -1;
-                wave_deposit64(d, G, s, key, f, hist, true);
-            }
+            tile_deposit64<PPT, true>(d, G, s, live, p, true, s_win, s_mm);
         }
     }
         __syncthreads();
@@ -1479,11 +1474,12 @@ __global__ void __launch_bounds__(256) k_sort_scatter(Dev d, int W)
     extern __shared__ unsigned long long s_dyn[];
     uint32_t *sCnt = (uint32_t *)s_dyn;   // [W] counts, then bases
     __shared__ int64_t s_tpre[kMaxSeg + 1];
+    __shared__ int64_t s_lim[2 * kMaxSeg];
     __shared__ int s_min;
     __shared__ bool s_last;
     const int BLOCK = blockDim.x;
     const int64_t TILE = (int64_t)BLOCK * PPT;
-    sched_prefix(d, TILE, s_tpre);
+    sched_prefix(d, TILE, s_tpre, s_lim);
     const int64_t T = s_tpre[d.nseg];
     int64_t t0, t1;
     block_run(T, t0, t1);
@@ -1492,23 +1488,36 @@ __global__ void __launch_bounds__(256) k_sort_scatter(Dev d, int W)
     for (int i = threadIdx.x; i < W; i += BLOCK) sCnt[i] = 0u;
     __syncthreads();
     for (int64_t t = t0; t < t1; ++t) {
-        const int sg = seg_of_tile(s_tpre, d.nseg, t);
+        const int sg = __builtin_amdgcn_readfirstlane(seg_of_tile(s_tpre, d.nseg, t));
         const SegC &S = d.seg[sg];
         const int64_t lt = t - s_tpre[sg];
-        const int64_t first = S.base + lt * TILE;
-        const int64_t last = S.base + min((lt + 1) * TILE, d.n_slots[sg]);
+        const int64_t first = s_lim[2 * sg] + lt * TILE;
+        const int64_t last = min(first + TILE, s_lim[2 * sg + 1]);
+        // the whole particle is loaded up front (every load in flight at once) and kept in
+        // registers until its store to the other buffer
+        double xv[PPT], vx[PPT], vy[PPT], vz[PPT];
+        uint32_t idv[PPT];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int64_t i = first + (int64_t)k * BLOCK + threadIdx.x;
+            xv[k] = -1.0;
+            if (i < last) {
+                xv[k] = d.x[b][i];
+                vx[k] = d.dvx[b][i];
+                vy[k] = d.dvy[b][i];
+                vz[k] = d.dvz[b][i];
+                idv[k] = d.id[b][i];
+            }
+        }
+        const Seg64 G = seg64(S, d.ens[S.ens]);
+        const int64_t sbase = S.base, scap = S.cap, scb = S.cbase, sstart = d.segstart[sg];
         int cell[PPT];
         uint32_t rank[PPT];
         int mn = INT32_MAX;
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-            const int64_t i = first + (int64_t)k * BLOCK + threadIdx.x;
-            cell[k] = kDead;
-            if (i < last) {
-                const double x = d.x[b][i];
-                double f;
-                cell[k] = (x >= 0.0) ? (int)cell_of_x(S, x, f) : kDead;
-            }
+            double f;
+            cell[k] = (xv[k] >= 0.0) ? (int)cell_of_x64(G, xv[k], f) : kDead;
             if (cell[k] != kDead) mn = min(mn, cell[k]);
         }
         mn = wave_min_i32(mn);
@@ -1543,42 +1552,45 @@ __global__ void __launch_bounds__(256) k_sort_scatter(Dev d, int W)
         // reserve runs: counts -> global bases
         for (int i = threadIdx.x; i < W; i += BLOCK) {
             const uint32_t c = sCnt[i];
-            if (c) sCnt[i] = atomicAdd(d.cursor + S.cbase + base + i, c);
+            if (c) sCnt[i] = atomicAdd(d.cursor + scb + base + i, c);
         }
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             if (cell[k] == kDead) continue;
-            const int64_t i = first + (int64_t)k * BLOCK + threadIdx.x;
             uint32_t pos;
             if (rank[k] != 0xFFFFFFFFu)
                 pos = sCnt[cell[k] - base] + rank[k];
             else
-                pos = atomicAdd(d.cursor + S.cbase + cell[k], 1u);
-            const int64_t o = S.base + (int64_t)pos - d.segstart[sg];
-            if (o < S.base || o >= S.base + S.cap) {  // histogram and slots disagree
+                pos = atomicAdd(d.cursor + scb + cell[k], 1u);
+            const int64_t o = sbase + (int64_t)pos - sstart;
+            if (o < sbase || o >= sbase + scap) {  // histogram and slots disagree
                 atomicOr(d.err, (int)E_CAP_PART);
                 continue;
             }
-            d.x[nb][o] = d.x[b][i];
-            d.dvx[nb][o] = d.dvx[b][i];
-            d.dvy[nb][o] = d.dvy[b][i];
-            d.dvz[nb][o] = d.dvz[b][i];
-            d.id[nb][o] = d.id[b][i];
+            d.x[nb][o] = xv[k];
+            d.dvx[nb][o] = vx[k];
+            d.dvy[nb][o] = vy[k];
+            d.dvz[nb][o] = vz[k];
+            d.id[nb][o] = idv[k];
         }
         __syncthreads();
         for (int i = threadIdx.x; i < W; i += BLOCK) sCnt[i] = 0u;
         __syncthreads();
     }
-    __threadfence();
+    // The last block sets the slot counts from the cursors, which the other blocks changed
+    // with atomics; it reads them with device-scope atomic loads (which see every block's
+    // atomics across the XCDs), so no block needs a device-scope fence: on gfx950 each such
+    // fence writes back its XCD's L2, which cost this kernel more the more blocks it had.
     __syncthreads();
     if (threadIdx.x == 0) s_last = (atomicAdd(d.ticket + 3, 1u) == gridDim.x - 1);
     __syncthreads();
     if (!s_last) return;
-    __threadfence();
     for (int sg = threadIdx.x; sg < d.nseg; sg += BLOCK) {
         const SegC &S = d.seg[sg];
-        const int64_t n = (int64_t)d.cursor[S.cbase + S.ncells - 1] - d.segstart[sg];
+        const uint32_t end =
+            __hip_atomic_load(d.cursor + S.cbase + S.ncells - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int64_t n = (int64_t)end - d.segstart[sg];
         d.n_slots[sg] = min(max(n, (int64_t)0), S.cap);
     }
     __syncthreads();
@@ -1845,8 +1857,10 @@ hipError_t launch_sort(const Dev &d, bool f64, const Launch &L, hipStream_t s)
     hipError_t e = launch_sort_prepare(d, s);
     if (e != hipSuccess) return e;
     if (!f64) return launch_sort32_scatter(d, L.sort_ppt, L.window, s, d.cap_tot, L.sort_nt != 0);
+    // the scatter's static runs of tiles are short: 8x the pass's persistent grid (a sweep
+    // from 1/2x to 8x on the 4e7-particle slab: 1.33, 1.07, 0.92, 0.85, 0.83 ms)
     const size_t lds = (size_t)L.window * 4;
-    hipLaunchKernelGGL((k_sort_scatter<4>), dim3(L.grid), dim3(L.block), lds, s, d, L.window);
+    hipLaunchKernelGGL((k_sort_scatter<4>), dim3(8 * L.grid), dim3(L.block), lds, s, d, L.window);
     LAUNCH_CHECK();
     return hipSuccess;
 }

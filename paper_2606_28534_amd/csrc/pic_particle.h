@@ -440,17 +440,25 @@ __device__ __forceinline__ void wave_deposit64(const Dev &d, const Seg64 &S, int
             unsafeAtomicAdd(Q + j1, c);
         }
     }
-    if (hist) atomicAdd(d.cellcnt + S.cbase + key, n);
+    if (hist) {
+        const int r = key - W.base;
+        if (cnt_only && r >= 0 && r < W.n)
+            unsafeAtomicAdd(W.w + r, (double)n);  // a count window: small exact integers
+        else
+            atomicAdd(d.cellcnt + S.cbase + key, n);
+    }
 }
 
 // Deposit of one FP64 tile through an LDS window over the nodes of its cells (at most
 // kWin64 nodes from the lowest cell of the tile; shares beyond it go to HBM atomics): the
 // window is cleared, the waves add their merged runs into it, and each nonzero node is
-// added to the node array with one FP64 atomic.  Called by every thread of the block;
-// `s_mm` holds 8 ints.  The next call's barriers order its clearing after this flush.
+// added to the node array with one FP64 atomic.  With COUNT the window holds the sort
+// histogram's counts per cell instead (the histogram-only pass), each touched cell added
+// with one atomic.  Called by every thread of the block; `s_mm` holds 8 ints.  The next
+// call's barriers order its clearing after this flush.
 constexpr int kWin64 = 1024;
 
-template <int PPT>
+template <int PPT, bool COUNT = false>
 __device__ __forceinline__ void tile_deposit64(const Dev &d, const Seg64 &S, int s, const bool (&live)[PPT],
                                                const PS<true> (&p)[PPT], bool hist, double *s_win, int *s_mm)
 {
@@ -480,20 +488,25 @@ __device__ __forceinline__ void tile_deposit64(const Dev &d, const Seg64 &S, int
         mn = min(mn, s_mm[i]);
         mx = max(mx, s_mm[4 + i]);
     }
-    const int n = mx >= 0 ? min(mx - mn + 2, kWin64) : 0;  // nodes mn .. mx + 1
+    // nodes mn .. mx + 1 (cells mn .. mx for the counts)
+    const int n = mx >= 0 ? min(mx - mn + (COUNT ? 1 : 2), kWin64) : 0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) s_win[i] = 0.0;
     __syncthreads();
     const Win64 W{s_win, mn, n};
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) wave_deposit64(d, S, s, key[k], f[k], hist, false, W);
+    for (int k = 0; k < PPT; ++k) wave_deposit64(d, S, s, key[k], f[k], COUNT || hist, COUNT, W);
     __syncthreads();
     double *Q = d.Qd + (int64_t)s * d.nodes_tot + S.gbase;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         const double v = s_win[i];
         if (v == 0.0) continue;
-        int node = mn + i;
-        if (S.periodic && node >= S.ncells) node -= S.ncells;
-        unsafeAtomicAdd(Q + node, v);
+        if constexpr (COUNT) {
+            atomicAdd(d.cellcnt + S.cbase + mn + i, (uint32_t)v);
+        } else {
+            int node = mn + i;
+            if (S.periodic && node >= S.ncells) node -= S.ncells;
+            unsafeAtomicAdd(Q + node, v);
+        }
     }
 }
 
