@@ -296,7 +296,8 @@ int pic_get_particles(pic_ctx *ctx, int32_t ens, int32_t species, pic_particles 
 int pic_get_slots(pic_ctx *ctx, int32_t ens, int32_t species, int64_t first, int64_t count,
                   pic_particles out, void *stream);
 
-/* Replace the particles of (ens, species) with `count` host particles (x in [0, L));
+/* Replace the particles of (ens, species) with `count` host particles (x in [0, L); in the
+ * FP32 form an x whose x / dx rounds up to N goes to the top of the last cell);
  * next_id is the id the next created particle of this species receives (ignored for the
  * neutral set, species 2, whose ids are those of the ions they came from). */
 int pic_set_particles(pic_ctx *ctx, int32_t ens, int32_t species, pic_particles in,

@@ -1024,7 +1024,10 @@ int set_neutrals(pic_ctx *c, int32_t ens, pic_particles in, int64_t count, hipSt
             o = 0.0f;
             cl += 1;
         }
-        if (cl >= E.ncells) return fail(c, PIC_EINVAL, "x rounds to L");
+        if (cl >= E.ncells) {  // x / dx rounded up to N: the last cell, as the device converts
+            cl = (int)E.ncells - 1;
+            o = 0x1.fffffep-1f;
+        }
         cell[i] = cl;
         off[i] = o;
         vx[i] = (float)in.vx[i];
@@ -1190,7 +1193,10 @@ int pic_set_particles(pic_ctx *c, int32_t ens, int32_t species, pic_particles in
                 o = 0.0f;
                 cl += 1;
             }
-            if (cl >= S.ncells) return fail(c, PIC_EINVAL, "x rounds to L");
+            if (cl >= S.ncells) {  // x / dx rounded up to N: the last cell, as the device converts
+                cl = S.ncells - 1;
+                o = 0x1.fffffep-1f;
+            }
             cell[i] = cl;
             off[i] = o;
             vx[i] = (float)in.vx[i];
