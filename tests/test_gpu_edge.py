@@ -240,3 +240,31 @@ def test_fp64_grid_sizes_leave_results_unchanged(pic, fused):
         assert np.max(np.abs(E - Er)) <= 1e-9 * np.max(np.abs(Er)), grid
         sim.close()
     ref.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_electrons_only_with_ionisation(pic, prec):
+    """One species (no ion segment) with collisions: an ionisation creates only the new
+    electron, and three steps (the births of each step placed before the next) match the
+    oracle: collision and creation counts exact in FP64 and within a few threshold flips in
+    FP32, particles by id (FP64), the charge of every particle accounted for."""
+    e = synth.ensemble(400, 50, collisions=True, nspecies=1, seed=5)
+    e["ngs_el"], e["ngs_iz"] = 0.1, 0.4
+    e["species"][0]["capacity"] *= 3
+    sim = pic.Sim(work_of(e, prec), fused=(prec == "fp32"))
+    o = oracle.Oracle(e)
+    sim.step(3)
+    o.step(3)
+    gd, od = sim.diag(), o.diag()
+    slack = 0 if prec == "fp64" else 4
+    for k in range(3):
+        assert abs(gd["coll"][k] - od["coll"][k]) <= slack, (k, gd["coll"], od["coll"])
+    assert abs(gd["created"][0] - od["created"][0]) <= slack
+    assert gd["created"][0] > 0 and gd["coll"][1] > 0
+    assert gd["wall_count"] == od["wall_count"]
+    n0 = 400 * 50
+    absorbed = gd["wall_count"][0][0] + gd["wall_count"][1][0]
+    assert gd["count"][0] + absorbed == n0 + gd["created"][0]
+    if prec == "fp64":
+        compare_particles(sim.particles(0, 0), o.particles(0), e["dx"], True, vtol=1e-11, xtol=1e-10)
+    sim.close()
