@@ -302,3 +302,31 @@ def test_periodic_collisional_steps_match_oracle(pic, prec):
         for s in range(2):
             compare_particles(sim.particles(0, s), o.particles(s), e["dx"], True, vtol=1e-10, xtol=1e-10)
     sim.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_external_field_in_collisional_steps(pic, prec):
+    """A uniform external field E_ext in a bounded collisional run: the push adds it at the
+    gather and the null-collision bound (R11) adds |q/m| dt |E_ext| to the speed bound; four
+    fused steps against the oracle (bound, counts, particles in FP64)."""
+    e = synth.ensemble(900, 30, collisions=True, seed=31, E_ext=0.3)
+    e["ngs_el"], e["ngs_iz"] = 0.1, 0.2
+    for sp in e["species"]:
+        sp["capacity"] *= 2
+    sim = pic.Sim(work_of(e, prec), fused=True)
+    o = oracle.Oracle(e)
+    sim.step(4)
+    o.step(4)
+    gd, od = sim.diag(), o.diag()
+    nu_o, _ = o.last_numax()
+    assert np.allclose(gd["numax"], nu_o, rtol=(1e-12 if prec == "fp64" else 1e-5), atol=0)
+    slack = 0 if prec == "fp64" else 4
+    for k in range(3):
+        assert abs(gd["coll"][k] - od["coll"][k]) <= slack, (k, gd["coll"], od["coll"])
+    assert gd["wall_count"] == od["wall_count"]
+    for s in range(2):
+        assert abs(gd["count"][s] - od["count"][s]) <= slack
+    if prec == "fp64":
+        for s in range(2):
+            compare_particles(sim.particles(0, s), o.particles(s), e["dx"], True, vtol=1e-10, xtol=1e-10)
+    sim.close()
