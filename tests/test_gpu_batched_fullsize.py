@@ -219,3 +219,29 @@ def test_large_share_one_percent_slice_matches_oracle(pic):
         assert abs(gd["coll"][k] - od["coll"][k]) <= 5, (k, gd["coll"], od["coll"])
     g, r = sim.grid(), o.grid()
     assert rel(g["E"], r["E"]) <= 1e-5
+
+
+def test_maximum_ensemble_count_equals_each_ensemble_alone(pic):
+    """PIC_MAX_ENSEMBLES (256) small uneven ensembles with collisions in one run (every
+    staged table of the births placement and the candidate kernel at its largest): twelve
+    fused steps, then a few ensembles checked bit for bit against each run alone."""
+    work = synth.c3_batched(n_ens=256, seed=5, scale=0.004)
+    for e in work["ensembles"]:
+        e["ngs_el"], e["ngs_iz"] = 0.05, 0.1
+        for sp in e["species"]:
+            sp["capacity"] *= 2
+    batch = pic.Sim(work, fused=True)
+    batch.step(12)
+    for k in (0, 101, 255):
+        alone = pic.Sim(_single(work, k), fused=True)
+        alone.step(12)
+        for s in range(2):
+            a, b = by_id(batch.particles(k, s)), by_id(alone.particles(0, s))
+            for key in ("id", "x", "vx", "vy", "vz"):
+                assert np.array_equal(a[key], b[key]), (k, s, key)
+        da, db = batch.diag(k), alone.diag(0)
+        for key in ("count", "coll", "created", "wall_count", "pushes"):
+            assert da[key] == db[key], (k, key)
+        alone.close()
+    assert sum(sum(batch.diag(k)["created"]) for k in range(0, 256, 15)) > 0
+    batch.close()
