@@ -225,6 +225,44 @@ def large_run(pic, shape, seed, warmup, steps):
             "frac_of_hbm_peak_46.8B": round((B_ALG_PARTICLE + 48.0 / 10) * pushes / (t1 - t0) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def correctness_configs_run(pic):
+    """Time only, for the two correctness configurations: the plain FP64 form on 256 cells x
+    100 ppc x 2 species with collisions (the full 1000-step run, eager), and one adjoint
+    window of the 2048-cell, 200-ppc Langmuir workload (200 steps, a checkpoint every 20,
+    forward, reverse sweep and gradients)."""
+    import torch
+
+    import synth
+
+    out = {}
+    w = synth.c1_plain_small(seed=1)
+    sim = pic.Sim(w, fused=False)
+    sim.step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(w["steps"] - 1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sim.close()
+    out["plain_small_256cells"] = {"steps": w["steps"] - 1, "ms_per_step": (t1 - t0) / (w["steps"] - 1) * 1e3,
+                                   "form": "FP64, one kernel per stage, eager"}
+    w = synth.c4_langmuir()
+    sim = pic.Sim(w, fused=True)
+    sim.adjoint_window(w["steps"], 20)  # warm: scratch, graphs of the recompute
+    sim.close()
+    sim = pic.Sim(w, fused=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.adjoint_window(w["steps"], 20)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    out["adjoint_window_langmuir"] = {"steps": w["steps"], "checkpoint_every": 20, "ms_per_window": (t1 - t0) * 1e3}
+    return out
+
+
 def stream_copy_gbs(torch, pic, gib=4.0, reps=10):
     """Device-to-device copy bandwidth on the same GPU (read + write bytes per second), for
     context next to the HBM peak: a plain torch copy, and the library's copy with the
@@ -275,6 +313,8 @@ def main():
     ap.add_argument("--no-walls-variant", action="store_true")
     ap.add_argument("--no-sheath-cases", action="store_true")
     ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the timings of the two correctness configurations")
     ap.add_argument("--case", choices=["sheath", "recycling", "source", "large", "batched"], default="sheath",
                     help="main workload: the sheath slab (default), one of the paper's two "
                          "sheath cases, the 1e9-particle share or the 64 batched ensembles "
@@ -419,6 +459,10 @@ def main():
     if not args.no_large:
         large = large_run(pic, shape, args.seed, 10, 20)
 
+    small = None
+    if not args.no_small:
+        small = correctness_configs_run(pic)
+
     stream = None
     if not args.no_stream:
         stream = stream_copy_gbs(torch, pic)
@@ -458,6 +502,7 @@ def main():
         "floating_walls_smoothed": walls,
         "sheath_cases": cases,
         "large": large,
+        "correctness_configs": small,
         "stream_copy": stream,
         "cpu_baseline": cpu,
     }
