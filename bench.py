@@ -165,34 +165,43 @@ def walls_variant_run(pic, shape, steps, seed, smooth):
             "ms_per_step": (t1 - t0) / steps * 1e3, "boundary": "floating", "smooth": smooth}
 
 
-def sheath_case_run(pic, shape, case, seed, warmup, steps):
+def sheath_case_run(pic, shape, case, seed, warmup, steps, refill=0):
     """The paper's two sheath cases at 1e5 cells: "recycling" is the uniform load with its
     three species (4.0e7 charged particles, ions recycled into neutrals at floating walls);
     "source" is the initially empty slab filled by 2e4 electron-ion pairs per step in its
     left half (measured after `warmup` steps of filling).  Same fused graph and launch
-    shape as the main workload."""
+    shape as the main workload.  With `refill`, the same run goes on filling until step
+    `refill` and is timed again there (entry "filled")."""
     import torch
 
     import synth
 
     work = synth.c6_sheath_recycling(seed=seed) if case == "recycling" else synth.c7_sheath_source(seed=seed)
     sim = pic.Sim(work, fused=True, **shape)
+
+    def timed(after):
+        sim.prepare(steps)
+        torch.cuda.synchronize()
+        d0 = sim.diag()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        d1 = sim.diag()
+        return {"value": (d1["pushes"] - d0["pushes"]) / (t1 - t0), "unit": "particle-pushes/s",
+                "steps": steps, "after_steps": after, "ms_per_step": (t1 - t0) / steps * 1e3,
+                "charged_particles": sum(d1["count"]), "neutrals": d1["neutral_count"],
+                "recycled": d1["recycled"], "sourced": d1["sourced"]}
+
     sim.step(warmup)
-    sim.prepare(steps)
-    torch.cuda.synchronize()
-    d0 = sim.diag()
-    t0 = time.perf_counter()
-    sim.step(steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    d1 = sim.diag()
+    out = timed(warmup)
+    if refill > warmup + steps:
+        sim.step(refill - warmup - steps)
+        out["filled"] = timed(refill)
     sim.close()
     del sim
     torch.cuda.empty_cache()
-    return {"value": (d1["pushes"] - d0["pushes"]) / (t1 - t0), "unit": "particle-pushes/s",
-            "steps": steps, "after_steps": warmup, "ms_per_step": (t1 - t0) / steps * 1e3,
-            "charged_particles": sum(d1["count"]), "neutrals": d1["neutral_count"],
-            "recycled": d1["recycled"], "sourced": d1["sourced"]}
+    return out
 
 
 def large_run(pic, shape, seed, warmup, steps):
@@ -453,7 +462,8 @@ def main():
     cases = None
     if not args.no_sheath_cases:
         cases = {"recycling": sheath_case_run(pic, shape, "recycling", args.seed, 20, args.batched_steps),
-                 "source": sheath_case_run(pic, shape, "source", args.seed, 200, args.batched_steps)}
+                 "source": sheath_case_run(pic, shape, "source", args.seed, 200, args.batched_steps,
+                                           refill=800)}
 
     large = None
     if not args.no_large:
