@@ -287,6 +287,7 @@ size_t carve(const Plan &P, char *base, Dev &d)
     d.fe = c.take<double>(P.nens);
     d.numax = c.take<double>(P.nseg);
     d.pnull = c.take<double>(P.nseg);
+    d.vmred = c.take<double>(P.nseg);
     d.vmax2 = c.take<unsigned long long>(2 * kCntStripes * P.nseg);
     d.vcur = c.take<int32_t>(1);
     d.cnt = c.take<unsigned long long>((int64_t)kCntStripes * P.nseg * C_NCNT);

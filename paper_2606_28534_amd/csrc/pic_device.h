@@ -130,6 +130,9 @@ struct Dev {
     double *part;             // [nchunks_tot][P_NPART]
     double *emax, *fe;        // [nens]
     double *numax, *pnull;    // [nseg]
+    // the largest |v|^2 of each segment over the stripes of the speed maxima the next bound
+    // uses, reduced by extra blocks of the first solve kernel of the fused step
+    double *vmred;            // [nseg]
     // tallies
     unsigned long long *vmax2;  // [2][kCntStripes][nseg] max |v|^2 as double bits
     int32_t *vcur;            // [1] which vmax2 half holds the current maxima
@@ -304,21 +307,33 @@ __device__ __forceinline__ BirthBuf birth_buf(const Dev &d, int parity)
 // |E_ext|)) (1 + 2^-16) and P_null = 1 - exp(-nu_max dt).  Called by a whole wave (lanes
 // read the stripes); every lane gets the result.
 // `half` is the vmax2 half holding the current maxima and `emax` the ensemble's max |E|.
-__device__ __forceinline__ void seg_params(const Dev &d, int sg, int half, double emax, double &numax,
-                                           double &pnull)
+// The largest |v|^2 of segment `sg` in one half of the striped speed maxima (a whole wave
+// reads the stripes; every lane gets the result).
+__device__ __forceinline__ double seg_vmax2(const Dev &d, int sg, int half)
 {
-    const SegC &S = d.seg[sg];
-    const EnsC &e = d.ens[S.ens];
     double m2 = 0.0;  // squared speeds are non-negative: bit patterns order as integers
     for (int st = lane_id(); st < kCntStripes; st += kWave)
         m2 = fmax(m2, __longlong_as_double((long long)d.vmax2[((int64_t)half * kCntStripes + st) * d.nseg + sg]));
-    m2 = wave_max_f64(m2);
+    return wave_max_f64(m2);
+}
+
+// The bound itself, from the largest |v|^2 and the max |E| (one thread suffices).
+__device__ __forceinline__ void seg_bound(const SegC &S, const EnsC &e, double m2, double emax, double &numax,
+                                          double &pnull)
+{
     const double vmax = __dsqrt_rn(m2);
     double Vb = __dadd_rn(vmax, __dmul_rn(__dmul_rn(S.qm_abs, e.dt), __dadd_rn(emax, fabs(e.E_ext))));
     // reading R26: the relative speed to a sampled neutral exceeds the ion's by at most vn_max
     if (S.species == 1) Vb = __dadd_rn(Vb, e.vn_max);
     numax = __dmul_rn(__dmul_rn(S.ngsT, Vb), kNuSafety);
     pnull = 1.0 - exp(-__dmul_rn(numax, e.dt));
+}
+
+__device__ __forceinline__ void seg_params(const Dev &d, int sg, int half, double emax, double &numax,
+                                           double &pnull)
+{
+    const SegC &S = d.seg[sg];
+    seg_bound(S, d.ens[S.ens], seg_vmax2(d, sg, half), emax, numax, pnull);
 }
 
 // Record a birth of parent `pid` (its bit and its group count) in one half.

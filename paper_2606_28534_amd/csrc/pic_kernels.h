@@ -33,7 +33,8 @@ hipError_t launch_vmax(const Dev &d, bool f64, hipStream_t s);
 hipError_t launch_zero_q(const Dev &d, bool f64, hipStream_t s);
 // The field solve; with `with_births` its two kernels also scan and place the previous
 // step's births in extra blocks (needs births_fit_solve: the one-block group scan); with
-// `with_params` the second kernel's last block computes the null-collision bound.
+// `with_params` extra blocks of the first kernel reduce the striped speed maxima per segment
+// and the second kernel's last block computes the null-collision bound from them.
 hipError_t launch_solve(const Dev &d, bool f64, int64_t nchunks, bool zero_q, hipStream_t s,
                         bool with_births = false, bool with_params = false);
 bool births_fit_solve(const Dev &d);

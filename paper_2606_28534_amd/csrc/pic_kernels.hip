@@ -599,13 +599,33 @@ __device__ void group_scan_body(const Dev &d);
 template <bool F64>
 __device__ void birth_place_body(const Dev &d, int deferred, int advance, int bid, int nblk);
 
+// For the null-collision bound (R11) that the second solve kernel's last block computes: the
+// largest |v|^2 of each segment over the stripes of the half the bound uses, one wave per
+// segment (a block of kSolveThreads covers kSolveThreads / kWave segments), so that block
+// reads one value per segment.  That half holds the previous step's maxima: the current
+// one, or with the previous step's births still to be placed (`pending`), the other one,
+// which their placement makes current.
+__device__ void vmax_reduce_body(const Dev &d, int pending, int bid)
+{
+    const int half = pending ? 1 - *d.vcur : *d.vcur;
+    const int sg = bid * (kSolveThreads / kWave) + (int)threadIdx.x / kWave;
+    if (sg >= d.nseg) return;
+    const double m2 = seg_vmax2(d, sg, half);
+    if (lane_id() == 0) d.vmred[sg] = m2;
+}
+
 // Blocks [0, nchunks) solve; with `scan`, one more block scans the group counts of the
-// previous step's births (independent data), so that scan costs no launch of its own.
+// previous step's births (independent data), so that scan costs no launch of its own;
+// `nred` more blocks reduce the speed maxima for the null-collision bound (vmax_reduce_body).
 template <bool F64>
-__global__ void __launch_bounds__(kSolveThreads) k_solve1(Dev d, int nchunks, int scan)
+__global__ void __launch_bounds__(kSolveThreads) k_solve1(Dev d, int nchunks, int scan, int nred)
 {
     if ((int)blockIdx.x >= nchunks) {
-        if (scan) group_scan_body(d);
+        const int r = (int)blockIdx.x - nchunks - scan;
+        if (r < 0)
+            group_scan_body(d);
+        else if (r < nred)
+            vmax_reduce_body(d, scan, r);
         return;
     }
     __shared__ double s_buf[8];
@@ -720,20 +740,13 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve1(Dev d, int nchunks, in
 
 // Reading R11: per-segment null-collision bound from the current max speed and max field.
 // One wave per segment (lanes read the striped speed maxima); every lane gets the result.
-// With `coherent`, the current half and max |E| were written by other blocks of the same
-// launch (the last block of the second solve kernel computes the bound), so they are read
-// with atomics, which see every block's atomic updates without a fence.
-__device__ void compute_params(const Dev &d, bool coherent)
+__device__ void compute_params(const Dev &d)
 {
     const int nw = blockDim.x / kWave, w = threadIdx.x / kWave;
-    const int half = coherent ? atomicAdd(d.vcur, 0) : *d.vcur;
+    const int half = *d.vcur;
     for (int sg = w; sg < d.nseg; sg += nw) {
         double numax, pnull;
-        const int en = d.seg[sg].ens;
-        const double emax = coherent
-            ? __longlong_as_double((long long)atomicMax((unsigned long long *)(d.emax + en), 0ull))
-            : d.emax[en];
-        seg_params(d, sg, half, emax, numax, pnull);
+        seg_params(d, sg, half, d.emax[d.seg[sg].ens], numax, pnull);
         if (lane_id() == 0) {
             d.numax[sg] = numax;
             d.pnull[sg] = pnull;
@@ -741,7 +754,25 @@ __device__ void compute_params(const Dev &d, bool coherent)
     }
 }
 
-__global__ void k_params(Dev d) { compute_params(d, false); }
+// The same bound in the last block of the second solve kernel, one thread per segment from
+// the maxima the first kernel reduced: max |E| was accumulated by other blocks of the same
+// launch, so it is read with an atomic, which sees every block's atomic update without a
+// fence, and every segment's loads go out at once.
+__device__ void compute_params_reduced(const Dev &d)
+{
+    for (int sg = threadIdx.x; sg < d.nseg; sg += blockDim.x) {
+        const SegC &S = d.seg[sg];
+        const double m2 = d.vmred[sg];
+        const double emax =
+            __longlong_as_double((long long)atomicMax((unsigned long long *)(d.emax + S.ens), 0ull));
+        double numax, pnull;
+        seg_bound(S, d.ens[S.ens], m2, emax, numax, pnull);
+        d.numax[sg] = numax;
+        d.pnull[sg] = pnull;
+    }
+}
+
+__global__ void k_params(Dev d) { compute_params(d); }
 
 // Inclusive prefix sum over the 64 lanes of a wave (FP64).
 __device__ __forceinline__ double wave_incl_scan_f64(double v)
@@ -997,7 +1028,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve2(Dev d, int zero_q, int
     if (threadIdx.x == 0) s_last = (atomicAdd(d.ticket + 6, 1u) == gridDim.x - 1);
     __syncthreads();
     if (!s_last) return;
-    compute_params(d, true);
+    compute_params_reduced(d);
     if (threadIdx.x == 0) d.ticket[6] = 0u;
 }
 
@@ -1238,48 +1269,56 @@ __device__ __forceinline__ uint32_t rank_in_group(const uint32_t *group, uint32_
     return r;
 }
 
-// Exclusive scan of the current half's group counts into gpre by one block: each thread
-// owns a contiguous run of g_tot / blockDim counts (g_tot is a multiple of 4096), sums it,
-// takes one block-wide scan of the sums, then writes its run; the run is read in groups of
-// four independent 16-byte loads so their latencies overlap.
+// Exclusive scan of the current half's group counts into gpre by one block.  Wave w owns the
+// w-th contiguous share of the counts (g_tot is a multiple of 4096, so every share is whole
+// rows of 64 16-byte vectors) and reads it row by row, lane l taking the row's l-th vector,
+// so every load instruction reads 1 KB of consecutive bytes: the block runs on one CU,
+// whose L1 would otherwise see 64 lines per instruction.  Rows are read kScanBatch at a time
+// (the last batch's row index clamped into the share and the extra rows masked), so the
+// block waits once per batch.  Pass 1 sums each share; the shares' bases come from one
+// exchange in LDS; pass 2 scans each row across the wave and writes it.
+constexpr int kScanBatch = 16;
+
 __device__ void group_scan_body(const Dev &d)
 {
-    __shared__ uint32_t s_buf[16];
+    __shared__ uint32_t s_w[16];
     const int p = (int)(*d.step & 1);
-    const uint4 *in = (const uint4 *)(d.gcnt + (int64_t)p * d.g_tot);
-    const int64_t per = d.g_tot / (4 * (int64_t)blockDim.x);  // uint4 per thread
-    const int64_t i0 = (int64_t)threadIdx.x * per;
+    const int nw = (int)blockDim.x / kWave, w = (int)threadIdx.x / kWave, lane = lane_id();
+    const int64_t rows = d.g_tot / (4 * kWave * (int64_t)nw);  // rows of 64 uint4 per wave
+    const uint4 *in = (const uint4 *)(d.gcnt + (int64_t)p * d.g_tot) + (int64_t)w * rows * kWave;
+    uint4 *out = (uint4 *)d.gpre + (int64_t)w * rows * kWave;
     uint32_t sum = 0;
-    int64_t i = 0;
-    for (; i + 4 <= per; i += 4) {
-        uint4 v[4];
+    for (int64_t r0 = 0; r0 < rows; r0 += kScanBatch) {
+        uint4 v[kScanBatch];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = in[i0 + i + u];
+        for (int u = 0; u < kScanBatch; ++u) v[u] = in[min(r0 + u, rows - 1) * kWave + lane];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) sum += v[u].x + v[u].y + v[u].z + v[u].w;
+        for (int u = 0; u < kScanBatch; ++u) sum += (r0 + u < rows) ? v[u].x + v[u].y + v[u].z + v[u].w : 0u;
     }
-    for (; i < per; ++i) {
-        const uint4 v = in[i0 + i];
-        sum += v.x + v.y + v.z + v.w;
-    }
-    uint32_t tot;
-    uint32_t ex = block_excl_scan_u32(sum, s_buf, tot);
-    uint4 *out = (uint4 *)d.gpre;
-    i = 0;
-    for (; i + 4 <= per; i += 4) {
-        uint4 v[4];
+    sum = wave_sum_u32(sum);
+    if (lane == 0) s_w[w] = sum;
+    __syncthreads();
+    uint32_t carry = 0;  // counts before this wave's share, then before the current row
+    for (int i = 0; i < w; ++i) carry += s_w[i];
+    for (int64_t r0 = 0; r0 < rows; r0 += kScanBatch) {
+        uint4 v[kScanBatch];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = in[i0 + i + u];
+        for (int u = 0; u < kScanBatch; ++u) v[u] = in[min(r0 + u, rows - 1) * kWave + lane];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            out[i0 + i + u] = make_uint4(ex, ex + v[u].x, ex + v[u].x + v[u].y, ex + v[u].x + v[u].y + v[u].z);
-            ex += v[u].x + v[u].y + v[u].z + v[u].w;
+        for (int u = 0; u < kScanBatch; ++u) {
+            if (r0 + u >= rows) break;
+            const uint32_t ls = v[u].x + v[u].y + v[u].z + v[u].w;
+            uint32_t inc = ls;
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const uint32_t n = __shfl_up(inc, o);
+                if (lane >= o) inc += n;
+            }
+            const uint32_t ex = carry + inc - ls;
+            out[(r0 + u) * kWave + lane] =
+                make_uint4(ex, ex + v[u].x, ex + v[u].x + v[u].y, ex + v[u].x + v[u].y + v[u].z);
+            carry += __shfl(inc, kWave - 1);
         }
-    }
-    for (; i < per; ++i) {
-        const uint4 v = in[i0 + i];
-        out[i0 + i] = make_uint4(ex, ex + v.x, ex + v.x + v.y, ex + v.x + v.y + v.z);
-        ex += v.x + v.y + v.z + v.w;
     }
 }
 
@@ -1744,13 +1783,15 @@ hipError_t launch_solve(const Dev &d, bool f64, int64_t nchunks, bool zero_q, hi
                         bool with_births, bool with_params)
 {
     const int nc = (int)nchunks, zq = zero_q ? 1 : 0;
-    const int scan = with_births ? 1 : 0, par = with_params ? 1 : 0;
-    const dim3 g1(nc + scan), g2(nc + (with_births ? kPlaceBlocks : 0));
+    const int scan = with_births ? 1 : 0;
+    const int nred = with_params ? (d.nseg + kSolveThreads / kWave - 1) / (kSolveThreads / kWave) : 0;
+    const int par = with_params ? 1 : 0;
+    const dim3 g1(nc + scan + nred), g2(nc + (with_births ? kPlaceBlocks : 0));
     if (f64) {
-        hipLaunchKernelGGL(k_solve1<true>, g1, dim3(kSolveThreads), 0, s, d, nc, scan);
+        hipLaunchKernelGGL(k_solve1<true>, g1, dim3(kSolveThreads), 0, s, d, nc, scan, nred);
         hipLaunchKernelGGL(k_solve2<true>, g2, dim3(kSolveThreads), 0, s, d, zq, nc, par);
     } else {
-        hipLaunchKernelGGL(k_solve1<false>, g1, dim3(kSolveThreads), 0, s, d, nc, scan);
+        hipLaunchKernelGGL(k_solve1<false>, g1, dim3(kSolveThreads), 0, s, d, nc, scan, nred);
         hipLaunchKernelGGL(k_solve2<false>, g2, dim3(kSolveThreads), 0, s, d, zq, nc, par);
     }
     LAUNCH_CHECK();
