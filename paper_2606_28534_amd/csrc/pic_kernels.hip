@@ -591,7 +591,14 @@ __device__ __forceinline__ int chunk_ens(const Dev &d, int64_t k)
 }
 
 constexpr int kNodesPerThread = kChunk / kSolveThreads;
-constexpr int kPlaceBlocks = 64;  // blocks that place a step's births
+// Blocks that place a step's births: the births grow with the particles (about 4.5e-4 of
+// the electrons per step), so the block count does too, from 64 (enough for the 4e7-particle
+// slab's ten thousand, under one per thread) to 256 from 5e8 slots on (64 batched
+// ensembles: their solve kernel 61 -> 49 us; on the slab 256 blocks cost 1 us more).
+__host__ __forceinline__ int place_blocks(const Dev &d)
+{
+    return (int)std::min<int64_t>(256, std::max<int64_t>(64, d.cap_tot >> 21));
+}
 
 // Birth ranking and placement, callable by a block of a kernel of their own or by extra
 // blocks of the two solve kernels (defined with the births below).
@@ -1786,7 +1793,7 @@ hipError_t launch_solve(const Dev &d, bool f64, int64_t nchunks, bool zero_q, hi
     const int scan = with_births ? 1 : 0;
     const int nred = with_params ? (d.nseg + kSolveThreads / kWave - 1) / (kSolveThreads / kWave) : 0;
     const int par = with_params ? 1 : 0;
-    const dim3 g1(nc + scan + nred), g2(nc + (with_births ? kPlaceBlocks : 0));
+    const dim3 g1(nc + scan + nred), g2(nc + (with_births ? place_blocks(d) : 0));
     if (f64) {
         hipLaunchKernelGGL(k_solve1<true>, g1, dim3(kSolveThreads), 0, s, d, nc, scan, nred);
         hipLaunchKernelGGL(k_solve2<true>, g2, dim3(kSolveThreads), 0, s, d, zq, nc, par);
@@ -1859,9 +1866,9 @@ hipError_t launch_births(const Dev &d, bool f64, bool in_step, bool advance, hip
     }
     const int deferred = in_step ? 1 : 0, adv = advance ? 1 : 0;
     if (f64)
-        hipLaunchKernelGGL(k_birth_place<true>, dim3(kPlaceBlocks), dim3(256), 0, s, d, deferred, adv);
+        hipLaunchKernelGGL(k_birth_place<true>, dim3(place_blocks(d)), dim3(256), 0, s, d, deferred, adv);
     else
-        hipLaunchKernelGGL(k_birth_place<false>, dim3(kPlaceBlocks), dim3(256), 0, s, d, deferred, adv);
+        hipLaunchKernelGGL(k_birth_place<false>, dim3(place_blocks(d)), dim3(256), 0, s, d, deferred, adv);
     LAUNCH_CHECK();
     if (!in_step) {
         hipLaunchKernelGGL(k_birth_clear, dim3(64), dim3(256), 0, s, d, -1);
