@@ -1019,9 +1019,9 @@ __device__ void solve2_body(const Dev &d, int zero_q)
 // particle slots beyond the ones in use, the id and slot counters, the birth lists, the
 // speed-maximum halves and the step counter, none of which the solve reads or writes).
 // With `params`, the last block to finish computes the next pass's null-collision bound
-// (R11) from this solve's max |E| and the current speed maxima, in place of a kernel of
-// its own; it reads what other blocks of this launch updated (max |E|, and the maxima half
-// the placement made current) through atomics, which need no fence.
+// (R11) from this solve's max |E| and the speed maxima the first kernel reduced, in place of
+// a kernel of its own; it reads max |E|, which other blocks of this launch updated, through
+// an atomic, which needs no fence.
 template <bool F64>
 __global__ void __launch_bounds__(kSolveThreads) k_solve2(Dev d, int zero_q, int nchunks, int params)
 {
