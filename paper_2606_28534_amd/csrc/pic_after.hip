@@ -26,7 +26,7 @@ namespace pic {
 constexpr int kNeutralBlocks = 128;  // blocks per ensemble of the neutral kernel (each takes a ticket)
 
 // =======================================================================================
-// Null-collision candidates of the FP32 pass.  A block takes kCandTiles consecutive tiles;
+// Null-collision candidates of the FP32 pass.  A block takes cand_tiles(T) consecutive tiles;
 // their candidate records (post-push state and slot, written by the pass) are concatenated
 // through a prefix of the tile counts, one candidate per thread.  Each candidate draws the
 // full Philox block 0 again, picks its channel (in FP64, the same decision in both
@@ -39,15 +39,21 @@ constexpr int kNeutralBlocks = 128;  // blocks per ensemble of the neutral kerne
 // gives the block what it needs to stage those segments' constants and collision bounds
 // in LDS, in the same round trip as the candidate records; then the birth reservation.
 // =======================================================================================
-constexpr int kCandTiles = 32;
+// Tiles per block: a block's time is a chain of round trips per round of 256 candidates,
+// and every block is resident at once on the 4e7-particle slab (1.5e3 blocks), where 32
+// tiles are fastest (16: 29.6 us, 24: 25.3 us, 32: 24.2 us, 64: 27.7 us); with ten times
+// the tiles (the 64 batched ensembles' 5e5) the blocks run in many waves and 64 tiles per
+// block, fewer and longer blocks, take the kernel from 156 to 123 us.
+constexpr int kCandTilesMax = 64;  // one lane of the first wave per tile
+__host__ __forceinline__ int cand_tiles(int64_t T) { return T > 65536 ? 64 : 32; }
 constexpr int kCandSegs = 12;  // segments a block stages (more: read from global memory)
 
 // Block `bid` (a kernel of its own, or the first blocks of the kernel that follows the pass).
 template <bool CXREL>
-__device__ void cand_body(const Dev &d, int tile, int64_t T, int hist, int bid)
+__device__ void cand_body(const Dev &d, int tile, int64_t T, int hist, int bid, int ct)
 {
-    __shared__ uint32_t s_pre[kCandTiles + 1];
-    __shared__ int s_tj[kCandTiles];  // staged entry of each tile's segment (-1: not staged)
+    __shared__ uint32_t s_pre[kCandTilesMax + 1];
+    __shared__ int s_tj[kCandTilesMax];  // staged entry of each tile's segment (-1: not staged)
     // staged segment constants: entry j is segment s_sg[j] of ensemble s_en[j]
     __shared__ SegC s_seg[kCandSegs];
     __shared__ EnsC s_ens[kCandSegs];
@@ -64,7 +70,7 @@ __device__ void cand_body(const Dev &d, int tile, int64_t T, int hist, int bid)
     __shared__ uint32_t s_dn[kCandSegs];
     // births of one round of the block: counted in LDS, then one reservation in the list
     __shared__ uint32_t s_nb, s_bbase;
-    const int64_t t0 = (int64_t)bid * kCandTiles;
+    const int64_t t0 = (int64_t)bid * ct;
     // per-launch values, read with the tile counts
     const int b = *d.cur;
     const uint32_t tag = (uint32_t)(*d.step);
@@ -75,14 +81,14 @@ __device__ void cand_body(const Dev &d, int tile, int64_t T, int hist, int bid)
         const int k = threadIdx.x;
         const int64_t t = t0 + k;
         uint32_t w = 0;
-        if (k < kCandTiles && t < T) {
+        if (k < ct && t < T) {
             w = d.ctile[t];
             d.ctile[t] = 0u;
         }
         const uint32_t c = w & kCandCountMask;
         uint32_t inc = c;
 #pragma unroll
-        for (int o = 1; o < kCandTiles; o <<= 1) {
+        for (int o = 1; o < kCandTilesMax; o <<= 1) {
             const uint32_t n = __shfl_up(inc, o);
             if (k >= o) inc += n;
         }
@@ -93,7 +99,7 @@ __device__ void cand_body(const Dev &d, int tile, int64_t T, int hist, int bid)
         const int key = c ? (int)((w >> 12) & 0x3FFu) : -1;
         int pm = key;
 #pragma unroll
-        for (int o = 1; o < kCandTiles; o <<= 1) {
+        for (int o = 1; o < kCandTilesMax; o <<= 1) {
             const int n = __shfl_up(pm, o);
             if (k >= o) pm = max(pm, n);
         }
@@ -102,11 +108,11 @@ __device__ void cand_body(const Dev &d, int tile, int64_t T, int hist, int bid)
         const bool head = key >= 0 && key != before;
         const unsigned long long hm = __ballot(head);
         const int hidx = __popcll(hm & ((1ull << k) - 1ull)) - (head ? 0 : 1);  // entry of the run k is in
-        if (k < kCandTiles) {
+        if (k < ct) {
             s_pre[k] = inc - c;
             s_tj[k] = (key >= 0 && hidx < kCandSegs) ? hidx : -1;
         }
-        if (k == kCandTiles - 1) s_pre[kCandTiles] = inc;
+        if (k == ct - 1) s_pre[ct] = inc;
         if (head && hidx < kCandSegs) {
             s_sg[hidx] = key;
             s_en[hidx] = (int)(w >> 22);
@@ -120,7 +126,7 @@ __device__ void cand_body(const Dev &d, int tile, int64_t T, int hist, int bid)
         }
     }
     __syncthreads();
-    const uint32_t m = s_pre[kCandTiles];
+    const uint32_t m = s_pre[ct];
     if (m == 0) return;
     {
         // stage the segments' constants (word copies; all loads in one round trip)
@@ -150,7 +156,7 @@ __device__ void cand_body(const Dev &d, int tile, int64_t T, int hist, int bid)
         int k = 0;
         uint4 r0 = make_uint4(0u, 0u, 0u, 0u), r1 = r0;
         if (act) {
-            int lo = 0, hi = kCandTiles;
+            int lo = 0, hi = ct;
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
                 if (s_pre[mid] <= q)
@@ -294,9 +300,9 @@ __device__ void cand_body(const Dev &d, int tile, int64_t T, int hist, int bid)
 }
 
 template <bool CXREL>
-__global__ void __launch_bounds__(256) k_cand32(Dev d, int tile, int64_t T, int hist)
+__global__ void __launch_bounds__(256) k_cand32(Dev d, int tile, int64_t T, int hist, int ct)
 {
-    cand_body<CXREL>(d, tile, T, hist, (int)blockIdx.x);
+    cand_body<CXREL>(d, tile, T, hist, (int)blockIdx.x, ct);
 }
 
 
@@ -637,11 +643,12 @@ hipError_t launch_cand32(const Dev &d, int ppt, hipStream_t s, int hist, int64_t
 {
     const int tile = 256 * ppt;
     const int64_t T = cap_tot / tile;
-    const dim3 g((unsigned)((T + kCandTiles - 1) / kCandTiles));
+    const int ct = cand_tiles(T);
+    const dim3 g((unsigned)((T + ct - 1) / ct));
     if (d.any_cx_rel)
-        hipLaunchKernelGGL(k_cand32<true>, g, dim3(256), 0, s, d, tile, T, hist);
+        hipLaunchKernelGGL(k_cand32<true>, g, dim3(256), 0, s, d, tile, T, hist, ct);
     else
-        hipLaunchKernelGGL(k_cand32<false>, g, dim3(256), 0, s, d, tile, T, hist);
+        hipLaunchKernelGGL(k_cand32<false>, g, dim3(256), 0, s, d, tile, T, hist, ct);
     return hipGetLastError();
 }
 
@@ -649,11 +656,11 @@ hipError_t launch_cand32(const Dev &d, int ppt, hipStream_t s, int hist, int64_t
 // nn = kNeutralBlocks x (nens + 1) the neutrals, the rest the source pairs.  Each range runs
 // the body its own kernel would, so the results are those of the three launches.
 template <bool CXREL>
-__global__ void __launch_bounds__(256) k_after(Dev d, int tile, int64_t T, int hist, int nc, int nn)
+__global__ void __launch_bounds__(256) k_after(Dev d, int tile, int64_t T, int hist, int nc, int nn, int ct)
 {
     const int b = (int)blockIdx.x;
     if (b < nc) {
-        cand_body<CXREL>(d, tile, T, hist, b);
+        cand_body<CXREL>(d, tile, T, hist, b, ct);
     } else if (b < nc + nn) {
         const int k = b - nc;
         neutrals_body(d, k % kNeutralBlocks, k / kNeutralBlocks, kNeutralBlocks, d.nens + 1);
@@ -666,15 +673,16 @@ hipError_t launch_after(const Dev &d, int ppt, hipStream_t s, int hist, int64_t 
 {
     const int tile = 256 * ppt;
     const int64_t T = cap_tot / tile;
-    const int nc = coll ? (int)((T + kCandTiles - 1) / kCandTiles) : 0;
+    const int ct = cand_tiles(T);
+    const int nc = coll ? (int)((T + ct - 1) / ct) : 0;
     const int nn = d.ncap_tot ? kNeutralBlocks * (d.nens + 1) : 0;
     const int ns = d.src_tot ? (int)((d.src_tot + 255) / 256) : 0;
     if (nc + nn + ns == 0) return hipSuccess;
     const dim3 g((unsigned)(nc + nn + ns));
     if (d.any_cx_rel)
-        hipLaunchKernelGGL(k_after<true>, g, dim3(256), 0, s, d, tile, T, hist, nc, nn);
+        hipLaunchKernelGGL(k_after<true>, g, dim3(256), 0, s, d, tile, T, hist, nc, nn, ct);
     else
-        hipLaunchKernelGGL(k_after<false>, g, dim3(256), 0, s, d, tile, T, hist, nc, nn);
+        hipLaunchKernelGGL(k_after<false>, g, dim3(256), 0, s, d, tile, T, hist, nc, nn, ct);
     return hipGetLastError();
 }
 
