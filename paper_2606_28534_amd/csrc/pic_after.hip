@@ -12,6 +12,8 @@
 // neutral, two buffers) that one kernel streams per step, instead of a third segment of the
 // charged pass.  Their order is free (nothing they compute depends on it), so survivors and
 // new neutrals are appended with wave-aggregated atomics.
+#include <algorithm>
+
 #include "pic_kernels.h"
 #include "pic_particle.h"
 
@@ -40,12 +42,16 @@ constexpr int kNeutralBlocks = 128;  // blocks per ensemble of the neutral kerne
 // in LDS, in the same round trip as the candidate records; then the birth reservation.
 // =======================================================================================
 // Tiles per block: a block's time is a chain of round trips per round of 256 candidates,
-// and every block is resident at once on the 4e7-particle slab (1.5e3 blocks), where 32
-// tiles are fastest (16: 29.6 us, 24: 25.3 us, 32: 24.2 us, 64: 27.7 us); with ten times
-// the tiles (the 64 batched ensembles' 5e5) the blocks run in many waves and 64 tiles per
-// block, fewer and longer blocks, take the kernel from 156 to 123 us.
+// so the kernel is fastest when its blocks fit one wave of resident blocks (four per CU at
+// its registers, 1024 on the chip) without making each block's rounds many: the
+// 4e7-particle slab's 4.9e4 tiles take 48 per block, 1018 blocks (16: 29.6 us, 24: 25.3 us,
+// 32: 24.5 us, 40: 23.7 us, 48: 23.3 us, 64: 27.7 us); the 64 batched ensembles' 5e5 tiles
+// take the most, 64 (156 us at 32, 124 us at 64).
 constexpr int kCandTilesMax = 64;  // one lane of the first wave per tile
-__host__ __forceinline__ int cand_tiles(int64_t T) { return T > 65536 ? 64 : 32; }
+__host__ __forceinline__ int cand_tiles(int64_t T)
+{
+    return (int)std::min<int64_t>(kCandTilesMax, std::max<int64_t>(32, (T + 1023) / 1024));
+}
 constexpr int kCandSegs = 12;  // segments a block stages (more: read from global memory)
 
 // Block `bid` (a kernel of its own, or the first blocks of the kernel that follows the pass).
