@@ -302,6 +302,8 @@ size_t carve(const Plan &P, char *base, Dev &d)
     d.gcnt = c.take<uint32_t>(2 * P.g_tot);
     d.gpre = c.take<uint32_t>(P.g_tot);
     d.g_tot = P.g_tot;
+    d.ngt = P.g_tot / kGroupTile <= kMaxGroupTiles ? (int32_t)(P.g_tot / kGroupTile) : 0;
+    d.gtile = c.take<uint32_t>(std::max<int64_t>(d.ngt, 1));
     d.ctile = c.take<uint32_t>(P.cap_tot / 1024 + 1);
     d.cellcnt = c.take<uint32_t>(P.cells_tot);
     d.cursor = c.take<uint32_t>(P.cells_tot);

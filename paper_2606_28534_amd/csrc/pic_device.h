@@ -34,6 +34,10 @@ constexpr int kScanBlock = 256;
 constexpr int kScanItems = 16;        // elements per thread in the generic scan
 constexpr double kFix = 16777216.0;   // 2^24 fixed-point scale of the deposit
 constexpr double kNuSafety = 1.0 + 1.0 / 65536.0;
+// births' group counts are scanned in tiles of kGroupTile groups (one block each); the
+// placement adds the tiles' bases, staged in LDS, so at most kMaxGroupTiles tiles
+constexpr int kGroupTile = 4096;
+constexpr int kMaxGroupTiles = 1024;
 constexpr int64_t kSlotAlign = 4096;  // segment slot ranges are multiples of the largest tile
 
 // Counter slots per (stripe, segment).
@@ -150,7 +154,10 @@ struct Dev {
     uint32_t *bitmap;         // [2][bm_words] per-ensemble bit per parent id
     int64_t bm_words;
     uint32_t *gcnt;           // [2][g_tot] per-ensemble births per group of kGroupIds ids
-    uint32_t *gpre;           // [g_tot] exclusive scan of the current half's gcnt
+    uint32_t *gpre;           // [g_tot] exclusive scan of the current half's gcnt, per tile
+                              // of kGroupTile groups when ngt > 0 (global otherwise)
+    uint32_t *gtile;          // [max(ngt, 1)] group-count total of each tile
+    int32_t ngt;              // tiles of the tiled scan (0: the global three-kernel scan)
     int64_t g_tot;            // a multiple of 4096
     // null-collision candidates of the FP32 pass: tile t keeps its candidate slots in
     // cand[t * tile .. t * tile + ctile[t])

@@ -602,7 +602,7 @@ __host__ __forceinline__ int place_blocks(const Dev &d)
 
 // Birth ranking and placement, callable by a block of a kernel of their own or by extra
 // blocks of the two solve kernels (defined with the births below).
-__device__ void group_scan_body(const Dev &d);
+__device__ void group_tile_scan_body(const Dev &d, int t);
 template <bool F64>
 __device__ void birth_place_body(const Dev &d, int deferred, int advance, int bid, int nblk);
 
@@ -621,18 +621,19 @@ __device__ void vmax_reduce_body(const Dev &d, int pending, int bid)
     if (lane_id() == 0) d.vmred[sg] = m2;
 }
 
-// Blocks [0, nchunks) solve; with `scan`, one more block scans the group counts of the
-// previous step's births (independent data), so that scan costs no launch of its own;
-// `nred` more blocks reduce the speed maxima for the null-collision bound (vmax_reduce_body).
+// Blocks [0, nchunks) solve; with `nscan` > 0, that many more blocks scan the group counts
+// of the previous step's births (independent data; one tile each), so that scan costs no
+// launch of its own; `nred` more blocks reduce the speed maxima for the null-collision bound
+// (vmax_reduce_body).
 template <bool F64>
-__global__ void __launch_bounds__(kSolveThreads) k_solve1(Dev d, int nchunks, int scan, int nred)
+__global__ void __launch_bounds__(kSolveThreads) k_solve1(Dev d, int nchunks, int nscan, int nred)
 {
     if ((int)blockIdx.x >= nchunks) {
-        const int r = (int)blockIdx.x - nchunks - scan;
-        if (r < 0)
-            group_scan_body(d);
-        else if (r < nred)
-            vmax_reduce_body(d, scan, r);
+        const int r = (int)blockIdx.x - nchunks;
+        if (r < nscan)
+            group_tile_scan_body(d, r);
+        else if (r - nscan < nred)
+            vmax_reduce_body(d, nscan > 0, r - nscan);
         return;
     }
     __shared__ double s_buf[8];
@@ -1276,60 +1277,54 @@ __device__ __forceinline__ uint32_t rank_in_group(const uint32_t *group, uint32_
     return r;
 }
 
-// Exclusive scan of the current half's group counts into gpre by one block.  Wave w owns the
-// w-th contiguous share of the counts (g_tot is a multiple of 4096, so every share is whole
-// rows of 64 16-byte vectors) and reads it row by row, lane l taking the row's l-th vector,
-// so every load instruction reads 1 KB of consecutive bytes: the block runs on one CU,
-// whose L1 would otherwise see 64 lines per instruction.  Rows are read kScanBatch at a time
-// (the last batch's row index clamped into the share and the extra rows masked), so the
-// block waits once per batch.  Pass 1 sums each share; the shares' bases come from one
-// exchange in LDS; pass 2 scans each row across the wave and writes it.
-constexpr int kScanBatch = 16;
+// Exclusive scan of the current half's group counts, one tile of kGroupTile groups per block:
+// gpre gets each group's prefix within its tile and gtile the tile's total (the placement
+// adds the tiles' bases).  Wave w owns the w-th contiguous share of the tile, whole rows of
+// 64 16-byte vectors, and reads it row by row, lane l taking the row's l-th vector, so every
+// load instruction reads 1 KB of consecutive bytes; the share's rows are all loaded before
+// any is used (one round trip), summed, the shares' bases exchanged in LDS, and each row
+// scanned across the wave and written.  (One block over every group, per-thread runs read
+// four vectors at a time, had taken 60 us for the 64 batched ensembles' 1.3e5 groups.)
+constexpr int kTileVec = kGroupTile / 4;  // uint4 per tile
 
-__device__ void group_scan_body(const Dev &d)
+// (a block of 256 threads: four waves of kRows rows each)
+__device__ void group_tile_scan_body(const Dev &d, int t)
 {
-    __shared__ uint32_t s_w[16];
+    constexpr int kRows = kTileVec / (kWave * 4);
+    __shared__ uint32_t s_w[4];
     const int p = (int)(*d.step & 1);
-    const int nw = (int)blockDim.x / kWave, w = (int)threadIdx.x / kWave, lane = lane_id();
-    const int64_t rows = d.g_tot / (4 * kWave * (int64_t)nw);  // rows of 64 uint4 per wave
-    const uint4 *in = (const uint4 *)(d.gcnt + (int64_t)p * d.g_tot) + (int64_t)w * rows * kWave;
-    uint4 *out = (uint4 *)d.gpre + (int64_t)w * rows * kWave;
+    const int w = (int)threadIdx.x / kWave, lane = lane_id();
+    const int64_t v0 = (int64_t)t * kTileVec + (int64_t)w * kRows * kWave;
+    const uint4 *in = (const uint4 *)(d.gcnt + (int64_t)p * d.g_tot) + v0;
+    uint4 *out = (uint4 *)d.gpre + v0;
+    uint4 v[kRows];
     uint32_t sum = 0;
-    for (int64_t r0 = 0; r0 < rows; r0 += kScanBatch) {
-        uint4 v[kScanBatch];
 #pragma unroll
-        for (int u = 0; u < kScanBatch; ++u) v[u] = in[min(r0 + u, rows - 1) * kWave + lane];
+    for (int r = 0; r < kRows; ++r) v[r] = in[r * kWave + lane];
 #pragma unroll
-        for (int u = 0; u < kScanBatch; ++u) sum += (r0 + u < rows) ? v[u].x + v[u].y + v[u].z + v[u].w : 0u;
-    }
+    for (int r = 0; r < kRows; ++r) sum += v[r].x + v[r].y + v[r].z + v[r].w;
     sum = wave_sum_u32(sum);
     if (lane == 0) s_w[w] = sum;
     __syncthreads();
-    uint32_t carry = 0;  // counts before this wave's share, then before the current row
+    uint32_t carry = 0;  // counts of the tile before this wave's share, then before the row
     for (int i = 0; i < w; ++i) carry += s_w[i];
-    for (int64_t r0 = 0; r0 < rows; r0 += kScanBatch) {
-        uint4 v[kScanBatch];
+    if (threadIdx.x == 0) d.gtile[t] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
 #pragma unroll
-        for (int u = 0; u < kScanBatch; ++u) v[u] = in[min(r0 + u, rows - 1) * kWave + lane];
+    for (int r = 0; r < kRows; ++r) {
+        const uint32_t ls = v[r].x + v[r].y + v[r].z + v[r].w;
+        uint32_t inc = ls;
 #pragma unroll
-        for (int u = 0; u < kScanBatch; ++u) {
-            if (r0 + u >= rows) break;
-            const uint32_t ls = v[u].x + v[u].y + v[u].z + v[u].w;
-            uint32_t inc = ls;
-#pragma unroll
-            for (int o = 1; o < kWave; o <<= 1) {
-                const uint32_t n = __shfl_up(inc, o);
-                if (lane >= o) inc += n;
-            }
-            const uint32_t ex = carry + inc - ls;
-            out[(r0 + u) * kWave + lane] =
-                make_uint4(ex, ex + v[u].x, ex + v[u].x + v[u].y, ex + v[u].x + v[u].y + v[u].z);
-            carry += __shfl(inc, kWave - 1);
+        for (int o = 1; o < kWave; o <<= 1) {
+            const uint32_t n = __shfl_up(inc, o);
+            if (lane >= o) inc += n;
         }
+        const uint32_t ex = carry + inc - ls;
+        out[r * kWave + lane] = make_uint4(ex, ex + v[r].x, ex + v[r].x + v[r].y, ex + v[r].x + v[r].y + v[r].z);
+        carry += __shfl(inc, kWave - 1);
     }
 }
 
-__global__ void __launch_bounds__(1024) k_group_scan(Dev d) { group_scan_body(d); }
+__global__ void __launch_bounds__(256) k_group_scan(Dev d) { group_tile_scan_body(d, (int)blockIdx.x); }
 
 // Place the births of this step (half p = step & 1).  With `deferred`, also clear the
 // bitmap bits and group counts of half 1 - p (the previous step's births) and reset its
@@ -1350,11 +1345,40 @@ struct PlaceSeg {
     uint32_t next_id;
 };
 
+// Bases of the group-count tiles (exclusive prefix of gtile) in LDS, by the whole block of
+// 256 threads (four tiles each); all zero when the global scan ran (ngt = 0).
+__device__ void stage_tile_bases(const Dev &d, uint32_t *s_tb)
+{
+    __shared__ uint32_t s_buf[16];
+    constexpr int kPer = kMaxGroupTiles / 256;
+    const int i0 = (int)threadIdx.x * kPer;
+    uint32_t v[kPer], sum = 0;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        v[u] = (i0 + u < d.ngt) ? d.gtile[i0 + u] : 0u;
+        sum += v[u];
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_scan_u32(sum, s_buf, tot);
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        s_tb[i0 + u] = ex;
+        ex += v[u];
+    }
+}
+
+// The births' scanned group count at group index i (global over every ensemble's groups).
+__device__ __forceinline__ uint32_t group_prefix(const Dev &d, const uint32_t *s_tb, int64_t i)
+{
+    return s_tb[i / kGroupTile] + d.gpre[i];
+}
+
 template <bool F64>
 __device__ void birth_place_body(const Dev &d, int deferred, int advance, int bid, int nblk)
 {
     __shared__ uint32_t s_pre[kStripes + 1];
     __shared__ uint32_t s_old[kStripes + 1];
+    __shared__ uint32_t s_tb[kMaxGroupTiles];
     __shared__ bool s_last;
     __shared__ PlaceEns s_pe[PIC_MAX_ENSEMBLES];
     __shared__ PlaceSeg s_ps[2 * PIC_MAX_ENSEMBLES];
@@ -1374,6 +1398,7 @@ __device__ void birth_place_body(const Dev &d, int deferred, int advance, int bi
         const SegC &S = d.seg[sg];
         s_ps[sg] = PlaceSeg{S.base, S.cap, d.n_slots[sg], d.next_id[sg]};
     }
+    stage_tile_bases(d, s_tb);
     __syncthreads();
     const int64_t M = s_pre[kStripes], Mo = deferred ? (int64_t)s_old[kStripes] : 0;
     const int b = *d.cur;
@@ -1400,7 +1425,7 @@ __device__ void birth_place_body(const Dev &d, int deferred, int advance, int bi
         const PlaceEns &E = s_pe[B.ens];
         const uint32_t pid = B.pid;
         const int64_t g = pid / kGroupIds;
-        const uint32_t r = d.gpre[E.grp_base + g] - d.gpre[E.grp_base] +
+        const uint32_t r = group_prefix(d, s_tb, E.grp_base + g) - group_prefix(d, s_tb, E.grp_base) +
                            rank_in_group(bb.bitmap + E.bm_base + g * kGroupWords, pid);
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
@@ -1445,7 +1470,7 @@ __device__ void birth_place_body(const Dev &d, int deferred, int advance, int bi
     for (int en = threadIdx.x; en < d.nens; en += blockDim.x) {
         const PlaceEns &E = s_pe[en];
         const int64_t ngrp = (E.idcap + kGroupIds - 1) / kGroupIds;
-        const uint32_t m = d.gpre[E.grp_base + ngrp] - d.gpre[E.grp_base];
+        const uint32_t m = group_prefix(d, s_tb, E.grp_base + ngrp) - group_prefix(d, s_tb, E.grp_base);
         for (int s = 0; s < E.nspecies; ++s) {
             const int sg = E.seg[s];
             const PlaceSeg &P = s_ps[sg];
@@ -1784,21 +1809,21 @@ hipError_t launch_zero_q(const Dev &d, bool f64, hipStream_t s)
     return hipSuccess;
 }
 
-bool births_fit_solve(const Dev &d) { return d.g_tot <= (int64_t)1 << 18; }
+bool births_fit_solve(const Dev &d) { return d.ngt > 0; }
 
 hipError_t launch_solve(const Dev &d, bool f64, int64_t nchunks, bool zero_q, hipStream_t s,
                         bool with_births, bool with_params)
 {
     const int nc = (int)nchunks, zq = zero_q ? 1 : 0;
-    const int scan = with_births ? 1 : 0;
+    const int nscan = with_births ? d.ngt : 0;
     const int nred = with_params ? (d.nseg + kSolveThreads / kWave - 1) / (kSolveThreads / kWave) : 0;
     const int par = with_params ? 1 : 0;
-    const dim3 g1(nc + scan + nred), g2(nc + (with_births ? place_blocks(d) : 0));
+    const dim3 g1(nc + nscan + nred), g2(nc + (with_births ? place_blocks(d) : 0));
     if (f64) {
-        hipLaunchKernelGGL(k_solve1<true>, g1, dim3(kSolveThreads), 0, s, d, nc, scan, nred);
+        hipLaunchKernelGGL(k_solve1<true>, g1, dim3(kSolveThreads), 0, s, d, nc, nscan, nred);
         hipLaunchKernelGGL(k_solve2<true>, g2, dim3(kSolveThreads), 0, s, d, zq, nc, par);
     } else {
-        hipLaunchKernelGGL(k_solve1<false>, g1, dim3(kSolveThreads), 0, s, d, nc, scan, nred);
+        hipLaunchKernelGGL(k_solve1<false>, g1, dim3(kSolveThreads), 0, s, d, nc, nscan, nred);
         hipLaunchKernelGGL(k_solve2<false>, g2, dim3(kSolveThreads), 0, s, d, zq, nc, par);
     }
     LAUNCH_CHECK();
@@ -1857,9 +1882,10 @@ int64_t scan_blocks(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
 hipError_t launch_births(const Dev &d, bool f64, bool in_step, bool advance, hipStream_t s)
 {
     hipError_t e;
-    // the group-count scan: one block up to 2^18 counts, the three-kernel scan above that
-    if (d.g_tot <= (int64_t)1 << 18) {
-        hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(1024), 0, s, d);
+    // the group-count scan: one block per tile up to kMaxGroupTiles tiles, the global
+    // three-kernel scan above that
+    if (d.ngt > 0) {
+        hipLaunchKernelGGL(k_group_scan, dim3(d.ngt), dim3(256), 0, s, d);
         LAUNCH_CHECK();
     } else if ((e = launch_scan_sel(d.gcnt, d.gpre, d.g_tot, d.scanpart, false, d.step, s)) != hipSuccess) {
         return e;
