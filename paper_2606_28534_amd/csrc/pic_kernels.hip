@@ -1347,6 +1347,7 @@ struct PlaceSeg {
 
 // Bases of the group-count tiles (exclusive prefix of gtile) in LDS, by the whole block of
 // 256 threads (four tiles each); all zero when the global scan ran (ngt = 0).
+static_assert(kSolveThreads == 256, "the solve kernels' births blocks have 256 threads, as k_birth_place");
 __device__ void stage_tile_bases(const Dev &d, uint32_t *s_tb)
 {
     __shared__ uint32_t s_buf[16];
