@@ -98,7 +98,7 @@ def load_library():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (no CPU fallback)")
+        raise ImportError(f"{LIB_PATH} is not built; build it with python -m paper_2606_28534_amd.build (no CPU fallback)")
     import torch  # noqa: F401  (loads the HIP runtime the library binds to)
     L = C.CDLL(LIB_PATH)
     P = C.c_void_p

@@ -1,4 +1,4 @@
-"""GPU runs far beyond the pointwise-parity windows, judged by statistics against the FP64
+"""GPU runs far beyond the pointwise-parity windows, checked by statistics against the FP64
 oracle's run of the same seeded workload.  PIC is chaotic: after a few hundred steps the two
 runs are different realisations of the same plasma (they start identical and decorrelate),
 so they are compared as such.
@@ -42,7 +42,7 @@ def _within_counts(a, b, what):
     assert abs(a - b) <= 3.0 * math.sqrt(a + b) + 1, (what, a, b)
 
 
-def _judge(e, gd, od, o, nload):
+def _check_statistics(e, gd, od, o, nload):
     for k in range(3):
         _within_counts(gd["coll"][k], od["coll"][k], f"coll[{k}]")
     assert sum(od["coll"]) > 1000
@@ -83,7 +83,7 @@ def test_small_plain_run_1000_steps(pic, prec):
     assert o.error == 0
     assert gd["step"] == od["step"] == 1000
     nload = [sp["ppc"] * e["ncells"] for sp in e["species"]]
-    _judge(e, gd, od, o, nload)
+    _check_statistics(e, gd, od, o, nload)
     sim.close()
 
 
@@ -106,6 +106,6 @@ def test_sheath_slab_300_steps_three_seeds(pic, seed):
     assert o.error == 0
     assert gd["step"] == od["step"] == 300
     nload = [sp["ppc"] * e["ncells"] for sp in e["species"]]
-    _judge(e, gd, od, o, nload)
+    _check_statistics(e, gd, od, o, nload)
     assert sim.graph_launches() > 0
     sim.close()
