@@ -9,7 +9,7 @@ solve, gather + Boris push, walls, null-collision MC, births, deposit, and the s
 every 20th step.  Inputs are synthetic (seeded Philox particle load) and resident in HBM
 before the timed region starts.
 
-Prints ONE JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+Prints ONE JSON line.  `--gpus N` with N > 1 exits: the hot path runs on one GPU.
 """
 from __future__ import annotations
 
@@ -342,7 +342,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs the hot path on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the hot path runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
