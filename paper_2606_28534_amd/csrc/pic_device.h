@@ -21,7 +21,7 @@ constexpr int kStripes = 32;          // stripes of the birth list
 constexpr int kCntStripes = 256;      // stripes of the counters, sums and speed maxima
 constexpr int kWave = 64;             // CDNA wavefront
 constexpr int32_t kDead = INT32_MIN;  // FP32 form: cell of an absorbed slot
-constexpr int kChunk = 2048;          // nodes per block in the field solve
+constexpr int kChunk = 1024;          // nodes per block in the field solve
 constexpr int kSolveThreads = 256;
 constexpr int kMaxEns = 256;          // ensembles per context
 constexpr int kMaxSmooth = 4;         // passes of the density filter

@@ -108,9 +108,9 @@ def test_deposit_and_solve_from_injected_state(pic, prec, periodic):
 @pytest.mark.parametrize("periodic", [False, True])
 def test_gather_table_matches_node_field(pic, periodic):
     """The FP32 gather table (E_j, E_{j+1} - E_j) built by the solve, across solve-chunk
-    boundaries (2048 nodes a chunk) and at sizes that are exact multiples of a chunk, against
+    boundaries (1024 nodes a chunk) and at sizes that are exact multiples of a chunk, against
     the node field the same solve returns, and the node field against the oracle."""
-    for N in (5, 2047, 2048, 4096, 6661):
+    for N in (5, 1023, 1024, 2047, 2048, 4096, 6661):
         e = ens_small(ncells=N, ppc=3, periodic=periodic, capacity=4 * N + 64)
         st = synth.random_state(e, [3 * N + 7, 3 * N + 1], seed=N + 11)
         sim = pic.Sim(work_of(e, "fp32"), fused=False)
@@ -136,7 +136,7 @@ def test_gather_table_matches_node_field(pic, periodic):
 
 def test_scan_solve_equals_thomas_fp64(pic):
     """The two-prefix-sum solve against the oracle's Thomas solve on the same charge."""
-    for N in (2, 3, 2047, 2048, 2049, 10007):
+    for N in (2, 3, 1023, 1024, 1025, 2047, 2048, 2049, 10007):
         e = ens_small(ncells=N, ppc=2, nspecies=1, collisions=False, capacity=5 * N + 3)
         st = synth.random_state(e, [5 * N + 3], seed=N)
         sim = pic.Sim(work_of(e, "fp64"), fused=False)

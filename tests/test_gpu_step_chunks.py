@@ -1,4 +1,4 @@
-"""GPU parity of the fused step on grids that span several solve chunks (2048 nodes each),
+"""GPU parity of the fused step on grids that span several solve chunks (1024 nodes each),
 with ragged tails, smoothing halos across chunk boundaries and both wall kinds, and of
 the births the step's solve launches place."""
 import numpy as np
@@ -29,7 +29,7 @@ def work_of(e):
 
 # one node short of a chunk, exactly one chunk of cells (the wall node alone in a second
 # chunk), one past, and ragged multi-chunk grids
-SIZES = [2047, 2048, 2049, 4097, 6661]
+SIZES = [1023, 1024, 1025, 4097, 6661]
 
 
 @pytest.mark.parametrize("N", SIZES)

@@ -1,7 +1,7 @@
 """GPU parity of the floating-wall solve (R22) and the density smoothing (R23) against the
 FP64 oracle, on identical seeded inputs from the synth module.
 
-Sizes span several 2048-node solve chunks with a ragged tail, and smoothing stencils that
+Sizes span several 1024-node solve chunks with a ragged tail, and smoothing stencils that
 cross chunk boundaries and fold at the walls (or wrap when periodic).
 """
 import numpy as np
