@@ -66,7 +66,7 @@ def test_fused_steps_match_oracle_across_chunks(pic, N, smooth, floating):
 
 def test_collisional_steps_with_births_in_the_solve(pic):
     """With collisions the graph-replayed fused step ranks and places the previous step's
-    births in extra blocks of its two solve kernels: 30 steps on a 3-chunk grid agree with
+    births in extra blocks of its two solve kernels: 30 steps on a 5-chunk grid agree with
     the separate-stage run (births placed by kernels of their own) bit for bit, and every
     particle is accounted for."""
     e = synth.ensemble(4500, 25, collisions=True, seed=41, sort_every=20)
